@@ -1,0 +1,254 @@
+"""FP64 CPU oracle for the CLAIRE registration hot path (arXiv 2209.08189).
+
+TEST INFRASTRUCTURE ONLY: the test suite, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` are the only callers.  It shares no code with
+the HIP library; the numerical work is in ``claire_oracle.c`` (plain C, FP64),
+this module only marshals numpy arrays.
+
+Readings of the paper that the oracle fixes (grid nodes x_i = 2 pi i / N,
+Heun RK2 feet, cubic Lagrange on floor(p)-1..floor(p)+2, central FD8, trapezoid
+time quadrature, H1-seminorm regulariser with K = I, spectral preconditioner
+(beta A)^-1 with the k = 0 mode mapped to 1/beta, PCG/Armijo constants) are
+listed in ``claire_oracle.c`` beside each function.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "claire_oracle.c")
+_LIB = os.path.join(_HERE, "libclaire_oracle.so")
+_lib = None
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+
+
+def build(force=True):
+    """Compile the oracle with gcc -O2 -fopenmp (no fast-math)."""
+    if not force and os.path.exists(_LIB):
+        return _LIB
+    tmp = _LIB + ".tmp"
+    cmd = ["gcc", "-O2", "-fopenmp", "-std=c11", "-fPIC", "-shared", "-Wall",
+           "-o", tmp, _SRC, "-lm"]
+    subprocess.check_call(cmd)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        L = ctypes.CDLL(_LIB)
+        i, d = ctypes.c_int, ctypes.c_double
+        vp = ctypes.c_void_p
+        sig = {
+            "orc_interp": (None, [i, i, i, _dp, _dp, _dp]),
+            "orc_interp_point": (d, [i, i, i, _dp, d, d, d]),
+            "orc_grad": (None, [i, i, i, _dp, _dp]),
+            "orc_div": (None, [i, i, i, _dp, _dp]),
+            "orc_fft3": (None, [i, i, i, _dp, _dp, i]),
+            "orc_spectral": (None, [i, i, i, _dp, _dp, i, i, d]),
+            "orc_spectral_resample": (None, [i, i, i, _dp, i, i, i, _dp]),
+            "orc_feet": (None, [i, i, i, i, _dp, _dp, _dp]),
+            "orc_adjoint_factor": (None, [i, i, i, i, _dp, _dp, _dp]),
+            "orc_create": (vp, [i, i, i, i, d]),
+            "orc_destroy": (None, [vp]),
+            "orc_set_images": (None, [vp, _dp, _dp]),
+            "orc_set_velocity": (None, [vp, _dp]),
+            "orc_state": (None, [vp]),
+            "orc_objective": (None, [vp, _dp, _dp, _dp]),
+            "orc_gradient": (None, [vp, _dp, _dp, _dp, _dp]),
+            "orc_matvec": (None, [vp, _dp, _dp]),
+            "orc_precond": (None, [vp, _dp, _dp]),
+            "orc_get_field": (None, [vp, i, i, _dp]),
+            "orc_get_velocity": (None, [vp, _dp]),
+            "orc_pcg": (i, [vp, _dp, _dp, i, d, i, _ip]),
+            "orc_solve": (i, [vp, i, i, d, _ip, _dp, _dp, _ip, _dp]),
+            "orc_num_threads": (i, []),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(_dp)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def num_threads():
+    return lib().orc_num_threads()
+
+
+# ------------------------------------------------------------- primitives
+
+def interp(u, d):
+    """I[u](x + d): tricubic Lagrange at node-relative displacements d (3,...)
+    in index units."""
+    u = _f64(u); d = _f64(d)
+    out = np.empty_like(u)
+    lib().orc_interp(*u.shape, _p(u), _p(d), _p(out))
+    return out
+
+
+def interp_point(u, p):
+    u = _f64(u)
+    return lib().orc_interp_point(*u.shape, _p(u), float(p[0]), float(p[1]), float(p[2]))
+
+
+def grad(u):
+    u = _f64(u)
+    g = np.empty((3,) + u.shape)
+    lib().orc_grad(*u.shape, _p(u), _p(g))
+    return g
+
+
+def div(v):
+    v = _f64(v)
+    out = np.empty(v.shape[1:])
+    lib().orc_div(*v.shape[1:], _p(v), _p(out))
+    return out
+
+
+def fft3(z, sign=-1):
+    """Unscaled 3D DFT with exp(sign 2 pi i n k / N)."""
+    z = np.asarray(z, dtype=np.complex128)
+    re = np.ascontiguousarray(z.real); im = np.ascontiguousarray(z.imag)
+    lib().orc_fft3(*z.shape, _p(re), _p(im), int(sign))
+    return re + 1j * im
+
+
+def spectral(u, kind, beta=1.0):
+    """kind 0: beta*A (A = -Laplacian); 1: (beta*A)^-1 with k=0 -> 1/beta;
+    2: identity through the FFT."""
+    u = _f64(u)
+    vec = u.ndim == 4
+    uu = u if vec else u[None]
+    out = np.empty_like(uu)
+    lib().orc_spectral(*uu.shape[1:], _p(uu), _p(out), uu.shape[0], int(kind), float(beta))
+    return out if vec else out[0]
+
+
+def spectral_resample(u, shape):
+    u = _f64(u)
+    out = np.empty(shape)
+    lib().orc_spectral_resample(*u.shape, _p(u), *shape, _p(out))
+    return out
+
+
+def feet(v, nt):
+    v = _f64(v)
+    df = np.empty_like(v); db = np.empty_like(v)
+    lib().orc_feet(*v.shape[1:], int(nt), _p(v), _p(df), _p(db))
+    return df, db
+
+
+def adjoint_factor(v, db, nt):
+    v = _f64(v); db = _f64(db)
+    c = np.empty(v.shape[1:])
+    lib().orc_adjoint_factor(*v.shape[1:], int(nt), _p(v), _p(db), _p(c))
+    return c
+
+
+# ---------------------------------------------------------------- context
+
+FIELD_STATE, FIELD_ADJOINT, FIELD_INC_STATE, FIELD_INC_ADJOINT = 0, 1, 2, 3
+FIELD_FEET_F, FIELD_FEET_B, FIELD_ADJ_FACTOR = 4, 5, 6
+
+
+class Oracle:
+    """Registration problem on an n1 x n2 x n3 periodic grid over [0, 2pi)^3."""
+
+    def __init__(self, shape, nt=4, beta=5e-4):
+        self.shape = tuple(int(s) for s in shape)
+        self.nt = int(nt)
+        self.beta = float(beta)
+        self._h = lib().orc_create(*self.shape, self.nt, self.beta)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().orc_destroy(h)
+            self._h = None
+
+    def set_images(self, m0, m1):
+        m0 = _f64(m0); m1 = _f64(m1)
+        lib().orc_set_images(self._h, _p(m0), _p(m1))
+
+    def set_velocity(self, v):
+        v = _f64(v)
+        lib().orc_set_velocity(self._h, _p(v))
+
+    def velocity(self):
+        v = np.empty((3,) + self.shape)
+        lib().orc_get_velocity(self._h, _p(v))
+        return v
+
+    def state(self):
+        lib().orc_state(self._h)
+
+    def objective(self):
+        J, m, r = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        lib().orc_objective(self._h, ctypes.byref(J), ctypes.byref(m), ctypes.byref(r))
+        return J.value, m.value, r.value
+
+    def gradient(self):
+        g = np.empty((3,) + self.shape)
+        J, m, r = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        lib().orc_gradient(self._h, _p(g), ctypes.byref(J), ctypes.byref(m), ctypes.byref(r))
+        return g, (J.value, m.value, r.value)
+
+    def matvec(self, vt):
+        vt = _f64(vt)
+        out = np.empty_like(vt)
+        lib().orc_matvec(self._h, _p(vt), _p(out))
+        return out
+
+    def precond(self, r):
+        r = _f64(r)
+        out = np.empty_like(r)
+        lib().orc_precond(self._h, _p(r), _p(out))
+        return out
+
+    def field(self, which, j=0):
+        n = 3 if which in (FIELD_FEET_F, FIELD_FEET_B) else 1
+        out = np.empty((n,) + self.shape) if n == 3 else np.empty(self.shape)
+        lib().orc_get_field(self._h, int(which), int(j), _p(out))
+        return out
+
+    def pcg(self, rhs, max_pcg, eta, forced_iters=-1):
+        rhs = _f64(rhs)
+        x = np.empty_like(rhs)
+        its = ctypes.c_int()
+        neg = lib().orc_pcg(self._h, _p(rhs), _p(x), int(max_pcg), float(eta), int(forced_iters), ctypes.byref(its))
+        return x, its.value, bool(neg)
+
+    def solve(self, max_outer=5, max_pcg=10, gtol=1e-2, forced_pcg=None, forced_alpha=None):
+        """Gauss-Newton-Krylov from the current velocity.  Returns
+        (status, log rows [k, J, mismatch, reg, ||g||, pcg_its, alpha, ls_trials],
+        gref).  status 0 converged, 1 iteration limit, 2 line search failed."""
+        log = np.zeros((max_outer + 1, 8))
+        nout = ctypes.c_int()
+        gref = ctypes.c_double()
+        fp = None
+        fa = None
+        if forced_pcg is not None:
+            fpa = np.ascontiguousarray(forced_pcg, dtype=np.int32)
+            fp = fpa.ctypes.data_as(_ip)
+        if forced_alpha is not None:
+            faa = _f64(forced_alpha)
+            fa = _p(faa)
+        st = lib().orc_solve(self._h, int(max_outer), int(max_pcg), float(gtol), fp, fa,
+                             _p(log), ctypes.byref(nout), ctypes.byref(gref))
+        return st, log[: nout.value + 1], gref.value

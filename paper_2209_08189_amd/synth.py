@@ -1,0 +1,138 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the oracle.
+
+This module draws and samples inputs only; it holds none of the registration
+method's arithmetic (no transport, no derivatives, no solver).  Where an input
+is defined as "an image transported by a velocity" the caller performs that
+transport with whichever implementation it is exercising.
+
+Workloads (periodic grid on [0, 2 pi)^3, node-centred x_i = 2 pi i / N):
+
+* ``trig_template`` / ``trig_velocity``: the closed-form 64^3 problem:
+  m0 = (sin^2 x1 + sin^2 x2 + sin^2 x3) / 3 and
+  v* = a (sin x3 cos x2 sin x2, sin x1 cos x3 sin x3, sin x2 cos x1 sin x1).
+* ``phantom``: brain-like piecewise-constant phantom standing in for the
+  paper's 256^3 T1 brain MRI (MUSE/NIREP): 4 classes (background, CSF-, GM-
+  and WM-like) from thresholded sums of periodic Gaussian blobs, smoothed with
+  a Gaussian of sigma = 1 voxel, intensities in [0, 1].
+* ``smooth_velocity``: random band-limited velocity (|k| <= kmax) scaled to a
+  given maximum displacement in voxels over unit time.
+* ``noise``: independent N(0, sigma^2) noise fields.
+"""
+import numpy as np
+
+TWO_PI = 2.0 * np.pi
+
+
+def grid(shape):
+    """Node coordinates x_d = 2 pi i_d / N_d as three broadcastable arrays."""
+    n1, n2, n3 = shape
+    x1 = (TWO_PI * np.arange(n1) / n1)[:, None, None]
+    x2 = (TWO_PI * np.arange(n2) / n2)[None, :, None]
+    x3 = (TWO_PI * np.arange(n3) / n3)[None, None, :]
+    return x1, x2, x3
+
+
+def trig_template(shape):
+    x1, x2, x3 = grid(shape)
+    m = (np.sin(x1) ** 2 + np.sin(x2) ** 2 + np.sin(x3) ** 2) / 3.0
+    return np.broadcast_to(m, shape).copy()
+
+
+def trig_velocity(shape, amplitude=0.5):
+    x1, x2, x3 = grid(shape)
+    v = np.empty((3,) + tuple(shape))
+    v[0] = np.broadcast_to(np.sin(x3) * np.cos(x2) * np.sin(x2), shape)
+    v[1] = np.broadcast_to(np.sin(x1) * np.cos(x3) * np.sin(x3), shape)
+    v[2] = np.broadcast_to(np.sin(x2) * np.cos(x1) * np.sin(x1), shape)
+    return amplitude * v
+
+
+def _fft_k(n):
+    return np.fft.fftfreq(n, d=1.0 / n)
+
+
+def phantom(shape, seed, n_blobs=(20, 40), sigma=(8.0, 30.0), smooth_sigma=1.0,
+            intensities=(0.0, 0.3, 0.6, 0.9), bg_frac=0.15):
+    """Brain-like phantom.  Returns (image float64 in [0,1], labels uint8 in 0..3).
+
+    Blob centres are uniform in [0.2 N, 0.8 N]^3 so the object sits in a zero
+    background (the images are periodic); sigma in voxels; amplitudes in
+    [0.5, 1].  Voxels with S < bg_frac * max S are background; the foreground
+    is split into three classes at the 1/3 and 2/3 quantiles of S.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    shape = tuple(int(s) for s in shape)
+    nb = int(rng.integers(n_blobs[0], n_blobs[1] + 1))
+    S = np.zeros(shape)
+    axes = [np.arange(n, dtype=np.float64) for n in shape]
+    for _ in range(nb):
+        c = [rng.uniform(0.2 * n, 0.8 * n) for n in shape]
+        s = rng.uniform(sigma[0], sigma[1])
+        a = rng.uniform(0.5, 1.0)
+        g = []
+        for ax, n, cc in zip(axes, shape, c):
+            d = np.abs(ax - cc)
+            d = np.minimum(d, n - d)                      # periodic distance
+            g.append(np.exp(-0.5 * (d / s) ** 2))
+        S += a * (g[0][:, None, None] * g[1][None, :, None] * g[2][None, None, :])
+    fg = S >= bg_frac * S.max()
+    q1, q2 = np.quantile(S[fg], [1.0 / 3.0, 2.0 / 3.0])
+    labels = np.zeros(shape, dtype=np.uint8)
+    labels[fg & (S < q1)] = 1
+    labels[fg & (S >= q1) & (S < q2)] = 2
+    labels[fg & (S >= q2)] = 3
+    img = np.asarray(intensities, dtype=np.float64)[labels]
+    if smooth_sigma > 0:
+        k1, k2, k3 = (_fft_k(n) for n in shape)
+        h = [TWO_PI / n for n in shape]
+        # Gaussian of smooth_sigma voxels as a Fourier multiplier
+        mult = (np.exp(-0.5 * (smooth_sigma * h[0] * k1) ** 2)[:, None, None]
+                * np.exp(-0.5 * (smooth_sigma * h[1] * k2) ** 2)[None, :, None]
+                * np.exp(-0.5 * (smooth_sigma * h[2] * k3[: shape[2] // 2 + 1]) ** 2)[None, None, :])
+        img = np.fft.irfftn(np.fft.rfftn(img) * mult, s=shape)
+    return np.clip(img, 0.0, 1.0), labels
+
+
+def smooth_velocity(shape, seed, kmax=8.0, max_disp_voxels=6.0):
+    """Random velocity: complex N(0,1) Fourier coefficients on 1 <= |k| <= kmax
+    weighted by 1/(1+|k|^2), real part of the inverse FFT, scaled so that
+    max_x |v(x)|_2 = max_disp_voxels * (2 pi / N) (displacement over t in [0,1])."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    shape = tuple(int(s) for s in shape)
+    k1, k2, k3 = (_fft_k(n) for n in shape)
+    ksq = k1[:, None, None] ** 2 + k2[None, :, None] ** 2 + k3[None, None, :] ** 2
+    band = (ksq >= 1.0) & (ksq <= kmax * kmax)
+    idx = np.nonzero(band)
+    v = np.empty((3,) + shape)
+    for c in range(3):
+        coef = np.zeros(shape, dtype=np.complex128)
+        z = rng.standard_normal(len(idx[0])) + 1j * rng.standard_normal(len(idx[0]))
+        coef[idx] = z / (1.0 + ksq[idx])
+        v[c] = np.fft.ifftn(coef).real
+    vmax = np.sqrt((v ** 2).sum(axis=0)).max()
+    h = TWO_PI / max(shape)
+    return v * (max_disp_voxels * h / vmax)
+
+
+def noise(shape, seed, sigma=0.02):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return sigma * rng.standard_normal(tuple(shape))
+
+
+def random_field(shape, seed, lo=-1.0, hi=1.0):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.uniform(lo, hi, size=tuple(shape))
+
+
+def smooth_random_field(shape, seed, kmax=4.0):
+    """Band-limited random scalar field (real part of random Fourier modes
+    with |k| <= kmax), normalised to max |u| = 1."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    shape = tuple(int(s) for s in shape)
+    k1, k2, k3 = (_fft_k(n) for n in shape)
+    ksq = k1[:, None, None] ** 2 + k2[None, :, None] ** 2 + k3[None, None, :] ** 2
+    idx = np.nonzero(ksq <= kmax * kmax)
+    coef = np.zeros(shape, dtype=np.complex128)
+    coef[idx] = rng.standard_normal(len(idx[0])) + 1j * rng.standard_normal(len(idx[0]))
+    u = np.fft.ifftn(coef).real
+    return u / np.abs(u).max()
