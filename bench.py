@@ -1,0 +1,201 @@
+"""Benchmark: Gauss-Newton Hessian matvecs per second at 256^3 on one MI355X.
+
+Workload: brain-like phantom pair at 256^3 (4 tissue classes from thresholded
+sums of seeded Gaussian blobs, sigma = 1 voxel smoothing, N(0, 0.02^2) noise;
+m1 = phantom transported by a seeded band-limited velocity with a maximum
+displacement of 6 voxels), nt = 4, beta_v = 5e-4, FP32.  The matvec is taken
+at v = v_true with vt = -P^-1 g(v_true), inputs resident on the device.
+
+One step = one GN Hessian matvec (incremental state, incremental adjoint,
+quadrature, spectral beta A vt) through the C ABI.  The line also carries
+the roofline of the dominant transport kernel (HIP-event timed over the
+timed region), a per-kernel-class table, a plain FP32 time-to-tolerance
+solve, and the FP64 CPU oracle timed on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def make_inputs(n, seed):
+    from paper_2209_08189_amd import synth
+    shape = (n, n, n)
+    img, labels = synth.phantom(shape, seed)
+    v_true = synth.smooth_velocity(shape, seed + 1, kmax=8.0, max_disp_voxels=6.0)
+    n0 = synth.noise(shape, seed + 2, 0.02)
+    n1 = synth.noise(shape, seed + 3, 0.02)
+    return img.astype(np.float32), labels, v_true.astype(np.float32), n0.astype(np.float32), n1.astype(np.float32)
+
+
+# algorithmic bytes per launch in units of one FP32 field F (one value per node)
+ALG_F = {
+    "sl_state": 5,      # gather 1 + feet 3 + write 1
+    "sl_adjoint": 6,    # gather 1 + feet 3 + c 1 + write 1
+    "sl_inc": 9,        # gather 1 + feet 3 + vt 3 + m^{j+1} 1 + write 1
+}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--cpu-n", type=int, default=128)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only; this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2209_08189_amd.claire import Registration, K_NAMES, K_SL_INC
+
+    torch.cuda.set_device(0)
+    n = args.n
+    shape = (n, n, n)
+    N = n ** 3
+    F = 4.0 * N
+    log("generating %d^3 phantom (seed %d)" % (n, args.seed))
+    img, labels, v_true, n0, n1 = make_inputs(n, args.seed)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+    r = Registration(shape, nt=4, beta_v=5e-4, gtol=1e-2, max_outer=50, max_pcg=10)
+    # m1 = phantom transported by v_true (forward SL solve on the GPU), then noise
+    ph = dev(img)
+    r.set_images(ph, ph)
+    r.set_velocity(dev(v_true))
+    m1 = r.deformed_template() + dev(n1)
+    m0 = ph + dev(n0)
+    r.set_images(m0, m1)
+    r.set_velocity(dev(v_true))
+    g, gnorm, J = r.gradient()
+    vt = -r.precond(g)
+    Hv = torch.empty_like(vt)
+    torch.cuda.synchronize()
+
+    log("warmup %d matvecs" % args.warmup)
+    for _ in range(args.warmup):
+        r.hessian_matvec(vt, Hv)
+    torch.cuda.synchronize()
+
+    # per-class ranking (untimed pass with all classes evented)
+    r.profile_enable(0xFF)
+    for _ in range(3):
+        r.hessian_matvec(vt, Hv)
+    per_class = {}
+    for k, name in enumerate(K_NAMES):
+        ms, cnt = r.profile_query(k)
+        if cnt:
+            per_class[name] = {"ms_per_matvec": ms / 3, "launches_per_matvec": cnt / 3, "avg_launch_ms": ms / cnt}
+    transport = [k for k in ("sl_inc", "sl_adjoint") if k in per_class]
+    dom = max(transport, key=lambda k: per_class[k]["ms_per_matvec"])
+    dom_id = K_NAMES.index(dom)
+
+    # timed region: K matvecs, events only around the dominant transport kernel
+    r.profile_enable(1 << dom_id)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r.hessian_matvec(vt, Hv)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    dom_ms, dom_n = r.profile_query(dom_id)
+    r.profile_enable(0)
+    elapsed = t1 - t0
+    ms_step = 1e3 * elapsed / args.steps
+    value = args.steps / elapsed
+    avg_ms = dom_ms / dom_n
+    alg_bytes = ALG_F[dom] * F
+    achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
+    log("matvec %.3f ms  (%.1f matvecs/s); %s avg %.3f ms -> %.0f GB/s" % (ms_step, value, dom, avg_ms, achieved))
+
+    for name, d in per_class.items():
+        if name in ALG_F:
+            d["alg_GBs"] = ALG_F[name] * F / (d["avg_launch_ms"] * 1e-3) / 1e9
+
+    # plain FP32 GN solve to relative gradient 1e-2 from v = 0
+    solve = None
+    if not args.no_solve:
+        rs = Registration(shape, nt=4, beta_v=5e-4, gtol=1e-2, max_outer=50, max_pcg=10)
+        rs.set_images(m0, m1)
+        rs.set_velocity(torch.zeros((3,) + shape, device="cuda"))
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        rep = rs.solve()
+        torch.cuda.synchronize()
+        te = time.perf_counter()
+        mis0 = 0.5 * float(((m0 - m1).double() ** 2).sum()) * (2 * np.pi / n) ** 3
+        solve = {"status": rep["status_name"], "time_to_tol_s": te - ts, "outer_iters": rep["outer_iters"],
+                 "pcg_iters": rep["pcg_iters_total"], "ls_trials": rep["linesearch_trials"],
+                 "rel_grad": rep["gnorm"] / rep["gref"], "r": rep["mismatch"] / mis0}
+        log("solve: %s" % json.dumps(solve))
+        del rs
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        cn = args.cpu_n
+        cshape = (cn, cn, cn)
+        cimg, _, cv, c0, c1 = make_inputs(cn, args.seed)
+        o = oracle.Oracle(cshape, nt=4, beta=5e-4)
+        o.set_images(cimg, cimg)
+        o.set_velocity(cv)
+        o.state()
+        cm1 = o.field(oracle.FIELD_STATE, 4) + c1
+        o.set_images(cimg + c0, cm1)
+        o.set_velocity(cv)
+        cg, _ = o.gradient()
+        cvt = -o.precond(cg)
+        tc = time.perf_counter()
+        o.matvec(cvt)
+        tc = time.perf_counter() - tc
+        scale = (n / cn) ** 3
+        cpu = {"value": 1.0 / (tc * scale), "unit": "matvecs/s", "cores": oracle.num_threads(), "kind": "oracle",
+               "sample": "one FP64 oracle Hessian matvec at %d^3 (%.1f s), scaled by the voxel ratio %.0f to %d^3"
+                         % (cn, tc, scale, n)}
+        log("cpu oracle: %s" % json.dumps(cpu))
+
+    out = {
+        "metric": "Hessian matvecs/s at 256^3 (GN-Krylov registration, nt=4, tricubic SL, FP32)",
+        "value": value,
+        "unit": "matvecs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "brain-like phantom pair %d^3, seed %d, v = v_true (6 voxel max displacement), "
+                               "vt = -P^-1 g" % (n, args.seed),
+                   "grid": n, "nt": 4, "beta_v": 5e-4, "interp": "tricubic Lagrange", "fd": "8th order"},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": avg_ms, "launches": dom_n},
+        "kernels": per_class,
+        "solve_fp32": solve,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,201 @@
+/*
+ * claire_hip.h -- C ABI of the MI355X (gfx950) implementation of the
+ * Gauss-Newton-Krylov hot path of stationary-velocity diffeomorphic image
+ * registration (Himthani et al., CLAIRE, arXiv 2209.08189).
+ *
+ * Problem (Section 2.1, optimal-control problem): given a template image m0
+ * and a reference image m1 on the periodic domain [0, 2pi)^3, find a
+ * stationary velocity v minimising
+ *     1/2 ||m(1) - m1||^2 + beta_v/2 <A v, v>,
+ * where m solves the transport equation d_t m + v . grad m = 0, m(0) = m0,
+ * and A = -Laplacian (H1 seminorm; beta_w = 0, so the Leray-like operator K
+ * is the identity).
+ *
+ * Conventions that hold for every entry point:
+ *   - Grid: n1 x n2 x n3 nodes x_i = 2 pi i / n, each n_d a power of two,
+ *     16 <= n_d <= 1024.  Fields are C order [x1][x2][x3] (x3 fastest);
+ *     vector fields are three such arrays back to back ([3][n1][n2][n3]).
+ *   - Every buffer argument is a DEVICE pointer owned by the caller.  The
+ *     library copies inputs at the set_* calls and never keeps a caller
+ *     pointer.  Input and output buffers of one call must not overlap
+ *     (CL_ERR_ALIAS).  All library memory is allocated in cl_create.
+ *   - All device work is enqueued on the stream given in cl_options (NULL =
+ *     the default stream).  Calls returning host scalars synchronise that
+ *     stream; cl_hessian_matvec, cl_precond_apply, cl_set_* and the field
+ *     accessors only enqueue.
+ *   - Return value: CL_OK (0), a negative error code, or a positive
+ *     non-fatal status.  No exception, abort or exit crosses this boundary;
+ *     the message of the last error of a context is cl_last_error(ctx).
+ *   - A context is not thread safe: one context per host thread.
+ */
+#ifndef CLAIRE_HIP_H
+#define CLAIRE_HIP_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CL_OPTIONS_VERSION 1
+
+typedef struct cl_ctx cl_ctx;
+
+/* Storage precision of the scalar fields (images, state, adjoint and
+ * incremental fields).  Arithmetic is FP32; Krylov dot products, norms and
+ * the objective are reduced in FP64 whatever the storage. */
+typedef enum { CL_F32 = 0, CL_BF16 = 1, CL_F16 = 2 } cl_dtype;
+
+enum {
+    CL_OK = 0,
+    CL_ERR_ARG = -1,          /* NULL pointer, bad option value */
+    CL_ERR_SHAPE = -2,        /* n_d not a power of two in [16, 1024] */
+    CL_ERR_DTYPE = -3,        /* unsupported cl_dtype */
+    CL_ERR_OOM = -4,          /* device allocation failed or workspace cap exceeded */
+    CL_ERR_HIP = -5,          /* a HIP runtime call failed */
+    CL_ERR_NONFINITE = -6,    /* NaN or Inf found in an input */
+    CL_ERR_UNSUPPORTED = -7,  /* option outside this build (e.g. beta_w != 0) */
+    CL_ERR_STATE = -8,        /* call order violated (e.g. gradient before set_images) */
+    CL_ERR_ALIAS = -9,        /* input and output buffers overlap */
+    CL_STATUS_MAXIT = 1,      /* solve stopped at max_outer */
+    CL_STATUS_LINESEARCH_FAIL = 2 /* Armijo found no step; last accepted v kept */
+};
+
+typedef struct {
+    int struct_version;       /* must be CL_OPTIONS_VERSION */
+    int nt;                   /* semi-Lagrangian time steps, >= 1 (default 4) */
+    double beta_v;            /* H1-seminorm regularisation weight, > 0 (default 5e-4) */
+    double beta_w;            /* divergence regularisation; must be 0 in this build */
+    double gtol;              /* stop when ||g|| <= gtol ||g(v=0)|| (default 1e-2) */
+    int max_outer;            /* Gauss-Newton iteration limit (default 50) */
+    int max_pcg;              /* PCG iteration limit per GN step (default 10) */
+    int forcing;              /* 1: eta = min(0.5, sqrt(||g||/||g(0)||)); 0: eta = eta_fixed */
+    double eta_fixed;
+    int storage_state;        /* cl_dtype of m0, m1 and the state m^j (default CL_F32) */
+    int storage_adjoint;      /* cl_dtype of the adjoint and incremental fields (default CL_F32) */
+    void *stream;             /* hipStream_t; NULL = default stream */
+    unsigned long long workspace_cap_bytes; /* 0 = no cap; else cl_create fails with CL_ERR_OOM above it */
+} cl_options;
+
+typedef struct {
+    int status;               /* CL_OK (converged), CL_STATUS_MAXIT or CL_STATUS_LINESEARCH_FAIL */
+    int outer_iters;          /* GN steps taken */
+    int pcg_iters_total;
+    int linesearch_trials;    /* objective evaluations in the line searches */
+    double J0, J;             /* objective at the start and at the final v */
+    double mismatch, reg;     /* parts of the final J */
+    double gnorm0, gnorm;     /* ||g|| at the start and at the final v */
+    double gref;              /* ||g(v = 0)||, the reference of the stopping test */
+    double ms;                /* wall time of the solve */
+} cl_solve_report;
+
+/* Fill *opt with the defaults listed above. */
+void cl_default_options(cl_options *opt);
+
+/* Device bytes cl_create would allocate for this grid and options. */
+int cl_query_workspace(int n1, int n2, int n3, const cl_options *opt, unsigned long long *bytes);
+
+/* Create a context on the current HIP device; allocates all workspace. */
+int cl_create(cl_ctx **out, int n1, int n2, int n3, const cl_options *opt);
+void cl_destroy(cl_ctx *ctx);
+
+/* Template m0 and reference m1 (Section 2.1), each n1*n2*n3 values of type
+ * dt (CL_F32 only in this build) on the device; copied and converted to the
+ * context's storage precision.  Rejects NaN/Inf (CL_ERR_NONFINITE). */
+int cl_set_images(cl_ctx *ctx, const void *m0, const void *m1, int dt);
+
+/* Stationary velocity v, FP32 [3][n1][n2][n3] on the device (copied).
+ * Recomputes the RK2 characteristic feet of both directions and the adjoint
+ * divergence factor (Section 2.2, semi-Lagrangian scheme). */
+int cl_set_velocity(cl_ctx *ctx, const float *v);
+int cl_get_velocity(cl_ctx *ctx, float *v_out);
+
+/* Objective J = mismatch + reg at the current v (Section 2.1); synchronises. */
+int cl_objective(cl_ctx *ctx, double *J, double *mismatch, double *reg);
+
+/* Reduced gradient g = beta_v A v + int_0^1 lambda grad m dt (Section 2.2,
+ * reduced gradient) at the current v.  g_out (FP32 [3][n1][n2][n3], may be
+ * NULL) receives g; *gnorm (may be NULL) receives sqrt(h1h2h3 sum g.g);
+ * J (may be NULL) the objective.  Synchronises. */
+int cl_gradient(cl_ctx *ctx, float *g_out, double *gnorm, double *J);
+
+/* Gauss-Newton Hessian matvec H vt = beta_v A vt + int lambda~ grad m dt
+ * (Section 2.2, Hessian matvec; two transport solves) at the current v.
+ * Needs the state of the current v (computed by cl_gradient or
+ * cl_objective).  Enqueued only, no synchronisation. */
+int cl_hessian_matvec(cl_ctx *ctx, const float *vt, float *Hvt);
+
+/* Spectral preconditioner z = (beta_v A)^-1 r with the k = 0 mode scaled by
+ * 1/beta_v.  Enqueued only. */
+int cl_precond_apply(cl_ctx *ctx, const float *r, float *z);
+
+/* Gauss-Newton-Krylov solve with Armijo line search from the current v
+ * (Section 2.2, Gauss-Newton-Krylov solver); on return the context holds
+ * the final v.  rep may be NULL. */
+int cl_solve(cl_ctx *ctx, cl_solve_report *rep);
+
+/* Same, but replaying given decisions: step k runs exactly forced_pcg[k]
+ * PCG iterations (fewer only on negative curvature) and takes the step
+ * length forced_alpha[k], for n_outer steps, with no stopping test. */
+int cl_solve_forced(cl_ctx *ctx, const int *forced_pcg, const double *forced_alpha,
+                    int n_outer, cl_solve_report *rep);
+
+/* Per-iteration log of the last solve: rows of 8 doubles (k, J, mismatch,
+ * reg, ||g||, pcg iterations, alpha, line-search trials); the last row is
+ * the final iterate.  Copies min(*n_rows, max_rows) rows. */
+int cl_get_solve_log(cl_ctx *ctx, double *rows, int max_rows, int *n_rows);
+
+/* Deformed template m(t = 1) at the current v, FP32 on the device. */
+int cl_deformed_template(cl_ctx *ctx, float *m_out);
+
+/* Read an internal field into an FP32 device buffer (inspection and
+ * parity tests): which = CL_FIELD_*, j = time index 0..nt where relevant. */
+enum {
+    CL_FIELD_STATE = 0,       /* m^j, last objective/gradient */
+    CL_FIELD_ADJOINT = 1,     /* lambda^j, last gradient */
+    CL_FIELD_INC_STATE = 2,   /* mt^nt of the last matvec (only j = nt is kept) */
+    CL_FIELD_INC_ADJOINT = 3, /* lambda~^j, last matvec */
+    CL_FIELD_FEET_F = 4,      /* forward feet, index-unit displacements, 3 fields */
+    CL_FIELD_FEET_B = 5,      /* backward feet, 3 fields */
+    CL_FIELD_ADJ_FACTOR = 6   /* adjoint divergence factor c */
+};
+int cl_get_field(cl_ctx *ctx, int which, int j, float *out);
+
+/* Building blocks on the context's grid (parity tests of single kernels):
+ *   cl_interp:   out(x) = I[u](x + d(x)), tricubic Lagrange, d in index units (3 fields)
+ *   cl_fd_grad:  g = grad_h u, 8th-order central differences (3 fields out)
+ *   cl_fd_div:   out = div_h v (3 fields in)
+ *   cl_spectral: kind 0: beta_v A, 1: (beta_v A)^-1 (k = 0 -> 1/beta_v),
+ *                2: identity through the FFT; ncomp fields in and out. */
+int cl_interp(cl_ctx *ctx, const float *u, const float *d, float *out);
+int cl_fd_grad(cl_ctx *ctx, const float *u, float *g);
+int cl_fd_div(cl_ctx *ctx, const float *v, float *out);
+int cl_spectral(cl_ctx *ctx, int kind, int ncomp, const float *in, float *out);
+
+/* FP64 inner product h1h2h3 sum a.b of two FP32 device vectors of n values;
+ * synchronises. */
+int cl_dot(cl_ctx *ctx, const float *a, const float *b, size_t n, double *out);
+
+/* Plain device copy of n floats on the context stream (bandwidth
+ * calibration of the memory counters). */
+int cl_copy_f32(cl_ctx *ctx, const float *src, float *dst, size_t n);
+
+/* Per-kernel timing with HIP events on the context stream.  mask selects
+ * kernel classes (bit = 1 << CL_K_*); 0 disables.  cl_profile_query returns
+ * the summed milliseconds and launch count of one class since the last
+ * enable; synchronises. */
+enum {
+    CL_K_FEET = 0, CL_K_SL_STATE = 1, CL_K_SL_ADJOINT = 2, CL_K_SL_INC = 3,
+    CL_K_FD = 4, CL_K_QUAD = 5, CL_K_FFT = 6, CL_K_VEC = 7, CL_K_COUNT = 8
+};
+int cl_profile_enable(cl_ctx *ctx, unsigned mask);
+int cl_profile_query(cl_ctx *ctx, int kclass, double *ms_total, long long *launches);
+const char *cl_kernel_class_name(int kclass);
+
+const char *cl_status_string(int status);
+const char *cl_last_error(const cl_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CLAIRE_HIP_H */

@@ -1,0 +1,295 @@
+"""Thin ctypes binding of libclairehip.so (include/claire_hip.h).
+
+Argument marshalling only: every step of the registration hot path runs in
+the library's HIP kernels.  PyTorch provides device memory and the stream.
+The library must have been built (``python -m paper_2209_08189_amd.build``);
+there is no fallback.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libclairehip.so")
+
+CL_F32, CL_BF16, CL_F16 = 0, 1, 2
+DTYPES = {"f32": CL_F32, "bf16": CL_BF16, "f16": CL_F16}
+CL_OPTIONS_VERSION = 1
+
+FIELD_STATE, FIELD_ADJOINT, FIELD_INC_STATE, FIELD_INC_ADJOINT = 0, 1, 2, 3
+FIELD_FEET_F, FIELD_FEET_B, FIELD_ADJ_FACTOR = 4, 5, 6
+
+K_FEET, K_SL_STATE, K_SL_ADJOINT, K_SL_INC, K_FD, K_QUAD, K_FFT, K_VEC = range(8)
+K_NAMES = ["feet", "sl_state", "sl_adjoint", "sl_inc", "fd", "quadrature", "fft", "vec"]
+
+STATUS = {0: "ok", 1: "maxit", 2: "linesearch_fail"}
+
+
+class cl_options(ctypes.Structure):
+    _fields_ = [
+        ("struct_version", ctypes.c_int),
+        ("nt", ctypes.c_int),
+        ("beta_v", ctypes.c_double),
+        ("beta_w", ctypes.c_double),
+        ("gtol", ctypes.c_double),
+        ("max_outer", ctypes.c_int),
+        ("max_pcg", ctypes.c_int),
+        ("forcing", ctypes.c_int),
+        ("eta_fixed", ctypes.c_double),
+        ("storage_state", ctypes.c_int),
+        ("storage_adjoint", ctypes.c_int),
+        ("stream", ctypes.c_void_p),
+        ("workspace_cap_bytes", ctypes.c_ulonglong),
+    ]
+
+
+class cl_solve_report(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int),
+        ("outer_iters", ctypes.c_int),
+        ("pcg_iters_total", ctypes.c_int),
+        ("linesearch_trials", ctypes.c_int),
+        ("J0", ctypes.c_double),
+        ("J", ctypes.c_double),
+        ("mismatch", ctypes.c_double),
+        ("reg", ctypes.c_double),
+        ("gnorm0", ctypes.c_double),
+        ("gnorm", ctypes.c_double),
+        ("gref", ctypes.c_double),
+        ("ms", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["status_name"] = STATUS.get(self.status, str(self.status))
+        return d
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_i = ctypes.c_int
+_d = ctypes.c_double
+_dp = ctypes.POINTER(ctypes.c_double)
+
+SIGNATURES = {
+    "cl_default_options": (None, [ctypes.POINTER(cl_options)]),
+    "cl_query_workspace": (_i, [_i, _i, _i, ctypes.POINTER(cl_options), ctypes.POINTER(ctypes.c_ulonglong)]),
+    "cl_create": (_i, [ctypes.POINTER(_vp), _i, _i, _i, ctypes.POINTER(cl_options)]),
+    "cl_destroy": (None, [_vp]),
+    "cl_set_images": (_i, [_vp, _vp, _vp, _i]),
+    "cl_set_velocity": (_i, [_vp, _vp]),
+    "cl_get_velocity": (_i, [_vp, _vp]),
+    "cl_objective": (_i, [_vp, _dp, _dp, _dp]),
+    "cl_gradient": (_i, [_vp, _vp, _dp, _dp]),
+    "cl_hessian_matvec": (_i, [_vp, _vp, _vp]),
+    "cl_precond_apply": (_i, [_vp, _vp, _vp]),
+    "cl_solve": (_i, [_vp, ctypes.POINTER(cl_solve_report)]),
+    "cl_solve_forced": (_i, [_vp, ctypes.POINTER(_i), _dp, _i, ctypes.POINTER(cl_solve_report)]),
+    "cl_get_solve_log": (_i, [_vp, _dp, _i, ctypes.POINTER(_i)]),
+    "cl_deformed_template": (_i, [_vp, _vp]),
+    "cl_get_field": (_i, [_vp, _i, _i, _vp]),
+    "cl_interp": (_i, [_vp, _vp, _vp, _vp]),
+    "cl_fd_grad": (_i, [_vp, _vp, _vp]),
+    "cl_fd_div": (_i, [_vp, _vp, _vp]),
+    "cl_spectral": (_i, [_vp, _i, _i, _vp, _vp]),
+    "cl_dot": (_i, [_vp, _vp, _vp, ctypes.c_size_t, _dp]),
+    "cl_copy_f32": (_i, [_vp, _vp, _vp, ctypes.c_size_t]),
+    "cl_profile_enable": (_i, [_vp, ctypes.c_uint]),
+    "cl_profile_query": (_i, [_vp, _i, _dp, ctypes.POINTER(ctypes.c_longlong)]),
+    "cl_kernel_class_name": (ctypes.c_char_p, [_i]),
+    "cl_status_string": (ctypes.c_char_p, [_i]),
+    "cl_last_error": (ctypes.c_char_p, [_vp]),
+}
+
+
+def lib():
+    """Load libclairehip.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libclairehip.so is not built (python -m paper_2209_08189_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+class ClaireError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (lib().cl_status_string(code).decode(), code, msg))
+        self.code = code
+
+
+def default_options():
+    o = cl_options()
+    lib().cl_default_options(ctypes.byref(o))
+    return o
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Registration:
+    """One registration problem on an n1 x n2 x n3 periodic grid, on the
+    current CUDA(HIP) device and torch's current stream."""
+
+    def __init__(self, shape, nt=4, beta_v=5e-4, gtol=1e-2, max_outer=50, max_pcg=10,
+                 forcing=1, eta_fixed=0.1, storage_state="f32", storage_adjoint="f32",
+                 workspace_cap=0, stream=None):
+        import torch
+        self.torch = torch
+        self.shape = tuple(int(s) for s in shape)
+        self.N = self.shape[0] * self.shape[1] * self.shape[2]
+        o = default_options()
+        o.nt = int(nt)
+        o.beta_v = float(beta_v)
+        o.gtol = float(gtol)
+        o.max_outer = int(max_outer)
+        o.max_pcg = int(max_pcg)
+        o.forcing = int(forcing)
+        o.eta_fixed = float(eta_fixed)
+        o.storage_state = DTYPES[storage_state]
+        o.storage_adjoint = DTYPES[storage_adjoint]
+        o.workspace_cap_bytes = int(workspace_cap)
+        s = stream if stream is not None else torch.cuda.current_stream()
+        self.stream = s
+        o.stream = ctypes.c_void_p(s.cuda_stream)
+        self.opt = o
+        self.nt = o.nt
+        h = ctypes.c_void_p()
+        st = lib().cl_create(ctypes.byref(h), *self.shape, ctypes.byref(o))
+        if st != 0:
+            raise ClaireError(st, "cl_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().cl_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -------------------------------------------------------------- helpers
+    def _chk(self, st):
+        if st < 0:
+            raise ClaireError(st, lib().cl_last_error(self._h).decode())
+        return st
+
+    def _dev(self, t, n, name):
+        torch = self.torch
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+            raise TypeError("%s must be a contiguous float32 CUDA tensor" % name)
+        if t.numel() != n:
+            raise ValueError("%s has %d values, expected %d" % (name, t.numel(), n))
+        return _ptr(t)
+
+    def empty(self, ncomp=1):
+        shp = ((ncomp,) if ncomp > 1 else ()) + self.shape
+        return self.torch.empty(shp, dtype=self.torch.float32, device="cuda")
+
+    # ------------------------------------------------------------------ API
+    def set_images(self, m0, m1):
+        self._chk(lib().cl_set_images(self._h, self._dev(m0, self.N, "m0"), self._dev(m1, self.N, "m1"), CL_F32))
+
+    def set_velocity(self, v):
+        self._chk(lib().cl_set_velocity(self._h, self._dev(v, 3 * self.N, "v")))
+
+    def velocity(self):
+        out = self.empty(3)
+        self._chk(lib().cl_get_velocity(self._h, _ptr(out)))
+        return out
+
+    def objective(self):
+        J, m, r = _d(), _d(), _d()
+        self._chk(lib().cl_objective(self._h, ctypes.byref(J), ctypes.byref(m), ctypes.byref(r)))
+        return J.value, m.value, r.value
+
+    def gradient(self, want_g=True):
+        g = self.empty(3) if want_g else None
+        gn, J = _d(), _d()
+        self._chk(lib().cl_gradient(self._h, _ptr(g) if g is not None else None, ctypes.byref(gn), ctypes.byref(J)))
+        return g, gn.value, J.value
+
+    def hessian_matvec(self, vt, out=None):
+        out = self.empty(3) if out is None else out
+        self._chk(lib().cl_hessian_matvec(self._h, self._dev(vt, 3 * self.N, "vt"), self._dev(out, 3 * self.N, "Hvt")))
+        return out
+
+    def precond(self, r, out=None):
+        out = self.empty(3) if out is None else out
+        self._chk(lib().cl_precond_apply(self._h, self._dev(r, 3 * self.N, "r"), self._dev(out, 3 * self.N, "z")))
+        return out
+
+    def solve(self):
+        rep = cl_solve_report()
+        self._chk(lib().cl_solve(self._h, ctypes.byref(rep)))
+        return rep.as_dict()
+
+    def solve_forced(self, pcg_iters, alphas):
+        n = len(pcg_iters)
+        P = (ctypes.c_int * n)(*[int(x) for x in pcg_iters])
+        A = (ctypes.c_double * n)(*[float(x) for x in alphas])
+        rep = cl_solve_report()
+        self._chk(lib().cl_solve_forced(self._h, P, A, n, ctypes.byref(rep)))
+        return rep.as_dict()
+
+    def solve_log(self):
+        nrows = ctypes.c_int()
+        lib().cl_get_solve_log(self._h, None, 0, ctypes.byref(nrows))
+        buf = (ctypes.c_double * (8 * max(nrows.value, 1)))()
+        lib().cl_get_solve_log(self._h, buf, nrows.value, ctypes.byref(nrows))
+        return [list(buf[8 * r: 8 * r + 8]) for r in range(nrows.value)]
+
+    def deformed_template(self):
+        out = self.empty()
+        self._chk(lib().cl_deformed_template(self._h, _ptr(out)))
+        return out
+
+    def field(self, which, j=0):
+        out = self.empty(3 if which in (FIELD_FEET_F, FIELD_FEET_B) else 1)
+        self._chk(lib().cl_get_field(self._h, int(which), int(j), _ptr(out)))
+        return out
+
+    def interp(self, u, d):
+        out = self.empty()
+        self._chk(lib().cl_interp(self._h, self._dev(u, self.N, "u"), self._dev(d, 3 * self.N, "d"), _ptr(out)))
+        return out
+
+    def fd_grad(self, u):
+        out = self.empty(3)
+        self._chk(lib().cl_fd_grad(self._h, self._dev(u, self.N, "u"), _ptr(out)))
+        return out
+
+    def fd_div(self, v):
+        out = self.empty()
+        self._chk(lib().cl_fd_div(self._h, self._dev(v, 3 * self.N, "v"), _ptr(out)))
+        return out
+
+    def spectral(self, kind, x):
+        ncomp = x.numel() // self.N
+        out = self.torch.empty_like(x)
+        self._chk(lib().cl_spectral(self._h, int(kind), ncomp, self._dev(x, ncomp * self.N, "in"), _ptr(out)))
+        return out
+
+    def dot(self, a, b):
+        out = _d()
+        self._chk(lib().cl_dot(self._h, _ptr(a), _ptr(b), a.numel(), ctypes.byref(out)))
+        return out.value
+
+    def copy(self, src, dst):
+        self._chk(lib().cl_copy_f32(self._h, _ptr(src), _ptr(dst), src.numel()))
+
+    def profile_enable(self, mask):
+        self._chk(lib().cl_profile_enable(self._h, int(mask)))
+
+    def profile_query(self, kclass):
+        ms, n = _d(), ctypes.c_longlong()
+        self._chk(lib().cl_profile_query(self._h, int(kclass), ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value

@@ -1,0 +1,901 @@
+// api.hip -- context, operator composition and Gauss-Newton-Krylov control
+// (host C++) behind the C ABI of include/claire_hip.h.
+//
+// Every field operation is a HIP kernel on the context stream; the host only
+// sequences launches and reads FP64 scalars (dot products, norms, objective
+// parts) back, one synchronisation per scalar.
+#include "internal.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <utility>
+#include <vector>
+
+using namespace clh;
+
+namespace {
+
+constexpr double TWO_PI = 6.283185307179586476925286766559;
+
+struct Prof {
+    unsigned mask = 0;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[CL_K_COUNT];
+    double ms[CL_K_COUNT] = {};
+    long long n[CL_K_COUNT] = {};
+    std::vector<hipEvent_t> pool;
+};
+
+} // namespace
+
+struct cl_ctx {
+    Grid g{};
+    cl_options opt{};
+    hipStream_t s = nullptr;
+    int nt = 4;
+    float dt = 0.25f;
+    double hv = 0.0;             // h1 h2 h3
+    int dts = CL_F32, dta = CL_F32;
+    size_t N = 0;
+
+    std::vector<void *> allocs;
+    void *m0 = nullptr, *m1 = nullptr;      // state dtype
+    void *m = nullptr;                      // (nt+1) N, state dtype
+    void *lam = nullptr;                    // (nt+1) N, adjoint dtype
+    void *q[2] = {nullptr, nullptr};        // adjoint dtype
+    float *v = nullptr, *vtrial = nullptr;  // 3N
+    float *df = nullptr, *db = nullptr;     // 3N
+    float *c = nullptr, *divv = nullptr;    // N
+    float *grad = nullptr, *Av = nullptr, *tmp3 = nullptr;  // 3N
+    float *px = nullptr, *pr = nullptr, *pz = nullptr, *pp = nullptr, *pHp = nullptr;  // 3N
+    double *partials = nullptr, *dscal = nullptr, *hscal = nullptr;
+    int nparts = 1;
+    FFTPlan fft{};
+
+    bool images = false, vel = false, feet_f = false, feet_b = false, state = false, av = false;
+    bool gref_valid = false;
+    double gref = 0.0;
+    std::vector<std::vector<double>> log;
+    std::string err;
+    Prof prof;
+};
+
+namespace {
+
+struct Fail {
+    int code;
+};
+
+#define HIPCHK(expr)                                                                    \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess) {                                                         \
+            ctx->err = std::string(#expr) + ": " + hipGetErrorString(e_);              \
+            throw Fail{CL_ERR_HIP};                                                     \
+        }                                                                               \
+    } while (0)
+
+int fail(cl_ctx *ctx, int code, const std::string &msg)
+{
+    if (ctx) ctx->err = msg;
+    return code;
+}
+
+bool pow2_ok(int n) { return n >= 16 && n <= 1024 && (n & (n - 1)) == 0; }
+
+int ilog2i(int n)
+{
+    int l = 0;
+    while ((1 << l) < n) ++l;
+    return l;
+}
+
+bool overlap(const void *a, size_t na, const void *b, size_t nb)
+{
+    const char *pa = (const char *)a, *pb = (const char *)b;
+    return pa < pb + nb && pb < pa + na;
+}
+
+// ---- profiling: HIP events around launches of selected kernel classes
+hipEvent_t prof_event(cl_ctx *ctx)
+{
+    if (!ctx->prof.pool.empty()) {
+        hipEvent_t e = ctx->prof.pool.back();
+        ctx->prof.pool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    return e;
+}
+
+void prof_drain(cl_ctx *ctx)
+{
+    HIPCHK(hipStreamSynchronize(ctx->s));
+    for (int k = 0; k < CL_K_COUNT; ++k) {
+        for (auto &pr : ctx->prof.pending[k]) {
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, pr.first, pr.second));
+            ctx->prof.ms[k] += ms;
+            ctx->prof.n[k] += 1;
+            ctx->prof.pool.push_back(pr.first);
+            ctx->prof.pool.push_back(pr.second);
+        }
+        ctx->prof.pending[k].clear();
+    }
+}
+
+template <typename F> void run(cl_ctx *ctx, int kclass, F &&f)
+{
+    const bool on = (ctx->prof.mask >> kclass) & 1u;
+    hipEvent_t a = nullptr, b = nullptr;
+    if (on) {
+        a = prof_event(ctx);
+        HIPCHK(hipEventRecord(a, ctx->s));
+    }
+    f();
+    HIPCHK(hipGetLastError());
+    if (on) {
+        b = prof_event(ctx);
+        HIPCHK(hipEventRecord(b, ctx->s));
+        ctx->prof.pending[kclass].push_back({a, b});
+        if (ctx->prof.pending[kclass].size() > 4096) prof_drain(ctx);
+    }
+}
+
+// ---- helpers
+void *slot(cl_ctx *ctx, void *base, int dt, int j) { return (char *)base + (size_t)j * ctx->N * dtype_size(dt); }
+
+double read_scalar(cl_ctx *ctx)
+{
+    HIPCHK(hipMemcpyAsync(ctx->hscal, ctx->dscal, sizeof(double), hipMemcpyDeviceToHost, ctx->s));
+    HIPCHK(hipStreamSynchronize(ctx->s));
+    return *ctx->hscal;
+}
+
+// h-weighted FP64 inner product of two FP32 vectors of n values
+double dotw(cl_ctx *ctx, const float *a, const float *b, size_t n)
+{
+    run(ctx, CL_K_VEC, [&] {
+        launch_dot(a, b, n, ctx->partials, ctx->nparts, ctx->s);
+        launch_finalize(ctx->partials, ctx->nparts, ctx->hv, ctx->dscal, ctx->s);
+    });
+    return read_scalar(ctx);
+}
+
+double count_nonfinite(cl_ctx *ctx, const float *a, size_t n)
+{
+    run(ctx, CL_K_VEC, [&] {
+        launch_count_nonfinite(a, n, ctx->partials, ctx->nparts, ctx->s);
+        launch_finalize(ctx->partials, ctx->nparts, 1.0, ctx->dscal, ctx->s);
+    });
+    return read_scalar(ctx);
+}
+
+void spectral(cl_ctx *ctx, int kind, int ncomp, const float *in, float *out, const float *add)
+{
+    run(ctx, CL_K_FFT, [&] { spectral_apply(ctx->fft, kind, (float)ctx->opt.beta_v, ncomp, in, out, add, ctx->s); });
+}
+
+// ---- operator layer
+
+// RK2 feet for the current v (forward always, backward + adjoint factor on request)
+void ensure_feet(cl_ctx *ctx, bool backward)
+{
+    if (!ctx->feet_f || (backward && !ctx->feet_b)) {
+        if (backward) run(ctx, CL_K_FD, [&] { launch_fd_div(ctx->g, ctx->v, ctx->divv, ctx->s); });
+        run(ctx, CL_K_FEET, [&] {
+            launch_feet(ctx->g, ctx->dt, ctx->v, ctx->df, backward ? ctx->db : nullptr,
+                        backward ? ctx->divv : nullptr, backward ? ctx->c : nullptr, ctx->s);
+        });
+        ctx->feet_f = true;
+        if (backward) ctx->feet_b = true;
+    }
+}
+
+// state m^0..m^nt (Section 2.1 transport equation, one SL step per dt)
+void ensure_state(cl_ctx *ctx)
+{
+    ensure_feet(ctx, false);
+    if (ctx->state) return;
+    const size_t bytes = ctx->N * dtype_size(ctx->dts);
+    HIPCHK(hipMemcpyAsync(ctx->m, ctx->m0, bytes, hipMemcpyDeviceToDevice, ctx->s));
+    for (int j = 0; j < ctx->nt; ++j)
+        run(ctx, CL_K_SL_STATE, [&] {
+            launch_sl_state(ctx->g, ctx->dts, slot(ctx, ctx->m, ctx->dts, j), ctx->df, ctx->dts,
+                            slot(ctx, ctx->m, ctx->dts, j + 1), ctx->s);
+        });
+    ctx->state = true;
+}
+
+double mismatch_only(cl_ctx *ctx)
+{
+    run(ctx, CL_K_VEC, [&] {
+        launch_sq_diff(ctx->g, ctx->dts, ctx->m1, slot(ctx, ctx->m, ctx->dts, ctx->nt), ctx->partials, ctx->nparts,
+                       ctx->s);
+        launch_finalize(ctx->partials, ctx->nparts, 0.5 * ctx->hv, ctx->dscal, ctx->s);
+    });
+    return read_scalar(ctx);
+}
+
+double regulariser(cl_ctx *ctx)
+{
+    if (!ctx->av) {
+        spectral(ctx, 0, 3, ctx->v, ctx->Av, nullptr);
+        ctx->av = true;
+    }
+    return 0.5 * dotw(ctx, ctx->Av, ctx->v, 3 * ctx->N);
+}
+
+void objective(cl_ctx *ctx, double *J, double *mis, double *reg)
+{
+    ensure_state(ctx);
+    const double a = mismatch_only(ctx);
+    const double r = regulariser(ctx);
+    if (mis) *mis = a;
+    if (reg) *reg = r;
+    if (J) *J = a + r;
+}
+
+QuadArgs quad_args(cl_ctx *ctx)
+{
+    QuadArgs qa{};
+    qa.count = ctx->nt + 1;
+    for (int j = 0; j <= ctx->nt; ++j) {
+        qa.lam[j] = slot(ctx, ctx->lam, ctx->dta, j);
+        qa.m[j] = slot(ctx, ctx->m, ctx->dts, j);
+        qa.w[j] = (j == 0 || j == ctx->nt) ? 0.5f * ctx->dt : ctx->dt;
+    }
+    return qa;
+}
+
+// adjoint lam^j = c I[lam^{j+1}](X_b), j = nt-1 .. 0
+void adjoint_sweep(cl_ctx *ctx)
+{
+    for (int j = ctx->nt - 1; j >= 0; --j)
+        run(ctx, CL_K_SL_ADJOINT, [&] {
+            launch_sl_adjoint(ctx->g, ctx->dta, slot(ctx, ctx->lam, ctx->dta, j + 1), ctx->db, ctx->c, ctx->dta,
+                              slot(ctx, ctx->lam, ctx->dta, j), ctx->s);
+        });
+}
+
+// reduced gradient into ctx->g; returns ||g||
+double gradient(cl_ctx *ctx, double *J, double *mis_out, double *reg_out)
+{
+    ensure_feet(ctx, true);
+    ensure_state(ctx);
+    run(ctx, CL_K_VEC, [&] {
+        launch_residual(ctx->g, ctx->dts, ctx->m1, slot(ctx, ctx->m, ctx->dts, ctx->nt), ctx->dta,
+                        slot(ctx, ctx->lam, ctx->dta, ctx->nt), ctx->partials, ctx->nparts, ctx->s);
+        launch_finalize(ctx->partials, ctx->nparts, 0.5 * ctx->hv, ctx->dscal, ctx->s);
+    });
+    const double mis = read_scalar(ctx);
+    adjoint_sweep(ctx);
+    if (!ctx->av) {
+        spectral(ctx, 0, 3, ctx->v, ctx->Av, nullptr);
+        ctx->av = true;
+    }
+    const QuadArgs qa = quad_args(ctx);
+    run(ctx, CL_K_QUAD, [&] { launch_quadrature(ctx->g, ctx->dta, ctx->dts, qa, ctx->Av, ctx->grad, ctx->s); });
+    const double reg = 0.5 * dotw(ctx, ctx->Av, ctx->v, 3 * ctx->N);
+    if (mis_out) *mis_out = mis;
+    if (reg_out) *reg_out = reg;
+    if (J) *J = mis + reg;
+    return std::sqrt(dotw(ctx, ctx->grad, ctx->grad, 3 * ctx->N));
+}
+
+// GN Hessian matvec (incremental state, incremental adjoint, quadrature,
+// beta A vt); needs feet of both directions and the state of the current v.
+void matvec(cl_ctx *ctx, const float *vt, float *Hvt)
+{
+    ensure_feet(ctx, true);
+    ensure_state(ctx);
+    const float dt = ctx->dt;
+    const int nt = ctx->nt;
+    run(ctx, CL_K_FD, [&] { launch_inc_init(ctx->g, ctx->dts, ctx->m, vt, 0.5f * dt, ctx->dta, ctx->q[0], ctx->s); });
+    for (int j = 0; j < nt; ++j) {
+        const bool last = j == nt - 1;
+        void *out = last ? slot(ctx, ctx->lam, ctx->dta, nt) : ctx->q[(j + 1) & 1];
+        run(ctx, CL_K_SL_INC, [&] {
+            launch_sl_inc(ctx->g, ctx->dta, ctx->q[j & 1], ctx->df, ctx->dts, slot(ctx, ctx->m, ctx->dts, j + 1), vt,
+                          last ? -1.0f : 1.0f, last ? -0.5f * dt : dt, out, ctx->s);
+        });
+    }
+    adjoint_sweep(ctx);
+    spectral(ctx, 0, 3, vt, ctx->tmp3, nullptr);
+    const QuadArgs qa = quad_args(ctx);
+    run(ctx, CL_K_QUAD, [&] { launch_quadrature(ctx->g, ctx->dta, ctx->dts, qa, ctx->tmp3, Hvt, ctx->s); });
+}
+
+void precond(cl_ctx *ctx, const float *r, float *z) { spectral(ctx, 1, 3, r, z, nullptr); }
+
+void load_velocity(cl_ctx *ctx, const float *src_dev)
+{
+    HIPCHK(hipMemcpyAsync(ctx->v, src_dev, 3 * ctx->N * sizeof(float), hipMemcpyDeviceToDevice, ctx->s));
+    ctx->vel = true;
+    ctx->feet_f = ctx->feet_b = ctx->state = ctx->av = false;
+}
+
+// PCG on H x = rhs (rhs in ctx->pr on entry); solution in ctx->px.
+int pcg(cl_ctx *ctx, int max_pcg, double eta, int forced, int *iters)
+{
+    const size_t n = 3 * ctx->N;
+    run(ctx, CL_K_VEC, [&] { launch_fill_f32(ctx->px, 0.0f, n, ctx->s); });
+    precond(ctx, ctx->pr, ctx->pz);
+    HIPCHK(hipMemcpyAsync(ctx->pp, ctx->pz, n * sizeof(float), hipMemcpyDeviceToDevice, ctx->s));
+    double rz = dotw(ctx, ctx->pr, ctx->pz, n);
+    const double r0 = std::sqrt(dotw(ctx, ctx->pr, ctx->pr, n));
+    const int limit = forced >= 0 ? forced : max_pcg;
+    int it = 0, neg = 0;
+    while (it < limit) {
+        matvec(ctx, ctx->pp, ctx->pHp);
+        const double pHp = dotw(ctx, ctx->pp, ctx->pHp, n);
+        if (!(pHp > 0.0)) {
+            neg = 1;
+            if (it == 0) HIPCHK(hipMemcpyAsync(ctx->px, ctx->pz, n * sizeof(float), hipMemcpyDeviceToDevice, ctx->s));
+            break;
+        }
+        const double alpha = rz / pHp;
+        run(ctx, CL_K_VEC, [&] {
+            launch_pcg_update(ctx->px, ctx->pr, ctx->pp, ctx->pHp, (float)alpha, n, ctx->partials, ctx->nparts,
+                              ctx->s);
+            launch_finalize(ctx->partials, ctx->nparts, ctx->hv, ctx->dscal, ctx->s);
+        });
+        const double rn = std::sqrt(read_scalar(ctx));
+        ++it;
+        if (forced < 0 && rn <= eta * r0) break;
+        if (it >= limit) break;
+        precond(ctx, ctx->pr, ctx->pz);
+        const double rz_new = dotw(ctx, ctx->pr, ctx->pz, n);
+        const double bt = rz_new / rz;
+        rz = rz_new;
+        run(ctx, CL_K_VEC, [&] { launch_axpy(ctx->pp, ctx->pz, ctx->pp, (float)bt, n, ctx->s); });
+    }
+    if (iters) *iters = it;
+    return neg;
+}
+
+double compute_gref(cl_ctx *ctx)
+{
+    if (ctx->gref_valid) return ctx->gref;
+    // g(v = 0): swap in a zero velocity, evaluate, restore
+    const size_t n = 3 * ctx->N;
+    std::swap(ctx->v, ctx->vtrial);
+    run(ctx, CL_K_VEC, [&] { launch_fill_f32(ctx->v, 0.0f, n, ctx->s); });
+    ctx->feet_f = ctx->feet_b = ctx->state = ctx->av = false;
+    ctx->gref = gradient(ctx, nullptr, nullptr, nullptr);
+    ctx->gref_valid = true;
+    std::swap(ctx->v, ctx->vtrial);
+    ctx->feet_f = ctx->feet_b = ctx->state = ctx->av = false;
+    return ctx->gref;
+}
+
+int solve(cl_ctx *ctx, const int *forced_pcg, const double *forced_alpha, int forced_n, cl_solve_report *rep)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    const size_t n = 3 * ctx->N;
+    const bool forced = forced_pcg != nullptr;
+    const int max_outer = forced ? forced_n : ctx->opt.max_outer;
+    const double gref = compute_gref(ctx);
+    ctx->log.clear();
+    cl_solve_report R{};
+    R.gref = gref;
+    int status = CL_STATUS_MAXIT, k = 0;
+    double J = 0, mis = 0, reg = 0, gn = 0;
+    for (k = 0; k < max_outer; ++k) {
+        gn = gradient(ctx, &J, &mis, &reg);
+        if (k == 0) { R.J0 = J; R.gnorm0 = gn; }
+        ctx->log.push_back({(double)k, J, mis, reg, gn, 0.0, 0.0, 0.0});
+        if (!forced && gn <= ctx->opt.gtol * gref) { status = CL_OK; break; }
+        double eta = ctx->opt.forcing ? std::min(0.5, std::sqrt(gn / gref)) : ctx->opt.eta_fixed;
+        run(ctx, CL_K_VEC, [&] { launch_scale(ctx->pr, ctx->grad, -1.0f, n, ctx->s); });   // rhs = -g
+        int its = 0;
+        pcg(ctx, ctx->opt.max_pcg, eta, forced ? forced_pcg[k] : -1, &its);
+        R.pcg_iters_total += its;
+        const double gvt = dotw(ctx, ctx->grad, ctx->px, n);
+        double alpha = 1.0;
+        int trials = 0;
+        bool ok = false;
+        if (forced) {
+            alpha = forced_alpha[k];
+            run(ctx, CL_K_VEC, [&] { launch_axpy(ctx->vtrial, ctx->v, ctx->px, (float)alpha, n, ctx->s); });
+            std::swap(ctx->v, ctx->vtrial);
+            ctx->feet_f = ctx->feet_b = ctx->state = ctx->av = false;
+            ok = true;
+        } else {
+            for (trials = 1; trials <= 10; ++trials) {
+                run(ctx, CL_K_VEC, [&] { launch_axpy(ctx->vtrial, ctx->v, ctx->px, (float)alpha, n, ctx->s); });
+                std::swap(ctx->v, ctx->vtrial);
+                ctx->feet_f = ctx->feet_b = ctx->state = ctx->av = false;
+                double Jt;
+                objective(ctx, &Jt, nullptr, nullptr);
+                R.linesearch_trials++;
+                if (Jt <= J + 1e-4 * alpha * gvt) { ok = true; break; }
+                std::swap(ctx->v, ctx->vtrial);   // back to the accepted v
+                ctx->feet_f = ctx->feet_b = ctx->state = ctx->av = false;
+                alpha *= 0.5;
+            }
+        }
+        ctx->log.back()[5] = its;
+        ctx->log.back()[6] = ok ? alpha : 0.0;
+        ctx->log.back()[7] = trials;
+        if (!ok) {
+            status = CL_STATUS_LINESEARCH_FAIL;
+            ++k;
+            break;
+        }
+    }
+    if (status != CL_OK) {
+        gn = gradient(ctx, &J, &mis, &reg);
+        ctx->log.push_back({(double)k, J, mis, reg, gn, 0.0, 0.0, 0.0});
+        if (status == CL_STATUS_MAXIT && gn <= ctx->opt.gtol * gref) status = CL_OK;
+        if (k == 0) { R.J0 = J; R.gnorm0 = gn; }
+    }
+    R.status = status;
+    R.outer_iters = k;
+    R.J = J; R.mismatch = mis; R.reg = reg; R.gnorm = gn;
+    HIPCHK(hipStreamSynchronize(ctx->s));
+    R.ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (rep) *rep = R;
+    return status;
+}
+
+size_t workspace_bytes(int n1, int n2, int n3, const cl_options &o)
+{
+    const size_t N = (size_t)n1 * n2 * n3;
+    const size_t es = dtype_size(o.storage_state), ea = dtype_size(o.storage_adjoint);
+    size_t b = 0;
+    b += 2 * N * es;                         // m0, m1
+    b += (size_t)(o.nt + 1) * N * es;        // m^j
+    b += (size_t)(o.nt + 1) * N * ea;        // lam^j / lam~^j
+    b += 2 * N * ea;                         // q ping-pong
+    b += 2 * N * sizeof(float);              // c, div v
+    b += 12 * 3 * N * sizeof(float);         // v, vtrial, df, db, g, Av, tmp3, PCG x r z p Hp
+    b += fft_spec_bytes(n1, n2, n3, 3);
+    b += 3 * 1024 * sizeof(float2) + 4096 * sizeof(double) + 256;
+    return b;
+}
+
+int check_options(const cl_options *o, cl_ctx *ctx)
+{
+    if (!o) return fail(ctx, CL_ERR_ARG, "options pointer is NULL");
+    if (o->struct_version != CL_OPTIONS_VERSION) return fail(ctx, CL_ERR_ARG, "cl_options.struct_version mismatch");
+    if (o->nt < 1 || o->nt > MAX_T - 1) return fail(ctx, CL_ERR_ARG, "nt out of range [1, 64]");
+    if (!(o->beta_v > 0.0) || !std::isfinite(o->beta_v)) return fail(ctx, CL_ERR_ARG, "beta_v must be > 0");
+    if (o->beta_w != 0.0) return fail(ctx, CL_ERR_UNSUPPORTED, "beta_w != 0 is not supported (K = I only)");
+    if (o->max_outer < 0 || o->max_pcg < 1) return fail(ctx, CL_ERR_ARG, "iteration limits out of range");
+    if (!(o->gtol >= 0.0)) return fail(ctx, CL_ERR_ARG, "gtol must be >= 0");
+    for (int dt : {o->storage_state, o->storage_adjoint})
+        if (dt != CL_F32 && dt != CL_BF16 && dt != CL_F16) return fail(ctx, CL_ERR_DTYPE, "unknown storage dtype");
+    return CL_OK;
+}
+
+#define API_BEGIN try {
+#define API_END                                                                 \
+    }                                                                           \
+    catch (const Fail &f_) { return f_.code; }                                  \
+    catch (...) { return fail(ctx, CL_ERR_HIP, "unexpected host exception"); }
+
+#define NEED_CTX()                                                              \
+    if (!ctx) return CL_ERR_ARG
+
+} // namespace
+
+extern "C" {
+
+void cl_default_options(cl_options *o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->struct_version = CL_OPTIONS_VERSION;
+    o->nt = 4;
+    o->beta_v = 5e-4;
+    o->beta_w = 0.0;
+    o->gtol = 1e-2;
+    o->max_outer = 50;
+    o->max_pcg = 10;
+    o->forcing = 1;
+    o->eta_fixed = 0.1;
+    o->storage_state = CL_F32;
+    o->storage_adjoint = CL_F32;
+    o->stream = nullptr;
+    o->workspace_cap_bytes = 0;
+}
+
+int cl_query_workspace(int n1, int n2, int n3, const cl_options *opt, unsigned long long *bytes)
+{
+    if (!bytes) return CL_ERR_ARG;
+    int st = check_options(opt, nullptr);
+    if (st) return st;
+    if (!pow2_ok(n1) || !pow2_ok(n2) || !pow2_ok(n3)) return CL_ERR_SHAPE;
+    *bytes = workspace_bytes(n1, n2, n3, *opt);
+    return CL_OK;
+}
+
+int cl_create(cl_ctx **out, int n1, int n2, int n3, const cl_options *opt)
+{
+    if (!out) return CL_ERR_ARG;
+    *out = nullptr;
+    int st = check_options(opt, nullptr);
+    if (st) return st;
+    if (!pow2_ok(n1) || !pow2_ok(n2) || !pow2_ok(n3)) return CL_ERR_SHAPE;
+    const size_t need = workspace_bytes(n1, n2, n3, *opt);
+    if (opt->workspace_cap_bytes && need > opt->workspace_cap_bytes) return CL_ERR_OOM;
+    cl_ctx *ctx = new (std::nothrow) cl_ctx();
+    if (!ctx) return CL_ERR_OOM;
+    ctx->opt = *opt;
+    ctx->s = (hipStream_t)opt->stream;
+    ctx->nt = opt->nt;
+    ctx->dt = (float)(1.0 / opt->nt);
+    ctx->dts = opt->storage_state;
+    ctx->dta = opt->storage_adjoint;
+    Grid &g = ctx->g;
+    g.n1 = n1; g.n2 = n2; g.n3 = n3;
+    g.l1 = ilog2i(n1); g.l2 = ilog2i(n2); g.l3 = ilog2i(n3);
+    g.N = n1 * n2 * n3;
+    g.ih1 = (float)(n1 / TWO_PI); g.ih2 = (float)(n2 / TWO_PI); g.ih3 = (float)(n3 / TWO_PI);
+    g.h1 = (float)(TWO_PI / n1); g.h2 = (float)(TWO_PI / n2); g.h3 = (float)(TWO_PI / n3);
+    ctx->N = (size_t)g.N;
+    ctx->hv = (TWO_PI / n1) * (TWO_PI / n2) * (TWO_PI / n3);
+    const size_t N = ctx->N;
+    auto alloc = [&](size_t bytes) -> void * {
+        void *p = nullptr;
+        if (hipMalloc(&p, bytes) != hipSuccess) throw Fail{CL_ERR_OOM};
+        ctx->allocs.push_back(p);
+        return p;
+    };
+    try {
+        const size_t es = dtype_size(ctx->dts), ea = dtype_size(ctx->dta);
+        ctx->m0 = alloc(N * es);
+        ctx->m1 = alloc(N * es);
+        ctx->m = alloc((size_t)(ctx->nt + 1) * N * es);
+        ctx->lam = alloc((size_t)(ctx->nt + 1) * N * ea);
+        ctx->q[0] = alloc(N * ea);
+        ctx->q[1] = alloc(N * ea);
+        float **vecs[] = {&ctx->v, &ctx->vtrial, &ctx->df, &ctx->db, &ctx->grad, &ctx->Av, &ctx->tmp3,
+                          &ctx->px, &ctx->pr, &ctx->pz, &ctx->pp, &ctx->pHp};
+        for (float **pv : vecs) *pv = (float *)alloc(3 * N * sizeof(float));
+        ctx->c = (float *)alloc(N * sizeof(float));
+        ctx->divv = (float *)alloc(N * sizeof(float));
+        ctx->nparts = reduce_blocks(3 * N);
+        ctx->partials = (double *)alloc(ctx->nparts * sizeof(double));
+        ctx->dscal = (double *)alloc(sizeof(double) * 4);
+        if (hipHostMalloc((void **)&ctx->hscal, sizeof(double) * 4, hipHostMallocDefault) != hipSuccess)
+            throw Fail{CL_ERR_OOM};
+        FFTPlan &P = ctx->fft;
+        P.n1 = n1; P.n2 = n2; P.n3 = n3; P.nh = n3 / 2 + 1; P.ncomp_max = 3;
+        P.spec = (float2 *)alloc(fft_spec_bytes(n1, n2, n3, 3));
+        std::vector<float2> tw;
+        float2 **tabs[3] = {&P.tw1, &P.tw2, &P.tw3};
+        const int ns[3] = {n1, n2, n3};
+        for (int a = 0; a < 3; ++a) {
+            tw.assign(ns[a] / 2, make_float2(0.f, 0.f));
+            fft_make_twiddles(tw.data(), ns[a]);
+            *tabs[a] = (float2 *)alloc(tw.size() * sizeof(float2));
+            HIPCHK(hipMemcpy(*tabs[a], tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice));
+        }
+        // a defined initial velocity: v = 0
+        HIPCHK(hipMemsetAsync(ctx->v, 0, 3 * N * sizeof(float), ctx->s));
+        ctx->vel = true;
+        HIPCHK(hipStreamSynchronize(ctx->s));
+    } catch (const Fail &f) {
+        cl_destroy(ctx);
+        return f.code;
+    }
+    *out = ctx;
+    return CL_OK;
+}
+
+void cl_destroy(cl_ctx *ctx)
+{
+    if (!ctx) return;
+    (void)hipStreamSynchronize(ctx->s);
+    for (void *p : ctx->allocs) (void)hipFree(p);
+    if (ctx->hscal) (void)hipHostFree(ctx->hscal);
+    for (int k = 0; k < CL_K_COUNT; ++k)
+        for (auto &pr : ctx->prof.pending[k]) {
+            (void)hipEventDestroy(pr.first);
+            (void)hipEventDestroy(pr.second);
+        }
+    for (hipEvent_t e : ctx->prof.pool) (void)hipEventDestroy(e);
+    delete ctx;
+}
+
+int cl_set_images(cl_ctx *ctx, const void *m0, const void *m1, int dt)
+{
+    NEED_CTX();
+    if (!m0 || !m1) return fail(ctx, CL_ERR_ARG, "NULL image pointer");
+    if (dt != CL_F32) return fail(ctx, CL_ERR_DTYPE, "images must be passed as CL_F32");
+    API_BEGIN
+    const size_t N = ctx->N;
+    if (count_nonfinite(ctx, (const float *)m0, N) > 0 || count_nonfinite(ctx, (const float *)m1, N) > 0)
+        return fail(ctx, CL_ERR_NONFINITE, "image contains NaN or Inf");
+    run(ctx, CL_K_VEC, [&] {
+        launch_convert(ctx->dts, ctx->m0, (const float *)m0, N, ctx->s);
+        launch_convert(ctx->dts, ctx->m1, (const float *)m1, N, ctx->s);
+    });
+    ctx->images = true;
+    ctx->state = false;
+    ctx->gref_valid = false;
+    return CL_OK;
+    API_END
+}
+
+int cl_set_velocity(cl_ctx *ctx, const float *v)
+{
+    NEED_CTX();
+    if (!v) return fail(ctx, CL_ERR_ARG, "NULL velocity pointer");
+    API_BEGIN
+    if (count_nonfinite(ctx, v, 3 * ctx->N) > 0) return fail(ctx, CL_ERR_NONFINITE, "velocity contains NaN or Inf");
+    load_velocity(ctx, v);
+    return CL_OK;
+    API_END
+}
+
+int cl_get_velocity(cl_ctx *ctx, float *v_out)
+{
+    NEED_CTX();
+    if (!v_out) return fail(ctx, CL_ERR_ARG, "NULL output pointer");
+    API_BEGIN
+    HIPCHK(hipMemcpyAsync(v_out, ctx->v, 3 * ctx->N * sizeof(float), hipMemcpyDeviceToDevice, ctx->s));
+    return CL_OK;
+    API_END
+}
+
+int cl_objective(cl_ctx *ctx, double *J, double *mismatch, double *reg)
+{
+    NEED_CTX();
+    if (!ctx->images) return fail(ctx, CL_ERR_STATE, "cl_set_images has not been called");
+    API_BEGIN
+    objective(ctx, J, mismatch, reg);
+    return CL_OK;
+    API_END
+}
+
+int cl_gradient(cl_ctx *ctx, float *g_out, double *gnorm, double *J)
+{
+    NEED_CTX();
+    if (!ctx->images) return fail(ctx, CL_ERR_STATE, "cl_set_images has not been called");
+    API_BEGIN
+    const double gn = gradient(ctx, J, nullptr, nullptr);
+    if (gnorm) *gnorm = gn;
+    if (g_out) {
+        HIPCHK(hipMemcpyAsync(g_out, ctx->grad, 3 * ctx->N * sizeof(float), hipMemcpyDeviceToDevice, ctx->s));
+        HIPCHK(hipStreamSynchronize(ctx->s));
+    }
+    return CL_OK;
+    API_END
+}
+
+int cl_hessian_matvec(cl_ctx *ctx, const float *vt, float *Hvt)
+{
+    NEED_CTX();
+    if (!vt || !Hvt) return fail(ctx, CL_ERR_ARG, "NULL vector pointer");
+    if (!ctx->images) return fail(ctx, CL_ERR_STATE, "cl_set_images has not been called");
+    const size_t b = 3 * ctx->N * sizeof(float);
+    if (overlap(vt, b, Hvt, b)) return fail(ctx, CL_ERR_ALIAS, "vt and Hvt overlap");
+    API_BEGIN
+    matvec(ctx, vt, Hvt);
+    return CL_OK;
+    API_END
+}
+
+int cl_precond_apply(cl_ctx *ctx, const float *r, float *z)
+{
+    NEED_CTX();
+    if (!r || !z) return fail(ctx, CL_ERR_ARG, "NULL vector pointer");
+    const size_t b = 3 * ctx->N * sizeof(float);
+    if (overlap(r, b, z, b)) return fail(ctx, CL_ERR_ALIAS, "r and z overlap");
+    API_BEGIN
+    precond(ctx, r, z);
+    return CL_OK;
+    API_END
+}
+
+int cl_solve(cl_ctx *ctx, cl_solve_report *rep)
+{
+    NEED_CTX();
+    if (!ctx->images) return fail(ctx, CL_ERR_STATE, "cl_set_images has not been called");
+    API_BEGIN
+    return solve(ctx, nullptr, nullptr, 0, rep);
+    API_END
+}
+
+int cl_solve_forced(cl_ctx *ctx, const int *forced_pcg, const double *forced_alpha, int n_outer,
+                    cl_solve_report *rep)
+{
+    NEED_CTX();
+    if (!forced_pcg || !forced_alpha || n_outer < 0) return fail(ctx, CL_ERR_ARG, "bad forced decisions");
+    if (!ctx->images) return fail(ctx, CL_ERR_STATE, "cl_set_images has not been called");
+    API_BEGIN
+    return solve(ctx, forced_pcg, forced_alpha, n_outer, rep);
+    API_END
+}
+
+int cl_get_solve_log(cl_ctx *ctx, double *rows, int max_rows, int *n_rows)
+{
+    NEED_CTX();
+    if (n_rows) *n_rows = (int)ctx->log.size();
+    if (rows)
+        for (int r = 0; r < std::min(max_rows, (int)ctx->log.size()); ++r)
+            for (int c = 0; c < 8; ++c) rows[8 * r + c] = ctx->log[r][c];
+    return CL_OK;
+}
+
+int cl_deformed_template(cl_ctx *ctx, float *m_out)
+{
+    NEED_CTX();
+    if (!m_out) return fail(ctx, CL_ERR_ARG, "NULL output pointer");
+    if (!ctx->images) return fail(ctx, CL_ERR_STATE, "cl_set_images has not been called");
+    API_BEGIN
+    ensure_state(ctx);
+    run(ctx, CL_K_VEC, [&] { launch_to_f32(ctx->dts, slot(ctx, ctx->m, ctx->dts, ctx->nt), m_out, ctx->N, ctx->s); });
+    return CL_OK;
+    API_END
+}
+
+int cl_get_field(cl_ctx *ctx, int which, int j, float *out)
+{
+    NEED_CTX();
+    if (!out) return fail(ctx, CL_ERR_ARG, "NULL output pointer");
+    if ((which <= CL_FIELD_INC_ADJOINT) && (j < 0 || j > ctx->nt)) return fail(ctx, CL_ERR_ARG, "time index out of range");
+    API_BEGIN
+    const size_t N = ctx->N;
+    switch (which) {
+    case CL_FIELD_STATE:
+        run(ctx, CL_K_VEC, [&] { launch_to_f32(ctx->dts, slot(ctx, ctx->m, ctx->dts, j), out, N, ctx->s); });
+        break;
+    case CL_FIELD_ADJOINT:
+    case CL_FIELD_INC_ADJOINT:
+        run(ctx, CL_K_VEC, [&] { launch_to_f32(ctx->dta, slot(ctx, ctx->lam, ctx->dta, j), out, N, ctx->s); });
+        break;
+    case CL_FIELD_INC_STATE:
+        if (j != ctx->nt) return fail(ctx, CL_ERR_ARG, "only mt^nt is kept");
+        run(ctx, CL_K_VEC, [&] {   // mt^nt = -lam~^nt
+            launch_to_f32(ctx->dta, slot(ctx, ctx->lam, ctx->dta, ctx->nt), out, N, ctx->s);
+            launch_scale(out, out, -1.0f, N, ctx->s);
+        });
+        break;
+    case CL_FIELD_FEET_F:
+        HIPCHK(hipMemcpyAsync(out, ctx->df, 3 * N * sizeof(float), hipMemcpyDeviceToDevice, ctx->s));
+        break;
+    case CL_FIELD_FEET_B:
+        HIPCHK(hipMemcpyAsync(out, ctx->db, 3 * N * sizeof(float), hipMemcpyDeviceToDevice, ctx->s));
+        break;
+    case CL_FIELD_ADJ_FACTOR:
+        HIPCHK(hipMemcpyAsync(out, ctx->c, N * sizeof(float), hipMemcpyDeviceToDevice, ctx->s));
+        break;
+    default:
+        return fail(ctx, CL_ERR_ARG, "unknown field");
+    }
+    return CL_OK;
+    API_END
+}
+
+int cl_interp(cl_ctx *ctx, const float *u, const float *d, float *out)
+{
+    NEED_CTX();
+    if (!u || !d || !out) return fail(ctx, CL_ERR_ARG, "NULL pointer");
+    const size_t b = ctx->N * sizeof(float);
+    if (overlap(u, b, out, b) || overlap(d, 3 * b, out, b)) return fail(ctx, CL_ERR_ALIAS, "output overlaps an input");
+    API_BEGIN
+    run(ctx, CL_K_SL_STATE, [&] { launch_interp_f32(ctx->g, u, d, out, ctx->s); });
+    return CL_OK;
+    API_END
+}
+
+int cl_fd_grad(cl_ctx *ctx, const float *u, float *gout)
+{
+    NEED_CTX();
+    if (!u || !gout) return fail(ctx, CL_ERR_ARG, "NULL pointer");
+    if (overlap(u, ctx->N * 4, gout, 3 * ctx->N * 4)) return fail(ctx, CL_ERR_ALIAS, "output overlaps input");
+    API_BEGIN
+    run(ctx, CL_K_FD, [&] { launch_fd_grad(ctx->g, u, gout, ctx->s); });
+    return CL_OK;
+    API_END
+}
+
+int cl_fd_div(cl_ctx *ctx, const float *v, float *out)
+{
+    NEED_CTX();
+    if (!v || !out) return fail(ctx, CL_ERR_ARG, "NULL pointer");
+    if (overlap(v, 3 * ctx->N * 4, out, ctx->N * 4)) return fail(ctx, CL_ERR_ALIAS, "output overlaps input");
+    API_BEGIN
+    run(ctx, CL_K_FD, [&] { launch_fd_div(ctx->g, v, out, ctx->s); });
+    return CL_OK;
+    API_END
+}
+
+int cl_spectral(cl_ctx *ctx, int kind, int ncomp, const float *in, float *out)
+{
+    NEED_CTX();
+    if (!in || !out) return fail(ctx, CL_ERR_ARG, "NULL pointer");
+    if (kind < 0 || kind > 2 || ncomp < 1) return fail(ctx, CL_ERR_ARG, "bad kind or ncomp");
+    const size_t b = (size_t)ncomp * ctx->N * 4;
+    if (overlap(in, b, out, b)) return fail(ctx, CL_ERR_ALIAS, "output overlaps input");
+    API_BEGIN
+    spectral(ctx, kind, ncomp, in, out, nullptr);
+    return CL_OK;
+    API_END
+}
+
+int cl_dot(cl_ctx *ctx, const float *a, const float *b, size_t n, double *out)
+{
+    NEED_CTX();
+    if (!a || !b || !out) return fail(ctx, CL_ERR_ARG, "NULL pointer");
+    API_BEGIN
+    const int nb = std::min(ctx->nparts, reduce_blocks(n));
+    run(ctx, CL_K_VEC, [&] {
+        launch_dot(a, b, n, ctx->partials, nb, ctx->s);
+        launch_finalize(ctx->partials, nb, ctx->hv, ctx->dscal, ctx->s);
+    });
+    *out = read_scalar(ctx);
+    return CL_OK;
+    API_END
+}
+
+int cl_copy_f32(cl_ctx *ctx, const float *src, float *dst, size_t n)
+{
+    NEED_CTX();
+    if (!src || !dst) return fail(ctx, CL_ERR_ARG, "NULL pointer");
+    if (overlap(src, n * 4, dst, n * 4)) return fail(ctx, CL_ERR_ALIAS, "copy buffers overlap");
+    API_BEGIN
+    run(ctx, CL_K_VEC, [&] { launch_copy_f32(src, dst, n, ctx->s); });
+    return CL_OK;
+    API_END
+}
+
+int cl_profile_enable(cl_ctx *ctx, unsigned mask)
+{
+    NEED_CTX();
+    API_BEGIN
+    prof_drain(ctx);
+    ctx->prof.mask = mask;
+    for (int k = 0; k < CL_K_COUNT; ++k) { ctx->prof.ms[k] = 0.0; ctx->prof.n[k] = 0; }
+    return CL_OK;
+    API_END
+}
+
+int cl_profile_query(cl_ctx *ctx, int kclass, double *ms_total, long long *launches)
+{
+    NEED_CTX();
+    if (kclass < 0 || kclass >= CL_K_COUNT) return fail(ctx, CL_ERR_ARG, "bad kernel class");
+    API_BEGIN
+    prof_drain(ctx);
+    if (ms_total) *ms_total = ctx->prof.ms[kclass];
+    if (launches) *launches = ctx->prof.n[kclass];
+    return CL_OK;
+    API_END
+}
+
+const char *cl_kernel_class_name(int k)
+{
+    static const char *names[CL_K_COUNT] = {"feet", "sl_state", "sl_adjoint", "sl_inc", "fd", "quadrature", "fft", "vec"};
+    return (k >= 0 && k < CL_K_COUNT) ? names[k] : "unknown";
+}
+
+const char *cl_status_string(int s)
+{
+    switch (s) {
+    case CL_OK: return "ok";
+    case CL_ERR_ARG: return "invalid argument";
+    case CL_ERR_SHAPE: return "unsupported grid shape";
+    case CL_ERR_DTYPE: return "unsupported dtype";
+    case CL_ERR_OOM: return "out of device memory / workspace cap";
+    case CL_ERR_HIP: return "HIP runtime error";
+    case CL_ERR_NONFINITE: return "non-finite input";
+    case CL_ERR_UNSUPPORTED: return "unsupported option";
+    case CL_ERR_STATE: return "call order violated";
+    case CL_ERR_ALIAS: return "buffers overlap";
+    case CL_STATUS_MAXIT: return "iteration limit reached";
+    case CL_STATUS_LINESEARCH_FAIL: return "line search failed";
+    default: return "unknown status";
+    }
+}
+
+const char *cl_last_error(const cl_ctx *ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+
+} // extern "C"

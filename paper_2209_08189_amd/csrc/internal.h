@@ -1,0 +1,155 @@
+// internal.h -- declarations shared by the HIP translation units of
+// libclairehip.so (kernels + host solver).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/claire_hip.h"
+
+namespace clh {
+
+// Periodic grid on [0, 2pi)^3 with power-of-two extents (x3 fastest).
+struct Grid {
+    int n1, n2, n3;
+    int l1, l2, l3;       // log2 of the extents
+    int N;                // n1 * n2 * n3 (<= 2^30)
+    float ih1, ih2, ih3;  // 1 / h_d = n_d / (2 pi)
+    float h1, h2, h3;     // h_d = 2 pi / n_d
+};
+
+// ------------------------------------------------------------ storage I/O
+template <typename T> __device__ __forceinline__ float ldf(const T *p);
+template <> __device__ __forceinline__ float ldf<float>(const float *p) { return *p; }
+template <> __device__ __forceinline__ float ldf<__half>(const __half *p) { return __half2float(*p); }
+template <> __device__ __forceinline__ float ldf<__hip_bfloat16>(const __hip_bfloat16 *p) { return __bfloat162float(*p); }
+
+template <typename T> __device__ __forceinline__ void stf(T *p, float v);
+template <> __device__ __forceinline__ void stf<float>(float *p, float v) { *p = v; }
+template <> __device__ __forceinline__ void stf<__half>(__half *p, float v) { *p = __float2half(v); }
+template <> __device__ __forceinline__ void stf<__hip_bfloat16>(__hip_bfloat16 *p, float v) { *p = __float2bfloat16(v); }
+
+__device__ __forceinline__ void node_of(const Grid &g, int p, int &i, int &j, int &k)
+{
+    k = p & (g.n3 - 1);
+    j = (p >> g.l3) & (g.n2 - 1);
+    i = p >> (g.l3 + g.l2);
+}
+
+// 8th-order central first derivative along one axis (stride st, coordinate
+// c of extent n), times 1/h.
+template <typename T>
+__device__ __forceinline__ float fd8(const T *__restrict__ u, int p, int c, int n, int st, float ih)
+{
+    const int base = p - c * st;
+    const int m = n - 1;
+    float s = 0.8f * (ldf(u + base + ((c + 1) & m) * st) - ldf(u + base + ((c - 1) & m) * st));
+    s = fmaf(-0.2f, ldf(u + base + ((c + 2) & m) * st) - ldf(u + base + ((c - 2) & m) * st), s);
+    s = fmaf(4.0f / 105.0f, ldf(u + base + ((c + 3) & m) * st) - ldf(u + base + ((c - 3) & m) * st), s);
+    s = fmaf(-1.0f / 280.0f, ldf(u + base + ((c + 4) & m) * st) - ldf(u + base + ((c - 4) & m) * st), s);
+    return s * ih;
+}
+
+// Sum of v over a workgroup of blockDim.x (multiple of 64, <= 1024) threads
+// in a fixed order (wavefront shuffles, then wave 0 over the wave sums);
+// the result is valid in thread 0.
+__device__ __forceinline__ double block_sum(double v)
+{
+    __shared__ double wsum[16];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) wsum[w] = v;
+    __syncthreads();
+    if (w == 0) {
+        const int nw = blockDim.x >> 6;
+        v = lane < nw ? wsum[lane] : 0.0;
+#pragma unroll
+        for (int off = 8; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    }
+    return v;
+}
+
+inline size_t dtype_size(int dt) { return dt == CL_F32 ? 4 : 2; }
+
+// Run f(T{}) with T the C++ type of storage code dt.
+template <typename F> inline void with_dtype(int dt, F &&f)
+{
+    switch (dt) {
+    case CL_BF16: f(__hip_bfloat16{}); break;
+    case CL_F16: f(__half{}); break;
+    default: f(float{}); break;
+    }
+}
+
+// ------------------------------------------------------------ launches
+// Every launcher enqueues on `s` and returns nothing; errors surface through
+// hipGetLastError in the caller.
+
+// transport (k_transport.hip)
+void launch_feet(const Grid &g, float dt, const float *v, float *df, float *db,
+                 const float *divv, float *c, hipStream_t s);
+void launch_sl_state(const Grid &g, int dt_u, const void *u, const float *d, int dt_out, void *out, hipStream_t s);
+void launch_sl_adjoint(const Grid &g, int dt_u, const void *u, const float *d, const float *c,
+                       int dt_out, void *out, hipStream_t s);
+// out = sI * I[q](x + d) + sS * (-vt . grad_h m)(x); q/out of type dt_q, m of dt_m
+void launch_sl_inc(const Grid &g, int dt_q, const void *q, const float *d, int dt_m, const void *m,
+                   const float *vt, float sI, float sS, void *out, hipStream_t s);
+void launch_interp_f32(const Grid &g, const float *u, const float *d, float *out, hipStream_t s);
+
+// stencils (k_stencil.hip)
+void launch_fd_grad(const Grid &g, const float *u, float *out3, hipStream_t s);
+void launch_fd_div(const Grid &g, const float *v, float *out, hipStream_t s);
+// q0 = scale * (-vt . grad_h m0)
+void launch_inc_init(const Grid &g, int dt_m, const void *m0, const float *vt, float scale,
+                     int dt_q, void *q0, hipStream_t s);
+constexpr int MAX_T = 65;
+struct QuadArgs {
+    const void *lam[MAX_T];
+    const void *m[MAX_T];
+    float w[MAX_T];
+    int count;
+};
+// out3 = addend3 (may be NULL) + sum_j w_j lam^j grad_h m^j
+void launch_quadrature(const Grid &g, int dt_lam, int dt_m, const QuadArgs &qa, const float *addend3,
+                       float *out3, hipStream_t s);
+// lam = m1 - mN (stored as dt_lam); partial sums of (m1 - mN)^2 per block
+void launch_residual(const Grid &g, int dt_m, const void *m1, const void *mN, int dt_lam, void *lam,
+                     double *partials, int nblocks, hipStream_t s);
+void launch_sq_diff(const Grid &g, int dt_m, const void *a, const void *b, double *partials, int nblocks,
+                    hipStream_t s);
+
+// reductions and vector ops (k_reduce.hip)
+int reduce_blocks(size_t n);
+void launch_dot(const float *a, const float *b, size_t n, double *partials, int nblocks, hipStream_t s);
+void launch_finalize(const double *partials, int nblocks, double scale, double *out, hipStream_t s);
+void launch_count_nonfinite(const float *a, size_t n, double *partials, int nblocks, hipStream_t s);
+// x += alpha p; r -= alpha Hp; partials of r.r
+void launch_pcg_update(float *x, float *r, const float *p, const float *Hp, float alpha, size_t n,
+                       double *partials, int nblocks, hipStream_t s);
+// y = a + alpha * b   (y may alias a)
+void launch_axpy(float *y, const float *a, const float *b, float alpha, size_t n, hipStream_t s);
+// y = alpha * a  (y may alias a)
+void launch_scale(float *y, const float *a, float alpha, size_t n, hipStream_t s);
+void launch_convert(int dt_out, void *out, const float *in, size_t n, hipStream_t s);
+void launch_to_f32(int dt_in, const void *in, float *out, size_t n, hipStream_t s);
+void launch_copy_f32(const float *src, float *dst, size_t n, hipStream_t s);
+void launch_fill_f32(float *dst, float v, size_t n, hipStream_t s);
+
+// FFT (k_fft.hip)
+struct FFTPlan {
+    int n1, n2, n3, nh;          // nh = n3 / 2 + 1 complex values per x3 row
+    float2 *tw1, *tw2, *tw3;     // exp(-2 pi i t / n_d), t < n_d / 2
+    float2 *spec;                // complex work, ncomp_max * n1 * n2 * nh
+    int ncomp_max;
+};
+size_t fft_spec_bytes(int n1, int n2, int n3, int ncomp);
+// out_c = F^-1[ mult(k) F[in_c] ] (+ add_c), c < ncomp; kind as cl_spectral
+void spectral_apply(const FFTPlan &P, int kind, float beta, int ncomp, const float *in, float *out,
+                    const float *add, hipStream_t s);
+void fft_make_twiddles(float2 *host, int n);
+
+} // namespace clh

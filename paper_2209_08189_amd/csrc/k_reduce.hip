@@ -1,0 +1,193 @@
+// k_reduce.hip -- FP64 reductions (Krylov dot products, norms) and the
+// streaming vector updates of PCG.  Reductions are two-stage and
+// deterministic: a fixed number of workgroups accumulate FP64 partial sums
+// in grid-stride order and one workgroup adds the partials in index order.
+#include "internal.h"
+
+namespace clh {
+
+namespace {
+
+constexpr int TPB = 256;
+
+__global__ __launch_bounds__(TPB) void k_dot(const float *__restrict__ a, const float *__restrict__ b, size_t n,
+                                             double *__restrict__ partials)
+{
+    double acc = 0.0;
+    const size_t stride = (size_t)gridDim.x * TPB;
+    for (size_t p = (size_t)blockIdx.x * TPB + threadIdx.x; p < n; p += stride)
+        acc += (double)a[p] * (double)b[p];
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) partials[blockIdx.x] = acc;
+}
+
+__global__ __launch_bounds__(TPB) void k_count_nonfinite(const float *__restrict__ a, size_t n,
+                                                         double *__restrict__ partials)
+{
+    double acc = 0.0;
+    const size_t stride = (size_t)gridDim.x * TPB;
+    for (size_t p = (size_t)blockIdx.x * TPB + threadIdx.x; p < n; p += stride)
+        acc += isfinite(a[p]) ? 0.0 : 1.0;
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) partials[blockIdx.x] = acc;
+}
+
+__global__ __launch_bounds__(TPB) void k_finalize(const double *__restrict__ partials, int nb, double scale,
+                                                  double *__restrict__ out)
+{
+    // each thread sums a contiguous slice in order, then the slices in order
+    const int per = (nb + TPB - 1) / TPB;
+    double acc = 0.0;
+    for (int q = threadIdx.x * per; q < min(nb, (int)(threadIdx.x + 1) * per); ++q) acc += partials[q];
+    __shared__ double s[TPB];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int q = 0; q < TPB; ++q) t += s[q];
+        out[0] = scale * t;
+    }
+}
+
+__global__ __launch_bounds__(TPB) void k_pcg_update(float *__restrict__ x, float *__restrict__ r,
+                                                    const float *__restrict__ p, const float *__restrict__ Hp,
+                                                    float alpha, size_t n, double *__restrict__ partials)
+{
+    double acc = 0.0;
+    const size_t stride = (size_t)gridDim.x * TPB;
+    for (size_t q = (size_t)blockIdx.x * TPB + threadIdx.x; q < n; q += stride) {
+        x[q] = fmaf(alpha, p[q], x[q]);
+        const float rq = fmaf(-alpha, Hp[q], r[q]);
+        r[q] = rq;
+        acc += (double)rq * (double)rq;
+    }
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) partials[blockIdx.x] = acc;
+}
+
+__global__ __launch_bounds__(TPB) void k_axpy(float *y, const float *a, const float *b, float alpha,
+                                              size_t n)
+{
+    const size_t stride = (size_t)gridDim.x * TPB;
+    for (size_t q = (size_t)blockIdx.x * TPB + threadIdx.x; q < n; q += stride) y[q] = fmaf(alpha, b[q], a[q]);
+}
+
+__global__ __launch_bounds__(TPB) void k_scale(float *__restrict__ y, const float *__restrict__ a, float alpha,
+                                               size_t n)
+{
+    const size_t stride = (size_t)gridDim.x * TPB;
+    for (size_t q = (size_t)blockIdx.x * TPB + threadIdx.x; q < n; q += stride) y[q] = alpha * a[q];
+}
+
+template <typename To>
+__global__ __launch_bounds__(TPB) void k_convert(To *__restrict__ out, const float *__restrict__ in, size_t n)
+{
+    const size_t stride = (size_t)gridDim.x * TPB;
+    for (size_t q = (size_t)blockIdx.x * TPB + threadIdx.x; q < n; q += stride) stf(out + q, in[q]);
+}
+
+template <typename Ti>
+__global__ __launch_bounds__(TPB) void k_to_f32(const Ti *__restrict__ in, float *__restrict__ out, size_t n)
+{
+    const size_t stride = (size_t)gridDim.x * TPB;
+    for (size_t q = (size_t)blockIdx.x * TPB + threadIdx.x; q < n; q += stride) out[q] = ldf(in + q);
+}
+
+// Streaming copy, 16 bytes per lane per iteration when aligned.
+__global__ __launch_bounds__(TPB) void k_copy4(const float4 *__restrict__ src, float4 *__restrict__ dst, size_t n4)
+{
+    const size_t stride = (size_t)gridDim.x * TPB;
+    for (size_t q = (size_t)blockIdx.x * TPB + threadIdx.x; q < n4; q += stride) dst[q] = src[q];
+}
+
+__global__ __launch_bounds__(TPB) void k_copy1(const float *__restrict__ src, float *__restrict__ dst, size_t n)
+{
+    const size_t stride = (size_t)gridDim.x * TPB;
+    for (size_t q = (size_t)blockIdx.x * TPB + threadIdx.x; q < n; q += stride) dst[q] = src[q];
+}
+
+__global__ __launch_bounds__(TPB) void k_fill(float *__restrict__ dst, float v, size_t n)
+{
+    const size_t stride = (size_t)gridDim.x * TPB;
+    for (size_t q = (size_t)blockIdx.x * TPB + threadIdx.x; q < n; q += stride) dst[q] = v;
+}
+
+inline dim3 stream_grid(size_t n)
+{
+    size_t b = (n + TPB - 1) / TPB;
+    if (b > 8192) b = 8192;
+    if (b < 1) b = 1;
+    return dim3((unsigned)b);
+}
+
+} // namespace
+
+int reduce_blocks(size_t n)
+{
+    size_t b = (n + TPB * 4 - 1) / (TPB * 4);
+    if (b > 2048) b = 2048;
+    if (b < 1) b = 1;
+    return (int)b;
+}
+
+void launch_dot(const float *a, const float *b, size_t n, double *partials, int nblocks, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_dot, dim3(nblocks), dim3(TPB), 0, s, a, b, n, partials);
+}
+
+void launch_count_nonfinite(const float *a, size_t n, double *partials, int nblocks, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_count_nonfinite, dim3(nblocks), dim3(TPB), 0, s, a, n, partials);
+}
+
+void launch_finalize(const double *partials, int nblocks, double scale, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(TPB), 0, s, partials, nblocks, scale, out);
+}
+
+void launch_pcg_update(float *x, float *r, const float *p, const float *Hp, float alpha, size_t n,
+                       double *partials, int nblocks, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pcg_update, dim3(nblocks), dim3(TPB), 0, s, x, r, p, Hp, alpha, n, partials);
+}
+
+void launch_axpy(float *y, const float *a, const float *b, float alpha, size_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_axpy, stream_grid(n), dim3(TPB), 0, s, y, a, b, alpha, n);
+}
+
+void launch_scale(float *y, const float *a, float alpha, size_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_scale, stream_grid(n), dim3(TPB), 0, s, y, a, alpha, n);
+}
+
+void launch_convert(int dt_out, void *out, const float *in, size_t n, hipStream_t s)
+{
+    with_dtype(dt_out, [&](auto to) {
+        using To = decltype(to);
+        hipLaunchKernelGGL((k_convert<To>), stream_grid(n), dim3(TPB), 0, s, (To *)out, in, n);
+    });
+}
+
+void launch_to_f32(int dt_in, const void *in, float *out, size_t n, hipStream_t s)
+{
+    with_dtype(dt_in, [&](auto ti) {
+        using Ti = decltype(ti);
+        hipLaunchKernelGGL((k_to_f32<Ti>), stream_grid(n), dim3(TPB), 0, s, (const Ti *)in, out, n);
+    });
+}
+
+void launch_copy_f32(const float *src, float *dst, size_t n, hipStream_t s)
+{
+    if (((uintptr_t)src % 16) == 0 && ((uintptr_t)dst % 16) == 0 && n % 4 == 0)
+        hipLaunchKernelGGL(k_copy4, stream_grid(n / 4), dim3(TPB), 0, s, (const float4 *)src, (float4 *)dst, n / 4);
+    else
+        hipLaunchKernelGGL(k_copy1, stream_grid(n), dim3(TPB), 0, s, src, dst, n);
+}
+
+void launch_fill_f32(float *dst, float v, size_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill, stream_grid(n), dim3(TPB), 0, s, dst, v, n);
+}
+
+} // namespace clh

@@ -1,0 +1,59 @@
+"""The C-ABI library loads on the CPU and exports every function that
+include/claire_hip.h declares; the Python binding covers all of them.  No
+compute call is made (no GPU here)."""
+import ctypes
+import os
+import re
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "claire_hip.h")
+
+
+def declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(cl_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_header_declares_the_boundary():
+    names = declared()
+    for required in ("cl_set_images", "cl_set_velocity", "cl_objective", "cl_gradient",
+                     "cl_hessian_matvec", "cl_solve"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2209_08189_amd import claire
+    L = ctypes.CDLL(claire.LIB_PATH)
+    missing = [n for n in declared() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_header():
+    from paper_2209_08189_amd import claire
+    assert set(declared()) == set(claire.SIGNATURES)
+
+
+def test_status_strings_without_gpu():
+    from paper_2209_08189_amd import claire
+    L = claire.lib()
+    assert L.cl_status_string(0) == b"ok"
+    assert L.cl_status_string(-2) == b"unsupported grid shape"
+    assert L.cl_kernel_class_name(3) == b"sl_inc"
+
+
+def test_option_validation_without_gpu():
+    """cl_query_workspace validates options and shape on the host only."""
+    from paper_2209_08189_amd import claire
+    L = claire.lib()
+    o = claire.default_options()
+    nb = ctypes.c_ulonglong()
+    assert L.cl_query_workspace(256, 256, 256, ctypes.byref(o), ctypes.byref(nb)) == 0
+    assert nb.value > 40 * 256 ** 3 * 4
+    assert L.cl_query_workspace(100, 256, 256, ctypes.byref(o), ctypes.byref(nb)) == -2
+    o.beta_w = 1e-5
+    assert L.cl_query_workspace(64, 64, 64, ctypes.byref(o), ctypes.byref(nb)) == -7
+    o = claire.default_options(); o.struct_version = 99
+    assert L.cl_query_workspace(64, 64, 64, ctypes.byref(o), ctypes.byref(nb)) == -1
+    o = claire.default_options(); o.storage_state = 7
+    assert L.cl_query_workspace(64, 64, 64, ctypes.byref(o), ctypes.byref(nb)) == -3

@@ -1,0 +1,278 @@
+"""GPU path (C ABI, HIP kernels) against the FP64 oracle, element by element
+on the same seeded FP32-rounded inputs.
+
+Tolerances (relative L2 of the output field):
+  * single kernels and each transport (m(1), lambda(0), mt(1), lambda~(0),
+    feet, c): 1e-5 -- FP32 storage and accumulation of 64-term tricubic sums
+    and 8-term stencils give a few ulp per step;
+  * gradient and Hessian matvec: 1e-4 -- they add an FP32 FFT pair (error
+    ~ log2(N) ulp) and a quadrature of products whose terms partly cancel;
+  * final mismatch and velocity of the solve: 1e-3.
+Exact special cases (v = 0 identity, integer-shift rolls) are bitwise.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2209_08189_amd import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+TWO_PI = 2 * np.pi
+TOL_KERNEL = 1e-5
+TOL_OP = 1e-4
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2209_08189_amd import claire
+    claire.lib()          # raises if the HIP library is missing
+    torch.cuda.set_device(0)
+
+
+def reg(shape, **kw):
+    from paper_2209_08189_amd.claire import Registration
+    return Registration(shape, **kw)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def f32(a):
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+
+
+SHAPES = [(32, 32, 32), (16, 32, 64)]
+
+
+# ------------------------------------------------------------- kernels
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_interp_matches_oracle(shape):
+    u = f32(synth.random_field(shape, 1))
+    d = f32(synth.random_field((3,) + shape, 2, -3.5, 3.5))
+    r = reg(shape)
+    out = host(r.interp(dev(u), dev(d)))
+    assert rel(out, oracle.interp(u, d)) < TOL_KERNEL
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_fd_matches_oracle(shape):
+    u = f32(synth.random_field(shape, 3))
+    v = f32(synth.random_field((3,) + shape, 4))
+    r = reg(shape)
+    assert rel(host(r.fd_grad(dev(u))), oracle.grad(u)) < TOL_KERNEL
+    assert rel(host(r.fd_div(dev(v))), oracle.div(v)) < TOL_KERNEL
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("kind", [0, 1, 2])
+def test_spectral_matches_oracle(shape, kind):
+    x = f32(synth.random_field((3,) + shape, 5))
+    r = reg(shape, beta_v=5e-4)
+    out = host(r.spectral(kind, dev(x)))
+    assert rel(out, oracle.spectral(x, kind, 5e-4)) < TOL_KERNEL
+
+
+def _cfg1(n, amp=0.5):
+    shape = (n,) * 3
+    m0 = f32(synth.trig_template(shape))
+    vs = f32(synth.trig_velocity(shape, amp))
+    o = oracle.Oracle(shape, nt=4, beta=5e-4)
+    o.set_images(m0, m0)
+    o.set_velocity(vs)
+    o.state()
+    m1 = f32(o.field(oracle.FIELD_STATE, 4))
+    return shape, m0, m1, vs
+
+
+@pytest.mark.parametrize("n", [32, 64])
+def test_feet_and_adjoint_factor(n):
+    shape, m0, m1, vs = _cfg1(n)
+    df, db = oracle.feet(vs, 4)
+    c = oracle.adjoint_factor(vs, db, 4)
+    r = reg(shape)
+    r.set_images(dev(m0), dev(m1))
+    r.set_velocity(dev(vs))
+    r.gradient(want_g=False)
+    assert rel(host(r.field(4)), df) < TOL_KERNEL
+    assert rel(host(r.field(5)), db) < TOL_KERNEL
+    assert rel(host(r.field(6)) - 1.0, c - 1.0) < TOL_KERNEL
+
+
+# ------------------------------------------------------ transports/operators
+
+def _setup_pair(n, frac=0.5, shape=None):
+    shape_c, m0, m1, vs = _cfg1(n)
+    v = f32(frac * vs)
+    o = oracle.Oracle(shape_c, nt=4, beta=5e-4)
+    o.set_images(m0, m1)
+    o.set_velocity(v)
+    r = reg(shape_c)
+    r.set_images(dev(m0), dev(m1))
+    r.set_velocity(dev(v))
+    return shape_c, o, r, v
+
+
+@pytest.mark.parametrize("n", [32, 64])
+def test_state_adjoint_gradient(n):
+    shape, o, r, v = _setup_pair(n)
+    g_ref, (J, mis, regv) = o.gradient()
+    g, gn, Jg = r.gradient()
+    for j in (1, 4):
+        assert rel(host(r.field(0, j)), o.field(oracle.FIELD_STATE, j)) < TOL_KERNEL
+    for j in (3, 0):
+        assert rel(host(r.field(1, j)), o.field(oracle.FIELD_ADJOINT, j)) < TOL_KERNEL
+    print("n=%d gradient rel err %.3e" % (n, rel(host(g), g_ref)))
+    assert rel(host(g), g_ref) < TOL_OP
+    assert abs(Jg - J) / J < TOL_KERNEL
+
+
+@pytest.mark.parametrize("n", [32, 64])
+def test_hessian_matvec(n):
+    shape, o, r, v = _setup_pair(n)
+    vt = f32(synth.trig_velocity(shape, 0.3)[[2, 0, 1]] + 0.1 * synth.random_field((3,) + shape, 9))
+    o.gradient()
+    Hv_ref = o.matvec(vt)
+    r.gradient(want_g=False)
+    Hv = host(r.hessian_matvec(dev(vt)))
+    assert rel(host(r.field(2, 4)), o.field(oracle.FIELD_INC_STATE, 4)) < TOL_KERNEL
+    assert rel(host(r.field(3, 0)), o.field(oracle.FIELD_INC_ADJOINT, 0)) < TOL_KERNEL
+    print("n=%d matvec rel err %.3e" % (n, rel(Hv, Hv_ref)))
+    assert rel(Hv, Hv_ref) < TOL_OP
+
+
+def test_objective_and_precond():
+    shape, o, r, v = _setup_pair(32)
+    J, mis, regv = o.objective()
+    Jg, misg, regg = r.objective()
+    assert abs(misg - mis) / mis < TOL_KERNEL and abs(regg - regv) / regv < TOL_KERNEL
+    x = f32(synth.random_field((3,) + shape, 11))
+    assert rel(host(r.precond(dev(x))), o.precond(x)) < TOL_KERNEL
+
+
+# ------------------------------------------------------ exact special cases
+
+def test_zero_velocity_identity_bitwise():
+    shape = (32, 32, 32)
+    m0 = synth.smooth_random_field(shape, 12).astype(np.float32)
+    m1 = synth.smooth_random_field(shape, 13).astype(np.float32)
+    r = reg(shape)
+    r.set_images(dev(m0), dev(m1))
+    r.set_velocity(dev(np.zeros((3,) + shape)))
+    r.gradient(want_g=False)
+    for j in range(5):
+        assert np.array_equal(host(r.field(0, j)), m0.astype(np.float64))
+        assert np.array_equal(host(r.field(1, j)), (m1 - m0).astype(np.float64))
+
+
+def test_integer_shift_is_exact_roll():
+    n, nt = 32, 4
+    shape = (n,) * 3
+    h32 = np.float32(TWO_PI / n)
+    s = (1, -2, 2)
+    v = np.zeros((3,) + shape, dtype=np.float32)
+    for a in range(3):
+        v[a] = np.float32(4 * s[a]) * h32
+    m0 = synth.smooth_random_field(shape, 14).astype(np.float32)
+    r = reg(shape, nt=nt)
+    r.set_images(dev(m0), dev(m0))
+    r.set_velocity(dev(v))
+    out = host(r.deformed_template())
+    assert np.array_equal(out, np.roll(m0, shift=tuple(nt * x for x in s), axis=(0, 1, 2)).astype(np.float64))
+
+
+# ------------------------------------------------------------ solve (cfg1)
+
+def test_solve_cfg1_replay_5x10():
+    """The closed-form 64^3 problem, 5 GN steps x <= 10 PCG, with the oracle's
+    decisions (PCG iteration counts, step lengths) replayed on the GPU.
+    Every logged quantity agrees to 1e-5 up to and including the first GN
+    step whose PCG stopped at the iteration limit without converging.
+    After such a step the 5-step iterate is transient (relative gradient
+    ~4e-4) and any 1e-7-relative perturbation of the operator -- measured on
+    the FP64 oracle itself -- moves it by ~1.6e-3 in v; the last iterate is
+    therefore held to 5e-3 here and the 1e-3 bar is applied to the converged
+    solve in the next test."""
+    shape, m0, m1, vs = _cfg1(64)
+    o = oracle.Oracle(shape, nt=4, beta=5e-4)
+    o.set_images(m0, m1)
+    o.set_velocity(np.zeros((3,) + shape))
+    st, log, gref = o.solve(max_outer=5, max_pcg=10, gtol=0.0)
+    v_ref = o.velocity()
+    r = reg(shape, gtol=0.0, max_outer=5, max_pcg=10)
+    r.set_images(dev(m0), dev(m1))
+    r.solve_forced(log[:-1, 5].astype(int), log[:-1, 6])
+    glog = np.array(r.solve_log())
+    np.set_printoptions(precision=10, linewidth=160)
+    print("oracle log (k, J, mismatch, reg, |g|, pcg, alpha):\n", log[:, :7])
+    print("gpu replay log:\n", glog[:, :7])
+    first_unconverged = int(np.argmax(log[:-1, 5] >= 10)) if np.any(log[:-1, 5] >= 10) else len(log) - 2
+    for k in range(first_unconverged + 1):
+        for c in (1, 2, 4):
+            assert abs(glog[k, c] - log[k, c]) <= 1e-5 * abs(log[k, c]), (k, c)
+    ev = rel(host(r.velocity()), v_ref)
+    em = abs(glog[-1, 2] - log[-1, 2]) / log[-1, 2]
+    print("5-step replay: rel mismatch %.3e  rel velocity %.3e" % (em, ev))
+    assert ev < 5e-3 and em < 2e-2
+
+
+def test_solve_cfg1_converged():
+    """Free runs (each side takes its own decisions) of the closed-form 64^3
+    problem to convergence (12 GN steps, <= 10 PCG each): final velocity and
+    mismatch agree to 1e-3; decision flips are reported."""
+    shape, m0, m1, vs = _cfg1(64)
+    o = oracle.Oracle(shape, nt=4, beta=5e-4)
+    o.set_images(m0, m1)
+    o.set_velocity(np.zeros((3,) + shape))
+    st, log, gref = o.solve(max_outer=12, max_pcg=10, gtol=0.0)
+    v_ref = o.velocity()
+    r = reg(shape, gtol=0.0, max_outer=12, max_pcg=10)
+    r.set_images(dev(m0), dev(m1))
+    rep = r.solve()
+    glog = np.array(r.solve_log())
+    n = min(len(glog), len(log)) - 1
+    flips = int(np.sum(glog[:n, 5] != log[:n, 5]) + np.sum(glog[:n, 6] != log[:n, 6]))
+    ev = rel(host(r.velocity()), v_ref)
+    em = abs(rep["mismatch"] - log[-1, 2]) / log[-1, 2]
+    print("converged: status %s, relgrad gpu %.2e oracle %.2e, decision flips %d, rel mismatch %.3e, rel v %.3e"
+          % (rep["status_name"], rep["gnorm"] / rep["gref"], log[-1, 4] / gref, flips, em, ev))
+    assert ev < 1e-3 and em < 1e-3
+
+
+# ----------------------------------------------------------- error paths
+
+def test_error_codes():
+    from paper_2209_08189_amd.claire import ClaireError, Registration
+    with pytest.raises(ClaireError) as e:
+        Registration((24, 32, 32))
+    assert e.value.code == -2
+    with pytest.raises(ClaireError) as e:
+        Registration((32, 32, 32), workspace_cap=1024)
+    assert e.value.code == -4
+    r = reg((16, 16, 16))
+    with pytest.raises(ClaireError) as e:
+        r.gradient()
+    assert e.value.code == -8
+    bad = np.zeros((16, 16, 16), dtype=np.float32); bad[3, 4, 5] = np.nan
+    with pytest.raises(ClaireError) as e:
+        r.set_images(dev(bad), dev(bad))
+    assert e.value.code == -6
+    x = torch.zeros((3, 16, 16, 16), device="cuda")
+    r.set_images(dev(np.zeros((16, 16, 16))), dev(np.zeros((16, 16, 16))))
+    with pytest.raises(ClaireError) as e:
+        r.hessian_matvec(x, out=x)
+    assert e.value.code == -9
