@@ -122,7 +122,8 @@ int cl_gradient(cl_ctx *ctx, float *g_out, double *gnorm, double *J);
 /* Gauss-Newton Hessian matvec H vt = beta_v A vt + int lambda~ grad m dt
  * (Section 2.2, Hessian matvec; two transport solves) at the current v.
  * Needs the state of the current v (computed by cl_gradient or
- * cl_objective).  Enqueued only, no synchronisation. */
+ * cl_objective).  vt and Hvt must be 16-byte aligned (CL_ERR_ARG).
+ * Enqueued only, no synchronisation. */
 int cl_hessian_matvec(cl_ctx *ctx, const float *vt, float *Hvt);
 
 /* Spectral preconditioner z = (beta_v A)^-1 r with the k = 0 mode scaled by

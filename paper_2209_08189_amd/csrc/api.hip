@@ -46,6 +46,7 @@ struct cl_ctx {
     void *m = nullptr;                      // (nt+1) N, state dtype
     void *lam = nullptr;                    // (nt+1) N, adjoint dtype
     void *q[2] = {nullptr, nullptr};        // adjoint dtype
+    float *G = nullptr;                     // grad_h m^j, (nt+1) x 3N FP32
     float *v = nullptr, *vtrial = nullptr;  // 3N
     float *df = nullptr, *db = nullptr;     // 3N
     float *c = nullptr, *divv = nullptr;    // N
@@ -56,6 +57,7 @@ struct cl_ctx {
     FFTPlan fft{};
 
     bool images = false, vel = false, feet_f = false, feet_b = false, state = false, av = false;
+    bool sgrad = false;                     // G valid for the current state
     bool gref_valid = false;
     double gref = 0.0;
     std::vector<std::vector<double>> log;
@@ -201,6 +203,7 @@ void ensure_state(cl_ctx *ctx)
 {
     ensure_feet(ctx, false);
     if (ctx->state) return;
+    ctx->sgrad = false;
     const size_t bytes = ctx->N * dtype_size(ctx->dts);
     HIPCHK(hipMemcpyAsync(ctx->m, ctx->m0, bytes, hipMemcpyDeviceToDevice, ctx->s));
     for (int j = 0; j < ctx->nt; ++j)
@@ -209,6 +212,21 @@ void ensure_state(cl_ctx *ctx)
                             slot(ctx, ctx->m, ctx->dts, j + 1), ctx->s);
         });
     ctx->state = true;
+}
+
+// G^j = grad_h m^j for the current state (used by the gradient and every
+// Hessian matvec at this velocity)
+void ensure_sgrad(cl_ctx *ctx)
+{
+    ensure_state(ctx);
+    if (ctx->sgrad) return;
+    StateGradArgs a{};
+    for (int j = 0; j <= ctx->nt; ++j) {
+        a.m[j] = slot(ctx, ctx->m, ctx->dts, j);
+        a.G[j] = ctx->G + (size_t)j * 3 * ctx->N;
+    }
+    run(ctx, CL_K_FD, [&] { launch_state_grad(ctx->g, ctx->dts, a, ctx->nt + 1, ctx->s); });
+    ctx->sgrad = true;
 }
 
 double mismatch_only(cl_ctx *ctx)
@@ -246,7 +264,7 @@ QuadArgs quad_args(cl_ctx *ctx)
     qa.count = ctx->nt + 1;
     for (int j = 0; j <= ctx->nt; ++j) {
         qa.lam[j] = slot(ctx, ctx->lam, ctx->dta, j);
-        qa.m[j] = slot(ctx, ctx->m, ctx->dts, j);
+        qa.G[j] = ctx->G + (size_t)j * 3 * ctx->N;
         qa.w[j] = (j == 0 || j == ctx->nt) ? 0.5f * ctx->dt : ctx->dt;
     }
     return qa;
@@ -266,7 +284,7 @@ void adjoint_sweep(cl_ctx *ctx)
 double gradient(cl_ctx *ctx, double *J, double *mis_out, double *reg_out)
 {
     ensure_feet(ctx, true);
-    ensure_state(ctx);
+    ensure_sgrad(ctx);
     run(ctx, CL_K_VEC, [&] {
         launch_residual(ctx->g, ctx->dts, ctx->m1, slot(ctx, ctx->m, ctx->dts, ctx->nt), ctx->dta,
                         slot(ctx, ctx->lam, ctx->dta, ctx->nt), ctx->partials, ctx->nparts, ctx->s);
@@ -279,7 +297,7 @@ double gradient(cl_ctx *ctx, double *J, double *mis_out, double *reg_out)
         ctx->av = true;
     }
     const QuadArgs qa = quad_args(ctx);
-    run(ctx, CL_K_QUAD, [&] { launch_quadrature(ctx->g, ctx->dta, ctx->dts, qa, ctx->Av, ctx->grad, ctx->s); });
+    run(ctx, CL_K_QUAD, [&] { launch_quadrature(ctx->g, ctx->dta, qa, ctx->Av, ctx->grad, ctx->s); });
     const double reg = 0.5 * dotw(ctx, ctx->Av, ctx->v, 3 * ctx->N);
     if (mis_out) *mis_out = mis;
     if (reg_out) *reg_out = reg;
@@ -292,22 +310,23 @@ double gradient(cl_ctx *ctx, double *J, double *mis_out, double *reg_out)
 void matvec(cl_ctx *ctx, const float *vt, float *Hvt)
 {
     ensure_feet(ctx, true);
-    ensure_state(ctx);
+    ensure_sgrad(ctx);
     const float dt = ctx->dt;
     const int nt = ctx->nt;
-    run(ctx, CL_K_FD, [&] { launch_inc_init(ctx->g, ctx->dts, ctx->m, vt, 0.5f * dt, ctx->dta, ctx->q[0], ctx->s); });
+    const size_t N3 = 3 * ctx->N;
+    run(ctx, CL_K_VEC, [&] { launch_inc_init(ctx->g, ctx->G, vt, 0.5f * dt, ctx->dta, ctx->q[0], ctx->s); });
     for (int j = 0; j < nt; ++j) {
         const bool last = j == nt - 1;
         void *out = last ? slot(ctx, ctx->lam, ctx->dta, nt) : ctx->q[(j + 1) & 1];
         run(ctx, CL_K_SL_INC, [&] {
-            launch_sl_inc(ctx->g, ctx->dta, ctx->q[j & 1], ctx->df, ctx->dts, slot(ctx, ctx->m, ctx->dts, j + 1), vt,
-                          last ? -1.0f : 1.0f, last ? -0.5f * dt : dt, out, ctx->s);
+            launch_sl_inc(ctx->g, ctx->dta, ctx->q[j & 1], ctx->df, ctx->G + (size_t)(j + 1) * N3, vt,
+                          last ? -1.0f : 1.0f, last ? -0.5f * dt : dt, ctx->dta, out, ctx->s);
         });
     }
     adjoint_sweep(ctx);
     spectral(ctx, 0, 3, vt, ctx->tmp3, nullptr);
     const QuadArgs qa = quad_args(ctx);
-    run(ctx, CL_K_QUAD, [&] { launch_quadrature(ctx->g, ctx->dta, ctx->dts, qa, ctx->tmp3, Hvt, ctx->s); });
+    run(ctx, CL_K_QUAD, [&] { launch_quadrature(ctx->g, ctx->dta, qa, ctx->tmp3, Hvt, ctx->s); });
 }
 
 void precond(cl_ctx *ctx, const float *r, float *z) { spectral(ctx, 1, 3, r, z, nullptr); }
@@ -452,6 +471,7 @@ size_t workspace_bytes(int n1, int n2, int n3, const cl_options &o)
     b += (size_t)(o.nt + 1) * N * es;        // m^j
     b += (size_t)(o.nt + 1) * N * ea;        // lam^j / lam~^j
     b += 2 * N * ea;                         // q ping-pong
+    b += (size_t)(o.nt + 1) * 3 * N * sizeof(float);  // grad_h m^j
     b += 2 * N * sizeof(float);              // c, div v
     b += 12 * 3 * N * sizeof(float);         // v, vtrial, df, db, g, Av, tmp3, PCG x r z p Hp
     b += fft_spec_bytes(n1, n2, n3, 3);
@@ -555,6 +575,7 @@ int cl_create(cl_ctx **out, int n1, int n2, int n3, const cl_options *opt)
         ctx->lam = alloc((size_t)(ctx->nt + 1) * N * ea);
         ctx->q[0] = alloc(N * ea);
         ctx->q[1] = alloc(N * ea);
+        ctx->G = (float *)alloc((size_t)(ctx->nt + 1) * 3 * N * sizeof(float));
         float **vecs[] = {&ctx->v, &ctx->vtrial, &ctx->df, &ctx->db, &ctx->grad, &ctx->Av, &ctx->tmp3,
                           &ctx->px, &ctx->pr, &ctx->pz, &ctx->pp, &ctx->pHp};
         for (float **pv : vecs) *pv = (float *)alloc(3 * N * sizeof(float));
@@ -677,6 +698,7 @@ int cl_hessian_matvec(cl_ctx *ctx, const float *vt, float *Hvt)
     if (!ctx->images) return fail(ctx, CL_ERR_STATE, "cl_set_images has not been called");
     const size_t b = 3 * ctx->N * sizeof(float);
     if (overlap(vt, b, Hvt, b)) return fail(ctx, CL_ERR_ALIAS, "vt and Hvt overlap");
+    if (((uintptr_t)vt | (uintptr_t)Hvt) & 15) return fail(ctx, CL_ERR_ARG, "vt and Hvt must be 16-byte aligned");
     API_BEGIN
     matvec(ctx, vt, Hvt);
     return CL_OK;

@@ -89,33 +89,45 @@ template <typename F> inline void with_dtype(int dt, F &&f)
 // Every launcher enqueues on `s` and returns nothing; errors surface through
 // hipGetLastError in the caller.
 
+// epilogue operands of the semi-Lagrangian step kernels
+struct SLParams {
+    const float *c;       // adjoint factor
+    const float *G;       // grad_h m^{j+1}, 3 fields
+    const float *vt;      // incremental velocity, 3 fields
+    float sI, sS;
+};
+
 // transport (k_transport.hip)
 void launch_feet(const Grid &g, float dt, const float *v, float *df, float *db,
                  const float *divv, float *c, hipStream_t s);
 void launch_sl_state(const Grid &g, int dt_u, const void *u, const float *d, int dt_out, void *out, hipStream_t s);
 void launch_sl_adjoint(const Grid &g, int dt_u, const void *u, const float *d, const float *c,
                        int dt_out, void *out, hipStream_t s);
-// out = sI * I[q](x + d) + sS * (-vt . grad_h m)(x); q/out of type dt_q, m of dt_m
-void launch_sl_inc(const Grid &g, int dt_q, const void *q, const float *d, int dt_m, const void *m,
-                   const float *vt, float sI, float sS, void *out, hipStream_t s);
+// out = sI * I[q](x + d) + sS * (-vt . G)(x), G = grad_h m^{j+1} (3 FP32 fields)
+void launch_sl_inc(const Grid &g, int dt_q, const void *q, const float *d, const float *G, const float *vt,
+                   float sI, float sS, int dt_out, void *out, hipStream_t s);
 void launch_interp_f32(const Grid &g, const float *u, const float *d, float *out, hipStream_t s);
 
 // stencils (k_stencil.hip)
 void launch_fd_grad(const Grid &g, const float *u, float *out3, hipStream_t s);
 void launch_fd_div(const Grid &g, const float *v, float *out, hipStream_t s);
-// q0 = scale * (-vt . grad_h m0)
-void launch_inc_init(const Grid &g, int dt_m, const void *m0, const float *vt, float scale,
-                     int dt_q, void *q0, hipStream_t s);
 constexpr int MAX_T = 65;
+// G^j = grad_h m^j, j < count (FP32, 3 fields each)
+struct StateGradArgs {
+    const void *m[MAX_T];
+    float *G[MAX_T];
+};
+void launch_state_grad(const Grid &g, int dt_m, const StateGradArgs &a, int count, hipStream_t s);
+// q0 = scale * (-vt . G^0)
+void launch_inc_init(const Grid &g, const float *G0, const float *vt, float scale, int dt_q, void *q0, hipStream_t s);
 struct QuadArgs {
     const void *lam[MAX_T];
-    const void *m[MAX_T];
+    const float *G[MAX_T];
     float w[MAX_T];
     int count;
 };
-// out3 = addend3 (may be NULL) + sum_j w_j lam^j grad_h m^j
-void launch_quadrature(const Grid &g, int dt_lam, int dt_m, const QuadArgs &qa, const float *addend3,
-                       float *out3, hipStream_t s);
+// out3 = addend3 (may be NULL) + sum_j w_j lam^j G^j
+void launch_quadrature(const Grid &g, int dt_lam, const QuadArgs &qa, const float *addend3, float *out3, hipStream_t s);
 // lam = m1 - mN (stored as dt_lam); partial sums of (m1 - mN)^2 per block
 void launch_residual(const Grid &g, int dt_m, const void *m1, const void *mN, int dt_lam, void *lam,
                      double *partials, int nblocks, hipStream_t s);

@@ -47,41 +47,71 @@ __global__ __launch_bounds__(TPB) void k_fd_div(Grid g, const float *__restrict_
     out[p] = d1 + d2 + d3;
 }
 
-template <typename Tm, typename Tq>
-__global__ __launch_bounds__(TPB) void k_inc_init(Grid g, const Tm *__restrict__ m0, const float *__restrict__ vt,
-                                                  float scale, Tq *__restrict__ q0)
+// G^j = grad_h m^j for every stored time point j = blockIdx.y.
+template <typename Tm>
+__global__ __launch_bounds__(TPB) void k_state_grad(Grid g, StateGradArgs a)
 {
     const int p = blockIdx.x * TPB + threadIdx.x;
     if (p >= g.N) return;
+    const int t = blockIdx.y;
     float gr[3];
-    grad_at(g, m0, p, gr);
-    const float s = -(vt[p] * gr[0] + vt[g.N + p] * gr[1] + vt[2 * (size_t)g.N + p] * gr[2]);
-    stf(q0 + p, scale * s);
+    grad_at(g, (const Tm *)a.m[t], p, gr);
+    float *G = a.G[t];
+    G[p] = gr[0];
+    G[g.N + p] = gr[1];
+    G[2 * (size_t)g.N + p] = gr[2];
 }
 
-template <typename Tl, typename Tm>
+// q0 = scale * (-vt . G^0), four nodes per thread
+template <typename Tq>
+__global__ __launch_bounds__(TPB) void k_inc_init(Grid g, const float *__restrict__ G0, const float *__restrict__ vt,
+                                                  float scale, Tq *__restrict__ q0)
+{
+    const size_t N = g.N;
+    const int p = (blockIdx.x * TPB + threadIdx.x) * 4;
+    if (p >= g.N) return;
+    const float4 v0 = *(const float4 *)(vt + p), v1 = *(const float4 *)(vt + N + p), v2 = *(const float4 *)(vt + 2 * N + p);
+    const float4 g0 = *(const float4 *)(G0 + p), g1 = *(const float4 *)(G0 + N + p), g2 = *(const float4 *)(G0 + 2 * N + p);
+    stf(q0 + p + 0, -scale * (v0.x * g0.x + v1.x * g1.x + v2.x * g2.x));
+    stf(q0 + p + 1, -scale * (v0.y * g0.y + v1.y * g1.y + v2.y * g2.y));
+    stf(q0 + p + 2, -scale * (v0.z * g0.z + v1.z * g1.z + v2.z * g2.z));
+    stf(q0 + p + 3, -scale * (v0.w * g0.w + v1.w * g1.w + v2.w * g2.w));
+}
+
+template <typename T> __device__ __forceinline__ float4 ld4(const T *p)
+{
+    return make_float4(ldf(p), ldf(p + 1), ldf(p + 2), ldf(p + 3));
+}
+template <> __device__ __forceinline__ float4 ld4<float>(const float *p) { return *(const float4 *)p; }
+
+// out3 = add3 + sum_j w_j lam^j G^j, four nodes per thread (streaming)
+template <typename Tl>
 __global__ __launch_bounds__(TPB) void k_quadrature(Grid g, QuadArgs qa, const float *__restrict__ add,
                                                     float *__restrict__ out)
 {
-    const int p = blockIdx.x * TPB + threadIdx.x;
+    const size_t N = g.N;
+    const int p = (blockIdx.x * TPB + threadIdx.x) * 4;
     if (p >= g.N) return;
-    float b0 = 0.f, b1 = 0.f, b2 = 0.f;
+    float4 b0 = make_float4(0.f, 0.f, 0.f, 0.f), b1 = b0, b2 = b0;
     for (int t = 0; t < qa.count; ++t) {
-        float gr[3];
-        grad_at(g, (const Tm *)qa.m[t], p, gr);
-        const float wl = qa.w[t] * ldf((const Tl *)qa.lam[t] + p);
-        b0 = fmaf(wl, gr[0], b0);
-        b1 = fmaf(wl, gr[1], b1);
-        b2 = fmaf(wl, gr[2], b2);
+        const float4 l = ld4((const Tl *)qa.lam[t] + p);
+        const float w = qa.w[t];
+        const float4 wl = make_float4(w * l.x, w * l.y, w * l.z, w * l.w);
+        const float *G = qa.G[t];
+        const float4 g0 = *(const float4 *)(G + p), g1 = *(const float4 *)(G + N + p), g2 = *(const float4 *)(G + 2 * N + p);
+        b0.x = fmaf(wl.x, g0.x, b0.x); b0.y = fmaf(wl.y, g0.y, b0.y); b0.z = fmaf(wl.z, g0.z, b0.z); b0.w = fmaf(wl.w, g0.w, b0.w);
+        b1.x = fmaf(wl.x, g1.x, b1.x); b1.y = fmaf(wl.y, g1.y, b1.y); b1.z = fmaf(wl.z, g1.z, b1.z); b1.w = fmaf(wl.w, g1.w, b1.w);
+        b2.x = fmaf(wl.x, g2.x, b2.x); b2.y = fmaf(wl.y, g2.y, b2.y); b2.z = fmaf(wl.z, g2.z, b2.z); b2.w = fmaf(wl.w, g2.w, b2.w);
     }
     if (add) {
-        b0 += add[p];
-        b1 += add[g.N + p];
-        b2 += add[2 * (size_t)g.N + p];
+        const float4 a0 = *(const float4 *)(add + p), a1 = *(const float4 *)(add + N + p), a2 = *(const float4 *)(add + 2 * N + p);
+        b0.x += a0.x; b0.y += a0.y; b0.z += a0.z; b0.w += a0.w;
+        b1.x += a1.x; b1.y += a1.y; b1.z += a1.z; b1.w += a1.w;
+        b2.x += a2.x; b2.y += a2.y; b2.z += a2.z; b2.w += a2.w;
     }
-    out[p] = b0;
-    out[g.N + p] = b1;
-    out[2 * (size_t)g.N + p] = b2;
+    *(float4 *)(out + p) = b0;
+    *(float4 *)(out + N + p) = b1;
+    *(float4 *)(out + 2 * N + p) = b2;
 }
 
 // lam^nt = m1 - m^nt and per-block partial sums of its square, grid-stride.
@@ -111,28 +141,28 @@ void launch_fd_div(const Grid &g, const float *v, float *out, hipStream_t s)
     hipLaunchKernelGGL(k_fd_div, grid_of(g), dim3(TPB), 0, s, g, v, out);
 }
 
-void launch_inc_init(const Grid &g, int dt_m, const void *m0, const float *vt, float scale, int dt_q, void *q0,
-                     hipStream_t s)
+void launch_state_grad(const Grid &g, int dt_m, const StateGradArgs &a, int count, hipStream_t s)
 {
     with_dtype(dt_m, [&](auto tm) {
         using Tm = decltype(tm);
-        with_dtype(dt_q, [&](auto tq) {
-            using Tq = decltype(tq);
-            hipLaunchKernelGGL((k_inc_init<Tm, Tq>), grid_of(g), dim3(TPB), 0, s, g, (const Tm *)m0, vt, scale,
-                               (Tq *)q0);
-        });
+        hipLaunchKernelGGL((k_state_grad<Tm>), dim3((g.N + TPB - 1) / TPB, count), dim3(TPB), 0, s, g, a);
     });
 }
 
-void launch_quadrature(const Grid &g, int dt_lam, int dt_m, const QuadArgs &qa, const float *addend3, float *out3,
-                       hipStream_t s)
+void launch_inc_init(const Grid &g, const float *G0, const float *vt, float scale, int dt_q, void *q0, hipStream_t s)
+{
+    with_dtype(dt_q, [&](auto tq) {
+        using Tq = decltype(tq);
+        hipLaunchKernelGGL((k_inc_init<Tq>), dim3((g.N / 4 + TPB - 1) / TPB), dim3(TPB), 0, s, g, G0, vt, scale,
+                           (Tq *)q0);
+    });
+}
+
+void launch_quadrature(const Grid &g, int dt_lam, const QuadArgs &qa, const float *addend3, float *out3, hipStream_t s)
 {
     with_dtype(dt_lam, [&](auto tl) {
         using Tl = decltype(tl);
-        with_dtype(dt_m, [&](auto tm) {
-            using Tm = decltype(tm);
-            hipLaunchKernelGGL((k_quadrature<Tl, Tm>), grid_of(g), dim3(TPB), 0, s, g, qa, addend3, out3);
-        });
+        hipLaunchKernelGGL((k_quadrature<Tl>), dim3((g.N / 4 + TPB - 1) / TPB), dim3(TPB), 0, s, g, qa, addend3, out3);
     });
 }
 

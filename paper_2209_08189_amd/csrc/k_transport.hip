@@ -42,7 +42,12 @@ __device__ __forceinline__ void make_foot(const Grid &g, int i, int j, int k, fl
     lagrange4(d1 - f1, F.w1);
     lagrange4(d2 - f2, F.w2);
     lagrange4(d3 - f3, F.w3);
-    const int b1 = i + (int)f1 - 1, b2 = j + (int)f2 - 1, b3 = k + (int)f3 - 1;
+    // integer parts clamped to +-2^24 so the conversion is defined for any
+    // finite input; indices are wrapped by masking below
+    const float c1 = fminf(fmaxf(f1, -16777216.0f), 16777216.0f);
+    const float c2 = fminf(fmaxf(f2, -16777216.0f), 16777216.0f);
+    const float c3 = fminf(fmaxf(f3, -16777216.0f), 16777216.0f);
+    const int b1 = i + (int)c1 - 1, b2 = j + (int)c2 - 1, b3 = k + (int)c3 - 1;
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
         F.o1[a] = ((b1 + a) & (g.n1 - 1)) << (g.l2 + g.l3);
@@ -143,22 +148,31 @@ __global__ __launch_bounds__(TPB) void k_feet(Grid g, float dt, const float *__r
     c[p] = 1.0f + 0.5f * dt * (dbar + d + dt * dbar * d);
 }
 
-template <typename Tu, typename To>
-__global__ __launch_bounds__(TPB) void k_sl_state(Grid g, const Tu *__restrict__ u, const float *__restrict__ d,
-                                                  To *__restrict__ out)
+// ------------------------------------------------ semi-Lagrangian steps
+// One SL step gathers u at the feet of every node and applies a mode-specific
+// epilogue:
+//   SL_STATE:  out = I[u](X)
+//   SL_ADJ:    out = c * I[u](X)                    (adjoint divergence factor)
+//   SL_INC:    out = sI * I[u](X) + sS * (-vt . G)  (incremental source,
+//              G = grad_h m^{j+1} precomputed once per velocity)
+enum { SL_STATE = 0, SL_ADJ = 1, SL_INC = 2 };
+
+template <int MODE>
+__device__ __forceinline__ float epilogue(const Grid &g, const SLParams &prm, int p, float val)
 {
-    const int p = blockIdx.x * TPB + threadIdx.x;
-    if (p >= g.N) return;
-    int i, j, k;
-    node_of(g, p, i, j, k);
-    Foot F;
-    make_foot(g, i, j, k, d[p], d[g.N + p], d[2 * (size_t)g.N + p], F);
-    stf(out + p, gather(u, F));
+    if (MODE == SL_ADJ) return prm.c[p] * val;
+    if (MODE == SL_INC) {
+        const size_t N = g.N;
+        const float src = -(prm.vt[p] * prm.G[p] + prm.vt[N + p] * prm.G[N + p] + prm.vt[2 * N + p] * prm.G[2 * N + p]);
+        return prm.sI * val + prm.sS * src;
+    }
+    return val;
 }
 
-template <typename Tu, typename To>
-__global__ __launch_bounds__(TPB) void k_sl_adjoint(Grid g, const Tu *__restrict__ u, const float *__restrict__ d,
-                                                    const float *__restrict__ c, To *__restrict__ out)
+// Per-node version (small grids, and tiles whose feet spread too far).
+template <typename Tu, typename To, int MODE>
+__global__ __launch_bounds__(TPB) void k_sl_node(Grid g, const Tu *__restrict__ u, const float *__restrict__ d,
+                                                 SLParams prm, To *__restrict__ out)
 {
     const int p = blockIdx.x * TPB + threadIdx.x;
     if (p >= g.N) return;
@@ -166,29 +180,187 @@ __global__ __launch_bounds__(TPB) void k_sl_adjoint(Grid g, const Tu *__restrict
     node_of(g, p, i, j, k);
     Foot F;
     make_foot(g, i, j, k, d[p], d[g.N + p], d[2 * (size_t)g.N + p], F);
-    stf(out + p, c[p] * gather(u, F));
+    stf(out + p, epilogue<MODE>(g, prm, p, gather(u, F)));
 }
 
-template <typename Tq, typename Tm>
-__global__ __launch_bounds__(TPB) void k_sl_inc(Grid g, const Tq *__restrict__ q, const float *__restrict__ d,
-                                                const Tm *__restrict__ m, const float *__restrict__ vt,
-                                                float sI, float sS, Tq *__restrict__ out)
+// Tiled version: a workgroup owns a TZ x TY x TX tile (x1, x2, x3), finds
+// the bounding box of the 4x4x4 stencils of its feet, stages that box in LDS
+// and gathers from LDS.  For a smooth velocity the feet of a tile form a
+// slightly deformed copy of the tile, so the box is the tile plus a thin
+// shell.  The box is stored with fixed pitches (PZ, PY, PX) so that the 64
+// stencil offsets of a point are compile-time LDS immediates; a tile whose
+// box exceeds them gathers straight from global memory instead (same
+// arithmetic, same result).  The kernel is VALU-bound, so the per-point
+// instruction count is what the layout minimises.
+constexpr int TX = 32, TY = 8, TZ = 8;
+constexpr int PX = 40, PY = 14, PZ = 14;      // box pitches: tile + 3 + slack of 5 / 3 / 3
+
+__device__ __forceinline__ int ifloor(float x)
 {
-    const int p = blockIdx.x * TPB + threadIdx.x;
-    if (p >= g.N) return;
-    int i, j, k;
-    node_of(g, p, i, j, k);
-    Foot F;
-    make_foot(g, i, j, k, d[p], d[g.N + p], d[2 * (size_t)g.N + p], F);
-    const float gi = gather(q, F);
-    const float g1 = fd8(m, p, i, g.n1, g.n2 * g.n3, g.ih1);
-    const float g2 = fd8(m, p, j, g.n2, g.n3, g.ih2);
-    const float g3 = fd8(m, p, k, g.n3, 1, g.ih3);
-    const float src = -(vt[p] * g1 + vt[g.N + p] * g2 + vt[2 * (size_t)g.N + p] * g3);
-    stf(out + p, sI * gi + sS * src);
+    const float f = fminf(fmaxf(floorf(x), -16777216.0f), 16777216.0f);
+    return (int)f;
+}
+
+__device__ __forceinline__ int wave_min(int v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
+    return v;
+}
+__device__ __forceinline__ int wave_max(int v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// Cubic Lagrange weights at fraction f, factored to share products.
+__device__ __forceinline__ void lagrange4_fast(float f, float w[4])
+{
+    const float fm1 = f - 1.0f, fp1 = f + 1.0f, fm2 = f - 2.0f;
+    const float a = f * fm1;          // f (f-1)
+    const float b = fp1 * fm2;        // (f+1)(f-2)
+    w[0] = (a * fm2) * (-1.0f / 6.0f);
+    w[1] = (b * fm1) * 0.5f;
+    w[2] = (b * f) * -0.5f;
+    w[3] = (a * fp1) * (1.0f / 6.0f);
+}
+
+template <typename Tu, typename To, int MODE>
+__global__ __launch_bounds__(TPB) void k_sl_tile(Grid g, const Tu *__restrict__ u, const float *__restrict__ d,
+                                                 SLParams prm, To *__restrict__ out, int ntx, int nty, int nblk)
+{
+    __shared__ Tu box[PZ * PY * PX];
+    __shared__ int red[TPB / 64][6];
+    // Workgroups go round-robin to the 8 XCDs; give each XCD a contiguous
+    // run of tiles so that neighbouring boxes meet in the same L2.
+    const int b = blockIdx.x;
+    const int tile = (nblk & 7) ? b : (b & 7) * (nblk >> 3) + (b >> 3);
+    const int tx = tile % ntx, ty = (tile / ntx) % nty, tz = tile / (ntx * nty);
+    const int lane = threadIdx.x & (TX - 1), row = threadIdx.x / TX;
+    const int i0 = tz * TZ, j = ty * TY + row, k = tx * TX + lane;
+    const int plane = g.n2 << g.l3;
+    const int p0 = ((i0 << g.l2) + j) * g.n3 + k;
+    const size_t N = g.N;
+
+    float d1[TZ], d2[TZ], d3[TZ];
+    int mn1 = 1 << 30, mx1 = -(1 << 30), mn2 = 1 << 30, mx2 = -(1 << 30), mn3 = 1 << 30, mx3 = -(1 << 30);
+#pragma unroll
+    for (int q = 0; q < TZ; ++q) {
+        const int p = p0 + q * plane;
+        d1[q] = d[p];
+        d2[q] = d[N + p];
+        d3[q] = d[2 * N + p];
+        const int b1 = q + ifloor(d1[q]), b2 = ifloor(d2[q]), b3 = ifloor(d3[q]);
+        mn1 = min(mn1, b1); mx1 = max(mx1, b1);
+        mn2 = min(mn2, b2); mx2 = max(mx2, b2);
+        mn3 = min(mn3, b3); mx3 = max(mx3, b3);
+    }
+    // row / lane are constant per thread: add them after the loop
+    mn2 += row; mx2 += row; mn3 += lane; mx3 += lane;
+    mn1 = wave_min(mn1); mx1 = wave_max(mx1);
+    mn2 = wave_min(mn2); mx2 = wave_max(mx2);
+    mn3 = wave_min(mn3); mx3 = wave_max(mx3);
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if ((threadIdx.x & 63) == 0) {
+        red[wv][0] = mn1; red[wv][1] = mx1; red[wv][2] = mn2;
+        red[wv][3] = mx2; red[wv][4] = mn3; red[wv][5] = mx3;
+    }
+    __syncthreads();
+    mn1 = red[0][0]; mx1 = red[0][1]; mn2 = red[0][2]; mx2 = red[0][3]; mn3 = red[0][4]; mx3 = red[0][5];
+#pragma unroll
+    for (int w = 1; w < TPB / 64; ++w) {
+        mn1 = min(mn1, red[w][0]); mx1 = max(mx1, red[w][1]);
+        mn2 = min(mn2, red[w][2]); mx2 = max(mx2, red[w][3]);
+        mn3 = min(mn3, red[w][4]); mx3 = max(mx3, red[w][5]);
+    }
+    // box origin (stencil starts one node below the floor), extents
+    mn1 -= 1; mn2 -= 1; mn3 -= 1;
+    const int E1 = mx1 + 3 - mn1, E2 = mx2 + 3 - mn2, E3 = mx3 + 3 - mn3;
+    const bool fits = E1 <= PZ && E2 <= PY && E3 <= PX;
+
+    if (fits) {
+        // Stage rows (a, bb) of the box: wave wv loads rows bb = wv, wv+4, ...
+        // of two x1 planes per batch, lane c < E3 loads column c.
+        const int l64 = threadIdx.x & 63;
+        const int gi0 = i0 + mn1, gj0 = ty * TY + mn2;
+        const int col = (tx * TX + mn3 + l64) & (g.n3 - 1);
+        const bool act = l64 < E3;
+        for (int a0 = 0; a0 < E1; a0 += 2) {
+            Tu vals[8];
+#pragma unroll
+            for (int ia = 0; ia < 2; ++ia)
+#pragma unroll
+                for (int jb = 0; jb < 4; ++jb) {
+                    const int a = a0 + ia, bb = wv + 4 * jb;
+                    if (act && a < E1 && bb < E2)
+                        vals[ia * 4 + jb] =
+                            u[(((gi0 + a) & (g.n1 - 1)) << (g.l2 + g.l3)) + (((gj0 + bb) & (g.n2 - 1)) << g.l3) + col];
+                }
+#pragma unroll
+            for (int ia = 0; ia < 2; ++ia)
+#pragma unroll
+                for (int jb = 0; jb < 4; ++jb) {
+                    const int a = a0 + ia, bb = wv + 4 * jb;
+                    if (act && a < E1 && bb < E2) box[(a * PY + bb) * PX + l64] = vals[ia * 4 + jb];
+                }
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (int q = 0; q < TZ; ++q) {
+            const float f1 = floorf(d1[q]), f2 = floorf(d2[q]), f3 = floorf(d3[q]);
+            float w1[4], w2[4], w3[4];
+            lagrange4_fast(d1[q] - f1, w1);
+            lagrange4_fast(d2[q] - f2, w2);
+            lagrange4_fast(d3[q] - f3, w3);
+            // same clamped integer parts as the bounding box, so the stencil
+            // lies inside the box for any finite displacement
+            const int s1 = q + ifloor(d1[q]) - mn1 - 1;
+            const int s2 = row + ifloor(d2[q]) - mn2 - 1;
+            const int s3 = lane + ifloor(d3[q]) - mn3 - 1;
+            const Tu *bp = box + (s1 * PY + s2) * PX + s3;
+            float s = 0.0f;
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                float sa = 0.0f;
+#pragma unroll
+                for (int bq = 0; bq < 4; ++bq) {
+                    const Tu *rp = bp + (a * PY + bq) * PX;
+                    float t = w3[0] * ldf(rp);
+                    t = fmaf(w3[1], ldf(rp + 1), t);
+                    t = fmaf(w3[2], ldf(rp + 2), t);
+                    t = fmaf(w3[3], ldf(rp + 3), t);
+                    sa = fmaf(w2[bq], t, sa);
+                }
+                s = fmaf(w1[a], sa, s);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            const int p = p0 + q * plane;
+            stf(out + p, epilogue<MODE>(g, prm, p, s));
+        }
+    } else {
+        for (int q = 0; q < TZ; ++q) {
+            const int p = p0 + q * plane;
+            Foot F;
+            make_foot(g, i0 + q, j, k, d1[q], d2[q], d3[q], F);
+            stf(out + p, epilogue<MODE>(g, prm, p, gather(u, F)));
+        }
+    }
 }
 
 inline dim3 grid_of(const Grid &g) { return dim3((g.N + TPB - 1) / TPB); }
+
+template <typename Tu, typename To, int MODE>
+void launch_sl(const Grid &g, const Tu *u, const float *d, const SLParams &prm, To *out, hipStream_t s)
+{
+    if (g.n3 >= TX && g.n2 >= TY && g.n1 >= TZ) {
+        const int ntx = g.n3 / TX, nty = g.n2 / TY, ntz = g.n1 / TZ;
+        const int nblk = ntx * nty * ntz;
+        hipLaunchKernelGGL((k_sl_tile<Tu, To, MODE>), dim3(nblk), dim3(TPB), 0, s, g, u, d, prm, out, ntx, nty, nblk);
+    } else {
+        hipLaunchKernelGGL((k_sl_node<Tu, To, MODE>), grid_of(g), dim3(TPB), 0, s, g, u, d, prm, out);
+    }
+}
 
 } // namespace
 
@@ -204,7 +376,7 @@ void launch_sl_state(const Grid &g, int dt_u, const void *u, const float *d, int
         using Tu = decltype(tu);
         with_dtype(dt_out, [&](auto to) {
             using To = decltype(to);
-            hipLaunchKernelGGL((k_sl_state<Tu, To>), grid_of(g), dim3(TPB), 0, s, g, (const Tu *)u, d, (To *)out);
+            launch_sl<Tu, To, SL_STATE>(g, (const Tu *)u, d, SLParams{}, (To *)out, s);
         });
     });
 }
@@ -212,32 +384,37 @@ void launch_sl_state(const Grid &g, int dt_u, const void *u, const float *d, int
 void launch_sl_adjoint(const Grid &g, int dt_u, const void *u, const float *d, const float *c, int dt_out,
                        void *out, hipStream_t s)
 {
+    SLParams prm{};
+    prm.c = c;
     with_dtype(dt_u, [&](auto tu) {
         using Tu = decltype(tu);
         with_dtype(dt_out, [&](auto to) {
             using To = decltype(to);
-            hipLaunchKernelGGL((k_sl_adjoint<Tu, To>), grid_of(g), dim3(TPB), 0, s, g, (const Tu *)u, d, c,
-                               (To *)out);
+            launch_sl<Tu, To, SL_ADJ>(g, (const Tu *)u, d, prm, (To *)out, s);
         });
     });
 }
 
-void launch_sl_inc(const Grid &g, int dt_q, const void *q, const float *d, int dt_m, const void *m,
-                   const float *vt, float sI, float sS, void *out, hipStream_t s)
+void launch_sl_inc(const Grid &g, int dt_q, const void *q, const float *d, const float *G, const float *vt, float sI,
+                   float sS, int dt_out, void *out, hipStream_t s)
 {
+    SLParams prm{};
+    prm.G = G;
+    prm.vt = vt;
+    prm.sI = sI;
+    prm.sS = sS;
     with_dtype(dt_q, [&](auto tq) {
         using Tq = decltype(tq);
-        with_dtype(dt_m, [&](auto tm) {
-            using Tm = decltype(tm);
-            hipLaunchKernelGGL((k_sl_inc<Tq, Tm>), grid_of(g), dim3(TPB), 0, s, g, (const Tq *)q, d,
-                               (const Tm *)m, vt, sI, sS, (Tq *)out);
+        with_dtype(dt_out, [&](auto to) {
+            using To = decltype(to);
+            launch_sl<Tq, To, SL_INC>(g, (const Tq *)q, d, prm, (To *)out, s);
         });
     });
 }
 
 void launch_interp_f32(const Grid &g, const float *u, const float *d, float *out, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_sl_state<float, float>), grid_of(g), dim3(TPB), 0, s, g, u, d, out);
+    launch_sl<float, float, SL_STATE>(g, u, d, SLParams{}, out, s);
 }
 
 } // namespace clh

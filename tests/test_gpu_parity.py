@@ -69,6 +69,19 @@ def test_interp_matches_oracle(shape):
     assert rel(out, oracle.interp(u, d)) < TOL_KERNEL
 
 
+@pytest.mark.parametrize("shape", [(64, 64, 64), (16, 32, 64), (32, 16, 128)])
+def test_interp_smooth_feet_matches_oracle(shape):
+    """Smooth displacements (up to 2.5 voxels): tiles stage their stencil
+    box in LDS; random displacements (previous test) overflow the box and
+    take the direct-gather path."""
+    u = f32(synth.random_field(shape, 21))
+    d = np.stack([2.5 * synth.smooth_random_field(shape, 22 + a, kmax=3.0) for a in range(3)])
+    d = f32(d)
+    r = reg(shape)
+    out = host(r.interp(dev(u), dev(d)))
+    assert rel(out, oracle.interp(u, d)) < TOL_KERNEL
+
+
 @pytest.mark.parametrize("shape", SHAPES)
 def test_fd_matches_oracle(shape):
     u = f32(synth.random_field(shape, 3))
