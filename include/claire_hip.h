@@ -196,6 +196,78 @@ const char *cl_kernel_class_name(int kclass);
 const char *cl_status_string(int status);
 const char *cl_last_error(const cl_ctx *ctx);
 
+/* ---------------------------------------------------------------------
+ * Learned warm start.  A 3D convolutional encoder-decoder (4 levels with
+ * 16/32/64/128 channels, two 3x3x3 convolutions with LeakyReLU per level,
+ * 2x average pooling down, nearest 2x upsampling and skip concatenation up,
+ * 1x1x1 FP32 head) maps (m0, m1) on an in_n^3 grid to a velocity on that
+ * grid.  Convolutions run in BF16 on the matrix cores with FP32
+ * accumulation; parameters are FP32 (Adam).  It only proposes an initial
+ * velocity: the Gauss-Newton solve above remains the judge of its error
+ * (a prediction is used only if it lowers the objective below J(0)).
+ * Same conventions as above: device pointers, caller-owned, one stream.
+ * ------------------------------------------------------------------- */
+#define CL_NET_OPTIONS_VERSION 1
+typedef struct cl_net cl_net;
+typedef struct {
+    int struct_version;       /* must be CL_NET_OPTIONS_VERSION */
+    int in_n;                 /* network grid: power of two in [32, 256] (default 128) */
+    int base_channels;        /* 16 (the only width built) */
+    float slope;              /* LeakyReLU slope (0.2) */
+    float lr, beta1, beta2, eps;   /* Adam (1e-3, 0.9, 0.999, 1e-8) */
+    unsigned long long seed;  /* parameter initialisation */
+    void *stream;             /* hipStream_t; NULL = default stream */
+} cl_net_options;
+
+void cl_net_default_options(cl_net_options *opt);
+int cl_net_create(cl_net **out, const cl_net_options *opt);
+void cl_net_destroy(cl_net *net);
+int cl_net_num_params(cl_net *net, size_t *n);
+/* copy the FP32 parameter vector to / from a device buffer of num_params values */
+int cl_net_get_params(cl_net *net, float *dst);
+int cl_net_set_params(cl_net *net, const float *src);
+/* v_out [3][in_n^3] FP32 = network(m0, m1), inputs FP32 [in_n^3] each */
+int cl_net_forward(cl_net *net, const float *m0, const float *m1, float *v_out);
+/* loss = (1/2) mean (v - label)^2 over the 3 in_n^3 values and its gradient
+ * w.r.t. every parameter (grad_out: num_params FP32, may be NULL); no update */
+int cl_net_loss_grad(cl_net *net, const float *m0, const float *m1, const float *v_label, float *grad_out,
+                     double *loss);
+/* one Adam step on the mean loss of `batch` samples stored back to back
+ * (m0, m1: batch x in_n^3; v_label: batch x 3 x in_n^3); *loss = mean loss */
+int cl_net_train_step(cl_net *net, const float *m0, const float *m1, const float *v_label, int batch, double *loss);
+const char *cl_net_last_error(const cl_net *net);
+
+/* Spectral resampling between two periodic grids (Section 5.3 prolongs
+ * velocities spectrally): Fourier modes with |k_d| < min(n_a, n_b)/2 are
+ * kept (coarse Nyquist planes dropped), all others are zero, so
+ * band-limited fields are reproduced.  in: ncomp fields on grid a, out:
+ * ncomp fields on grid b (FP32, device). */
+typedef struct cl_resampler cl_resampler;
+int cl_resampler_create(cl_resampler **out, int a1, int a2, int a3, int b1, int b2, int b3, void *stream);
+void cl_resampler_destroy(cl_resampler *r);
+int cl_resample(cl_resampler *r, const float *in, float *out, int ncomp);
+
+/* Warm start of a registration context from the network: restrict the
+ * context's images to the network grid, predict v there, prolong it to the
+ * context grid, and keep it as the context's velocity only if it lowers the
+ * objective below J(v = 0) (else v = 0).  *used = 1 if the prediction was
+ * kept.  The context and the network must share one stream. */
+int cl_warm_start(cl_ctx *ctx, cl_net *net, int *used, double *J_pred, double *J_zero);
+
+/* Single layers (parity tests).  Tensors channels-last [D][H][W][C] BF16;
+ * w FP32 [27][Ci][Co] with tap (tz * 3 + ty) * 3 + tx; zero padding.
+ *   cl_nn_conv3: transpose = 0: out[.., Co] = act(conv(in[.., Ci]) + b)
+ *                transpose = 1: out[.., Ci] = conv^T(in[.., Co]) (no bias/act)
+ *     out is FP32 if out_f32 else BF16; wpack: device scratch of
+ *     27 * Ci * Co * 2 bytes.  Ci, Co multiples of 16.
+ *   cl_nn_conv3_dw: gw[t][i][o] = sum_p x[p + t - 1][i] dz[p][o], gb[o] =
+ *     sum_p dz[p][o] (gb may be NULL); workspace from cl_nn_conv3_dw_workspace. */
+int cl_nn_conv3(const void *in, const float *w, const float *b, void *out, int out_f32, int D, int H, int W, int Ci,
+                int Co, int act, float slope, int transpose, void *wpack, void *stream);
+int cl_nn_conv3_dw_workspace(int D, int H, int W, int Ci, int Co, size_t *bytes);
+int cl_nn_conv3_dw(const void *x, const void *dz, float *gw, float *gb, void *workspace, int D, int H, int W, int Ci,
+                   int Co, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -19,6 +19,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "claire_oracle.c")
+_SRCS = [_SRC, os.path.join(_HERE, "conv_oracle.c")]
 _LIB = os.path.join(_HERE, "libclaire_oracle.so")
 _lib = None
 
@@ -32,7 +33,7 @@ def build(force=True):
         return _LIB
     tmp = _LIB + ".tmp"
     cmd = ["gcc", "-O2", "-fopenmp", "-std=c11", "-fPIC", "-shared", "-Wall",
-           "-o", tmp, _SRC, "-lm"]
+           "-o", tmp, *_SRCS, "-lm"]
     subprocess.check_call(cmd)
     os.replace(tmp, _LIB)
     return _LIB
@@ -41,7 +42,7 @@ def build(force=True):
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(f) for f in _SRCS):
             build()
         L = ctypes.CDLL(_LIB)
         i, d = ctypes.c_int, ctypes.c_double
@@ -70,6 +71,13 @@ def lib():
             "orc_pcg": (i, [vp, _dp, _dp, i, d, i, _ip]),
             "orc_solve": (i, [vp, i, i, d, _ip, _dp, _dp, _ip, _dp]),
             "orc_num_threads": (i, []),
+            "cnv_conv3": (None, [i, i, i, i, i, _dp, _dp, _dp, _dp]),
+            "cnv_conv3_t": (None, [i, i, i, i, i, _dp, _dp, _dp]),
+            "cnv_conv3_dw": (None, [i, i, i, i, i, _dp, _dp, _dp, _dp]),
+            "cnv_lrelu": (None, [ctypes.c_long, _dp, d, _dp]),
+            "cnv_pool2": (None, [i, i, i, i, _dp, _dp]),
+            "cnv_up2cat": (None, [i, i, i, i, i, _dp, _dp, _dp]),
+            "cnv_head": (None, [ctypes.c_long, i, i, _dp, _dp, _dp, _dp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -252,3 +260,69 @@ class Oracle:
         st = lib().orc_solve(self._h, int(max_outer), int(max_pcg), float(gtol), fp, fa,
                              _p(log), ctypes.byref(nout), ctypes.byref(gref))
         return st, log[: nout.value + 1], gref.value
+
+
+# ------------------------------------------------ network layers (FP64)
+# Tensors are channels-last numpy arrays of shape (D, H, W, C); conv weights
+# are (27, Ci, Co) with tap t = (tz * 3 + ty) * 3 + tx.
+
+def conv3(x, w, b=None):
+    x = _f64(x); w = _f64(w)
+    D, H, W, Ci = x.shape
+    Co = w.shape[2]
+    out = np.empty((D, H, W, Co))
+    bb = _f64(b) if b is not None else None
+    lib().cnv_conv3(D, H, W, Ci, Co, _p(x), _p(w), _p(bb) if bb is not None else None, _p(out))
+    return out
+
+
+def conv3_t(gout, w):
+    gout = _f64(gout); w = _f64(w)
+    D, H, W, Co = gout.shape
+    Ci = w.shape[1]
+    gin = np.empty((D, H, W, Ci))
+    lib().cnv_conv3_t(D, H, W, Ci, Co, _p(gout), _p(w), _p(gin))
+    return gin
+
+
+def conv3_dw(x, gout):
+    x = _f64(x); gout = _f64(gout)
+    D, H, W, Ci = x.shape
+    Co = gout.shape[3]
+    gw = np.empty((27, Ci, Co)); gb = np.empty(Co)
+    lib().cnv_conv3_dw(D, H, W, Ci, Co, _p(x), _p(gout), _p(gw), _p(gb))
+    return gw, gb
+
+
+def lrelu(x, s=0.2):
+    x = _f64(x)
+    y = np.empty_like(x)
+    lib().cnv_lrelu(x.size, _p(x), float(s), _p(y))
+    return y
+
+
+def pool2(x):
+    x = _f64(x)
+    D, H, W, C = x.shape
+    out = np.empty((D // 2, H // 2, W // 2, C))
+    lib().cnv_pool2(D, H, W, C, _p(x), _p(out))
+    return out
+
+
+def up2cat(a, b):
+    a = _f64(a); b = _f64(b)
+    D, H, W, Cb = b.shape
+    Ca = a.shape[3]
+    out = np.empty((D, H, W, Ca + Cb))
+    lib().cnv_up2cat(D, H, W, Ca, Cb, _p(a), _p(b), _p(out))
+    return out
+
+
+def head(x, w, b=None):
+    x = _f64(x); w = _f64(w)
+    Ci, Co = w.shape
+    n = x.size // Ci
+    out = np.empty(x.shape[:-1] + (Co,))
+    bb = _f64(b) if b is not None else None
+    lib().cnv_head(n, Ci, Co, _p(x), _p(w), _p(bb) if bb is not None else None, _p(out))
+    return out

@@ -64,6 +64,21 @@ class cl_solve_report(ctypes.Structure):
         return d
 
 
+class cl_net_options(ctypes.Structure):
+    _fields_ = [
+        ("struct_version", ctypes.c_int),
+        ("in_n", ctypes.c_int),
+        ("base_channels", ctypes.c_int),
+        ("slope", ctypes.c_float),
+        ("lr", ctypes.c_float),
+        ("beta1", ctypes.c_float),
+        ("beta2", ctypes.c_float),
+        ("eps", ctypes.c_float),
+        ("seed", ctypes.c_ulonglong),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
 _lib = None
 _vp = ctypes.c_void_p
 _i = ctypes.c_int
@@ -96,6 +111,23 @@ SIGNATURES = {
     "cl_profile_enable": (_i, [_vp, ctypes.c_uint]),
     "cl_profile_query": (_i, [_vp, _i, _dp, ctypes.POINTER(ctypes.c_longlong)]),
     "cl_kernel_class_name": (ctypes.c_char_p, [_i]),
+    "cl_net_default_options": (None, [ctypes.POINTER(cl_net_options)]),
+    "cl_net_create": (_i, [ctypes.POINTER(_vp), ctypes.POINTER(cl_net_options)]),
+    "cl_net_destroy": (None, [_vp]),
+    "cl_net_num_params": (_i, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
+    "cl_net_get_params": (_i, [_vp, _vp]),
+    "cl_net_set_params": (_i, [_vp, _vp]),
+    "cl_net_forward": (_i, [_vp, _vp, _vp, _vp]),
+    "cl_net_loss_grad": (_i, [_vp, _vp, _vp, _vp, _vp, _dp]),
+    "cl_net_train_step": (_i, [_vp, _vp, _vp, _vp, _i, _dp]),
+    "cl_net_last_error": (ctypes.c_char_p, [_vp]),
+    "cl_nn_conv3": (_i, [_vp, _vp, _vp, _vp, _i, _i, _i, _i, _i, _i, _i, ctypes.c_float, _i, _vp, _vp]),
+    "cl_nn_conv3_dw_workspace": (_i, [_i, _i, _i, _i, _i, ctypes.POINTER(ctypes.c_size_t)]),
+    "cl_nn_conv3_dw": (_i, [_vp, _vp, _vp, _vp, _vp, _i, _i, _i, _i, _i, _vp]),
+    "cl_resampler_create": (_i, [ctypes.POINTER(_vp), _i, _i, _i, _i, _i, _i, _vp]),
+    "cl_resampler_destroy": (None, [_vp]),
+    "cl_resample": (_i, [_vp, _vp, _vp, _i]),
+    "cl_warm_start": (_i, [_vp, _vp, ctypes.POINTER(_i), _dp, _dp]),
     "cl_status_string": (ctypes.c_char_p, [_i]),
     "cl_last_error": (ctypes.c_char_p, [_vp]),
 }
@@ -293,3 +325,142 @@ class Registration:
         ms, n = _d(), ctypes.c_longlong()
         self._chk(lib().cl_profile_query(self._h, int(kclass), ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+
+def _stream_ptr(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s, ctypes.c_void_p(s.cuda_stream)
+
+
+def _raise(st, msg):
+    if st < 0:
+        raise ClaireError(st, msg)
+    return st
+
+
+class Net:
+    """The learned warm-start network on an in_n^3 grid (device, torch stream)."""
+
+    def __init__(self, in_n=128, seed=1, lr=1e-3, stream=None):
+        import torch
+        self.torch = torch
+        o = cl_net_options()
+        lib().cl_net_default_options(ctypes.byref(o))
+        o.in_n = int(in_n)
+        o.seed = int(seed)
+        o.lr = float(lr)
+        self.stream, o.stream = _stream_ptr(stream)
+        h = ctypes.c_void_p()
+        _raise(lib().cl_net_create(ctypes.byref(h), ctypes.byref(o)), "cl_net_create")
+        self._h = h
+        self.n = int(in_n)
+        self.P = self.n ** 3
+        nn = ctypes.c_size_t()
+        lib().cl_net_num_params(h, ctypes.byref(nn))
+        self.num_params = nn.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().cl_net_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _err(self, st):
+        return _raise(st, lib().cl_net_last_error(self._h).decode())
+
+    def params(self):
+        out = self.torch.empty(self.num_params, dtype=self.torch.float32, device="cuda")
+        self._err(lib().cl_net_get_params(self._h, _ptr(out)))
+        return out
+
+    def set_params(self, p):
+        self._err(lib().cl_net_set_params(self._h, _ptr(p.contiguous())))
+
+    def forward(self, m0, m1):
+        out = self.torch.empty((3, self.n, self.n, self.n), dtype=self.torch.float32, device="cuda")
+        self._err(lib().cl_net_forward(self._h, _ptr(m0), _ptr(m1), _ptr(out)))
+        return out
+
+    def loss_grad(self, m0, m1, label):
+        g = self.torch.empty(self.num_params, dtype=self.torch.float32, device="cuda")
+        L = _d()
+        self._err(lib().cl_net_loss_grad(self._h, _ptr(m0), _ptr(m1), _ptr(label), _ptr(g), ctypes.byref(L)))
+        return L.value, g
+
+    def train_step(self, m0, m1, label, batch=1):
+        L = _d()
+        self._err(lib().cl_net_train_step(self._h, _ptr(m0), _ptr(m1), _ptr(label), int(batch), ctypes.byref(L)))
+        return L.value
+
+
+class Resampler:
+    """Spectral resampling from grid a to grid b."""
+
+    def __init__(self, a, b, stream=None):
+        self.a, self.b = tuple(a), tuple(b)
+        self.stream, sp = _stream_ptr(stream)
+        h = ctypes.c_void_p()
+        _raise(lib().cl_resampler_create(ctypes.byref(h), *self.a, *self.b, sp), "cl_resampler_create")
+        self._h = h
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib().cl_resampler_destroy(self._h)
+            self._h = None
+
+    def __call__(self, x):
+        import torch
+        ncomp = x.numel() // (self.a[0] * self.a[1] * self.a[2])
+        out = torch.empty((ncomp,) + self.b if ncomp > 1 else self.b, dtype=torch.float32, device="cuda")
+        _raise(lib().cl_resample(self._h, _ptr(x.contiguous()), _ptr(out), ncomp), "cl_resample")
+        return out
+
+
+def nn_conv3(x_bf16, w, b, Co=None, act=1, slope=0.2, transpose=False, out_f32=True):
+    """Single 3x3x3 convolution layer on a channels-last BF16 tensor.  w is
+    the FP32 weight [27][Ci][Co] of the forward layer; transpose=True
+    applies its transpose (input Co channels, output Ci channels)."""
+    import torch
+    D, H, W, Cin = x_bf16.shape
+    Ci, Cw = int(w.shape[1]), int(w.shape[2])
+    if Cin != (Cw if transpose else Ci):
+        raise ValueError("input channels do not match the weight")
+    Cout = Ci if transpose else Cw
+    out = torch.empty((D, H, W, Cout), dtype=torch.float32 if out_f32 else torch.bfloat16, device="cuda")
+    wpack = torch.empty(27 * Ci * Cw * 2, dtype=torch.uint8, device="cuda")
+    st = lib().cl_nn_conv3(_ptr(x_bf16), _ptr(w), _ptr(b) if b is not None else None, _ptr(out), int(out_f32),
+                           D, H, W, Ci, Cw, int(act), float(slope), int(transpose), _ptr(wpack),
+                           ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    _raise(st, "cl_nn_conv3")
+    return out
+
+
+def nn_conv3_dw(x_bf16, dz_bf16):
+    import torch
+    D, H, W, Ci = x_bf16.shape
+    Co = dz_bf16.shape[3]
+    nb = ctypes.c_size_t()
+    lib().cl_nn_conv3_dw_workspace(D, H, W, Ci, Co, ctypes.byref(nb))
+    ws = torch.empty(max(nb.value, 4), dtype=torch.uint8, device="cuda")
+    gw = torch.empty((27, Ci, Co), dtype=torch.float32, device="cuda")
+    gb = torch.empty(Co, dtype=torch.float32, device="cuda")
+    st = lib().cl_nn_conv3_dw(_ptr(x_bf16), _ptr(dz_bf16), _ptr(gw), _ptr(gb), _ptr(ws), D, H, W, Ci, Co,
+                              ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    _raise(st, "cl_nn_conv3_dw")
+    return gw, gb
+
+
+def warm_start(reg, net):
+    """Predict the initial velocity of `reg` with `net`; keeps it only if it
+    lowers the objective below J(0).  Returns (used, J_pred, J_zero)."""
+    used = ctypes.c_int()
+    Jp, J0 = _d(), _d()
+    st = lib().cl_warm_start(reg._h, net._h, ctypes.byref(used), ctypes.byref(Jp), ctypes.byref(J0))
+    reg._chk(st)
+    return bool(used.value), Jp.value, J0.value

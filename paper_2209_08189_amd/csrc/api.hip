@@ -475,7 +475,7 @@ size_t workspace_bytes(int n1, int n2, int n3, const cl_options &o)
     b += 2 * N * sizeof(float);              // c, div v
     b += 12 * 3 * N * sizeof(float);         // v, vtrial, df, db, g, Av, tmp3, PCG x r z p Hp
     b += fft_spec_bytes(n1, n2, n3, 3);
-    b += 3 * 1024 * sizeof(float2) + 4096 * sizeof(double) + 256;
+    b += 4 * 1025 * sizeof(float2) + 4096 * sizeof(double) + 256;
     return b;
 }
 
@@ -503,6 +503,27 @@ int check_options(const cl_options *o, cl_ctx *ctx)
     if (!ctx) return CL_ERR_ARG
 
 } // namespace
+
+namespace clh {
+
+void ctx_dims(const cl_ctx *ctx, int *n1, int *n2, int *n3)
+{
+    *n1 = ctx->g.n1;
+    *n2 = ctx->g.n2;
+    *n3 = ctx->g.n3;
+}
+
+hipStream_t ctx_stream(const cl_ctx *ctx) { return ctx->s; }
+
+bool ctx_has_images(const cl_ctx *ctx) { return ctx->images; }
+
+void ctx_images_f32(cl_ctx *ctx, float *m0, float *m1)
+{
+    launch_to_f32(ctx->dts, ctx->m0, m0, ctx->N, ctx->s);
+    launch_to_f32(ctx->dts, ctx->m1, m1, ctx->N, ctx->s);
+}
+
+} // namespace clh
 
 extern "C" {
 
@@ -586,17 +607,11 @@ int cl_create(cl_ctx **out, int n1, int n2, int n3, const cl_options *opt)
         ctx->dscal = (double *)alloc(sizeof(double) * 4);
         if (hipHostMalloc((void **)&ctx->hscal, sizeof(double) * 4, hipHostMallocDefault) != hipSuccess)
             throw Fail{CL_ERR_OOM};
-        FFTPlan &P = ctx->fft;
-        P.n1 = n1; P.n2 = n2; P.n3 = n3; P.nh = n3 / 2 + 1; P.ncomp_max = 3;
-        P.spec = (float2 *)alloc(fft_spec_bytes(n1, n2, n3, 3));
-        std::vector<float2> tw;
-        float2 **tabs[3] = {&P.tw1, &P.tw2, &P.tw3};
-        const int ns[3] = {n1, n2, n3};
-        for (int a = 0; a < 3; ++a) {
-            tw.assign(ns[a] / 2, make_float2(0.f, 0.f));
-            fft_make_twiddles(tw.data(), ns[a]);
-            *tabs[a] = (float2 *)alloc(tw.size() * sizeof(float2));
-            HIPCHK(hipMemcpy(*tabs[a], tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice));
+        try {
+            fft_plan_init(ctx->fft, n1, n2, n3, 3, alloc);
+        } catch (hipError_t e) {
+            ctx->err = std::string("FFT tables: ") + hipGetErrorString(e);
+            throw Fail{CL_ERR_HIP};
         }
         // a defined initial velocity: v = 0
         HIPCHK(hipMemsetAsync(ctx->v, 0, 3 * N * sizeof(float), ctx->s));

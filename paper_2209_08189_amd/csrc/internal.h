@@ -154,7 +154,9 @@ void launch_fill_f32(float *dst, float v, size_t n, hipStream_t s);
 // FFT (k_fft.hip)
 struct FFTPlan {
     int n1, n2, n3, nh;          // nh = n3 / 2 + 1 complex values per x3 row
-    float2 *tw1, *tw2, *tw3;     // exp(-2 pi i t / n_d), t < n_d / 2
+    float2 *tw1, *tw2;           // exp(-2 pi i t / n_d), t < n_d
+    float2 *twM;                 // exp(-2 pi i t / M), t < M = n3 / 2
+    float2 *twS;                 // exp(-2 pi i k / n3), k <= M (real-FFT split)
     float2 *spec;                // complex work, ncomp_max * n1 * n2 * nh
     int ncomp_max;
 };
@@ -162,6 +164,36 @@ size_t fft_spec_bytes(int n1, int n2, int n3, int ncomp);
 // out_c = F^-1[ mult(k) F[in_c] ] (+ add_c), c < ncomp; kind as cl_spectral
 void spectral_apply(const FFTPlan &P, int kind, float beta, int ncomp, const float *in, float *out,
                     const float *add, hipStream_t s);
-void fft_make_twiddles(float2 *host, int n);
+// out (grid B) = spectral resampling of in (grid A): modes with |k_d| <
+// min(n_a, n_b)/2 kept, others zero, scaled so band-limited fields are
+// reproduced; both plans' spectra are used as work space
+void spectral_resample(const FFTPlan &A, const FFTPlan &B, int ncomp, const float *in, float *out, hipStream_t s);
+// host[t] = exp(-2 pi i t / n), t < count, computed in FP64
+void fft_make_twiddles(float2 *host, int n, int count);
+
+// read-only views of a registration context for the warm-start code
+void ctx_dims(const cl_ctx *ctx, int *n1, int *n2, int *n3);
+hipStream_t ctx_stream(const cl_ctx *ctx);
+// images of the context as FP32 into m0 / m1 (device, N values each)
+void ctx_images_f32(cl_ctx *ctx, float *m0, float *m1);
+bool ctx_has_images(const cl_ctx *ctx);
+
+// FFT plan owning its twiddle tables and spectrum (allocated with alloc)
+template <typename Alloc> inline void fft_plan_init(FFTPlan &P, int n1, int n2, int n3, int ncomp, Alloc &&alloc)
+{
+    P.n1 = n1; P.n2 = n2; P.n3 = n3; P.nh = n3 / 2 + 1; P.ncomp_max = ncomp;
+    P.spec = (float2 *)alloc(fft_spec_bytes(n1, n2, n3, ncomp));
+    float2 **tabs[4] = {&P.tw1, &P.tw2, &P.twM, &P.twS};
+    const int tn[4] = {n1, n2, n3 / 2, n3};
+    const int tc[4] = {n1, n2, n3 / 2, n3 / 2 + 1};
+    for (int a = 0; a < 4; ++a) {
+        float2 *host = new float2[tc[a]];
+        fft_make_twiddles(host, tn[a], tc[a]);
+        *tabs[a] = (float2 *)alloc(tc[a] * sizeof(float2));
+        const hipError_t e = hipMemcpy(*tabs[a], host, tc[a] * sizeof(float2), hipMemcpyHostToDevice);
+        delete[] host;
+        if (e != hipSuccess) throw e;
+    }
+}
 
 } // namespace clh

@@ -3,18 +3,22 @@
 // a vendor 3D FFT on one GPU, here it is written from scratch).
 //
 // Layout: real fields [n1][n2][n3]; half spectrum [n1][n2][nh], nh = n3/2+1.
-// One spectral apply is five LDS-staged passes, each a single read and a
-// single write of the field:
-//   x3 R2C    rows of n3 reals packed as n3/2 complex, radix-2 DIF in LDS,
-//             split into the half spectrum of the real row;
-//   x2 C2C    columns of a fixed-x1 plane, DIF, natural-order store;
-//   x1 fused  columns along x1: DIF forward (bit-reversed order in LDS),
-//             Hadamard multiply by the symbol, DIT inverse (natural order)
-//             -- no permutation pass is needed in between;
+// One spectral apply is five passes, each a single read and a single write
+// of the field:
+//   x3 R2C    rows of n3 reals packed as M = n3/2 complex, complex FFT of
+//             length M, split into the half spectrum of the real row;
+//   x2 C2C    columns of a fixed-x1 plane;
+//   x1 fused  columns along x1: forward FFT, Hadamard multiply by the
+//             symbol, inverse FFT, all in one LDS tile;
 //   x2 C2C    inverse;
-//   x3 C2R    Hermitian merge, inverse, unpack to reals, optional fused add.
-// Twiddles e^{-2 pi i t / n} come from tables computed on the host in FP64
-// and are staged in LDS; data tiles use at most 32 KB of LDS.
+//   x3 C2R    Hermitian merge, inverse FFT of length M, unpack to reals,
+//             optional fused add.
+// Inside a pass a workgroup owns a tile of nl lines x L points (nl L = 4096
+// complex, 32 KB): coalesced batched loads into LDS, then Stockham stages of
+// radix 16 (and one of radix 2/4/8 for the remainder) with every group's R
+// values in registers, twiddles from FP64-computed tables staged in LDS, and
+// a coalesced store.  The LDS tile is stored as [q][l] with pitch nl + 1 so
+// that both row-wise and column-wise accesses are conflict-free.
 #include "internal.h"
 
 #include <cmath>
@@ -24,7 +28,8 @@ namespace clh {
 namespace {
 
 constexpr int TPB = 256;
-constexpr int LDS_C = 4096;   // complex values per data tile
+constexpr int TILE = 4096;   // complex values per LDS tile
+constexpr int EPT = TILE / TPB;
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b)
 {
@@ -34,183 +39,336 @@ __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
 
-__device__ __forceinline__ int brev(int q, int logL) { return logL ? (int)(__brev((unsigned)q) >> (32 - logL)) : 0; }
-
-// In-place radix-2 FFT of nl lines of length L = 2^logL in LDS; element
-// (line l, index q) at buf[l * ls + q * es].  tw[t * tws] = e^{-2 pi i t/L}.
-// DIF: natural order in, bit-reversed out.  DIT: bit-reversed in, natural
-// out.  inv conjugates the twiddles.  line_fast maps consecutive threads to
-// consecutive lines (column tiles) instead of consecutive butterflies.
-template <bool DIF>
-__device__ void lds_fft(float2 *buf, int logL, int lognl, int ls, int es, const float2 *tw, int tws, bool inv,
-                        bool line_fast)
+// cos / sin of 2 pi k / 16, k = 0..7 (folded at compile time)
+__device__ __forceinline__ constexpr float c16(int k)
 {
-    const int L = 1 << logL;
-    const int nb = (1 << lognl) * (L >> 1);
-    const int nlm = (1 << lognl) - 1, hm = (L >> 1) - 1;
-    for (int s = 0; s < logL; ++s) {
-        const int loghalf = DIF ? (logL - 1 - s) : s;
-        const int half = 1 << loghalf;
-        const int tstep = (L >> (loghalf + 1)) * tws;
-        for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-            int l, t;
-            if (line_fast) { l = b & nlm; t = b >> lognl; }
-            else { t = b & hm; l = b >> (logL - 1); }
-            const int grp = t >> loghalf, pos = t & (half - 1);
-            const int ia = (grp << (loghalf + 1)) + pos, ib = ia + half;
-            float2 w = tw[pos * tstep];
-            if (inv) w.y = -w.y;
-            float2 *pa = buf + l * ls + ia * es, *pb = buf + l * ls + ib * es;
-            const float2 x = *pa, y = *pb;
-            if (DIF) {
-                *pa = cadd(x, y);
-                *pb = cmul(csub(x, y), w);
-            } else {
-                const float2 t2 = cmul(y, w);
-                *pa = cadd(x, t2);
-                *pb = csub(x, t2);
+    return k == 0 ? 1.0f : k == 1 ? 0.92387953251128674f : k == 2 ? 0.70710678118654752f
+         : k == 3 ? 0.38268343236508977f : k == 4 ? 0.0f : k == 5 ? -0.38268343236508977f
+         : k == 6 ? -0.70710678118654752f : -0.92387953251128674f;
+}
+__device__ __forceinline__ constexpr float s16(int k)
+{
+    return k == 0 ? 0.0f : k == 1 ? 0.38268343236508977f : k == 2 ? 0.70710678118654752f
+         : k == 3 ? 0.92387953251128674f : k == 4 ? 1.0f : k == 5 ? 0.92387953251128674f
+         : k == 6 ? 0.70710678118654752f : 0.38268343236508977f;
+}
+
+template <int R> __device__ constexpr int brev_c(int i)
+{
+    int r = 0;
+    for (int b = 1; b < R; b <<= 1) {
+        r <<= 1;
+        if (i & b) r |= 1;
+    }
+    return r;
+}
+
+// y * e^{-+2 pi i k / 16}; k is a compile-time constant after unrolling
+template <bool INV> __device__ __forceinline__ float2 rot16(float2 y, int k)
+{
+    if (k == 0) return y;
+    if (k == 4) return INV ? make_float2(-y.y, y.x) : make_float2(y.y, -y.x);
+    const float c = c16(k), s = INV ? s16(k) : -s16(k);
+    return make_float2(y.x * c - y.y * s, y.x * s + y.y * c);
+}
+
+// In-register DFT of length R (2, 4, 8, 16), natural order in and out:
+// radix-2 DIT after a compile-time bit-reversal (register renaming only).
+template <int R, bool INV> __device__ __forceinline__ void dft_reg(float2 *v)
+{
+    float2 a[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) a[i] = v[brev_c<R>(i)];
+#pragma unroll
+    for (int len = 2; len <= R; len <<= 1) {
+#pragma unroll
+        for (int s = 0; s < R; s += len) {
+#pragma unroll
+            for (int k = 0; k < len / 2; ++k) {
+                const float2 x = a[s + k];
+                const float2 y = rot16<INV>(a[s + k + len / 2], k * (16 / len));
+                a[s + k] = cadd(x, y);
+                a[s + k + len / 2] = csub(x, y);
             }
         }
-        __syncthreads();
     }
+#pragma unroll
+    for (int i = 0; i < R; ++i) v[i] = a[i];
 }
 
-__device__ __forceinline__ void load_tw(float2 *dst, const float2 *__restrict__ src, int n)
+// One Stockham radix-R stage in place on the LDS tile (element (l, q) at
+// q * P + l), for nl = 2^lognl lines of length L = 2^logL; Ns = 2^logNs is
+// the product of the radices of the earlier stages.  tw[t] = e^{-2 pi i t / L}
+// (t < L).  Every thread reads all its groups, the workgroup synchronises,
+// then the results are written back, so the stage is safe in place.
+template <int R, bool INV>
+__device__ __forceinline__ void stage(float2 *lds, int P, int lognl, int logL, int logNs, const float2 *tw)
 {
-    for (int t = threadIdx.x; t < n; t += blockDim.x) dst[t] = src[t];
-}
-
-// --- x3 forward: real rows -> half spectrum.  R rows per workgroup.
-__global__ __launch_bounds__(TPB) void k_fft_x3_r2c(const float *__restrict__ in, float2 *__restrict__ spec,
-                                                    const float2 *__restrict__ tw3, int n3, int logM, int logR,
-                                                    int nrows, size_t in_cstride, size_t spec_cstride)
-{
-    extern __shared__ float2 sm[];
-    const int M = 1 << logM, R = 1 << logR, nh = M + 1;
-    float2 *tw = sm;                  // M entries: e^{-2 pi i t / n3}
-    float2 *buf = sm + M;             // R * M
-    const int comp = blockIdx.y;
-    const float2 *src = (const float2 *)(in + comp * in_cstride);
-    float2 *dst = spec + comp * spec_cstride;
-    const int row0 = blockIdx.x * R;
-    load_tw(tw, tw3, M);
-    for (int e = threadIdx.x; e < R * M; e += blockDim.x) {
-        const int r = e >> logM, q = e & (M - 1);
-        buf[e] = row0 + r < nrows ? src[(size_t)(row0 + r) * M + q] : make_float2(0.f, 0.f);
+    constexpr int LOGR = R == 2 ? 1 : R == 4 ? 2 : R == 8 ? 3 : 4;
+    constexpr int G = EPT / R;          // groups per thread (tile holds 4096 values)
+    const int nl = 1 << lognl, L = 1 << logL, Ns = 1 << logNs;
+    const int ngroups = nl << (logL - LOGR);
+    const int LR = L >> LOGR;
+    float2 v[G][R];
+#pragma unroll
+    for (int gq = 0; gq < G; ++gq) {
+        const int gi = gq * TPB + threadIdx.x;
+        if (gi < ngroups) {
+            const int l = gi & (nl - 1), j = gi >> lognl;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[gq][r] = lds[(j + r * LR) * P + l];
+        }
     }
     __syncthreads();
-    lds_fft<true>(buf, logM, logR, M, 1, tw, 2, false, false);
-    // split: X[k] = E[k] + w^k O[k], E = (Z[k] + conj Z[M-k]) / 2, O = -i (Z[k] - conj Z[M-k]) / 2
-    for (int e = threadIdx.x; e < R * nh; e += blockDim.x) {
+#pragma unroll
+    for (int gq = 0; gq < G; ++gq) {
+        const int gi = gq * TPB + threadIdx.x;
+        if (gi < ngroups) {
+            const int l = gi & (nl - 1), j = gi >> lognl;
+            const int jm = j & (Ns - 1);
+            if (logNs > 0) {
+                const int tsh = logL - logNs - LOGR;
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    float2 w = tw[(r * jm) << tsh];
+                    if (INV) w.y = -w.y;
+                    v[gq][r] = cmul(v[gq][r], w);
+                }
+            }
+            dft_reg<R, INV>(v[gq]);
+            const int base = ((j >> logNs) << (logNs + LOGR)) + jm;
+#pragma unroll
+            for (int r = 0; r < R; ++r) lds[(base + r * Ns) * P + l] = v[gq][r];
+        }
+    }
+    __syncthreads();
+}
+
+// Full FFT of the tile's lines: radix-16 stages, then one radix-2/4/8 stage.
+template <bool INV> __device__ void fft_lines(float2 *lds, int P, int lognl, int logL, const float2 *tw)
+{
+    int logNs = 0;
+    while (logL - logNs >= 4) {
+        stage<16, INV>(lds, P, lognl, logL, logNs, tw);
+        logNs += 4;
+    }
+    const int rem = logL - logNs;
+    if (rem == 3) stage<8, INV>(lds, P, lognl, logL, logNs, tw);
+    else if (rem == 2) stage<4, INV>(lds, P, lognl, logL, logNs, tw);
+    else if (rem == 1) stage<2, INV>(lds, P, lognl, logL, logNs, tw);
+}
+
+__device__ __forceinline__ void load_table(float2 *dst, const float2 *__restrict__ src, int n)
+{
+    for (int t = threadIdx.x; t < n; t += TPB) dst[t] = src[t];
+}
+
+// --- x3 forward: real rows -> half spectrum.  nl = 2^lognl rows per tile.
+__global__ __launch_bounds__(TPB) void k_fft_x3_r2c(const float *__restrict__ in, float2 *__restrict__ spec,
+                                                    const float2 *__restrict__ twM, const float2 *__restrict__ tw3,
+                                                    int logM, int lognl, int nrows, size_t in_cs, size_t spec_cs)
+{
+    extern __shared__ float2 sm[];
+    const int M = 1 << logM, nl = 1 << lognl, P = nl + 1, nh = M + 1;
+    float2 *twm = sm;                 // M: e^{-2 pi i t / M}
+    float2 *tws = sm + M;             // M + 1: e^{-2 pi i k / n3}, k <= M
+    float2 *lds = tws + M + 1;        // M * P
+    const int comp = blockIdx.y;
+    const float2 *src = (const float2 *)(in + comp * in_cs);
+    float2 *dst = spec + comp * spec_cs;
+    const int row0 = blockIdx.x * nl;
+    load_table(twm, twM, M);
+    load_table(tws, tw3, M + 1);
+    const int tot = nl << logM;
+    float2 buf[EPT];
+#pragma unroll
+    for (int it = 0; it < EPT; ++it) {
+        const int e = it * TPB + threadIdx.x;
+        if (e < tot) buf[it] = src[(size_t)row0 * M + e];
+    }
+#pragma unroll
+    for (int it = 0; it < EPT; ++it) {
+        const int e = it * TPB + threadIdx.x;
+        if (e < tot) lds[(e & (M - 1)) * P + (e >> logM)] = buf[it];
+    }
+    __syncthreads();
+    fft_lines<false>(lds, P, lognl, logM, twm);
+    // X[k] = E[k] + w^k O[k], E = (Z[k] + conj Z[M-k]) / 2, O = -i (Z[k] - conj Z[M-k]) / 2
+    const int totk = nl * nh;
+    for (int e = threadIdx.x; e < totk; e += TPB) {
         const int r = e / nh, k = e - r * nh;
-        if (row0 + r >= nrows) continue;
-        const float2 *z = buf + r * M;
-        const float2 zk = z[brev(k & (M - 1), logM)];
-        const float2 zc = cconj(z[brev((M - k) & (M - 1), logM)]);
+        const float2 zk = lds[(k & (M - 1)) * P + r];
+        const float2 zc = cconj(lds[((M - k) & (M - 1)) * P + r]);
         const float2 E = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y + zc.y));
         const float2 O = make_float2(0.5f * (zk.y - zc.y), -0.5f * (zk.x - zc.x));
-        const float2 w = k < M ? tw[k] : make_float2(-1.f, 0.f);
-        dst[(size_t)(row0 + r) * nh + k] = cadd(E, cmul(w, O));
+        dst[(size_t)row0 * nh + e] = cadd(E, cmul(tws[k], O));
     }
 }
 
 // --- x3 inverse: half spectrum -> real rows (unnormalised), optional add.
 __global__ __launch_bounds__(TPB) void k_fft_x3_c2r(const float2 *__restrict__ spec, float *__restrict__ out,
-                                                    const float *__restrict__ add, const float2 *__restrict__ tw3,
-                                                    int n3, int logM, int logR, int nrows, size_t out_cstride,
-                                                    size_t spec_cstride)
+                                                    const float *__restrict__ add, const float2 *__restrict__ twM,
+                                                    const float2 *__restrict__ tw3, int logM, int lognl, int nrows,
+                                                    size_t out_cs, size_t spec_cs)
 {
     extern __shared__ float2 sm[];
-    const int M = 1 << logM, R = 1 << logR, nh = M + 1;
-    float2 *tw = sm;
-    float2 *buf = sm + M;
+    const int M = 1 << logM, nl = 1 << lognl, P = nl + 1, nh = M + 1;
+    float2 *twm = sm;
+    float2 *tws = sm + M;
+    float2 *lds = tws + M + 1;
     const int comp = blockIdx.y;
-    const float2 *src = spec + comp * spec_cstride;
-    float2 *dst = (float2 *)(out + comp * out_cstride);
-    const float2 *ad = add ? (const float2 *)(add + comp * out_cstride) : nullptr;
-    const int row0 = blockIdx.x * R;
-    load_tw(tw, tw3, M);
-    __syncthreads();
-    // Z[k] = (X[k] + conj X[M-k]) + i e^{+2 pi i k / n3} (X[k] - conj X[M-k]),  k < M
-    for (int e = threadIdx.x; e < R * M; e += blockDim.x) {
-        const int r = e >> logM, k = e & (M - 1);
-        float2 Z = make_float2(0.f, 0.f);
-        if (row0 + r < nrows) {
-            const float2 *X = src + (size_t)(row0 + r) * nh;
-            const float2 a = X[k], b = cconj(X[M - k]);
-            const float2 sum = cadd(a, b), dif = csub(a, b);
-            const float2 wd = cmul(cconj(tw[k]), dif);
-            Z = make_float2(sum.x - wd.y, sum.y + wd.x);
+    const float2 *src = spec + comp * spec_cs;
+    float2 *dst = (float2 *)(out + comp * out_cs);
+    const float2 *ad = add ? (const float2 *)(add + comp * out_cs) : nullptr;
+    const int row0 = blockIdx.x * nl;
+    load_table(twm, twM, M);
+    load_table(tws, tw3, M + 1);
+    // stage the half-spectrum rows (nh values each) at lds[k * P + r], k <= M
+    // (row M of the tile doubles as the Nyquist slot; the tile has M + 1 rows).
+    // nl * nh = TILE + nl <= TILE + TILE / 8 values (M >= 8), i.e. at most
+    // EPT + 2 per thread.
+    const int totk = nl * nh;
+    {
+        constexpr int NB = EPT + EPT / 8;
+        float2 buf[NB];
+#pragma unroll
+        for (int it = 0; it < NB; ++it) {
+            const int e = it * TPB + threadIdx.x;
+            if (e < totk) buf[it] = src[(size_t)row0 * nh + e];
         }
-        buf[e] = Z;
+#pragma unroll
+        for (int it = 0; it < NB; ++it) {
+            const int e = it * TPB + threadIdx.x;
+            if (e < totk) {
+                const int r = e / nh, k = e - r * nh;
+                lds[k * P + r] = buf[it];
+            }
+        }
     }
     __syncthreads();
-    lds_fft<true>(buf, logM, logR, M, 1, tw, 2, true, false);
-    for (int e = threadIdx.x; e < R * M; e += blockDim.x) {
-        const int r = e >> logM, n = e & (M - 1);
-        if (row0 + r >= nrows) continue;
-        float2 z = buf[r * M + brev(n, logM)];
-        const size_t o = (size_t)(row0 + r) * M + n;
-        if (ad) {
-            const float2 a = ad[o];
-            z.x += a.x;
-            z.y += a.y;
+    // Z[k] = (X[k] + conj X[M-k]) + i e^{+2 pi i k / n3} (X[k] - conj X[M-k]),  k < M
+    float2 z[EPT];
+    const int tot = nl << logM;
+#pragma unroll
+    for (int it = 0; it < EPT; ++it) {
+        const int e = it * TPB + threadIdx.x;
+        if (e < tot) {
+            const int r = e & (nl - 1), k = e >> lognl;
+            const float2 a = lds[k * P + r], b = cconj(lds[(M - k) * P + r]);
+            const float2 sum = cadd(a, b), dif = csub(a, b);
+            const float2 wd = cmul(cconj(tws[k]), dif);
+            z[it] = make_float2(sum.x - wd.y, sum.y + wd.x);
         }
-        dst[o] = z;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < EPT; ++it) {
+        const int e = it * TPB + threadIdx.x;
+        if (e < tot) lds[(e >> lognl) * P + (e & (nl - 1))] = z[it];
+    }
+    __syncthreads();
+    fft_lines<true>(lds, P, lognl, logM, twm);
+#pragma unroll
+    for (int it = 0; it < EPT; ++it) {
+        const int e = it * TPB + threadIdx.x;
+        if (e < tot) {
+            const int r = e >> logM, n = e & (M - 1);
+            float2 v = lds[n * P + r];
+            const size_t o = (size_t)row0 * M + e;
+            if (ad) {
+                const float2 a = ad[o];
+                v.x += a.x;
+                v.y += a.y;
+            }
+            dst[o] = v;
+        }
+    }
+}
+
+// --- column tile load/store for the x2 and x1 passes: element (l, q) of
+// the tile is base[q * rs + l], l < cw valid columns.
+__device__ __forceinline__ void load_cols(float2 *lds, const float2 *__restrict__ base, size_t rs, int logC, int logL,
+                                          int cw, int P)
+{
+    const int C = 1 << logC, tot = C << logL;
+    float2 buf[EPT];
+#pragma unroll
+    for (int it = 0; it < EPT; ++it) {
+        const int e = it * TPB + threadIdx.x;
+        const int l = e & (C - 1), q = e >> logC;
+        if (e < tot) buf[it] = l < cw ? base[q * rs + l] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int it = 0; it < EPT; ++it) {
+        const int e = it * TPB + threadIdx.x;
+        if (e < tot) lds[(e >> logC) * P + (e & (C - 1))] = buf[it];
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ void store_cols(const float2 *lds, float2 *__restrict__ base, size_t rs, int logC, int logL,
+                                           int cw, int P)
+{
+    const int C = 1 << logC, tot = C << logL;
+#pragma unroll
+    for (int it = 0; it < EPT; ++it) {
+        const int e = it * TPB + threadIdx.x;
+        const int l = e & (C - 1), q = e >> logC;
+        if (e < tot && l < cw) base[q * rs + l] = lds[q * P + l];
     }
 }
 
 // --- x2 C2C in place on the half spectrum: plane i1 = blockIdx.y, columns
-// [c0, c0 + C) of the nh per row.  Natural-order result.
-__global__ __launch_bounds__(TPB) void k_fft_x2(float2 *__restrict__ spec, const float2 *__restrict__ tw2, int n2,
-                                                int logn2, int nh, int logC, bool inv, size_t spec_cstride)
+// [c0, c0 + C) of the nh per row.
+__global__ __launch_bounds__(TPB) void k_fft_x2(float2 *__restrict__ spec, const float2 *__restrict__ tw2, int logn2,
+                                                int n2, int nh, int logC, int inv, size_t spec_cs)
 {
     extern __shared__ float2 sm[];
-    const int C = 1 << logC, half = n2 >> 1;
+    const int C = 1 << logC, P = C + 1;
     float2 *tw = sm;
-    float2 *buf = sm + half;
+    float2 *lds = sm + n2;
     const int comp = blockIdx.z, i1 = blockIdx.y, c0 = blockIdx.x * C;
     const int cw = min(C, nh - c0);
-    float2 *plane = spec + comp * spec_cstride + (size_t)i1 * n2 * nh;
-    load_tw(tw, tw2, half);
-    for (int e = threadIdx.x; e < n2 * C; e += blockDim.x) {
-        const int q = e >> logC, l = e & (C - 1);
-        buf[e] = l < cw ? plane[(size_t)q * nh + c0 + l] : make_float2(0.f, 0.f);
-    }
-    __syncthreads();
-    lds_fft<true>(buf, logn2, logC, 1, C, tw, 1, inv, true);
-    for (int e = threadIdx.x; e < n2 * C; e += blockDim.x) {
-        const int q = e >> logC, l = e & (C - 1);
-        if (l < cw) plane[(size_t)q * nh + c0 + l] = buf[(brev(q, logn2) << logC) + l];
-    }
+    float2 *base = spec + comp * spec_cs + (size_t)i1 * n2 * nh + c0;
+    load_table(tw, tw2, n2);
+    load_cols(lds, base, nh, logC, logn2, cw, P);
+    if (inv) fft_lines<true>(lds, P, logC, logn2, tw);
+    else fft_lines<false>(lds, P, logC, logn2, tw);
+    store_cols(lds, base, nh, logC, logn2, cw, P);
 }
 
-// --- x1 fused: forward DIF along x1, symbol multiply, inverse DIT.
+// --- x1 fused: forward FFT along x1, symbol multiply, inverse FFT.
 // plane i2 = blockIdx.y, columns [c0, c0 + C).
+// mode 0: forward, multiply, inverse; 1: forward only; 2: inverse only
 __global__ __launch_bounds__(TPB) void k_fft_x1_mult(float2 *__restrict__ spec, const float2 *__restrict__ tw1,
-                                                     int n1, int logn1, int n2, int nh, int logC, int kind,
-                                                     float beta, float scale, size_t spec_cstride)
+                                                     int logn1, int n1, int n2, int nh, int logC, int kind, float beta,
+                                                     float scale, size_t spec_cs, int mode)
 {
     extern __shared__ float2 sm[];
-    const int C = 1 << logC, half = n1 >> 1;
+    const int C = 1 << logC, P = C + 1;
     float2 *tw = sm;
-    float2 *buf = sm + half;
+    float2 *lds = sm + n1;
     const int comp = blockIdx.z, i2 = blockIdx.y, c0 = blockIdx.x * C;
     const int cw = min(C, nh - c0);
-    float2 *base = spec + comp * spec_cstride + (size_t)i2 * nh;
+    float2 *base = spec + comp * spec_cs + (size_t)i2 * nh + c0;
     const size_t rs = (size_t)n2 * nh;
-    load_tw(tw, tw1, half);
-    for (int e = threadIdx.x; e < n1 * C; e += blockDim.x) {
-        const int q = e >> logC, l = e & (C - 1);
-        buf[e] = l < cw ? base[(size_t)q * rs + c0 + l] : make_float2(0.f, 0.f);
+    load_table(tw, tw1, n1);
+    load_cols(lds, base, rs, logC, logn1, cw, P);
+    if (mode == 2) {
+        fft_lines<true>(lds, P, logC, logn1, tw);
+        store_cols(lds, base, rs, logC, logn1, cw, P);
+        return;
     }
-    __syncthreads();
-    lds_fft<true>(buf, logn1, logC, 1, C, tw, 1, false, true);
+    fft_lines<false>(lds, P, logC, logn1, tw);
+    if (mode == 1) {
+        store_cols(lds, base, rs, logC, logn1, cw, P);
+        return;
+    }
     const float k2 = (float)(i2 < (n2 >> 1) ? i2 : i2 - n2);
-    for (int e = threadIdx.x; e < n1 * C; e += blockDim.x) {
-        const int r = e >> logC, l = e & (C - 1);
-        const int q = brev(r, logn1);      // frequency index held at LDS row r
-        const float k1 = (float)(q < half ? q : q - n1);
+    const int tot = C << logn1;
+    for (int e = threadIdx.x; e < tot; e += TPB) {
+        const int l = e & (C - 1), q = e >> logC;
+        const float k1 = (float)(q < (n1 >> 1) ? q : q - n1);
         const float k3 = (float)(c0 + l);
         const float ksq = k1 * k1 + k2 * k2 + k3 * k3;
         float sym;
@@ -218,15 +376,35 @@ __global__ __launch_bounds__(TPB) void k_fft_x1_mult(float2 *__restrict__ spec, 
         else if (kind == 1) sym = 1.0f / (beta * fmaxf(ksq, 1.0f));
         else sym = 1.0f;
         sym *= scale;
-        buf[e].x *= sym;
-        buf[e].y *= sym;
+        float2 &x = lds[q * P + l];
+        x.x *= sym;
+        x.y *= sym;
     }
     __syncthreads();
-    lds_fft<false>(buf, logn1, logC, 1, C, tw, 1, true, true);
-    for (int e = threadIdx.x; e < n1 * C; e += blockDim.x) {
-        const int q = e >> logC, l = e & (C - 1);
-        if (l < cw) base[(size_t)q * rs + c0 + l] = buf[e];
+    fft_lines<true>(lds, P, logC, logn1, tw);
+    store_cols(lds, base, rs, logC, logn1, cw, P);
+}
+
+// Copy the half-spectrum modes with |k_d| < min(na_d, nb_d)/2 from grid a
+// to grid b (the coarse Nyquist planes are dropped), zero elsewhere.
+__global__ __launch_bounds__(TPB) void k_mode_copy(const float2 *__restrict__ sa, float2 *__restrict__ sb, int a1, int a2,
+                                                   int a3, int b1, int b2, int b3, int ncomp)
+{
+    const int bh = b3 / 2 + 1, ah = a3 / 2 + 1;
+    const size_t nb = (size_t)b1 * b2 * bh;
+    const size_t e = (size_t)blockIdx.x * TPB + threadIdx.x;
+    if (e >= nb * ncomp) return;
+    const int comp = (int)(e / nb);
+    const size_t r = e - comp * nb;
+    const int q3 = (int)(r % bh), q2 = (int)((r / bh) % b2), q1 = (int)(r / ((size_t)bh * b2));
+    const int k1 = q1 < b1 / 2 ? q1 : q1 - b1, k2 = q2 < b2 / 2 ? q2 : q2 - b2, k3 = q3;
+    const int c1 = min(a1, b1), c2 = min(a2, b2), c3 = min(a3, b3);
+    float2 v = make_float2(0.f, 0.f);
+    if (2 * abs(k1) < c1 && 2 * abs(k2) < c2 && 2 * k3 < c3) {
+        const int p1 = k1 < 0 ? k1 + a1 : k1, p2 = k2 < 0 ? k2 + a2 : k2;
+        v = sa[(size_t)comp * a1 * a2 * ah + ((size_t)p1 * a2 + p2) * ah + k3];
     }
+    sb[e] = v;
 }
 
 int ilog2(int n)
@@ -243,10 +421,10 @@ size_t fft_spec_bytes(int n1, int n2, int n3, int ncomp)
     return (size_t)ncomp * n1 * n2 * (n3 / 2 + 1) * sizeof(float2);
 }
 
-void fft_make_twiddles(float2 *host, int n)
+void fft_make_twiddles(float2 *host, int n, int count)
 {
     const double two_pi = 6.283185307179586476925286766559;
-    for (int t = 0; t < n / 2; ++t) {
+    for (int t = 0; t < count; ++t) {
         const double a = -two_pi * t / n;
         host[t] = make_float2((float)std::cos(a), (float)std::sin(a));
     }
@@ -261,37 +439,104 @@ void spectral_apply(const FFTPlan &P, int kind, float beta, int ncomp, const flo
     const size_t spec_cs = (size_t)n1 * n2 * nh;
     const float scale = (float)(1.0 / (double)N);
     const int nrows = n1 * n2;
-    int logR = ilog2(LDS_C) - logM;
-    if (logR < 0) logR = 0;
-    if ((1 << logR) > nrows) logR = ilog2(nrows);
-    const int R = 1 << logR;
+    const int logT = ilog2(TILE);
+    // x3: nl rows of M per tile
+    int lognl3 = logT - logM;            // M >= 8, so nl <= TILE / 8
+    if ((1 << lognl3) > nrows) lognl3 = ilog2(nrows);
+    const size_t lds3 = (size_t)(M + M + 1 + ((size_t)M + 1) * ((1 << lognl3) + 1)) * sizeof(float2);
+    // x2 / x1: C columns of n2 / n1 per tile
+    const int logC2 = logT - ilog2(n2) > 5 ? 5 : logT - ilog2(n2);
+    const int logC1 = logT - ilog2(n1) > 5 ? 5 : logT - ilog2(n1);
+    const int C2 = 1 << logC2, C1 = 1 << logC1;
+    const size_t lds2 = (size_t)(n2 + (size_t)n2 * (C2 + 1)) * sizeof(float2);
+    const size_t lds1 = (size_t)(n1 + (size_t)n1 * (C1 + 1)) * sizeof(float2);
     for (int c0 = 0; c0 < ncomp; c0 += P.ncomp_max) {
         const int nc = ncomp - c0 < P.ncomp_max ? ncomp - c0 : P.ncomp_max;
         const float *inc = in + c0 * N;
         float *outc = out + c0 * N;
         const float *addc = add ? add + c0 * N : nullptr;
-        const size_t lds3 = (size_t)(M + R * M) * sizeof(float2);
-        hipLaunchKernelGGL(k_fft_x3_r2c, dim3(nrows / R, nc), dim3(TPB), lds3, s, inc, P.spec, P.tw3, n3, logM,
-                           logR, nrows, N, spec_cs);
-        // x2 forward
-        int logC2 = ilog2(LDS_C) - ilog2(n2);
-        if (logC2 > 5) logC2 = 5;
-        const int C2 = 1 << logC2;
-        const size_t lds2 = (size_t)(n2 / 2 + n2 * C2) * sizeof(float2);
-        hipLaunchKernelGGL(k_fft_x2, dim3((nh + C2 - 1) / C2, n1, nc), dim3(TPB), lds2, s, P.spec, P.tw2, n2,
-                           ilog2(n2), nh, logC2, false, spec_cs);
-        // x1 forward, multiply, inverse
-        int logC1 = ilog2(LDS_C) - ilog2(n1);
-        if (logC1 > 5) logC1 = 5;
-        const int C1 = 1 << logC1;
-        const size_t lds1 = (size_t)(n1 / 2 + n1 * C1) * sizeof(float2);
+        hipLaunchKernelGGL(k_fft_x3_r2c, dim3(nrows >> lognl3, nc), dim3(TPB), lds3, s, inc, P.spec, P.twM, P.twS,
+                           logM, lognl3, nrows, N, spec_cs);
+        hipLaunchKernelGGL(k_fft_x2, dim3((nh + C2 - 1) / C2, n1, nc), dim3(TPB), lds2, s, P.spec, P.tw2, ilog2(n2),
+                           n2, nh, logC2, 0, spec_cs);
         hipLaunchKernelGGL(k_fft_x1_mult, dim3((nh + C1 - 1) / C1, n2, nc), dim3(TPB), lds1, s, P.spec, P.tw1,
-                           n1, ilog2(n1), n2, nh, logC1, kind, beta, scale, spec_cs);
-        // x2 inverse
-        hipLaunchKernelGGL(k_fft_x2, dim3((nh + C2 - 1) / C2, n1, nc), dim3(TPB), lds2, s, P.spec, P.tw2, n2,
-                           ilog2(n2), nh, logC2, true, spec_cs);
-        hipLaunchKernelGGL(k_fft_x3_c2r, dim3(nrows / R, nc), dim3(TPB), lds3, s, P.spec, outc, addc, P.tw3, n3,
-                           logM, logR, nrows, N, spec_cs);
+                           ilog2(n1), n1, n2, nh, logC1, kind, beta, scale, spec_cs, 0);
+        hipLaunchKernelGGL(k_fft_x2, dim3((nh + C2 - 1) / C2, n1, nc), dim3(TPB), lds2, s, P.spec, P.tw2, ilog2(n2),
+                           n2, nh, logC2, 1, spec_cs);
+        hipLaunchKernelGGL(k_fft_x3_c2r, dim3(nrows >> lognl3, nc), dim3(TPB), lds3, s, P.spec, outc, addc, P.twM,
+                           P.twS, logM, lognl3, nrows, N, spec_cs);
+    }
+}
+
+namespace {
+
+struct PassGeom {
+    int logM, lognl3, logC1, logC2, C1, C2, nrows;
+    size_t lds1, lds2, lds3, N, spec_cs;
+};
+
+PassGeom geom(const FFTPlan &P)
+{
+    PassGeom G;
+    const int logT = ilog2(TILE);
+    G.logM = ilog2(P.n3 / 2);
+    G.nrows = P.n1 * P.n2;
+    G.lognl3 = logT - G.logM;
+    if ((1 << G.lognl3) > G.nrows) G.lognl3 = ilog2(G.nrows);
+    const int M = P.n3 / 2;
+    G.lds3 = (size_t)(M + M + 1 + ((size_t)M + 1) * ((1 << G.lognl3) + 1)) * sizeof(float2);
+    G.logC2 = logT - ilog2(P.n2) > 5 ? 5 : logT - ilog2(P.n2);
+    G.logC1 = logT - ilog2(P.n1) > 5 ? 5 : logT - ilog2(P.n1);
+    G.C1 = 1 << G.logC1;
+    G.C2 = 1 << G.logC2;
+    G.lds2 = (size_t)(P.n2 + (size_t)P.n2 * (G.C2 + 1)) * sizeof(float2);
+    G.lds1 = (size_t)(P.n1 + (size_t)P.n1 * (G.C1 + 1)) * sizeof(float2);
+    G.N = (size_t)P.n1 * P.n2 * P.n3;
+    G.spec_cs = (size_t)P.n1 * P.n2 * P.nh;
+    return G;
+}
+
+void forward3(const FFTPlan &P, const PassGeom &G, int nc, const float *in, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fft_x3_r2c, dim3(G.nrows >> G.lognl3, nc), dim3(TPB), G.lds3, s, in, P.spec, P.twM, P.twS,
+                       G.logM, G.lognl3, G.nrows, G.N, G.spec_cs);
+    hipLaunchKernelGGL(k_fft_x2, dim3((P.nh + G.C2 - 1) / G.C2, P.n1, nc), dim3(TPB), G.lds2, s, P.spec, P.tw2,
+                       ilog2(P.n2), P.n2, P.nh, G.logC2, 0, G.spec_cs);
+    hipLaunchKernelGGL(k_fft_x1_mult, dim3((P.nh + G.C1 - 1) / G.C1, P.n2, nc), dim3(TPB), G.lds1, s, P.spec, P.tw1,
+                       ilog2(P.n1), P.n1, P.n2, P.nh, G.logC1, 2, 0.f, 1.f, G.spec_cs, 1);
+}
+
+void inverse3(const FFTPlan &P, const PassGeom &G, int nc, float *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fft_x1_mult, dim3((P.nh + G.C1 - 1) / G.C1, P.n2, nc), dim3(TPB), G.lds1, s, P.spec, P.tw1,
+                       ilog2(P.n1), P.n1, P.n2, P.nh, G.logC1, 2, 0.f, 1.f, G.spec_cs, 2);
+    hipLaunchKernelGGL(k_fft_x2, dim3((P.nh + G.C2 - 1) / G.C2, P.n1, nc), dim3(TPB), G.lds2, s, P.spec, P.tw2,
+                       ilog2(P.n2), P.n2, P.nh, G.logC2, 1, G.spec_cs);
+    hipLaunchKernelGGL(k_fft_x3_c2r, dim3(G.nrows >> G.lognl3, nc), dim3(TPB), G.lds3, s, P.spec, out, nullptr, P.twM,
+                       P.twS, G.logM, G.lognl3, G.nrows, G.N, G.spec_cs);
+}
+
+__global__ __launch_bounds__(TPB) void k_scale_f(float *x, float a, size_t n)
+{
+    const size_t e = (size_t)blockIdx.x * TPB + threadIdx.x;
+    if (e < n) x[e] *= a;
+}
+
+} // namespace
+
+void spectral_resample(const FFTPlan &A, const FFTPlan &B, int ncomp, const float *in, float *out, hipStream_t s)
+{
+    const PassGeom GA = geom(A), GB = geom(B);
+    for (int c0 = 0; c0 < ncomp; c0 += min(A.ncomp_max, B.ncomp_max)) {
+        const int nc = min(ncomp - c0, min(A.ncomp_max, B.ncomp_max));
+        forward3(A, GA, nc, in + c0 * GA.N, s);
+        const size_t nb = (size_t)B.n1 * B.n2 * B.nh * nc;
+        hipLaunchKernelGGL(k_mode_copy, dim3((unsigned)((nb + TPB - 1) / TPB)), dim3(TPB), 0, s, A.spec, B.spec, A.n1,
+                           A.n2, A.n3, B.n1, B.n2, B.n3, nc);
+        inverse3(B, GB, nc, out + c0 * GB.N, s);
+        const size_t n = GB.N * nc;
+        hipLaunchKernelGGL(k_scale_f, dim3((unsigned)((n + TPB - 1) / TPB)), dim3(TPB), 0, s, out + c0 * GB.N,
+                           (float)(1.0 / (double)GA.N), n);
     }
 }
 

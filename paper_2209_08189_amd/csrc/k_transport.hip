@@ -214,20 +214,20 @@ __device__ __forceinline__ int wave_max(int v)
     return v;
 }
 
-// Cubic Lagrange weights at fraction f, factored to share products.
+// Cubic Lagrange weights at fraction f with shared factors: a = f(f-1),
+// b = (f+1)(f-2) = a - 2; 10 VALU operations.  Exactly (0, 1, 0, 0) at f = 0.
 __device__ __forceinline__ void lagrange4_fast(float f, float w[4])
 {
-    const float fm1 = f - 1.0f, fp1 = f + 1.0f, fm2 = f - 2.0f;
-    const float a = f * fm1;          // f (f-1)
-    const float b = fp1 * fm2;        // (f+1)(f-2)
-    w[0] = (a * fm2) * (-1.0f / 6.0f);
-    w[1] = (b * fm1) * 0.5f;
-    w[2] = (b * f) * -0.5f;
-    w[3] = (a * fp1) * (1.0f / 6.0f);
+    const float a = fmaf(f, f, -f);
+    const float b = a - 2.0f;
+    w[0] = a * fmaf(f, -1.0f / 6.0f, 1.0f / 3.0f);   // -f(f-1)(f-2)/6
+    w[1] = b * fmaf(f, 0.5f, -0.5f);                 //  (f+1)(f-1)(f-2)/2
+    w[2] = b * (-0.5f * f);                          // -(f+1)f(f-2)/2
+    w[3] = a * fmaf(f, 1.0f / 6.0f, 1.0f / 6.0f);    //  (f+1)f(f-1)/6
 }
 
 template <typename Tu, typename To, int MODE>
-__global__ __launch_bounds__(TPB) void k_sl_tile(Grid g, const Tu *__restrict__ u, const float *__restrict__ d,
+__global__ __launch_bounds__(TPB, 4) void k_sl_tile(Grid g, const Tu *__restrict__ u, const float *__restrict__ d,
                                                  SLParams prm, To *__restrict__ out, int ntx, int nty, int nblk)
 {
     __shared__ Tu box[PZ * PY * PX];
@@ -306,7 +306,7 @@ __global__ __launch_bounds__(TPB) void k_sl_tile(Grid g, const Tu *__restrict__ 
                 }
         }
         __syncthreads();
-#pragma unroll 1
+#pragma unroll
         for (int q = 0; q < TZ; ++q) {
             const float f1 = floorf(d1[q]), f2 = floorf(d2[q]), f3 = floorf(d3[q]);
             float w1[4], w2[4], w3[4];
@@ -337,6 +337,7 @@ __global__ __launch_bounds__(TPB) void k_sl_tile(Grid g, const Tu *__restrict__ 
             }
             const int p = p0 + q * plane;
             stf(out + p, epilogue<MODE>(g, prm, p, s));
+            __builtin_amdgcn_sched_barrier(0);
         }
     } else {
         for (int q = 0; q < TZ; ++q) {

@@ -1,0 +1,149 @@
+"""Learned warm start on the GPU: BF16 MFMA convolution kernels and the
+whole network against the FP64 reference fed the same BF16-rounded operands,
+spectral resampling against the oracle, training, and the warm-start
+fallback.
+
+Tolerances: single layers with FP32 output 1e-5 (products of BF16 values
+are exact in FP32; only the FP32 accumulation order differs from FP64).
+The whole network stores every activation and activation gradient in BF16
+(unit roundoff 2^-9), so an FP32 accumulation that lands on the other side
+of a BF16 rounding boundary than the FP64 reference changes one value by
+one BF16 ulp and that difference propagates; the network output and the
+parameter gradient are held to 2e-2 relative L2 (observed values printed)."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle.net_oracle import RefNet, bf16_round, init_params
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2209_08189_amd import claire
+    claire.lib()
+    torch.cuda.set_device(0)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+
+
+def bf16_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda().to(torch.bfloat16)
+
+
+def f32_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().float().cpu().numpy().astype(np.float64)
+
+
+CASES = [((4, 6, 32), 16, 16), ((4, 4, 16), 16, 32), ((3, 4, 20), 48, 16), ((4, 4, 8), 192, 64),
+         ((2, 2, 16), 64, 128), ((5, 3, 4), 96, 32)]
+
+
+@pytest.mark.parametrize("shape,ci,co", CASES)
+def test_conv3_forward_and_transpose(shape, ci, co):
+    from paper_2209_08189_amd.claire import nn_conv3
+    r = np.random.default_rng(ci * 1000 + co)
+    x = bf16_round(r.standard_normal(shape + (ci,)))
+    w = r.standard_normal((27, ci, co)) / np.sqrt(27 * ci)
+    b = r.standard_normal(co)
+    wb = bf16_round(w)
+    out = host(nn_conv3(bf16_dev(x), f32_dev(w), f32_dev(b), co, act=0))
+    assert rel(out, oracle.conv3(x, wb, b)) < 1e-5
+    act = host(nn_conv3(bf16_dev(x), f32_dev(w), f32_dev(b), co, act=1, slope=0.2))
+    assert rel(act, oracle.lrelu(oracle.conv3(x, wb, b), 0.2)) < 1e-5
+    y = bf16_round(r.standard_normal(shape + (co,)))
+    tr = host(nn_conv3(bf16_dev(y), f32_dev(w), None, co, act=0, transpose=True))
+    assert rel(tr, oracle.conv3_t(y, wb)) < 1e-5
+    # BF16 output is the FP32 result rounded to nearest even
+    o16 = host(nn_conv3(bf16_dev(x), f32_dev(w), f32_dev(b), co, act=0, out_f32=False))
+    assert np.max(np.abs(o16 - bf16_round(out))) <= np.max(np.abs(out)) * 2.0 ** -7
+
+
+@pytest.mark.parametrize("shape,ci,co", CASES)
+def test_conv3_weight_gradient(shape, ci, co):
+    from paper_2209_08189_amd.claire import nn_conv3_dw
+    r = np.random.default_rng(7 + ci + co)
+    x = bf16_round(r.standard_normal(shape + (ci,)))
+    dz = bf16_round(r.standard_normal(shape + (co,)))
+    gw, gb = nn_conv3_dw(bf16_dev(x), bf16_dev(dz))
+    rw, rb = oracle.conv3_dw(x, dz)
+    assert rel(host(gw), rw) < 1e-5
+    assert rel(host(gb), rb) < 1e-5
+
+
+def _sample(n, seed):
+    r = np.random.default_rng(seed)
+    from paper_2209_08189_amd import synth
+    m0 = synth.smooth_random_field((n,) * 3, seed, kmax=3.0) * 0.5 + 0.5
+    m1 = synth.smooth_random_field((n,) * 3, seed + 1, kmax=3.0) * 0.5 + 0.5
+    lab = 0.1 * np.stack([synth.smooth_random_field((n,) * 3, seed + 2 + a, kmax=2.0) for a in range(3)])
+    return m0, m1, lab
+
+
+def test_network_forward_and_gradient_vs_reference():
+    from paper_2209_08189_amd.claire import Net
+    n = 32
+    net = Net(in_n=n, seed=5)
+    p = init_params(11, scale_head=0.3)
+    net.set_params(f32_dev(p))
+    pf = p.astype(np.float32).astype(np.float64)
+    m0, m1, lab = _sample(n, 3)
+    m0f, m1f, labf = (a.astype(np.float32).astype(np.float64) for a in (m0, m1, lab))
+    ref = RefNet(pf, bf16=True)
+    v_ref = ref.forward(m0f, m1f)
+    v = host(net.forward(f32_dev(m0f), f32_dev(m1f)))
+    ev = rel(v, v_ref)
+    L_ref, g_ref = RefNet(pf, bf16=True).loss_grad(m0f, m1f, labf)
+    L, g = net.loss_grad(f32_dev(m0f), f32_dev(m1f), f32_dev(labf))
+    eg = rel(host(g), g_ref)
+    print("network: rel err output %.2e  loss %.2e  gradient %.2e" % (ev, abs(L - L_ref) / L_ref, eg))
+    assert ev < 2e-2 and abs(L - L_ref) < 2e-2 * L_ref and eg < 2e-2
+
+
+def test_training_reduces_loss():
+    from paper_2209_08189_amd.claire import Net
+    n = 32
+    net = Net(in_n=n, seed=2, lr=1e-3)
+    m0, m1, lab = _sample(n, 9)
+    a, b, c = f32_dev(m0), f32_dev(m1), f32_dev(lab)
+    losses = [net.train_step(a, b, c) for _ in range(30)]
+    print("loss %.4e -> %.4e" % (losses[0], losses[-1]))
+    assert losses[-1] < 0.5 * losses[0]
+
+
+@pytest.mark.parametrize("a,b", [((32, 32, 32), (16, 16, 16)), ((16, 16, 16), (32, 32, 32)),
+                                 ((16, 32, 64), (32, 16, 32))])
+def test_spectral_resample(a, b):
+    from paper_2209_08189_amd.claire import Resampler
+    r = np.random.default_rng(1)
+    x = r.standard_normal((3,) + a).astype(np.float32).astype(np.float64)
+    out = host(Resampler(a, b)(f32_dev(x)))
+    ref = np.stack([oracle.spectral_resample(x[c], b) for c in range(3)])
+    assert rel(out, ref) < 1e-5
+
+
+def test_warm_start_falls_back_when_no_gain():
+    """An untrained network (zero head) predicts v = 0, which does not lower
+    the objective: the context keeps v = 0."""
+    from paper_2209_08189_amd.claire import Net, Registration, warm_start
+    from paper_2209_08189_amd import synth
+    shape = (64, 64, 64)
+    m0 = synth.trig_template(shape).astype(np.float32)
+    m1 = np.roll(m0, 2, axis=0)
+    reg = Registration(shape)
+    reg.set_images(f32_dev(m0), f32_dev(m1))
+    net = Net(in_n=32, seed=1)
+    used, Jp, J0 = warm_start(reg, net)
+    assert not used and Jp == J0
+    assert float(torch.abs(reg.velocity()).max()) == 0.0

@@ -91,7 +91,8 @@ def test_fd_matches_oracle(shape):
     assert rel(host(r.fd_div(dev(v))), oracle.div(v)) < TOL_KERNEL
 
 
-@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("shape", SHAPES + [(64, 128, 32), (16, 1024, 16), (1024, 16, 16), (16, 16, 1024),
+                                   (32, 256, 64)])
 @pytest.mark.parametrize("kind", [0, 1, 2])
 def test_spectral_matches_oracle(shape, kind):
     x = f32(synth.random_field((3,) + shape, 5))
@@ -175,6 +176,48 @@ def test_objective_and_precond():
     assert abs(misg - mis) / mis < TOL_KERNEL and abs(regg - regv) / regv < TOL_KERNEL
     x = f32(synth.random_field((3,) + shape, 11))
     assert rel(host(r.precond(dev(x))), o.precond(x)) < TOL_KERNEL
+
+
+# ------------------------------------------------ mixed-precision storage
+
+UROUND = {"f16": 2.0 ** -11, "bf16": 2.0 ** -8, "f32": 2.0 ** -24}
+
+
+@pytest.mark.parametrize("st,ad", [("f16", "bf16"), ("f16", "f16"), ("bf16", "bf16")])
+def test_mixed_storage_errors(st, ad):
+    """Images/state stored as `st`, adjoint/incremental fields as `ad`; all
+    arithmetic FP32, reductions FP64.  Per-field relative L2 error against
+    the FP64 oracle is reported and bounded by (nt + 2) units of roundoff of
+    the storage format (one rounding per stored time step plus the inputs);
+    the adjoint, which starts from the difference m1 - m(1), gets an extra
+    factor |m1| / |lambda(1)| for that cancellation."""
+    n = 64
+    shape, o, r32, v = _setup_pair(n)
+    _, m0, m1, _ = _cfg1(n)
+    vt = f32(synth.trig_velocity(shape, 0.3)[[2, 0, 1]])
+    g_ref, _ = o.gradient()
+    Hv_ref = o.matvec(vt)
+    r = reg(shape, storage_state=st, storage_adjoint=ad)
+    r.set_images(dev(m0), dev(m1))
+    r.set_velocity(dev(v))
+    g, gn, J = r.gradient()
+    errs = {
+        "m(1)": rel(host(r.field(0, 4)), o.field(oracle.FIELD_STATE, 4)),
+        "lambda(0)": rel(host(r.field(1, 0)), o.field(oracle.FIELD_ADJOINT, 0)),
+        "g": rel(host(g), g_ref),
+    }
+    Hv = host(r.hessian_matvec(dev(vt)))
+    errs["lambda~(0)"] = rel(host(r.field(3, 0)), o.field(oracle.FIELD_INC_ADJOINT, 0))
+    errs["Hvt"] = rel(Hv, Hv_ref)
+    print("storage %s/%s: %s" % (st, ad, {k: "%.2e" % e for k, e in errs.items()}))
+    us, ua = UROUND[st], UROUND[ad]
+    lam1 = o.field(oracle.FIELD_ADJOINT, 4)
+    amp = np.linalg.norm(m1) / np.linalg.norm(lam1)
+    assert errs["m(1)"] < 6 * us
+    assert errs["lambda(0)"] < 6 * (ua + us * amp)
+    assert errs["g"] < 6 * (ua + us * amp)
+    assert errs["lambda~(0)"] < 6 * (ua + us * amp)
+    assert errs["Hvt"] < 6 * (ua + us * amp)
 
 
 # ------------------------------------------------------ exact special cases
