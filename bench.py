@@ -24,6 +24,23 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRANSPORT_SRC = os.path.join(ROOT, "paper_2209_08189_amd", "csrc", "k_transport.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sl_traffic_256.json")
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed memory-counter
+    summary, if it was taken on the current transport-kernel source."""
+    import hashlib
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+        sha = hashlib.sha1(open(TRANSPORT_SRC, "rb").read()).hexdigest()
+        if rec.get("source_sha1") != sha or kernel not in rec.get("kernels", {}):
+            return None
+        k = rec["kernels"][kernel]
+        return k["fetch_bytes"] * rec["fetch_scale"] + k["write_bytes"] * rec["write_scale"]
+    except (OSError, ValueError, KeyError):
+        return None
 
 
 def log(msg):
@@ -58,6 +75,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=128)
+    ap.add_argument("--learned-train", type=int, default=8, help="training pairs (0 disables the learned leg)")
+    ap.add_argument("--learned-eval", type=int, default=2, help="held-out evaluation pairs")
+    ap.add_argument("--learned-epochs", type=int, default=8)
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="also run the library's plain copy kernel on this many MiB (memory-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only; this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
@@ -88,6 +110,14 @@ def main():
     vt = -r.precond(g)
     Hv = torch.empty_like(vt)
     torch.cuda.synchronize()
+
+    if args.copy_calibration > 0:
+        nc = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(nc, device="cuda")
+        dst = torch.empty_like(src)
+        r.copy(src, dst)
+        torch.cuda.synchronize()
+        del src, dst
 
     log("warmup %d matvecs" % args.warmup)
     for _ in range(args.warmup):
@@ -147,6 +177,38 @@ def main():
         log("solve: %s" % json.dumps(solve))
         del rs
 
+    learned = None
+    if args.learned_train > 0 and not args.no_solve:
+        try:
+            from paper_2209_08189_amd import warmstart
+            from paper_2209_08189_amd.claire import Net
+            tl = time.perf_counter()
+            train_seeds = list(range(1000, 1000 + args.learned_train))
+            eval_seeds = list(range(10000, 10000 + args.learned_eval))
+            data = warmstart.generate(train_seeds, n=n, n_net=n // 2, log=log)
+            net = Net(in_n=n // 2, seed=1, lr=1e-3)
+            t_train = time.perf_counter()
+            hist = warmstart.train(net, data, args.learned_epochs, log=log)
+            t_train = time.perf_counter() - t_train
+            del data
+            rows = warmstart.evaluate(net, eval_seeds, n=n, storage=("f16", "bf16"), log=log)
+            learned = {
+                "train_pairs": len(train_seeds), "eval_pairs": len(eval_seeds), "epochs": args.learned_epochs,
+                "net_grid": n // 2, "train_seconds": t_train, "loss_first": hist[0], "loss_last": hist[-1],
+                "plain_fp32_time_to_tol_s": float(np.mean([r["plain_s"] for r in rows])),
+                "learned_mixed_time_to_tol_s": float(np.mean([r["learned_s"] for r in rows])),
+                "plain_gn_iters": float(np.mean([r["plain_gn"] for r in rows])),
+                "learned_gn_iters": float(np.mean([r["learned_gn"] for r in rows])),
+                "prediction_used_frac": float(np.mean([r["used_prediction"] for r in rows])),
+                "max_rel_mismatch_diff": float(np.max([r["rel_mismatch_diff"] for r in rows])),
+                "storage": "images/state f16, adjoint/incremental bf16, FP32 arithmetic, FP64 reductions",
+                "rows": rows, "wall_s": time.perf_counter() - tl,
+            }
+            log("learned: %s" % json.dumps({k: v for k, v in learned.items() if k != "rows"}))
+        except Exception as e:   # report, do not lose the benchmark line
+            learned = {"error": repr(e)}
+            log("learned leg failed: %r" % (e,))
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -188,10 +250,11 @@ def main():
                                "vt = -P^-1 g" % (n, args.seed),
                    "grid": n, "nt": 4, "beta_v": 5e-4, "interp": "tricubic Lagrange", "fd": "8th order"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom),
                      "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": avg_ms, "launches": dom_n},
         "kernels": per_class,
         "solve_fp32": solve,
+        "learned_warm_start": learned,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -307,7 +307,7 @@ double gradient(cl_ctx *ctx, double *J, double *mis_out, double *reg_out)
 
 // GN Hessian matvec (incremental state, incremental adjoint, quadrature,
 // beta A vt); needs feet of both directions and the state of the current v.
-void matvec(cl_ctx *ctx, const float *vt, float *Hvt)
+void matvec(cl_ctx *ctx, const float *vt, float *Hvt, const float *Avt_known = nullptr)
 {
     ensure_feet(ctx, true);
     ensure_sgrad(ctx);
@@ -324,9 +324,13 @@ void matvec(cl_ctx *ctx, const float *vt, float *Hvt)
         });
     }
     adjoint_sweep(ctx);
-    spectral(ctx, 0, 3, vt, ctx->tmp3, nullptr);
+    const float *Avt = Avt_known;
+    if (!Avt) {
+        spectral(ctx, 0, 3, vt, ctx->tmp3, nullptr);
+        Avt = ctx->tmp3;
+    }
     const QuadArgs qa = quad_args(ctx);
-    run(ctx, CL_K_QUAD, [&] { launch_quadrature(ctx->g, ctx->dta, qa, ctx->tmp3, Hvt, ctx->s); });
+    run(ctx, CL_K_QUAD, [&] { launch_quadrature(ctx->g, ctx->dta, qa, Avt, Hvt, ctx->s); });
 }
 
 void precond(cl_ctx *ctx, const float *r, float *z) { spectral(ctx, 1, 3, r, z, nullptr); }
@@ -347,10 +351,19 @@ int pcg(cl_ctx *ctx, int max_pcg, double eta, int forced, int *iters)
     HIPCHK(hipMemcpyAsync(ctx->pp, ctx->pz, n * sizeof(float), hipMemcpyDeviceToDevice, ctx->s));
     double rz = dotw(ctx, ctx->pr, ctx->pz, n);
     const double r0 = std::sqrt(dotw(ctx, ctx->pr, ctx->pr, n));
+    // beta A p by recurrence: p = z + b p and beta A z = r - mean(r) (A has
+    // no k = 0 mode, the preconditioner maps it by 1/beta), so the matvecs
+    // inside PCG need no FFT pair of their own
+    float *pAp = ctx->tmp3;
+    run(ctx, CL_K_VEC, [&] {
+        launch_fill_f32(pAp, 0.0f, n, ctx->s);
+        launch_comp_sums3(ctx->pr, ctx->N, ctx->partials, ctx->nparts / 3, ctx->dscal + 1, ctx->s);
+        launch_mean_free_axpy(pAp, ctx->pr, ctx->dscal + 1, 0.0f, ctx->N, ctx->s);
+    });
     const int limit = forced >= 0 ? forced : max_pcg;
     int it = 0, neg = 0;
     while (it < limit) {
-        matvec(ctx, ctx->pp, ctx->pHp);
+        matvec(ctx, ctx->pp, ctx->pHp, pAp);
         const double pHp = dotw(ctx, ctx->pp, ctx->pHp, n);
         if (!(pHp > 0.0)) {
             neg = 1;
@@ -371,7 +384,11 @@ int pcg(cl_ctx *ctx, int max_pcg, double eta, int forced, int *iters)
         const double rz_new = dotw(ctx, ctx->pr, ctx->pz, n);
         const double bt = rz_new / rz;
         rz = rz_new;
-        run(ctx, CL_K_VEC, [&] { launch_axpy(ctx->pp, ctx->pz, ctx->pp, (float)bt, n, ctx->s); });
+        run(ctx, CL_K_VEC, [&] {
+            launch_axpy(ctx->pp, ctx->pz, ctx->pp, (float)bt, n, ctx->s);
+            launch_comp_sums3(ctx->pr, ctx->N, ctx->partials, ctx->nparts / 3, ctx->dscal + 1, ctx->s);
+            launch_mean_free_axpy(pAp, ctx->pr, ctx->dscal + 1, (float)bt, ctx->N, ctx->s);
+        });
     }
     if (iters) *iters = it;
     return neg;

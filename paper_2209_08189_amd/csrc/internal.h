@@ -144,6 +144,11 @@ void launch_pcg_update(float *x, float *r, const float *p, const float *Hp, floa
                        double *partials, int nblocks, hipStream_t s);
 // y = a + alpha * b   (y may alias a)
 void launch_axpy(float *y, const float *a, const float *b, float alpha, size_t n, hipStream_t s);
+// sums_out[c] = sum of component c of a 3-field vector (device, FP64);
+// partials must hold 3 * nblocks doubles
+void launch_comp_sums3(const float *a, size_t n, double *partials, int nblocks, double *sums_out, hipStream_t s);
+// y_c = (r_c - sums[c] / n) + beta * y_c  (3 components of n values)
+void launch_mean_free_axpy(float *y, const float *r, const double *sums, float beta, size_t n, hipStream_t s);
 // y = alpha * a  (y may alias a)
 void launch_scale(float *y, const float *a, float alpha, size_t n, hipStream_t s);
 void launch_convert(int dt_out, void *out, const float *in, size_t n, hipStream_t s);

@@ -79,6 +79,30 @@ __global__ __launch_bounds__(TPB) void k_scale(float *__restrict__ y, const floa
     for (size_t q = (size_t)blockIdx.x * TPB + threadIdx.x; q < n; q += stride) y[q] = alpha * a[q];
 }
 
+// per-component sums of a 3-field vector: partials[c * nb + block]
+__global__ __launch_bounds__(TPB) void k_comp_sums(const float *__restrict__ a, size_t n, double *__restrict__ partials)
+{
+    const int c = blockIdx.y;
+    const float *x = a + c * n;
+    double acc = 0.0;
+    const size_t stride = (size_t)gridDim.x * TPB;
+    for (size_t p = (size_t)blockIdx.x * TPB + threadIdx.x; p < n; p += stride) acc += (double)x[p];
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) partials[c * gridDim.x + blockIdx.x] = acc;
+}
+
+// y_c = (r_c - sum_c / n) + beta * y_c  for the 3 components (sums on device)
+__global__ __launch_bounds__(TPB) void k_mean_free_axpy(float *y, const float *__restrict__ r,
+                                                        const double *__restrict__ sums, float beta, size_t n)
+{
+    const size_t stride = (size_t)gridDim.x * TPB;
+    for (size_t q = (size_t)blockIdx.x * TPB + threadIdx.x; q < 3 * n; q += stride) {
+        const int c = (int)(q / n);
+        const float mean = (float)(sums[c] / (double)n);
+        y[q] = (r[q] - mean) + beta * y[q];
+    }
+}
+
 template <typename To>
 __global__ __launch_bounds__(TPB) void k_convert(To *__restrict__ out, const float *__restrict__ in, size_t n)
 {
@@ -159,6 +183,17 @@ void launch_axpy(float *y, const float *a, const float *b, float alpha, size_t n
 void launch_scale(float *y, const float *a, float alpha, size_t n, hipStream_t s)
 {
     hipLaunchKernelGGL(k_scale, stream_grid(n), dim3(TPB), 0, s, y, a, alpha, n);
+}
+
+void launch_comp_sums3(const float *a, size_t n, double *partials, int nblocks, double *sums_out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_comp_sums, dim3(nblocks, 3), dim3(TPB), 0, s, a, n, partials);
+    for (int c = 0; c < 3; ++c) launch_finalize(partials + c * nblocks, nblocks, 1.0, sums_out + c, s);
+}
+
+void launch_mean_free_axpy(float *y, const float *r, const double *sums, float beta, size_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_mean_free_axpy, stream_grid(3 * n), dim3(TPB), 0, s, y, r, sums, beta, n);
 }
 
 void launch_convert(int dt_out, void *out, const float *in, size_t n, hipStream_t s)

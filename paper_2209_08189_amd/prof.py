@@ -1,0 +1,77 @@
+"""Summaries of rocprofv3 CSV output (kernel statistics, memory counters).
+
+  python -m paper_2209_08189_amd.prof stats <kernel_stats.csv> <title> <command>
+      -> markdown table of per-kernel calls / total / average time
+  python -m paper_2209_08189_amd.prof traffic <fetch_dir> <write_dir> <copy_MiB> <out.json> <command>
+      -> HBM bytes per launch of the SL kernels from FETCH_SIZE / WRITE_SIZE
+         runs, scaled by what the same counters read for the library's plain
+         copy kernel (k_copy4) of a known size; stamped with the SHA-1 of the
+         transport kernel source so stale numbers are not reused.
+"""
+import csv
+import glob
+import hashlib
+import json
+import os
+import sys
+from collections import defaultdict
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+TRANSPORT_SRC = os.path.join(HERE, "csrc", "k_transport.hip")
+
+
+def short(name):
+    n = name.replace("clh::(anonymous namespace)::", "").replace("void ", "")
+    return n.split("(")[0]
+
+
+def stats_md(path, title, command):
+    rows = list(csv.DictReader(open(path)))
+    out = ["# %s" % title, "", "Command:", "", "```", command, "```", "",
+           "| kernel | calls | total us | avg us | % |", "|---|---:|---:|---:|---:|"]
+    for r in rows:
+        if float(r["Percentage"]) < 0.05:
+            continue
+        out.append("| %s | %s | %.1f | %.2f | %.2f |" % (short(r["Name"]), r["Calls"], float(r["TotalDurationNs"]) / 1e3,
+                                                        float(r["AverageNs"]) / 1e3, float(r["Percentage"])))
+    return "\n".join(out) + "\n"
+
+
+def counter_means(directory, counter):
+    path = glob.glob(os.path.join(directory, "**", "*counter_collection.csv"), recursive=True)[0]
+    acc = defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] == counter:
+            acc[short(r["Kernel_Name"])].append(float(r["Counter_Value"]) * 1024.0)   # KiB -> bytes
+    return {k: sum(v) / len(v) for k, v in acc.items()}
+
+
+SL_NAMES = {"sl_state": "k_sl_tile<float, float, 0>", "sl_adjoint": "k_sl_tile<float, float, 1>",
+            "sl_inc": "k_sl_tile<float, float, 2>"}
+
+
+def traffic(fetch_dir, write_dir, copy_mib, command):
+    fetch = counter_means(fetch_dir, "FETCH_SIZE")
+    write = counter_means(write_dir, "WRITE_SIZE")
+    nbytes = copy_mib * (1 << 20)
+    fs = nbytes / fetch["k_copy4"]
+    ws = nbytes / write["k_copy4"]
+    rec = {"source_sha1": hashlib.sha1(open(TRANSPORT_SRC, "rb").read()).hexdigest(),
+           "fetch_scale": fs, "write_scale": ws,
+           "calibration": "k_copy4 over %d MiB: FETCH_SIZE %.0f B, WRITE_SIZE %.0f B" % (copy_mib, fetch["k_copy4"],
+                                                                                       write["k_copy4"]),
+           "command": command, "kernels": {}}
+    for k, kn in SL_NAMES.items():
+        if kn in fetch and kn in write:
+            rec["kernels"][k] = {"fetch_bytes": fetch[kn], "write_bytes": write[kn],
+                                 "hbm_bytes_scaled": fetch[kn] * fs + write[kn] * ws}
+    return rec
+
+
+if __name__ == "__main__":
+    if sys.argv[1] == "stats":
+        sys.stdout.write(stats_md(sys.argv[2], sys.argv[3], sys.argv[4]))
+    elif sys.argv[1] == "traffic":
+        rec = traffic(sys.argv[2], sys.argv[3], int(sys.argv[4]), sys.argv[6])
+        json.dump(rec, open(sys.argv[5], "w"), indent=1)
+        print(json.dumps(rec, indent=1))
