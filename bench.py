@@ -61,7 +61,7 @@ def make_inputs(n, seed):
 ALG_F = {
     "sl_state": 5,      # gather 1 + feet 3 + write 1
     "sl_adjoint": 6,    # gather 1 + feet 3 + c 1 + write 1
-    "sl_inc": 9,        # gather 1 + feet 3 + vt 3 + m^{j+1} 1 + write 1
+    "sl_inc": 6,        # gather 1 + feet 3 + source s^{j+1} 1 + write 1
 }
 
 

@@ -47,6 +47,8 @@ struct cl_ctx {
     void *lam = nullptr;                    // (nt+1) N, adjoint dtype
     void *q[2] = {nullptr, nullptr};        // adjoint dtype
     float *G = nullptr;                     // grad_h m^j, (nt+1) x 3N FP32
+    float *S = nullptr;                     // incremental sources s^1..s^nt, nt x N FP32
+    int *box_f = nullptr, *box_b = nullptr, *box_t = nullptr;  // tile stencil boxes: X_f, X_b, scratch
     float *v = nullptr, *vtrial = nullptr;  // 3N
     float *df = nullptr, *db = nullptr;     // 3N
     float *c = nullptr, *divv = nullptr;    // N
@@ -192,6 +194,8 @@ void ensure_feet(cl_ctx *ctx, bool backward)
         run(ctx, CL_K_FEET, [&] {
             launch_feet(ctx->g, ctx->dt, ctx->v, ctx->df, backward ? ctx->db : nullptr,
                         backward ? ctx->divv : nullptr, backward ? ctx->c : nullptr, ctx->s);
+            launch_tile_boxes(ctx->g, ctx->df, ctx->box_f, ctx->s);
+            if (backward) launch_tile_boxes(ctx->g, ctx->db, ctx->box_b, ctx->s);
         });
         ctx->feet_f = true;
         if (backward) ctx->feet_b = true;
@@ -208,7 +212,7 @@ void ensure_state(cl_ctx *ctx)
     HIPCHK(hipMemcpyAsync(ctx->m, ctx->m0, bytes, hipMemcpyDeviceToDevice, ctx->s));
     for (int j = 0; j < ctx->nt; ++j)
         run(ctx, CL_K_SL_STATE, [&] {
-            launch_sl_state(ctx->g, ctx->dts, slot(ctx, ctx->m, ctx->dts, j), ctx->df, ctx->dts,
+            launch_sl_state(ctx->g, ctx->dts, slot(ctx, ctx->m, ctx->dts, j), ctx->df, ctx->box_f, ctx->dts,
                             slot(ctx, ctx->m, ctx->dts, j + 1), ctx->s);
         });
     ctx->state = true;
@@ -275,7 +279,7 @@ void adjoint_sweep(cl_ctx *ctx)
 {
     for (int j = ctx->nt - 1; j >= 0; --j)
         run(ctx, CL_K_SL_ADJOINT, [&] {
-            launch_sl_adjoint(ctx->g, ctx->dta, slot(ctx, ctx->lam, ctx->dta, j + 1), ctx->db, ctx->c, ctx->dta,
+            launch_sl_adjoint(ctx->g, ctx->dta, slot(ctx, ctx->lam, ctx->dta, j + 1), ctx->db, ctx->box_b, ctx->c, ctx->dta,
                               slot(ctx, ctx->lam, ctx->dta, j), ctx->s);
         });
 }
@@ -313,13 +317,15 @@ void matvec(cl_ctx *ctx, const float *vt, float *Hvt, const float *Avt_known = n
     ensure_sgrad(ctx);
     const float dt = ctx->dt;
     const int nt = ctx->nt;
-    const size_t N3 = 3 * ctx->N;
-    run(ctx, CL_K_VEC, [&] { launch_inc_init(ctx->g, ctx->G, vt, 0.5f * dt, ctx->dta, ctx->q[0], ctx->s); });
+    // sources s^j = -vt . grad_h m^j for all j, q^0 = dt/2 s^0
+    run(ctx, CL_K_VEC, [&] {
+        launch_inc_sources(ctx->g, ctx->G, vt, nt, 0.5f * dt, ctx->dta, ctx->q[0], ctx->S, ctx->s);
+    });
     for (int j = 0; j < nt; ++j) {
         const bool last = j == nt - 1;
         void *out = last ? slot(ctx, ctx->lam, ctx->dta, nt) : ctx->q[(j + 1) & 1];
         run(ctx, CL_K_SL_INC, [&] {
-            launch_sl_inc(ctx->g, ctx->dta, ctx->q[j & 1], ctx->df, ctx->G + (size_t)(j + 1) * N3, vt,
+            launch_sl_inc(ctx->g, ctx->dta, ctx->q[j & 1], ctx->df, ctx->box_f, ctx->S + (size_t)j * ctx->N,
                           last ? -1.0f : 1.0f, last ? -0.5f * dt : dt, ctx->dta, out, ctx->s);
         });
     }
@@ -489,6 +495,8 @@ size_t workspace_bytes(int n1, int n2, int n3, const cl_options &o)
     b += (size_t)(o.nt + 1) * N * ea;        // lam^j / lam~^j
     b += 2 * N * ea;                         // q ping-pong
     b += (size_t)(o.nt + 1) * 3 * N * sizeof(float);  // grad_h m^j
+    b += (size_t)o.nt * N * sizeof(float);   // incremental sources s^j
+    b += 3 * (N / 2048 + 1) * 8 * sizeof(int);  // tile stencil boxes
     b += 2 * N * sizeof(float);              // c, div v
     b += 12 * 3 * N * sizeof(float);         // v, vtrial, df, db, g, Av, tmp3, PCG x r z p Hp
     b += fft_spec_bytes(n1, n2, n3, 3);
@@ -614,6 +622,13 @@ int cl_create(cl_ctx **out, int n1, int n2, int n3, const cl_options *opt)
         ctx->q[0] = alloc(N * ea);
         ctx->q[1] = alloc(N * ea);
         ctx->G = (float *)alloc((size_t)(ctx->nt + 1) * 3 * N * sizeof(float));
+        ctx->S = (float *)alloc((size_t)ctx->nt * N * sizeof(float));
+        {
+            const size_t nb = std::max<size_t>(tile_box_ints(ctx->g), 8) * sizeof(int);
+            ctx->box_f = (int *)alloc(nb);
+            ctx->box_b = (int *)alloc(nb);
+            ctx->box_t = (int *)alloc(nb);
+        }
         float **vecs[] = {&ctx->v, &ctx->vtrial, &ctx->df, &ctx->db, &ctx->grad, &ctx->Av, &ctx->tmp3,
                           &ctx->px, &ctx->pr, &ctx->pz, &ctx->pp, &ctx->pHp};
         for (float **pv : vecs) *pv = (float *)alloc(3 * N * sizeof(float));
@@ -836,7 +851,7 @@ int cl_interp(cl_ctx *ctx, const float *u, const float *d, float *out)
     const size_t b = ctx->N * sizeof(float);
     if (overlap(u, b, out, b) || overlap(d, 3 * b, out, b)) return fail(ctx, CL_ERR_ALIAS, "output overlaps an input");
     API_BEGIN
-    run(ctx, CL_K_SL_STATE, [&] { launch_interp_f32(ctx->g, u, d, out, ctx->s); });
+    run(ctx, CL_K_SL_STATE, [&] { launch_interp_f32(ctx->g, u, d, ctx->box_t, out, ctx->s); });
     return CL_OK;
     API_END
 }

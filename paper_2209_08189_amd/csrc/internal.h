@@ -91,22 +91,27 @@ template <typename F> inline void with_dtype(int dt, F &&f)
 
 // epilogue operands of the semi-Lagrangian step kernels
 struct SLParams {
-    const float *c;       // adjoint factor
-    const float *G;       // grad_h m^{j+1}, 3 fields
-    const float *vt;      // incremental velocity, 3 fields
+    const float *e;       // per-node operand: adjoint factor c, or incremental source s^{j+1}
     float sI, sS;
 };
 
 // transport (k_transport.hip)
 void launch_feet(const Grid &g, float dt, const float *v, float *df, float *db,
                  const float *divv, float *c, hipStream_t s);
-void launch_sl_state(const Grid &g, int dt_u, const void *u, const float *d, int dt_out, void *out, hipStream_t s);
-void launch_sl_adjoint(const Grid &g, int dt_u, const void *u, const float *d, const float *c,
+// Per-tile stencil bounding boxes of the feet d (8 ints per 8x8x32 tile;
+// tile_box_ints() == 0 for grids too small for the tiled kernels).  Computed
+// once per velocity and direction and passed to every SL step with those feet.
+size_t tile_box_ints(const Grid &g);
+void launch_tile_boxes(const Grid &g, const float *d, int *boxes, hipStream_t s);
+void launch_sl_state(const Grid &g, int dt_u, const void *u, const float *d, const int *boxes, int dt_out, void *out,
+                     hipStream_t s);
+void launch_sl_adjoint(const Grid &g, int dt_u, const void *u, const float *d, const int *boxes, const float *c,
                        int dt_out, void *out, hipStream_t s);
-// out = sI * I[q](x + d) + sS * (-vt . G)(x), G = grad_h m^{j+1} (3 FP32 fields)
-void launch_sl_inc(const Grid &g, int dt_q, const void *q, const float *d, const float *G, const float *vt,
-                   float sI, float sS, int dt_out, void *out, hipStream_t s);
-void launch_interp_f32(const Grid &g, const float *u, const float *d, float *out, hipStream_t s);
+// out = sI * I[q](x + d) + sS * S(x), S = s^{j+1} = -vt . grad_h m^{j+1} (FP32)
+void launch_sl_inc(const Grid &g, int dt_q, const void *q, const float *d, const int *boxes, const float *S, float sI,
+                   float sS, int dt_out, void *out, hipStream_t s);
+// boxes: scratch of tile_box_ints(g) ints (filled here from d)
+void launch_interp_f32(const Grid &g, const float *u, const float *d, int *boxes, float *out, hipStream_t s);
 
 // stencils (k_stencil.hip)
 void launch_fd_grad(const Grid &g, const float *u, float *out3, hipStream_t s);
@@ -118,8 +123,10 @@ struct StateGradArgs {
     float *G[MAX_T];
 };
 void launch_state_grad(const Grid &g, int dt_m, const StateGradArgs &a, int count, hipStream_t s);
-// q0 = scale * (-vt . G^0)
-void launch_inc_init(const Grid &g, const float *G0, const float *vt, float scale, int dt_q, void *q0, hipStream_t s);
+// incremental sources s^j = -vt . G^j (G^j = G + 3 N j): q0 = scale * s^0
+// (stored as dt_q) and S + N (j - 1) = s^j for j = 1..nt (FP32)
+void launch_inc_sources(const Grid &g, const float *G, const float *vt, int nt, float scale, int dt_q, void *q0,
+                        float *S, hipStream_t s);
 struct QuadArgs {
     const void *lam[MAX_T];
     const float *G[MAX_T];

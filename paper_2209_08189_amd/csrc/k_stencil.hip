@@ -62,20 +62,34 @@ __global__ __launch_bounds__(TPB) void k_state_grad(Grid g, StateGradArgs a)
     G[2 * (size_t)g.N + p] = gr[2];
 }
 
-// q0 = scale * (-vt . G^0), four nodes per thread
+// incremental sources s^j = -vt . G^j for j = 0..nt, four nodes per thread:
+// q0 = scale * s^0, S_j = s^j (j >= 1).  vt is read once for all times.
 template <typename Tq>
-__global__ __launch_bounds__(TPB) void k_inc_init(Grid g, const float *__restrict__ G0, const float *__restrict__ vt,
-                                                  float scale, Tq *__restrict__ q0)
+__global__ __launch_bounds__(TPB) void k_inc_sources(Grid g, const float *__restrict__ G, const float *__restrict__ vt,
+                                                     int nt, float scale, Tq *__restrict__ q0, float *__restrict__ S)
 {
     const size_t N = g.N;
     const int p = (blockIdx.x * TPB + threadIdx.x) * 4;
     if (p >= g.N) return;
     const float4 v0 = *(const float4 *)(vt + p), v1 = *(const float4 *)(vt + N + p), v2 = *(const float4 *)(vt + 2 * N + p);
-    const float4 g0 = *(const float4 *)(G0 + p), g1 = *(const float4 *)(G0 + N + p), g2 = *(const float4 *)(G0 + 2 * N + p);
-    stf(q0 + p + 0, -scale * (v0.x * g0.x + v1.x * g1.x + v2.x * g2.x));
-    stf(q0 + p + 1, -scale * (v0.y * g0.y + v1.y * g1.y + v2.y * g2.y));
-    stf(q0 + p + 2, -scale * (v0.z * g0.z + v1.z * g1.z + v2.z * g2.z));
-    stf(q0 + p + 3, -scale * (v0.w * g0.w + v1.w * g1.w + v2.w * g2.w));
+    for (int t = 0; t <= nt; ++t) {
+        const float *Gt = G + 3 * N * t;
+        const float4 g0 = *(const float4 *)(Gt + p), g1 = *(const float4 *)(Gt + N + p),
+                     g2 = *(const float4 *)(Gt + 2 * N + p);
+        float4 r;
+        r.x = -(v0.x * g0.x + v1.x * g1.x + v2.x * g2.x);
+        r.y = -(v0.y * g0.y + v1.y * g1.y + v2.y * g2.y);
+        r.z = -(v0.z * g0.z + v1.z * g1.z + v2.z * g2.z);
+        r.w = -(v0.w * g0.w + v1.w * g1.w + v2.w * g2.w);
+        if (t == 0) {
+            stf(q0 + p + 0, scale * r.x);
+            stf(q0 + p + 1, scale * r.y);
+            stf(q0 + p + 2, scale * r.z);
+            stf(q0 + p + 3, scale * r.w);
+        } else {
+            *(float4 *)(S + N * (t - 1) + p) = r;
+        }
+    }
 }
 
 template <typename T> __device__ __forceinline__ float4 ld4(const T *p)
@@ -149,12 +163,13 @@ void launch_state_grad(const Grid &g, int dt_m, const StateGradArgs &a, int coun
     });
 }
 
-void launch_inc_init(const Grid &g, const float *G0, const float *vt, float scale, int dt_q, void *q0, hipStream_t s)
+void launch_inc_sources(const Grid &g, const float *G, const float *vt, int nt, float scale, int dt_q, void *q0,
+                        float *S, hipStream_t s)
 {
     with_dtype(dt_q, [&](auto tq) {
         using Tq = decltype(tq);
-        hipLaunchKernelGGL((k_inc_init<Tq>), dim3((g.N / 4 + TPB - 1) / TPB), dim3(TPB), 0, s, g, G0, vt, scale,
-                           (Tq *)q0);
+        hipLaunchKernelGGL((k_inc_sources<Tq>), dim3((g.N / 4 + TPB - 1) / TPB), dim3(TPB), 0, s, g, G, vt, nt, scale,
+                           (Tq *)q0, S);
     });
 }
 

@@ -150,22 +150,18 @@ __global__ __launch_bounds__(TPB) void k_feet(Grid g, float dt, const float *__r
 
 // ------------------------------------------------ semi-Lagrangian steps
 // One SL step gathers u at the feet of every node and applies a mode-specific
-// epilogue:
+// epilogue with one per-node operand e:
 //   SL_STATE:  out = I[u](X)
-//   SL_ADJ:    out = c * I[u](X)                    (adjoint divergence factor)
-//   SL_INC:    out = sI * I[u](X) + sS * (-vt . G)  (incremental source,
-//              G = grad_h m^{j+1} precomputed once per velocity)
+//   SL_ADJ:    out = e * I[u](X)             (e = c, adjoint divergence factor)
+//   SL_INC:    out = sI * I[u](X) + sS * e   (e = s^{j+1} = -vt . grad_h m^{j+1},
+//                                             incremental source, precomputed)
 enum { SL_STATE = 0, SL_ADJ = 1, SL_INC = 2 };
 
 template <int MODE>
-__device__ __forceinline__ float epilogue(const Grid &g, const SLParams &prm, int p, float val)
+__device__ __forceinline__ float epilogue(const SLParams &prm, float e, float val)
 {
-    if (MODE == SL_ADJ) return prm.c[p] * val;
-    if (MODE == SL_INC) {
-        const size_t N = g.N;
-        const float src = -(prm.vt[p] * prm.G[p] + prm.vt[N + p] * prm.G[N + p] + prm.vt[2 * N + p] * prm.G[2 * N + p]);
-        return prm.sI * val + prm.sS * src;
-    }
+    if (MODE == SL_ADJ) return e * val;
+    if (MODE == SL_INC) return fmaf(prm.sI, val, prm.sS * e);
     return val;
 }
 
@@ -178,22 +174,35 @@ __global__ __launch_bounds__(TPB) void k_sl_node(Grid g, const Tu *__restrict__ 
     if (p >= g.N) return;
     int i, j, k;
     node_of(g, p, i, j, k);
+    const float e = MODE == SL_STATE ? 0.0f : prm.e[p];
     Foot F;
     make_foot(g, i, j, k, d[p], d[g.N + p], d[2 * (size_t)g.N + p], F);
-    stf(out + p, epilogue<MODE>(g, prm, p, gather(u, F)));
+    stf(out + p, epilogue<MODE>(prm, e, gather(u, F)));
 }
 
-// Tiled version: a workgroup owns a TZ x TY x TX tile (x1, x2, x3), finds
-// the bounding box of the 4x4x4 stencils of its feet, stages that box in LDS
-// and gathers from LDS.  For a smooth velocity the feet of a tile form a
-// slightly deformed copy of the tile, so the box is the tile plus a thin
-// shell.  The box is stored with fixed pitches (PZ, PY, PX) so that the 64
-// stencil offsets of a point are compile-time LDS immediates; a tile whose
+// Tiled version: tiles of TZ x TY x TX nodes (x1, x2, x3).  For a smooth
+// velocity the feet of a tile form a slightly deformed copy of the tile, so
+// the 4x4x4 stencils of all its feet lie in a box that is the tile plus a
+// thin shell.  The box of every tile is computed once per velocity and
+// direction (k_tile_boxes); an SL step stages the box in LDS and gathers
+// from LDS.  The box is stored with fixed pitches (PZ, PY, PX) so that the
+// 64 stencil offsets of a point are compile-time LDS immediates; a tile whose
 // box exceeds them gathers straight from global memory instead (same
-// arithmetic, same result).  The kernel is VALU-bound, so the per-point
-// instruction count is what the layout minimises.
+// arithmetic, same result).
+//
+// Bank layout: PX (in 32-bit words) and PY * PX are multiples of 32, so the
+// LDS bank of a lane's stencil element depends only on its x3 position;
+// lanes whose feet fall in different box rows or planes do not collide.
+//
+// Latency: the feet, the epilogue operands and the box (as direct-to-LDS
+// loads: one wave-uniform box row per instruction, lane = column) are all
+// requested before the first wait; several workgroups per CU overlap one
+// another's memory waits with their gathers.
 constexpr int TX = 32, TY = 8, TZ = 8;
-constexpr int PX = 40, PY = 14, PZ = 14;      // box pitches: tile + 3 + slack of 5 / 3 / 3
+constexpr int PY = 12, PZ = 12;               // box pitches: tile + 3 + slack of 1
+// x3 pitch in elements: 64 words for FP32; 16-bit boxes load element pairs
+// from an even start (one-element shift) and use 64 elements (32 words).
+template <typename T> constexpr int box_px() { return sizeof(T) == 4 ? 64 : 64; }
 
 __device__ __forceinline__ int ifloor(float x)
 {
@@ -226,138 +235,272 @@ __device__ __forceinline__ void lagrange4_fast(float f, float w[4])
     w[3] = a * fmaf(f, 1.0f / 6.0f, 1.0f / 6.0f);    //  (f+1)f(f-1)/6
 }
 
-template <typename Tu, typename To, int MODE>
-__global__ __launch_bounds__(TPB, 4) void k_sl_tile(Grid g, const Tu *__restrict__ u, const float *__restrict__ d,
-                                                 SLParams prm, To *__restrict__ out, int ntx, int nty, int nblk)
-{
-    __shared__ Tu box[PZ * PY * PX];
-    __shared__ int red[TPB / 64][6];
-    // Workgroups go round-robin to the 8 XCDs; give each XCD a contiguous
-    // run of tiles so that neighbouring boxes meet in the same L2.
-    const int b = blockIdx.x;
-    const int tile = (nblk & 7) ? b : (b & 7) * (nblk >> 3) + (b >> 3);
-    const int tx = tile % ntx, ty = (tile / ntx) % nty, tz = tile / (ntx * nty);
-    const int lane = threadIdx.x & (TX - 1), row = threadIdx.x / TX;
-    const int i0 = tz * TZ, j = ty * TY + row, k = tx * TX + lane;
-    const int plane = g.n2 << g.l3;
-    const int p0 = ((i0 << g.l2) + j) * g.n3 + k;
-    const size_t N = g.N;
+typedef __attribute__((address_space(3))) void lds_void;
 
-    float d1[TZ], d2[TZ], d3[TZ];
+// Thread layout of the tile kernels: with 256 * SPLIT threads, thread
+// (part, row, lane) owns nodes (i0 + q0 + q, j, k), q < TZ / SPLIT, where
+// q0 = part * TZ / SPLIT.
+struct TileIdx {
+    int tx, ty, tz, lane, row, i0, q0, j, k, p0, plane;
+};
+template <int SPLIT>
+__device__ __forceinline__ TileIdx tile_idx(const Grid &g, int tile, int ntx, int nty)
+{
+    TileIdx t;
+    t.tx = tile % ntx;
+    t.ty = (tile / ntx) % nty;
+    t.tz = tile / (ntx * nty);
+    t.lane = threadIdx.x & (TX - 1);
+    t.row = (threadIdx.x & 255) / TX;
+    t.i0 = t.tz * TZ;
+    t.q0 = SPLIT == 1 ? 0 : (threadIdx.x >> 8) * (TZ / SPLIT);
+    t.j = t.ty * TY + t.row;
+    t.k = t.tx * TX + t.lane;
+    t.plane = g.n2 << g.l3;
+    t.p0 = (((t.i0 + t.q0) << g.l2) + t.j) * g.n3 + t.k;
+    return t;
+}
+
+// Bounding box of the 4x4x4 stencils of the feet of every tile, once per
+// velocity and direction: box[8 tile + 0..2] = origin relative to the tile
+// origin (x1, x2, x3), box[8 tile + 3..5] = extents.  The integer parts are
+// the same clamped floors that the SL kernels use, so every stencil lies
+// inside its box for any finite displacement.
+__global__ __launch_bounds__(TPB) void k_tile_boxes(Grid g, const float *__restrict__ d, int ntx, int nty,
+                                                    int *__restrict__ box)
+{
+    __shared__ int red[TPB / 64][6];
+    const TileIdx t = tile_idx<1>(g, blockIdx.x, ntx, nty);
+    const size_t N = g.N;
     int mn1 = 1 << 30, mx1 = -(1 << 30), mn2 = 1 << 30, mx2 = -(1 << 30), mn3 = 1 << 30, mx3 = -(1 << 30);
 #pragma unroll
     for (int q = 0; q < TZ; ++q) {
-        const int p = p0 + q * plane;
-        d1[q] = d[p];
-        d2[q] = d[N + p];
-        d3[q] = d[2 * N + p];
-        const int b1 = q + ifloor(d1[q]), b2 = ifloor(d2[q]), b3 = ifloor(d3[q]);
+        const int p = t.p0 + q * t.plane;
+        const int b1 = q + ifloor(d[p]), b2 = ifloor(d[N + p]), b3 = ifloor(d[2 * N + p]);
         mn1 = min(mn1, b1); mx1 = max(mx1, b1);
         mn2 = min(mn2, b2); mx2 = max(mx2, b2);
         mn3 = min(mn3, b3); mx3 = max(mx3, b3);
     }
-    // row / lane are constant per thread: add them after the loop
-    mn2 += row; mx2 += row; mn3 += lane; mx3 += lane;
+    mn2 += t.row; mx2 += t.row; mn3 += t.lane; mx3 += t.lane;
     mn1 = wave_min(mn1); mx1 = wave_max(mx1);
     mn2 = wave_min(mn2); mx2 = wave_max(mx2);
     mn3 = wave_min(mn3); mx3 = wave_max(mx3);
-    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wv = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
         red[wv][0] = mn1; red[wv][1] = mx1; red[wv][2] = mn2;
         red[wv][3] = mx2; red[wv][4] = mn3; red[wv][5] = mx3;
     }
     __syncthreads();
-    mn1 = red[0][0]; mx1 = red[0][1]; mn2 = red[0][2]; mx2 = red[0][3]; mn3 = red[0][4]; mx3 = red[0][5];
-#pragma unroll
+    if (threadIdx.x != 0) return;
     for (int w = 1; w < TPB / 64; ++w) {
         mn1 = min(mn1, red[w][0]); mx1 = max(mx1, red[w][1]);
         mn2 = min(mn2, red[w][2]); mx2 = max(mx2, red[w][3]);
         mn3 = min(mn3, red[w][4]); mx3 = max(mx3, red[w][5]);
     }
-    // box origin (stencil starts one node below the floor), extents
-    mn1 -= 1; mn2 -= 1; mn3 -= 1;
-    const int E1 = mx1 + 3 - mn1, E2 = mx2 + 3 - mn2, E3 = mx3 + 3 - mn3;
-    const bool fits = E1 <= PZ && E2 <= PY && E3 <= PX;
+    // the stencil starts one node below the floor and spans 4 nodes
+    int *o = box + 8 * blockIdx.x;
+    o[0] = mn1 - 1; o[1] = mn2 - 1; o[2] = mn3 - 1;
+    o[3] = mx1 - mn1 + 4; o[4] = mx2 - mn2 + 4; o[5] = mx3 - mn3 + 4;
+    o[6] = 0; o[7] = 0;
+}
 
-    if (fits) {
-        // Stage rows (a, bb) of the box: wave wv loads rows bb = wv, wv+4, ...
-        // of two x1 planes per batch, lane c < E3 loads column c.
-        const int l64 = threadIdx.x & 63;
-        const int gi0 = i0 + mn1, gj0 = ty * TY + mn2;
-        const int col = (tx * TX + mn3 + l64) & (g.n3 - 1);
-        const bool act = l64 < E3;
-        for (int a0 = 0; a0 < E1; a0 += 2) {
-            Tu vals[8];
+// Box of one tile as the SL kernels use it.
+struct TileBox {
+    int r1, r2, r3, E1, E2, E3, c0, sh;
+    bool fits;
+};
+template <typename Tu>
+__device__ __forceinline__ TileBox tile_box(const int *__restrict__ boxes, int tile, const TileIdx &t)
+{
+    constexpr int PX = box_px<Tu>();
+    TileBox B;
+    const int *bx = boxes + 8 * tile;
+    B.r1 = bx[0]; B.r2 = bx[1]; B.r3 = bx[2];
+    B.E1 = bx[3]; B.E2 = bx[4]; B.E3 = bx[5];
+    // global x3 index of box column 0; 16-bit boxes start at the even index
+    // at or below it and shift the stencil by the difference
+    B.c0 = t.tx * TX + B.r3;
+    B.sh = sizeof(Tu) == 2 ? (B.c0 & 1) : 0;
+    B.fits = B.E1 <= PZ && B.E2 <= PY && B.E3 + B.sh <= PX;
+    return B;
+}
+
+// SL tile kernel: 512 threads, each owning QT = 4 nodes along x1.
+constexpr int SPLIT = 2, QT = TZ / SPLIT, TPB_SL = 256 * SPLIT;
+
+// Feet and epilogue operand of the QT nodes of this thread.
+template <int MODE>
+__device__ __forceinline__ void load_feet(const Grid &g, const float *__restrict__ d, const SLParams &prm,
+                                          const TileIdx &t, float (&d1)[QT], float (&d2)[QT], float (&d3)[QT],
+                                          float (&e)[QT])
+{
+    const size_t N = g.N;
 #pragma unroll
-            for (int ia = 0; ia < 2; ++ia)
+    for (int q = 0; q < QT; ++q) {
+        const int p = t.p0 + q * t.plane;
+        d1[q] = d[p];
+        d2[q] = d[N + p];
+        d3[q] = d[2 * N + p];
+    }
 #pragma unroll
-                for (int jb = 0; jb < 4; ++jb) {
-                    const int a = a0 + ia, bb = wv + 4 * jb;
-                    if (act && a < E1 && bb < E2)
-                        vals[ia * 4 + jb] =
-                            u[(((gi0 + a) & (g.n1 - 1)) << (g.l2 + g.l3)) + (((gj0 + bb) & (g.n2 - 1)) << g.l3) + col];
-                }
+    for (int q = 0; q < QT; ++q) e[q] = MODE == SL_STATE ? 0.0f : prm.e[t.p0 + q * t.plane];
+}
+
+// Direct-to-LDS staging of a box: wave wv loads box rows (a, bb) with
+// bb = wv, wv + NW, ... (NW waves); lane l loads column l (FP32) or the column pair 2l,
+// 2l+1 (16-bit) into LDS at row start + 4 l bytes; lanes past the row are
+// switched off.  A row wider than one wave's load takes several chunks.
+template <typename Tu>
+__device__ __forceinline__ void stage_box(const Grid &g, const Tu *__restrict__ u, Tu *box, const TileIdx &t,
+                                          const TileBox &B)
+{
+    constexpr int PX = box_px<Tu>();
+    constexpr int EPL = sizeof(Tu) == 2 ? 2 : 1;       // elements per lane
+    constexpr int NCH = (PX + 64 * EPL - 1) / (64 * EPL);
+    constexpr int NW = TPB_SL / 64;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int l64 = threadIdx.x & 63;
+    const int gi0 = t.i0 + B.r1, gj0 = t.ty * TY + B.r2;
+    for (int a = 0; a < B.E1; ++a) {
+        const int ga = ((gi0 + a) & (g.n1 - 1)) << (g.l2 + g.l3);
+        for (int bb = wv; bb < B.E2; bb += NW) {
+            const int rowoff = ga + (((gj0 + bb) & (g.n2 - 1)) << g.l3);
 #pragma unroll
-            for (int ia = 0; ia < 2; ++ia)
-#pragma unroll
-                for (int jb = 0; jb < 4; ++jb) {
-                    const int a = a0 + ia, bb = wv + 4 * jb;
-                    if (act && a < E1 && bb < E2) box[(a * PY + bb) * PX + l64] = vals[ia * 4 + jb];
-                }
+            for (int ch = 0; ch < NCH; ++ch) {
+                const int c = 64 * EPL * ch + EPL * l64;    // box column of this lane's first element
+                if (c < B.E3 + B.sh)
+                    __builtin_amdgcn_global_load_lds((const void *)(u + rowoff + ((B.c0 - B.sh + c) & (g.n3 - 1))),
+                                                     (lds_void *)(box + (a * PY + bb) * PX + 64 * EPL * ch), 4, 0,
+                                                     0);
+            }
         }
-        __syncthreads();
+    }
+}
+
+// LDS loads by 32-bit LDS byte address, converted to float.
+template <typename T> __device__ __forceinline__ float lds_ld(unsigned a);
+template <> __device__ __forceinline__ float lds_ld<float>(unsigned a)
+{
+    return *reinterpret_cast<__attribute__((address_space(3))) const float *>(static_cast<uintptr_t>(a));
+}
+template <> __device__ __forceinline__ float lds_ld<__hip_bfloat16>(unsigned a)
+{
+    const unsigned short h =
+        *reinterpret_cast<__attribute__((address_space(3))) const unsigned short *>(static_cast<uintptr_t>(a));
+    return __uint_as_float(static_cast<unsigned>(h) << 16);
+}
+template <> __device__ __forceinline__ float lds_ld<__half>(unsigned a)
+{
+    const unsigned short h =
+        *reinterpret_cast<__attribute__((address_space(3))) const unsigned short *>(static_cast<uintptr_t>(a));
+    return __half2float(__ushort_as_half(h));
+}
+template <typename T> __device__ __forceinline__ unsigned lds_addr(const T *p)
+{
+    return (unsigned)(uintptr_t)(lds_void *)(p);
+}
+
+// Gather of the QT nodes of this thread from a staged box (or from global
+// memory when the box did not fit) and the epilogue, into res.
+template <typename Tu, int MODE>
+__device__ __forceinline__ void compute_tile(const Grid &g, const Tu *__restrict__ u, const Tu *box, const TileIdx &t,
+                                             const TileBox &B, const float (&d1)[QT], const float (&d2)[QT],
+                                             const float (&d3)[QT], const float (&e)[QT], const SLParams &prm,
+                                             float (&res)[QT])
+{
+    constexpr int PX = box_px<Tu>();
+    if (B.fits) {
 #pragma unroll
-        for (int q = 0; q < TZ; ++q) {
+        for (int q = 0; q < QT; ++q) {
             const float f1 = floorf(d1[q]), f2 = floorf(d2[q]), f3 = floorf(d3[q]);
             float w1[4], w2[4], w3[4];
             lagrange4_fast(d1[q] - f1, w1);
             lagrange4_fast(d2[q] - f2, w2);
             lagrange4_fast(d3[q] - f3, w3);
-            // same clamped integer parts as the bounding box, so the stencil
-            // lies inside the box for any finite displacement
-            const int s1 = q + ifloor(d1[q]) - mn1 - 1;
-            const int s2 = row + ifloor(d2[q]) - mn2 - 1;
-            const int s3 = lane + ifloor(d3[q]) - mn3 - 1;
-            const Tu *bp = box + (s1 * PY + s2) * PX + s3;
+            // same clamped integer parts as the tile box
+            const int s1 = t.q0 + q + ifloor(d1[q]) - 1 - B.r1;
+            const int s2 = t.row + ifloor(d2[q]) - 1 - B.r2;
+            const int s3 = t.lane + ifloor(d3[q]) - 1 - B.r3 + B.sh;
+            const unsigned bp = lds_addr(box) + ((s1 * PY + s2) * PX + s3) * (unsigned)sizeof(Tu);
             float s = 0.0f;
 #pragma unroll
             for (int a = 0; a < 4; ++a) {
+                // one base register per x1 slice: its 16 rows are then
+                // within the 8-bit word offsets of paired LDS reads
+                unsigned ba = bp + a * PY * PX * (unsigned)sizeof(Tu);
+                asm volatile("" : "+v"(ba));
                 float sa = 0.0f;
 #pragma unroll
                 for (int bq = 0; bq < 4; ++bq) {
-                    const Tu *rp = bp + (a * PY + bq) * PX;
-                    float t = w3[0] * ldf(rp);
-                    t = fmaf(w3[1], ldf(rp + 1), t);
-                    t = fmaf(w3[2], ldf(rp + 2), t);
-                    t = fmaf(w3[3], ldf(rp + 3), t);
-                    sa = fmaf(w2[bq], t, sa);
+                    const unsigned rp = ba + bq * PX * (unsigned)sizeof(Tu);
+                    float tt = w3[0] * lds_ld<Tu>(rp);
+                    tt = fmaf(w3[1], lds_ld<Tu>(rp + sizeof(Tu)), tt);
+                    tt = fmaf(w3[2], lds_ld<Tu>(rp + 2 * sizeof(Tu)), tt);
+                    tt = fmaf(w3[3], lds_ld<Tu>(rp + 3 * sizeof(Tu)), tt);
+                    sa = fmaf(w2[bq], tt, sa);
                 }
                 s = fmaf(w1[a], sa, s);
                 __builtin_amdgcn_sched_barrier(0);
             }
-            const int p = p0 + q * plane;
-            stf(out + p, epilogue<MODE>(g, prm, p, s));
+            res[q] = epilogue<MODE>(prm, e[q], s);
             __builtin_amdgcn_sched_barrier(0);
         }
     } else {
-        for (int q = 0; q < TZ; ++q) {
-            const int p = p0 + q * plane;
+#pragma unroll
+        for (int q = 0; q < QT; ++q) {
             Foot F;
-            make_foot(g, i0 + q, j, k, d1[q], d2[q], d3[q], F);
-            stf(out + p, epilogue<MODE>(g, prm, p, gather(u, F)));
+            make_foot(g, t.i0 + t.q0 + q, t.j, t.k, d1[q], d2[q], d3[q], F);
+            res[q] = epilogue<MODE>(prm, e[q], gather(u, F));
         }
     }
 }
 
+template <typename To>
+__device__ __forceinline__ void store_tile(To *__restrict__ out, const TileIdx &t, const float (&res)[QT])
+{
+#pragma unroll
+    for (int q = 0; q < QT; ++q) stf(out + t.p0 + q * t.plane, res[q]);
+}
+
+// One tile per workgroup: the feet, epilogue operands and box of the tile
+// are requested together, then one wait, then the gather.  At most 80 VGPRs
+// (6 waves per SIMD) so that three 512-thread workgroups share a CU; their
+// phases (waiting for memory, gathering) overlap.
+template <typename Tu, typename To, int MODE>
+__global__ __launch_bounds__(TPB_SL, 6) void k_sl_tile(Grid g, const Tu *__restrict__ u, const float *__restrict__ d,
+                                                  SLParams prm, To *__restrict__ out, const int *__restrict__ boxes,
+                                                  int ntx, int nty, int nblk)
+{
+    constexpr int PX = box_px<Tu>();
+    __shared__ __align__(16) Tu box[PZ * PY * PX];
+    // XCD-contiguous tile order (workgroups go round-robin to the 8 XCDs)
+    const int b = blockIdx.x;
+    const int tile = (nblk & 7) ? b : (b & 7) * (nblk >> 3) + (b >> 3);
+    const TileIdx t = tile_idx<SPLIT>(g, tile, ntx, nty);
+    const TileBox B = tile_box<Tu>(boxes, tile, t);
+    float d1[QT], d2[QT], d3[QT], e[QT], r[QT];
+    load_feet<MODE>(g, d, prm, t, d1, d2, d3, e);
+    __builtin_amdgcn_sched_barrier(0);
+    if (B.fits) stage_box(g, u, box, t, B);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    compute_tile<Tu, MODE>(g, u, box, t, B, d1, d2, d3, e, prm, r);
+    store_tile(out, t, r);
+}
+
+inline bool tiled(const Grid &g) { return g.n3 >= TX && g.n2 >= TY && g.n1 >= TZ; }
+
 inline dim3 grid_of(const Grid &g) { return dim3((g.N + TPB - 1) / TPB); }
 
 template <typename Tu, typename To, int MODE>
-void launch_sl(const Grid &g, const Tu *u, const float *d, const SLParams &prm, To *out, hipStream_t s)
+void launch_sl(const Grid &g, const Tu *u, const float *d, const SLParams &prm, To *out, const int *boxes,
+               hipStream_t s)
 {
-    if (g.n3 >= TX && g.n2 >= TY && g.n1 >= TZ) {
+    if (tiled(g)) {
         const int ntx = g.n3 / TX, nty = g.n2 / TY, ntz = g.n1 / TZ;
         const int nblk = ntx * nty * ntz;
-        hipLaunchKernelGGL((k_sl_tile<Tu, To, MODE>), dim3(nblk), dim3(TPB), 0, s, g, u, d, prm, out, ntx, nty, nblk);
+        hipLaunchKernelGGL((k_sl_tile<Tu, To, MODE>), dim3(nblk), dim3(TPB_SL), 0, s, g, u, d, prm, out, boxes, ntx,
+                           nty, nblk);
     } else {
         hipLaunchKernelGGL((k_sl_node<Tu, To, MODE>), grid_of(g), dim3(TPB), 0, s, g, u, d, prm, out);
     }
@@ -371,51 +514,61 @@ void launch_feet(const Grid &g, float dt, const float *v, float *df, float *db, 
     hipLaunchKernelGGL(k_feet, grid_of(g), dim3(TPB), 0, s, g, dt, v, df, db, divv, c);
 }
 
-void launch_sl_state(const Grid &g, int dt_u, const void *u, const float *d, int dt_out, void *out, hipStream_t s)
+size_t tile_box_ints(const Grid &g) { return tiled(g) ? (size_t)8 * (g.N / (TX * TY * TZ)) : 0; }
+
+void launch_tile_boxes(const Grid &g, const float *d, int *boxes, hipStream_t s)
+{
+    if (!tiled(g)) return;
+    const int ntx = g.n3 / TX, nty = g.n2 / TY, ntz = g.n1 / TZ;
+    hipLaunchKernelGGL(k_tile_boxes, dim3(ntx * nty * ntz), dim3(TPB), 0, s, g, d, ntx, nty, boxes);
+}
+
+void launch_sl_state(const Grid &g, int dt_u, const void *u, const float *d, const int *boxes, int dt_out, void *out,
+                     hipStream_t s)
 {
     with_dtype(dt_u, [&](auto tu) {
         using Tu = decltype(tu);
         with_dtype(dt_out, [&](auto to) {
             using To = decltype(to);
-            launch_sl<Tu, To, SL_STATE>(g, (const Tu *)u, d, SLParams{}, (To *)out, s);
+            launch_sl<Tu, To, SL_STATE>(g, (const Tu *)u, d, SLParams{}, (To *)out, boxes, s);
         });
     });
 }
 
-void launch_sl_adjoint(const Grid &g, int dt_u, const void *u, const float *d, const float *c, int dt_out,
-                       void *out, hipStream_t s)
+void launch_sl_adjoint(const Grid &g, int dt_u, const void *u, const float *d, const int *boxes, const float *c,
+                       int dt_out, void *out, hipStream_t s)
 {
     SLParams prm{};
-    prm.c = c;
+    prm.e = c;
     with_dtype(dt_u, [&](auto tu) {
         using Tu = decltype(tu);
         with_dtype(dt_out, [&](auto to) {
             using To = decltype(to);
-            launch_sl<Tu, To, SL_ADJ>(g, (const Tu *)u, d, prm, (To *)out, s);
+            launch_sl<Tu, To, SL_ADJ>(g, (const Tu *)u, d, prm, (To *)out, boxes, s);
         });
     });
 }
 
-void launch_sl_inc(const Grid &g, int dt_q, const void *q, const float *d, const float *G, const float *vt, float sI,
+void launch_sl_inc(const Grid &g, int dt_q, const void *q, const float *d, const int *boxes, const float *S, float sI,
                    float sS, int dt_out, void *out, hipStream_t s)
 {
     SLParams prm{};
-    prm.G = G;
-    prm.vt = vt;
+    prm.e = S;
     prm.sI = sI;
     prm.sS = sS;
     with_dtype(dt_q, [&](auto tq) {
         using Tq = decltype(tq);
         with_dtype(dt_out, [&](auto to) {
             using To = decltype(to);
-            launch_sl<Tq, To, SL_INC>(g, (const Tq *)q, d, prm, (To *)out, s);
+            launch_sl<Tq, To, SL_INC>(g, (const Tq *)q, d, prm, (To *)out, boxes, s);
         });
     });
 }
 
-void launch_interp_f32(const Grid &g, const float *u, const float *d, float *out, hipStream_t s)
+void launch_interp_f32(const Grid &g, const float *u, const float *d, int *boxes, float *out, hipStream_t s)
 {
-    launch_sl<float, float, SL_STATE>(g, u, d, SLParams{}, out, s);
+    launch_tile_boxes(g, d, boxes, s);
+    launch_sl<float, float, SL_STATE>(g, u, d, SLParams{}, out, boxes, s);
 }
 
 } // namespace clh
