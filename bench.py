@@ -74,16 +74,26 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
-    ap.add_argument("--cpu-n", type=int, default=128)
-    ap.add_argument("--learned-train", type=int, default=8, help="training pairs (0 disables the learned leg)")
-    ap.add_argument("--learned-eval", type=int, default=2, help="held-out evaluation pairs")
-    ap.add_argument("--learned-epochs", type=int, default=8)
+    ap.add_argument("--no-mixed", action="store_true", help="skip the 16-bit storage matvec measurement")
+    ap.add_argument("--cpu-matvecs", type=int, default=3, help="oracle matvecs timed for the CPU baseline")
+    ap.add_argument("--max-pcg", type=int, default=40, help="PCG iterations per GN step in the solve legs")
+    ap.add_argument("--learned-train", type=int, default=48, help="training pairs (0 disables the learned leg)")
+    ap.add_argument("--learned-eval", type=int, default=4, help="held-out evaluation pairs")
+    ap.add_argument("--learned-epochs", type=int, default=24)
+    ap.add_argument("--learned-lr", type=float, default=1e-4)
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="also run the library's plain copy kernel on this many MiB (memory-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only; this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
+
+    host = None
+    if args.learned_train > 0 and not args.no_solve:
+        # CPU side of the training / evaluation pairs: worker processes
+        # started before this process touches the GPU
+        from paper_2209_08189_amd import warmstart
+        host = warmstart.HostPairs()
 
     import torch
     from paper_2209_08189_amd.claire import Registration, K_NAMES, K_SL_INC
@@ -159,10 +169,41 @@ def main():
         if name in ALG_F:
             d["alg_GBs"] = ALG_F[name] * F / (d["avg_launch_ms"] * 1e-3) / 1e9
 
+    # the same matvec with 16-bit field storage (images/state FP16,
+    # adjoint/incremental BF16; FP32 arithmetic, FP64 reductions)
+    mixed = None
+    if not args.no_mixed:
+        rm = Registration(shape, nt=4, beta_v=5e-4, gtol=1e-2, max_outer=50, max_pcg=args.max_pcg,
+                          storage_state="f16", storage_adjoint="bf16")
+        rm.set_images(m0, m1)
+        rm.set_velocity(dev(v_true))
+        gm, _, _ = rm.gradient()
+        vtm = -rm.precond(gm)
+        for _ in range(args.warmup):
+            rm.hessian_matvec(vtm, Hv)
+        rm.profile_enable(0xFF)
+        for _ in range(3):
+            rm.hessian_matvec(vtm, Hv)
+        mclass = {}
+        for k, name in enumerate(K_NAMES):
+            ms, cnt = rm.profile_query(k)
+            if cnt:
+                mclass[name] = {"ms_per_matvec": ms / 3, "avg_launch_ms": ms / cnt}
+        rm.profile_enable(0)
+        torch.cuda.synchronize()
+        tm0 = time.perf_counter()
+        for _ in range(args.steps):
+            rm.hessian_matvec(vtm, Hv)
+        torch.cuda.synchronize()
+        tm = time.perf_counter() - tm0
+        mixed = {"matvecs_per_s": args.steps / tm, "storage": "state f16, adjoint bf16", "kernels": mclass}
+        log("mixed-storage matvec %.3f ms (%.1f matvecs/s)" % (1e3 * tm / args.steps, args.steps / tm))
+        del rm
+
     # plain FP32 GN solve to relative gradient 1e-2 from v = 0
     solve = None
     if not args.no_solve:
-        rs = Registration(shape, nt=4, beta_v=5e-4, gtol=1e-2, max_outer=50, max_pcg=10)
+        rs = Registration(shape, nt=4, beta_v=5e-4, gtol=1e-2, max_outer=50, max_pcg=args.max_pcg)
         rs.set_images(m0, m1)
         rs.set_velocity(torch.zeros((3,) + shape, device="cuda"))
         torch.cuda.synchronize()
@@ -185,22 +226,29 @@ def main():
             tl = time.perf_counter()
             train_seeds = list(range(1000, 1000 + args.learned_train))
             eval_seeds = list(range(10000, 10000 + args.learned_eval))
-            data = warmstart.generate(train_seeds, n=n, n_net=n // 2, log=log)
-            net = Net(in_n=n // 2, seed=1, lr=1e-3)
+            data = warmstart.generate(train_seeds, n=n, n_net=n // 2, log=log, host=host, max_pcg=args.max_pcg)
+            net = Net(in_n=n // 2, seed=1, lr=args.learned_lr)
             t_train = time.perf_counter()
             hist = warmstart.train(net, data, args.learned_epochs, log=log)
             t_train = time.perf_counter() - t_train
             del data
-            rows = warmstart.evaluate(net, eval_seeds, n=n, storage=("f16", "bf16"), log=log)
+            rows = warmstart.evaluate(net, eval_seeds, n=n, storage=("f16", "bf16"), log=log, host=host,
+                                      max_pcg=args.max_pcg)
             learned = {
                 "train_pairs": len(train_seeds), "eval_pairs": len(eval_seeds), "epochs": args.learned_epochs,
+                "lr": args.learned_lr,
                 "net_grid": n // 2, "train_seconds": t_train, "loss_first": hist[0], "loss_last": hist[-1],
+                "max_pcg": args.max_pcg,
                 "plain_fp32_time_to_tol_s": float(np.mean([r["plain_s"] for r in rows])),
+                "mixed_only_time_to_tol_s": float(np.mean([r["mixed_s"] for r in rows])),
+                "learned_fp32_time_to_tol_s": float(np.mean([r["learned_f32_s"] for r in rows])),
                 "learned_mixed_time_to_tol_s": float(np.mean([r["learned_s"] for r in rows])),
                 "plain_gn_iters": float(np.mean([r["plain_gn"] for r in rows])),
                 "learned_gn_iters": float(np.mean([r["learned_gn"] for r in rows])),
+                "initial_rel_velocity_error": float(np.mean([r["pred_rel_err"] for r in rows])),
                 "prediction_used_frac": float(np.mean([r["used_prediction"] for r in rows])),
                 "max_rel_mismatch_diff": float(np.max([r["rel_mismatch_diff"] for r in rows])),
+                "max_abs_diff_relative_mismatch": float(np.max([r["abs_diff_r"] for r in rows])),
                 "storage": "images/state f16, adjoint/incremental bf16, FP32 arithmetic, FP64 reductions",
                 "rows": rows, "wall_s": time.perf_counter() - tl,
             }
@@ -208,33 +256,35 @@ def main():
         except Exception as e:   # report, do not lose the benchmark line
             learned = {"error": repr(e)}
             log("learned leg failed: %r" % (e,))
+        finally:
+            host.close()
 
     cpu = None
     if not args.no_cpu_baseline:
+        # the FP64 oracle on the same workload (same phantom pair, v = v_true,
+        # vt = -P^-1 g), timed over a few matvecs on the host cores
         import oracle
-        cn = args.cpu_n
-        cshape = (cn, cn, cn)
-        cimg, _, cv, c0, c1 = make_inputs(cn, args.seed)
-        o = oracle.Oracle(cshape, nt=4, beta=5e-4)
-        o.set_images(cimg, cimg)
-        o.set_velocity(cv)
+        o = oracle.Oracle(shape, nt=4, beta=5e-4)
+        o.set_images(img, img)
+        o.set_velocity(v_true)
         o.state()
-        cm1 = o.field(oracle.FIELD_STATE, 4) + c1
-        o.set_images(cimg + c0, cm1)
-        o.set_velocity(cv)
+        cm1 = o.field(oracle.FIELD_STATE, 4) + n1
+        o.set_images(img + n0, cm1)
+        o.set_velocity(v_true)
         cg, _ = o.gradient()
         cvt = -o.precond(cg)
         tc = time.perf_counter()
-        o.matvec(cvt)
+        for _ in range(args.cpu_matvecs):
+            o.matvec(cvt)
         tc = time.perf_counter() - tc
-        scale = (n / cn) ** 3
-        cpu = {"value": 1.0 / (tc * scale), "unit": "matvecs/s", "cores": oracle.num_threads(), "kind": "oracle",
-               "sample": "one FP64 oracle Hessian matvec at %d^3 (%.1f s), scaled by the voxel ratio %.0f to %d^3"
-                         % (cn, tc, scale, n)}
+        cpu = {"value": args.cpu_matvecs / tc, "unit": "matvecs/s", "cores": oracle.num_threads(), "kind": "oracle",
+               "sample": "%d FP64 oracle Hessian matvecs on the same %d^3 workload (%.1f s)"
+                         % (args.cpu_matvecs, n, tc)}
         log("cpu oracle: %s" % json.dumps(cpu))
+        del o
 
     out = {
-        "metric": "Hessian matvecs/s at 256^3 (GN-Krylov registration, nt=4, tricubic SL, FP32)",
+        "metric": "Hessian matvecs/s at 256^3; time-to-tol learned+mixed vs plain (same GPU)",
         "value": value,
         "unit": "matvecs/s",
         "n_gpus": 1,
@@ -253,6 +303,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom),
                      "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": avg_ms, "launches": dom_n},
         "kernels": per_class,
+        "mixed_storage_matvec": mixed,
         "solve_fp32": solve,
         "learned_warm_start": learned,
         "cpu_baseline": cpu,

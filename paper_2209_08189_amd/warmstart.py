@@ -12,6 +12,8 @@ Time-to-tolerance is wall time from images resident on the device to
 ||g|| <= gtol ||g(v = 0)|| for both runs; the learned run includes
 restriction, inference, prolongation and the fallback test.
 """
+import multiprocessing
+import os
 import time
 
 import numpy as np
@@ -25,23 +27,73 @@ def _dev(a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
 
 
-def make_pair(n, seed, max_disp=6.0):
-    """Phantom pair on an n^3 grid.  Returns device tensors (m0, m1) and the
-    labels of the clean phantom (host)."""
+def host_pair(n, seed, max_disp=6.0):
+    """CPU side of a phantom pair: (phantom, labels, v_true, noise of m0,
+    noise of m1), FP32 except the labels."""
     shape = (n, n, n)
     img, labels = synth.phantom(shape, seed)
     v_true = synth.smooth_velocity(shape, seed + 1, kmax=8.0, max_disp_voxels=max_disp)
-    reg = Registration(shape)
+    return (img.astype(np.float32), labels, v_true.astype(np.float32),
+            synth.noise(shape, seed + 2, 0.02).astype(np.float32),
+            synth.noise(shape, seed + 3, 0.02).astype(np.float32))
+
+
+def _host_pair_job(args):
+    return host_pair(*args)
+
+
+def _pool_init():
+    synth.FFT_WORKERS = 1
+
+
+class HostPairs:
+    """Process pool that generates the CPU side of phantom pairs.  Create it
+    before the process touches the GPU (the workers are separate interpreters
+    started by the spawn method); each worker is single-threaded."""
+
+    def __init__(self, procs=None):
+        procs = procs or max(1, min(16, (os.cpu_count() or 2) - 1))
+        saved = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS")}
+        os.environ["OMP_NUM_THREADS"] = os.environ["OPENBLAS_NUM_THREADS"] = "1"
+        try:
+            self.pool = multiprocessing.get_context("spawn").Pool(procs, initializer=_pool_init)
+        finally:
+            for k, v in saved.items():
+                if v is None:
+                    os.environ.pop(k, None)
+                else:
+                    os.environ[k] = v
+
+    def pairs(self, n, seeds):
+        return self.pool.imap(_host_pair_job, [(n, s) for s in seeds])
+
+    def close(self):
+        self.pool.close()
+        self.pool.join()
+
+
+def device_pair(host):
+    """Device images (m0, m1) from host_pair(): m0 = phantom + noise, m1 =
+    phantom transported by v_true (forward SL solve on the GPU) + noise."""
+    img, labels, v_true, n0, n1 = host
+    n = img.shape[0]
+    reg = Registration((n, n, n))
     ph = _dev(img)
     reg.set_images(ph, ph)
     reg.set_velocity(_dev(v_true))
-    m1 = reg.deformed_template() + _dev(synth.noise(shape, seed + 3, 0.02))
-    m0 = ph + _dev(synth.noise(shape, seed + 2, 0.02))
+    m1 = reg.deformed_template() + _dev(n1)
+    m0 = ph + _dev(n0)
     reg.close()
     return m0, m1, labels
 
 
-def solve(m0, m1, storage=("f32", "f32"), gtol=1e-2, net=None, max_outer=50, max_pcg=10):
+def make_pair(n, seed, max_disp=6.0):
+    """Phantom pair on an n^3 grid: device tensors (m0, m1) and the labels of
+    the clean phantom (host)."""
+    return device_pair(host_pair(n, seed, max_disp))
+
+
+def solve(m0, m1, storage=("f32", "f32"), gtol=1e-2, net=None, max_outer=50, max_pcg=40):
     """Gauss-Newton solve from v = 0 (or from the network's warm start).
     Returns (report dict, final velocity tensor, seconds)."""
     import torch
@@ -63,18 +115,30 @@ def solve(m0, m1, storage=("f32", "f32"), gtol=1e-2, net=None, max_outer=50, max
     return rep, v, dt
 
 
-def generate(seeds, n=256, n_net=128, log=None):
+def generate(seeds, n=256, n_net=128, log=None, host=None, max_pcg=40):
     """Training data on the network grid: list of (m0, m1, v_label) device
-    tensors restricted from n^3 solves."""
+    tensors restricted from n^3 solves.  host: a HostPairs pool (optional)."""
     down = Resampler((n,) * 3, (n_net,) * 3)
     data = []
-    for s in seeds:
-        m0, m1, _ = make_pair(n, s)
-        rep, v, dt = solve(m0, m1)
+    src = host.pairs(n, seeds) if host else (host_pair(n, s) for s in seeds)
+    for s, hp in zip(seeds, src):
+        m0, m1, _ = device_pair(hp)
+        del hp
+        rep, v, dt = solve(m0, m1, max_pcg=max_pcg)
         data.append((down(m0), down(m1), down(v)))
         if log:
             log("label seed %d: %d GN, %d PCG, %.2f s" % (s, rep["outer_iters"], rep["pcg_iters_total"], dt))
     return data
+
+
+def predict(net, m0, m1):
+    """The network's velocity on the grid of (m0, m1): restriction to the
+    network grid, inference, spectral prolongation."""
+    n = m0.shape[0]
+    nn = net.n
+    down = Resampler((n,) * 3, (nn,) * 3)
+    up = Resampler((nn,) * 3, (n,) * 3)
+    return up(net.forward(down(m0), down(m1)))
 
 
 def train(net, data, epochs, batch=1, log=None, seed=0):
@@ -97,22 +161,39 @@ def train(net, data, epochs, batch=1, log=None, seed=0):
     return hist
 
 
-def evaluate(net, seeds, n=256, storage=("f16", "bf16"), log=None):
-    """Per held-out seed: plain FP32 solve from v = 0 versus warm start +
-    mixed-precision storage.  Returns a list of dicts."""
+def evaluate(net, seeds, n=256, storage=("f16", "bf16"), log=None, host=None, max_pcg=40):
+    """Per held-out seed: plain FP32 solve from v = 0, mixed-precision storage
+    from v = 0, warm start in FP32, and warm start + mixed storage.  Returns a
+    list of dicts (times in seconds, GN iterations, mismatches, and the
+    relative L2 error of the network's prediction against the plain
+    solution)."""
     rows = []
-    for s in seeds:
-        m0, m1, _ = make_pair(n, s)
-        rp, vp, tp = solve(m0, m1)
-        rl, vl, tl = solve(m0, m1, storage=storage, net=net)
+    src = host.pairs(n, seeds) if host else (host_pair(n, s) for s in seeds)
+    for s, hp in zip(seeds, src):
+        m0, m1, _ = device_pair(hp)
+        del hp
+        mis0 = 0.5 * float(((m0 - m1).double() ** 2).sum()) * (2.0 * np.pi / n) ** 3
+        rp, vp, tp = solve(m0, m1, max_pcg=max_pcg)
+        rm, _, tm = solve(m0, m1, storage=storage, max_pcg=max_pcg)
+        rf, _, tf = solve(m0, m1, net=net, max_pcg=max_pcg)
+        rl, vl, tl = solve(m0, m1, storage=storage, net=net, max_pcg=max_pcg)
+        pred = predict(net, m0, m1)
+        err = float((pred - vp).norm() / vp.norm())
         row = {"seed": s, "plain_s": tp, "plain_gn": rp["outer_iters"], "plain_pcg": rp["pcg_iters_total"],
+               "mixed_s": tm, "mixed_gn": rm["outer_iters"], "learned_f32_s": tf, "learned_f32_gn": rf["outer_iters"],
+               "pred_rel_err": err,
                "plain_mismatch": rp["mismatch"], "learned_s": tl, "learned_gn": rl["outer_iters"],
                "learned_pcg": rl["pcg_iters_total"], "learned_mismatch": rl["mismatch"],
                "used_prediction": rl["warm_start_used"],
                "rel_mismatch_diff": abs(rl["mismatch"] - rp["mismatch"]) / rp["mismatch"],
+               # relative mismatch r = mismatch / mismatch at v = 0 (the
+               # convention of the paper's tables); absolute difference in r
+               "abs_diff_r": abs(rl["mismatch"] - rp["mismatch"]) / mis0,
                "status_plain": rp["status_name"], "status_learned": rl["status_name"]}
         rows.append(row)
         if log:
-            log("eval seed %d: plain %.2f s (%d GN), learned+mixed %.2f s (%d GN, used=%s), mismatch diff %.2e"
-                % (s, tp, rp["outer_iters"], tl, rl["outer_iters"], row["used_prediction"], row["rel_mismatch_diff"]))
+            log("eval seed %d: plain %.2f s (%d GN), mixed %.2f s (%d GN), learned %.2f s (%d GN), learned+mixed "
+                "%.2f s (%d GN, used=%s), prediction error %.3f, mismatch diff %.2e (in r: %.2e)"
+                % (s, tp, rp["outer_iters"], tm, rm["outer_iters"], tf, rf["outer_iters"], tl, rl["outer_iters"],
+                   row["used_prediction"], err, row["rel_mismatch_diff"], row["abs_diff_r"]))
     return rows
