@@ -150,3 +150,29 @@ def test_warm_start_falls_back_when_no_gain():
     used, Jp, J0 = warm_start(reg, net)
     assert not used and Jp == J0
     assert float(torch.abs(reg.velocity()).max()) == 0.0
+
+
+def test_trained_network_gains_over_zero_start():
+    """What training buys: a network trained on pairs labelled by the plain
+    solver (128^3 registrations, 64^3 network, 16 pairs, 40 epochs) predicts
+    held-out velocities that lower the objective below J(0) (so the warm
+    start is taken), and the warm-started solves need no more GN iterations
+    in total than the solves from v = 0 while ending at the same relative
+    mismatch.  Observed: loss 3.0e-4 -> 6.3e-5, prediction error 0.48-0.57,
+    GN iterations 16 -> 14, |dr| <= 3.8e-4."""
+    from paper_2209_08189_amd import warmstart
+    from paper_2209_08189_amd.claire import Net
+    data = warmstart.generate(list(range(500, 516)), n=128, n_net=64)
+    net = Net(in_n=64, seed=1, lr=3e-4)
+    hist = warmstart.train(net, data, 40)
+    rows = warmstart.evaluate(net, [900, 901, 902], n=128)
+    plain = sum(r["plain_gn"] for r in rows)
+    learned = sum(r["learned_f32_gn"] for r in rows)
+    print("loss %.3e -> %.3e; GN plain %d learned %d; prediction error %s; |dr| %s"
+          % (hist[0], hist[-1], plain, learned, [round(r["pred_rel_err"], 3) for r in rows],
+             ["%.1e" % r["abs_diff_r"] for r in rows]))
+    assert hist[-1] < 0.5 * hist[0]
+    assert all(r["used_prediction"] for r in rows)
+    assert all(r["pred_rel_err"] < 0.8 for r in rows)
+    assert learned <= plain
+    assert all(r["abs_diff_r"] < 1e-3 for r in rows)
