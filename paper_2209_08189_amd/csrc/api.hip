@@ -55,6 +55,9 @@ struct cl_ctx {
     float *grad = nullptr, *Av = nullptr, *tmp3 = nullptr;  // 3N
     float *px = nullptr, *pr = nullptr, *pz = nullptr, *pp = nullptr, *pHp = nullptr;  // 3N
     double *partials = nullptr, *dscal = nullptr, *hscal = nullptr;
+    double *qparts = nullptr;                // partials of the fused PCG reductions
+    int nqparts = 1;
+    double *pscal = nullptr;                 // PCG device scalars (PCG_* slots)
     int nparts = 1;
     FFTPlan fft{};
 
@@ -311,7 +314,9 @@ double gradient(cl_ctx *ctx, double *J, double *mis_out, double *reg_out)
 
 // GN Hessian matvec (incremental state, incremental adjoint, quadrature,
 // beta A vt); needs feet of both directions and the state of the current v.
-void matvec(cl_ctx *ctx, const float *vt, float *Hvt, const float *Avt_known = nullptr)
+// dot_out (device, optional): <vt, Hvt> (weighted by h1 h2 h3), fused into
+// the quadrature that produces Hvt.
+void matvec(cl_ctx *ctx, const float *vt, float *Hvt, const float *Avt_known = nullptr, double *dot_out = nullptr)
 {
     ensure_feet(ctx, true);
     ensure_sgrad(ctx);
@@ -336,7 +341,14 @@ void matvec(cl_ctx *ctx, const float *vt, float *Hvt, const float *Avt_known = n
         Avt = ctx->tmp3;
     }
     const QuadArgs qa = quad_args(ctx);
-    run(ctx, CL_K_QUAD, [&] { launch_quadrature(ctx->g, ctx->dta, qa, Avt, Hvt, ctx->s); });
+    if (dot_out) {
+        run(ctx, CL_K_QUAD, [&] {
+            launch_quadrature_dot(ctx->g, ctx->dta, qa, Avt, Hvt, vt, ctx->qparts, ctx->s);
+            launch_finalize(ctx->qparts, quadrature_blocks(ctx->g), ctx->hv, dot_out, ctx->s);
+        });
+    } else {
+        run(ctx, CL_K_QUAD, [&] { launch_quadrature(ctx->g, ctx->dta, qa, Avt, Hvt, ctx->s); });
+    }
 }
 
 void precond(cl_ctx *ctx, const float *r, float *z) { spectral(ctx, 1, 3, r, z, nullptr); }
@@ -351,11 +363,19 @@ void load_velocity(cl_ctx *ctx, const float *src_dev)
 // PCG on H x = rhs (rhs in ctx->pr on entry); solution in ctx->px.
 int pcg(cl_ctx *ctx, int max_pcg, double eta, int forced, int *iters)
 {
+    // Scalars stay on the device (PCG_* slots of pscal): alpha, beta and the
+    // curvature test are formed there, and the host reads ||r|| and the
+    // curvature flag once per iteration for the stopping test.
     const size_t n = 3 * ctx->N;
+    double *sc = ctx->pscal;
+    const int nbc = reduce_blocks(ctx->N);
     run(ctx, CL_K_VEC, [&] { launch_fill_f32(ctx->px, 0.0f, n, ctx->s); });
     precond(ctx, ctx->pr, ctx->pz);
     HIPCHK(hipMemcpyAsync(ctx->pp, ctx->pz, n * sizeof(float), hipMemcpyDeviceToDevice, ctx->s));
-    double rz = dotw(ctx, ctx->pr, ctx->pz, n);
+    run(ctx, CL_K_VEC, [&] {
+        launch_dot(ctx->pr, ctx->pz, n, ctx->partials, ctx->nparts, ctx->s);
+        launch_finalize(ctx->partials, ctx->nparts, ctx->hv, sc + PCG_RZ, ctx->s);
+    });
     const double r0 = std::sqrt(dotw(ctx, ctx->pr, ctx->pr, n));
     // beta A p by recurrence: p = z + b p and beta A z = r - mean(r) (A has
     // no k = 0 mode, the preconditioner maps it by 1/beta), so the matvecs
@@ -363,37 +383,34 @@ int pcg(cl_ctx *ctx, int max_pcg, double eta, int forced, int *iters)
     float *pAp = ctx->tmp3;
     run(ctx, CL_K_VEC, [&] {
         launch_fill_f32(pAp, 0.0f, n, ctx->s);
-        launch_comp_sums3(ctx->pr, ctx->N, ctx->partials, ctx->nparts / 3, ctx->dscal + 1, ctx->s);
-        launch_mean_free_axpy(pAp, ctx->pr, ctx->dscal + 1, 0.0f, ctx->N, ctx->s);
+        launch_comp_sums3(ctx->pr, ctx->N, ctx->partials, ctx->nparts / 3, sc + PCG_SUMR, ctx->s);
+        launch_mean_free_axpy(pAp, ctx->pr, sc + PCG_SUMR, 0.0f, ctx->N, ctx->s);
     });
     const int limit = forced >= 0 ? forced : max_pcg;
     int it = 0, neg = 0;
     while (it < limit) {
-        matvec(ctx, ctx->pp, ctx->pHp, pAp);
-        const double pHp = dotw(ctx, ctx->pp, ctx->pHp, n);
-        if (!(pHp > 0.0)) {
+        matvec(ctx, ctx->pp, ctx->pHp, pAp, sc + PCG_PHP);
+        run(ctx, CL_K_VEC, [&] {
+            launch_pcg_alpha(sc, ctx->s);
+            launch_pcg_update3(ctx->px, ctx->pr, ctx->pp, ctx->pHp, sc, ctx->N, ctx->qparts, nbc, ctx->hv, ctx->s);
+        });
+        HIPCHK(hipMemcpyAsync(ctx->hscal, sc, sizeof(double) * PCG_NSCAL, hipMemcpyDeviceToHost, ctx->s));
+        HIPCHK(hipStreamSynchronize(ctx->s));
+        if (ctx->hscal[PCG_NEG] != 0.0) {
             neg = 1;
             if (it == 0) HIPCHK(hipMemcpyAsync(ctx->px, ctx->pz, n * sizeof(float), hipMemcpyDeviceToDevice, ctx->s));
             break;
         }
-        const double alpha = rz / pHp;
-        run(ctx, CL_K_VEC, [&] {
-            launch_pcg_update(ctx->px, ctx->pr, ctx->pp, ctx->pHp, (float)alpha, n, ctx->partials, ctx->nparts,
-                              ctx->s);
-            launch_finalize(ctx->partials, ctx->nparts, ctx->hv, ctx->dscal, ctx->s);
-        });
-        const double rn = std::sqrt(read_scalar(ctx));
+        const double rn = std::sqrt(ctx->hscal[PCG_RR]);
         ++it;
         if (forced < 0 && rn <= eta * r0) break;
         if (it >= limit) break;
         precond(ctx, ctx->pr, ctx->pz);
-        const double rz_new = dotw(ctx, ctx->pr, ctx->pz, n);
-        const double bt = rz_new / rz;
-        rz = rz_new;
         run(ctx, CL_K_VEC, [&] {
-            launch_axpy(ctx->pp, ctx->pz, ctx->pp, (float)bt, n, ctx->s);
-            launch_comp_sums3(ctx->pr, ctx->N, ctx->partials, ctx->nparts / 3, ctx->dscal + 1, ctx->s);
-            launch_mean_free_axpy(pAp, ctx->pr, ctx->dscal + 1, (float)bt, ctx->N, ctx->s);
+            launch_dot(ctx->pr, ctx->pz, n, ctx->partials, ctx->nparts, ctx->s);
+            launch_finalize(ctx->partials, ctx->nparts, ctx->hv, sc + PCG_RZNEW, ctx->s);
+            launch_pcg_beta(sc, ctx->s);
+            launch_pcg_direction(ctx->pp, pAp, ctx->pz, ctx->pr, sc, ctx->N, ctx->s);
         });
     }
     if (iters) *iters = it;
@@ -637,7 +654,10 @@ int cl_create(cl_ctx **out, int n1, int n2, int n3, const cl_options *opt)
         ctx->nparts = reduce_blocks(3 * N);
         ctx->partials = (double *)alloc(ctx->nparts * sizeof(double));
         ctx->dscal = (double *)alloc(sizeof(double) * 4);
-        if (hipHostMalloc((void **)&ctx->hscal, sizeof(double) * 4, hipHostMallocDefault) != hipSuccess)
+        ctx->nqparts = std::max(quadrature_blocks(ctx->g), 6 * reduce_blocks(ctx->N));
+        ctx->qparts = (double *)alloc(sizeof(double) * ctx->nqparts);
+        ctx->pscal = (double *)alloc(sizeof(double) * PCG_NSCAL);
+        if (hipHostMalloc((void **)&ctx->hscal, sizeof(double) * PCG_NSCAL, hipHostMallocDefault) != hipSuccess)
             throw Fail{CL_ERR_OOM};
         try {
             fft_plan_init(ctx->fft, n1, n2, n3, 3, alloc);

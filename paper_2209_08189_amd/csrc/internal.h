@@ -135,6 +135,10 @@ struct QuadArgs {
 };
 // out3 = addend3 (may be NULL) + sum_j w_j lam^j G^j
 void launch_quadrature(const Grid &g, int dt_lam, const QuadArgs &qa, const float *addend3, float *out3, hipStream_t s);
+// same, and per-block FP64 partial sums of dp . out3 in partials[0 .. quadrature_blocks(g))
+int quadrature_blocks(const Grid &g);
+void launch_quadrature_dot(const Grid &g, int dt_lam, const QuadArgs &qa, const float *addend3, float *out3,
+                           const float *dp, double *partials, hipStream_t s);
 // lam = m1 - mN (stored as dt_lam); partial sums of (m1 - mN)^2 per block
 void launch_residual(const Grid &g, int dt_m, const void *m1, const void *mN, int dt_lam, void *lam,
                      double *partials, int nblocks, hipStream_t s);
@@ -147,6 +151,19 @@ void launch_dot(const float *a, const float *b, size_t n, double *partials, int 
 void launch_finalize(const double *partials, int nblocks, double scale, double *out, hipStream_t s);
 void launch_count_nonfinite(const float *a, size_t n, double *partials, int nblocks, hipStream_t s);
 // x += alpha p; r -= alpha Hp; partials of r.r
+// Fused PCG: FP64 device scalars sc[PCG_*]
+enum { PCG_RR = 0, PCG_SUMR = 1, PCG_PHP = 4, PCG_RZ = 5, PCG_RZNEW = 6, PCG_ALPHA = 7, PCG_BETA = 8, PCG_NEG = 9,
+       PCG_NSCAL = 16 };
+void launch_pcg_alpha(double *sc, hipStream_t s);
+void launch_pcg_beta(double *sc, hipStream_t s);
+// x += alpha p, r -= alpha Hp (nothing when alpha = 0); sc[PCG_RR] = rscale
+// ||r||^2, sc[PCG_SUMR + c] = sum of component c; partials needs 6 nblocks
+// entries
+void launch_pcg_update3(float *x, float *r, const float *p, const float *Hp, double *sc, size_t n, double *partials,
+                        int nblocks, double rscale, hipStream_t s);
+// p = z + beta p, q = (r - mean r) + beta q (beta, means from sc)
+void launch_pcg_direction(float *p, float *q, const float *z, const float *r, const double *sc, size_t n,
+                          hipStream_t s);
 void launch_pcg_update(float *x, float *r, const float *p, const float *Hp, float alpha, size_t n,
                        double *partials, int nblocks, hipStream_t s);
 // y = a + alpha * b   (y may alias a)

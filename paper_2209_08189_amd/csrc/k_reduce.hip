@@ -103,6 +103,70 @@ __global__ __launch_bounds__(TPB) void k_mean_free_axpy(float *y, const float *_
     }
 }
 
+// Fused PCG kernels.  Device scalars (FP64) in sc[]: see the PCG_* slots in
+// internal.h.
+
+// alpha = rz / pHp; a non-positive curvature sets the flag and alpha = 0, so
+// the update that follows leaves x and r unchanged
+__global__ void k_pcg_alpha(double *sc)
+{
+    const double pHp = sc[PCG_PHP], rz = sc[PCG_RZ];
+    const bool ok = pHp > 0.0;
+    sc[PCG_ALPHA] = ok ? rz / pHp : 0.0;
+    sc[PCG_NEG] = ok ? 0.0 : 1.0;
+}
+
+// beta = rz_new / rz, then rz = rz_new
+__global__ void k_pcg_beta(double *sc)
+{
+    sc[PCG_BETA] = sc[PCG_RZNEW] / sc[PCG_RZ];
+    sc[PCG_RZ] = sc[PCG_RZNEW];
+}
+
+// x += alpha p, r -= alpha Hp on component c = blockIdx.y; per-block partial
+// sums of r^2 (partials[c nb + b]) and of r (partials[(3 + c) nb + b])
+__global__ __launch_bounds__(TPB) void k_pcg_update3(float *__restrict__ x, float *__restrict__ r,
+                                                     const float *__restrict__ p, const float *__restrict__ Hp,
+                                                     const double *__restrict__ sc, size_t n,
+                                                     double *__restrict__ partials)
+{
+    const int c = blockIdx.y, nb = gridDim.x;
+    const float alpha = (float)sc[PCG_ALPHA];
+    const size_t off = c * n;
+    double a2 = 0.0, a1 = 0.0;
+    const size_t stride = (size_t)nb * TPB;
+    for (size_t q = (size_t)blockIdx.x * TPB + threadIdx.x; q < n; q += stride) {
+        float rq = r[off + q];
+        if (alpha != 0.0f) {          // alpha = 0: curvature exit, x and r stay as they are
+            x[off + q] = fmaf(alpha, p[off + q], x[off + q]);
+            rq = fmaf(-alpha, Hp[off + q], rq);
+            r[off + q] = rq;
+        }
+        a2 += (double)rq * (double)rq;
+        a1 += (double)rq;
+    }
+    a2 = block_sum(a2);
+    if (threadIdx.x == 0) partials[c * nb + blockIdx.x] = a2;
+    a1 = block_sum(a1);
+    if (threadIdx.x == 0) partials[(3 + c) * nb + blockIdx.x] = a1;
+}
+
+// p = z + beta p and q = (r - mean r) + beta q on every component (q is
+// beta A p carried by recurrence; means from the component sums in sc)
+__global__ __launch_bounds__(TPB) void k_pcg_direction(float *__restrict__ p, float *__restrict__ q,
+                                                       const float *__restrict__ z, const float *__restrict__ r,
+                                                       const double *__restrict__ sc, size_t n)
+{
+    const float beta = (float)sc[PCG_BETA];
+    const size_t stride = (size_t)gridDim.x * TPB;
+    for (size_t e = (size_t)blockIdx.x * TPB + threadIdx.x; e < 3 * n; e += stride) {
+        const int c = (int)(e / n);
+        const float mean = (float)(sc[PCG_SUMR + c] / (double)n);
+        p[e] = fmaf(beta, p[e], z[e]);
+        q[e] = (r[e] - mean) + beta * q[e];
+    }
+}
+
 template <typename To>
 __global__ __launch_bounds__(TPB) void k_convert(To *__restrict__ out, const float *__restrict__ in, size_t n)
 {
@@ -194,6 +258,25 @@ void launch_comp_sums3(const float *a, size_t n, double *partials, int nblocks, 
 void launch_mean_free_axpy(float *y, const float *r, const double *sums, float beta, size_t n, hipStream_t s)
 {
     hipLaunchKernelGGL(k_mean_free_axpy, stream_grid(3 * n), dim3(TPB), 0, s, y, r, sums, beta, n);
+}
+
+void launch_pcg_alpha(double *sc, hipStream_t s) { hipLaunchKernelGGL(k_pcg_alpha, dim3(1), dim3(1), 0, s, sc); }
+
+void launch_pcg_beta(double *sc, hipStream_t s) { hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(1), 0, s, sc); }
+
+void launch_pcg_update3(float *x, float *r, const float *p, const float *Hp, double *sc, size_t n, double *partials,
+                        int nblocks, double rscale, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pcg_update3, dim3(nblocks, 3), dim3(TPB), 0, s, x, r, p, Hp, sc, n, partials);
+    // ||r||^2 over the three components in order, then the component sums
+    launch_finalize(partials, 3 * nblocks, rscale, sc + PCG_RR, s);
+    for (int c = 0; c < 3; ++c) launch_finalize(partials + (3 + c) * nblocks, nblocks, 1.0, sc + PCG_SUMR + c, s);
+}
+
+void launch_pcg_direction(float *p, float *q, const float *z, const float *r, const double *sc, size_t n,
+                          hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pcg_direction, stream_grid(3 * n), dim3(TPB), 0, s, p, q, z, r, sc, n);
 }
 
 void launch_convert(int dt_out, void *out, const float *in, size_t n, hipStream_t s)

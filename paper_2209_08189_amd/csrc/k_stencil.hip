@@ -98,34 +98,52 @@ template <typename T> __device__ __forceinline__ float4 ld4(const T *p)
 }
 template <> __device__ __forceinline__ float4 ld4<float>(const float *p) { return *(const float4 *)p; }
 
-// out3 = add3 + sum_j w_j lam^j G^j, four nodes per thread (streaming)
+// out3 = add3 + sum_j w_j lam^j G^j, four nodes per thread (streaming).
+// With dp != NULL also the per-block FP64 partial sums of dp . out3 (from
+// the FP32 values stored), one per block in partials[blockIdx.x].
 template <typename Tl>
 __global__ __launch_bounds__(TPB) void k_quadrature(Grid g, QuadArgs qa, const float *__restrict__ add,
-                                                    float *__restrict__ out)
+                                                    float *__restrict__ out, const float *__restrict__ dp,
+                                                    double *__restrict__ partials)
 {
     const size_t N = g.N;
     const int p = (blockIdx.x * TPB + threadIdx.x) * 4;
-    if (p >= g.N) return;
-    float4 b0 = make_float4(0.f, 0.f, 0.f, 0.f), b1 = b0, b2 = b0;
-    for (int t = 0; t < qa.count; ++t) {
-        const float4 l = ld4((const Tl *)qa.lam[t] + p);
-        const float w = qa.w[t];
-        const float4 wl = make_float4(w * l.x, w * l.y, w * l.z, w * l.w);
-        const float *G = qa.G[t];
-        const float4 g0 = *(const float4 *)(G + p), g1 = *(const float4 *)(G + N + p), g2 = *(const float4 *)(G + 2 * N + p);
-        b0.x = fmaf(wl.x, g0.x, b0.x); b0.y = fmaf(wl.y, g0.y, b0.y); b0.z = fmaf(wl.z, g0.z, b0.z); b0.w = fmaf(wl.w, g0.w, b0.w);
-        b1.x = fmaf(wl.x, g1.x, b1.x); b1.y = fmaf(wl.y, g1.y, b1.y); b1.z = fmaf(wl.z, g1.z, b1.z); b1.w = fmaf(wl.w, g1.w, b1.w);
-        b2.x = fmaf(wl.x, g2.x, b2.x); b2.y = fmaf(wl.y, g2.y, b2.y); b2.z = fmaf(wl.z, g2.z, b2.z); b2.w = fmaf(wl.w, g2.w, b2.w);
+    double acc = 0.0;
+    if (p < g.N) {
+        float4 b0 = make_float4(0.f, 0.f, 0.f, 0.f), b1 = b0, b2 = b0;
+        for (int t = 0; t < qa.count; ++t) {
+            const float4 l = ld4((const Tl *)qa.lam[t] + p);
+            const float w = qa.w[t];
+            const float4 wl = make_float4(w * l.x, w * l.y, w * l.z, w * l.w);
+            const float *G = qa.G[t];
+            const float4 g0 = *(const float4 *)(G + p), g1 = *(const float4 *)(G + N + p),
+                         g2 = *(const float4 *)(G + 2 * N + p);
+            b0.x = fmaf(wl.x, g0.x, b0.x); b0.y = fmaf(wl.y, g0.y, b0.y); b0.z = fmaf(wl.z, g0.z, b0.z); b0.w = fmaf(wl.w, g0.w, b0.w);
+            b1.x = fmaf(wl.x, g1.x, b1.x); b1.y = fmaf(wl.y, g1.y, b1.y); b1.z = fmaf(wl.z, g1.z, b1.z); b1.w = fmaf(wl.w, g1.w, b1.w);
+            b2.x = fmaf(wl.x, g2.x, b2.x); b2.y = fmaf(wl.y, g2.y, b2.y); b2.z = fmaf(wl.z, g2.z, b2.z); b2.w = fmaf(wl.w, g2.w, b2.w);
+        }
+        if (add) {
+            const float4 a0 = *(const float4 *)(add + p), a1 = *(const float4 *)(add + N + p),
+                         a2 = *(const float4 *)(add + 2 * N + p);
+            b0.x += a0.x; b0.y += a0.y; b0.z += a0.z; b0.w += a0.w;
+            b1.x += a1.x; b1.y += a1.y; b1.z += a1.z; b1.w += a1.w;
+            b2.x += a2.x; b2.y += a2.y; b2.z += a2.z; b2.w += a2.w;
+        }
+        *(float4 *)(out + p) = b0;
+        *(float4 *)(out + N + p) = b1;
+        *(float4 *)(out + 2 * N + p) = b2;
+        if (dp) {
+            const float4 d0 = *(const float4 *)(dp + p), d1 = *(const float4 *)(dp + N + p),
+                         d2 = *(const float4 *)(dp + 2 * N + p);
+            acc = (double)d0.x * b0.x + (double)d0.y * b0.y + (double)d0.z * b0.z + (double)d0.w * b0.w;
+            acc += (double)d1.x * b1.x + (double)d1.y * b1.y + (double)d1.z * b1.z + (double)d1.w * b1.w;
+            acc += (double)d2.x * b2.x + (double)d2.y * b2.y + (double)d2.z * b2.z + (double)d2.w * b2.w;
+        }
     }
-    if (add) {
-        const float4 a0 = *(const float4 *)(add + p), a1 = *(const float4 *)(add + N + p), a2 = *(const float4 *)(add + 2 * N + p);
-        b0.x += a0.x; b0.y += a0.y; b0.z += a0.z; b0.w += a0.w;
-        b1.x += a1.x; b1.y += a1.y; b1.z += a1.z; b1.w += a1.w;
-        b2.x += a2.x; b2.y += a2.y; b2.z += a2.z; b2.w += a2.w;
+    if (dp) {
+        acc = block_sum(acc);
+        if (threadIdx.x == 0) partials[blockIdx.x] = acc;
     }
-    *(float4 *)(out + p) = b0;
-    *(float4 *)(out + N + p) = b1;
-    *(float4 *)(out + 2 * N + p) = b2;
 }
 
 // lam^nt = m1 - m^nt and per-block partial sums of its square, grid-stride.
@@ -175,9 +193,18 @@ void launch_inc_sources(const Grid &g, const float *G, const float *vt, int nt, 
 
 void launch_quadrature(const Grid &g, int dt_lam, const QuadArgs &qa, const float *addend3, float *out3, hipStream_t s)
 {
+    launch_quadrature_dot(g, dt_lam, qa, addend3, out3, nullptr, nullptr, s);
+}
+
+int quadrature_blocks(const Grid &g) { return (int)((g.N / 4 + TPB - 1) / TPB); }
+
+void launch_quadrature_dot(const Grid &g, int dt_lam, const QuadArgs &qa, const float *addend3, float *out3,
+                           const float *dp, double *partials, hipStream_t s)
+{
     with_dtype(dt_lam, [&](auto tl) {
         using Tl = decltype(tl);
-        hipLaunchKernelGGL((k_quadrature<Tl>), dim3((g.N / 4 + TPB - 1) / TPB), dim3(TPB), 0, s, g, qa, addend3, out3);
+        hipLaunchKernelGGL((k_quadrature<Tl>), dim3(quadrature_blocks(g)), dim3(TPB), 0, s, g, qa, addend3, out3, dp,
+                           partials);
     });
 }
 
