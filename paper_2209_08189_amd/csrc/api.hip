@@ -53,6 +53,7 @@ struct cl_ctx {
     float *df = nullptr, *db = nullptr;     // 3N
     float *c = nullptr, *divv = nullptr;    // N
     float *grad = nullptr, *Av = nullptr, *tmp3 = nullptr;  // 3N
+    float *fscr = nullptr;                  // 3N workspace of the feet computation
     float *px = nullptr, *pr = nullptr, *pz = nullptr, *pp = nullptr, *pHp = nullptr;  // 3N
     double *partials = nullptr, *dscal = nullptr, *hscal = nullptr;
     double *qparts = nullptr;                // partials of the fused PCG reductions
@@ -196,9 +197,8 @@ void ensure_feet(cl_ctx *ctx, bool backward)
         if (backward) run(ctx, CL_K_FD, [&] { launch_fd_div(ctx->g, ctx->v, ctx->divv, ctx->s); });
         run(ctx, CL_K_FEET, [&] {
             launch_feet(ctx->g, ctx->dt, ctx->v, ctx->df, backward ? ctx->db : nullptr,
-                        backward ? ctx->divv : nullptr, backward ? ctx->c : nullptr, ctx->s);
-            launch_tile_boxes(ctx->g, ctx->df, ctx->box_f, ctx->s);
-            if (backward) launch_tile_boxes(ctx->g, ctx->db, ctx->box_b, ctx->s);
+                        backward ? ctx->divv : nullptr, backward ? ctx->c : nullptr, ctx->box_f, ctx->box_b,
+                        ctx->fscr, ctx->s);
         });
         ctx->feet_f = true;
         if (backward) ctx->feet_b = true;
@@ -515,9 +515,10 @@ size_t workspace_bytes(int n1, int n2, int n3, const cl_options &o)
     b += (size_t)o.nt * N * sizeof(float);   // incremental sources s^j
     b += 3 * (N / 2048 + 1) * 8 * sizeof(int);  // tile stencil boxes
     b += 2 * N * sizeof(float);              // c, div v
-    b += 12 * 3 * N * sizeof(float);         // v, vtrial, df, db, g, Av, tmp3, PCG x r z p Hp
+    b += 13 * 3 * N * sizeof(float);         // v, vtrial, df, db, g, Av, tmp3, PCG x r z p Hp, feet workspace
     b += fft_spec_bytes(n1, n2, n3, 3);
-    b += 4 * 1025 * sizeof(float2) + 4096 * sizeof(double) + 256;
+    b += 4 * 1025 * sizeof(float2) + 4096 * sizeof(double) + 256;   // FFT tables, reduction partials, scalars
+    b += (std::max<size_t>((N / 4 + 255) / 256, 6 * (size_t)reduce_blocks(N)) + PCG_NSCAL) * sizeof(double);
     return b;
 }
 
@@ -647,7 +648,7 @@ int cl_create(cl_ctx **out, int n1, int n2, int n3, const cl_options *opt)
             ctx->box_t = (int *)alloc(nb);
         }
         float **vecs[] = {&ctx->v, &ctx->vtrial, &ctx->df, &ctx->db, &ctx->grad, &ctx->Av, &ctx->tmp3,
-                          &ctx->px, &ctx->pr, &ctx->pz, &ctx->pp, &ctx->pHp};
+                          &ctx->px, &ctx->pr, &ctx->pz, &ctx->pp, &ctx->pHp, &ctx->fscr};
         for (float **pv : vecs) *pv = (float *)alloc(3 * N * sizeof(float));
         ctx->c = (float *)alloc(N * sizeof(float));
         ctx->divv = (float *)alloc(N * sizeof(float));

@@ -109,43 +109,45 @@ __device__ __forceinline__ void gather3(const float *__restrict__ u0, const floa
 
 // RK2 (Heun) feet of both characteristic directions, as index-unit
 // displacements:  X_f = x - dt/2 [v(x) + v(x - dt v(x))],
-//                 X_b = x + dt/2 [v(x) + v(x + dt v(x))].
-// If db != NULL also the adjoint factor c = 1 + dt/2 (dbar + d + dt dbar d),
-// d = div_h v (precomputed), dbar = d(X_b).
-__global__ __launch_bounds__(TPB) void k_feet(Grid g, float dt, const float *__restrict__ v,
-                                              float *__restrict__ df, float *__restrict__ db,
-                                              const float *__restrict__ divv, float *__restrict__ c)
+//                 X_b = x + dt/2 [v(x) + v(x + dt v(x))],
+// and the adjoint factor c = 1 + dt/2 (dbar + d + dt dbar d), d = div_h v,
+// dbar = d(X_b).  The velocity at the predictor feet and dbar are tricubic
+// interpolations done by the tiled SL gather (launch_feet below); these
+// kernels are the elementwise steps around them.  Displacements divide by h
+// (correctly rounded), so a velocity that is an exact multiple of h/dt gives
+// an exactly integer foot.
+
+// predictor displacement d = (a v) / h, a = -dt (X_f) or +dt (X_b)
+__global__ __launch_bounds__(TPB) void k_feet_pred(Grid g, float a, const float *__restrict__ v, float *__restrict__ d)
 {
     const int p = blockIdx.x * TPB + threadIdx.x;
     if (p >= g.N) return;
-    int i, j, k;
-    node_of(g, p, i, j, k);
-    const float *v0 = v, *v1 = v + g.N, *v2 = v + 2 * (size_t)g.N;
-    const float a0 = v0[p], a1 = v1[p], a2 = v2[p];
-    // Displacements divide by h (correctly rounded), so a velocity that is an
-    // exact multiple of h/dt gives an exactly integer foot.
-    const float h[3] = {g.h1, g.h2, g.h3};
-    const float va[3] = {a0, a1, a2};
-    Foot F;
-    float vi[3];
-    make_foot(g, i, j, k, (-dt * a0) / g.h1, (-dt * a1) / g.h2, (-dt * a2) / g.h3, F);
-    gather3(v0, v1, v2, F, vi);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) df[a * (size_t)g.N + p] = (-0.5f * dt * (va[a] + vi[a])) / h[a];
-    if (!db) return;
-    make_foot(g, i, j, k, (dt * a0) / g.h1, (dt * a1) / g.h2, (dt * a2) / g.h3, F);
-    gather3(v0, v1, v2, F, vi);
-    float dbv[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        dbv[a] = (0.5f * dt * (va[a] + vi[a])) / h[a];
-        db[a * (size_t)g.N + p] = dbv[a];
-    }
-    if (!c) return;
-    make_foot(g, i, j, k, dbv[0], dbv[1], dbv[2], F);
-    const float dbar = gather(divv, F);
-    const float d = divv[p];
-    c[p] = 1.0f + 0.5f * dt * (dbar + d + dt * dbar * d);
+    const size_t N = g.N;
+    d[p] = (a * v[p]) / g.h1;
+    d[N + p] = (a * v[N + p]) / g.h2;
+    d[2 * N + p] = (a * v[2 * N + p]) / g.h3;
+}
+
+// corrector displacement d = (b (v + vi)) / h, b = -dt/2 (X_f) or +dt/2 (X_b),
+// vi = v interpolated at the predictor feet
+__global__ __launch_bounds__(TPB) void k_feet_corr(Grid g, float b, const float *__restrict__ v,
+                                                   const float *__restrict__ vi, float *__restrict__ d)
+{
+    const int p = blockIdx.x * TPB + threadIdx.x;
+    if (p >= g.N) return;
+    const size_t N = g.N;
+    d[p] = (b * (v[p] + vi[p])) / g.h1;
+    d[N + p] = (b * (v[N + p] + vi[N + p])) / g.h2;
+    d[2 * N + p] = (b * (v[2 * N + p] + vi[2 * N + p])) / g.h3;
+}
+
+__global__ __launch_bounds__(TPB) void k_adj_factor(Grid g, float dt, const float *__restrict__ divv,
+                                                    const float *__restrict__ dbar, float *__restrict__ c)
+{
+    const int p = blockIdx.x * TPB + threadIdx.x;
+    if (p >= g.N) return;
+    const float d = divv[p], db = dbar[p];
+    c[p] = 1.0f + 0.5f * dt * (db + d + dt * db * d);
 }
 
 // ------------------------------------------------ semi-Lagrangian steps
@@ -509,9 +511,25 @@ void launch_sl(const Grid &g, const Tu *u, const float *d, const SLParams &prm, 
 } // namespace
 
 void launch_feet(const Grid &g, float dt, const float *v, float *df, float *db, const float *divv, float *c,
-                 hipStream_t s)
+                 int *box_f, int *box_b, float *scratch3, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_feet, grid_of(g), dim3(TPB), 0, s, g, dt, v, df, db, divv, c);
+    const size_t N = g.N;
+    // one direction: predictor, interpolate v there (one SL gather per
+    // component), corrector; the tile boxes follow the displacements
+    auto heun = [&](float a, float b, float *d, int *box) {
+        hipLaunchKernelGGL(k_feet_pred, grid_of(g), dim3(TPB), 0, s, g, a, v, d);
+        launch_tile_boxes(g, d, box, s);
+        for (int k = 0; k < 3; ++k)
+            launch_sl<float, float, SL_STATE>(g, v + k * N, d, SLParams{}, scratch3 + k * N, box, s);
+        hipLaunchKernelGGL(k_feet_corr, grid_of(g), dim3(TPB), 0, s, g, b, v, scratch3, d);
+        launch_tile_boxes(g, d, box, s);
+    };
+    heun(-dt, -0.5f * dt, df, box_f);
+    if (!db) return;
+    heun(dt, 0.5f * dt, db, box_b);
+    if (!c) return;
+    launch_sl<float, float, SL_STATE>(g, divv, db, SLParams{}, scratch3, box_b, s);
+    hipLaunchKernelGGL(k_adj_factor, grid_of(g), dim3(TPB), 0, s, g, dt, divv, scratch3, c);
 }
 
 size_t tile_box_ints(const Grid &g) { return tiled(g) ? (size_t)8 * (g.N / (TX * TY * TZ)) : 0; }
