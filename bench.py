@@ -169,12 +169,12 @@ def main():
         if name in ALG_F:
             d["alg_GBs"] = ALG_F[name] * F / (d["avg_launch_ms"] * 1e-3) / 1e9
 
-    # the same matvec with 16-bit field storage (images/state FP16,
-    # adjoint/incremental BF16; FP32 arithmetic, FP64 reductions)
+    # the same matvec with 16-bit field storage (images, state, adjoint and
+    # incremental fields FP16; FP32 arithmetic, FP64 reductions)
     mixed = None
     if not args.no_mixed:
         rm = Registration(shape, nt=4, beta_v=5e-4, gtol=1e-2, max_outer=50, max_pcg=args.max_pcg,
-                          storage_state="f16", storage_adjoint="bf16")
+                          storage_state="f16", storage_adjoint="f16")
         rm.set_images(m0, m1)
         rm.set_velocity(dev(v_true))
         gm, _, _ = rm.gradient()
@@ -196,7 +196,7 @@ def main():
             rm.hessian_matvec(vtm, Hv)
         torch.cuda.synchronize()
         tm = time.perf_counter() - tm0
-        mixed = {"matvecs_per_s": args.steps / tm, "storage": "state f16, adjoint bf16", "kernels": mclass}
+        mixed = {"matvecs_per_s": args.steps / tm, "storage": "state f16, adjoint f16", "kernels": mclass}
         log("mixed-storage matvec %.3f ms (%.1f matvecs/s)" % (1e3 * tm / args.steps, args.steps / tm))
         del rm
 
@@ -232,7 +232,7 @@ def main():
             hist = warmstart.train(net, data, args.learned_epochs, log=log)
             t_train = time.perf_counter() - t_train
             del data
-            rows = warmstart.evaluate(net, eval_seeds, n=n, storage=("f16", "bf16"), log=log, host=host,
+            rows = warmstart.evaluate(net, eval_seeds, n=n, storage=("f16", "f16"), log=log, host=host,
                                       max_pcg=args.max_pcg)
             learned = {
                 "train_pairs": len(train_seeds), "eval_pairs": len(eval_seeds), "epochs": args.learned_epochs,
@@ -249,7 +249,7 @@ def main():
                 "prediction_used_frac": float(np.mean([r["used_prediction"] for r in rows])),
                 "max_rel_mismatch_diff": float(np.max([r["rel_mismatch_diff"] for r in rows])),
                 "max_abs_diff_relative_mismatch": float(np.max([r["abs_diff_r"] for r in rows])),
-                "storage": "images/state f16, adjoint/incremental bf16, FP32 arithmetic, FP64 reductions",
+                "storage": "images, state, adjoint and incremental fields f16; FP32 arithmetic, FP64 reductions",
                 "rows": rows, "wall_s": time.perf_counter() - tl,
             }
             log("learned: %s" % json.dumps({k: v for k, v in learned.items() if k != "rows"}))

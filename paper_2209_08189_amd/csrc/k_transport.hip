@@ -397,6 +397,36 @@ template <> __device__ __forceinline__ float lds_ld<__half>(unsigned a)
         *reinterpret_cast<__attribute__((address_space(3))) const unsigned short *>(static_cast<uintptr_t>(a));
     return __half2float(__ushort_as_half(h));
 }
+__device__ __forceinline__ unsigned lds_ld_u32(unsigned a)
+{
+    return *reinterpret_cast<__attribute__((address_space(3))) const unsigned *>(static_cast<uintptr_t>(a));
+}
+__device__ __forceinline__ void lds_st_u32(unsigned a, unsigned v)
+{
+    *reinterpret_cast<__attribute__((address_space(3))) unsigned *>(static_cast<uintptr_t>(a)) = v;
+}
+
+// x3 row of 4 consecutive 16-bit values held in two words (lo, hi halves),
+// contracted with the weights w3 in FP32.  FP16: the conversions fold into
+// mixed-precision FMAs; BF16: a value is the high half of an FP32 word.
+typedef _Float16 h2_t __attribute__((ext_vector_type(2)));
+template <typename T> __device__ __forceinline__ float row4(unsigned d0, unsigned d1, const float w3[4]);
+template <> __device__ __forceinline__ float row4<__half>(unsigned d0, unsigned d1, const float w3[4])
+{
+    const h2_t a = __builtin_bit_cast(h2_t, d0), b = __builtin_bit_cast(h2_t, d1);
+    float t = fmaf(w3[0], (float)a.x, 0.0f);
+    t = fmaf(w3[1], (float)a.y, t);
+    t = fmaf(w3[2], (float)b.x, t);
+    return fmaf(w3[3], (float)b.y, t);
+}
+template <> __device__ __forceinline__ float row4<__hip_bfloat16>(unsigned d0, unsigned d1, const float w3[4])
+{
+    float t = w3[0] * __uint_as_float(d0 << 16);
+    t = fmaf(w3[1], __uint_as_float(d0 & 0xffff0000u), t);
+    t = fmaf(w3[2], __uint_as_float(d1 << 16), t);
+    return fmaf(w3[3], __uint_as_float(d1 & 0xffff0000u), t);
+}
+
 template <typename T> __device__ __forceinline__ unsigned lds_addr(const T *p)
 {
     return (unsigned)(uintptr_t)(lds_void *)(p);
@@ -411,7 +441,39 @@ __device__ __forceinline__ void compute_tile(const Grid &g, const Tu *__restrict
                                              float (&res)[QT])
 {
     constexpr int PX = box_px<Tu>();
-    if (B.fits) {
+    if (B.fits && sizeof(Tu) == 2) {
+        // 16-bit box: copy A as loaded, copy B shifted by one element, so the
+        // 4 values of any stencil row are two aligned words of one copy
+#pragma unroll
+        for (int q = 0; q < QT; ++q) {
+            const float f1 = floorf(d1[q]), f2 = floorf(d2[q]), f3 = floorf(d3[q]);
+            float w1[4], w2[4], w3[4];
+            lagrange4_fast(d1[q] - f1, w1);
+            lagrange4_fast(d2[q] - f2, w2);
+            lagrange4_fast(d3[q] - f3, w3);
+            const int s1 = t.q0 + q + ifloor(d1[q]) - 1 - B.r1;
+            const int s2 = t.row + ifloor(d2[q]) - 1 - B.r2;
+            const int s3 = t.lane + ifloor(d3[q]) - 1 - B.r3 + B.sh;
+            const unsigned bp = lds_addr(box) + ((s3 & 1) ? (unsigned)(PZ * PY * PX * 2) : 0u) +
+                                ((s1 * PY + s2) * PX + (s3 & ~1)) * 2u;
+            float s = 0.0f;
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                unsigned ba = bp + a * PY * PX * 2;
+                asm volatile("" : "+v"(ba));
+                float sa = 0.0f;
+#pragma unroll
+                for (int bq = 0; bq < 4; ++bq) {
+                    const unsigned rp = ba + bq * PX * 2;
+                    sa = fmaf(w2[bq], row4<Tu>(lds_ld_u32(rp), lds_ld_u32(rp + 4), w3), sa);
+                }
+                s = fmaf(w1[a], sa, s);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            res[q] = epilogue<MODE>(prm, e[q], s);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    } else if (B.fits) {
 #pragma unroll
         for (int q = 0; q < QT; ++q) {
             const float f1 = floorf(d1[q]), f2 = floorf(d2[q]), f3 = floorf(d3[q]);
@@ -464,6 +526,26 @@ __device__ __forceinline__ void store_tile(To *__restrict__ out, const TileIdx &
     for (int q = 0; q < QT; ++q) stf(out + t.p0 + q * t.plane, res[q]);
 }
 
+// 16-bit boxes: copy B (words after copy A) holds the elements shifted by
+// one, B word j = elements 2j+1, 2j+2 of copy A, built from copy A in LDS.
+template <typename Tu>
+__device__ __forceinline__ void shift_copy(const Tu *box, const TileBox &B)
+{
+    constexpr int PX = box_px<Tu>();
+    constexpr int WPR = PX / 2;                        // words per box row
+    const unsigned A0 = lds_addr(box), B0 = A0 + PZ * PY * PX * 2;
+    const int nw = (B.E3 + B.sh + 1) >> 1;             // words of copy A in use per row
+    const int tot = B.E1 * PY * WPR;
+    for (int e = threadIdx.x; e < tot; e += TPB_SL) {
+        const int r = e / WPR, j = e - r * WPR;
+        const int bb = r - (r / PY) * PY;
+        if (bb < B.E2 && j < nw) {
+            const unsigned o = (unsigned)e * 4u;
+            lds_st_u32(B0 + o, __builtin_amdgcn_alignbit(lds_ld_u32(A0 + o + 4), lds_ld_u32(A0 + o), 16));
+        }
+    }
+}
+
 // One tile per workgroup: the feet, epilogue operands and box of the tile
 // are requested together, then one wait, then the gather.  At most 80 VGPRs
 // (6 waves per SIMD) so that three 512-thread workgroups share a CU; their
@@ -474,7 +556,9 @@ __global__ __launch_bounds__(TPB_SL, 6) void k_sl_tile(Grid g, const Tu *__restr
                                                   int ntx, int nty, int nblk)
 {
     constexpr int PX = box_px<Tu>();
-    __shared__ __align__(16) Tu box[PZ * PY * PX];
+    // 16-bit boxes hold two copies (and a word of padding read by the shift)
+    constexpr int BOXN = sizeof(Tu) == 2 ? 2 * PZ * PY * PX + 2 : PZ * PY * PX;
+    __shared__ __align__(16) Tu box[BOXN];
     // XCD-contiguous tile order (workgroups go round-robin to the 8 XCDs)
     const int b = blockIdx.x;
     const int tile = (nblk & 7) ? b : (b & 7) * (nblk >> 3) + (b >> 3);
@@ -486,6 +570,10 @@ __global__ __launch_bounds__(TPB_SL, 6) void k_sl_tile(Grid g, const Tu *__restr
     if (B.fits) stage_box(g, u, box, t, B);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
+    if (sizeof(Tu) == 2 && B.fits) {
+        shift_copy(box, B);
+        __syncthreads();
+    }
     compute_tile<Tu, MODE>(g, u, box, t, B, d1, d2, d3, e, prm, r);
     store_tile(out, t, r);
 }

@@ -161,7 +161,7 @@ def train(net, data, epochs, batch=1, log=None, seed=0):
     return hist
 
 
-def evaluate(net, seeds, n=256, storage=("f16", "bf16"), log=None, host=None, max_pcg=40):
+def evaluate(net, seeds, n=256, storage=("f16", "f16"), log=None, host=None, max_pcg=40):
     """Per held-out seed: plain FP32 solve from v = 0, mixed-precision storage
     from v = 0, warm start in FP32, and warm start + mixed storage.  Returns a
     list of dicts (times in seconds, GN iterations, mismatches, and the
