@@ -215,6 +215,12 @@ def main():
         solve = {"status": rep["status_name"], "time_to_tol_s": te - ts, "outer_iters": rep["outer_iters"],
                  "pcg_iters": rep["pcg_iters_total"], "ls_trials": rep["linesearch_trials"],
                  "rel_grad": rep["gnorm"] / rep["gref"], "r": rep["mismatch"] / mis0}
+        # Dice of the warped labels (D_vw over the three tissue labels):
+        # reference labels = phantom labels transported by v_true
+        from paper_2209_08189_amd.metrics import dice, warp_labels
+        lab1 = warp_labels(labels, dev(v_true))
+        solve["dice_pre"] = dice(labels, lab1)
+        solve["dice_post"] = dice(warp_labels(labels, rs.velocity()), lab1)
         log("solve: %s" % json.dumps(solve))
         del rs
 
@@ -246,6 +252,9 @@ def main():
                 "plain_gn_iters": float(np.mean([r["plain_gn"] for r in rows])),
                 "learned_gn_iters": float(np.mean([r["learned_gn"] for r in rows])),
                 "initial_rel_velocity_error": float(np.mean([r["pred_rel_err"] for r in rows])),
+                "dice_vw_pre": float(np.mean([r["dice_vw_pre"] for r in rows])),
+                "dice_vw_plain": float(np.mean([r["dice_vw_plain"] for r in rows])),
+                "dice_vw_learned_mixed": float(np.mean([r["dice_vw_learned"] for r in rows])),
                 "prediction_used_frac": float(np.mean([r["used_prediction"] for r in rows])),
                 "max_rel_mismatch_diff": float(np.max([r["rel_mismatch_diff"] for r in rows])),
                 "max_abs_diff_relative_mismatch": float(np.max([r["abs_diff_r"] for r in rows])),

@@ -164,6 +164,20 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def query_workspace(shape, nt=4, storage_state="f32", storage_adjoint="f32"):
+    """Device bytes a registration context of this shape and storage needs
+    (host-only query, cl_query_workspace)."""
+    o = default_options()
+    o.nt = int(nt)
+    o.storage_state = DTYPES[storage_state]
+    o.storage_adjoint = DTYPES[storage_adjoint]
+    nb = ctypes.c_ulonglong()
+    st = lib().cl_query_workspace(*[int(x) for x in shape], ctypes.byref(o), ctypes.byref(nb))
+    if st != 0:
+        raise ClaireError(st, "cl_query_workspace")
+    return int(nb.value)
+
+
 class Registration:
     """One registration problem on an n1 x n2 x n3 periodic grid, on the
     current CUDA(HIP) device and torch's current stream."""

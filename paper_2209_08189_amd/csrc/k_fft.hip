@@ -320,8 +320,9 @@ __device__ __forceinline__ void store_cols(const float2 *lds, float2 *__restrict
 
 // --- x2 C2C in place on the half spectrum: plane i1 = blockIdx.y, columns
 // [c0, c0 + C) of the nh per row.
+template <bool INV>
 __global__ __launch_bounds__(TPB) void k_fft_x2(float2 *__restrict__ spec, const float2 *__restrict__ tw2, int logn2,
-                                                int n2, int nh, int logC, int inv, size_t spec_cs)
+                                                int n2, int nh, int logC, size_t spec_cs)
 {
     extern __shared__ float2 sm[];
     const int C = 1 << logC, P = C + 1;
@@ -332,8 +333,7 @@ __global__ __launch_bounds__(TPB) void k_fft_x2(float2 *__restrict__ spec, const
     float2 *base = spec + comp * spec_cs + (size_t)i1 * n2 * nh + c0;
     load_table(tw, tw2, n2);
     load_cols(lds, base, nh, logC, logn2, cw, P);
-    if (inv) fft_lines<true>(lds, P, logC, logn2, tw);
-    else fft_lines<false>(lds, P, logC, logn2, tw);
+    fft_lines<INV>(lds, P, logC, logn2, tw);
     store_cols(lds, base, nh, logC, logn2, cw, P);
 }
 
@@ -457,12 +457,12 @@ void spectral_apply(const FFTPlan &P, int kind, float beta, int ncomp, const flo
         const float *addc = add ? add + c0 * N : nullptr;
         hipLaunchKernelGGL(k_fft_x3_r2c, dim3(nrows >> lognl3, nc), dim3(TPB), lds3, s, inc, P.spec, P.twM, P.twS,
                            logM, lognl3, nrows, N, spec_cs);
-        hipLaunchKernelGGL(k_fft_x2, dim3((nh + C2 - 1) / C2, n1, nc), dim3(TPB), lds2, s, P.spec, P.tw2, ilog2(n2),
-                           n2, nh, logC2, 0, spec_cs);
+        hipLaunchKernelGGL(k_fft_x2<false>, dim3((nh + C2 - 1) / C2, n1, nc), dim3(TPB), lds2, s, P.spec, P.tw2, ilog2(n2),
+                           n2, nh, logC2, spec_cs);
         hipLaunchKernelGGL(k_fft_x1_mult, dim3((nh + C1 - 1) / C1, n2, nc), dim3(TPB), lds1, s, P.spec, P.tw1,
                            ilog2(n1), n1, n2, nh, logC1, kind, beta, scale, spec_cs, 0);
-        hipLaunchKernelGGL(k_fft_x2, dim3((nh + C2 - 1) / C2, n1, nc), dim3(TPB), lds2, s, P.spec, P.tw2, ilog2(n2),
-                           n2, nh, logC2, 1, spec_cs);
+        hipLaunchKernelGGL(k_fft_x2<true>, dim3((nh + C2 - 1) / C2, n1, nc), dim3(TPB), lds2, s, P.spec, P.tw2, ilog2(n2),
+                           n2, nh, logC2, spec_cs);
         hipLaunchKernelGGL(k_fft_x3_c2r, dim3(nrows >> lognl3, nc), dim3(TPB), lds3, s, P.spec, outc, addc, P.twM,
                            P.twS, logM, lognl3, nrows, N, spec_cs);
     }
@@ -500,8 +500,8 @@ void forward3(const FFTPlan &P, const PassGeom &G, int nc, const float *in, hipS
 {
     hipLaunchKernelGGL(k_fft_x3_r2c, dim3(G.nrows >> G.lognl3, nc), dim3(TPB), G.lds3, s, in, P.spec, P.twM, P.twS,
                        G.logM, G.lognl3, G.nrows, G.N, G.spec_cs);
-    hipLaunchKernelGGL(k_fft_x2, dim3((P.nh + G.C2 - 1) / G.C2, P.n1, nc), dim3(TPB), G.lds2, s, P.spec, P.tw2,
-                       ilog2(P.n2), P.n2, P.nh, G.logC2, 0, G.spec_cs);
+    hipLaunchKernelGGL(k_fft_x2<false>, dim3((P.nh + G.C2 - 1) / G.C2, P.n1, nc), dim3(TPB), G.lds2, s, P.spec, P.tw2,
+                       ilog2(P.n2), P.n2, P.nh, G.logC2, G.spec_cs);
     hipLaunchKernelGGL(k_fft_x1_mult, dim3((P.nh + G.C1 - 1) / G.C1, P.n2, nc), dim3(TPB), G.lds1, s, P.spec, P.tw1,
                        ilog2(P.n1), P.n1, P.n2, P.nh, G.logC1, 2, 0.f, 1.f, G.spec_cs, 1);
 }
@@ -510,8 +510,8 @@ void inverse3(const FFTPlan &P, const PassGeom &G, int nc, float *out, hipStream
 {
     hipLaunchKernelGGL(k_fft_x1_mult, dim3((P.nh + G.C1 - 1) / G.C1, P.n2, nc), dim3(TPB), G.lds1, s, P.spec, P.tw1,
                        ilog2(P.n1), P.n1, P.n2, P.nh, G.logC1, 2, 0.f, 1.f, G.spec_cs, 2);
-    hipLaunchKernelGGL(k_fft_x2, dim3((P.nh + G.C2 - 1) / G.C2, P.n1, nc), dim3(TPB), G.lds2, s, P.spec, P.tw2,
-                       ilog2(P.n2), P.n2, P.nh, G.logC2, 1, G.spec_cs);
+    hipLaunchKernelGGL(k_fft_x2<true>, dim3((P.nh + G.C2 - 1) / G.C2, P.n1, nc), dim3(TPB), G.lds2, s, P.spec, P.tw2,
+                       ilog2(P.n2), P.n2, P.nh, G.logC2, G.spec_cs);
     hipLaunchKernelGGL(k_fft_x3_c2r, dim3(G.nrows >> G.lognl3, nc), dim3(TPB), G.lds3, s, P.spec, out, nullptr, P.twM,
                        P.twS, G.logM, G.lognl3, G.nrows, G.N, G.spec_cs);
 }

@@ -72,19 +72,21 @@ class HostPairs:
         self.pool.join()
 
 
-def device_pair(host):
+def device_pair(host, with_velocity=False):
     """Device images (m0, m1) from host_pair(): m0 = phantom + noise, m1 =
-    phantom transported by v_true (forward SL solve on the GPU) + noise."""
+    phantom transported by v_true (forward SL solve on the GPU) + noise; the
+    clean phantom's labels (host); with_velocity: also v_true (device)."""
     img, labels, v_true, n0, n1 = host
     n = img.shape[0]
     reg = Registration((n, n, n))
     ph = _dev(img)
+    vt = _dev(v_true)
     reg.set_images(ph, ph)
-    reg.set_velocity(_dev(v_true))
+    reg.set_velocity(vt)
     m1 = reg.deformed_template() + _dev(n1)
     m0 = ph + _dev(n0)
     reg.close()
-    return m0, m1, labels
+    return (m0, m1, labels, vt) if with_velocity else (m0, m1, labels)
 
 
 def make_pair(n, seed, max_disp=6.0):
@@ -167,11 +169,13 @@ def evaluate(net, seeds, n=256, storage=("f16", "f16"), log=None, host=None, max
     list of dicts (times in seconds, GN iterations, mismatches, and the
     relative L2 error of the network's prediction against the plain
     solution)."""
+    from .metrics import dice, warp_labels
     rows = []
     src = host.pairs(n, seeds) if host else (host_pair(n, s) for s in seeds)
     for s, hp in zip(seeds, src):
-        m0, m1, _ = device_pair(hp)
+        m0, m1, lab0, v_true = device_pair(hp, with_velocity=True)
         del hp
+        lab1 = warp_labels(lab0, v_true)           # labels of m1
         mis0 = 0.5 * float(((m0 - m1).double() ** 2).sum()) * (2.0 * np.pi / n) ** 3
         rp, vp, tp = solve(m0, m1, max_pcg=max_pcg)
         rm, _, tm = solve(m0, m1, storage=storage, max_pcg=max_pcg)
@@ -179,9 +183,12 @@ def evaluate(net, seeds, n=256, storage=("f16", "f16"), log=None, host=None, max
         rl, vl, tl = solve(m0, m1, storage=storage, net=net, max_pcg=max_pcg)
         pred = predict(net, m0, m1)
         err = float((pred - vp).norm() / vp.norm())
+        d_pre = dice(lab0, lab1)["D_vw"]
+        d_plain = dice(warp_labels(lab0, vp), lab1)["D_vw"]
+        d_learned = dice(warp_labels(lab0, vl), lab1)["D_vw"]
         row = {"seed": s, "plain_s": tp, "plain_gn": rp["outer_iters"], "plain_pcg": rp["pcg_iters_total"],
                "mixed_s": tm, "mixed_gn": rm["outer_iters"], "learned_f32_s": tf, "learned_f32_gn": rf["outer_iters"],
-               "pred_rel_err": err,
+               "pred_rel_err": err, "dice_vw_pre": d_pre, "dice_vw_plain": d_plain, "dice_vw_learned": d_learned,
                "plain_mismatch": rp["mismatch"], "learned_s": tl, "learned_gn": rl["outer_iters"],
                "learned_pcg": rl["pcg_iters_total"], "learned_mismatch": rl["mismatch"],
                "used_prediction": rl["warm_start_used"],

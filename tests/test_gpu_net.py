@@ -176,3 +176,20 @@ def test_trained_network_gains_over_zero_start():
     assert all(r["pred_rel_err"] < 0.8 for r in rows)
     assert learned <= plain
     assert all(r["abs_diff_r"] < 1e-3 for r in rows)
+
+
+def test_label_warp_identity_and_roll():
+    """Label warping through the forward SL solve: v = 0 keeps every label;
+    a constant velocity of an integer number of voxels per time step rolls
+    the label map exactly (Dice 1 against the rolled labels)."""
+    from paper_2209_08189_amd.metrics import dice, warp_labels
+    n = 32
+    lab = np.random.default_rng(3).integers(0, 4, size=(n, n, n)).astype(np.uint8)
+    v = torch.zeros((3, n, n, n), device="cuda")
+    assert np.array_equal(host(warp_labels(lab, v)).astype(np.uint8), lab)
+    # one voxel per step along x2 for nt = 4 steps of dt = 1/4
+    v[1] = (2 * np.pi / n) / 0.25
+    w = host(warp_labels(lab, v)).astype(np.uint8)
+    ref = np.roll(lab, 4, axis=1)
+    assert np.array_equal(w, ref)
+    assert dice(w, ref)["D_a"] == 1.0
