@@ -74,7 +74,10 @@ typedef struct {
     int storage_state;        /* cl_dtype of m0, m1 and the state m^j (default CL_F32) */
     int storage_adjoint;      /* cl_dtype of the adjoint and incremental fields (default CL_F32) */
     void *stream;             /* hipStream_t; NULL = default stream */
-    unsigned long long workspace_cap_bytes; /* 0 = no cap; else cl_create fails with CL_ERR_OOM above it */
+    unsigned long long workspace_cap_bytes; /* device memory the context may take: when the full layout
+                                                exceeds it (0: exceeds 15/16 of the free device memory), the
+                                                lean layout is used (see cl_layout); cl_create fails with
+                                                CL_ERR_OOM when a nonzero cap is below even that */
 } cl_options;
 
 typedef struct {
@@ -92,11 +95,19 @@ typedef struct {
 /* Fill *opt with the defaults listed above. */
 void cl_default_options(cl_options *opt);
 
-/* Device bytes cl_create would allocate for this grid and options. */
+/* Device bytes cl_create would allocate for this grid and options (host-only query; with
+ * workspace_cap_bytes = 0 it reports the full layout). */
 int cl_query_workspace(int n1, int n2, int n3, const cl_options *opt, unsigned long long *bytes);
 
 /* Create a context on the current HIP device; allocates all workspace. */
 int cl_create(cl_ctx **out, int n1, int n2, int n3, const cl_options *opt);
+
+/* Memory layout of a context: 0 = full (the state gradients grad_h m^j, (nt+1) x 3 FP32 fields, are
+ * stored once per velocity and every incremental source field is kept), 1 = lean (the gradients are
+ * taken by the 8th-order stencil inside the kernels that need them, one source field; 3(nt+1)+nt-1
+ * fewer FP32 fields, slower quadrature and source passes).  Same results up to FP32 rounding order.
+ * Negative: error code (NULL context). */
+int cl_layout(const cl_ctx *ctx);
 void cl_destroy(cl_ctx *ctx);
 
 /* Template m0 and reference m1 (Section 2.1), each n1*n2*n3 values of type

@@ -88,6 +88,7 @@ _dp = ctypes.POINTER(ctypes.c_double)
 SIGNATURES = {
     "cl_default_options": (None, [ctypes.POINTER(cl_options)]),
     "cl_query_workspace": (_i, [_i, _i, _i, ctypes.POINTER(cl_options), ctypes.POINTER(ctypes.c_ulonglong)]),
+    "cl_layout": (_i, [ctypes.c_void_p]),
     "cl_create": (_i, [ctypes.POINTER(_vp), _i, _i, _i, ctypes.POINTER(cl_options)]),
     "cl_destroy": (None, [_vp]),
     "cl_set_images": (_i, [_vp, _vp, _vp, _i]),
@@ -164,11 +165,13 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def query_workspace(shape, nt=4, storage_state="f32", storage_adjoint="f32"):
+def query_workspace(shape, nt=4, storage_state="f32", storage_adjoint="f32", workspace_cap=0):
     """Device bytes a registration context of this shape and storage needs
-    (host-only query, cl_query_workspace)."""
+    (host-only query, cl_query_workspace; the lean layout when the full one
+    exceeds a nonzero workspace_cap)."""
     o = default_options()
     o.nt = int(nt)
+    o.workspace_cap_bytes = int(workspace_cap)
     o.storage_state = DTYPES[storage_state]
     o.storage_adjoint = DTYPES[storage_adjoint]
     nb = ctypes.c_ulonglong()
@@ -246,6 +249,10 @@ class Registration:
 
     def set_velocity(self, v):
         self._chk(lib().cl_set_velocity(self._h, self._dev(v, 3 * self.N, "v")))
+
+    def layout(self):
+        """0: full memory layout, 1: lean (gradients by FD8 in the kernels)."""
+        return int(lib().cl_layout(self._h))
 
     def velocity(self):
         out = self.empty(3)

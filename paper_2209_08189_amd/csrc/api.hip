@@ -47,7 +47,8 @@ struct cl_ctx {
     void *lam = nullptr;                    // (nt+1) N, adjoint dtype
     void *q[2] = {nullptr, nullptr};        // adjoint dtype
     float *G = nullptr;                     // grad_h m^j, (nt+1) x 3N FP32
-    float *S = nullptr;                     // incremental sources s^1..s^nt, nt x N FP32
+    float *S = nullptr;                     // incremental sources s^1..s^nt, nt x N FP32 (lean: one field)
+    bool lean = false;                      // lean layout: no stored gradients, one source field
     int *box_f = nullptr, *box_b = nullptr, *box_t = nullptr;  // tile stencil boxes: X_f, X_b, scratch
     float *v = nullptr, *vtrial = nullptr;  // 3N
     float *df = nullptr, *db = nullptr;     // 3N
@@ -226,7 +227,7 @@ void ensure_state(cl_ctx *ctx)
 void ensure_sgrad(cl_ctx *ctx)
 {
     ensure_state(ctx);
-    if (ctx->sgrad) return;
+    if (ctx->sgrad || ctx->lean) return;
     StateGradArgs a{};
     for (int j = 0; j <= ctx->nt; ++j) {
         a.m[j] = slot(ctx, ctx->m, ctx->dts, j);
@@ -269,9 +270,12 @@ QuadArgs quad_args(cl_ctx *ctx)
 {
     QuadArgs qa{};
     qa.count = ctx->nt + 1;
+    qa.lean = ctx->lean ? 1 : 0;
+    qa.dt_m = ctx->dts;
     for (int j = 0; j <= ctx->nt; ++j) {
         qa.lam[j] = slot(ctx, ctx->lam, ctx->dta, j);
-        qa.G[j] = ctx->G + (size_t)j * 3 * ctx->N;
+        qa.m[j] = slot(ctx, ctx->m, ctx->dts, j);
+        qa.G[j] = ctx->lean ? nullptr : ctx->G + (size_t)j * 3 * ctx->N;
         qa.w[j] = (j == 0 || j == ctx->nt) ? 0.5f * ctx->dt : ctx->dt;
     }
     return qa;
@@ -322,16 +326,30 @@ void matvec(cl_ctx *ctx, const float *vt, float *Hvt, const float *Avt_known = n
     ensure_sgrad(ctx);
     const float dt = ctx->dt;
     const int nt = ctx->nt;
-    // sources s^j = -vt . grad_h m^j for all j, q^0 = dt/2 s^0
-    run(ctx, CL_K_VEC, [&] {
-        launch_inc_sources(ctx->g, ctx->G, vt, nt, 0.5f * dt, ctx->dta, ctx->q[0], ctx->S, ctx->s);
-    });
+    // sources s^j = -vt . grad_h m^j, q^0 = dt/2 s^0: all at once from the
+    // stored gradients, or one time level at a time by FD8 (lean layout)
+    if (ctx->lean) {
+        run(ctx, CL_K_VEC, [&] {
+            launch_inc_source_fd(ctx->g, ctx->dts, slot(ctx, ctx->m, ctx->dts, 0), vt, 0.5f * dt, ctx->dta,
+                                 ctx->q[0], ctx->s);
+        });
+    } else {
+        run(ctx, CL_K_VEC, [&] {
+            launch_inc_sources(ctx->g, ctx->G, vt, nt, 0.5f * dt, ctx->dta, ctx->q[0], ctx->S, ctx->s);
+        });
+    }
     for (int j = 0; j < nt; ++j) {
         const bool last = j == nt - 1;
         void *out = last ? slot(ctx, ctx->lam, ctx->dta, nt) : ctx->q[(j + 1) & 1];
+        const float *Sj = ctx->lean ? ctx->S : ctx->S + (size_t)j * ctx->N;
+        if (ctx->lean)
+            run(ctx, CL_K_VEC, [&] {
+                launch_inc_source_fd(ctx->g, ctx->dts, slot(ctx, ctx->m, ctx->dts, j + 1), vt, 1.0f, CL_F32,
+                                     ctx->S, ctx->s);
+            });
         run(ctx, CL_K_SL_INC, [&] {
-            launch_sl_inc(ctx->g, ctx->dta, ctx->q[j & 1], ctx->df, ctx->box_f, ctx->S + (size_t)j * ctx->N,
-                          last ? -1.0f : 1.0f, last ? -0.5f * dt : dt, ctx->dta, out, ctx->s);
+            launch_sl_inc(ctx->g, ctx->dta, ctx->q[j & 1], ctx->df, ctx->box_f, Sj, last ? -1.0f : 1.0f,
+                          last ? -0.5f * dt : dt, ctx->dta, out, ctx->s);
         });
     }
     adjoint_sweep(ctx);
@@ -502,7 +520,7 @@ int solve(cl_ctx *ctx, const int *forced_pcg, const double *forced_alpha, int fo
     return status;
 }
 
-size_t workspace_bytes(int n1, int n2, int n3, const cl_options &o)
+size_t workspace_bytes(int n1, int n2, int n3, const cl_options &o, bool lean)
 {
     const size_t N = (size_t)n1 * n2 * n3;
     const size_t es = dtype_size(o.storage_state), ea = dtype_size(o.storage_adjoint);
@@ -511,11 +529,11 @@ size_t workspace_bytes(int n1, int n2, int n3, const cl_options &o)
     b += (size_t)(o.nt + 1) * N * es;        // m^j
     b += (size_t)(o.nt + 1) * N * ea;        // lam^j / lam~^j
     b += 2 * N * ea;                         // q ping-pong
-    b += (size_t)(o.nt + 1) * 3 * N * sizeof(float);  // grad_h m^j
-    b += (size_t)o.nt * N * sizeof(float);   // incremental sources s^j
+    if (!lean) b += (size_t)(o.nt + 1) * 3 * N * sizeof(float);  // grad_h m^j
+    b += (size_t)(lean ? 1 : o.nt) * N * sizeof(float);   // incremental sources s^j
     b += 3 * (N / 2048 + 1) * 8 * sizeof(int);  // tile stencil boxes
     b += 2 * N * sizeof(float);              // c, div v
-    b += 13 * 3 * N * sizeof(float);         // v, vtrial, df, db, g, Av, tmp3, PCG x r z p Hp, feet workspace
+    b += 12 * 3 * N * sizeof(float);         // v, vtrial, df, db, g, Av, tmp3, PCG x r z p Hp
     b += fft_spec_bytes(n1, n2, n3, 3);
     b += 4 * 1025 * sizeof(float2) + 4096 * sizeof(double) + 256;   // FFT tables, reduction partials, scalars
     b += (std::max<size_t>((N / 4 + 255) / 256, 6 * (size_t)reduce_blocks(N)) + PCG_NSCAL) * sizeof(double);
@@ -595,7 +613,9 @@ int cl_query_workspace(int n1, int n2, int n3, const cl_options *opt, unsigned l
     int st = check_options(opt, nullptr);
     if (st) return st;
     if (!pow2_ok(n1) || !pow2_ok(n2) || !pow2_ok(n3)) return CL_ERR_SHAPE;
-    *bytes = workspace_bytes(n1, n2, n3, *opt);
+    const size_t full = workspace_bytes(n1, n2, n3, *opt, false);
+    const bool lean = opt->workspace_cap_bytes && full > opt->workspace_cap_bytes;
+    *bytes = lean ? workspace_bytes(n1, n2, n3, *opt, true) : full;
     return CL_OK;
 }
 
@@ -606,10 +626,20 @@ int cl_create(cl_ctx **out, int n1, int n2, int n3, const cl_options *opt)
     int st = check_options(opt, nullptr);
     if (st) return st;
     if (!pow2_ok(n1) || !pow2_ok(n2) || !pow2_ok(n3)) return CL_ERR_SHAPE;
-    const size_t need = workspace_bytes(n1, n2, n3, *opt);
-    if (opt->workspace_cap_bytes && need > opt->workspace_cap_bytes) return CL_ERR_OOM;
+    // layout: the full one when it fits the cap (or, without a cap, the free
+    // device memory), else the lean one; CL_ERR_OOM if neither fits the cap
+    const size_t full = workspace_bytes(n1, n2, n3, *opt, false);
+    size_t limit = opt->workspace_cap_bytes;
+    if (!limit) {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) == hipSuccess) limit = fr - fr / 16;
+    }
+    const bool lean = limit && full > limit;
+    if (lean && opt->workspace_cap_bytes && workspace_bytes(n1, n2, n3, *opt, true) > opt->workspace_cap_bytes)
+        return CL_ERR_OOM;
     cl_ctx *ctx = new (std::nothrow) cl_ctx();
     if (!ctx) return CL_ERR_OOM;
+    ctx->lean = lean;
     ctx->opt = *opt;
     ctx->s = (hipStream_t)opt->stream;
     ctx->nt = opt->nt;
@@ -639,8 +669,8 @@ int cl_create(cl_ctx **out, int n1, int n2, int n3, const cl_options *opt)
         ctx->lam = alloc((size_t)(ctx->nt + 1) * N * ea);
         ctx->q[0] = alloc(N * ea);
         ctx->q[1] = alloc(N * ea);
-        ctx->G = (float *)alloc((size_t)(ctx->nt + 1) * 3 * N * sizeof(float));
-        ctx->S = (float *)alloc((size_t)ctx->nt * N * sizeof(float));
+        if (!ctx->lean) ctx->G = (float *)alloc((size_t)(ctx->nt + 1) * 3 * N * sizeof(float));
+        ctx->S = (float *)alloc((size_t)(ctx->lean ? 1 : ctx->nt) * N * sizeof(float));
         {
             const size_t nb = std::max<size_t>(tile_box_ints(ctx->g), 8) * sizeof(int);
             ctx->box_f = (int *)alloc(nb);
@@ -648,8 +678,10 @@ int cl_create(cl_ctx **out, int n1, int n2, int n3, const cl_options *opt)
             ctx->box_t = (int *)alloc(nb);
         }
         float **vecs[] = {&ctx->v, &ctx->vtrial, &ctx->df, &ctx->db, &ctx->grad, &ctx->Av, &ctx->tmp3,
-                          &ctx->px, &ctx->pr, &ctx->pz, &ctx->pp, &ctx->pHp, &ctx->fscr};
+                          &ctx->px, &ctx->pr, &ctx->pz, &ctx->pp, &ctx->pHp};
         for (float **pv : vecs) *pv = (float *)alloc(3 * N * sizeof(float));
+        // the feet are computed outside PCG, where z is free
+        ctx->fscr = ctx->pz;
         ctx->c = (float *)alloc(N * sizeof(float));
         ctx->divv = (float *)alloc(N * sizeof(float));
         ctx->nparts = reduce_blocks(3 * N);
@@ -676,6 +708,12 @@ int cl_create(cl_ctx **out, int n1, int n2, int n3, const cl_options *opt)
     }
     *out = ctx;
     return CL_OK;
+}
+
+int cl_layout(const cl_ctx *ctx)
+{
+    if (!ctx) return CL_ERR_ARG;
+    return ctx->lean ? 1 : 0;
 }
 
 void cl_destroy(cl_ctx *ctx)

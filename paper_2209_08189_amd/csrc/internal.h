@@ -125,15 +125,21 @@ struct StateGradArgs {
     float *G[MAX_T];
 };
 void launch_state_grad(const Grid &g, int dt_m, const StateGradArgs &a, int count, hipStream_t s);
+// lean layout: out = scale * (-vt . grad_h m), FD8 in the kernel (out stored as dt_out)
+void launch_inc_source_fd(const Grid &g, int dt_m, const void *m, const float *vt, float scale, int dt_out, void *out,
+                          hipStream_t s);
 // incremental sources s^j = -vt . G^j (G^j = G + 3 N j): q0 = scale * s^0
 // (stored as dt_q) and S + N (j - 1) = s^j for j = 1..nt (FP32)
 void launch_inc_sources(const Grid &g, const float *G, const float *vt, int nt, float scale, int dt_q, void *q0,
                         float *S, hipStream_t s);
 struct QuadArgs {
     const void *lam[MAX_T];
-    const float *G[MAX_T];
+    const float *G[MAX_T];    // grad_h m^j (full layout)
+    const void *m[MAX_T];     // m^j, gradients by FD8 in the kernel (lean layout)
     float w[MAX_T];
     int count;
+    int lean;                 // 1: use m[] (storage dtype dt_m), 0: use G[]
+    int dt_m;
 };
 // out3 = addend3 (may be NULL) + sum_j w_j lam^j G^j
 void launch_quadrature(const Grid &g, int dt_lam, const QuadArgs &qa, const float *addend3, float *out3, hipStream_t s);

@@ -146,6 +146,60 @@ __global__ __launch_bounds__(TPB) void k_quadrature(Grid g, QuadArgs qa, const f
     }
 }
 
+// Lean layout (no stored gradients): the same quadrature with grad_h m^j
+// taken by FD8 in the kernel, four consecutive x3 nodes per thread.
+template <typename Tm, typename Tl>
+__global__ __launch_bounds__(TPB) void k_quadrature_fd(Grid g, QuadArgs qa, const float *__restrict__ add,
+                                                       float *__restrict__ out, const float *__restrict__ dp,
+                                                       double *__restrict__ partials)
+{
+    const size_t N = g.N;
+    const int p0 = (blockIdx.x * TPB + threadIdx.x) * 4;
+    double acc = 0.0;
+    if (p0 < g.N) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int p = p0 + u;
+            float b0 = 0.f, b1 = 0.f, b2 = 0.f;
+            for (int t = 0; t < qa.count; ++t) {
+                const float wl = qa.w[t] * ldf((const Tl *)qa.lam[t] + p);
+                float gr[3];
+                grad_at(g, (const Tm *)qa.m[t], p, gr);
+                b0 = fmaf(wl, gr[0], b0);
+                b1 = fmaf(wl, gr[1], b1);
+                b2 = fmaf(wl, gr[2], b2);
+            }
+            if (add) {
+                b0 += add[p];
+                b1 += add[N + p];
+                b2 += add[2 * N + p];
+            }
+            out[p] = b0;
+            out[N + p] = b1;
+            out[2 * N + p] = b2;
+            if (dp) acc += (double)dp[p] * b0 + (double)dp[N + p] * b1 + (double)dp[2 * N + p] * b2;
+        }
+    }
+    if (dp) {
+        acc = block_sum(acc);
+        if (threadIdx.x == 0) partials[blockIdx.x] = acc;
+    }
+}
+
+// Lean layout: out = scale * (-vt . grad_h m), FD8 in the kernel.
+template <typename Tm, typename To>
+__global__ __launch_bounds__(TPB) void k_inc_source_fd(Grid g, const Tm *__restrict__ m, const float *__restrict__ vt,
+                                                       float scale, To *__restrict__ out)
+{
+    const size_t N = g.N;
+    const int p = blockIdx.x * TPB + threadIdx.x;
+    if (p >= g.N) return;
+    float gr[3];
+    grad_at(g, m, p, gr);
+    const float r = -(vt[p] * gr[0] + vt[N + p] * gr[1] + vt[2 * N + p] * gr[2]);
+    stf(out + p, scale * r);
+}
+
 // lam^nt = m1 - m^nt and per-block partial sums of its square, grid-stride.
 template <typename Tm, typename Tl>
 __global__ __launch_bounds__(TPB) void k_residual(Grid g, const Tm *__restrict__ m1, const Tm *__restrict__ mN,
@@ -203,8 +257,29 @@ void launch_quadrature_dot(const Grid &g, int dt_lam, const QuadArgs &qa, const 
 {
     with_dtype(dt_lam, [&](auto tl) {
         using Tl = decltype(tl);
-        hipLaunchKernelGGL((k_quadrature<Tl>), dim3(quadrature_blocks(g)), dim3(TPB), 0, s, g, qa, addend3, out3, dp,
-                           partials);
+        if (qa.lean) {
+            with_dtype(qa.dt_m, [&](auto tm) {
+                using Tm = decltype(tm);
+                hipLaunchKernelGGL((k_quadrature_fd<Tm, Tl>), dim3(quadrature_blocks(g)), dim3(TPB), 0, s, g, qa,
+                                   addend3, out3, dp, partials);
+            });
+        } else {
+            hipLaunchKernelGGL((k_quadrature<Tl>), dim3(quadrature_blocks(g)), dim3(TPB), 0, s, g, qa, addend3, out3,
+                               dp, partials);
+        }
+    });
+}
+
+void launch_inc_source_fd(const Grid &g, int dt_m, const void *m, const float *vt, float scale, int dt_out, void *out,
+                          hipStream_t s)
+{
+    with_dtype(dt_m, [&](auto tm) {
+        using Tm = decltype(tm);
+        with_dtype(dt_out, [&](auto to) {
+            using To = decltype(to);
+            hipLaunchKernelGGL((k_inc_source_fd<Tm, To>), dim3((g.N + TPB - 1) / TPB), dim3(TPB), 0, s, g,
+                               (const Tm *)m, vt, scale, (To *)out);
+        });
     });
 }
 

@@ -178,6 +178,47 @@ def test_objective_and_precond():
     assert rel(host(r.precond(dev(x))), o.precond(x)) < TOL_KERNEL
 
 
+@pytest.mark.parametrize("st", ["f32", "f16"])
+def test_lean_layout(st):
+    """Lean memory layout (chosen when the full one exceeds the workspace
+    cap): gradients of m^j by FD8 inside the source and quadrature kernels,
+    one source field.  Same operators as the full layout: transports, g and
+    Hv against the FP64 oracle (FP32 storage) and against the full layout to
+    FP32 rounding-order differences."""
+    from paper_2209_08189_amd.claire import query_workspace
+    n = 64
+    shape, m0, m1, vs = _cfg1(n)
+    v = f32(0.5 * vs)
+    o = oracle.Oracle(shape, nt=4, beta=5e-4)
+    o.set_images(m0, m1)
+    o.set_velocity(v)
+    cap = query_workspace(shape, storage_state=st, storage_adjoint=st, workspace_cap=1)
+    assert cap < query_workspace(shape, storage_state=st, storage_adjoint=st)
+    ctx = {}
+    for name, kw in (("full", {}), ("lean", {"workspace_cap": cap})):
+        r = reg(shape, storage_state=st, storage_adjoint=st, **kw)
+        r.set_images(dev(m0), dev(m1))
+        r.set_velocity(dev(v))
+        ctx[name] = r
+    assert ctx["full"].layout() == 0 and ctx["lean"].layout() == 1
+    vt = f32(synth.trig_velocity(shape, 0.3)[[2, 0, 1]] + 0.1 * synth.random_field((3,) + shape, 9))
+    out = {}
+    for name, r in ctx.items():
+        g, _, _ = r.gradient()
+        Hv = r.hessian_matvec(dev(vt))
+        out[name] = (host(g), host(Hv), host(r.field(2, 4)), host(r.field(3, 0)))
+    gl, Hl = out["lean"][0], out["lean"][1]
+    print("lean %s: g vs full %.2e, Hv vs full %.2e" % (st, rel(gl, out["full"][0]), rel(Hl, out["full"][1])))
+    for a, b in zip(out["lean"], out["full"]):
+        assert rel(a, b) < 1e-5
+    if st == "f32":
+        g_ref, _ = o.gradient()
+        Hv_ref = o.matvec(vt)
+        assert rel(gl, g_ref) < TOL_OP and rel(Hl, Hv_ref) < TOL_OP
+        assert rel(out["lean"][2], o.field(oracle.FIELD_INC_STATE, 4)) < TOL_KERNEL
+        assert rel(out["lean"][3], o.field(oracle.FIELD_INC_ADJOINT, 0)) < TOL_KERNEL
+
+
 # ------------------------------------------------ mixed-precision storage
 
 UROUND = {"f16": 2.0 ** -11, "bf16": 2.0 ** -8, "f32": 2.0 ** -24}
