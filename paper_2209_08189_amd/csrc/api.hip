@@ -362,7 +362,7 @@ void matvec(cl_ctx *ctx, const float *vt, float *Hvt, const float *Avt_known = n
     if (dot_out) {
         run(ctx, CL_K_QUAD, [&] {
             launch_quadrature_dot(ctx->g, ctx->dta, qa, Avt, Hvt, vt, ctx->qparts, ctx->s);
-            launch_finalize(ctx->qparts, quadrature_blocks(ctx->g), ctx->hv, dot_out, ctx->s);
+            launch_finalize(ctx->qparts, quadrature_blocks(ctx->g, qa), ctx->hv, dot_out, ctx->s);
         });
     } else {
         run(ctx, CL_K_QUAD, [&] { launch_quadrature(ctx->g, ctx->dta, qa, Avt, Hvt, ctx->s); });
@@ -687,7 +687,7 @@ int cl_create(cl_ctx **out, int n1, int n2, int n3, const cl_options *opt)
         ctx->nparts = reduce_blocks(3 * N);
         ctx->partials = (double *)alloc(ctx->nparts * sizeof(double));
         ctx->dscal = (double *)alloc(sizeof(double) * 4);
-        ctx->nqparts = std::max(quadrature_blocks(ctx->g), 6 * reduce_blocks(ctx->N));
+        ctx->nqparts = std::max(quadrature_blocks_max(ctx->g), 6 * reduce_blocks(ctx->N));
         ctx->qparts = (double *)alloc(sizeof(double) * ctx->nqparts);
         ctx->pscal = (double *)alloc(sizeof(double) * PCG_NSCAL);
         if (hipHostMalloc((void **)&ctx->hscal, sizeof(double) * PCG_NSCAL, hipHostMallocDefault) != hipSuccess)

@@ -143,8 +143,12 @@ struct QuadArgs {
 };
 // out3 = addend3 (may be NULL) + sum_j w_j lam^j G^j
 void launch_quadrature(const Grid &g, int dt_lam, const QuadArgs &qa, const float *addend3, float *out3, hipStream_t s);
-// same, and per-block FP64 partial sums of dp . out3 in partials[0 .. quadrature_blocks(g))
-int quadrature_blocks(const Grid &g);
+// same, and per-block FP64 partial sums of dp . out3 in partials[0 .. quadrature_blocks(g, qa))
+int quadrature_blocks(const Grid &g, const QuadArgs &qa);
+// largest block count any quadrature launch on g uses (partials buffer size)
+int quadrature_blocks_max(const Grid &g);
+// whether the quadrature of qa on g runs the marching FD8 kernel (lean layout)
+bool quadrature_marches(const Grid &g, const QuadArgs &qa);
 void launch_quadrature_dot(const Grid &g, int dt_lam, const QuadArgs &qa, const float *addend3, float *out3,
                            const float *dp, double *partials, hipStream_t s);
 // lam = m1 - mN (stored as dt_lam); partial sums of (m1 - mN)^2 per block

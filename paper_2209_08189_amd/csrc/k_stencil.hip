@@ -6,6 +6,8 @@
 // x1/x2 are re-read from L2 by neighbouring workgroups.
 #include "internal.h"
 
+#include <algorithm>
+
 namespace clh {
 
 namespace {
@@ -200,6 +202,164 @@ __global__ __launch_bounds__(TPB) void k_inc_source_fd(Grid g, const Tm *__restr
     stf(out + p, scale * r);
 }
 
+// ------------------------------------------------ FD8 by marching along x1
+// Lean-layout consumers of grad_h m on grids whose +-4 planes along x1 do not
+// stay in L2 (a plane of a 1024^3 grid is 4 MiB): a block owns a 64 (x3) by
+// 8 (x2) tile of nodes, one per thread, and walks a chunk of planes along x1.
+// Each thread keeps m(i-4 .. i+4) at its (x2, x3) position in registers and
+// loads one new plane per step, so m is read from HBM once per chunk (plus 8
+// halo planes); the current plane with a 4-node halo in x2 and x3 is staged
+// in LDS for the other two derivatives (two buffers: one barrier per step).
+// Every derivative is the same expression, in the same order, as fd8().
+constexpr int MX = 64, MY = 8, MH = 4;
+constexpr int MPX = MX + 2 * MH, MPY = MY + 2 * MH;    // staged plane 72 x 16
+constexpr int TPB_M = MX * MY;                         // 512 threads, wave w = row w
+constexpr int MAX_NL = 5;                              // time levels kept in registers
+
+struct MarchGeom {
+    int ntx, nty;   // tiles along x3 and x2
+    int ch;         // planes per chunk along x1
+};
+
+__device__ __forceinline__ float fd8_ring(const float *u, float ih)   // u[4] is the centre
+{
+    float s = 0.8f * (u[5] - u[3]);
+    s = fmaf(-0.2f, u[6] - u[2], s);
+    s = fmaf(4.0f / 105.0f, u[7] - u[1], s);
+    s = fmaf(-1.0f / 280.0f, u[8] - u[0], s);
+    return s * ih;
+}
+
+__device__ __forceinline__ float fd8_lds(const float *c, int st, float ih)   // c -> centre, stride st
+{
+    float s = 0.8f * (c[st] - c[-st]);
+    s = fmaf(-0.2f, c[2 * st] - c[-2 * st], s);
+    s = fmaf(4.0f / 105.0f, c[3 * st] - c[-3 * st], s);
+    s = fmaf(-1.0f / 280.0f, c[4 * st] - c[-4 * st], s);
+    return s * ih;
+}
+
+// MODE 0: out3 = add + sum_t w_t lam^t grad_h m^t (NL = qa.count levels),
+//         optional FP64 partials of dp . out3 per block.
+// MODE 1: out1 = scale * (-vt . grad_h m^0) (NL = 1).
+template <typename Tm, typename Tl, typename To, int NL, int MODE>
+__global__ __launch_bounds__(TPB_M) void k_fd_march(Grid g, MarchGeom mg, QuadArgs qa, const float *__restrict__ add,
+                                                    float *__restrict__ out3, const float *__restrict__ dp,
+                                                    double *__restrict__ partials, const float *__restrict__ vt,
+                                                    float scale, To *__restrict__ out1)
+{
+    __shared__ float pl[2][NL][MPY][MPX];
+    const size_t N = g.N;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    // XCD-aware order: each XCD takes a contiguous range of tiles, so the
+    // x2 neighbours of a tile run on the same L2
+    int b = blockIdx.x;
+    const int nb = gridDim.x;
+    if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);
+    const int tx = b % mg.ntx;
+    b /= mg.ntx;
+    const int ty = b % mg.nty;
+    const int i0 = (b / mg.nty) * mg.ch;
+    const int l23 = g.l2 + g.l3, m1 = g.n1 - 1;
+    const int k = tx * MX + lane, j = ty * MY + w;
+    const int col = (j << g.l3) + k;                                     // offset inside a plane
+    const int hr = w < MH ? w - MH : w + MH;                             // x2 halo row of this thread
+    const int hcol = (((ty * MY + hr) & (g.n2 - 1)) << g.l3) + k;
+    const bool xh = lane < 2 * MH;                                       // lanes that load the x3 halo
+    const int xc = lane < MH ? lane - MH : MX + lane - MH;
+    const int xcol = (j << g.l3) + ((tx * MX + xc) & (g.n3 - 1));
+    const Tm *mp[NL];
+#pragma unroll
+    for (int t = 0; t < NL; ++t) mp[t] = (const Tm *)qa.m[t];
+
+    float ring[NL][9], nxt[NL], hv[NL], xv[NL];
+#pragma unroll
+    for (int t = 0; t < NL; ++t) {
+#pragma unroll
+        for (int s = 0; s < 8; ++s) ring[t][s] = ldf(mp[t] + ((((i0 - MH + s) & m1) << l23) + col));
+        const int base = (i0 & m1) << l23;
+        hv[t] = ldf(mp[t] + base + hcol);
+        xv[t] = xh ? ldf(mp[t] + base + xcol) : 0.f;
+        nxt[t] = ldf(mp[t] + ((((i0 + MH) & m1) << l23) + col));
+    }
+    double acc = 0.0;
+    for (int step = 0; step < mg.ch; ++step) {
+        const int i = i0 + step;
+        const int buf = step & 1;
+        const int p = ((i & m1) << l23) + col;
+#pragma unroll
+        for (int t = 0; t < NL; ++t) {
+            ring[t][8] = nxt[t];
+            pl[buf][t][w + MH][lane + MH] = ring[t][4];
+            pl[buf][t][hr + MH][lane + MH] = hv[t];
+            if (xh) pl[buf][t][w + MH][xc + MH] = xv[t];
+        }
+        // operands of this plane's epilogue
+        float lw[NL], e0, e1, e2;
+        if (MODE == 0) {
+#pragma unroll
+            for (int t = 0; t < NL; ++t) lw[t] = qa.w[t] * ldf((const Tl *)qa.lam[t] + p);
+            e0 = add ? add[p] : 0.f;
+            e1 = add ? add[N + p] : 0.f;
+            e2 = add ? add[2 * N + p] : 0.f;
+        } else {
+            e0 = vt[p];
+            e1 = vt[N + p];
+            e2 = vt[2 * N + p];
+        }
+        __syncthreads();
+        // prefetch the next plane's halo and the plane i + 5 of the ring
+        if (step + 1 < mg.ch) {
+            const int nbase = ((i + 1) & m1) << l23;
+            const int rbase = ((i + 1 + MH) & m1) << l23;
+#pragma unroll
+            for (int t = 0; t < NL; ++t) {
+                hv[t] = ldf(mp[t] + nbase + hcol);
+                if (xh) xv[t] = ldf(mp[t] + nbase + xcol);
+                nxt[t] = ldf(mp[t] + rbase + col);
+            }
+        }
+        float b0 = 0.f, b1 = 0.f, b2 = 0.f;
+#pragma unroll
+        for (int t = 0; t < NL; ++t) {
+            const float *c = &pl[buf][t][w + MH][lane + MH];
+            const float d0 = fd8_ring(ring[t], g.ih1);
+            const float d1 = fd8_lds(c, MPX, g.ih2);
+            const float d2 = fd8_lds(c, 1, g.ih3);
+            if (MODE == 0) {
+                b0 = fmaf(lw[t], d0, b0);
+                b1 = fmaf(lw[t], d1, b1);
+                b2 = fmaf(lw[t], d2, b2);
+            } else {
+                b0 = d0;
+                b1 = d1;
+                b2 = d2;
+            }
+        }
+        if (MODE == 0) {
+            if (add) {
+                b0 += e0;
+                b1 += e1;
+                b2 += e2;
+            }
+            out3[p] = b0;
+            out3[N + p] = b1;
+            out3[2 * N + p] = b2;
+            if (dp) acc += (double)dp[p] * b0 + (double)dp[N + p] * b1 + (double)dp[2 * N + p] * b2;
+        } else {
+            stf(out1 + p, scale * -(e0 * b0 + e1 * b1 + e2 * b2));
+        }
+#pragma unroll
+        for (int t = 0; t < NL; ++t)
+#pragma unroll
+            for (int s = 0; s < 8; ++s) ring[t][s] = ring[t][s + 1];
+    }
+    if (MODE == 0 && dp) {
+        acc = block_sum(acc);
+        if (threadIdx.x == 0) partials[blockIdx.x] = acc;
+    }
+}
+
 // lam^nt = m1 - m^nt and per-block partial sums of its square, grid-stride.
 template <typename Tm, typename Tl>
 __global__ __launch_bounds__(TPB) void k_residual(Grid g, const Tm *__restrict__ m1, const Tm *__restrict__ mN,
@@ -250,22 +410,79 @@ void launch_quadrature(const Grid &g, int dt_lam, const QuadArgs &qa, const floa
     launch_quadrature_dot(g, dt_lam, qa, addend3, out3, nullptr, nullptr, s);
 }
 
-int quadrature_blocks(const Grid &g) { return (int)((g.N / 4 + TPB - 1) / TPB); }
+namespace {
+
+// The marching kernels need whole 64 x 8 tiles in (x3, x2).  Chunk length
+// along x1: 64 planes (8 halo planes per chunk, 12.5 % extra reads of m),
+// halved down to 16 until the launch has at least 2048 blocks.
+bool march_ok(const Grid &g) { return g.n3 >= MX && g.n2 >= MY; }
+
+MarchGeom march_geom(const Grid &g)
+{
+    MarchGeom mg;
+    mg.ntx = g.n3 / MX;
+    mg.nty = g.n2 / MY;
+    mg.ch = std::min(g.n1, 64);
+    while (mg.ch > 16 && (long)mg.ntx * mg.nty * (g.n1 / mg.ch) < 2048) mg.ch /= 2;
+    return mg;
+}
+
+int march_blocks(const Grid &g)
+{
+    const MarchGeom mg = march_geom(g);
+    return mg.ntx * mg.nty * (g.n1 / mg.ch);
+}
+
+template <typename Tm, typename Tl>
+void launch_quad_march(const Grid &g, const QuadArgs &qa, const float *add, float *out3, const float *dp,
+                       double *partials, hipStream_t s)
+{
+    const MarchGeom mg = march_geom(g);
+    const dim3 grid(march_blocks(g));
+    switch (qa.count) {
+#define CLH_QM(NL)                                                                                                   \
+    case NL:                                                                                                         \
+        hipLaunchKernelGGL((k_fd_march<Tm, Tl, float, NL, 0>), grid, dim3(TPB_M), 0, s, g, mg, qa, add, out3, dp,    \
+                           partials, (const float *)nullptr, 0.f, (float *)nullptr);                                 \
+        break;
+        CLH_QM(1) CLH_QM(2) CLH_QM(3) CLH_QM(4) CLH_QM(5)
+#undef CLH_QM
+    }
+}
+
+} // namespace
+
+bool quadrature_marches(const Grid &g, const QuadArgs &qa) { return qa.lean && march_ok(g) && qa.count <= MAX_NL; }
+
+int quadrature_blocks(const Grid &g, const QuadArgs &qa)
+{
+    return quadrature_marches(g, qa) ? march_blocks(g) : (int)((g.N / 4 + TPB - 1) / TPB);
+}
+
+int quadrature_blocks_max(const Grid &g)
+{
+    return std::max((int)((g.N / 4 + TPB - 1) / TPB), march_ok(g) ? march_blocks(g) : 0);
+}
 
 void launch_quadrature_dot(const Grid &g, int dt_lam, const QuadArgs &qa, const float *addend3, float *out3,
                            const float *dp, double *partials, hipStream_t s)
 {
     with_dtype(dt_lam, [&](auto tl) {
         using Tl = decltype(tl);
-        if (qa.lean) {
+        if (quadrature_marches(g, qa)) {
             with_dtype(qa.dt_m, [&](auto tm) {
                 using Tm = decltype(tm);
-                hipLaunchKernelGGL((k_quadrature_fd<Tm, Tl>), dim3(quadrature_blocks(g)), dim3(TPB), 0, s, g, qa,
+                launch_quad_march<Tm, Tl>(g, qa, addend3, out3, dp, partials, s);
+            });
+        } else if (qa.lean) {
+            with_dtype(qa.dt_m, [&](auto tm) {
+                using Tm = decltype(tm);
+                hipLaunchKernelGGL((k_quadrature_fd<Tm, Tl>), dim3(quadrature_blocks(g, qa)), dim3(TPB), 0, s, g, qa,
                                    addend3, out3, dp, partials);
             });
         } else {
-            hipLaunchKernelGGL((k_quadrature<Tl>), dim3(quadrature_blocks(g)), dim3(TPB), 0, s, g, qa, addend3, out3,
-                               dp, partials);
+            hipLaunchKernelGGL((k_quadrature<Tl>), dim3(quadrature_blocks(g, qa)), dim3(TPB), 0, s, g, qa, addend3,
+                               out3, dp, partials);
         }
     });
 }
@@ -277,8 +494,17 @@ void launch_inc_source_fd(const Grid &g, int dt_m, const void *m, const float *v
         using Tm = decltype(tm);
         with_dtype(dt_out, [&](auto to) {
             using To = decltype(to);
-            hipLaunchKernelGGL((k_inc_source_fd<Tm, To>), dim3((g.N + TPB - 1) / TPB), dim3(TPB), 0, s, g,
-                               (const Tm *)m, vt, scale, (To *)out);
+            if (march_ok(g)) {
+                QuadArgs qa{};
+                qa.m[0] = m;
+                qa.count = 1;
+                hipLaunchKernelGGL((k_fd_march<Tm, float, To, 1, 1>), dim3(march_blocks(g)), dim3(TPB_M), 0, s, g,
+                                   march_geom(g), qa, (const float *)nullptr, (float *)nullptr,
+                                   (const float *)nullptr, (double *)nullptr, vt, scale, (To *)out);
+            } else {
+                hipLaunchKernelGGL((k_inc_source_fd<Tm, To>), dim3((g.N + TPB - 1) / TPB), dim3(TPB), 0, s, g,
+                                   (const Tm *)m, vt, scale, (To *)out);
+            }
         });
     });
 }

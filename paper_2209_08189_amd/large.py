@@ -1,0 +1,124 @@
+"""The large single-GPU configuration: a 1024^3 phantom pair (about 400
+blobs, widths 4-60 voxels, band-limited texture on 64 <= |k| <= 256,
+velocity of 20-voxel maximum displacement, n_t = 4), FP32 and 16-bit field
+storage; each context takes the full memory layout when it fits the free
+device memory and the lean one otherwise.  Reports the layout and device
+workspace, the per-kernel launch times and algorithmic GB/s from a capped
+solve, the exact integer-shift roll at this size, and the solve's progress
+(time, GN / PCG iterations, relative mismatch and gradient per GN
+iteration, Dice of the warped labels).
+
+    python -m paper_2209_08189_amd.large [--n 1024] [--max-outer 4] > result.json
+"""
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+# algorithmic bytes per launch in FP32 fields (one value per node), as in
+# the benchmark; 16-bit storage halves the gathered field and the output
+ALG_F = {"sl_state": 5, "sl_adjoint": 6, "sl_inc": 6}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--n", type=int, default=1024)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--max-outer", type=int, default=4)
+    ap.add_argument("--max-pcg", type=int, default=40)
+    ap.add_argument("--storage", default="f32,f16")
+    a = ap.parse_args()
+    log = lambda m: print("[large] " + m, file=sys.stderr, flush=True)
+    from . import synth
+    n = a.n
+    shape = (n, n, n)
+    t = time.perf_counter()
+    img, lab0 = synth.phantom_large(shape, a.seed, log=log)
+    log("phantom %.1f s" % (time.perf_counter() - t))
+    v_true = synth.smooth_velocity_large(shape, a.seed + 1, kmax=8.0, max_disp_voxels=20.0, log=log)
+    n0 = synth.noise32(shape, a.seed + 2, 0.02)
+    n1 = synth.noise32(shape, a.seed + 3, 0.02)
+    log("inputs %.1f s" % (time.perf_counter() - t))
+    import torch
+    from .claire import K_NAMES, Registration, query_workspace
+    from .metrics import dice, warp_labels
+    torch.cuda.set_device(0)
+    dev = lambda x: torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    out = {"n": n, "seed": a.seed, "max_outer": a.max_outer, "max_pcg": a.max_pcg, "runs": {}}
+    F = 4.0 * n ** 3
+    for st in a.storage.split(","):
+        reg = Registration(shape, max_outer=a.max_outer, max_pcg=a.max_pcg, storage_state=st, storage_adjoint=st)
+        run = {"storage": st, "layout": "lean" if reg.layout() else "full",
+               "workspace_GB": query_workspace(shape, storage_state=st, storage_adjoint=st,
+                                               workspace_cap=torch.cuda.mem_get_info()[0] if reg.layout() else 0) / 1e9}
+        log("%s: layout %s" % (st, run["layout"]))
+        # m1 = phantom transported by v_true and the labels of m1, made once
+        # by the first (FP32) context and kept on the host; device tensors
+        # are freed as soon as the context holds a copy
+        if "m1" not in out:
+            x = dev(img)
+            reg.set_images(x, x)
+            del x
+            vd = dev(v_true)
+            reg.set_velocity(vd)
+            del vd
+            m1h = reg.deformed_template()
+            out["m1"] = (m1h + dev(n1)).cpu()
+            del m1h
+            out["lab1"] = warp_labels(lab0, None, reg=reg).cpu()
+        m1 = out["m1"]
+        lab1 = out["lab1"]
+        # exact roll: 4 voxels per unit time along x1 -> m(1) = roll(m0, 4)
+        vs = torch.zeros((3,) + shape, dtype=torch.float32, device="cuda")
+        vs[0] = (2 * np.pi / n) * 4
+        reg.set_velocity(vs)
+        del vs
+        x = dev(img)
+        reg.set_images(x, x)
+        rolled = reg.deformed_template()
+        xs = x if st == "f32" else x.to(torch.float16 if st == "f16" else torch.bfloat16).float()
+        run["exact_roll"] = bool(torch.equal(rolled, torch.roll(xs, 4, dims=0)))
+        del xs
+        del rolled, x
+        m0 = torch.from_numpy(img + n0)
+        mis0 = 0.5 * float(((m0.double() - m1.double()) ** 2).sum()) * (2 * np.pi / n) ** 3
+        x0, x1 = m0.cuda(), m1.cuda()
+        reg.set_images(x0, x1)
+        del x0, x1, m0
+        reg.set_velocity(torch.zeros((3,) + shape, dtype=torch.float32, device="cuda"))
+        torch.cuda.empty_cache()
+        reg.profile_enable(0xFF)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rep = reg.solve()
+        torch.cuda.synchronize()
+        run["solve_s"] = time.perf_counter() - t0
+        kern = {}
+        for k, name in enumerate(K_NAMES):
+            ms, cnt = reg.profile_query(k)
+            if cnt:
+                kern[name] = {"launches": cnt, "avg_launch_ms": ms / cnt}
+                if name in ALG_F:
+                    kern[name]["alg_GBs"] = ALG_F[name] * F / (ms / cnt * 1e-3) / 1e9
+        reg.profile_enable(0)
+        run.update({"gn": rep["outer_iters"], "pcg": rep["pcg_iters_total"], "status": rep["status_name"],
+                    "rel_grad": rep["gnorm"] / rep["gref"], "r": rep["mismatch"] / mis0, "kernels": kern})
+        # per GN iteration: relative mismatch, relative gradient, PCG iterations, step length
+        run["history"] = [{"r": row[2] / mis0, "rel_grad": row[4] / rep["gref"], "pcg": int(row[5]),
+                           "alpha": row[6]} for row in reg.solve_log()]
+        run["dice_pre"] = dice(lab0, lab1)
+        run["dice_post"] = dice(warp_labels(lab0, None, reg=reg), lab1)   # the solved velocity
+        log("%s: %s" % (st, json.dumps({k: x for k, x in run.items() if k not in ("kernels",)})))
+        out["runs"][st] = run
+        reg.close()
+        del reg
+        torch.cuda.empty_cache()
+    out.pop("m1", None)
+    out.pop("lab1", None)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -31,23 +31,39 @@ def dice(la, lb, labels=(1, 2, 3)):
             "D_ivw": float((inv * D).sum() / inv.sum()) if inv.sum() else 1.0}
 
 
-def warp_labels(labels, v, nlabels=4):
+def warp_labels(labels, v, nlabels=4, reg=None):
     """Label map transported by the velocity v (device tensor [3, n1, n2, n3])
     through the library's forward semi-Lagrangian solve; returns a device
-    uint8 tensor."""
+    uint8 tensor.  reg: an existing context of the same grid to use (its
+    images are replaced; v = None keeps its current velocity), else a
+    temporary one."""
     import torch
     from .claire import Registration
-    shape = tuple(v.shape[1:])
-    lab = torch.as_tensor(_np(labels).astype(np.int64)).cuda()
-    reg = Registration(shape)
-    reg.set_velocity(v)
-    warped = []
+    lab = torch.as_tensor(_np(labels)).cuda()
+    shape = tuple(lab.shape)
+    own = reg is None
+    if own:
+        reg = Registration(shape)
+    if v is not None:
+        reg.set_velocity(v)
+    best = None
+    arg = torch.zeros(shape, dtype=torch.uint8, device="cuda")
     for i in range(nlabels):
         ind = (lab == i).float()
         reg.set_images(ind, ind)
-        warped.append(reg.deformed_template())
-    reg.close()
-    return torch.argmax(torch.stack(warped), dim=0).to(torch.uint8)
+        del ind
+        w = reg.deformed_template()
+        # running argmax; ties keep the lower label
+        if best is None:
+            best = w
+        else:
+            take = w > best
+            torch.maximum(best, w, out=best)
+            arg[take] = i
+            del take, w
+    if own:
+        reg.close()
+    return arg
 
 
 def relative_mismatch(m1, mt, m0):

@@ -143,3 +143,113 @@ def smooth_random_field(shape, seed, kmax=4.0):
     coef[idx] = rng.standard_normal(len(idx[0])) + 1j * rng.standard_normal(len(idx[0]))
     u = sfft.ifftn(coef, workers=FFT_WORKERS).real
     return u / np.abs(u).max()
+
+
+# ----------------------------------------------------------- large grids
+# The same recipes for grids where full 3D FP64 work is too slow on the
+# host: FP32 arrays, the blob sum as one GEMM, the band-limited velocity
+# evaluated separably from its few Fourier modes.
+
+def phantom_large(shape, seed, n_blobs=(380, 420), sigma=(4.0, 60.0), smooth_sigma=1.0, texture=0.05,
+                  kband=(64.0, 256.0), intensities=(0.0, 0.3, 0.6, 0.9), bg_frac=0.15, log=None):
+    """Phantom of the large-grid configuration (FP32): blobs as in phantom()
+    (more of them, wider range of widths), the same 4 classes, Gaussian
+    smoothing, then band-limited texture (random complex coefficients of
+    flat amplitude on kband[0] <= |k| <= kband[1], scaled to standard
+    deviation `texture`) added inside the foreground; clipped to [0, 1].
+    Returns (image float32, labels uint8); log(msg) reports the steps."""
+    log = log or (lambda m: None)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    shape = tuple(int(s) for s in shape)
+    nb = int(rng.integers(n_blobs[0], n_blobs[1] + 1))
+    axes = [np.arange(n, dtype=np.float64) for n in shape]
+    G = [np.empty((nb, n), dtype=np.float32) for n in shape]
+    for b in range(nb):
+        c = [rng.uniform(0.2 * n, 0.8 * n) for n in shape]
+        s = rng.uniform(sigma[0], sigma[1])
+        a = rng.uniform(0.5, 1.0)
+        for ax, n, cc, Gd in zip(axes, shape, c, G):
+            d = np.abs(ax - cc)
+            d = np.minimum(d, n - d)
+            Gd[b] = np.exp(-0.5 * (d / s) ** 2)
+        G[0][b] *= a
+    G23 = (G[1][:, :, None] * G[2][:, None, :]).reshape(nb, -1)
+    S = (G[0].T @ G23).reshape(shape)
+    del G23
+    log("blob sum of %d blobs" % nb)
+    thr = bg_frac * S.max()
+    fg = S >= thr
+    q1, q2 = np.quantile(S[fg], [1.0 / 3.0, 2.0 / 3.0])
+    labels = np.zeros(shape, dtype=np.uint8)
+    labels[fg] = 1
+    labels[S >= q1] = 2
+    labels[S >= q2] = 3
+    labels[~fg] = 0
+    del S, fg
+    log("labels")
+    img = np.asarray(intensities, dtype=np.float32)[labels]
+    k1, k2, k3 = (_fft_k(n) for n in shape)
+    h = [TWO_PI / n for n in shape]
+    if smooth_sigma > 0:
+        mult = (np.exp(-0.5 * (smooth_sigma * h[0] * k1) ** 2)[:, None, None]
+                * np.exp(-0.5 * (smooth_sigma * h[1] * k2) ** 2)[None, :, None]
+                * np.exp(-0.5 * (smooth_sigma * h[2] * k3[: shape[2] // 2 + 1]) ** 2)[None, None, :]).astype(np.float32)
+        img = sfft.irfftn(sfft.rfftn(img, workers=FFT_WORKERS) * mult, s=shape, workers=FFT_WORKERS).astype(np.float32)
+        del mult
+        log("smoothing")
+    if texture > 0:
+        kh = k3[: shape[2] // 2 + 1]
+        ksq = (k1.astype(np.float32)[:, None, None] ** 2 + k2.astype(np.float32)[None, :, None] ** 2
+               + kh.astype(np.float32)[None, None, :] ** 2)
+        band = (ksq >= kband[0] ** 2) & (ksq <= kband[1] ** 2)
+        del ksq
+        nz = int(band.sum())
+        coef = np.zeros(band.shape, dtype=np.complex64)
+        coef[band] = (rng.standard_normal(nz, dtype=np.float32) + 1j * rng.standard_normal(nz, dtype=np.float32))
+        del band
+        tex = sfft.irfftn(coef, s=shape, workers=FFT_WORKERS).astype(np.float32)
+        del coef
+        tex *= texture / max(float(tex.std()), 1e-30)
+        img += np.where(labels > 0, tex, np.float32(0.0))
+        del tex
+        log("texture")
+    return np.clip(img, 0.0, 1.0), labels
+
+
+def smooth_velocity_large(shape, seed, kmax=8.0, max_disp_voxels=20.0, log=None):
+    """Band-limited velocity of smooth_velocity() (complex N(0,1) modes on
+    1 <= |k| <= kmax weighted by 1 / (1 + |k|^2), real part), evaluated as
+    a separable sum over the (2 kmax + 1)^3 modes in FP32; scaled to the
+    given maximum displacement.  Returns float32 [3, n1, n2, n3]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    shape = tuple(int(s) for s in shape)
+    K = int(np.floor(kmax))
+    kk = np.arange(-K, K + 1, dtype=np.float64)
+    ksq = kk[:, None, None] ** 2 + kk[None, :, None] ** 2 + kk[None, None, :] ** 2
+    band = (ksq >= 1.0) & (ksq <= kmax * kmax)
+    E = [np.exp(1j * np.outer(kk, TWO_PI * np.arange(n) / n)) for n in shape]     # [2K+1, n]
+    v = np.empty((3,) + shape, dtype=np.float32)
+    for c in range(3):
+        C = np.zeros(ksq.shape, dtype=np.complex128)
+        nz = int(band.sum())
+        C[band] = (rng.standard_normal(nz) + 1j * rng.standard_normal(nz)) / (1.0 + ksq[band])
+        T1 = C.reshape(-1, 2 * K + 1) @ E[2]                                      # [a b, x3]
+        T1 = T1.reshape(2 * K + 1, 2 * K + 1, shape[2])
+        T2 = np.einsum("bj,abk->ajk", E[1], T1).reshape(2 * K + 1, -1)           # [a, x2 x3]
+        E1 = E[0].T                                                               # [x1, a]
+        v[c] = ((E1.real.astype(np.float32) @ T2.real.astype(np.float32))
+                - (E1.imag.astype(np.float32) @ T2.imag.astype(np.float32))).reshape(shape)
+        if log:
+            log("velocity component %d" % c)
+    vmax = 0.0
+    for i in range(shape[0]):
+        vmax = max(vmax, float(np.sqrt((v[:, i].astype(np.float64) ** 2).sum(axis=0)).max()))
+    h = TWO_PI / max(shape)
+    v *= np.float32(max_disp_voxels * h / vmax)
+    return v
+
+
+def noise32(shape, seed, sigma):
+    """N(0, sigma^2) noise in FP32 (large grids)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return (rng.standard_normal(tuple(int(s) for s in shape), dtype=np.float32) * np.float32(sigma))

@@ -219,6 +219,40 @@ def test_lean_layout(st):
         assert rel(out["lean"][3], o.field(oracle.FIELD_INC_ADJOINT, 0)) < TOL_KERNEL
 
 
+@pytest.mark.parametrize("shape,nt", [((32, 16, 128), 4), ((16, 16, 64), 2), ((16, 32, 32), 4), ((64, 16, 64), 6)])
+def test_lean_layout_shapes(shape, nt):
+    """Lean layout on non-cubic grids: x3 >= 64 runs the marching FD8
+    kernels (register ring along x1, LDS-staged plane), x3 < 64 or more than
+    five time levels the per-node kernels.  Gradient, Hessian matvec and a
+    forced two-iteration GN solve (fused <p, Hp> partials of the PCG) against
+    the full layout, to FP32 rounding-order differences."""
+    from paper_2209_08189_amd.claire import query_workspace
+    m0 = f32(synth.smooth_random_field(shape, 3, kmax=4.0))
+    m1 = f32(synth.smooth_random_field(shape, 4, kmax=4.0))
+    v = f32(np.stack([0.3 * synth.smooth_random_field(shape, 5 + a, kmax=3.0) for a in range(3)]))
+    vt = f32(np.stack([synth.smooth_random_field(shape, 8 + a, kmax=5.0) for a in range(3)]))
+    cap = query_workspace(shape, nt=nt, workspace_cap=1)
+    out = {}
+    for name, kw in (("full", {}), ("lean", {"workspace_cap": cap})):
+        r = reg(shape, nt=nt, **kw)
+        assert r.layout() == (name == "lean")
+        r.set_images(dev(m0), dev(m1))
+        r.set_velocity(dev(v))
+        g, _, _ = r.gradient()
+        Hv = r.hessian_matvec(dev(vt))
+        res = (host(g), host(Hv))
+        r.set_velocity(dev(np.zeros_like(v)))
+        rep = r.solve_forced([3, 3], [1.0, 1.0])
+        out[name] = res + (host(r.velocity()), rep["mismatch"])
+        r.close()
+    print("lean %s nt=%d: g %.2e Hv %.2e v %.2e" % (shape, nt, rel(out["lean"][0], out["full"][0]),
+                                                    rel(out["lean"][1], out["full"][1]),
+                                                    rel(out["lean"][2], out["full"][2])))
+    for a, b in zip(out["lean"][:3], out["full"][:3]):
+        assert rel(a, b) < 1e-5
+    assert abs(out["lean"][3] - out["full"][3]) <= 1e-5 * abs(out["full"][3])
+
+
 # ------------------------------------------------ mixed-precision storage
 
 UROUND = {"f16": 2.0 ** -11, "bf16": 2.0 ** -8, "f32": 2.0 ** -24}
