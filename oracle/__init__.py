@@ -8,8 +8,9 @@ this module only marshals numpy arrays.
 Readings of the paper that the oracle fixes (grid nodes x_i = 2 pi i / N,
 Heun RK2 feet, cubic Lagrange on floor(p)-1..floor(p)+2, central FD8, trapezoid
 time quadrature, H1-seminorm regulariser with K = I, spectral preconditioner
-(beta A)^-1 with the k = 0 mode mapped to 1/beta, PCG/Armijo constants) are
-listed in ``claire_oracle.c`` beside each function.
+(beta A)^-1 with the k = 0 mode mapped to 1/beta, PCG/Armijo constants, and
+for beta_w > 0 the H1 norm of div v with spectral derivatives, K = beta A L^-1)
+are listed in ``claire_oracle.c`` beside each function.
 """
 import ctypes
 import os
@@ -55,6 +56,12 @@ def lib():
             "orc_fft3": (None, [i, i, i, _dp, _dp, i]),
             "orc_spectral": (None, [i, i, i, _dp, _dp, i, i, d]),
             "orc_spectral_resample": (None, [i, i, i, _dp, i, i, i, _dp]),
+            "orc_spec_div": (None, [i, i, i, _dp, _dp]),
+            "orc_spec_grad": (None, [i, i, i, _dp, _dp]),
+            "orc_reg_op": (None, [i, i, i, _dp, _dp, i, d, d]),
+            "orc_set_beta_w": (None, [vp, d]),
+            "orc_gradient_l2": (None, [vp, _dp]),
+            "orc_matvec_sym": (None, [vp, _dp, _dp]),
             "orc_feet": (None, [i, i, i, i, _dp, _dp, _dp]),
             "orc_adjoint_factor": (None, [i, i, i, i, _dp, _dp, _dp]),
             "orc_create": (vp, [i, i, i, i, d]),
@@ -148,6 +155,35 @@ def spectral(u, kind, beta=1.0):
     return out if vec else out[0]
 
 
+def spec_div(v):
+    """div v by spectral derivatives (Nyquist derivative wavenumber 0)."""
+    v = _f64(v)
+    out = np.empty(v.shape[1:])
+    lib().orc_spec_div(*v.shape[1:], _p(v), _p(out))
+    return out
+
+
+def spec_grad(u):
+    """grad u by spectral derivatives (Nyquist derivative wavenumber 0)."""
+    u = _f64(u)
+    g = np.empty((3,) + u.shape)
+    lib().orc_spec_grad(*u.shape, _p(u), _p(g))
+    return g
+
+
+REG_L, REG_PRECOND, REG_K = 0, 1, 3
+
+
+def reg_op(v, kind, beta_v, beta_w):
+    """Per-mode operators on a vector field: kind 0 L (Hessian of the
+    regularisation), 1 preconditioner L^-1 (k = 0 -> 1/beta_v), 3 the
+    Leray-like K = beta_v A L^-1 (k = 0 -> I)."""
+    v = _f64(v)
+    out = np.empty_like(v)
+    lib().orc_reg_op(*v.shape[1:], _p(v), _p(out), int(kind), float(beta_v), float(beta_w))
+    return out
+
+
 def spectral_resample(u, shape):
     u = _f64(u)
     out = np.empty(shape)
@@ -178,11 +214,13 @@ FIELD_FEET_F, FIELD_FEET_B, FIELD_ADJ_FACTOR = 4, 5, 6
 class Oracle:
     """Registration problem on an n1 x n2 x n3 periodic grid over [0, 2pi)^3."""
 
-    def __init__(self, shape, nt=4, beta=5e-4):
+    def __init__(self, shape, nt=4, beta=5e-4, beta_w=0.0):
         self.shape = tuple(int(s) for s in shape)
         self.nt = int(nt)
         self.beta = float(beta)
+        self.beta_w = float(beta_w)
         self._h = lib().orc_create(*self.shape, self.nt, self.beta)
+        lib().orc_set_beta_w(self._h, self.beta_w)
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -216,6 +254,19 @@ class Oracle:
         J, m, r = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
         lib().orc_gradient(self._h, _p(g), ctypes.byref(J), ctypes.byref(m), ctypes.byref(r))
         return g, (J.value, m.value, r.value)
+
+    def gradient_l2(self):
+        """L2 gradient of J (L v + b); equals gradient() when beta_w = 0."""
+        g = np.empty((3,) + self.shape)
+        lib().orc_gradient_l2(self._h, _p(g))
+        return g
+
+    def matvec_sym(self, vt):
+        """L2-symmetric Hessian L vt + b~ (= matvec when beta_w = 0)."""
+        vt = _f64(vt)
+        out = np.empty_like(vt)
+        lib().orc_matvec_sym(self._h, _p(vt), _p(out))
+        return out
 
     def matvec(self, vt):
         vt = _f64(vt)

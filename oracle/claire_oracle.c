@@ -231,6 +231,148 @@ void orc_spectral(int n1, int n2, int n3, const double *in, double *out, int nco
     free(re); free(im);
 }
 
+/* ------------------------------------------ near-incompressible part
+ * The objective of Section 2.1 with beta_w > 0: w = div v is penalised by
+ * its H1 norm, so the regularisation is
+ *   R(v) = beta_v/2 <A v, v> + beta_w/2 (<w, w> + <A w, w>),
+ * the H1 norm written with A = -Laplacian (symbol |k|^2), as the H1
+ * seminorm of v is.  Reading: div is spectral, with the derivative
+ * wavenumber kappa_d = k_d except at the Nyquist index, where kappa_d = 0
+ * (the odd derivative of a real field has no Nyquist component); |k|^2
+ * keeps the Nyquist wavenumber, as in A.                                */
+static double dwavenum(int q, int n) { return q == n / 2 ? 0.0 : wavenum(q, n); }
+
+/* w = div v by spectral derivatives (sum_d i kappa_d v_d^). */
+void orc_spec_div(int n1, int n2, int n3, const double *v, double *w)
+{
+    long N = (long)n1 * n2 * n3;
+    double *re = malloc(sizeof(double) * N), *im = malloc(sizeof(double) * N);
+    double *ar = calloc(N, sizeof(double)), *ai = calloc(N, sizeof(double));
+    for (int c = 0; c < 3; ++c) {
+        for (long p = 0; p < N; ++p) { re[p] = v[c * N + p]; im[p] = 0.0; }
+        orc_fft3(n1, n2, n3, re, im, -1);
+        for (long i = 0; i < n1; ++i)
+            for (long j = 0; j < n2; ++j)
+                for (long k = 0; k < n3; ++k) {
+                    long p = (i * n2 + j) * n3 + k;
+                    double kap = c == 0 ? dwavenum((int)i, n1) : c == 1 ? dwavenum((int)j, n2) : dwavenum((int)k, n3);
+                    ar[p] += -kap * im[p];      /* i kappa (re + i im) */
+                    ai[p] += kap * re[p];
+                }
+    }
+    orc_fft3(n1, n2, n3, ar, ai, +1);
+    for (long p = 0; p < N; ++p) w[p] = ar[p] / (double)N;
+    free(re); free(im); free(ar); free(ai);
+}
+
+/* g = grad u by spectral derivatives (i kappa_d u^). */
+void orc_spec_grad(int n1, int n2, int n3, const double *u, double *g)
+{
+    long N = (long)n1 * n2 * n3;
+    double *re = malloc(sizeof(double) * N), *im = malloc(sizeof(double) * N);
+    double *br = malloc(sizeof(double) * N), *bi = malloc(sizeof(double) * N);
+    for (long p = 0; p < N; ++p) { re[p] = u[p]; im[p] = 0.0; }
+    orc_fft3(n1, n2, n3, re, im, -1);
+    for (int c = 0; c < 3; ++c) {
+        for (long i = 0; i < n1; ++i)
+            for (long j = 0; j < n2; ++j)
+                for (long k = 0; k < n3; ++k) {
+                    long p = (i * n2 + j) * n3 + k;
+                    double kap = c == 0 ? dwavenum((int)i, n1) : c == 1 ? dwavenum((int)j, n2) : dwavenum((int)k, n3);
+                    br[p] = -kap * im[p];
+                    bi[p] = kap * re[p];
+                }
+        orc_fft3(n1, n2, n3, br, bi, +1);
+        for (long p = 0; p < N; ++p) g[c * N + p] = br[p] / (double)N;
+    }
+    free(re); free(im); free(br); free(bi);
+}
+
+/* Solve the real 3x3 system M x = b (Gaussian elimination with partial
+ * pivoting); M is overwritten.                                          */
+static void solve3(double M[3][3], double b[3], double x[3])
+{
+    for (int c = 0; c < 3; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < 3; ++r)
+            if (fabs(M[r][c]) > fabs(M[piv][c])) piv = r;
+        if (piv != c) {
+            for (int q = 0; q < 3; ++q) { double t = M[c][q]; M[c][q] = M[piv][q]; M[piv][q] = t; }
+            double t = b[c]; b[c] = b[piv]; b[piv] = t;
+        }
+        for (int r = c + 1; r < 3; ++r) {
+            double f = M[r][c] / M[c][c];
+            for (int q = c; q < 3; ++q) M[r][q] -= f * M[c][q];
+            b[r] -= f * b[c];
+        }
+    }
+    for (int r = 2; r >= 0; --r) {
+        double t = b[r];
+        for (int q = r + 1; q < 3; ++q) t -= M[r][q] * x[q];
+        x[r] = t / M[r][r];
+    }
+}
+
+/* Operators on a vector field (3 consecutive fields) that act on each
+ * Fourier mode's 3-vector.  L is the Hessian of R (the first variation of
+ * the regularisation): per mode L = beta_v |k|^2 I + beta_w (1 + |k|^2)
+ * kappa kappa^T, the second term being -grad (1 - Laplacian) div.
+ *   kind 0: L
+ *   kind 1: preconditioner, L^-1 on k != 0 (3x3 solve), 1/beta_v at k = 0
+ *   kind 3: K = beta_v A L^-1 (3x3 solve, then beta_v |k|^2), I at k = 0;
+ *           with it the reduced gradient beta_v A v + K b is beta_v A L^-1
+ *           applied to the L2 gradient L v + b (the Leray-like operator of
+ *           the reduced-gradient equation, Section 2.2)
+ * With beta_w = 0 these are beta_v A, (beta_v A)^-1 and I.              */
+void orc_reg_op(int n1, int n2, int n3, const double *in, double *out, int kind, double beta_v, double beta_w)
+{
+    long N = (long)n1 * n2 * n3;
+    double *re[3], *im[3];
+    for (int c = 0; c < 3; ++c) {
+        re[c] = malloc(sizeof(double) * N);
+        im[c] = malloc(sizeof(double) * N);
+        for (long p = 0; p < N; ++p) { re[c][p] = in[c * N + p]; im[c][p] = 0.0; }
+        orc_fft3(n1, n2, n3, re[c], im[c], -1);
+    }
+    for (long i = 0; i < n1; ++i)
+        for (long j = 0; j < n2; ++j)
+            for (long k = 0; k < n3; ++k) {
+                long p = (i * n2 + j) * n3 + k;
+                double kk[3] = {wavenum((int)i, n1), wavenum((int)j, n2), wavenum((int)k, n3)};
+                double ka[3] = {dwavenum((int)i, n1), dwavenum((int)j, n2), dwavenum((int)k, n3)};
+                double ksq = kk[0] * kk[0] + kk[1] * kk[1] + kk[2] * kk[2];
+                double L[3][3];
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b)
+                        L[a][b] = (a == b ? beta_v * ksq : 0.0) + beta_w * (1.0 + ksq) * ka[a] * ka[b];
+                double xr[3] = {re[0][p], re[1][p], re[2][p]}, xi[3] = {im[0][p], im[1][p], im[2][p]};
+                double yr[3], yi[3];
+                if (kind == 0) {
+                    for (int a = 0; a < 3; ++a) {
+                        yr[a] = L[a][0] * xr[0] + L[a][1] * xr[1] + L[a][2] * xr[2];
+                        yi[a] = L[a][0] * xi[0] + L[a][1] * xi[1] + L[a][2] * xi[2];
+                    }
+                } else if (ksq == 0.0) {
+                    double s = kind == 1 ? 1.0 / beta_v : 1.0;
+                    for (int a = 0; a < 3; ++a) { yr[a] = s * xr[a]; yi[a] = s * xi[a]; }
+                } else {
+                    double M[3][3];
+                    memcpy(M, L, sizeof(M));
+                    solve3(M, xr, yr);
+                    memcpy(M, L, sizeof(M));
+                    solve3(M, xi, yi);
+                    if (kind == 3)
+                        for (int a = 0; a < 3; ++a) { yr[a] *= beta_v * ksq; yi[a] *= beta_v * ksq; }
+                }
+                for (int a = 0; a < 3; ++a) { re[a][p] = yr[a]; im[a][p] = yi[a]; }
+            }
+    for (int c = 0; c < 3; ++c) {
+        orc_fft3(n1, n2, n3, re[c], im[c], +1);
+        for (long p = 0; p < N; ++p) out[c * N + p] = re[c][p] / (double)N;
+        free(re[c]); free(im[c]);
+    }
+}
+
 /* Spectral prolongation (coarse nc -> fine nf grid) or restriction (fine
  * -> coarse): copy the Fourier modes with |k_d| < nc_d/2 on every axis,
  * zero everything else (the coarse Nyquist planes included), rescale by
@@ -315,6 +457,7 @@ typedef struct orc_ctx {
     double *m, *lam;        /* state and adjoint at t_j, j = 0..nt */
     double *mt, *lamt;      /* incremental state and adjoint of the last matvec */
     double *work3a, *work3b;
+    double beta_w;          /* divergence regularisation (0: K = I) */
     int have_feet, have_state;
 } orc_ctx;
 
@@ -334,6 +477,8 @@ orc_ctx *orc_create(int n1, int n2, int n3, int nt, double beta)
     o->work3a = calloc(3 * N, sizeof(double)); o->work3b = calloc(3 * N, sizeof(double));
     return o;
 }
+
+void orc_set_beta_w(orc_ctx *o, double beta_w) { o->beta_w = beta_w; }
 
 void orc_destroy(orc_ctx *o)
 {
@@ -377,8 +522,10 @@ void orc_state(orc_ctx *o)
     o->have_state = 1;
 }
 
-/* J = 1/2 <m(1)-m1, m(1)-m1> + beta/2 <A v, v>, <a,b> = h1h2h3 sum a b
- * (objective of the optimal-control problem, Section 2.1).              */
+/* J = 1/2 <m(1)-m1, m(1)-m1> + beta/2 <A v, v>
+ *     + beta_w/2 (<w, w> + <A w, w>), w = div v,
+ * <a,b> = h1h2h3 sum a b (objective of the optimal-control problem,
+ * Section 2.1; the beta_w term is the H1 norm of w).                      */
 void orc_objective(orc_ctx *o, double *J, double *mis, double *reg)
 {
     long N = o->N;
@@ -389,6 +536,13 @@ void orc_objective(orc_ctx *o, double *J, double *mis, double *reg)
     double mm = 0.5 * o->hv * s;
     orc_spectral(o->n1, o->n2, o->n3, o->v, o->work3a, 3, 0, o->beta);
     double rr = 0.5 * dot(o->work3a, o->v, 3 * N, o->hv);
+    if (o->beta_w != 0.0) {
+        double *w = malloc(sizeof(double) * N), *Aw = malloc(sizeof(double) * N);
+        orc_spec_div(o->n1, o->n2, o->n3, o->v, w);
+        orc_spectral(o->n1, o->n2, o->n3, w, Aw, 1, 0, 1.0);
+        rr += 0.5 * o->beta_w * (dot(w, w, N, o->hv) + dot(Aw, w, N, o->hv));
+        free(w); free(Aw);
+    }
     if (mis) *mis = mm;
     if (reg) *reg = rr;
     if (J) *J = mm + rr;
@@ -409,9 +563,9 @@ static void quadrature(orc_ctx *o, const double *lamj, double *b)
     }
 }
 
-/* Reduced gradient g = beta A v + int lam grad m dt (eq. of the reduced
- * gradient, K = I), adjoint final condition lam(1) = m1 - m(1).         */
-void orc_gradient(orc_ctx *o, double *g, double *J, double *mis, double *reg)
+/* Adjoint solve (final condition lam(1) = m1 - m(1)) and the data part
+ * b = int lam grad m dt of the reduced gradient.                         */
+static void data_gradient(orc_ctx *o, double *b)
 {
     long N = o->N;
     int nt = o->nt;
@@ -422,20 +576,58 @@ void orc_gradient(orc_ctx *o, double *g, double *J, double *mis, double *reg)
         orc_interp(o->n1, o->n2, o->n3, o->lam + (j + 1) * N, o->db, o->lam + j * N);
         for (long p = 0; p < N; ++p) o->lam[j * N + p] *= o->c[p];
     }
-    double *b = malloc(sizeof(double) * 3 * N);
     quadrature(o, o->lam, b);
+}
+
+/* Both gradients at the current v: the reduced gradient of Section 2.2,
+ * g = beta A v + K b (g may be NULL), and the L2 gradient of J,
+ * g_l2 = L v + b (may be NULL); with beta_w = 0 both are beta A v + b.  */
+static void gradients(orc_ctx *o, double *g, double *g_l2, double *J, double *mis, double *reg)
+{
+    long N = o->N;
+    double *b = malloc(sizeof(double) * 3 * N);
+    data_gradient(o, b);
     orc_objective(o, J, mis, reg);          /* leaves beta A v in work3a */
-    for (long p = 0; p < 3 * N; ++p) g[p] = o->work3a[p] + b[p];
+    if (o->beta_w == 0.0) {
+        for (long p = 0; p < 3 * N; ++p) {
+            if (g) g[p] = o->work3a[p] + b[p];
+            if (g_l2) g_l2[p] = o->work3a[p] + b[p];
+        }
+    } else {
+        double *t = malloc(sizeof(double) * 3 * N);
+        if (g) {
+            orc_reg_op(o->n1, o->n2, o->n3, b, t, 3, o->beta, o->beta_w);
+            for (long p = 0; p < 3 * N; ++p) g[p] = o->work3a[p] + t[p];
+        }
+        if (g_l2) {
+            orc_reg_op(o->n1, o->n2, o->n3, o->v, t, 0, o->beta, o->beta_w);
+            for (long p = 0; p < 3 * N; ++p) g_l2[p] = t[p] + b[p];
+        }
+        free(t);
+    }
     free(b);
 }
 
-/* Gauss-Newton Hessian matvec (eq. of the matvec, K = I):
+/* Reduced gradient g = beta A v + K int lam grad m dt (eq. of the reduced
+ * gradient).                                                              */
+void orc_gradient(orc_ctx *o, double *g, double *J, double *mis, double *reg)
+{
+    gradients(o, g, NULL, J, mis, reg);
+}
+
+/* L2 gradient of the objective, L v + int lam grad m dt. */
+void orc_gradient_l2(orc_ctx *o, double *g_l2)
+{
+    gradients(o, NULL, g_l2, NULL, NULL, NULL);
+}
+
+/* Data part of the Gauss-Newton Hessian matvec:
  *   incremental state  d_t mt + v.grad mt = -vt.grad m,  mt(0) = 0
  *   incremental adjoint as the adjoint, lamt(1) = -mt(1)
- *   H vt = beta A vt + int lamt grad m dt.
+ *   b~ = int lamt grad m dt.
  * The source s^j = -vt.grad_h m^j is integrated by the trapezoid rule along
  * the characteristic: mt^{j+1} = I[mt^j + dt/2 s^j](X_f) + dt/2 s^{j+1}. */
-void orc_matvec(orc_ctx *o, const double *vt, double *Hvt)
+static void data_matvec(orc_ctx *o, const double *vt, double *bt)
 {
     long N = o->N;
     int nt = o->nt;
@@ -459,16 +651,52 @@ void orc_matvec(orc_ctx *o, const double *vt, double *Hvt)
         orc_interp(o->n1, o->n2, o->n3, o->lamt + (j + 1) * N, o->db, o->lamt + j * N);
         for (long p = 0; p < N; ++p) o->lamt[j * N + p] *= o->c[p];
     }
-    double *b = malloc(sizeof(double) * 3 * N);
-    quadrature(o, o->lamt, b);
-    orc_spectral(o->n1, o->n2, o->n3, vt, Hvt, 3, 0, o->beta);
-    for (long p = 0; p < 3 * N; ++p) Hvt[p] += b[p];
-    free(b); free(s); free(gm); free(q);
+    quadrature(o, o->lamt, bt);
+    free(s); free(gm); free(q);
 }
 
+/* Gauss-Newton Hessian matvec of the reduced gradient (Section 2.2):
+ * H vt = beta A vt + K b~.                                               */
+void orc_matvec(orc_ctx *o, const double *vt, double *Hvt)
+{
+    long N = o->N;
+    double *b = malloc(sizeof(double) * 3 * N);
+    data_matvec(o, vt, b);
+    orc_spectral(o->n1, o->n2, o->n3, vt, Hvt, 3, 0, o->beta);
+    if (o->beta_w != 0.0) {
+        double *t = malloc(sizeof(double) * 3 * N);
+        orc_reg_op(o->n1, o->n2, o->n3, b, t, 3, o->beta, o->beta_w);
+        memcpy(b, t, sizeof(double) * 3 * N);
+        free(t);
+    }
+    for (long p = 0; p < 3 * N; ++p) Hvt[p] += b[p];
+    free(b);
+}
+
+/* The same operator in its L2-symmetric form, L vt + b~ = K^-1 H vt: the
+ * Hessian of J itself (equal to H when beta_w = 0).                      */
+void orc_matvec_sym(orc_ctx *o, const double *vt, double *Hvt)
+{
+    long N = o->N;
+    if (o->beta_w == 0.0) {
+        orc_matvec(o, vt, Hvt);
+        return;
+    }
+    double *b = malloc(sizeof(double) * 3 * N);
+    data_matvec(o, vt, b);
+    orc_reg_op(o->n1, o->n2, o->n3, vt, Hvt, 0, o->beta, o->beta_w);
+    for (long p = 0; p < 3 * N; ++p) Hvt[p] += b[p];
+    free(b);
+}
+
+/* Preconditioner: (beta A)^-1 with the k = 0 mode mapped to 1/beta; with
+ * beta_w > 0 the inverse of L (same k = 0 rule).                        */
 void orc_precond(orc_ctx *o, const double *r, double *z)
 {
-    orc_spectral(o->n1, o->n2, o->n3, r, z, 3, 1, o->beta);
+    if (o->beta_w == 0.0)
+        orc_spectral(o->n1, o->n2, o->n3, r, z, 3, 1, o->beta);
+    else
+        orc_reg_op(o->n1, o->n2, o->n3, r, z, 1, o->beta, o->beta_w);
 }
 
 /* Read back an internal field: which = 0 state m^j, 1 adjoint lam^j,
@@ -499,6 +727,13 @@ void orc_get_field(orc_ctx *o, int which, int j, double *out)
  *  - Armijo: alpha = 1, halve while J(v + alpha vt) > J(v) + 1e-4 alpha
  *    <g, vt>, at most 10 trials;
  *  - g_ref = ||g(v = 0)||, stop when ||g|| <= gtol g_ref.
+ *  - beta_w > 0: g and H are the reduced gradient and Hessian, K times the
+ *    L2 gradient and Hessian of J.  PCG runs on the L2-symmetric form
+ *    (L + B) x = -g_l2 with the preconditioner L^-1, which is PCG on
+ *    H x = -g with K as a left preconditioner: the same Newton step; its
+ *    residual test is on the symmetric system.  Armijo uses <g_l2, vt>,
+ *    the directional derivative of J; the stopping test and the forcing
+ *    term use ||g||.
  * A forced run (forced_pcg / forced_alpha non-NULL) takes exactly the given
  * PCG iteration counts and step lengths instead of testing them.
  * log is [max_outer + 1][8]: k, J, mismatch, reg, ||g||, pcg iterations,
@@ -518,7 +753,7 @@ int orc_pcg(orc_ctx *o, const double *rhs, double *x, int max_pcg, double eta, i
     int limit = forced_iters >= 0 ? forced_iters : max_pcg;
     int it = 0, negcurv = 0;
     while (it < limit) {
-        orc_matvec(o, p, Hp);
+        orc_matvec_sym(o, p, Hp);
         double pHp = dot(p, Hp, n, w);
         if (pHp <= 0.0) {
             negcurv = 1;
@@ -549,6 +784,7 @@ int orc_solve(orc_ctx *o, int max_outer, int max_pcg, double gtol,
     long n = 3 * o->N;
     double w = o->hv;
     double *v = malloc(sizeof(double) * n), *g = malloc(sizeof(double) * n);
+    double *gl = malloc(sizeof(double) * n);
     double *vt = malloc(sizeof(double) * n), *rhs = malloc(sizeof(double) * n);
     double *vtrial = malloc(sizeof(double) * n);
     memcpy(v, o->v, sizeof(double) * n);
@@ -564,17 +800,17 @@ int orc_solve(orc_ctx *o, int max_outer, int max_pcg, double gtol,
     int status = 1, k = 0;
     double J, mis, reg;
     for (k = 0; k < max_outer; ++k) {
-        orc_gradient(o, g, &J, &mis, &reg);
+        gradients(o, g, gl, &J, &mis, &reg);
         double gn = sqrt(dot(g, g, n, w));
         double *row = log ? log + 8 * k : NULL;
         if (row) { row[0] = k; row[1] = J; row[2] = mis; row[3] = reg; row[4] = gn; row[5] = 0; row[6] = 0; row[7] = 0; }
         if (!forced_pcg && gn <= gtol * gref) { status = 0; break; }
         double eta = sqrt(gn / gref);
         if (eta > 0.5) eta = 0.5;
-        for (long q = 0; q < n; ++q) rhs[q] = -g[q];
+        for (long q = 0; q < n; ++q) rhs[q] = -gl[q];
         int its = 0;
         orc_pcg(o, rhs, vt, max_pcg, eta, forced_pcg ? forced_pcg[k] : -1, &its);
-        double gvt = dot(g, vt, n, w);
+        double gvt = dot(gl, vt, n, w);
         double alpha = 1.0;
         int trials = 0, ok = 0;
         if (forced_alpha) {
@@ -615,7 +851,7 @@ int orc_solve(orc_ctx *o, int max_outer, int max_pcg, double gtol,
         if (status == 1 && gn <= gtol * gref) status = 0;
     }
     if (n_outer) *n_outer = k;
-    free(v); free(g); free(vt); free(rhs); free(vtrial);
+    free(v); free(g); free(gl); free(vt); free(rhs); free(vtrial);
     return status;
 }
 
