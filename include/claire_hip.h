@@ -6,10 +6,14 @@
  * Problem (Section 2.1, optimal-control problem): given a template image m0
  * and a reference image m1 on the periodic domain [0, 2pi)^3, find a
  * stationary velocity v minimising
- *     1/2 ||m(1) - m1||^2 + beta_v/2 <A v, v>,
+ *     1/2 ||m(1) - m1||^2 + beta_v/2 <A v, v> + beta_w/2 (<w, w> + <A w, w>),
  * where m solves the transport equation d_t m + v . grad m = 0, m(0) = m0,
- * and A = -Laplacian (H1 seminorm; beta_w = 0, so the Leray-like operator K
- * is the identity).
+ * A = -Laplacian (H1 seminorm of v) and w = div v, penalised by its H1 norm
+ * (Section 2.1; beta_w = 0 drops the term).  The regularisation's Hessian is
+ * L = beta_v A + beta_w (-grad)(1 + A) div; the Leray-like operator of the
+ * reduced gradient (Section 2.2) is K = beta_v A L^-1, the identity when
+ * beta_w = 0.  Spectral first derivatives (div, and grad in L) use
+ * wavenumber 0 at the Nyquist index; A keeps it.
  *
  * Conventions that hold for every entry point:
  *   - Grid: n1 x n2 x n3 nodes x_i = 2 pi i / n, each n_d a power of two,
@@ -54,7 +58,7 @@ enum {
     CL_ERR_OOM = -4,          /* device allocation failed or workspace cap exceeded */
     CL_ERR_HIP = -5,          /* a HIP runtime call failed */
     CL_ERR_NONFINITE = -6,    /* NaN or Inf found in an input */
-    CL_ERR_UNSUPPORTED = -7,  /* option outside this build (e.g. beta_w != 0) */
+    CL_ERR_UNSUPPORTED = -7,  /* option outside this build */
     CL_ERR_STATE = -8,        /* call order violated (e.g. gradient before set_images) */
     CL_ERR_ALIAS = -9,        /* input and output buffers overlap */
     CL_STATUS_MAXIT = 1,      /* solve stopped at max_outer */
@@ -65,7 +69,7 @@ typedef struct {
     int struct_version;       /* must be CL_OPTIONS_VERSION */
     int nt;                   /* semi-Lagrangian time steps, >= 1 (default 4) */
     double beta_v;            /* H1-seminorm regularisation weight, > 0 (default 5e-4) */
-    double beta_w;            /* divergence regularisation; must be 0 in this build */
+    double beta_w;            /* H1-norm weight of div v, >= 0 (default 0: K = I) */
     double gtol;              /* stop when ||g|| <= gtol ||g(v=0)|| (default 1e-2) */
     int max_outer;            /* Gauss-Newton iteration limit (default 50) */
     int max_pcg;              /* PCG iteration limit per GN step (default 10) */
@@ -124,21 +128,25 @@ int cl_get_velocity(cl_ctx *ctx, float *v_out);
 /* Objective J = mismatch + reg at the current v (Section 2.1); synchronises. */
 int cl_objective(cl_ctx *ctx, double *J, double *mismatch, double *reg);
 
-/* Reduced gradient g = beta_v A v + int_0^1 lambda grad m dt (Section 2.2,
- * reduced gradient) at the current v.  g_out (FP32 [3][n1][n2][n3], may be
- * NULL) receives g; *gnorm (may be NULL) receives sqrt(h1h2h3 sum g.g);
- * J (may be NULL) the objective.  Synchronises. */
+/* Reduced gradient g = beta_v A v + K int_0^1 lambda grad m dt (Section
+ * 2.2, reduced gradient) at the current v.  g_out (FP32 [3][n1][n2][n3], may
+ * be NULL) receives g; *gnorm (may be NULL) receives sqrt(h1h2h3 sum g.g);
+ * J (may be NULL) the objective.  g = K times the L2 gradient of J; the two
+ * coincide when beta_w = 0.  Synchronises. */
 int cl_gradient(cl_ctx *ctx, float *g_out, double *gnorm, double *J);
 
-/* Gauss-Newton Hessian matvec H vt = beta_v A vt + int lambda~ grad m dt
- * (Section 2.2, Hessian matvec; two transport solves) at the current v.
+/* Gauss-Newton Hessian matvec H vt = beta_v A vt + K int lambda~ grad m dt
+ * (Section 2.2, Hessian matvec; two transport solves) at the current v; K
+ * times the L2 Hessian of J, which the solver's PCG uses (K acts there as a
+ * left preconditioner, so the Newton step is the same).
  * Needs the state of the current v (computed by cl_gradient or
  * cl_objective).  vt and Hvt must be 16-byte aligned (CL_ERR_ARG).
  * Enqueued only, no synchronisation. */
 int cl_hessian_matvec(cl_ctx *ctx, const float *vt, float *Hvt);
 
 /* Spectral preconditioner z = (beta_v A)^-1 r with the k = 0 mode scaled by
- * 1/beta_v.  Enqueued only. */
+ * 1/beta_v; with beta_w > 0, z = L^-1 r (same k = 0 rule), i.e.
+ * (beta_v A)^-1 K r.  Enqueued only. */
 int cl_precond_apply(cl_ctx *ctx, const float *r, float *z);
 
 /* Gauss-Newton-Krylov solve with Armijo line search from the current v
@@ -178,7 +186,10 @@ int cl_get_field(cl_ctx *ctx, int which, int j, float *out);
  *   cl_fd_grad:  g = grad_h u, 8th-order central differences (3 fields out)
  *   cl_fd_div:   out = div_h v (3 fields in)
  *   cl_spectral: kind 0: beta_v A, 1: (beta_v A)^-1 (k = 0 -> 1/beta_v),
- *                2: identity through the FFT; ncomp fields in and out. */
+ *                2: identity through the FFT, 3: K; ncomp fields in and
+ *                out.  With beta_w > 0 and ncomp = 3, kinds 0, 1 and 3
+ *                are L, L^-1 (k = 0 -> 1/beta_v) and K, which couple the
+ *                three components per Fourier mode. */
 int cl_interp(cl_ctx *ctx, const float *u, const float *d, float *out);
 int cl_fd_grad(cl_ctx *ctx, const float *u, float *g);
 int cl_fd_div(cl_ctx *ctx, const float *v, float *out);

@@ -187,7 +187,7 @@ class Registration:
 
     def __init__(self, shape, nt=4, beta_v=5e-4, gtol=1e-2, max_outer=50, max_pcg=10,
                  forcing=1, eta_fixed=0.1, storage_state="f32", storage_adjoint="f32",
-                 workspace_cap=0, stream=None):
+                 workspace_cap=0, stream=None, beta_w=0.0):
         import torch
         self.torch = torch
         self.shape = tuple(int(s) for s in shape)
@@ -195,6 +195,7 @@ class Registration:
         o = default_options()
         o.nt = int(nt)
         o.beta_v = float(beta_v)
+        o.beta_w = float(beta_w)
         o.gtol = float(gtol)
         o.max_outer = int(max_outer)
         o.max_pcg = int(max_pcg)

@@ -186,7 +186,17 @@ double count_nonfinite(cl_ctx *ctx, const float *a, size_t n)
 
 void spectral(cl_ctx *ctx, int kind, int ncomp, const float *in, float *out, const float *add)
 {
-    run(ctx, CL_K_FFT, [&] { spectral_apply(ctx->fft, kind, (float)ctx->opt.beta_v, ncomp, in, out, add, ctx->s); });
+    run(ctx, CL_K_FFT, [&] {
+        spectral_apply(ctx->fft, kind, (float)ctx->opt.beta_v, (float)ctx->opt.beta_w, ncomp, in, out, add, ctx->s);
+    });
+}
+
+// the same without the divergence term: beta_v A, (beta_v A)^-1, identity
+void spectral_scalar(cl_ctx *ctx, int kind, int ncomp, const float *in, float *out)
+{
+    run(ctx, CL_K_FFT, [&] {
+        spectral_apply(ctx->fft, kind, (float)ctx->opt.beta_v, 0.f, ncomp, in, out, nullptr, ctx->s);
+    });
 }
 
 // ---- operator layer
@@ -291,7 +301,11 @@ void adjoint_sweep(cl_ctx *ctx)
         });
 }
 
-// reduced gradient into ctx->g; returns ||g||
+// Gradient at the current v.  ctx->grad receives the L2 gradient of J,
+// L v + b (the PCG right-hand side and the Armijo slope); the reduced
+// gradient of Section 2.2, g = beta_v A v + K b = K (L v + b), is returned
+// by reduced_grad() and its norm by this function.  With beta_w = 0 the two
+// coincide (K = I, L = beta_v A).
 double gradient(cl_ctx *ctx, double *J, double *mis_out, double *reg_out)
 {
     ensure_feet(ctx, true);
@@ -308,19 +322,37 @@ double gradient(cl_ctx *ctx, double *J, double *mis_out, double *reg_out)
         ctx->av = true;
     }
     const QuadArgs qa = quad_args(ctx);
-    run(ctx, CL_K_QUAD, [&] { launch_quadrature(ctx->g, ctx->dta, qa, ctx->Av, ctx->grad, ctx->s); });
+    const size_t n3 = 3 * ctx->N;
+    if (ctx->opt.beta_w == 0.0) {
+        run(ctx, CL_K_QUAD, [&] { launch_quadrature(ctx->g, ctx->dta, qa, ctx->Av, ctx->grad, ctx->s); });
+    } else {
+        // b into the PCG z vector (free outside PCG; the feet scratch that
+        // may share it is consumed by now), L v + b into ctx->grad, and the
+        // reduced gradient beta_v A v + K b in z, each term formed directly
+        run(ctx, CL_K_QUAD, [&] { launch_quadrature(ctx->g, ctx->dta, qa, nullptr, ctx->pz, ctx->s); });
+        run(ctx, CL_K_VEC, [&] { launch_axpy(ctx->grad, ctx->Av, ctx->pz, 1.0f, n3, ctx->s); });
+        spectral(ctx, 3, 3, ctx->pz, ctx->pz, nullptr);
+        spectral_scalar(ctx, 0, 3, ctx->v, ctx->tmp3);
+        run(ctx, CL_K_VEC, [&] { launch_axpy(ctx->pz, ctx->pz, ctx->tmp3, 1.0f, n3, ctx->s); });
+    }
     const double reg = 0.5 * dotw(ctx, ctx->Av, ctx->v, 3 * ctx->N);
     if (mis_out) *mis_out = mis;
     if (reg_out) *reg_out = reg;
     if (J) *J = mis + reg;
-    return std::sqrt(dotw(ctx, ctx->grad, ctx->grad, 3 * ctx->N));
+    const float *g = ctx->opt.beta_w != 0.0 ? ctx->pz : ctx->grad;
+    return std::sqrt(dotw(ctx, g, g, 3 * ctx->N));
 }
+
+// the reduced gradient after gradient(): beta_v A v + K b, or ctx->grad
+const float *reduced_grad(cl_ctx *ctx) { return ctx->opt.beta_w != 0.0 ? ctx->pz : ctx->grad; }
 
 // GN Hessian matvec (incremental state, incremental adjoint, quadrature,
 // beta A vt); needs feet of both directions and the state of the current v.
 // dot_out (device, optional): <vt, Hvt> (weighted by h1 h2 h3), fused into
 // the quadrature that produces Hvt.
-void matvec(cl_ctx *ctx, const float *vt, float *Hvt, const float *Avt_known = nullptr, double *dot_out = nullptr)
+// data_only: Hvt = the data term b~ alone (no regularisation term added).
+void matvec(cl_ctx *ctx, const float *vt, float *Hvt, const float *Avt_known = nullptr, double *dot_out = nullptr,
+            bool data_only = false)
 {
     ensure_feet(ctx, true);
     ensure_sgrad(ctx);
@@ -354,7 +386,7 @@ void matvec(cl_ctx *ctx, const float *vt, float *Hvt, const float *Avt_known = n
     }
     adjoint_sweep(ctx);
     const float *Avt = Avt_known;
-    if (!Avt) {
+    if (!Avt && !data_only) {
         spectral(ctx, 0, 3, vt, ctx->tmp3, nullptr);
         Avt = ctx->tmp3;
     }
@@ -546,7 +578,7 @@ int check_options(const cl_options *o, cl_ctx *ctx)
     if (o->struct_version != CL_OPTIONS_VERSION) return fail(ctx, CL_ERR_ARG, "cl_options.struct_version mismatch");
     if (o->nt < 1 || o->nt > MAX_T - 1) return fail(ctx, CL_ERR_ARG, "nt out of range [1, 64]");
     if (!(o->beta_v > 0.0) || !std::isfinite(o->beta_v)) return fail(ctx, CL_ERR_ARG, "beta_v must be > 0");
-    if (o->beta_w != 0.0) return fail(ctx, CL_ERR_UNSUPPORTED, "beta_w != 0 is not supported (K = I only)");
+    if (!(o->beta_w >= 0.0) || !std::isfinite(o->beta_w)) return fail(ctx, CL_ERR_ARG, "beta_w must be >= 0");
     if (o->max_outer < 0 || o->max_pcg < 1) return fail(ctx, CL_ERR_ARG, "iteration limits out of range");
     if (!(o->gtol >= 0.0)) return fail(ctx, CL_ERR_ARG, "gtol must be >= 0");
     for (int dt : {o->storage_state, o->storage_adjoint})
@@ -790,7 +822,7 @@ int cl_gradient(cl_ctx *ctx, float *g_out, double *gnorm, double *J)
     const double gn = gradient(ctx, J, nullptr, nullptr);
     if (gnorm) *gnorm = gn;
     if (g_out) {
-        HIPCHK(hipMemcpyAsync(g_out, ctx->grad, 3 * ctx->N * sizeof(float), hipMemcpyDeviceToDevice, ctx->s));
+        HIPCHK(hipMemcpyAsync(g_out, reduced_grad(ctx), 3 * ctx->N * sizeof(float), hipMemcpyDeviceToDevice, ctx->s));
         HIPCHK(hipStreamSynchronize(ctx->s));
     }
     return CL_OK;
@@ -806,7 +838,15 @@ int cl_hessian_matvec(cl_ctx *ctx, const float *vt, float *Hvt)
     if (overlap(vt, b, Hvt, b)) return fail(ctx, CL_ERR_ALIAS, "vt and Hvt overlap");
     if (((uintptr_t)vt | (uintptr_t)Hvt) & 15) return fail(ctx, CL_ERR_ARG, "vt and Hvt must be 16-byte aligned");
     API_BEGIN
-    matvec(ctx, vt, Hvt);
+    if (ctx->opt.beta_w == 0.0) {
+        matvec(ctx, vt, Hvt);
+    } else {
+        // reduced form H vt = beta_v A vt + K b~, each term formed directly
+        matvec(ctx, vt, Hvt, nullptr, nullptr, true);
+        spectral(ctx, 3, 3, Hvt, Hvt, nullptr);
+        spectral_scalar(ctx, 0, 3, vt, ctx->tmp3);
+        run(ctx, CL_K_VEC, [&] { launch_axpy(Hvt, Hvt, ctx->tmp3, 1.0f, 3 * ctx->N, ctx->s); });
+    }
     return CL_OK;
     API_END
 }
@@ -941,7 +981,7 @@ int cl_spectral(cl_ctx *ctx, int kind, int ncomp, const float *in, float *out)
 {
     NEED_CTX();
     if (!in || !out) return fail(ctx, CL_ERR_ARG, "NULL pointer");
-    if (kind < 0 || kind > 2 || ncomp < 1) return fail(ctx, CL_ERR_ARG, "bad kind or ncomp");
+    if (kind < 0 || kind > 3 || ncomp < 1) return fail(ctx, CL_ERR_ARG, "bad kind or ncomp");
     const size_t b = (size_t)ncomp * ctx->N * 4;
     if (overlap(in, b, out, b)) return fail(ctx, CL_ERR_ALIAS, "output overlaps input");
     API_BEGIN

@@ -202,8 +202,10 @@ struct FFTPlan {
     int ncomp_max;
 };
 size_t fft_spec_bytes(int n1, int n2, int n3, int ncomp);
-// out_c = F^-1[ mult(k) F[in_c] ] (+ add_c), c < ncomp; kind as cl_spectral
-void spectral_apply(const FFTPlan &P, int kind, float beta, int ncomp, const float *in, float *out,
+// out_c = F^-1[ mult(k) F[in_c] ] (+ add_c), c < ncomp; kind as cl_spectral.
+// With beta_w != 0 and ncomp = 3, kinds 0, 1 and 3 couple the components per
+// mode (regularisation Hessian L, its inverse, K); in may equal out.
+void spectral_apply(const FFTPlan &P, int kind, float beta, float beta_w, int ncomp, const float *in, float *out,
                     const float *add, hipStream_t s);
 // out (grid B) = spectral resampling of in (grid A): modes with |k_d| <
 // min(n_a, n_b)/2 kept, others zero, scaled so band-limited fields are

@@ -407,6 +407,53 @@ __global__ __launch_bounds__(TPB) void k_mode_copy(const float2 *__restrict__ sa
     sb[e] = v;
 }
 
+// Per-mode 3x3 operators of the near-incompressible regularisation on the
+// half spectrum of a vector field (three components spec_cs apart), scaled
+// by 1/N.  With a = beta_v |k|^2, c = beta_w (1 + |k|^2) and kappa the
+// derivative wavenumber (k_d, 0 at the Nyquist index):
+//   kind 0: L = a I + c kappa kappa^T (Hessian of the regularisation)
+//   kind 1: L^-1 = (I - c/(a + c |kappa|^2) kappa kappa^T) / a, 1/beta_v at k = 0
+//   kind 3: K = beta_v A L^-1 = I - c/(a + c |kappa|^2) kappa kappa^T, I at k = 0
+// (Sherman-Morrison on the rank-one term).
+__global__ __launch_bounds__(TPB) void k_spec_mult3(float2 *__restrict__ spec, int n1, int n2, int nh, int kind,
+                                                    float beta_v, float beta_w, float scale, size_t spec_cs)
+{
+    const size_t e = (size_t)blockIdx.x * TPB + threadIdx.x;
+    if (e >= spec_cs) return;
+    const int q3 = (int)(e % nh);
+    const int q2 = (int)((e / nh) % n2);
+    const int q1 = (int)(e / ((size_t)nh * n2));
+    const float k1 = (float)(q1 < (n1 >> 1) ? q1 : q1 - n1);
+    const float k2 = (float)(q2 < (n2 >> 1) ? q2 : q2 - n2);
+    const float k3 = (float)q3;
+    const float c1 = q1 == (n1 >> 1) ? 0.f : k1, c2 = q2 == (n2 >> 1) ? 0.f : k2, c3 = q3 == nh - 1 ? 0.f : k3;
+    const float ksq = k1 * k1 + k2 * k2 + k3 * k3;
+    const float a = beta_v * ksq, c = beta_w * (1.0f + ksq);
+    float2 x0 = spec[e], x1 = spec[spec_cs + e], x2 = spec[2 * spec_cs + e];
+    const float pr = c1 * x0.x + c2 * x1.x + c3 * x2.x;   // kappa . x
+    const float pi = c1 * x0.y + c2 * x1.y + c3 * x2.y;
+    float d, f;   // y = d x + f kappa (kappa . x)
+    if (kind == 0) {
+        d = a;
+        f = c;
+    } else if (ksq == 0.f) {
+        d = kind == 1 ? 1.0f / beta_v : 1.0f;
+        f = 0.f;
+    } else {
+        const float r = c / (a + c * (c1 * c1 + c2 * c2 + c3 * c3));
+        d = kind == 1 ? 1.0f / a : 1.0f;
+        f = -r * d;
+    }
+    d *= scale;
+    f *= scale;
+    x0 = make_float2(fmaf(f * c1, pr, d * x0.x), fmaf(f * c1, pi, d * x0.y));
+    x1 = make_float2(fmaf(f * c2, pr, d * x1.x), fmaf(f * c2, pi, d * x1.y));
+    x2 = make_float2(fmaf(f * c3, pr, d * x2.x), fmaf(f * c3, pi, d * x2.y));
+    spec[e] = x0;
+    spec[spec_cs + e] = x1;
+    spec[2 * spec_cs + e] = x2;
+}
+
 int ilog2(int n)
 {
     int l = 0;
@@ -430,9 +477,22 @@ void fft_make_twiddles(float2 *host, int n, int count)
     }
 }
 
-void spectral_apply(const FFTPlan &P, int kind, float beta, int ncomp, const float *in, float *out,
+namespace {
+struct PassGeom;
+void coupled3(const FFTPlan &P, int kind, float beta_v, float beta_w, const float *in, float *out, hipStream_t s);
+} // namespace
+
+void spectral_apply(const FFTPlan &P, int kind, float beta, float beta_w, int ncomp, const float *in, float *out,
                     const float *add, hipStream_t s)
 {
+    if (beta_w != 0.f && ncomp == 3 && kind != 2) {
+        // the three components are coupled per mode: forward transforms,
+        // one 3x3 pass over the half spectrum, inverse transforms
+        coupled3(P, kind, beta, beta_w, in, out, s);
+        if (add) launch_axpy(out, out, add, 1.0f, 3 * (size_t)P.n1 * P.n2 * P.n3, s);
+        return;
+    }
+    if (kind == 3) kind = 2;   // K = I without the divergence term
     const int n1 = P.n1, n2 = P.n2, n3 = P.n3, nh = P.nh;
     const int M = n3 / 2, logM = ilog2(M);
     const size_t N = (size_t)n1 * n2 * n3;
@@ -514,6 +574,16 @@ void inverse3(const FFTPlan &P, const PassGeom &G, int nc, float *out, hipStream
                        ilog2(P.n2), P.n2, P.nh, G.logC2, G.spec_cs);
     hipLaunchKernelGGL(k_fft_x3_c2r, dim3(G.nrows >> G.lognl3, nc), dim3(TPB), G.lds3, s, P.spec, out, nullptr, P.twM,
                        P.twS, G.logM, G.lognl3, G.nrows, G.N, G.spec_cs);
+}
+
+void coupled3(const FFTPlan &P, int kind, float beta_v, float beta_w, const float *in, float *out, hipStream_t s)
+{
+    // every plan of the library holds three components of spectrum
+    const PassGeom G = geom(P);
+    forward3(P, G, 3, in, s);
+    hipLaunchKernelGGL(k_spec_mult3, dim3((unsigned)((G.spec_cs + TPB - 1) / TPB)), dim3(TPB), 0, s, P.spec, P.n1,
+                       P.n2, P.nh, kind, beta_v, beta_w, (float)(1.0 / (double)G.N), G.spec_cs);
+    inverse3(P, G, 3, out, s);
 }
 
 __global__ __launch_bounds__(TPB) void k_scale_f(float *x, float a, size_t n)

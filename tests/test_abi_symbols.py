@@ -52,7 +52,12 @@ def test_option_validation_without_gpu():
     assert nb.value > 40 * 256 ** 3 * 4
     assert L.cl_query_workspace(100, 256, 256, ctypes.byref(o), ctypes.byref(nb)) == -2
     o.beta_w = 1e-5
-    assert L.cl_query_workspace(64, 64, 64, ctypes.byref(o), ctypes.byref(nb)) == -7
+    assert L.cl_query_workspace(64, 64, 64, ctypes.byref(o), ctypes.byref(nb)) == 0
+    o.beta_w = -1e-5
+    assert L.cl_query_workspace(64, 64, 64, ctypes.byref(o), ctypes.byref(nb)) == -1
+    o.beta_w = float("nan")
+    assert L.cl_query_workspace(64, 64, 64, ctypes.byref(o), ctypes.byref(nb)) == -1
+    o = claire.default_options()
     o = claire.default_options(); o.struct_version = 99
     assert L.cl_query_workspace(64, 64, 64, ctypes.byref(o), ctypes.byref(nb)) == -1
     o = claire.default_options(); o.storage_state = 7
