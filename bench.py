@@ -76,6 +76,8 @@ def main():
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the 16-bit storage matvec measurement")
     ap.add_argument("--cpu-matvecs", type=int, default=3, help="oracle matvecs timed for the CPU baseline")
+    ap.add_argument("--beta-w", type=float, default=1e-5,
+                    help="divergence weight of the near-incompressible leg (0 disables the leg)")
     ap.add_argument("--max-pcg", type=int, default=40, help="PCG iterations per GN step in the solve legs")
     ap.add_argument("--learned-train", type=int, default=48, help="training pairs (0 disables the learned leg)")
     ap.add_argument("--learned-eval", type=int, default=4, help="held-out evaluation pairs")
@@ -221,8 +223,57 @@ def main():
         lab1 = warp_labels(labels, dev(v_true))
         solve["dice_pre"] = dice(labels, lab1)
         solve["dice_post"] = dice(warp_labels(labels, rs.velocity()), lab1)
+        vsol = rs.velocity()
+        solve["div_ratio"] = float(rs.fd_div(vsol).norm() / vsol.norm())
         log("solve: %s" % json.dumps(solve))
-        del rs
+        del rs, vsol
+
+    # near-incompressible formulation (beta_w > 0, K != I): the reduced
+    # Hessian matvec beta_v A vt + K b~ and the solve on the same pair
+    incompressible = None
+    if args.beta_w > 0 and not args.no_solve:
+        ri = Registration(shape, nt=4, beta_v=5e-4, beta_w=args.beta_w, gtol=1e-2, max_outer=50,
+                          max_pcg=args.max_pcg)
+        ri.set_images(m0, m1)
+        ri.set_velocity(dev(v_true))
+        gi, _, _ = ri.gradient()
+        vti = -ri.precond(gi)
+        for _ in range(args.warmup):
+            ri.hessian_matvec(vti, Hv)
+        ri.profile_enable(0xFF)
+        for _ in range(3):
+            ri.hessian_matvec(vti, Hv)
+            ri.precond(vti, gi)
+        iclass = {}
+        for k, name in enumerate(K_NAMES):
+            ms, cnt = ri.profile_query(k)
+            if cnt:
+                iclass[name] = {"ms_per_matvec_and_precond": ms / 3, "avg_launch_ms": ms / cnt}
+        ri.profile_enable(0)
+        torch.cuda.synchronize()
+        ti0 = time.perf_counter()
+        for _ in range(args.steps):
+            ri.hessian_matvec(vti, Hv)
+        torch.cuda.synchronize()
+        ti = time.perf_counter() - ti0
+        ri.set_velocity(torch.zeros((3,) + shape, device="cuda"))
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        rep = ri.solve()
+        torch.cuda.synchronize()
+        te = time.perf_counter()
+        vsol = ri.velocity()
+        incompressible = {"beta_w": args.beta_w, "matvecs_per_s": args.steps / ti,
+                          "matvec": "reduced form beta_v A vt + K b~ (two extra FFT pairs over the PCG's internal "
+                                    "matvec)", "kernels": iclass,
+                          "solve": {"status": rep["status_name"], "time_to_tol_s": te - ts,
+                                    "outer_iters": rep["outer_iters"], "pcg_iters": rep["pcg_iters_total"],
+                                    "rel_grad": rep["gnorm"] / rep["gref"],
+                                    "r": rep["mismatch"] / (0.5 * float(((m0 - m1).double() ** 2).sum())
+                                                            * (2 * np.pi / n) ** 3),
+                                    "div_ratio": float(ri.fd_div(vsol).norm() / vsol.norm())}}
+        log("near-incompressible: %s" % json.dumps(incompressible))
+        del ri, vsol, gi, vti
 
     learned = None
     if args.learned_train > 0 and not args.no_solve:
@@ -313,6 +364,7 @@ def main():
                      "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": avg_ms, "launches": dom_n},
         "kernels": per_class,
         "mixed_storage_matvec": mixed,
+        "near_incompressible": incompressible,
         "solve_fp32": solve,
         "learned_warm_start": learned,
         "cpu_baseline": cpu,
