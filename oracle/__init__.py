@@ -62,6 +62,7 @@ def lib():
             "orc_set_beta_w": (None, [vp, d]),
             "orc_gradient_l2": (None, [vp, _dp]),
             "orc_matvec_sym": (None, [vp, _dp, _dp]),
+            "orc_jacobian_det": (None, [vp, _dp]),
             "orc_feet": (None, [i, i, i, i, _dp, _dp, _dp]),
             "orc_adjoint_factor": (None, [i, i, i, i, _dp, _dp, _dp]),
             "orc_create": (vp, [i, i, i, i, d]),
@@ -273,6 +274,12 @@ class Oracle:
         out = np.empty_like(vt)
         lib().orc_matvec(self._h, _p(vt), _p(out))
         return out
+
+    def jacobian_det(self):
+        """det grad y of the map y with m(1) = m0 o y at the current v."""
+        J = np.empty(self.shape)
+        lib().orc_jacobian_det(self._h, _p(J))
+        return J
 
     def precond(self, r):
         r = _f64(r)

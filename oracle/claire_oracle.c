@@ -699,6 +699,34 @@ void orc_precond(orc_ctx *o, const double *r, double *z)
         orc_reg_op(o->n1, o->n2, o->n3, r, z, 1, o->beta, o->beta_w);
 }
 
+/* Jacobian determinant J = det grad y of the map y with m(x, 1) =
+ * m0(y(x)) (Section 2.3, the bounds [J_min, 1/J_min] of the parameter
+ * search).  Reading (the paper does not say how J is computed): grad y
+ * transported by v gives d_t J + v.grad J = -(div v) J, J(x, 0) = 1,
+ * solved with the state's semi-Lagrangian step and Heun's rule for the
+ * source along the characteristic from X_f (time t_j) to x (time t_j+1):
+ *   J^{j+1}(x) = J^j(X_f) (1 - dt/2 (d_f + d - dt d_f d)),
+ * d = div_h v at x and d_f = d interpolated at X_f.                      */
+void orc_jacobian_det(orc_ctx *o, double *J)
+{
+    long N = o->N;
+    double dt = 1.0 / o->nt;
+    double *d = malloc(sizeof(double) * N), *dfo = malloc(sizeof(double) * N);
+    double *f = malloc(sizeof(double) * N), *cur = malloc(sizeof(double) * N);
+    orc_div(o->n1, o->n2, o->n3, o->v, d);
+    orc_interp(o->n1, o->n2, o->n3, d, o->df, dfo);
+    for (long p = 0; p < N; ++p) {
+        f[p] = 1.0 - 0.5 * dt * (dfo[p] + d[p] - dt * dfo[p] * d[p]);
+        cur[p] = 1.0;
+    }
+    for (int j = 0; j < o->nt; ++j) {
+        orc_interp(o->n1, o->n2, o->n3, cur, o->df, J);
+        for (long p = 0; p < N; ++p) J[p] *= f[p];
+        memcpy(cur, J, sizeof(double) * N);
+    }
+    free(d); free(dfo); free(f); free(cur);
+}
+
 /* Read back an internal field: which = 0 state m^j, 1 adjoint lam^j,
  * 2 incremental state mt^j, 3 incremental adjoint lamt^j, 4 forward feet
  * (3N), 5 backward feet (3N), 6 adjoint factor c.                         */
