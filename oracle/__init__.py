@@ -63,6 +63,9 @@ def lib():
             "orc_gradient_l2": (None, [vp, _dp]),
             "orc_matvec_sym": (None, [vp, _dp, _dp]),
             "orc_jacobian_det": (None, [vp, _dp]),
+            "orc_set_beta": (None, [vp, d, d]),
+            "orc_param_search": (i, [vp, d, d, d, d, d, d, i, i, i, d, _dp, i, _ip, _dp, _dp]),
+            "orc_param_continuation": (i, [vp, d, d, d, d, i, i, d, _dp, i, _ip]),
             "orc_feet": (None, [i, i, i, i, _dp, _dp, _dp]),
             "orc_adjoint_factor": (None, [i, i, i, i, _dp, _dp, _dp]),
             "orc_create": (vp, [i, i, i, i, d]),
@@ -280,6 +283,34 @@ class Oracle:
         J = np.empty(self.shape)
         lib().orc_jacobian_det(self._h, _p(J))
         return J
+
+    def set_beta(self, beta_v, beta_w=0.0):
+        self.beta, self.beta_w = float(beta_v), float(beta_w)
+        lib().orc_set_beta(self._h, self.beta, self.beta_w)
+
+    def param_search(self, jmin=0.25, beta_v_max=1.0, beta_v_min=1e-5, beta_w_max=1e-5, beta_w_min=1e-7,
+                     rel_change=0.1, search_beta_w=True, max_outer=50, max_pcg=10, gtol=1e-2):
+        """Returns (status, beta_v*, beta_w*, log rows [beta_v, beta_w, min J,
+        max J, valid, GN, PCG, status, mismatch, 0])."""
+        cap = 256
+        log = np.zeros((cap, 10))
+        nr = ctypes.c_int()
+        bv, bw = ctypes.c_double(), ctypes.c_double()
+        st = lib().orc_param_search(self._h, jmin, beta_v_max, beta_v_min, beta_w_max, beta_w_min, rel_change,
+                                    int(search_beta_w), int(max_outer), int(max_pcg), float(gtol), _p(log), cap,
+                                    ctypes.byref(nr), ctypes.byref(bv), ctypes.byref(bw))
+        self.beta, self.beta_w = bv.value, bw.value
+        return st, bv.value, bw.value, log[: min(nr.value, cap)]
+
+    def param_continuation(self, beta_v, beta_w, beta_v_max=1.0, beta_w_max=1e-5, max_outer=50, max_pcg=10,
+                           gtol=1e-2):
+        cap = 256
+        log = np.zeros((cap, 10))
+        nr = ctypes.c_int()
+        lib().orc_param_continuation(self._h, beta_v_max, beta_w_max, float(beta_v), float(beta_w), int(max_outer),
+                                     int(max_pcg), float(gtol), _p(log), cap, ctypes.byref(nr))
+        self.beta, self.beta_w = float(beta_v), float(beta_w)
+        return log[: min(nr.value, cap)]
 
     def precond(self, r):
         r = _f64(r)

@@ -883,6 +883,146 @@ int orc_solve(orc_ctx *o, int max_outer, int max_pcg, double gtol,
     return status;
 }
 
+/* ------------------------------------------ parameter identification
+ * Section 2.3.  A trial sets (beta_v, beta_w), runs the GN solve from the
+ * current velocity (the previous trial's result) and tests the bounds
+ * J_min <= det grad y <= 1/J_min.  Each trial appends a log row: beta_v,
+ * beta_w, min J, max J, valid, GN iterations, PCG iterations, status,
+ * final mismatch, 0.                                                     */
+void orc_set_beta(orc_ctx *o, double beta_v, double beta_w)
+{
+    o->beta = beta_v;
+    o->beta_w = beta_w;
+}
+
+typedef struct {
+    int max_outer, max_pcg;
+    double gtol, jmin;
+    double *log;
+    int max_rows, rows;
+    double *best;           /* velocity of the last valid trial (3N) */
+    int last_ok;
+} search_run;
+
+static int search_trial(orc_ctx *o, search_run *sr, double bv, double bw)
+{
+    orc_set_beta(o, bv, bw);
+    double *log = malloc(sizeof(double) * 8 * (sr->max_outer + 1));
+    int nout = 0;
+    double gref;
+    int st = orc_solve(o, sr->max_outer, sr->max_pcg, sr->gtol, NULL, NULL, log, &nout, &gref);
+    int pcg = 0;
+    for (int k = 0; k < nout; ++k) pcg += (int)log[8 * k + 5];
+    double mis = log[8 * nout + 2];
+    free(log);
+    double *J = malloc(sizeof(double) * o->N);
+    orc_jacobian_det(o, J);
+    double lo = J[0], hi = J[0];
+    for (long p = 1; p < o->N; ++p) {
+        if (J[p] < lo) lo = J[p];
+        if (J[p] > hi) hi = J[p];
+    }
+    free(J);
+    int ok = isfinite(lo) && isfinite(hi) && lo >= sr->jmin && hi <= 1.0 / sr->jmin;
+    if (ok && sr->best) memcpy(sr->best, o->v, sizeof(double) * 3 * o->N);
+    sr->last_ok = ok;
+    if (sr->rows < sr->max_rows) {
+        double *row = sr->log + 10 * sr->rows;
+        row[0] = bv; row[1] = bw; row[2] = lo; row[3] = hi; row[4] = ok;
+        row[5] = nout; row[6] = pcg; row[7] = st; row[8] = mis; row[9] = 0.0;
+    }
+    sr->rows++;
+    return ok;
+}
+
+/* Parameter search: (i) beta_w = beta_w_max; beta_v = beta_v_max and then
+ * one decade smaller per trial while the bounds hold (never below
+ * beta_v_min); after the first breach, bisection between the last valid
+ * value and the breaching one until the next midpoint would move beta_v by
+ * less than rel_change of the valid value; beta_v* is the last valid value.
+ * (ii) beta_v = beta_v*; beta_w one decade smaller per trial from
+ * beta_w_max while the bounds hold (never below beta_w_min); beta_w* is the
+ * last valid value.  Decade steps below a minimum are compared with a
+ * relative slack of 1e-9.  The context ends at the solution of the last
+ * valid trial, the one for (beta_v*, beta_w*), restored when a later trial
+ * breached the bounds.  Returns 0, or 3 when beta_v_max already breaches
+ * the bounds.                                                             */
+int orc_param_search(orc_ctx *o, double jmin, double bv_max, double bv_min, double bw_max, double bw_min,
+                     double rel_change, int search_bw, int max_outer, int max_pcg, double gtol,
+                     double *log, int max_rows, int *n_rows, double *bv_star, double *bw_star)
+{
+    double *best = malloc(sizeof(double) * 3 * o->N);
+    search_run sr = {max_outer, max_pcg, gtol, jmin, log, max_rows, 0, best, 0};
+    double valid_bv = -1.0, breach_bv = -1.0;
+    double bv = bv_max;
+    while (1) {
+        if (!search_trial(o, &sr, bv, bw_max)) { breach_bv = bv; break; }
+        valid_bv = bv;
+        if (bv / 10.0 < bv_min * (1.0 - 1e-9)) break;
+        bv = bv / 10.0;
+    }
+    int status = 0;
+    if (valid_bv < 0.0) {
+        status = 3;
+        valid_bv = bv_max;
+    } else if (breach_bv > 0.0) {
+        while (1) {
+            double mid = 0.5 * (valid_bv + breach_bv);
+            if (valid_bv - mid < rel_change * valid_bv) break;
+            if (search_trial(o, &sr, mid, bw_max)) valid_bv = mid;
+            else breach_bv = mid;
+        }
+    }
+    double bw_valid = bw_max;
+    if (status == 0 && search_bw && bw_max > 0.0) {
+        double bw = bw_max;
+        while (bw / 10.0 >= bw_min * (1.0 - 1e-9)) {
+            bw = bw / 10.0;
+            if (!search_trial(o, &sr, valid_bv, bw)) break;
+            bw_valid = bw;
+        }
+    }
+    if (status == 0 && !sr.last_ok) {
+        orc_set_velocity(o, best);
+        orc_set_beta(o, valid_bv, bw_valid);
+    }
+    free(best);
+    if (n_rows) *n_rows = sr.rows;
+    if (bv_star) *bv_star = valid_bv;
+    if (bw_star) *bw_star = bw_valid;
+    return status;
+}
+
+/* Parameter continuation toward (bv_target, bw_target): beta_w = bw_max
+ * with beta_v = bv_max, bv_max/10, ... down to 10^ceil(log10 bv_target),
+ * then bv_target; then beta_v = bv_target with beta_w one decade smaller
+ * per solve from bw_max down to bw_target.  No bounds test (jmin = 0 in
+ * the valid column).                                                     */
+int orc_param_continuation(orc_ctx *o, double bv_max, double bw_max, double bv_target, double bw_target,
+                           int max_outer, int max_pcg, double gtol, double *log, int max_rows, int *n_rows)
+{
+    search_run sr = {max_outer, max_pcg, gtol, 0.0, log, max_rows, 0, NULL, 0};
+    double stop = pow(10.0, ceil(log10(bv_target)));
+    double bv = bv_max;
+    while (bv > stop * (1.0 + 1e-9)) {
+        search_trial(o, &sr, bv, bw_max);
+        bv = bv / 10.0;
+    }
+    search_trial(o, &sr, bv, bw_max);
+    if (fabs(bv - bv_target) > 1e-9 * bv_target) search_trial(o, &sr, bv_target, bw_max);
+    if (bw_target <= 0.0) {
+        if (bw_max > 0.0) search_trial(o, &sr, bv_target, 0.0);
+    } else {
+        double bw = bw_max;
+        while (bw > bw_target * (1.0 + 1e-9)) {
+            bw = bw / 10.0 > bw_target ? bw / 10.0 : bw_target;
+            search_trial(o, &sr, bv_target, bw);
+        }
+    }
+    if (n_rows) *n_rows = sr.rows;
+    return 0;
+}
+
 void orc_get_velocity(orc_ctx *o, double *v) { memcpy(v, o->v, sizeof(double) * 3 * o->N); }
 
 int orc_num_threads(void)
