@@ -62,7 +62,8 @@ enum {
     CL_ERR_STATE = -8,        /* call order violated (e.g. gradient before set_images) */
     CL_ERR_ALIAS = -9,        /* input and output buffers overlap */
     CL_STATUS_MAXIT = 1,      /* solve stopped at max_outer */
-    CL_STATUS_LINESEARCH_FAIL = 2 /* Armijo found no step; last accepted v kept */
+    CL_STATUS_LINESEARCH_FAIL = 2, /* Armijo found no step; last accepted v kept */
+    CL_STATUS_BOUNDS = 3      /* parameter search: beta_v_max already breaches the J bounds */
 };
 
 typedef struct {
@@ -180,6 +181,73 @@ enum {
     CL_FIELD_ADJ_FACTOR = 6   /* adjoint divergence factor c */
 };
 int cl_get_field(cl_ctx *ctx, int which, int j, float *out);
+
+/* ---------------------------------------------------------------------
+ * Parameter identification (Section 2.3).
+ *
+ * J = det grad y, y the map with m(1) = m0 o y, bounded by [J_min, 1/J_min]
+ * (Section 2.3).  The paper does not say how J is computed; here grad y is
+ * transported by v: d_t J + v.grad J = -(div v) J, J(0) = 1, with the
+ * state's semi-Lagrangian step and Heun's rule for the source along the
+ * characteristic, J^{j+1}(x) = J^j(X_f) (1 - dt/2 (d_f + d - dt d_f d)),
+ * d = div_h v, d_f = d at the foot X_f.
+ */
+
+/* New regularisation weights for the following solves (beta_v > 0,
+ * beta_w >= 0; CL_ERR_ARG otherwise).  Host only. */
+int cl_set_regularization(cl_ctx *ctx, double beta_v, double beta_w);
+
+/* J at the current v: *jmin, *jmax (may be NULL) receive its extremes (NaN
+ * if any value is not finite); J_out (device, n1 n2 n3 FP32, may be NULL)
+ * receives the field.  Synchronises. */
+int cl_jacobian_det(cl_ctx *ctx, float *J_out, double *jmin, double *jmax);
+
+typedef struct {
+    double jmin;              /* J_min in (0, 1): bounds [J_min, 1/J_min] (default 0.25) */
+    double beta_v_max;        /* first beta_v (default 1) */
+    double beta_v_min;        /* lowest beta_v tried (default 1e-5) */
+    double beta_w_max;        /* beta_w of the first stage, start of the second (default 1e-5) */
+    double beta_w_min;        /* lowest beta_w tried (default 1e-7) */
+    double rel_change;        /* bisection stop: relative change of beta_v (default 0.1) */
+    int search_beta_w;        /* 1: run the beta_w stage (default 1) */
+} cl_search_options;
+
+typedef struct {
+    double beta_v, beta_w;    /* beta_v*, beta_w* */
+    double jmin, jmax;        /* J extremes of the final solution */
+    int status;               /* CL_OK or CL_STATUS_BOUNDS */
+    int solves, gn_total, pcg_total;
+    double ms;                /* wall time */
+} cl_search_report;
+
+void cl_default_search_options(cl_search_options *so);
+
+/* Parameter search from the current v (Section 2.3, two stages):
+ *  (i)  beta_w = beta_w_max; beta_v = beta_v_max, then down by decades
+ *       (not below beta_v_min) while J stays within bounds; at the first
+ *       breach a bisection between the last valid and the breaching value,
+ *       stopped when the next midpoint would change beta_v by less than
+ *       rel_change times the valid value; beta_v* = the last valid value.
+ *  (ii) beta_v = beta_v*; beta_w down by decades from beta_w_max (not below
+ *       beta_w_min) while J stays within bounds; beta_w* = the last valid.
+ * Every trial is a cl_solve warm-started from the previous trial's v.  On
+ * return the context holds the solution for (beta_v*, beta_w*) and those
+ * weights.  CL_STATUS_BOUNDS if beta_v_max already breaches the bounds
+ * (then beta_v* = beta_v_max).  Each trial is logged (cl_get_search_log). */
+int cl_param_search(cl_ctx *ctx, const cl_search_options *so, cl_search_report *rep);
+
+/* Parameter continuation toward known weights (Section 2.3): solves at
+ * beta_w = beta_w_max for beta_v = beta_v_max, beta_v_max / 10, ... down to
+ * 10^ceil(log10 beta_v*), then beta_v*; then at beta_v* for beta_w from
+ * beta_w_max down by decades to beta_w* (beta_w_target <= beta_w_max).
+ * No bounds test; every solution's J extremes are logged. */
+int cl_param_continuation(cl_ctx *ctx, const cl_search_options *so, double beta_v_target, double beta_w_target,
+                          cl_search_report *rep);
+
+/* Trials of the last search or continuation, 10 doubles per row: beta_v,
+ * beta_w, J min, J max, within bounds (1/0), GN iterations, PCG iterations,
+ * solve status, final mismatch, solve ms.  rows may be NULL (count only). */
+int cl_get_search_log(cl_ctx *ctx, double *rows, int max_rows, int *n_rows);
 
 /* Building blocks on the context's grid (parity tests of single kernels):
  *   cl_interp:   out(x) = I[u](x + d(x)), tricubic Lagrange, d in index units (3 fields)

@@ -21,7 +21,7 @@ FIELD_FEET_F, FIELD_FEET_B, FIELD_ADJ_FACTOR = 4, 5, 6
 K_FEET, K_SL_STATE, K_SL_ADJOINT, K_SL_INC, K_FD, K_QUAD, K_FFT, K_VEC = range(8)
 K_NAMES = ["feet", "sl_state", "sl_adjoint", "sl_inc", "fd", "quadrature", "fft", "vec"]
 
-STATUS = {0: "ok", 1: "maxit", 2: "linesearch_fail"}
+STATUS = {0: "ok", 1: "maxit", 2: "linesearch_fail", 3: "bounds"}
 
 
 class cl_options(ctypes.Structure):
@@ -55,6 +55,37 @@ class cl_solve_report(ctypes.Structure):
         ("gnorm0", ctypes.c_double),
         ("gnorm", ctypes.c_double),
         ("gref", ctypes.c_double),
+        ("ms", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["status_name"] = STATUS.get(self.status, str(self.status))
+        return d
+
+
+class cl_search_options(ctypes.Structure):
+    _fields_ = [
+        ("jmin", ctypes.c_double),
+        ("beta_v_max", ctypes.c_double),
+        ("beta_v_min", ctypes.c_double),
+        ("beta_w_max", ctypes.c_double),
+        ("beta_w_min", ctypes.c_double),
+        ("rel_change", ctypes.c_double),
+        ("search_beta_w", ctypes.c_int),
+    ]
+
+
+class cl_search_report(ctypes.Structure):
+    _fields_ = [
+        ("beta_v", ctypes.c_double),
+        ("beta_w", ctypes.c_double),
+        ("jmin", ctypes.c_double),
+        ("jmax", ctypes.c_double),
+        ("status", ctypes.c_int),
+        ("solves", ctypes.c_int),
+        ("gn_total", ctypes.c_int),
+        ("pcg_total", ctypes.c_int),
         ("ms", ctypes.c_double),
     ]
 
@@ -102,6 +133,13 @@ SIGNATURES = {
     "cl_solve_forced": (_i, [_vp, ctypes.POINTER(_i), _dp, _i, ctypes.POINTER(cl_solve_report)]),
     "cl_get_solve_log": (_i, [_vp, _dp, _i, ctypes.POINTER(_i)]),
     "cl_deformed_template": (_i, [_vp, _vp]),
+    "cl_set_regularization": (_i, [_vp, _d, _d]),
+    "cl_jacobian_det": (_i, [_vp, _vp, _dp, _dp]),
+    "cl_default_search_options": (None, [ctypes.POINTER(cl_search_options)]),
+    "cl_param_search": (_i, [_vp, ctypes.POINTER(cl_search_options), ctypes.POINTER(cl_search_report)]),
+    "cl_param_continuation": (_i, [_vp, ctypes.POINTER(cl_search_options), _d, _d,
+                                   ctypes.POINTER(cl_search_report)]),
+    "cl_get_search_log": (_i, [_vp, _dp, _i, ctypes.POINTER(_i)]),
     "cl_get_field": (_i, [_vp, _i, _i, _vp]),
     "cl_interp": (_i, [_vp, _vp, _vp, _vp]),
     "cl_fd_grad": (_i, [_vp, _vp, _vp]),
@@ -300,6 +338,48 @@ class Registration:
         buf = (ctypes.c_double * (8 * max(nrows.value, 1)))()
         lib().cl_get_solve_log(self._h, buf, nrows.value, ctypes.byref(nrows))
         return [list(buf[8 * r: 8 * r + 8]) for r in range(nrows.value)]
+
+    def set_regularization(self, beta_v, beta_w=0.0):
+        self._chk(lib().cl_set_regularization(self._h, float(beta_v), float(beta_w)))
+
+    def jacobian_det(self, want_field=False):
+        """(J field or None, min J, max J) of J = det grad y at the current v."""
+        J = self.empty() if want_field else None
+        lo, hi = _d(), _d()
+        self._chk(lib().cl_jacobian_det(self._h, _ptr(J) if J is not None else None, ctypes.byref(lo),
+                                        ctypes.byref(hi)))
+        return J, lo.value, hi.value
+
+    @staticmethod
+    def search_options(**kw):
+        so = cl_search_options()
+        lib().cl_default_search_options(ctypes.byref(so))
+        for k, v in kw.items():
+            setattr(so, k, v)
+        return so
+
+    def param_search(self, **kw):
+        """Two-stage beta_v / beta_w search under the J bounds; keyword
+        arguments override cl_search_options fields."""
+        so = self.search_options(**kw)
+        rep = cl_search_report()
+        self._chk(lib().cl_param_search(self._h, ctypes.byref(so), ctypes.byref(rep)))
+        return rep.as_dict()
+
+    def param_continuation(self, beta_v, beta_w, **kw):
+        so = self.search_options(**kw)
+        rep = cl_search_report()
+        self._chk(lib().cl_param_continuation(self._h, ctypes.byref(so), float(beta_v), float(beta_w),
+                                              ctypes.byref(rep)))
+        return rep.as_dict()
+
+    def search_log(self):
+        """Rows [beta_v, beta_w, J min, J max, valid, GN, PCG, status, mismatch, ms]."""
+        nrows = ctypes.c_int()
+        lib().cl_get_search_log(self._h, None, 0, ctypes.byref(nrows))
+        buf = (ctypes.c_double * (10 * max(nrows.value, 1)))()
+        lib().cl_get_search_log(self._h, buf, nrows.value, ctypes.byref(nrows))
+        return [list(buf[10 * r: 10 * r + 10]) for r in range(nrows.value)]
 
     def deformed_template(self):
         out = self.empty()

@@ -68,6 +68,7 @@ struct cl_ctx {
     bool gref_valid = false;
     double gref = 0.0;
     std::vector<std::vector<double>> log;
+    std::vector<std::vector<double>> slog;  // parameter search / continuation trials
     std::string err;
     Prof prof;
 };
@@ -572,6 +573,198 @@ size_t workspace_bytes(int n1, int n2, int n3, const cl_options &o, bool lean)
     return b;
 }
 
+// J = det grad y at the current v: min and max, and the field (N floats,
+// device) if J_out is given.  Uses the feet of the current v and tmp3.
+void jacobian(cl_ctx *ctx, double *jmin, double *jmax, float *J_out)
+{
+    ensure_feet(ctx, true);
+    float *J = ctx->tmp3 + 2 * ctx->N;
+    run(ctx, CL_K_SL_STATE, [&] {
+        launch_jacobian(ctx->g, ctx->dt, ctx->nt, ctx->divv, ctx->df, ctx->box_f, ctx->tmp3, J, ctx->s);
+    });
+    run(ctx, CL_K_VEC, [&] { launch_minmax(J, ctx->N, ctx->partials, ctx->nparts / 2, ctx->dscal, ctx->s); });
+    HIPCHK(hipMemcpyAsync(ctx->hscal, ctx->dscal, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->s));
+    if (J_out) HIPCHK(hipMemcpyAsync(J_out, J, ctx->N * sizeof(float), hipMemcpyDeviceToDevice, ctx->s));
+    HIPCHK(hipStreamSynchronize(ctx->s));
+    *jmin = ctx->hscal[0];
+    *jmax = ctx->hscal[1];
+}
+
+// new regularisation weights: the cached beta A v and g_ref depend on them
+void set_regularization(cl_ctx *ctx, double beta_v, double beta_w)
+{
+    ctx->opt.beta_v = beta_v;
+    ctx->opt.beta_w = beta_w;
+    ctx->av = false;
+    ctx->gref_valid = false;
+}
+
+// Parameter search (Section 2.3, parameter identification).  Every trial
+// is a GN solve warm-started from the previous trial's velocity, followed
+// by the bounds test J_min <= det grad y <= 1/J_min.
+//  (i)  beta_w = beta_w_max; beta_v from beta_v_max down by decades while
+//       the bounds hold (not below beta_v_min); on the first breach a
+//       bisection between the last valid and the breaching value, stopped
+//       when the next step would change beta_v by less than rel_change of
+//       the valid value; beta_v* = the last valid value.
+//  (ii) beta_v = beta_v*; beta_w from beta_w_max down by decades while the
+//       bounds hold (not below beta_w_min); beta_w* = the last valid value.
+// The velocity of the last valid trial, the solution for (beta_v*,
+// beta_w*), is kept in host memory and restored at the end when a later
+// trial breached the bounds.
+struct Search {
+    cl_ctx *ctx;
+    const cl_search_options &so;
+    cl_search_report R{};
+    std::vector<float> best;     // v of the last valid trial (host)
+    double best_jmin = 0, best_jmax = 0;
+
+    bool trial(double bv, double bw)
+    {
+        set_regularization(ctx, bv, bw);
+        cl_solve_report sr{};
+        solve(ctx, nullptr, nullptr, 0, &sr);
+        double jl = 0, jh = 0;
+        jacobian(ctx, &jl, &jh, nullptr);
+        const bool ok = std::isfinite(jl) && std::isfinite(jh) && jl >= so.jmin && jh <= 1.0 / so.jmin;
+        R.solves++;
+        R.gn_total += sr.outer_iters;
+        R.pcg_total += sr.pcg_iters_total;
+        R.jmin = jl;
+        R.jmax = jh;
+        ctx->slog.push_back({bv, bw, jl, jh, ok ? 1.0 : 0.0, (double)sr.outer_iters, (double)sr.pcg_iters_total,
+                             (double)sr.status, sr.mismatch, sr.ms});
+        if (ok && so.jmin > 0.0) {
+            best.resize(3 * ctx->N);
+            HIPCHK(hipMemcpy(best.data(), ctx->v, best.size() * sizeof(float), hipMemcpyDeviceToHost));
+            best_jmin = jl;
+            best_jmax = jh;
+        }
+        return ok;
+    }
+
+    // back to the last valid trial's solution and weights
+    void restore(double bv, double bw)
+    {
+        HIPCHK(hipMemcpy(ctx->v, best.data(), best.size() * sizeof(float), hipMemcpyHostToDevice));
+        ctx->vel = true;
+        ctx->feet_f = ctx->feet_b = ctx->state = ctx->av = false;
+        set_regularization(ctx, bv, bw);
+        R.jmin = best_jmin;
+        R.jmax = best_jmax;
+    }
+};
+
+constexpr double DECADE_SLACK = 1e-9;   // decade steps compared with a relative slack
+
+int param_search(cl_ctx *ctx, const cl_search_options &so, cl_search_report *rep)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    ctx->slog.clear();
+    Search S{ctx, so};
+    const double bw = so.beta_w_max;
+    double bv = so.beta_v_max, good = -1.0, bad = -1.0;
+    for (;;) {
+        if (!S.trial(bv, bw)) {
+            bad = bv;
+            break;
+        }
+        good = bv;
+        const double next = bv / 10.0;
+        if (next < so.beta_v_min * (1.0 - DECADE_SLACK)) break;
+        bv = next;
+    }
+    int status = CL_OK;
+    if (good < 0.0) {
+        status = CL_STATUS_BOUNDS;
+        good = so.beta_v_max;
+    } else if (bad > 0.0) {
+        for (;;) {
+            const double mid = 0.5 * (good + bad);
+            if (good - mid < so.rel_change * good) break;
+            if (S.trial(mid, bw))
+                good = mid;
+            else
+                bad = mid;
+        }
+    }
+    double bw_star = bw;
+    if (status == CL_OK && so.search_beta_w && bw > 0.0) {
+        for (double b = bw;;) {
+            const double next = b / 10.0;
+            if (next < so.beta_w_min * (1.0 - DECADE_SLACK)) break;
+            if (!S.trial(good, next)) break;
+            bw_star = b = next;
+        }
+    }
+    const auto &last = ctx->slog.back();
+    if (status == CL_OK && last[4] != 1.0) S.restore(good, bw_star);
+    S.R.beta_v = good;
+    S.R.beta_w = bw_star;
+    S.R.status = status;
+    S.R.ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (rep) *rep = S.R;
+    return status;
+}
+
+// Parameter continuation (Section 2.3): the search's solve sequence toward
+// known targets without bounds tests or bisection.  (i) beta_w = beta_w_max,
+// beta_v = beta_v_max, beta_v_max / 10, ... down to 10^k, k = ceil(log10
+// beta_v*), then beta_v*; (ii) beta_v = beta_v*, beta_w from beta_w_max down
+// by decades to beta_w*.  Each solve is warm-started from the previous one;
+// J bounds of every solution are logged.
+int param_continuation(cl_ctx *ctx, const cl_search_options &so, double bv_star, double bw_star,
+                       cl_search_report *rep)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    ctx->slog.clear();
+    cl_search_options loose = so;
+    loose.jmin = 0.0;   // the log's valid column then only flags finite J
+    Search S{ctx, loose};
+    const double stop = std::pow(10.0, std::ceil(std::log10(bv_star)));
+    double bv = so.beta_v_max;
+    for (; bv > stop * (1.0 + DECADE_SLACK); bv /= 10.0) S.trial(bv, so.beta_w_max);
+    S.trial(bv, so.beta_w_max);
+    if (std::fabs(bv - bv_star) > DECADE_SLACK * bv_star) S.trial(bv_star, so.beta_w_max);
+    if (bw_star <= 0.0) {
+        if (so.beta_w_max > 0.0) S.trial(bv_star, 0.0);
+    } else {
+        for (double b = so.beta_w_max; b > bw_star * (1.0 + DECADE_SLACK);) {
+            b = std::max(b / 10.0, bw_star);
+            S.trial(bv_star, b);
+        }
+    }
+    S.R.beta_v = bv_star;
+    S.R.beta_w = bw_star;
+    S.R.status = CL_OK;
+    S.R.ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (rep) *rep = S.R;
+    return CL_OK;
+}
+
+int check_reg(double beta_v, double beta_w, cl_ctx *ctx)
+{
+    if (!(beta_v > 0.0) || !std::isfinite(beta_v)) return fail(ctx, CL_ERR_ARG, "beta_v must be > 0");
+    if (!(beta_w >= 0.0) || !std::isfinite(beta_w)) return fail(ctx, CL_ERR_ARG, "beta_w must be >= 0");
+    return CL_OK;
+}
+
+int check_search(const cl_search_options *so, cl_ctx *ctx)
+{
+    if (!so) return fail(ctx, CL_ERR_ARG, "search options pointer is NULL");
+    if (!(so->jmin > 0.0 && so->jmin < 1.0)) return fail(ctx, CL_ERR_ARG, "jmin must lie in (0, 1)");
+    if (!(so->beta_v_max > 0.0) || !(so->beta_v_min > 0.0) || !(so->beta_v_min <= so->beta_v_max) ||
+        !std::isfinite(so->beta_v_max))
+        return fail(ctx, CL_ERR_ARG, "need 0 < beta_v_min <= beta_v_max");
+    if (!(so->beta_w_max >= 0.0) || !(so->beta_w_min >= 0.0) || !(so->beta_w_min <= so->beta_w_max) ||
+        !std::isfinite(so->beta_w_max))
+        return fail(ctx, CL_ERR_ARG, "need 0 <= beta_w_min <= beta_w_max");
+    if (!(so->rel_change > 0.0 && so->rel_change < 1.0)) return fail(ctx, CL_ERR_ARG, "rel_change must lie in (0, 1)");
+    if (so->search_beta_w && so->beta_w_max > 0.0 && !(so->beta_w_min > 0.0))
+        return fail(ctx, CL_ERR_ARG, "the beta_w search needs beta_w_min > 0");
+    return CL_OK;
+}
+
 int check_options(const cl_options *o, cl_ctx *ctx)
 {
     if (!o) return fail(ctx, CL_ERR_ARG, "options pointer is NULL");
@@ -890,6 +1083,77 @@ int cl_get_solve_log(cl_ctx *ctx, double *rows, int max_rows, int *n_rows)
     if (rows)
         for (int r = 0; r < std::min(max_rows, (int)ctx->log.size()); ++r)
             for (int c = 0; c < 8; ++c) rows[8 * r + c] = ctx->log[r][c];
+    return CL_OK;
+}
+
+int cl_set_regularization(cl_ctx *ctx, double beta_v, double beta_w)
+{
+    NEED_CTX();
+    const int st = check_reg(beta_v, beta_w, ctx);
+    if (st != CL_OK) return st;
+    set_regularization(ctx, beta_v, beta_w);
+    return CL_OK;
+}
+
+int cl_jacobian_det(cl_ctx *ctx, float *J_out, double *jmin, double *jmax)
+{
+    NEED_CTX();
+    if (!ctx->vel) return fail(ctx, CL_ERR_STATE, "cl_set_velocity has not been called");
+    API_BEGIN
+    double lo = 0, hi = 0;
+    jacobian(ctx, &lo, &hi, J_out);
+    if (jmin) *jmin = lo;
+    if (jmax) *jmax = hi;
+    return CL_OK;
+    API_END
+}
+
+void cl_default_search_options(cl_search_options *so)
+{
+    if (!so) return;
+    std::memset(so, 0, sizeof(*so));
+    so->jmin = 0.25;
+    so->beta_v_max = 1.0;
+    so->beta_v_min = 1e-5;
+    so->beta_w_max = 1e-5;
+    so->beta_w_min = 1e-7;
+    so->rel_change = 0.1;
+    so->search_beta_w = 1;
+}
+
+int cl_param_search(cl_ctx *ctx, const cl_search_options *so, cl_search_report *rep)
+{
+    NEED_CTX();
+    const int st = check_search(so, ctx);
+    if (st != CL_OK) return st;
+    if (!ctx->images) return fail(ctx, CL_ERR_STATE, "cl_set_images has not been called");
+    API_BEGIN
+    return param_search(ctx, *so, rep);
+    API_END
+}
+
+int cl_param_continuation(cl_ctx *ctx, const cl_search_options *so, double beta_v_target, double beta_w_target,
+                          cl_search_report *rep)
+{
+    NEED_CTX();
+    int st = check_search(so, ctx);
+    if (st != CL_OK) return st;
+    st = check_reg(beta_v_target, beta_w_target, ctx);
+    if (st != CL_OK) return st;
+    if (beta_w_target > so->beta_w_max) return fail(ctx, CL_ERR_ARG, "beta_w target above beta_w_max");
+    if (!ctx->images) return fail(ctx, CL_ERR_STATE, "cl_set_images has not been called");
+    API_BEGIN
+    return param_continuation(ctx, *so, beta_v_target, beta_w_target, rep);
+    API_END
+}
+
+int cl_get_search_log(cl_ctx *ctx, double *rows, int max_rows, int *n_rows)
+{
+    NEED_CTX();
+    if (n_rows) *n_rows = (int)ctx->slog.size();
+    if (rows)
+        for (int r = 0; r < std::min(max_rows, (int)ctx->slog.size()); ++r)
+            for (int c = 0; c < 10; ++c) rows[10 * r + c] = ctx->slog[r][c];
     return CL_OK;
 }
 

@@ -55,7 +55,9 @@ __device__ __forceinline__ float fd8(const T *__restrict__ u, int p, int c, int 
 
 // Sum of v over a workgroup of blockDim.x (multiple of 64, <= 1024) threads
 // in a fixed order (wavefront shuffles, then wave 0 over the wave sums);
-// the result is valid in thread 0.
+// the result is valid in thread 0.  Every thread of the block must call it;
+// the closing barrier keeps wave 0's reads of wsum ahead of the writes of a
+// following call.
 __device__ __forceinline__ double block_sum(double v)
 {
     __shared__ double wsum[16];
@@ -70,6 +72,7 @@ __device__ __forceinline__ double block_sum(double v)
 #pragma unroll
         for (int off = 8; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
     }
+    __syncthreads();
     return v;
 }
 
@@ -114,6 +117,12 @@ void launch_sl_inc(const Grid &g, int dt_q, const void *q, const float *d, const
                    float sS, int dt_out, void *out, hipStream_t s);
 // boxes: scratch of tile_box_ints(g) ints (filled here from d)
 void launch_interp_f32(const Grid &g, const float *u, const float *d, int *boxes, float *out, hipStream_t s);
+// det grad y by SL transport with the Heun source factor (forward feet and
+// boxes); work: 2N floats; out: N floats
+void launch_jacobian(const Grid &g, float dt, int nt, const float *divv, const float *df, const int *box_f,
+                     float *work, float *out, hipStream_t s);
+// min and max of n floats into out[0], out[1] (FP64), partials: 2 * nblocks
+void launch_minmax(const float *a, size_t n, double *partials, int nblocks, double *out, hipStream_t s);
 
 // stencils (k_stencil.hip)
 void launch_fd_grad(const Grid &g, const float *u, float *out3, hipStream_t s);

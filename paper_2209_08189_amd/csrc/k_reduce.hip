@@ -49,6 +49,49 @@ __global__ __launch_bounds__(TPB) void k_finalize(const double *__restrict__ par
     }
 }
 
+// per-block min and max (a non-finite value turns both into NaN)
+__global__ __launch_bounds__(TPB) void k_minmax(const float *__restrict__ a, size_t n, double *__restrict__ partials)
+{
+    float lo = INFINITY, hi = -INFINITY;
+    bool bad = false;
+    const size_t stride = (size_t)gridDim.x * TPB;
+    for (size_t p = (size_t)blockIdx.x * TPB + threadIdx.x; p < n; p += stride) {
+        const float x = a[p];
+        bad |= !isfinite(x);
+        lo = fminf(lo, x);
+        hi = fmaxf(hi, x);
+    }
+    if (bad) lo = hi = NAN;
+    __shared__ float slo[TPB], shi[TPB];
+    slo[threadIdx.x] = lo;
+    shi[threadIdx.x] = hi;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float l = slo[0], h = shi[0];
+        for (int q = 1; q < TPB; ++q) {
+            const float lq = slo[q], hq = shi[q];
+            l = (isnan(l) || isnan(lq)) ? NAN : fminf(l, lq);
+            h = (isnan(h) || isnan(hq)) ? NAN : fmaxf(h, hq);
+        }
+        partials[2 * blockIdx.x] = l;
+        partials[2 * blockIdx.x + 1] = h;
+    }
+}
+
+__global__ __launch_bounds__(TPB) void k_minmax_final(const double *__restrict__ partials, int nb,
+                                                      double *__restrict__ out)
+{
+    if (threadIdx.x != 0) return;
+    double l = partials[0], h = partials[1];
+    for (int q = 1; q < nb; ++q) {
+        const double lq = partials[2 * q], hq = partials[2 * q + 1];
+        l = (isnan(l) || isnan(lq)) ? NAN : fmin(l, lq);
+        h = (isnan(h) || isnan(hq)) ? NAN : fmax(h, hq);
+    }
+    out[0] = l;
+    out[1] = h;
+}
+
 __global__ __launch_bounds__(TPB) void k_pcg_update(float *__restrict__ x, float *__restrict__ r,
                                                     const float *__restrict__ p, const float *__restrict__ Hp,
                                                     float alpha, size_t n, double *__restrict__ partials)
@@ -226,6 +269,12 @@ void launch_dot(const float *a, const float *b, size_t n, double *partials, int 
 void launch_count_nonfinite(const float *a, size_t n, double *partials, int nblocks, hipStream_t s)
 {
     hipLaunchKernelGGL(k_count_nonfinite, dim3(nblocks), dim3(TPB), 0, s, a, n, partials);
+}
+
+void launch_minmax(const float *a, size_t n, double *partials, int nblocks, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_minmax, dim3(nblocks), dim3(TPB), 0, s, a, n, partials);
+    hipLaunchKernelGGL(k_minmax_final, dim3(1), dim3(TPB), 0, s, partials, nblocks, out);
 }
 
 void launch_finalize(const double *partials, int nblocks, double scale, double *out, hipStream_t s)

@@ -9,6 +9,8 @@
 // between neighbouring lanes and neighbouring workgroups.
 #include "internal.h"
 
+#include <utility>
+
 namespace clh {
 
 namespace {
@@ -148,6 +150,24 @@ __global__ __launch_bounds__(TPB) void k_adj_factor(Grid g, float dt, const floa
     if (p >= g.N) return;
     const float d = divv[p], db = dbar[p];
     c[p] = 1.0f + 0.5f * dt * (db + d + dt * db * d);
+}
+
+// Source factor of the Jacobian determinant transport d_t J + v.grad J =
+// -(div v) J over one step along the forward characteristic (Heun):
+// f = 1 - dt/2 (d_f + d - dt d_f d), d_f = div v at the foot X_f (in place:
+// dfoot holds d_f on entry and f on exit).
+__global__ __launch_bounds__(TPB) void k_jac_factor(Grid g, float dt, const float *__restrict__ divv, float *dfoot)
+{
+    const int p = blockIdx.x * TPB + threadIdx.x;
+    if (p >= g.N) return;
+    const float d = divv[p], df = dfoot[p];
+    dfoot[p] = 1.0f - 0.5f * dt * (df + d - dt * df * d);
+}
+
+__global__ __launch_bounds__(TPB) void k_fill1(float *x, int n)
+{
+    const int p = blockIdx.x * TPB + threadIdx.x;
+    if (p < n) x[p] = 1.0f;
 }
 
 // ------------------------------------------------ semi-Lagrangian steps
@@ -669,6 +689,26 @@ void launch_sl_inc(const Grid &g, int dt_q, const void *q, const float *d, const
             launch_sl<Tq, To, SL_INC>(g, (const Tq *)q, d, prm, (To *)out, boxes, s);
         });
     });
+}
+
+// J = det grad y of the map y with m(1) = m0 o y: J^0 = 1, J^{j+1} =
+// f . I[J^j](X_f) with the Heun source factor f; work holds 2N floats (f and
+// one ping-pong half), the result goes to out (N floats).
+void launch_jacobian(const Grid &g, float dt, int nt, const float *divv, const float *df, const int *box_f,
+                     float *work, float *out, hipStream_t s)
+{
+    float *f = work, *tmp = work + (size_t)g.N;
+    launch_sl<float, float, SL_STATE>(g, divv, df, SLParams{}, f, box_f, s);
+    hipLaunchKernelGGL(k_jac_factor, grid_of(g), dim3(TPB), 0, s, g, dt, divv, f);
+    // ping-pong so that the last step writes out
+    float *a = (nt & 1) ? tmp : out, *b = (nt & 1) ? out : tmp;
+    hipLaunchKernelGGL(k_fill1, grid_of(g), dim3(TPB), 0, s, a, g.N);
+    SLParams prm{};
+    prm.e = f;
+    for (int j = 0; j < nt; ++j) {
+        launch_sl<float, float, SL_ADJ>(g, a, df, prm, b, box_f, s);
+        std::swap(a, b);
+    }
 }
 
 void launch_interp_f32(const Grid &g, const float *u, const float *d, int *boxes, float *out, hipStream_t s)

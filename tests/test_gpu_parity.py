@@ -361,6 +361,33 @@ def test_solve_cfg1_replay_5x10():
     assert ev < 5e-3 and em < 2e-2
 
 
+@pytest.mark.parametrize("bw", [0.0, 1e-5])
+def test_free_solve_decisions_match_oracle(bw):
+    """Free runs at 32^3 (beta_v = 0.1, gtol 1e-2, <= 10 PCG): both sides
+    take their own decisions, which must be the same PCG iteration counts
+    and step lengths per GN step, with J, mismatch and ||g|| to 1e-5.  The
+    PCG stopping test reads the device-reduced ||r||^2; a race in that
+    reduction once made the GPU take extra PCG iterations while the forced
+    replays, which do not read it, still agreed."""
+    shape, m0, m1, _ = _cfg1(32)
+    o = oracle.Oracle(shape, nt=4, beta=0.1, beta_w=bw)
+    o.set_images(m0, m1)
+    o.set_velocity(np.zeros((3,) + shape))
+    st, log, gref = o.solve(max_outer=10, max_pcg=10, gtol=1e-2)
+    r = reg(shape, beta_v=0.1, beta_w=bw, max_outer=10, max_pcg=10)
+    r.set_images(dev(m0), dev(m1))
+    rep = r.solve()
+    glog = np.array(r.solve_log())
+    print("oracle:", log[:, [1, 2, 4, 5, 6]].tolist())
+    print("gpu:   ", glog[:, [1, 2, 4, 5, 6]].tolist())
+    assert glog.shape == log.shape
+    assert np.array_equal(glog[:, 5], log[:, 5]) and np.array_equal(glog[:, 6], log[:, 6])
+    for c in (1, 2):
+        assert np.all(np.abs(glog[:, c] - log[:, c]) <= 1e-5 * np.abs(log[:, c]))
+    assert np.all(np.abs(glog[:, 4] - log[:, 4]) <= 1e-5 * gref)
+    assert rep["status"] == st
+
+
 def test_solve_cfg1_converged():
     """Free runs (each side takes its own decisions) of the closed-form 64^3
     problem to convergence (12 GN steps, <= 10 PCG each): final velocity and
