@@ -76,6 +76,7 @@ def main():
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the 16-bit storage matvec measurement")
     ap.add_argument("--cpu-matvecs", type=int, default=3, help="oracle matvecs timed for the CPU baseline")
+    ap.add_argument("--no-search", action="store_true", help="skip the parameter search leg")
     ap.add_argument("--beta-w", type=float, default=1e-5,
                     help="divergence weight of the near-incompressible leg (0 disables the leg)")
     ap.add_argument("--max-pcg", type=int, default=40, help="PCG iterations per GN step in the solve legs")
@@ -275,6 +276,31 @@ def main():
         log("near-incompressible: %s" % json.dumps(incompressible))
         del ri, vsol, gi, vti
 
+    # parameter search (beta_v decades and bisection, then beta_w decades)
+    # under the Jacobian bounds [0.25, 4], from v = 0
+    search = None
+    if not args.no_search and not args.no_solve:
+        rq = Registration(shape, nt=4, gtol=1e-2, max_outer=50, max_pcg=args.max_pcg)
+        rq.set_images(m0, m1)
+        torch.cuda.synchronize()
+        tq = time.perf_counter()
+        srep = rq.param_search(jmin=0.25)
+        torch.cuda.synchronize()
+        tq = time.perf_counter() - tq
+        from paper_2209_08189_amd.metrics import dice, warp_labels
+        lab1 = warp_labels(labels, dev(v_true))
+        mis0 = 0.5 * float(((m0 - m1).double() ** 2).sum()) * (2 * np.pi / n) ** 3
+        slog = rq.search_log()
+        search = {"jmin_bound": 0.25, "wall_s": tq, "beta_v": srep["beta_v"], "beta_w": srep["beta_w"],
+                  "status": srep["status_name"], "solves": srep["solves"], "gn_total": srep["gn_total"],
+                  "pcg_total": srep["pcg_total"], "J_range": [srep["jmin"], srep["jmax"]],
+                  "r": [row[8] / mis0 for row in slog if row[4] == 1][-1],
+                  "dice_post": dice(warp_labels(labels, rq.velocity()), lab1),
+                  "trials": [{"beta_v": row[0], "beta_w": row[1], "J": [row[2], row[3]], "valid": bool(row[4]),
+                              "gn": int(row[5]), "pcg": int(row[6]), "r": row[8] / mis0} for row in slog]}
+        log("parameter search: %s" % json.dumps({k: v for k, v in search.items() if k != "trials"}))
+        del rq
+
     learned = None
     if args.learned_train > 0 and not args.no_solve:
         try:
@@ -365,6 +391,7 @@ def main():
         "kernels": per_class,
         "mixed_storage_matvec": mixed,
         "near_incompressible": incompressible,
+        "parameter_search": search,
         "solve_fp32": solve,
         "learned_warm_start": learned,
         "cpu_baseline": cpu,

@@ -210,6 +210,7 @@ typedef struct {
     double beta_w_min;        /* lowest beta_w tried (default 1e-7) */
     double rel_change;        /* bisection stop: relative change of beta_v (default 0.1) */
     int search_beta_w;        /* 1: run the beta_w stage (default 1) */
+    int verbose;              /* 1: one line per trial on stderr (default 0) */
 } cl_search_options;
 
 typedef struct {

@@ -73,6 +73,7 @@ class cl_search_options(ctypes.Structure):
         ("beta_w_min", ctypes.c_double),
         ("rel_change", ctypes.c_double),
         ("search_beta_w", ctypes.c_int),
+        ("verbose", ctypes.c_int),
     ]
 
 

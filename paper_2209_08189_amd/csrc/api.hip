@@ -634,6 +634,12 @@ struct Search {
         R.jmax = jh;
         ctx->slog.push_back({bv, bw, jl, jh, ok ? 1.0 : 0.0, (double)sr.outer_iters, (double)sr.pcg_iters_total,
                              (double)sr.status, sr.mismatch, sr.ms});
+        if (so.verbose) {
+            std::fprintf(stderr, "[claire] trial beta_v %.6g beta_w %.3g: J [%.4f, %.4f] %s, %d GN, %d PCG, %.1f s\n",
+                         bv, bw, jl, jh, so.jmin > 0.0 ? (ok ? "within bounds" : "breach") : "", sr.outer_iters,
+                         sr.pcg_iters_total, sr.ms / 1e3);
+            std::fflush(stderr);
+        }
         if (ok && so.jmin > 0.0) {
             best.resize(3 * ctx->N);
             HIPCHK(hipMemcpy(best.data(), ctx->v, best.size() * sizeof(float), hipMemcpyDeviceToHost));

@@ -29,6 +29,11 @@ def main():
     ap.add_argument("--max-outer", type=int, default=4)
     ap.add_argument("--max-pcg", type=int, default=40)
     ap.add_argument("--storage", default="f32,f16")
+    ap.add_argument("--search", type=float, default=0.0,
+                    help="J_min of a parameter search (beta_v, beta_w) run instead of the plain solve (0: off)")
+    ap.add_argument("--continuation", type=float, default=0.0,
+                    help="beta_v target of a parameter continuation (beta_w = 0) run before the capped solve "
+                         "is reported instead (0: plain solve from v = 0)")
     a = ap.parse_args()
     log = lambda m: print("[large] " + m, file=sys.stderr, flush=True)
     from . import synth
@@ -92,7 +97,42 @@ def main():
         reg.profile_enable(0xFF)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        rep = reg.solve()
+        if a.search > 0:
+            srep = reg.param_search(jmin=a.search, verbose=1)
+            slog = reg.search_log()
+            run["search"] = {"jmin_bound": a.search, "beta_v": srep["beta_v"], "beta_w": srep["beta_w"],
+                             "status": srep["status_name"], "solves": srep["solves"], "gn_total": srep["gn_total"],
+                             "pcg_total": srep["pcg_total"], "J_range": [srep["jmin"], srep["jmax"]],
+                             "trials": [{"beta_v": row[0], "beta_w": row[1], "J": [row[2], row[3]],
+                                         "valid": bool(row[4]), "gn": int(row[5]), "pcg": int(row[6]),
+                                         "status": int(row[7]), "r": row[8] / mis0, "s": row[9] / 1e3}
+                                        for row in slog]}
+            rep = reg.solve()   # report at (beta_v*, beta_w*) from the kept solution
+        elif a.continuation > 0:
+            # the continuation schedule (beta_v = 1, 0.1, ... down to
+            # 10^ceil(log10 target), then the target; beta_w = 0), one solve
+            # per call so that every stage reports as it ends
+            sched = [1.0]
+            stop = 10.0 ** np.ceil(np.log10(a.continuation))
+            while sched[-1] > stop * (1 + 1e-9):
+                sched.append(sched[-1] / 10.0)
+            if abs(sched[-1] - a.continuation) > 1e-9 * a.continuation:
+                sched.append(a.continuation)
+            trials = []
+            for bv in sched:
+                reg.set_regularization(bv, 0.0)
+                ts = time.perf_counter()
+                rep = reg.solve()
+                _, jl, jh = reg.jacobian_det()
+                trials.append({"beta_v": bv, "J": [jl, jh], "gn": rep["outer_iters"], "pcg": rep["pcg_iters_total"],
+                               "status": rep["status_name"], "r": rep["mismatch"] / mis0,
+                               "rel_grad": rep["gnorm"] / rep["gref"], "s": time.perf_counter() - ts})
+                log("%s: continuation beta_v %.3g: J [%.3f, %.3f], %d GN, %d PCG, %s, r %.4f, %.1f s"
+                    % (st, bv, jl, jh, rep["outer_iters"], rep["pcg_iters_total"], rep["status_name"],
+                       trials[-1]["r"], trials[-1]["s"]))
+            run["continuation"] = {"beta_v": a.continuation, "trials": trials}
+        else:
+            rep = reg.solve()
         torch.cuda.synchronize()
         run["solve_s"] = time.perf_counter() - t0
         kern = {}
@@ -110,6 +150,8 @@ def main():
                            "alpha": row[6]} for row in reg.solve_log()]
         run["dice_pre"] = dice(lab0, lab1)
         run["dice_post"] = dice(warp_labels(lab0, None, reg=reg), lab1)   # the solved velocity
+        _, jl, jh = reg.jacobian_det()
+        run["J_range"] = [jl, jh]
         log("%s: %s" % (st, json.dumps({k: x for k, x in run.items() if k not in ("kernels",)})))
         out["runs"][st] = run
         reg.close()
