@@ -64,6 +64,7 @@ def lib():
             "orc_matvec_sym": (None, [vp, _dp, _dp]),
             "orc_jacobian_det": (None, [vp, _dp]),
             "orc_set_beta": (None, [vp, d, d]),
+            "orc_set_precond": (None, [vp, i, i]),
             "orc_param_search": (i, [vp, d, d, d, d, d, d, i, i, i, d, _dp, i, _ip, _dp, _dp]),
             "orc_param_continuation": (i, [vp, d, d, d, d, i, i, d, _dp, i, _ip]),
             "orc_feet": (None, [i, i, i, i, _dp, _dp, _dp]),
@@ -283,6 +284,11 @@ class Oracle:
         J = np.empty(self.shape)
         lib().orc_jacobian_det(self._h, _p(J))
         return J
+
+    def set_precond(self, kind, inner=5):
+        """kind 0: spectral L^-1; 1: zero-velocity Hessian H0 by `inner` CG
+        steps (the outer PCG is then flexible)."""
+        lib().orc_set_precond(self._h, int(kind), int(inner))
 
     def set_beta(self, beta_v, beta_w=0.0):
         self.beta, self.beta_w = float(beta_v), float(beta_w)

@@ -168,9 +168,17 @@ static void fft_line(double *re, double *im, int L, int sign)
     }
 }
 
-/* In-place unscaled 3D DFT of a complex array (re, im) with sign +-1. */
+/* In-place unscaled 3D DFT of a complex array (re, im) with sign +-1.
+ * Every extent must be a power of two (radix-2 lines); anything else stops
+ * the process with a message rather than running past the line buffers.  */
 void orc_fft3(int n1, int n2, int n3, double *re, double *im, int sign)
 {
+    int dims_chk[3] = {n1, n2, n3};
+    for (int a = 0; a < 3; ++a)
+        if (dims_chk[a] < 1 || (dims_chk[a] & (dims_chk[a] - 1)) != 0) {
+            fprintf(stderr, "orc_fft3: extent %d is not a power of two\n", dims_chk[a]);
+            abort();
+        }
     int dims[3] = {n1, n2, n3};
     long strides[3] = {(long)n2 * n3, n3, 1};
     long N = (long)n1 * n2 * n3;
@@ -458,6 +466,8 @@ typedef struct orc_ctx {
     double *mt, *lamt;      /* incremental state and adjoint of the last matvec */
     double *work3a, *work3b;
     double beta_w;          /* divergence regularisation (0: K = I) */
+    int precond;            /* 0: spectral L^-1; 1: zero-velocity Hessian H0 */
+    int precond_inner;      /* inner CG iterations of the H0 preconditioner */
     int have_feet, have_state;
 } orc_ctx;
 
@@ -689,14 +699,78 @@ void orc_matvec_sym(orc_ctx *o, const double *vt, double *Hvt)
     free(b);
 }
 
-/* Preconditioner: (beta A)^-1 with the k = 0 mode mapped to 1/beta; with
- * beta_w > 0 the inverse of L (same k = 0 rule).                        */
-void orc_precond(orc_ctx *o, const double *r, double *z)
+/* Spectral preconditioner: (beta A)^-1 with the k = 0 mode mapped to
+ * 1/beta; with beta_w > 0 the inverse of L (same k = 0 rule).           */
+static void precond_spectral(orc_ctx *o, const double *r, double *z)
 {
     if (o->beta_w == 0.0)
         orc_spectral(o->n1, o->n2, o->n3, r, z, 3, 1, o->beta);
     else
         orc_reg_op(o->n1, o->n2, o->n3, r, z, 1, o->beta, o->beta_w);
+}
+
+/* L x: beta A x, with beta_w > 0 the coupled operator */
+static void reg_apply(orc_ctx *o, const double *x, double *y)
+{
+    if (o->beta_w == 0.0)
+        orc_spectral(o->n1, o->n2, o->n3, x, y, 3, 0, o->beta);
+    else
+        orc_reg_op(o->n1, o->n2, o->n3, x, y, 0, o->beta, o->beta_w);
+}
+
+/* Zero-velocity Hessian preconditioner (Section 2.2 names the zero
+ * velocity approximation of H as a preconditioner; its construction is in
+ * a cited paper that is not at hand).  Reading: at v = 0 the state is m0
+ * for all t, the incremental state is -t vt.grad m0 and the incremental
+ * adjoint is constant, so the Gauss-Newton Hessian of J is
+ *   H0 vt = L vt + (grad_h m0 . vt) grad_h m0,
+ * a pointwise rank-one data term.  z ~ H0^-1 r by precond_inner steps of
+ * CG from z = 0, preconditioned by the spectral L^-1.                    */
+static void precond_h0(orc_ctx *o, const double *r, double *z)
+{
+    long n = 3 * o->N, N = o->N;
+    double w = o->hv;
+    double *gm = malloc(sizeof(double) * n), *ri = malloc(sizeof(double) * n), *zi = malloc(sizeof(double) * n);
+    double *p = malloc(sizeof(double) * n), *Hp = malloc(sizeof(double) * n);
+    orc_grad(o->n1, o->n2, o->n3, o->m0, gm);
+    memset(z, 0, sizeof(double) * n);
+    memcpy(ri, r, sizeof(double) * n);
+    precond_spectral(o, ri, zi);
+    memcpy(p, zi, sizeof(double) * n);
+    double rz = dot(ri, zi, n, w);
+    for (int it = 0; it < o->precond_inner && rz > 0.0; ++it) {
+        reg_apply(o, p, Hp);
+        for (long q = 0; q < N; ++q) {
+            double gp = gm[q] * p[q] + gm[N + q] * p[N + q] + gm[2 * N + q] * p[2 * N + q];
+            for (int a = 0; a < 3; ++a) Hp[a * N + q] += gp * gm[a * N + q];
+        }
+        double pHp = dot(p, Hp, n, w);
+        if (!(pHp > 0.0)) break;
+        double alpha = rz / pHp;
+        for (long q = 0; q < n; ++q) { z[q] += alpha * p[q]; ri[q] -= alpha * Hp[q]; }
+        if (it == o->precond_inner - 1) break;
+        precond_spectral(o, ri, zi);
+        double rzn = dot(ri, zi, n, w);
+        double b = rzn / rz;
+        rz = rzn;
+        for (long q = 0; q < n; ++q) p[q] = zi[q] + b * p[q];
+    }
+    free(gm); free(ri); free(zi); free(p); free(Hp);
+}
+
+void orc_set_precond(orc_ctx *o, int kind, int inner)
+{
+    o->precond = kind;
+    o->precond_inner = inner;
+}
+
+/* The solver's preconditioner: spectral, or the H0 inner solve.           */
+void orc_precond(orc_ctx *o, const double *r, double *z)
+{
+    if (o->precond == 1)
+        precond_h0(o, r, z);
+    else
+        precond_spectral(o, r, z);
 }
 
 /* Jacobian determinant J = det grad y of the map y with m(x, 1) =
@@ -755,6 +829,8 @@ void orc_get_field(orc_ctx *o, int which, int j, double *out)
  *  - Armijo: alpha = 1, halve while J(v + alpha vt) > J(v) + 1e-4 alpha
  *    <g, vt>, at most 10 trials;
  *  - g_ref = ||g(v = 0)||, stop when ||g|| <= gtol g_ref.
+ *  - with the H0 preconditioner (an inner Krylov solve, not a fixed linear
+ *    operator) PCG is flexible: beta = <r_new, z_new - z_old> / <r, z>.
  *  - beta_w > 0: g and H are the reduced gradient and Hessian, K times the
  *    L2 gradient and Hessian of J.  PCG runs on the L2-symmetric form
  *    (L + B) x = -g_l2 with the preconditioner L^-1, which is PCG on
@@ -794,9 +870,11 @@ int orc_pcg(orc_ctx *o, const double *rhs, double *x, int max_pcg, double eta, i
         double rn = sqrt(dot(r, r, n, w));
         if (forced_iters < 0 && rn <= eta * r0) break;
         if (it >= limit) break;
+        double rz_old = 0.0;
+        if (o->precond == 1) rz_old = dot(r, z, n, w);
         orc_precond(o, r, z);
         double rz_new = dot(r, z, n, w);
-        double bt = rz_new / rz;
+        double bt = (rz_new - rz_old) / rz;
         rz = rz_new;
         for (long q = 0; q < n; ++q) p[q] = z[q] + bt * p[q];
     }
