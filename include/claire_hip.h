@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define CL_OPTIONS_VERSION 1
+#define CL_OPTIONS_VERSION 2
 
 typedef struct cl_ctx cl_ctx;
 
@@ -83,7 +83,22 @@ typedef struct {
                                                 exceeds it (0: exceeds 15/16 of the free device memory), the
                                                 lean layout is used (see cl_layout); cl_create fails with
                                                 CL_ERR_OOM when a nonzero cap is below even that */
+    int precond;              /* CL_PRECOND_SPECTRAL (default) or CL_PRECOND_H0 */
+    int precond_inner;        /* inner CG iterations of CL_PRECOND_H0, 1..100 (default 5) */
 } cl_options;
+
+/* Preconditioners of the GN system (Section 2.2).
+ *   CL_PRECOND_SPECTRAL: L^-1, i.e. (beta_v A)^-1 (k = 0 -> 1/beta_v) when
+ *     beta_w = 0; one FFT pair.
+ *   CL_PRECOND_H0: the zero-velocity approximation of the Hessian.  At
+ *     v = 0 the Gauss-Newton Hessian of J is H0 vt = L vt + (grad_h m0 .
+ *     vt) grad_h m0 (state m0 at all times, incremental adjoint constant);
+ *     z ~ H0^-1 r by precond_inner steps of CG from z = 0 preconditioned
+ *     by L^-1, at full resolution.  The outer PCG is then flexible
+ *     (beta = <r_new, z_new - z_old> / <r, z>).  Needs the full memory
+ *     layout (stored grad_h m^j) and six more vector fields of workspace;
+ *     cl_create returns CL_ERR_UNSUPPORTED in the lean layout. */
+enum { CL_PRECOND_SPECTRAL = 0, CL_PRECOND_H0 = 1 };
 
 typedef struct {
     int status;               /* CL_OK (converged), CL_STATUS_MAXIT or CL_STATUS_LINESEARCH_FAIL */
@@ -145,9 +160,10 @@ int cl_gradient(cl_ctx *ctx, float *g_out, double *gnorm, double *J);
  * Enqueued only, no synchronisation. */
 int cl_hessian_matvec(cl_ctx *ctx, const float *vt, float *Hvt);
 
-/* Spectral preconditioner z = (beta_v A)^-1 r with the k = 0 mode scaled by
- * 1/beta_v; with beta_w > 0, z = L^-1 r (same k = 0 rule), i.e.
- * (beta_v A)^-1 K r.  Enqueued only. */
+/* The context's preconditioner applied to r (3 fields): the spectral
+ * z = (beta_v A)^-1 r with the k = 0 mode scaled by 1/beta_v (with beta_w >
+ * 0, z = L^-1 r, i.e. (beta_v A)^-1 K r), or the zero-velocity inner solve
+ * (CL_PRECOND_H0; needs the images).  Enqueued only. */
 int cl_precond_apply(cl_ctx *ctx, const float *r, float *z);
 
 /* Gauss-Newton-Krylov solve with Armijo line search from the current v

@@ -60,6 +60,10 @@ struct cl_ctx {
     double *qparts = nullptr;                // partials of the fused PCG reductions
     int nqparts = 1;
     double *pscal = nullptr;                 // PCG device scalars (PCG_* slots)
+    // zero-velocity preconditioner: inner CG vectors, L z of its result, the
+    // previous outer z (flexible PCG); 3N each, allocated with that option
+    float *ir = nullptr, *izi = nullptr, *ip = nullptr, *iLp = nullptr, *ih = nullptr, *ilz = nullptr,
+          *zold = nullptr;
     int nparts = 1;
     FFTPlan fft{};
 
@@ -402,7 +406,59 @@ void matvec(cl_ctx *ctx, const float *vt, float *Hvt, const float *Avt_known = n
     }
 }
 
-void precond(cl_ctx *ctx, const float *r, float *z) { spectral(ctx, 1, 3, r, z, nullptr); }
+// z ~ H0^-1 r (zero-velocity Hessian) by opt.precond_inner CG steps from
+// z = 0 with the spectral preconditioner; ctx->ilz receives L z.  L p of
+// the inner directions is carried by the recurrence L p = (r - mean r) +
+// beta L p, so the only FFT pair per step is the spectral preconditioner.
+// grad_h m0 is the stored G^0.
+void precond_h0(cl_ctx *ctx, const float *r, float *z)
+{
+    ensure_sgrad(ctx);
+    const size_t N = ctx->N, n = 3 * N;
+    double *sc = ctx->pscal + PCG_INNER;
+    const int nbc = reduce_blocks(N);
+    const float *G0 = ctx->G;
+    HIPCHK(hipMemcpyAsync(ctx->ir, r, n * sizeof(float), hipMemcpyDeviceToDevice, ctx->s));
+    run(ctx, CL_K_VEC, [&] {
+        launch_fill_f32(z, 0.0f, n, ctx->s);
+        launch_fill_f32(ctx->ilz, 0.0f, n, ctx->s);
+    });
+    spectral(ctx, 1, 3, ctx->ir, ctx->izi, nullptr);
+    HIPCHK(hipMemcpyAsync(ctx->ip, ctx->izi, n * sizeof(float), hipMemcpyDeviceToDevice, ctx->s));
+    run(ctx, CL_K_VEC, [&] {
+        launch_comp_sums3(ctx->ir, N, ctx->partials, ctx->nparts / 3, sc + PCG_SUMR, ctx->s);
+        launch_fill_f32(ctx->iLp, 0.0f, n, ctx->s);
+        launch_mean_free_axpy(ctx->iLp, ctx->ir, sc + PCG_SUMR, 0.0f, N, ctx->s);
+        launch_dot(ctx->ir, ctx->izi, n, ctx->partials, ctx->nparts, ctx->s);
+        launch_finalize(ctx->partials, ctx->nparts, ctx->hv, sc + PCG_RZ, ctx->s);
+    });
+    const int inner = ctx->opt.precond_inner;
+    for (int it = 0; it < inner; ++it) {
+        run(ctx, CL_K_VEC, [&] {
+            launch_h0_apply(ctx->ip, ctx->iLp, G0, ctx->ih, N, ctx->partials, ctx->nparts, ctx->s);
+            launch_finalize(ctx->partials, ctx->nparts, ctx->hv, sc + PCG_PHP, ctx->s);
+            launch_pcg_alpha(sc, ctx->s);
+            launch_pcg_update3(z, ctx->ir, ctx->ip, ctx->ih, sc, N, ctx->qparts, nbc, ctx->hv, ctx->s);
+            launch_axpy_sc(ctx->ilz, ctx->iLp, sc, N, ctx->s);
+        });
+        if (it == inner - 1) break;
+        spectral(ctx, 1, 3, ctx->ir, ctx->izi, nullptr);
+        run(ctx, CL_K_VEC, [&] {
+            launch_dot(ctx->ir, ctx->izi, n, ctx->partials, ctx->nparts, ctx->s);
+            launch_finalize(ctx->partials, ctx->nparts, ctx->hv, sc + PCG_RZNEW, ctx->s);
+            launch_pcg_beta(sc, ctx->s);
+            launch_pcg_direction(ctx->ip, ctx->iLp, ctx->izi, ctx->ir, sc, N, ctx->s);
+        });
+    }
+}
+
+void precond(cl_ctx *ctx, const float *r, float *z)
+{
+    if (ctx->opt.precond == CL_PRECOND_H0)
+        precond_h0(ctx, r, z);
+    else
+        spectral(ctx, 1, 3, r, z, nullptr);
+}
 
 void load_velocity(cl_ctx *ctx, const float *src_dev)
 {
@@ -430,13 +486,19 @@ int pcg(cl_ctx *ctx, int max_pcg, double eta, int forced, int *iters)
     const double r0 = std::sqrt(dotw(ctx, ctx->pr, ctx->pr, n));
     // beta A p by recurrence: p = z + b p and beta A z = r - mean(r) (A has
     // no k = 0 mode, the preconditioner maps it by 1/beta), so the matvecs
-    // inside PCG need no FFT pair of their own
+    // inside PCG need no FFT pair of their own.  With the zero-velocity
+    // preconditioner L z comes from its inner solve.
+    const bool h0 = ctx->opt.precond == CL_PRECOND_H0;
     float *pAp = ctx->tmp3;
-    run(ctx, CL_K_VEC, [&] {
-        launch_fill_f32(pAp, 0.0f, n, ctx->s);
-        launch_comp_sums3(ctx->pr, ctx->N, ctx->partials, ctx->nparts / 3, sc + PCG_SUMR, ctx->s);
-        launch_mean_free_axpy(pAp, ctx->pr, sc + PCG_SUMR, 0.0f, ctx->N, ctx->s);
-    });
+    if (h0) {
+        HIPCHK(hipMemcpyAsync(pAp, ctx->ilz, n * sizeof(float), hipMemcpyDeviceToDevice, ctx->s));
+    } else {
+        run(ctx, CL_K_VEC, [&] {
+            launch_fill_f32(pAp, 0.0f, n, ctx->s);
+            launch_comp_sums3(ctx->pr, ctx->N, ctx->partials, ctx->nparts / 3, sc + PCG_SUMR, ctx->s);
+            launch_mean_free_axpy(pAp, ctx->pr, sc + PCG_SUMR, 0.0f, ctx->N, ctx->s);
+        });
+    }
     const int limit = forced >= 0 ? forced : max_pcg;
     int it = 0, neg = 0;
     while (it < limit) {
@@ -456,6 +518,20 @@ int pcg(cl_ctx *ctx, int max_pcg, double eta, int forced, int *iters)
         ++it;
         if (forced < 0 && rn <= eta * r0) break;
         if (it >= limit) break;
+        if (h0) {
+            // flexible PCG: beta = <r, z_new - z_old> / <r_old, z_old>
+            HIPCHK(hipMemcpyAsync(ctx->zold, ctx->pz, n * sizeof(float), hipMemcpyDeviceToDevice, ctx->s));
+            precond(ctx, ctx->pr, ctx->pz);
+            run(ctx, CL_K_VEC, [&] {
+                launch_dot(ctx->pr, ctx->pz, n, ctx->partials, ctx->nparts, ctx->s);
+                launch_finalize(ctx->partials, ctx->nparts, ctx->hv, sc + PCG_RZNEW, ctx->s);
+                launch_dot(ctx->pr, ctx->zold, n, ctx->partials, ctx->nparts, ctx->s);
+                launch_finalize(ctx->partials, ctx->nparts, ctx->hv, sc + PCG_RZOLD, ctx->s);
+                launch_pcg_beta_flex(sc, ctx->s);
+                launch_pcg_direction_lz(ctx->pp, pAp, ctx->pz, ctx->ilz, sc, ctx->N, ctx->s);
+            });
+            continue;
+        }
         precond(ctx, ctx->pr, ctx->pz);
         run(ctx, CL_K_VEC, [&] {
             launch_dot(ctx->pr, ctx->pz, n, ctx->partials, ctx->nparts, ctx->s);
@@ -567,6 +643,7 @@ size_t workspace_bytes(int n1, int n2, int n3, const cl_options &o, bool lean)
     b += 3 * (N / 2048 + 1) * 8 * sizeof(int);  // tile stencil boxes
     b += 2 * N * sizeof(float);              // c, div v
     b += 12 * 3 * N * sizeof(float);         // v, vtrial, df, db, g, Av, tmp3, PCG x r z p Hp
+    if (o.precond == CL_PRECOND_H0) b += 7 * 3 * N * sizeof(float);   // inner CG, L z, previous z
     b += fft_spec_bytes(n1, n2, n3, 3);
     b += 4 * 1025 * sizeof(float2) + 4096 * sizeof(double) + 256;   // FFT tables, reduction partials, scalars
     b += (std::max<size_t>((N / 4 + 255) / 256, 6 * (size_t)reduce_blocks(N)) + PCG_NSCAL) * sizeof(double);
@@ -779,6 +856,10 @@ int check_options(const cl_options *o, cl_ctx *ctx)
     if (!(o->beta_v > 0.0) || !std::isfinite(o->beta_v)) return fail(ctx, CL_ERR_ARG, "beta_v must be > 0");
     if (!(o->beta_w >= 0.0) || !std::isfinite(o->beta_w)) return fail(ctx, CL_ERR_ARG, "beta_w must be >= 0");
     if (o->max_outer < 0 || o->max_pcg < 1) return fail(ctx, CL_ERR_ARG, "iteration limits out of range");
+    if (o->precond != CL_PRECOND_SPECTRAL && o->precond != CL_PRECOND_H0)
+        return fail(ctx, CL_ERR_ARG, "unknown preconditioner");
+    if (o->precond == CL_PRECOND_H0 && (o->precond_inner < 1 || o->precond_inner > 100))
+        return fail(ctx, CL_ERR_ARG, "precond_inner out of range [1, 100]");
     if (!(o->gtol >= 0.0)) return fail(ctx, CL_ERR_ARG, "gtol must be >= 0");
     for (int dt : {o->storage_state, o->storage_adjoint})
         if (dt != CL_F32 && dt != CL_BF16 && dt != CL_F16) return fail(ctx, CL_ERR_DTYPE, "unknown storage dtype");
@@ -827,6 +908,8 @@ void cl_default_options(cl_options *o)
     o->nt = 4;
     o->beta_v = 5e-4;
     o->beta_w = 0.0;
+    o->precond = CL_PRECOND_SPECTRAL;
+    o->precond_inner = 5;
     o->gtol = 1e-2;
     o->max_outer = 50;
     o->max_pcg = 10;
@@ -866,6 +949,7 @@ int cl_create(cl_ctx **out, int n1, int n2, int n3, const cl_options *opt)
         if (hipMemGetInfo(&fr, &tot) == hipSuccess) limit = fr - fr / 16;
     }
     const bool lean = limit && full > limit;
+    if (lean && opt->precond == CL_PRECOND_H0) return CL_ERR_UNSUPPORTED;
     if (lean && opt->workspace_cap_bytes && workspace_bytes(n1, n2, n3, *opt, true) > opt->workspace_cap_bytes)
         return CL_ERR_OOM;
     cl_ctx *ctx = new (std::nothrow) cl_ctx();
@@ -911,6 +995,10 @@ int cl_create(cl_ctx **out, int n1, int n2, int n3, const cl_options *opt)
         float **vecs[] = {&ctx->v, &ctx->vtrial, &ctx->df, &ctx->db, &ctx->grad, &ctx->Av, &ctx->tmp3,
                           &ctx->px, &ctx->pr, &ctx->pz, &ctx->pp, &ctx->pHp};
         for (float **pv : vecs) *pv = (float *)alloc(3 * N * sizeof(float));
+        if (opt->precond == CL_PRECOND_H0) {
+            float **hv[] = {&ctx->ir, &ctx->izi, &ctx->ip, &ctx->iLp, &ctx->ih, &ctx->ilz, &ctx->zold};
+            for (float **pv : hv) *pv = (float *)alloc(3 * N * sizeof(float));
+        }
         // the feet are computed outside PCG, where z is free
         ctx->fscr = ctx->pz;
         ctx->c = (float *)alloc(N * sizeof(float));
@@ -1056,6 +1144,8 @@ int cl_precond_apply(cl_ctx *ctx, const float *r, float *z)
     if (!r || !z) return fail(ctx, CL_ERR_ARG, "NULL vector pointer");
     const size_t b = 3 * ctx->N * sizeof(float);
     if (overlap(r, b, z, b)) return fail(ctx, CL_ERR_ALIAS, "r and z overlap");
+    if (ctx->opt.precond == CL_PRECOND_H0 && !ctx->images)
+        return fail(ctx, CL_ERR_STATE, "the zero-velocity preconditioner needs the images");
     API_BEGIN
     precond(ctx, r, z);
     return CL_OK;

@@ -173,8 +173,21 @@ void launch_finalize(const double *partials, int nblocks, double scale, double *
 void launch_count_nonfinite(const float *a, size_t n, double *partials, int nblocks, hipStream_t s);
 // x += alpha p; r -= alpha Hp; partials of r.r
 // Fused PCG: FP64 device scalars sc[PCG_*]
+// (PCG_INNER: a second block with the same slots for the inner solve of the
+// zero-velocity preconditioner)
 enum { PCG_RR = 0, PCG_SUMR = 1, PCG_PHP = 4, PCG_RZ = 5, PCG_RZNEW = 6, PCG_ALPHA = 7, PCG_BETA = 8, PCG_NEG = 9,
-       PCG_NSCAL = 16 };
+       PCG_RZOLD = 10, PCG_INNER = 16, PCG_NSCAL = 32 };
+// flexible beta = (rz_new - rz_old) / rz, then rz = rz_new
+void launch_pcg_beta_flex(double *sc, hipStream_t s);
+// p = z + beta p, q = Lz + beta q (3 n values)
+void launch_pcg_direction_lz(float *p, float *q, const float *z, const float *Lz, const double *sc, size_t n,
+                             hipStream_t s);
+// y += sc[PCG_ALPHA] x over 3 n values
+void launch_axpy_sc(float *y, const float *x, const double *sc, size_t n, hipStream_t s);
+// out = Lp + (G . p) G per node (3 components n apart), per-block partials
+// of p . out in partials[0 .. nblocks)
+void launch_h0_apply(const float *p, const float *Lp, const float *G, float *out, size_t n, double *partials,
+                     int nblocks, hipStream_t s);
 void launch_pcg_alpha(double *sc, hipStream_t s);
 void launch_pcg_beta(double *sc, hipStream_t s);
 // x += alpha p, r -= alpha Hp (nothing when alpha = 0); sc[PCG_RR] = rscale

@@ -194,6 +194,53 @@ __global__ __launch_bounds__(TPB) void k_pcg_update3(float *__restrict__ x, floa
     if (threadIdx.x == 0) partials[(3 + c) * nb + blockIdx.x] = a1;
 }
 
+__global__ void k_pcg_beta_flex(double *sc)
+{
+    sc[PCG_BETA] = (sc[PCG_RZNEW] - sc[PCG_RZOLD]) / sc[PCG_RZ];
+    sc[PCG_RZ] = sc[PCG_RZNEW];
+}
+
+__global__ __launch_bounds__(TPB) void k_pcg_direction_lz(float *__restrict__ p, float *__restrict__ q,
+                                                          const float *__restrict__ z, const float *__restrict__ Lz,
+                                                          const double *__restrict__ sc, size_t n3)
+{
+    const float beta = (float)sc[PCG_BETA];
+    const size_t stride = (size_t)gridDim.x * TPB;
+    for (size_t e = (size_t)blockIdx.x * TPB + threadIdx.x; e < n3; e += stride) {
+        p[e] = fmaf(beta, p[e], z[e]);
+        q[e] = Lz[e] + beta * q[e];
+    }
+}
+
+__global__ __launch_bounds__(TPB) void k_axpy_sc(float *__restrict__ y, const float *__restrict__ x,
+                                                 const double *__restrict__ sc, size_t n3)
+{
+    const float alpha = (float)sc[PCG_ALPHA];
+    const size_t stride = (size_t)gridDim.x * TPB;
+    for (size_t e = (size_t)blockIdx.x * TPB + threadIdx.x; e < n3; e += stride) y[e] = fmaf(alpha, x[e], y[e]);
+}
+
+// Zero-velocity Hessian: out = Lp + (G . p) G, and p . out per block
+__global__ __launch_bounds__(TPB) void k_h0_apply(const float *__restrict__ p, const float *__restrict__ Lp,
+                                                  const float *__restrict__ G, float *__restrict__ out, size_t n,
+                                                  double *__restrict__ partials)
+{
+    double acc = 0.0;
+    const size_t stride = (size_t)gridDim.x * TPB;
+    for (size_t q = (size_t)blockIdx.x * TPB + threadIdx.x; q < n; q += stride) {
+        const float g0 = G[q], g1 = G[n + q], g2 = G[2 * n + q];
+        const float p0 = p[q], p1 = p[n + q], p2 = p[2 * n + q];
+        const float gp = g0 * p0 + g1 * p1 + g2 * p2;
+        const float o0 = fmaf(gp, g0, Lp[q]), o1 = fmaf(gp, g1, Lp[n + q]), o2 = fmaf(gp, g2, Lp[2 * n + q]);
+        out[q] = o0;
+        out[n + q] = o1;
+        out[2 * n + q] = o2;
+        acc += (double)p0 * o0 + (double)p1 * o1 + (double)p2 * o2;
+    }
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) partials[blockIdx.x] = acc;
+}
+
 // p = z + beta p and q = (r - mean r) + beta q on every component (q is
 // beta A p carried by recurrence; means from the component sums in sc)
 __global__ __launch_bounds__(TPB) void k_pcg_direction(float *__restrict__ p, float *__restrict__ q,
@@ -320,6 +367,28 @@ void launch_pcg_update3(float *x, float *r, const float *p, const float *Hp, dou
     // ||r||^2 over the three components in order, then the component sums
     launch_finalize(partials, 3 * nblocks, rscale, sc + PCG_RR, s);
     for (int c = 0; c < 3; ++c) launch_finalize(partials + (3 + c) * nblocks, nblocks, 1.0, sc + PCG_SUMR + c, s);
+}
+
+void launch_pcg_beta_flex(double *sc, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pcg_beta_flex, dim3(1), dim3(1), 0, s, sc);
+}
+
+void launch_pcg_direction_lz(float *p, float *q, const float *z, const float *Lz, const double *sc, size_t n,
+                             hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pcg_direction_lz, stream_grid(3 * n), dim3(TPB), 0, s, p, q, z, Lz, sc, 3 * n);
+}
+
+void launch_axpy_sc(float *y, const float *x, const double *sc, size_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_axpy_sc, stream_grid(3 * n), dim3(TPB), 0, s, y, x, sc, 3 * n);
+}
+
+void launch_h0_apply(const float *p, const float *Lp, const float *G, float *out, size_t n, double *partials,
+                     int nblocks, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_h0_apply, dim3(nblocks), dim3(TPB), 0, s, p, Lp, G, out, n, partials);
 }
 
 void launch_pcg_direction(float *p, float *q, const float *z, const float *r, const double *sc, size_t n,
