@@ -77,6 +77,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the 16-bit storage matvec measurement")
     ap.add_argument("--cpu-matvecs", type=int, default=3, help="oracle matvecs timed for the CPU baseline")
     ap.add_argument("--no-search", action="store_true", help="skip the parameter search leg")
+    ap.add_argument("--h0-inner", type=int, default=12,
+                    help="inner CG steps of the zero-velocity preconditioner leg (0 disables the leg)")
     ap.add_argument("--beta-w", type=float, default=1e-5,
                     help="divergence weight of the near-incompressible leg (0 disables the leg)")
     ap.add_argument("--max-pcg", type=int, default=40, help="PCG iterations per GN step in the solve legs")
@@ -228,6 +230,28 @@ def main():
         solve["div_ratio"] = float(rs.fd_div(vsol).norm() / vsol.norm())
         log("solve: %s" % json.dumps(solve))
         del rs, vsol
+
+    # the same solve with the zero-velocity Hessian preconditioner (inner CG
+    # on L + grad m0 grad m0^T, flexible outer PCG)
+    h0 = None
+    if args.h0_inner > 0 and not args.no_solve:
+        rh = Registration(shape, nt=4, beta_v=5e-4, gtol=1e-2, max_outer=50, max_pcg=args.max_pcg, precond="h0",
+                          precond_inner=args.h0_inner)
+        rh.set_images(m0, m1)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        rep = rh.solve()
+        torch.cuda.synchronize()
+        te = time.perf_counter()
+        mis0 = 0.5 * float(((m0 - m1).double() ** 2).sum()) * (2 * np.pi / n) ** 3
+        h0 = {"precond_inner": args.h0_inner, "status": rep["status_name"], "time_to_tol_s": te - ts,
+              "outer_iters": rep["outer_iters"], "pcg_iters": rep["pcg_iters_total"],
+              "rel_grad": rep["gnorm"] / rep["gref"], "r": rep["mismatch"] / mis0}
+        if solve:
+            h0["abs_diff_r_vs_spectral"] = abs(h0["r"] - solve["r"])
+            h0["speedup_vs_spectral"] = solve["time_to_tol_s"] / h0["time_to_tol_s"]
+        log("zero-velocity preconditioner: %s" % json.dumps(h0))
+        del rh
 
     # near-incompressible formulation (beta_w > 0, K != I): the reduced
     # Hessian matvec beta_v A vt + K b~ and the solve on the same pair
@@ -392,6 +416,7 @@ def main():
         "mixed_storage_matvec": mixed,
         "near_incompressible": incompressible,
         "parameter_search": search,
+        "solve_fp32_h0_precond": h0,
         "solve_fp32": solve,
         "learned_warm_start": learned,
         "cpu_baseline": cpu,
