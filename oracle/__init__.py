@@ -64,6 +64,10 @@ def lib():
             "orc_matvec_sym": (None, [vp, _dp, _dp]),
             "orc_jacobian_det": (None, [vp, _dp]),
             "orc_set_beta": (None, [vp, d, d]),
+            "orc_set_interp": (None, [vp, i]),
+            "orc_interp_order": (None, [i, i, i, i, _dp, _dp, _dp]),
+            "orc_interp_point_lin": (d, [i, i, i, _dp, d, d, d]),
+            "orc_feet_order": (None, [i, i, i, i, i, _dp, _dp, _dp]),
             "orc_set_precond": (None, [vp, i, i]),
             "orc_param_search": (i, [vp, d, d, d, d, d, d, i, i, i, d, _dp, i, _ip, _dp, _dp]),
             "orc_param_continuation": (i, [vp, d, d, d, d, i, i, d, _dp, i, _ip]),
@@ -120,6 +124,19 @@ def interp(u, d):
     out = np.empty_like(u)
     lib().orc_interp(*u.shape, _p(u), _p(d), _p(out))
     return out
+
+
+def interp_linear(u, d):
+    """I[u](x + d) with trilinear interpolation (d in index units)."""
+    u = _f64(u); d = _f64(d)
+    out = np.empty_like(u)
+    lib().orc_interp_order(*u.shape, 1, _p(u), _p(d), _p(out))
+    return out
+
+
+def interp_point_linear(u, p):
+    u = _f64(u)
+    return lib().orc_interp_point_lin(*u.shape, _p(u), float(p[0]), float(p[1]), float(p[2]))
 
 
 def interp_point(u, p):
@@ -219,13 +236,15 @@ FIELD_FEET_F, FIELD_FEET_B, FIELD_ADJ_FACTOR = 4, 5, 6
 class Oracle:
     """Registration problem on an n1 x n2 x n3 periodic grid over [0, 2pi)^3."""
 
-    def __init__(self, shape, nt=4, beta=5e-4, beta_w=0.0):
+    def __init__(self, shape, nt=4, beta=5e-4, beta_w=0.0, interp=3):
+        """interp: 3 tricubic Lagrange (default), 1 trilinear."""
         self.shape = tuple(int(s) for s in shape)
         self.nt = int(nt)
         self.beta = float(beta)
         self.beta_w = float(beta_w)
         self._h = lib().orc_create(*self.shape, self.nt, self.beta)
         lib().orc_set_beta_w(self._h, self.beta_w)
+        lib().orc_set_interp(self._h, int(interp))
 
     def __del__(self):
         h = getattr(self, "_h", None)

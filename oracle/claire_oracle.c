@@ -73,8 +73,34 @@ static double interp_node(int n1, int n2, int n3, const double *u,
     return s;
 }
 
-/* out(x_ijk) = I[u](x_ijk + d_ijk), d in index units (3 arrays). */
-void orc_interp(int n1, int n2, int n3, const double *u, const double *d, double *out)
+/* Trilinear value (the paper's linear interpolation option, Section 2.3
+ * and Section 3): nodes base and base + 1 per axis with weights 1 - f and
+ * f, base = node + floor(d), f = d - floor(d).                            */
+static double interp_node_lin(int n1, int n2, int n3, const double *u,
+                              long i, long j, long k, double d1, double d2, double d3)
+{
+    double f1 = floor(d1), f2 = floor(d2), f3 = floor(d3);
+    long b1 = i + (long)f1, b2 = j + (long)f2, b3 = k + (long)f3;
+    double w1[2] = {1.0 - (d1 - f1), d1 - f1}, w2[2] = {1.0 - (d2 - f2), d2 - f2}, w3[2] = {1.0 - (d3 - f3), d3 - f3};
+    double s = 0.0;
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            for (int c = 0; c < 2; ++c)
+                s += w1[a] * w2[b] * w3[c] * u[at(n1, n2, n3, b1 + a, b2 + b, b3 + c)];
+    return s;
+}
+
+/* order 1: trilinear, otherwise tricubic Lagrange */
+static double interp_node_ord(int order, int n1, int n2, int n3, const double *u,
+                              long i, long j, long k, double d1, double d2, double d3)
+{
+    return order == 1 ? interp_node_lin(n1, n2, n3, u, i, j, k, d1, d2, d3)
+                      : interp_node(n1, n2, n3, u, i, j, k, d1, d2, d3);
+}
+
+/* out(x_ijk) = I[u](x_ijk + d_ijk), d in index units (3 arrays), with the
+ * interpolation of the given order (1 trilinear, 3 tricubic Lagrange). */
+void orc_interp_order(int n1, int n2, int n3, int order, const double *u, const double *d, double *out)
 {
     long N = (long)n1 * n2 * n3;
 #pragma omp parallel for schedule(static)
@@ -82,14 +108,25 @@ void orc_interp(int n1, int n2, int n3, const double *u, const double *d, double
         for (long j = 0; j < n2; ++j)
             for (long k = 0; k < n3; ++k) {
                 long p = (i * n2 + j) * n3 + k;
-                out[p] = interp_node(n1, n2, n3, u, i, j, k, d[p], d[N + p], d[2 * N + p]);
+                out[p] = interp_node_ord(order, n1, n2, n3, u, i, j, k, d[p], d[N + p], d[2 * N + p]);
             }
+}
+
+/* out(x_ijk) = I[u](x_ijk + d_ijk), tricubic Lagrange. */
+void orc_interp(int n1, int n2, int n3, const double *u, const double *d, double *out)
+{
+    orc_interp_order(n1, n2, n3, 3, u, d, out);
 }
 
 /* Value of I[u] at an arbitrary point p (index units, any real). */
 double orc_interp_point(int n1, int n2, int n3, const double *u, double p1, double p2, double p3)
 {
     return interp_node(n1, n2, n3, u, 0, 0, 0, p1, p2, p3);
+}
+
+double orc_interp_point_lin(int n1, int n2, int n3, const double *u, double p1, double p2, double p3)
+{
+    return interp_node_lin(n1, n2, n3, u, 0, 0, 0, p1, p2, p3);
 }
 
 /* ------------------------------------------------ 8th-order central FD
@@ -415,7 +452,7 @@ void orc_spectral_resample(int a1, int a2, int a3, const double *in, int b1, int
  *   forward (state):    X_f = x - dt/2 [v(x) + v(x - dt v(x))]
  *   backward (adjoint): X_b = x + dt/2 [v(x) + v(x + dt v(x))]
  * Stored as displacements from the node in index units.                  */
-void orc_feet(int n1, int n2, int n3, int nt, const double *v, double *df, double *db)
+void orc_feet_order(int n1, int n2, int n3, int nt, int order, const double *v, double *df, double *db)
 {
     long N = (long)n1 * n2 * n3;
     double dt = 1.0 / nt;
@@ -431,27 +468,38 @@ void orc_feet(int n1, int n2, int n3, int nt, const double *v, double *df, doubl
                     pb[a] = dt * v[a * N + p] / h[a];
                 }
                 for (int a = 0; a < 3; ++a) {
-                    double vf = interp_node(n1, n2, n3, v + a * N, i, j, k, pf[0], pf[1], pf[2]);
-                    double vb = interp_node(n1, n2, n3, v + a * N, i, j, k, pb[0], pb[1], pb[2]);
+                    double vf = interp_node_ord(order, n1, n2, n3, v + a * N, i, j, k, pf[0], pf[1], pf[2]);
+                    double vb = interp_node_ord(order, n1, n2, n3, v + a * N, i, j, k, pb[0], pb[1], pb[2]);
                     df[a * N + p] = -0.5 * dt * (v[a * N + p] + vf) / h[a];
                     db[a * N + p] = 0.5 * dt * (v[a * N + p] + vb) / h[a];
                 }
             }
 }
 
+void orc_feet(int n1, int n2, int n3, int nt, const double *v, double *df, double *db)
+{
+    orc_feet_order(n1, n2, n3, nt, 3, v, df, db);
+}
+
 /* Adjoint transport -d_t lambda - div(lambda v) = 0 (eq. of the adjoint)
  * written along the backward characteristic: d lambda / d tau = lambda *
  * div v.  Heun along that path gives lambda^j = c * lambda^{j+1}(X_b) with
  *   c = 1 + dt/2 (dbar + d + dt dbar d),  d = div_h v,  dbar = d(X_b).   */
-void orc_adjoint_factor(int n1, int n2, int n3, int nt, const double *v, const double *db, double *c)
+void orc_adjoint_factor_order(int n1, int n2, int n3, int nt, int order, const double *v, const double *db,
+                              double *c)
 {
     long N = (long)n1 * n2 * n3;
     double dt = 1.0 / nt;
     double *d = malloc(sizeof(double) * N), *dbar = malloc(sizeof(double) * N);
     orc_div(n1, n2, n3, v, d);
-    orc_interp(n1, n2, n3, d, db, dbar);
+    orc_interp_order(n1, n2, n3, order, d, db, dbar);
     for (long p = 0; p < N; ++p) c[p] = 1.0 + 0.5 * dt * (dbar[p] + d[p] + dt * dbar[p] * d[p]);
     free(d); free(dbar);
+}
+
+void orc_adjoint_factor(int n1, int n2, int n3, int nt, const double *v, const double *db, double *c)
+{
+    orc_adjoint_factor_order(n1, n2, n3, nt, 3, v, db, c);
 }
 
 /* ------------------------------------------------------------ context */
@@ -466,6 +514,7 @@ typedef struct orc_ctx {
     double *mt, *lamt;      /* incremental state and adjoint of the last matvec */
     double *work3a, *work3b;
     double beta_w;          /* divergence regularisation (0: K = I) */
+    int interp;             /* interpolation order: 3 tricubic (default), 1 trilinear */
     int precond;            /* 0: spectral L^-1; 1: zero-velocity Hessian H0 */
     int precond_inner;      /* inner CG iterations of the H0 preconditioner */
     int have_feet, have_state;
@@ -475,6 +524,7 @@ orc_ctx *orc_create(int n1, int n2, int n3, int nt, double beta)
 {
     orc_ctx *o = calloc(1, sizeof(orc_ctx));
     o->n1 = n1; o->n2 = n2; o->n3 = n3; o->nt = nt; o->beta = beta;
+    o->interp = 3;
     o->N = (long)n1 * n2 * n3;
     o->hv = (TWO_PI / n1) * (TWO_PI / n2) * (TWO_PI / n3);
     long N = o->N;
@@ -489,6 +539,21 @@ orc_ctx *orc_create(int n1, int n2, int n3, int nt, double beta)
 }
 
 void orc_set_beta_w(orc_ctx *o, double beta_w) { o->beta_w = beta_w; }
+
+/* Interpolation order of every SL step of the context (3 tricubic, 1
+ * trilinear); the feet of the current velocity are recomputed.            */
+void orc_set_velocity(orc_ctx *o, const double *v);
+
+void orc_set_interp(orc_ctx *o, int order)
+{
+    o->interp = order == 1 ? 1 : 3;
+    if (o->have_feet) {
+        double *v = malloc(sizeof(double) * 3 * o->N);
+        memcpy(v, o->v, sizeof(double) * 3 * o->N);
+        orc_set_velocity(o, v);
+        free(v);
+    }
+}
 
 void orc_destroy(orc_ctx *o)
 {
@@ -515,8 +580,8 @@ void orc_set_images(orc_ctx *o, const double *m0, const double *m1)
 void orc_set_velocity(orc_ctx *o, const double *v)
 {
     memcpy(o->v, v, sizeof(double) * 3 * o->N);
-    orc_feet(o->n1, o->n2, o->n3, o->nt, o->v, o->df, o->db);
-    orc_adjoint_factor(o->n1, o->n2, o->n3, o->nt, o->v, o->db, o->c);
+    orc_feet_order(o->n1, o->n2, o->n3, o->nt, o->interp, o->v, o->df, o->db);
+    orc_adjoint_factor_order(o->n1, o->n2, o->n3, o->nt, o->interp, o->v, o->db, o->c);
     o->have_feet = 1;
     o->have_state = 0;
 }
@@ -528,7 +593,7 @@ void orc_state(orc_ctx *o)
     long N = o->N;
     memcpy(o->m, o->m0, sizeof(double) * N);
     for (int j = 0; j < o->nt; ++j)
-        orc_interp(o->n1, o->n2, o->n3, o->m + j * N, o->df, o->m + (j + 1) * N);
+        orc_interp_order(o->n1, o->n2, o->n3, o->interp, o->m + j * N, o->df, o->m + (j + 1) * N);
     o->have_state = 1;
 }
 
@@ -583,7 +648,7 @@ static void data_gradient(orc_ctx *o, double *b)
     double *lamN = o->lam + nt * N;
     for (long p = 0; p < N; ++p) lamN[p] = o->m1[p] - o->m[nt * N + p];
     for (int j = nt - 1; j >= 0; --j) {
-        orc_interp(o->n1, o->n2, o->n3, o->lam + (j + 1) * N, o->db, o->lam + j * N);
+        orc_interp_order(o->n1, o->n2, o->n3, o->interp, o->lam + (j + 1) * N, o->db, o->lam + j * N);
         for (long p = 0; p < N; ++p) o->lam[j * N + p] *= o->c[p];
     }
     quadrature(o, o->lam, b);
@@ -653,12 +718,12 @@ static void data_matvec(orc_ctx *o, const double *vt, double *bt)
     memset(o->mt, 0, sizeof(double) * N);
     for (int j = 0; j < nt; ++j) {
         for (long p = 0; p < N; ++p) q[p] = o->mt[j * N + p] + 0.5 * dt * s[j * N + p];
-        orc_interp(o->n1, o->n2, o->n3, q, o->df, o->mt + (j + 1) * N);
+        orc_interp_order(o->n1, o->n2, o->n3, o->interp, q, o->df, o->mt + (j + 1) * N);
         for (long p = 0; p < N; ++p) o->mt[(j + 1) * N + p] += 0.5 * dt * s[(j + 1) * N + p];
     }
     for (long p = 0; p < N; ++p) o->lamt[nt * N + p] = -o->mt[nt * N + p];
     for (int j = nt - 1; j >= 0; --j) {
-        orc_interp(o->n1, o->n2, o->n3, o->lamt + (j + 1) * N, o->db, o->lamt + j * N);
+        orc_interp_order(o->n1, o->n2, o->n3, o->interp, o->lamt + (j + 1) * N, o->db, o->lamt + j * N);
         for (long p = 0; p < N; ++p) o->lamt[j * N + p] *= o->c[p];
     }
     quadrature(o, o->lamt, bt);
@@ -788,13 +853,13 @@ void orc_jacobian_det(orc_ctx *o, double *J)
     double *d = malloc(sizeof(double) * N), *dfo = malloc(sizeof(double) * N);
     double *f = malloc(sizeof(double) * N), *cur = malloc(sizeof(double) * N);
     orc_div(o->n1, o->n2, o->n3, o->v, d);
-    orc_interp(o->n1, o->n2, o->n3, d, o->df, dfo);
+    orc_interp_order(o->n1, o->n2, o->n3, o->interp, d, o->df, dfo);
     for (long p = 0; p < N; ++p) {
         f[p] = 1.0 - 0.5 * dt * (dfo[p] + d[p] - dt * dfo[p] * d[p]);
         cur[p] = 1.0;
     }
     for (int j = 0; j < o->nt; ++j) {
-        orc_interp(o->n1, o->n2, o->n3, cur, o->df, J);
+        orc_interp_order(o->n1, o->n2, o->n3, o->interp, cur, o->df, J);
         for (long p = 0; p < N; ++p) J[p] *= f[p];
         memcpy(cur, J, sizeof(double) * N);
     }
