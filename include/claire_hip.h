@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define CL_OPTIONS_VERSION 2
+#define CL_OPTIONS_VERSION 3
 
 typedef struct cl_ctx cl_ctx;
 
@@ -85,6 +85,8 @@ typedef struct {
                                                 CL_ERR_OOM when a nonzero cap is below even that */
     int precond;              /* CL_PRECOND_SPECTRAL (default) or CL_PRECOND_H0 */
     int precond_inner;        /* inner CG iterations of CL_PRECOND_H0, 1..100 (default 5) */
+    int interp_order;         /* interpolation of every SL step: 3 tricubic Lagrange (default),
+                                 1 trilinear (the paper's choice above 256^3, Section 2.3) */
 } cl_options;
 
 /* Preconditioners of the GN system (Section 2.2).
@@ -267,7 +269,8 @@ int cl_param_continuation(cl_ctx *ctx, const cl_search_options *so, double beta_
 int cl_get_search_log(cl_ctx *ctx, double *rows, int max_rows, int *n_rows);
 
 /* Building blocks on the context's grid (parity tests of single kernels):
- *   cl_interp:   out(x) = I[u](x + d(x)), tricubic Lagrange, d in index units (3 fields)
+ *   cl_interp:   out(x) = I[u](x + d(x)) with the context's interpolation (tricubic
+ *                Lagrange, or trilinear with interp_order = 1), d in index units (3 fields)
  *   cl_fd_grad:  g = grad_h u, 8th-order central differences (3 fields out)
  *   cl_fd_div:   out = div_h v (3 fields in)
  *   cl_spectral: kind 0: beta_v A, 1: (beta_v A)^-1 (k = 0 -> 1/beta_v),

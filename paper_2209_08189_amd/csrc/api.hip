@@ -856,6 +856,7 @@ int check_options(const cl_options *o, cl_ctx *ctx)
     if (!(o->beta_v > 0.0) || !std::isfinite(o->beta_v)) return fail(ctx, CL_ERR_ARG, "beta_v must be > 0");
     if (!(o->beta_w >= 0.0) || !std::isfinite(o->beta_w)) return fail(ctx, CL_ERR_ARG, "beta_w must be >= 0");
     if (o->max_outer < 0 || o->max_pcg < 1) return fail(ctx, CL_ERR_ARG, "iteration limits out of range");
+    if (o->interp_order != 1 && o->interp_order != 3) return fail(ctx, CL_ERR_ARG, "interp_order must be 1 or 3");
     if (o->precond != CL_PRECOND_SPECTRAL && o->precond != CL_PRECOND_H0)
         return fail(ctx, CL_ERR_ARG, "unknown preconditioner");
     if (o->precond == CL_PRECOND_H0 && (o->precond_inner < 1 || o->precond_inner > 100))
@@ -910,6 +911,7 @@ void cl_default_options(cl_options *o)
     o->beta_w = 0.0;
     o->precond = CL_PRECOND_SPECTRAL;
     o->precond_inner = 5;
+    o->interp_order = 3;
     o->gtol = 1e-2;
     o->max_outer = 50;
     o->max_pcg = 10;
@@ -967,6 +969,7 @@ int cl_create(cl_ctx **out, int n1, int n2, int n3, const cl_options *opt)
     g.N = n1 * n2 * n3;
     g.ih1 = (float)(n1 / TWO_PI); g.ih2 = (float)(n2 / TWO_PI); g.ih3 = (float)(n3 / TWO_PI);
     g.h1 = (float)(TWO_PI / n1); g.h2 = (float)(TWO_PI / n2); g.h3 = (float)(TWO_PI / n3);
+    g.interp = opt->interp_order;
     ctx->N = (size_t)g.N;
     ctx->hv = (TWO_PI / n1) * (TWO_PI / n2) * (TWO_PI / n3);
     const size_t N = ctx->N;

@@ -19,6 +19,7 @@ struct Grid {
     int N;                // n1 * n2 * n3 (<= 2^30)
     float ih1, ih2, ih3;  // 1 / h_d = n_d / (2 pi)
     float h1, h2, h3;     // h_d = 2 pi / n_d
+    int interp;           // interpolation order of every SL step: 3 tricubic, 1 trilinear
 };
 
 // ------------------------------------------------------------ storage I/O

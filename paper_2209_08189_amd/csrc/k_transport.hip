@@ -202,6 +202,38 @@ __global__ __launch_bounds__(TPB) void k_sl_node(Grid g, const Tu *__restrict__ 
     stf(out + p, epilogue<MODE>(prm, e, gather(u, F)));
 }
 
+// Trilinear version (the linear interpolation option): 2 x 2 x 2 nodes from
+// base = node + floor(d) with weights (1 - f, f) per axis, one node per
+// thread; the eight values come from L2 (the feet of neighbouring threads
+// are neighbours).
+template <typename Tu, typename To, int MODE>
+__global__ __launch_bounds__(TPB) void k_sl_lin(Grid g, const Tu *__restrict__ u, const float *__restrict__ d,
+                                                SLParams prm, To *__restrict__ out)
+{
+    const int p = blockIdx.x * TPB + threadIdx.x;
+    if (p >= g.N) return;
+    int i, j, k;
+    node_of(g, p, i, j, k);
+    const float e = MODE == SL_STATE ? 0.0f : prm.e[p];
+    const float d1 = d[p], d2 = d[g.N + p], d3 = d[2 * (size_t)g.N + p];
+    const float f1 = floorf(d1), f2 = floorf(d2), f3 = floorf(d3);
+    const float a1 = d1 - f1, a2 = d2 - f2, a3 = d3 - f3;
+    const int b1 = i + (int)fminf(fmaxf(f1, -16777216.0f), 16777216.0f);
+    const int b2 = j + (int)fminf(fmaxf(f2, -16777216.0f), 16777216.0f);
+    const int b3 = k + (int)fminf(fmaxf(f3, -16777216.0f), 16777216.0f);
+    const int r0 = (b1 & (g.n1 - 1)) << (g.l2 + g.l3), r1 = ((b1 + 1) & (g.n1 - 1)) << (g.l2 + g.l3);
+    const int c0 = (b2 & (g.n2 - 1)) << g.l3, c1 = ((b2 + 1) & (g.n2 - 1)) << g.l3;
+    const int k0 = b3 & (g.n3 - 1), k1 = (b3 + 1) & (g.n3 - 1);
+    const float w30 = 1.0f - a3;
+    const float s00 = fmaf(a3, ldf(u + r0 + c0 + k1), w30 * ldf(u + r0 + c0 + k0));
+    const float s01 = fmaf(a3, ldf(u + r0 + c1 + k1), w30 * ldf(u + r0 + c1 + k0));
+    const float s10 = fmaf(a3, ldf(u + r1 + c0 + k1), w30 * ldf(u + r1 + c0 + k0));
+    const float s11 = fmaf(a3, ldf(u + r1 + c1 + k1), w30 * ldf(u + r1 + c1 + k0));
+    const float s0 = fmaf(a2, s01, (1.0f - a2) * s00);
+    const float s1 = fmaf(a2, s11, (1.0f - a2) * s10);
+    stf(out + p, epilogue<MODE>(prm, e, fmaf(a1, s1, (1.0f - a1) * s0)));
+}
+
 // Tiled version: tiles of TZ x TY x TX nodes (x1, x2, x3).  For a smooth
 // velocity the feet of a tile form a slightly deformed copy of the tile, so
 // the 4x4x4 stencils of all its feet lie in a box that is the tile plus a
@@ -606,7 +638,9 @@ template <typename Tu, typename To, int MODE>
 void launch_sl(const Grid &g, const Tu *u, const float *d, const SLParams &prm, To *out, const int *boxes,
                hipStream_t s)
 {
-    if (tiled(g)) {
+    if (g.interp == 1) {
+        hipLaunchKernelGGL((k_sl_lin<Tu, To, MODE>), grid_of(g), dim3(TPB), 0, s, g, u, d, prm, out);
+    } else if (tiled(g)) {
         const int ntx = g.n3 / TX, nty = g.n2 / TY, ntz = g.n1 / TZ;
         const int nblk = ntx * nty * ntz;
         hipLaunchKernelGGL((k_sl_tile<Tu, To, MODE>), dim3(nblk), dim3(TPB_SL), 0, s, g, u, d, prm, out, boxes, ntx,
@@ -644,7 +678,7 @@ size_t tile_box_ints(const Grid &g) { return tiled(g) ? (size_t)8 * (g.N / (TX *
 
 void launch_tile_boxes(const Grid &g, const float *d, int *boxes, hipStream_t s)
 {
-    if (!tiled(g)) return;
+    if (!tiled(g) || g.interp == 1) return;   // the trilinear steps gather per node
     const int ntx = g.n3 / TX, nty = g.n2 / TY, ntz = g.n1 / TZ;
     hipLaunchKernelGGL(k_tile_boxes, dim3(ntx * nty * ntz), dim3(TPB), 0, s, g, d, ntx, nty, boxes);
 }
