@@ -253,3 +253,73 @@ def noise32(shape, seed, sigma):
     """N(0, sigma^2) noise in FP32 (large grids)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     return (rng.standard_normal(tuple(int(s) for s in shape), dtype=np.float32) * np.float32(sigma))
+
+
+# ------------------------------------------------------------------ SYN
+# The paper's synthetic resolution study (Section 4, SYN): a template made
+# of ten star-shaped solids whose radius is a spherical harmonic, and a
+# closed-form velocity of frequency K.  Readings: image coordinates are the
+# node coordinates shifted to (-pi, pi]; |Y_l^m| does not depend on the
+# azimuth, so the radius is |Re Y_l^m| = N_lm |cos(m (phi + phi_i))|
+# |P_l^m(cos(theta + theta_i))| with the physics convention (theta polar,
+# phi azimuth); labels are the integer intensities 0..10 (overlaps add).
+
+def syn_coords(shape):
+    """Image coordinates in (-pi, pi] per axis (node coordinate - pi)."""
+    return [(TWO_PI * np.arange(n) / n - np.pi) for n in shape]
+
+
+def syn_template(shape, seed, l=8, m=6, n_solids=10, return_params=False):
+    """SYN template m0 = sum of n_solids indicator functions (uint8
+    intensities 0..n_solids): solid i is {x : |x - c_i| <= |Re Y_l^m(theta +
+    dtheta_i, phi + dphi_i)|} with c_i uniform in [-0.4 pi, 0.4 pi]^3 and
+    dtheta_i, dphi_i random multiples of pi/2; (theta, phi) are the polar
+    and azimuthal angles of x - c_i.  Each solid is evaluated on the
+    bounding box of its largest radius only.  return_params: also the list
+    of (centre, dtheta, dphi) per solid."""
+    from scipy.special import lpmv
+    from math import factorial
+    rng = np.random.Generator(np.random.PCG64(seed))
+    shape = tuple(int(s) for s in shape)
+    norm = np.sqrt((2 * l + 1) / (4 * np.pi) * factorial(l - m) / factorial(l + m))
+    xs = np.linspace(-1.0, 1.0, 20001)
+    rmax = float(norm * np.abs(lpmv(m, l, xs)).max()) * 1.01
+    ax = syn_coords(shape)
+    h = [TWO_PI / n for n in shape]
+    out = np.zeros(shape, dtype=np.uint8)
+    params = []
+    for _ in range(n_solids):
+        c = rng.uniform(-0.4 * np.pi, 0.4 * np.pi, 3)
+        dth, dph = (np.pi / 2) * rng.integers(0, 4, 2)
+        params.append((c, float(dth), float(dph)))
+        sl = []
+        for d in range(3):
+            lo = max(0, int(np.floor((c[d] - rmax + np.pi) / h[d])))
+            hi = min(shape[d], int(np.ceil((c[d] + rmax + np.pi) / h[d])) + 1)
+            sl.append(slice(lo, hi))
+        y1 = ax[0][sl[0]][:, None, None] - c[0]
+        y2 = ax[1][sl[1]][None, :, None] - c[1]
+        y3 = ax[2][sl[2]][None, None, :] - c[2]
+        rho = np.sqrt(y1 * y1 + y2 * y2 + y3 * y3)
+        theta = np.arccos(np.clip(y3 / np.maximum(rho, 1e-300), -1.0, 1.0))
+        phi = np.arctan2(y2, y1)
+        radius = norm * np.abs(np.cos(m * (phi + dph))) * np.abs(lpmv(m, l, np.cos(theta + dth)))
+        out[sl[0], sl[1], sl[2]] += (rho <= radius).astype(np.uint8)
+    return (out, params) if return_params else out
+
+
+def syn_velocity(shape, K):
+    """SYN velocity: v_x = sum_k k^-1/2 cos(k y) cos(k x), v_y = sum_k
+    k^-1/2 sin(k z) sin(k y), v_z = sum_k k^-1/2 cos(k x) cos(k z), k = 1..K,
+    with (x, y, z) = (x1, x2, x3) in (-pi, pi].  float32 [3, n1, n2, n3]."""
+    shape = tuple(int(s) for s in shape)
+    x, y, z = syn_coords(shape)
+    v = np.zeros((3,) + shape, dtype=np.float32)
+    for k in range(1, int(K) + 1):
+        a = np.float32(k ** -0.5)
+        cx, cy, cz = (np.cos(k * t).astype(np.float32) for t in (x, y, z))
+        sy, sz = (np.sin(k * t).astype(np.float32) for t in (y, z))
+        v[0] += a * cx[:, None, None] * cy[None, :, None]
+        v[1] += a * sy[None, :, None] * sz[None, None, :]
+        v[2] += a * cx[:, None, None] * cz[None, None, :]
+    return v
