@@ -205,6 +205,37 @@ def main():
         log("mixed-storage matvec %.3f ms (%.1f matvecs/s)" % (1e3 * tm / args.steps, args.steps / tm))
         del rm
 
+    # the same matvec with trilinear interpolation in every SL step
+    linear = None
+    if not args.no_mixed:
+        rl = Registration(shape, nt=4, beta_v=5e-4, gtol=1e-2, max_outer=50, max_pcg=args.max_pcg, interp="linear")
+        rl.set_images(m0, m1)
+        rl.set_velocity(dev(v_true))
+        gl, _, _ = rl.gradient()
+        vtl = -rl.precond(gl)
+        for _ in range(args.warmup):
+            rl.hessian_matvec(vtl, Hv)
+        rl.profile_enable(0xFF)
+        for _ in range(3):
+            rl.hessian_matvec(vtl, Hv)
+        lclass = {}
+        for k, name in enumerate(K_NAMES):
+            ms, cnt = rl.profile_query(k)
+            if cnt:
+                lclass[name] = {"ms_per_matvec": ms / 3, "avg_launch_ms": ms / cnt}
+                if name in ALG_F:
+                    lclass[name]["alg_GBs"] = ALG_F[name] * F / (ms / cnt * 1e-3) / 1e9
+        rl.profile_enable(0)
+        torch.cuda.synchronize()
+        tl0 = time.perf_counter()
+        for _ in range(args.steps):
+            rl.hessian_matvec(vtl, Hv)
+        torch.cuda.synchronize()
+        tl = time.perf_counter() - tl0
+        linear = {"matvecs_per_s": args.steps / tl, "interp": "trilinear", "kernels": lclass}
+        log("trilinear matvec %.3f ms (%.1f matvecs/s)" % (1e3 * tl / args.steps, args.steps / tl))
+        del rl, gl, vtl
+
     # plain FP32 GN solve to relative gradient 1e-2 from v = 0
     solve = None
     if not args.no_solve:
@@ -414,6 +445,7 @@ def main():
                      "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": avg_ms, "launches": dom_n},
         "kernels": per_class,
         "mixed_storage_matvec": mixed,
+        "trilinear_matvec": linear,
         "near_incompressible": incompressible,
         "parameter_search": search,
         "solve_fp32_h0_precond": h0,

@@ -269,21 +269,22 @@ def syn_coords(shape):
     return [(TWO_PI * np.arange(n) / n - np.pi) for n in shape]
 
 
-def syn_template(shape, seed, l=8, m=6, n_solids=10, return_params=False):
+def syn_template(shape, seed, l=8, m=6, n_solids=10, return_params=False, rscale=1.0):
     """SYN template m0 = sum of n_solids indicator functions (uint8
     intensities 0..n_solids): solid i is {x : |x - c_i| <= |Re Y_l^m(theta +
     dtheta_i, phi + dphi_i)|} with c_i uniform in [-0.4 pi, 0.4 pi]^3 and
     dtheta_i, dphi_i random multiples of pi/2; (theta, phi) are the polar
     and azimuthal angles of x - c_i.  Each solid is evaluated on the
-    bounding box of its largest radius only.  return_params: also the list
-    of (centre, dtheta, dphi) per solid."""
+    bounding box of its largest radius only.  rscale multiplies the radius
+    (1: the printed |Re Y_l^m|, at most 0.45).  return_params: also the
+    list of (centre, dtheta, dphi) per solid."""
     from scipy.special import lpmv
     from math import factorial
     rng = np.random.Generator(np.random.PCG64(seed))
     shape = tuple(int(s) for s in shape)
     norm = np.sqrt((2 * l + 1) / (4 * np.pi) * factorial(l - m) / factorial(l + m))
     xs = np.linspace(-1.0, 1.0, 20001)
-    rmax = float(norm * np.abs(lpmv(m, l, xs)).max()) * 1.01
+    rmax = float(norm * np.abs(lpmv(m, l, xs)).max()) * 1.01 * rscale
     ax = syn_coords(shape)
     h = [TWO_PI / n for n in shape]
     out = np.zeros(shape, dtype=np.uint8)
@@ -303,7 +304,7 @@ def syn_template(shape, seed, l=8, m=6, n_solids=10, return_params=False):
         rho = np.sqrt(y1 * y1 + y2 * y2 + y3 * y3)
         theta = np.arccos(np.clip(y3 / np.maximum(rho, 1e-300), -1.0, 1.0))
         phi = np.arctan2(y2, y1)
-        radius = norm * np.abs(np.cos(m * (phi + dph))) * np.abs(lpmv(m, l, np.cos(theta + dth)))
+        radius = rscale * norm * np.abs(np.cos(m * (phi + dph))) * np.abs(lpmv(m, l, np.cos(theta + dth)))
         out[sl[0], sl[1], sl[2]] += (rho <= radius).astype(np.uint8)
     return (out, params) if return_params else out
 
