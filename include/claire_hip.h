@@ -96,7 +96,9 @@ typedef struct {
  *     v = 0 the Gauss-Newton Hessian of J is H0 vt = L vt + (grad_h m0 .
  *     vt) grad_h m0 (state m0 at all times, incremental adjoint constant);
  *     z ~ H0^-1 r by precond_inner steps of CG from z = 0 preconditioned
- *     by L^-1, at full resolution.  The outer PCG is then flexible
+ *     by L^-1, at full resolution, with the k = 0 mode of L taken as beta_v
+ *     (the preconditioner's convention) so the inner operator stays
+ *     definite where the data term vanishes.  The outer PCG is then flexible
  *     (beta = <r_new, z_new - z_old> / <r, z>).  Needs the full memory
  *     layout (stored grad_h m^j) and six more vector fields of workspace;
  *     cl_create returns CL_ERR_UNSUPPORTED in the lean layout. */

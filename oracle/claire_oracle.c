@@ -774,15 +774,6 @@ static void precond_spectral(orc_ctx *o, const double *r, double *z)
         orc_reg_op(o->n1, o->n2, o->n3, r, z, 1, o->beta, o->beta_w);
 }
 
-/* L x: beta A x, with beta_w > 0 the coupled operator */
-static void reg_apply(orc_ctx *o, const double *x, double *y)
-{
-    if (o->beta_w == 0.0)
-        orc_spectral(o->n1, o->n2, o->n3, x, y, 3, 0, o->beta);
-    else
-        orc_reg_op(o->n1, o->n2, o->n3, x, y, 0, o->beta, o->beta_w);
-}
-
 /* Zero-velocity Hessian preconditioner (Section 2.2 names the zero
  * velocity approximation of H as a preconditioner; its construction is in
  * a cited paper that is not at hand).  Reading: at v = 0 the state is m0
@@ -790,21 +781,49 @@ static void reg_apply(orc_ctx *o, const double *x, double *y)
  * adjoint is constant, so the Gauss-Newton Hessian of J is
  *   H0 vt = L vt + (grad_h m0 . vt) grad_h m0,
  * a pointwise rank-one data term.  z ~ H0^-1 r by precond_inner steps of
- * CG from z = 0, preconditioned by the spectral L^-1.                    */
-static void precond_h0(orc_ctx *o, const double *r, double *z)
+ * CG from z = 0, preconditioned by the spectral L^-1; the k = 0 mode of L
+ * is taken as beta_v (L_0), the preconditioner's own convention, so that
+ * the inner operator stays definite where the data term vanishes.        */
+/* Spectral L^-1 and L_0 on a given grid. */
+static void grid_precond(int n1, int n2, int n3, double bv, double bw, const double *r, double *z)
 {
-    long n = 3 * o->N, N = o->N;
-    double w = o->hv;
-    double *gm = malloc(sizeof(double) * n), *ri = malloc(sizeof(double) * n), *zi = malloc(sizeof(double) * n);
+    if (bw == 0.0) orc_spectral(n1, n2, n3, r, z, 3, 1, bv);
+    else orc_reg_op(n1, n2, n3, r, z, 1, bv, bw);
+}
+
+/* L_0 = L with the k = 0 mode mapped by beta_v (the spectral
+ * preconditioner's convention), which keeps L_0 + g g^T definite even when
+ * the data term vanishes: y = L x + beta_v mean(x) per component.        */
+static void grid_reg0(int n1, int n2, int n3, double bv, double bw, const double *x, double *y)
+{
+    long N = (long)n1 * n2 * n3;
+    if (bw == 0.0) orc_spectral(n1, n2, n3, x, y, 3, 0, bv);
+    else orc_reg_op(n1, n2, n3, x, y, 0, bv, bw);
+    for (int a = 0; a < 3; ++a) {
+        double mean = 0.0;
+        for (long q = 0; q < N; ++q) mean += x[a * N + q];
+        mean /= (double)N;
+        for (long q = 0; q < N; ++q) y[a * N + q] += bv * mean;
+    }
+}
+
+/* iters CG steps from z = 0 on (L_0 + g g^T) z = r over an n1 x n2 x n3
+ * grid (g = grad m0 on that grid), preconditioned by the grid's spectral
+ * L^-1 (= L_0^-1).                                                       */
+static void h0_cg(int n1, int n2, int n3, double bv, double bw, int iters, const double *gm, const double *r,
+                  double *z)
+{
+    long N = (long)n1 * n2 * n3, n = 3 * N;
+    double w = (TWO_PI / n1) * (TWO_PI / n2) * (TWO_PI / n3);
+    double *ri = malloc(sizeof(double) * n), *zi = malloc(sizeof(double) * n);
     double *p = malloc(sizeof(double) * n), *Hp = malloc(sizeof(double) * n);
-    orc_grad(o->n1, o->n2, o->n3, o->m0, gm);
     memset(z, 0, sizeof(double) * n);
     memcpy(ri, r, sizeof(double) * n);
-    precond_spectral(o, ri, zi);
+    grid_precond(n1, n2, n3, bv, bw, ri, zi);
     memcpy(p, zi, sizeof(double) * n);
     double rz = dot(ri, zi, n, w);
-    for (int it = 0; it < o->precond_inner && rz > 0.0; ++it) {
-        reg_apply(o, p, Hp);
+    for (int it = 0; it < iters && rz > 0.0; ++it) {
+        grid_reg0(n1, n2, n3, bv, bw, p, Hp);
         for (long q = 0; q < N; ++q) {
             double gp = gm[q] * p[q] + gm[N + q] * p[N + q] + gm[2 * N + q] * p[2 * N + q];
             for (int a = 0; a < 3; ++a) Hp[a * N + q] += gp * gm[a * N + q];
@@ -813,14 +832,22 @@ static void precond_h0(orc_ctx *o, const double *r, double *z)
         if (!(pHp > 0.0)) break;
         double alpha = rz / pHp;
         for (long q = 0; q < n; ++q) { z[q] += alpha * p[q]; ri[q] -= alpha * Hp[q]; }
-        if (it == o->precond_inner - 1) break;
-        precond_spectral(o, ri, zi);
+        if (it == iters - 1) break;
+        grid_precond(n1, n2, n3, bv, bw, ri, zi);
         double rzn = dot(ri, zi, n, w);
         double b = rzn / rz;
         rz = rzn;
         for (long q = 0; q < n; ++q) p[q] = zi[q] + b * p[q];
     }
-    free(gm); free(ri); free(zi); free(p); free(Hp);
+    free(ri); free(zi); free(p); free(Hp);
+}
+
+static void precond_h0(orc_ctx *o, const double *r, double *z)
+{
+    double *gm = malloc(sizeof(double) * 3 * o->N);
+    orc_grad(o->n1, o->n2, o->n3, o->m0, gm);
+    h0_cg(o->n1, o->n2, o->n3, o->beta, o->beta_w, o->precond_inner, gm, r, z);
+    free(gm);
 }
 
 void orc_set_precond(orc_ctx *o, int kind, int inner)
@@ -936,7 +963,7 @@ int orc_pcg(orc_ctx *o, const double *rhs, double *x, int max_pcg, double eta, i
         if (forced_iters < 0 && rn <= eta * r0) break;
         if (it >= limit) break;
         double rz_old = 0.0;
-        if (o->precond == 1) rz_old = dot(r, z, n, w);
+        if (o->precond != 0) rz_old = dot(r, z, n, w);
         orc_precond(o, r, z);
         double rz_new = dot(r, z, n, w);
         double bt = (rz_new - rz_old) / rz;

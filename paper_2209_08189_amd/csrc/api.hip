@@ -407,9 +407,12 @@ void matvec(cl_ctx *ctx, const float *vt, float *Hvt, const float *Avt_known = n
 }
 
 // z ~ H0^-1 r (zero-velocity Hessian) by opt.precond_inner CG steps from
-// z = 0 with the spectral preconditioner; ctx->ilz receives L z.  L p of
-// the inner directions is carried by the recurrence L p = (r - mean r) +
-// beta L p, so the only FFT pair per step is the spectral preconditioner.
+// z = 0 with the spectral preconditioner; ctx->ilz receives L z.  The inner
+// operator is L_0 + G G^T with L_0 = L except that the k = 0 mode is mapped
+// by beta_v (the preconditioner's convention, definite where the data term
+// vanishes); L_0 p of the inner directions is carried by the recurrence
+// L_0 p = r + beta L_0 p (L_0 P_s = I), so the only FFT pair per step is the
+// spectral preconditioner, and L z = L_0 z - beta_v mean(z) at the end.
 // grad_h m0 is the stored G^0.
 void precond_h0(cl_ctx *ctx, const float *r, float *z)
 {
@@ -425,10 +428,8 @@ void precond_h0(cl_ctx *ctx, const float *r, float *z)
     });
     spectral(ctx, 1, 3, ctx->ir, ctx->izi, nullptr);
     HIPCHK(hipMemcpyAsync(ctx->ip, ctx->izi, n * sizeof(float), hipMemcpyDeviceToDevice, ctx->s));
+    HIPCHK(hipMemcpyAsync(ctx->iLp, ctx->ir, n * sizeof(float), hipMemcpyDeviceToDevice, ctx->s));
     run(ctx, CL_K_VEC, [&] {
-        launch_comp_sums3(ctx->ir, N, ctx->partials, ctx->nparts / 3, sc + PCG_SUMR, ctx->s);
-        launch_fill_f32(ctx->iLp, 0.0f, n, ctx->s);
-        launch_mean_free_axpy(ctx->iLp, ctx->ir, sc + PCG_SUMR, 0.0f, N, ctx->s);
         launch_dot(ctx->ir, ctx->izi, n, ctx->partials, ctx->nparts, ctx->s);
         launch_finalize(ctx->partials, ctx->nparts, ctx->hv, sc + PCG_RZ, ctx->s);
     });
@@ -447,9 +448,14 @@ void precond_h0(cl_ctx *ctx, const float *r, float *z)
             launch_dot(ctx->ir, ctx->izi, n, ctx->partials, ctx->nparts, ctx->s);
             launch_finalize(ctx->partials, ctx->nparts, ctx->hv, sc + PCG_RZNEW, ctx->s);
             launch_pcg_beta(sc, ctx->s);
-            launch_pcg_direction(ctx->ip, ctx->iLp, ctx->izi, ctx->ir, sc, N, ctx->s);
+            launch_pcg_direction_lz(ctx->ip, ctx->iLp, ctx->izi, ctx->ir, sc, N, ctx->s);
         });
     }
+    // L z = L_0 z - beta_v mean(z)
+    run(ctx, CL_K_VEC, [&] {
+        launch_comp_sums3(z, N, ctx->partials, ctx->nparts / 3, sc + PCG_SUMR, ctx->s);
+        launch_add_sums3(ctx->ilz, sc + PCG_SUMR, -ctx->opt.beta_v / (double)N, N, ctx->s);
+    });
 }
 
 void precond(cl_ctx *ctx, const float *r, float *z)

@@ -185,6 +185,8 @@ void launch_pcg_direction_lz(float *p, float *q, const float *z, const float *Lz
                              hipStream_t s);
 // y += sc[PCG_ALPHA] x over 3 n values
 void launch_axpy_sc(float *y, const float *x, const double *sc, size_t n, hipStream_t s);
+// y_c += scale * sums[c] (3 components of n values)
+void launch_add_sums3(float *y, const double *sums, double scale, size_t n, hipStream_t s);
 // out = Lp + (G . p) G per node (3 components n apart), per-block partials
 // of p . out in partials[0 .. nblocks)
 void launch_h0_apply(const float *p, const float *Lp, const float *G, float *out, size_t n, double *partials,

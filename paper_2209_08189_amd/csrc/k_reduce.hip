@@ -220,6 +220,15 @@ __global__ __launch_bounds__(TPB) void k_axpy_sc(float *__restrict__ y, const fl
     for (size_t e = (size_t)blockIdx.x * TPB + threadIdx.x; e < n3; e += stride) y[e] = fmaf(alpha, x[e], y[e]);
 }
 
+// y_c += scale * sums[c] on the 3 components of n values
+__global__ __launch_bounds__(TPB) void k_add_sums3(float *__restrict__ y, const double *__restrict__ sums, double scale,
+                                                   size_t n)
+{
+    const size_t stride = (size_t)gridDim.x * TPB;
+    for (size_t e = (size_t)blockIdx.x * TPB + threadIdx.x; e < 3 * n; e += stride)
+        y[e] += (float)(scale * sums[e / n]);
+}
+
 // Zero-velocity Hessian: out = Lp + (G . p) G, and p . out per block
 __global__ __launch_bounds__(TPB) void k_h0_apply(const float *__restrict__ p, const float *__restrict__ Lp,
                                                   const float *__restrict__ G, float *__restrict__ out, size_t n,
@@ -383,6 +392,11 @@ void launch_pcg_direction_lz(float *p, float *q, const float *z, const float *Lz
 void launch_axpy_sc(float *y, const float *x, const double *sc, size_t n, hipStream_t s)
 {
     hipLaunchKernelGGL(k_axpy_sc, stream_grid(3 * n), dim3(TPB), 0, s, y, x, sc, 3 * n);
+}
+
+void launch_add_sums3(float *y, const double *sums, double scale, size_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_add_sums3, stream_grid(3 * n), dim3(TPB), 0, s, y, sums, scale, n);
 }
 
 void launch_h0_apply(const float *p, const float *Lp, const float *G, float *out, size_t n, double *partials,

@@ -5,8 +5,10 @@ CPU only.
 At v = 0 the full Hessian matvec (transport of the incremental state with
 trapezoid sources, incremental adjoint, quadrature) must reduce to
 H0 vt = L vt + (grad_h m0 . vt) grad_h m0, so an inner solve run to
-convergence inverts the full Hessian there; a wrong sign, a dropped factor
-or a transposed outer product of the data term fails."""
+convergence inverts the full Hessian there, up to the mean mode, which the
+inner operator maps by beta_v like the spectral preconditioner
+(H(0) z + beta_v mean(z) = r); a wrong sign, a dropped factor or a
+transposed outer product of the data term fails."""
 import numpy as np
 import pytest
 
@@ -31,22 +33,23 @@ def test_converged_h0_inverts_the_hessian_at_zero(orc, beta_w):
     r = synth.random_field((3,) + shape, 92)
     o.set_precond(1, 400)
     z = o.precond(r)
-    Hz = o.matvec_sym(z)
+    Hz = o.matvec_sym(z) + 5e-3 * z.mean(axis=(1, 2, 3), keepdims=True)
     err = np.linalg.norm(Hz - r) / np.linalg.norm(r)
     assert err < 1e-7, err
 
 
 def test_h0_pcg_at_zero_converges_in_one_step(orc):
-    """With a converged inner solve the preconditioner is H(0)^-1, so PCG at
-    v = 0 reaches a 1e-6 residual in one outer iteration; the spectral
-    preconditioner needs many."""
+    """With a converged inner solve the preconditioner is H(0)^-1 up to the
+    mean mode (beta_v there instead of the data term's coupling alone), so
+    PCG at v = 0 reaches a 1e-6 residual in at most three outer iterations;
+    the spectral preconditioner needs many."""
     o, shape = _problem(orc)
     rhs = -o.gradient_l2()
     o.set_precond(1, 400)
     _, its_h0, _ = o.pcg(rhs, 50, 1e-6)
     o.set_precond(0)
     _, its_sp, _ = o.pcg(rhs, 50, 1e-6)
-    assert its_h0 == 1 and its_sp > 5, (its_h0, its_sp)
+    assert its_h0 <= 3 and its_sp > 5, (its_h0, its_sp)
 
 
 def test_h0_one_inner_step_is_a_scaled_spectral_step(orc):
@@ -58,6 +61,7 @@ def test_h0_one_inner_step_is_a_scaled_spectral_step(orc):
     pr = o.precond(r)
     o.set_precond(1, 1)
     z = o.precond(r)
-    H = o.matvec_sym(pr)                     # = H0 pr at v = 0
+    H = o.matvec_sym(pr) + 5e-3 * pr.mean(axis=(1, 2, 3), keepdims=True)   # = (L_0 + D) pr at v = 0
     scale = np.sum(r * pr) / np.sum(pr * H)
     assert np.linalg.norm(z - scale * pr) < 1e-10 * np.linalg.norm(z)
+
