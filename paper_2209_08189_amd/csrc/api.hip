@@ -412,20 +412,17 @@ void matvec(cl_ctx *ctx, const float *vt, float *Hvt, const float *Avt_known = n
 // by beta_v (the preconditioner's convention, definite where the data term
 // vanishes); L_0 p of the inner directions is carried by the recurrence
 // L_0 p = r + beta L_0 p (L_0 P_s = I), so the only FFT pair per step is the
-// spectral preconditioner, and L z = L_0 z - beta_v mean(z) at the end.
-// grad_h m0 is the stored G^0.
+// spectral preconditioner.  Each step after the first updates the direction
+// and applies the operator in one pass.  L z for the outer recurrence is
+// one spectral operation at the end.  grad_h m0 is the stored G^0.
 void precond_h0(cl_ctx *ctx, const float *r, float *z)
 {
     ensure_sgrad(ctx);
     const size_t N = ctx->N, n = 3 * N;
     double *sc = ctx->pscal + PCG_INNER;
-    const int nbc = reduce_blocks(N);
     const float *G0 = ctx->G;
     HIPCHK(hipMemcpyAsync(ctx->ir, r, n * sizeof(float), hipMemcpyDeviceToDevice, ctx->s));
-    run(ctx, CL_K_VEC, [&] {
-        launch_fill_f32(z, 0.0f, n, ctx->s);
-        launch_fill_f32(ctx->ilz, 0.0f, n, ctx->s);
-    });
+    run(ctx, CL_K_VEC, [&] { launch_fill_f32(z, 0.0f, n, ctx->s); });
     spectral(ctx, 1, 3, ctx->ir, ctx->izi, nullptr);
     HIPCHK(hipMemcpyAsync(ctx->ip, ctx->izi, n * sizeof(float), hipMemcpyDeviceToDevice, ctx->s));
     HIPCHK(hipMemcpyAsync(ctx->iLp, ctx->ir, n * sizeof(float), hipMemcpyDeviceToDevice, ctx->s));
@@ -436,11 +433,14 @@ void precond_h0(cl_ctx *ctx, const float *r, float *z)
     const int inner = ctx->opt.precond_inner;
     for (int it = 0; it < inner; ++it) {
         run(ctx, CL_K_VEC, [&] {
-            launch_h0_apply(ctx->ip, ctx->iLp, G0, ctx->ih, N, ctx->partials, ctx->nparts, ctx->s);
+            if (it == 0)
+                launch_h0_apply(ctx->ip, ctx->iLp, G0, ctx->ih, N, ctx->partials, ctx->nparts, ctx->s);
+            else
+                launch_h0_direction_apply(ctx->ip, ctx->iLp, ctx->izi, ctx->ir, G0, ctx->ih, sc, N, ctx->partials,
+                                          ctx->nparts, ctx->s);
             launch_finalize(ctx->partials, ctx->nparts, ctx->hv, sc + PCG_PHP, ctx->s);
             launch_pcg_alpha(sc, ctx->s);
-            launch_pcg_update3(z, ctx->ir, ctx->ip, ctx->ih, sc, N, ctx->qparts, nbc, ctx->hv, ctx->s);
-            launch_axpy_sc(ctx->ilz, ctx->iLp, sc, N, ctx->s);
+            launch_h0_update(z, ctx->ir, ctx->ip, ctx->ih, sc, N, ctx->s);
         });
         if (it == inner - 1) break;
         spectral(ctx, 1, 3, ctx->ir, ctx->izi, nullptr);
@@ -448,14 +448,10 @@ void precond_h0(cl_ctx *ctx, const float *r, float *z)
             launch_dot(ctx->ir, ctx->izi, n, ctx->partials, ctx->nparts, ctx->s);
             launch_finalize(ctx->partials, ctx->nparts, ctx->hv, sc + PCG_RZNEW, ctx->s);
             launch_pcg_beta(sc, ctx->s);
-            launch_pcg_direction_lz(ctx->ip, ctx->iLp, ctx->izi, ctx->ir, sc, N, ctx->s);
         });
     }
-    // L z = L_0 z - beta_v mean(z)
-    run(ctx, CL_K_VEC, [&] {
-        launch_comp_sums3(z, N, ctx->partials, ctx->nparts / 3, sc + PCG_SUMR, ctx->s);
-        launch_add_sums3(ctx->ilz, sc + PCG_SUMR, -ctx->opt.beta_v / (double)N, N, ctx->s);
-    });
+    // L z for the outer recurrence
+    spectral(ctx, 0, 3, z, ctx->ilz, nullptr);
 }
 
 void precond(cl_ctx *ctx, const float *r, float *z)

@@ -185,6 +185,12 @@ void launch_pcg_direction_lz(float *p, float *q, const float *z, const float *Lz
                              hipStream_t s);
 // y += sc[PCG_ALPHA] x over 3 n values
 void launch_axpy_sc(float *y, const float *x, const double *sc, size_t n, hipStream_t s);
+// p = z + beta p, q = r + beta q, out = q + (G . p) G (beta = sc[PCG_BETA]),
+// per-block partials of p . out
+void launch_h0_direction_apply(float *p, float *q, const float *z, const float *r, const float *G, float *out,
+                               const double *sc, size_t n, double *partials, int nblocks, hipStream_t s);
+// z += alpha p, r -= alpha H (alpha = sc[PCG_ALPHA]) over 3 n values
+void launch_h0_update(float *z, float *r, const float *p, const float *H, const double *sc, size_t n, hipStream_t s);
 // y_c += scale * sums[c] (3 components of n values)
 void launch_add_sums3(float *y, const double *sums, double scale, size_t n, hipStream_t s);
 // out = Lp + (G . p) G per node (3 components n apart), per-block partials

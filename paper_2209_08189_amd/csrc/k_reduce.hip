@@ -250,6 +250,54 @@ __global__ __launch_bounds__(TPB) void k_h0_apply(const float *__restrict__ p, c
     if (threadIdx.x == 0) partials[blockIdx.x] = acc;
 }
 
+// Inner step of the zero-velocity preconditioner, direction and operator in
+// one pass: p = z + beta p, q = r + beta q (q = L_0 p), out = q + (G . p) G,
+// per-block partials of p . out
+__global__ __launch_bounds__(TPB) void k_h0_direction_apply(float *__restrict__ p, float *__restrict__ q,
+                                                            const float *__restrict__ z, const float *__restrict__ r,
+                                                            const float *__restrict__ G, float *__restrict__ out,
+                                                            const double *__restrict__ sc, size_t n,
+                                                            double *__restrict__ partials)
+{
+    const float beta = (float)sc[PCG_BETA];
+    double acc = 0.0;
+    const size_t stride = (size_t)gridDim.x * TPB;
+    for (size_t e = (size_t)blockIdx.x * TPB + threadIdx.x; e < n; e += stride) {
+        const float p0 = fmaf(beta, p[e], z[e]), p1 = fmaf(beta, p[n + e], z[n + e]),
+                    p2 = fmaf(beta, p[2 * n + e], z[2 * n + e]);
+        const float q0 = r[e] + beta * q[e], q1 = r[n + e] + beta * q[n + e], q2 = r[2 * n + e] + beta * q[2 * n + e];
+        p[e] = p0;
+        p[n + e] = p1;
+        p[2 * n + e] = p2;
+        q[e] = q0;
+        q[n + e] = q1;
+        q[2 * n + e] = q2;
+        const float g0 = G[e], g1 = G[n + e], g2 = G[2 * n + e];
+        const float gp = g0 * p0 + g1 * p1 + g2 * p2;
+        const float o0 = fmaf(gp, g0, q0), o1 = fmaf(gp, g1, q1), o2 = fmaf(gp, g2, q2);
+        out[e] = o0;
+        out[n + e] = o1;
+        out[2 * n + e] = o2;
+        acc += (double)p0 * o0 + (double)p1 * o1 + (double)p2 * o2;
+    }
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) partials[blockIdx.x] = acc;
+}
+
+// z += alpha p, r -= alpha H over 3 n values (alpha = sc[PCG_ALPHA]; no
+// reductions)
+__global__ __launch_bounds__(TPB) void k_h0_update(float *__restrict__ z, float *__restrict__ r,
+                                                   const float *__restrict__ p, const float *__restrict__ H,
+                                                   const double *__restrict__ sc, size_t n3)
+{
+    const float alpha = (float)sc[PCG_ALPHA];
+    const size_t stride = (size_t)gridDim.x * TPB;
+    for (size_t e = (size_t)blockIdx.x * TPB + threadIdx.x; e < n3; e += stride) {
+        z[e] = fmaf(alpha, p[e], z[e]);
+        r[e] = fmaf(-alpha, H[e], r[e]);
+    }
+}
+
 // p = z + beta p and q = (r - mean r) + beta q on every component (q is
 // beta A p carried by recurrence; means from the component sums in sc)
 __global__ __launch_bounds__(TPB) void k_pcg_direction(float *__restrict__ p, float *__restrict__ q,
@@ -397,6 +445,17 @@ void launch_axpy_sc(float *y, const float *x, const double *sc, size_t n, hipStr
 void launch_add_sums3(float *y, const double *sums, double scale, size_t n, hipStream_t s)
 {
     hipLaunchKernelGGL(k_add_sums3, stream_grid(3 * n), dim3(TPB), 0, s, y, sums, scale, n);
+}
+
+void launch_h0_direction_apply(float *p, float *q, const float *z, const float *r, const float *G, float *out,
+                               const double *sc, size_t n, double *partials, int nblocks, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_h0_direction_apply, dim3(nblocks), dim3(TPB), 0, s, p, q, z, r, G, out, sc, n, partials);
+}
+
+void launch_h0_update(float *z, float *r, const float *p, const float *H, const double *sc, size_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_h0_update, stream_grid(3 * n), dim3(TPB), 0, s, z, r, p, H, sc, 3 * n);
 }
 
 void launch_h0_apply(const float *p, const float *Lp, const float *G, float *out, size_t n, double *partials,
