@@ -168,3 +168,21 @@ def test_search_error_paths():
     _, lo, hi = r.jacobian_det()
     assert lo == 1.0 and hi == 1.0
     r.close()
+
+
+def test_search_reports_bounds_when_the_first_trial_breaches():
+    """J_min = 0.999 breaches at beta_v = 1: status bounds, one trial, as
+    the oracle reports."""
+    shape, m0, m1 = _pair()
+    o = oracle.Oracle(shape, nt=4, beta=1.0)
+    o.set_images(m0, m1)
+    o.set_velocity(np.zeros((3,) + shape))
+    st, bv, bw, olog = o.param_search(jmin=0.999, max_outer=10, max_pcg=10)
+    r = reg(shape, max_outer=10, max_pcg=10)
+    r.set_images(dev(m0), dev(m1))
+    rep = r.param_search(jmin=0.999)
+    glog = np.array(r.search_log())
+    assert st == 3 and rep["status"] == 3 and rep["status_name"] == "bounds"
+    assert (rep["beta_v"], rep["beta_w"]) == (bv, bw) == (1.0, 1e-5)
+    assert glog.shape[0] == olog.shape[0] == 1 and glog[0, 4] == olog[0, 4] == 0
+    r.close()

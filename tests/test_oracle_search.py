@@ -80,3 +80,15 @@ def test_continuation_sequence(orc):
     assert seq[4][0] == 0.015625 and abs(seq[4][1] - 1e-7) < 1e-18
     assert len(seq) == 5
     assert np.all(np.diff(log[:, 8]) <= 0)     # mismatch does not rise along the path
+
+
+def test_search_reports_bounds_when_the_first_trial_breaches(orc):
+    """J_min = 0.999 cannot hold even at beta_v = 1: one trial, status 3
+    (bounds), beta_v* = beta_v_max, no beta_w stage."""
+    shape, m0, m1 = _pair(orc)
+    o = orc.Oracle(shape, nt=4, beta=1.0)
+    o.set_images(m0, m1)
+    o.set_velocity(np.zeros((3,) + shape))
+    st, bv, bw, log = o.param_search(jmin=0.999, max_outer=10, max_pcg=10)
+    assert st == 3 and bv == 1.0 and bw == 1e-5
+    assert len(log) == 1 and log[0, 4] == 0
