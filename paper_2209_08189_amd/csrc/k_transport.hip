@@ -79,34 +79,6 @@ __device__ __forceinline__ float gather(const T *__restrict__ u, const Foot &F)
     return s;
 }
 
-__device__ __forceinline__ void gather3(const float *__restrict__ u0, const float *__restrict__ u1,
-                                        const float *__restrict__ u2, const Foot &F, float out[3])
-{
-    float s0 = 0.f, s1 = 0.f, s2 = 0.f;
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        float a0 = 0.f, a1 = 0.f, a2 = 0.f;
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const int r = F.o1[a] + F.o2[b];
-            float t0 = 0.f, t1 = 0.f, t2 = 0.f;
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                t0 = fmaf(F.w3[c], u0[r + F.o3[c]], t0);
-                t1 = fmaf(F.w3[c], u1[r + F.o3[c]], t1);
-                t2 = fmaf(F.w3[c], u2[r + F.o3[c]], t2);
-            }
-            a0 = fmaf(F.w2[b], t0, a0);
-            a1 = fmaf(F.w2[b], t1, a1);
-            a2 = fmaf(F.w2[b], t2, a2);
-        }
-        s0 = fmaf(F.w1[a], a0, s0);
-        s1 = fmaf(F.w1[a], a1, s1);
-        s2 = fmaf(F.w1[a], a2, s2);
-    }
-    out[0] = s0; out[1] = s1; out[2] = s2;
-}
-
 // ------------------------------------------------------------- kernels
 
 // RK2 (Heun) feet of both characteristic directions, as index-unit
@@ -431,23 +403,11 @@ __device__ __forceinline__ void stage_box(const Grid &g, const Tu *__restrict__ 
     }
 }
 
-// LDS loads by 32-bit LDS byte address, converted to float.
+// FP32 LDS load by 32-bit LDS byte address (the 32-bit box path).
 template <typename T> __device__ __forceinline__ float lds_ld(unsigned a);
 template <> __device__ __forceinline__ float lds_ld<float>(unsigned a)
 {
     return *reinterpret_cast<__attribute__((address_space(3))) const float *>(static_cast<uintptr_t>(a));
-}
-template <> __device__ __forceinline__ float lds_ld<__hip_bfloat16>(unsigned a)
-{
-    const unsigned short h =
-        *reinterpret_cast<__attribute__((address_space(3))) const unsigned short *>(static_cast<uintptr_t>(a));
-    return __uint_as_float(static_cast<unsigned>(h) << 16);
-}
-template <> __device__ __forceinline__ float lds_ld<__half>(unsigned a)
-{
-    const unsigned short h =
-        *reinterpret_cast<__attribute__((address_space(3))) const unsigned short *>(static_cast<uintptr_t>(a));
-    return __half2float(__ushort_as_half(h));
 }
 __device__ __forceinline__ unsigned lds_ld_u32(unsigned a)
 {
@@ -493,7 +453,14 @@ __device__ __forceinline__ void compute_tile(const Grid &g, const Tu *__restrict
                                              float (&res)[QT])
 {
     constexpr int PX = box_px<Tu>();
-    if (B.fits && sizeof(Tu) == 2) {
+    if (!B.fits) {
+#pragma unroll
+        for (int q = 0; q < QT; ++q) {
+            Foot F;
+            make_foot(g, t.i0 + t.q0 + q, t.j, t.k, d1[q], d2[q], d3[q], F);
+            res[q] = epilogue<MODE>(prm, e[q], gather(u, F));
+        }
+    } else if constexpr (sizeof(Tu) == 2) {
         // 16-bit box: copy A as loaded, copy B shifted by one element, so the
         // 4 values of any stencil row are two aligned words of one copy
 #pragma unroll
@@ -525,7 +492,7 @@ __device__ __forceinline__ void compute_tile(const Grid &g, const Tu *__restrict
             res[q] = epilogue<MODE>(prm, e[q], s);
             __builtin_amdgcn_sched_barrier(0);
         }
-    } else if (B.fits) {
+    } else {
 #pragma unroll
         for (int q = 0; q < QT; ++q) {
             const float f1 = floorf(d1[q]), f2 = floorf(d2[q]), f3 = floorf(d3[q]);
@@ -560,13 +527,6 @@ __device__ __forceinline__ void compute_tile(const Grid &g, const Tu *__restrict
             }
             res[q] = epilogue<MODE>(prm, e[q], s);
             __builtin_amdgcn_sched_barrier(0);
-        }
-    } else {
-#pragma unroll
-        for (int q = 0; q < QT; ++q) {
-            Foot F;
-            make_foot(g, t.i0 + t.q0 + q, t.j, t.k, d1[q], d2[q], d3[q], F);
-            res[q] = epilogue<MODE>(prm, e[q], gather(u, F));
         }
     }
 }
