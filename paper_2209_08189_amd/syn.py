@@ -14,7 +14,15 @@ solid is carried far outside itself (Dice 0 before and after registration):
 --rscale and --vscale scale the radius and the velocity, and the record
 states both.  n_t of the registrations grows
 with the resolution (4 at 256^3) for trilinear interpolation, as the paper
-does to keep the CFL number fixed, and is 4 for tricubic.
+does to keep the CFL number fixed, and is 4 for tricubic; --nt-max caps it
+(a 1024^3 context with n_t = 16 does not fit one GPU's memory).
+
+At large base grids: --gen-nt / --gen-storage set the generator's steps and
+field storage, --storage the registration contexts' field storage, and
+--top-from-coarse registers the base level by one GN solve at the weights
+the next coarser level's search found, warm-started from that level's
+prolonged velocity, run in calls of --top-chunk GN iterations (the levels
+are then processed coarse to fine).
 
     python -m paper_2209_08189_amd.syn [--n 256] [--K 4] [--levels 256,128,64]
         [--interp linear] [--jmin 0.25] > result.json
@@ -39,6 +47,13 @@ def main():
     ap.add_argument("--max-pcg", type=int, default=40)
     ap.add_argument("--rscale", type=float, default=2.5, help="radius scale of the SYN solids")
     ap.add_argument("--vscale", type=float, default=0.1, help="scale of the SYN velocity")
+    ap.add_argument("--nt-max", type=int, default=0, help="cap on n_t of the registrations (0: none)")
+    ap.add_argument("--gen-nt", type=int, default=32, help="n_t of the forward solve that makes the reference")
+    ap.add_argument("--gen-storage", default="f32", choices=["f32", "f16", "bf16"])
+    ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"],
+                    help="field storage of the registration and evaluation contexts")
+    ap.add_argument("--top-from-coarse", action="store_true")
+    ap.add_argument("--top-chunk", type=int, default=2)
     a = ap.parse_args()
     log = lambda m: print("[syn] " + m, file=sys.stderr, flush=True)
     import torch
@@ -48,59 +63,112 @@ def main():
     torch.cuda.set_device(0)
     n = a.n
     shape = (n,) * 3
-    labels0 = synth.syn_template(shape, a.seed, rscale=a.rscale)
+    st = {"storage_state": a.storage, "storage_adjoint": a.storage}
+
+    def nt_for(L):
+        nt = max(4, 4 * L // 256) if a.interp == "linear" else 4
+        return min(nt, a.nt_max) if a.nt_max else nt
+
+    t_in = time.perf_counter()
+    labels0 = synth.syn_template(shape, a.seed, rscale=a.rscale, log=log if n >= 512 else None)
+    log("template %.1f s" % (time.perf_counter() - t_in))
     v_syn = torch.from_numpy(synth.syn_velocity(shape, a.K) * np.float32(a.vscale)).cuda()
     m0 = torch.from_numpy(labels0.astype(np.float32) / 10.0).cuda()
-    gen = Registration(shape, nt=32, interp=a.interp)
+    log("inputs %.1f s" % (time.perf_counter() - t_in))
+    gen = Registration(shape, nt=a.gen_nt, interp=a.interp, storage_state=a.gen_storage,
+                       storage_adjoint=a.gen_storage)
     gen.set_images(m0, m0)
     gen.set_velocity(v_syn)
     m1 = gen.deformed_template()
     labels1 = warp_labels(labels0, None, nlabels=11, reg=gen)
     gen.close()
-    del gen
+    del gen, v_syn
+    torch.cuda.empty_cache()
     # labels present in the reference (an empty label would score Dice 1)
-    cnt1 = np.bincount(labels1.cpu().numpy().ravel(), minlength=11)
+    labels1 = labels1.cpu().numpy()
+    cnt1 = np.bincount(labels1.ravel(), minlength=11)
     lab_ids = tuple(i for i in range(1, 11) if cnt1[i] > 0)
     pre = dice(labels0, labels1, labels=lab_ids)
     log("inputs: %d^3, K %d, label voxels %s, scored labels %s, Dice before D_a %.4f"
         % (n, a.K, np.bincount(labels0.ravel(), minlength=11)[1:].tolist(), lab_ids, pre["D_a"]))
     out = {"n": n, "K": a.K, "seed": a.seed, "interp": a.interp, "jmin": a.jmin, "rscale": a.rscale,
-           "vscale": a.vscale, "label_voxels": np.bincount(labels0.ravel(), minlength=11)[1:].tolist(),
+           "vscale": a.vscale, "gen_nt": a.gen_nt, "gen_storage": a.gen_storage, "storage": a.storage,
+           "top_from_coarse": a.top_from_coarse, "label_voxels": np.bincount(labels0.ravel(), minlength=11)[1:].tolist(),
            "scored_labels": list(lab_ids), "dice_pre": pre, "levels": []}
     mis0 = 0.5 * float(((m0 - m1).double() ** 2).sum()) * (2 * np.pi / n) ** 3
-    for L in [int(x) for x in a.levels.split(",")]:
+    levels = [int(x) for x in a.levels.split(",")]
+    if a.top_from_coarse:
+        levels = sorted(levels)
+    prev = None   # (beta_v, beta_w, velocity on the base grid) of the last level
+    for L in levels:
         s = n // L
-        nt = max(4, 4 * L // 256) if a.interp == "linear" else 4
-        m0c = m0[::s, ::s, ::s].contiguous()
-        m1c = m1[::s, ::s, ::s].contiguous()
-        reg = Registration((L,) * 3, nt=nt, interp=a.interp, max_outer=a.max_outer, max_pcg=a.max_pcg)
-        reg.set_images(m0c, m1c)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        srep = reg.param_search(jmin=a.jmin, verbose=1)
-        torch.cuda.synchronize()
-        ts = time.perf_counter() - t0
+        nt = nt_for(L)
+        if L == n and a.top_from_coarse and prev is not None:
+            # one solve at the coarser level's weights from its velocity
+            bv, bw, vp = prev
+            reg = Registration(shape, nt=nt, interp=a.interp, beta_v=bv, beta_w=bw, max_outer=a.top_chunk,
+                               max_pcg=a.max_pcg, **st)
+            reg.set_images(m0, m1)
+            reg.set_velocity(vp)
+            del vp
+            prev = None
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            gn = pcg = 0
+            while True:
+                rep = reg.solve()
+                gn += rep["outer_iters"]
+                pcg += rep["pcg_iters_total"]
+                log("level %d: %d GN, %d PCG, rel grad %.3g, %s, %.1f s"
+                    % (L, gn, pcg, rep["gnorm"] / rep["gref"], rep["status_name"], time.perf_counter() - t0))
+                if rep["status_name"] != "maxit" or gn >= a.max_outer:
+                    break
+            torch.cuda.synchronize()
+            ts = time.perf_counter() - t0
+            _, jl, jh = reg.jacobian_det()
+            srep = {"beta_v": bv, "beta_w": bw, "solves": 1, "gn_total": gn, "pcg_total": pcg, "jmin": jl,
+                    "jmax": jh, "status_name": rep["status_name"]}
+        else:
+            m0c = m0[::s, ::s, ::s].contiguous()
+            m1c = m1[::s, ::s, ::s].contiguous()
+            reg = Registration((L,) * 3, nt=nt, interp=a.interp, max_outer=a.max_outer, max_pcg=a.max_pcg, **st)
+            reg.set_images(m0c, m1c)
+            del m0c, m1c
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            srep = reg.param_search(jmin=a.jmin, verbose=1)
+            torch.cuda.synchronize()
+            ts = time.perf_counter() - t0
         vc = reg.velocity()
         reg.close()
+        del reg
         v = vc if L == n else Resampler((L,) * 3, shape)(vc)
+        del vc
         # the prolonged velocity on the base grid: labels, relative mismatch
         # and J bounds there
-        base = Registration(shape, nt=max(4, 4 * n // 256) if a.interp == "linear" else 4, interp=a.interp)
+        base = Registration(shape, nt=nt_for(n), interp=a.interp, **st)
         base.set_images(m0, m1)
         base.set_velocity(v)
         J, mis, _ = base.objective()
         _, jlo, jhi = base.jacobian_det()
         lw = warp_labels(labels0, None, nlabels=11, reg=base)
         base.close()
+        del base
         d = dice(lw, labels1, labels=lab_ids)
+        del lw
         row = {"level": L, "nt": nt, "beta_v": srep["beta_v"], "beta_w": srep["beta_w"], "search_s": ts,
                "solves": srep["solves"], "gn_total": srep["gn_total"], "pcg_total": srep["pcg_total"],
                "J_range_level": [srep["jmin"], srep["jmax"]], "J_range_base": [jlo, jhi], "r_base": mis / mis0,
                "dice": d}
+        if L == n and a.top_from_coarse and "status_name" in srep:
+            row["protocol"] = "one solve at the coarser level's weights from its prolonged velocity"
+            row["status"] = srep["status_name"]
         out["levels"].append(row)
         log("level %d: beta_v %.3g beta_w %.3g, %d solves %.1f s, r %.4f, Dice D_a %.4f D_vw %.4f D_ivw %.4f"
             % (L, srep["beta_v"], srep["beta_w"], srep["solves"], ts, row["r_base"], d["D_a"], d["D_vw"], d["D_ivw"]))
-        del v, vc
+        if a.top_from_coarse and L < n:
+            prev = (srep["beta_v"], srep["beta_w"], v)
+        del v
         torch.cuda.empty_cache()
     print(json.dumps(out), flush=True)
 

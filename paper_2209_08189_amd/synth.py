@@ -269,7 +269,7 @@ def syn_coords(shape):
     return [(TWO_PI * np.arange(n) / n - np.pi) for n in shape]
 
 
-def syn_template(shape, seed, l=8, m=6, n_solids=10, return_params=False, rscale=1.0):
+def syn_template(shape, seed, l=8, m=6, n_solids=10, return_params=False, rscale=1.0, log=None):
     """SYN template m0 = sum of n_solids indicator functions (uint8
     intensities 0..n_solids): solid i is {x : |x - c_i| <= |Re Y_l^m(theta +
     dtheta_i, phi + dphi_i)|} with c_i uniform in [-0.4 pi, 0.4 pi]^3 and
@@ -277,7 +277,8 @@ def syn_template(shape, seed, l=8, m=6, n_solids=10, return_params=False, rscale
     and azimuthal angles of x - c_i.  Each solid is evaluated on the
     bounding box of its largest radius only.  rscale multiplies the radius
     (1: the printed |Re Y_l^m|, at most 0.45).  return_params: also the
-    list of (centre, dtheta, dphi) per solid."""
+    list of (centre, dtheta, dphi) per solid.  log: optional callable
+    given one progress line per solid."""
     from scipy.special import lpmv
     from math import factorial
     rng = np.random.Generator(np.random.PCG64(seed))
@@ -306,6 +307,8 @@ def syn_template(shape, seed, l=8, m=6, n_solids=10, return_params=False, rscale
         phi = np.arctan2(y2, y1)
         radius = rscale * norm * np.abs(np.cos(m * (phi + dph))) * np.abs(lpmv(m, l, np.cos(theta + dth)))
         out[sl[0], sl[1], sl[2]] += (rho <= radius).astype(np.uint8)
+        if log:
+            log("SYN solid %d of %d" % (len(params), n_solids))
     return (out, params) if return_params else out
 
 
