@@ -174,20 +174,14 @@ __global__ __launch_bounds__(TPB) void k_sl_node(Grid g, const Tu *__restrict__ 
     stf(out + p, epilogue<MODE>(prm, e, gather(u, F)));
 }
 
-// Trilinear version (the linear interpolation option): 2 x 2 x 2 nodes from
-// base = node + floor(d) with weights (1 - f, f) per axis, one node per
-// thread; the eight values come from L2 (the feet of neighbouring threads
-// are neighbours).
-template <typename Tu, typename To, int MODE>
-__global__ __launch_bounds__(TPB) void k_sl_lin(Grid g, const Tu *__restrict__ u, const float *__restrict__ d,
-                                                SLParams prm, To *__restrict__ out)
+// Trilinear interpolation (the linear interpolation option) of u at node
+// (i, j, k) + d from global memory: 2 x 2 x 2 nodes from base = node +
+// floor(d) with weights (1 - f, f) per axis, contracted along x3, then x2,
+// then x1.  The tiled kernel takes the same operations on LDS values.
+template <typename Tu>
+__device__ __forceinline__ float lin_node(const Grid &g, const Tu *__restrict__ u, int i, int j, int k, float d1,
+                                          float d2, float d3)
 {
-    const int p = blockIdx.x * TPB + threadIdx.x;
-    if (p >= g.N) return;
-    int i, j, k;
-    node_of(g, p, i, j, k);
-    const float e = MODE == SL_STATE ? 0.0f : prm.e[p];
-    const float d1 = d[p], d2 = d[g.N + p], d3 = d[2 * (size_t)g.N + p];
     const float f1 = floorf(d1), f2 = floorf(d2), f3 = floorf(d3);
     const float a1 = d1 - f1, a2 = d2 - f2, a3 = d3 - f3;
     const int b1 = i + (int)fminf(fmaxf(f1, -16777216.0f), 16777216.0f);
@@ -203,7 +197,22 @@ __global__ __launch_bounds__(TPB) void k_sl_lin(Grid g, const Tu *__restrict__ u
     const float s11 = fmaf(a3, ldf(u + r1 + c1 + k1), w30 * ldf(u + r1 + c1 + k0));
     const float s0 = fmaf(a2, s01, (1.0f - a2) * s00);
     const float s1 = fmaf(a2, s11, (1.0f - a2) * s10);
-    stf(out + p, epilogue<MODE>(prm, e, fmaf(a1, s1, (1.0f - a1) * s0)));
+    return fmaf(a1, s1, (1.0f - a1) * s0);
+}
+
+// Per-node trilinear version (grids too small for tiles): one node per
+// thread; the eight values come from L2 (the feet of neighbouring threads
+// are neighbours).
+template <typename Tu, typename To, int MODE>
+__global__ __launch_bounds__(TPB) void k_sl_lin(Grid g, const Tu *__restrict__ u, const float *__restrict__ d,
+                                                SLParams prm, To *__restrict__ out)
+{
+    const int p = blockIdx.x * TPB + threadIdx.x;
+    if (p >= g.N) return;
+    int i, j, k;
+    node_of(g, p, i, j, k);
+    const float e = MODE == SL_STATE ? 0.0f : prm.e[p];
+    stf(out + p, epilogue<MODE>(prm, e, lin_node(g, u, i, j, k, d[p], d[g.N + p], d[2 * (size_t)g.N + p])));
 }
 
 // Tiled version: tiles of TZ x TY x TX nodes (x1, x2, x3).  For a smooth
@@ -293,7 +302,7 @@ __device__ __forceinline__ TileIdx tile_idx(const Grid &g, int tile, int ntx, in
 // the same clamped floors that the SL kernels use, so every stencil lies
 // inside its box for any finite displacement.
 __global__ __launch_bounds__(TPB) void k_tile_boxes(Grid g, const float *__restrict__ d, int ntx, int nty,
-                                                    int *__restrict__ box)
+                                                    int *__restrict__ box, int lo, int span)
 {
     __shared__ int red[TPB / 64][6];
     const TileIdx t = tile_idx<1>(g, blockIdx.x, ntx, nty);
@@ -323,10 +332,11 @@ __global__ __launch_bounds__(TPB) void k_tile_boxes(Grid g, const float *__restr
         mn2 = min(mn2, red[w][2]); mx2 = max(mx2, red[w][3]);
         mn3 = min(mn3, red[w][4]); mx3 = max(mx3, red[w][5]);
     }
-    // the stencil starts one node below the floor and spans 4 nodes
+    // the stencil starts lo nodes below the floor and spans span nodes
+    // (cubic: 1, 4; trilinear: 0, 2)
     int *o = box + 8 * blockIdx.x;
-    o[0] = mn1 - 1; o[1] = mn2 - 1; o[2] = mn3 - 1;
-    o[3] = mx1 - mn1 + 4; o[4] = mx2 - mn2 + 4; o[5] = mx3 - mn3 + 4;
+    o[0] = mn1 - lo; o[1] = mn2 - lo; o[2] = mn3 - lo;
+    o[3] = mx1 - mn1 + span; o[4] = mx2 - mn2 + span; o[5] = mx3 - mn3 + span;
     o[6] = 0; o[7] = 0;
 }
 
@@ -444,9 +454,70 @@ template <typename T> __device__ __forceinline__ unsigned lds_addr(const T *p)
     return (unsigned)(uintptr_t)(lds_void *)(p);
 }
 
-// Gather of the QT nodes of this thread from a staged box (or from global
-// memory when the box did not fit) and the epilogue, into res.
+// The two values of a trilinear stencil row at LDS byte address a: FP32
+// boxes read two words; 16-bit boxes read the one aligned word of the copy
+// the caller chose (lo half first).
+template <typename T> __device__ __forceinline__ void row2(unsigned a, float &x0, float &x1);
+template <> __device__ __forceinline__ void row2<float>(unsigned a, float &x0, float &x1)
+{
+    x0 = lds_ld<float>(a);
+    x1 = lds_ld<float>(a + 4);
+}
+template <> __device__ __forceinline__ void row2<__half>(unsigned a, float &x0, float &x1)
+{
+    const h2_t h = __builtin_bit_cast(h2_t, lds_ld_u32(a));
+    x0 = (float)h.x;
+    x1 = (float)h.y;
+}
+template <> __device__ __forceinline__ void row2<__hip_bfloat16>(unsigned a, float &x0, float &x1)
+{
+    const unsigned w = lds_ld_u32(a);
+    x0 = __uint_as_float(w << 16);
+    x1 = __uint_as_float(w & 0xffff0000u);
+}
+
+// Trilinear gather of the QT nodes of this thread from a staged box (box
+// origin at the lowest floor of the tile's feet), with the operations of
+// lin_node.
 template <typename Tu, int MODE>
+__device__ __forceinline__ void compute_tile_lin(const Tu *box, const TileIdx &t, const TileBox &B,
+                                                 const float (&d1)[QT], const float (&d2)[QT], const float (&d3)[QT],
+                                                 const float (&e)[QT], const SLParams &prm, float (&res)[QT])
+{
+    constexpr int PX = box_px<Tu>();
+    constexpr unsigned ES = sizeof(Tu);
+#pragma unroll
+    for (int q = 0; q < QT; ++q) {
+        const float f1 = floorf(d1[q]), f2 = floorf(d2[q]), f3 = floorf(d3[q]);
+        const float a1 = d1[q] - f1, a2 = d2[q] - f2, a3 = d3[q] - f3;
+        const int s1 = t.q0 + q + ifloor(d1[q]) - B.r1;
+        const int s2 = t.row + ifloor(d2[q]) - B.r2;
+        const int s3 = t.lane + ifloor(d3[q]) - B.r3 + B.sh;
+        unsigned bp;
+        if constexpr (ES == 2)   // 16-bit: the copy in which the row pair is one aligned word
+            bp = lds_addr(box) + ((s3 & 1) ? (unsigned)(PZ * PY * PX * 2) : 0u) + ((s1 * PY + s2) * PX + (s3 & ~1)) * 2u;
+        else
+            bp = lds_addr(box) + ((s1 * PY + s2) * PX + s3) * ES;
+        float x000, x001, x010, x011, x100, x101, x110, x111;
+        row2<Tu>(bp, x000, x001);
+        row2<Tu>(bp + PX * ES, x010, x011);
+        row2<Tu>(bp + PY * PX * ES, x100, x101);
+        row2<Tu>(bp + (PY * PX + PX) * ES, x110, x111);
+        const float w30 = 1.0f - a3;
+        const float s00 = fmaf(a3, x001, w30 * x000);
+        const float s01 = fmaf(a3, x011, w30 * x010);
+        const float s10 = fmaf(a3, x101, w30 * x100);
+        const float s11 = fmaf(a3, x111, w30 * x110);
+        const float s0 = fmaf(a2, s01, (1.0f - a2) * s00);
+        const float s1v = fmaf(a2, s11, (1.0f - a2) * s10);
+        res[q] = epilogue<MODE>(prm, e[q], fmaf(a1, s1v, (1.0f - a1) * s0));
+    }
+}
+
+// Gather of the QT nodes of this thread from a staged box (or from global
+// memory when the box did not fit) and the epilogue, into res.  ORDER 1:
+// trilinear, 3: tricubic.
+template <typename Tu, int MODE, int ORDER>
 __device__ __forceinline__ void compute_tile(const Grid &g, const Tu *__restrict__ u, const Tu *box, const TileIdx &t,
                                              const TileBox &B, const float (&d1)[QT], const float (&d2)[QT],
                                              const float (&d3)[QT], const float (&e)[QT], const SLParams &prm,
@@ -456,10 +527,16 @@ __device__ __forceinline__ void compute_tile(const Grid &g, const Tu *__restrict
     if (!B.fits) {
 #pragma unroll
         for (int q = 0; q < QT; ++q) {
-            Foot F;
-            make_foot(g, t.i0 + t.q0 + q, t.j, t.k, d1[q], d2[q], d3[q], F);
-            res[q] = epilogue<MODE>(prm, e[q], gather(u, F));
+            if constexpr (ORDER == 1) {
+                res[q] = epilogue<MODE>(prm, e[q], lin_node(g, u, t.i0 + t.q0 + q, t.j, t.k, d1[q], d2[q], d3[q]));
+            } else {
+                Foot F;
+                make_foot(g, t.i0 + t.q0 + q, t.j, t.k, d1[q], d2[q], d3[q], F);
+                res[q] = epilogue<MODE>(prm, e[q], gather(u, F));
+            }
         }
+    } else if constexpr (ORDER == 1) {
+        compute_tile_lin<Tu, MODE>(box, t, B, d1, d2, d3, e, prm, res);
     } else if constexpr (sizeof(Tu) == 2) {
         // 16-bit box: copy A as loaded, copy B shifted by one element, so the
         // 4 values of any stencil row are two aligned words of one copy
@@ -562,7 +639,7 @@ __device__ __forceinline__ void shift_copy(const Tu *box, const TileBox &B)
 // are requested together, then one wait, then the gather.  At most 80 VGPRs
 // (6 waves per SIMD) so that three 512-thread workgroups share a CU; their
 // phases (waiting for memory, gathering) overlap.
-template <typename Tu, typename To, int MODE>
+template <typename Tu, typename To, int MODE, int ORDER>
 __global__ __launch_bounds__(TPB_SL, 6) void k_sl_tile(Grid g, const Tu *__restrict__ u, const float *__restrict__ d,
                                                   SLParams prm, To *__restrict__ out, const int *__restrict__ boxes,
                                                   int ntx, int nty, int nblk)
@@ -586,7 +663,7 @@ __global__ __launch_bounds__(TPB_SL, 6) void k_sl_tile(Grid g, const Tu *__restr
         shift_copy(box, B);
         __syncthreads();
     }
-    compute_tile<Tu, MODE>(g, u, box, t, B, d1, d2, d3, e, prm, r);
+    compute_tile<Tu, MODE, ORDER>(g, u, box, t, B, d1, d2, d3, e, prm, r);
     store_tile(out, t, r);
 }
 
@@ -598,13 +675,17 @@ template <typename Tu, typename To, int MODE>
 void launch_sl(const Grid &g, const Tu *u, const float *d, const SLParams &prm, To *out, const int *boxes,
                hipStream_t s)
 {
-    if (g.interp == 1) {
-        hipLaunchKernelGGL((k_sl_lin<Tu, To, MODE>), grid_of(g), dim3(TPB), 0, s, g, u, d, prm, out);
-    } else if (tiled(g)) {
+    if (tiled(g)) {
         const int ntx = g.n3 / TX, nty = g.n2 / TY, ntz = g.n1 / TZ;
         const int nblk = ntx * nty * ntz;
-        hipLaunchKernelGGL((k_sl_tile<Tu, To, MODE>), dim3(nblk), dim3(TPB_SL), 0, s, g, u, d, prm, out, boxes, ntx,
-                           nty, nblk);
+        if (g.interp == 1)
+            hipLaunchKernelGGL((k_sl_tile<Tu, To, MODE, 1>), dim3(nblk), dim3(TPB_SL), 0, s, g, u, d, prm, out, boxes,
+                               ntx, nty, nblk);
+        else
+            hipLaunchKernelGGL((k_sl_tile<Tu, To, MODE, 3>), dim3(nblk), dim3(TPB_SL), 0, s, g, u, d, prm, out, boxes,
+                               ntx, nty, nblk);
+    } else if (g.interp == 1) {
+        hipLaunchKernelGGL((k_sl_lin<Tu, To, MODE>), grid_of(g), dim3(TPB), 0, s, g, u, d, prm, out);
     } else {
         hipLaunchKernelGGL((k_sl_node<Tu, To, MODE>), grid_of(g), dim3(TPB), 0, s, g, u, d, prm, out);
     }
@@ -638,9 +719,10 @@ size_t tile_box_ints(const Grid &g) { return tiled(g) ? (size_t)8 * (g.N / (TX *
 
 void launch_tile_boxes(const Grid &g, const float *d, int *boxes, hipStream_t s)
 {
-    if (!tiled(g) || g.interp == 1) return;   // the trilinear steps gather per node
+    if (!tiled(g)) return;
     const int ntx = g.n3 / TX, nty = g.n2 / TY, ntz = g.n1 / TZ;
-    hipLaunchKernelGGL(k_tile_boxes, dim3(ntx * nty * ntz), dim3(TPB), 0, s, g, d, ntx, nty, boxes);
+    const int lo = g.interp == 1 ? 0 : 1, span = g.interp == 1 ? 2 : 4;
+    hipLaunchKernelGGL(k_tile_boxes, dim3(ntx * nty * ntz), dim3(TPB), 0, s, g, d, ntx, nty, boxes, lo, span);
 }
 
 void launch_sl_state(const Grid &g, int dt_u, const void *u, const float *d, const int *boxes, int dt_out, void *out,

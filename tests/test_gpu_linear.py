@@ -44,14 +44,29 @@ def rel(a, b):
     return float(np.linalg.norm(np.ravel(a - b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
 
 
-@pytest.mark.parametrize("shape", [(32, 16, 64), (64, 64, 64)])
-def test_trilinear_gather(shape):
+@pytest.mark.parametrize("shape", [(32, 16, 64), (64, 64, 64), (16, 16, 16), (16, 16, 32)])
+@pytest.mark.parametrize("feet", ["smooth", "rough", "mixed"])
+def test_trilinear_gather(shape, feet):
+    """Against the oracle's trilinear interpolation.  Grids with n3 >= 32
+    gather tile by tile from LDS boxes; smooth displacements fit
+    the boxes, rough ones (independent random shifts of up to +-6 voxels per
+    node) send their tiles to the per-node global-memory path, and "mixed"
+    holds both kinds of tile in one launch; 16^3 uses the per-node kernel."""
     u = f32(synth.random_field(shape, 11))
-    d = f32(np.stack([3.0 * synth.smooth_random_field(shape, 12 + a, kmax=3.0) for a in range(3)]))
+    smooth = np.stack([3.0 * synth.smooth_random_field(shape, 12 + a, kmax=3.0) for a in range(3)])
+    rough = synth.random_field((3,) + shape, 15, lo=-6.0, hi=6.0)
+    if feet == "smooth":
+        d = smooth
+    elif feet == "rough":
+        d = rough
+    else:
+        d = smooth.copy()
+        d[:, : shape[0] // 2] = rough[:, : shape[0] // 2]
+    d = f32(d)
     r = reg(shape)
     out = host(r.interp(dev(u), dev(d)))
     e = rel(out, oracle.interp_linear(u, d))
-    print("trilinear gather %s: %.2e" % (shape, e))
+    print("trilinear gather %s %s: %.2e" % (shape, feet, e))
     assert e < 1e-5
     r.close()
 
