@@ -17,15 +17,19 @@ namespace {
 
 constexpr int TPB = 256;
 
-// Cubic Lagrange weights of the nodes base-1..base+2 at fraction f in [0,1).
-// At f = 0 they are exactly (0, 1, 0, 0).
-__device__ __forceinline__ void lagrange4(float f, float w[4])
+// Cubic Lagrange weights of the nodes base-1..base+2 at fraction f in [0,1),
+// with the shared factors a = f(f-1) and b = (f+1)(f-2) = a - 2 (10 VALU
+// operations); exactly (0, 1, 0, 0) at f = 0.  Every tricubic path (per
+// node, tiled, global-memory fallback) takes these weights and the same
+// contraction order, so the three agree bitwise.
+__device__ __forceinline__ void lagrange4_fast(float f, float w[4])
 {
-    const float fm1 = f - 1.0f, fm2 = f - 2.0f, fp1 = f + 1.0f;
-    w[0] = -f * fm1 * fm2 * (1.0f / 6.0f);
-    w[1] = fp1 * fm1 * fm2 * 0.5f;
-    w[2] = -fp1 * f * fm2 * 0.5f;
-    w[3] = fp1 * f * fm1 * (1.0f / 6.0f);
+    const float a = fmaf(f, f, -f);
+    const float b = a - 2.0f;
+    w[0] = a * fmaf(f, -1.0f / 6.0f, 1.0f / 3.0f);   // -f(f-1)(f-2)/6
+    w[1] = b * fmaf(f, 0.5f, -0.5f);                 //  (f+1)(f-1)(f-2)/2
+    w[2] = b * (-0.5f * f);                          // -(f+1)f(f-2)/2
+    w[3] = a * fmaf(f, 1.0f / 6.0f, 1.0f / 6.0f);    //  (f+1)f(f-1)/6
 }
 
 // Stencil of one foot: row offsets of the 4 x1 planes, 4 x2 rows, 4 x3
@@ -41,9 +45,9 @@ struct Foot {
 __device__ __forceinline__ void make_foot(const Grid &g, int i, int j, int k, float d1, float d2, float d3, Foot &F)
 {
     const float f1 = floorf(d1), f2 = floorf(d2), f3 = floorf(d3);
-    lagrange4(d1 - f1, F.w1);
-    lagrange4(d2 - f2, F.w2);
-    lagrange4(d3 - f3, F.w3);
+    lagrange4_fast(d1 - f1, F.w1);
+    lagrange4_fast(d2 - f2, F.w2);
+    lagrange4_fast(d3 - f3, F.w3);
     // integer parts clamped to +-2^24 so the conversion is defined for any
     // finite input; indices are wrapped by masking below
     const float c1 = fminf(fmaxf(f1, -16777216.0f), 16777216.0f);
@@ -258,17 +262,6 @@ __device__ __forceinline__ int wave_max(int v)
     return v;
 }
 
-// Cubic Lagrange weights at fraction f with shared factors: a = f(f-1),
-// b = (f+1)(f-2) = a - 2; 10 VALU operations.  Exactly (0, 1, 0, 0) at f = 0.
-__device__ __forceinline__ void lagrange4_fast(float f, float w[4])
-{
-    const float a = fmaf(f, f, -f);
-    const float b = a - 2.0f;
-    w[0] = a * fmaf(f, -1.0f / 6.0f, 1.0f / 3.0f);   // -f(f-1)(f-2)/6
-    w[1] = b * fmaf(f, 0.5f, -0.5f);                 //  (f+1)(f-1)(f-2)/2
-    w[2] = b * (-0.5f * f);                          // -(f+1)f(f-2)/2
-    w[3] = a * fmaf(f, 1.0f / 6.0f, 1.0f / 6.0f);    //  (f+1)f(f-1)/6
-}
 
 typedef __attribute__((address_space(3))) void lds_void;
 

@@ -82,6 +82,42 @@ def test_interp_smooth_feet_matches_oracle(shape):
     assert rel(out, oracle.interp(u, d)) < TOL_KERNEL
 
 
+@pytest.mark.parametrize("interp", ["cubic", "linear"])
+def test_tile_and_fallback_paths_agree_bitwise(interp):
+    """The tiled gather takes a tile's stencils from its LDS box, or, when
+    the tile's feet spread beyond the box pitches, from global memory with
+    the same operations.  Two gathers whose feet differ at one node only,
+    moved 20 voxels so that its tile (8 x 8 x 32 nodes from the origin)
+    takes the global-memory path in the second: every other node of that
+    tile, and every node outside it, is bitwise the same in both."""
+    shape = (32, 32, 64)
+    u = f32(synth.random_field(shape, 21))
+    d = f32(np.stack([0.6 * synth.smooth_random_field(shape, 22 + a, kmax=1.0) for a in range(3)]))
+    d2 = d.copy()
+    d2[0, 3, 3, 5] += 20.0
+
+    def origin_tile_fits(dd):
+        # the box of the tile's stencils against the FP32 box pitches 12 x 12 x 64
+        idx = np.meshgrid(np.arange(8), np.arange(8), np.arange(32), indexing="ij")
+        span = 4 if interp == "cubic" else 2
+        ext = [np.floor(dd[a][:8, :8, :32]) + idx[a] for a in range(3)]
+        ext = [x.max() - x.min() + span for x in ext]
+        return ext[0] <= 12 and ext[1] <= 12 and ext[2] <= 64
+
+    assert origin_tile_fits(d) and not origin_tile_fits(d2)
+    r = reg(shape, interp=interp)
+    a = host(r.interp(dev(u), dev(d)))
+    b = host(r.interp(dev(u), dev(d2)))
+    r.close()
+    same = np.ones(shape, dtype=bool)
+    same[3, 3, 5] = False
+    ref = oracle.interp(u, d) if interp == "cubic" else oracle.interp_linear(u, d)
+    print("%s: tile vs fallback max |diff| %.3e over %d nodes; rel to oracle %.2e"
+          % (interp, np.abs(a - b)[same].max(), same.sum(), rel(a, ref)))
+    assert np.array_equal(a[same], b[same])
+    assert rel(a, ref) < TOL_KERNEL
+
+
 @pytest.mark.parametrize("shape", SHAPES)
 def test_fd_matches_oracle(shape):
     u = f32(synth.random_field(shape, 3))
