@@ -110,6 +110,44 @@ def test_transports_gradient_matvec():
     r.close()
 
 
+UROUND = {"f16": 2.0 ** -11, "bf16": 2.0 ** -8}
+
+
+@pytest.mark.parametrize("st,ad", [("f16", "f16"), ("f16", "bf16"), ("bf16", "bf16")])
+def test_mixed_storage_transports(st, ad):
+    """Trilinear steps on 16-bit boxes (the LDS copy holding each row pair
+    as one aligned word, and the per-node path on the same storage): state
+    stored as `st`, adjoint / incremental fields as `ad`, FP32 arithmetic.
+    Errors against the FP64 oracle bounded as the tricubic mixed-storage
+    test: (n_t + 2) roundings of the storage format, the adjoint with the
+    extra factor |m1| / |lambda(1)| of its starting difference."""
+    shape, m0, m1, vs = _pair(64, 1)
+    v = f32(0.5 * vs)
+    vt = f32(synth.trig_velocity(shape, 0.3)[[2, 0, 1]])
+    o = oracle.Oracle(shape, nt=4, beta=5e-4, interp=1)
+    o.set_images(m0, m1)
+    o.set_velocity(v)
+    g_ref, _ = o.gradient()
+    Hv_ref = o.matvec(vt)
+    r = reg(shape, storage_state=st, storage_adjoint=ad)
+    r.set_images(dev(m0), dev(m1))
+    r.set_velocity(dev(v))
+    g, _, _ = r.gradient()
+    errs = {"m(1)": rel(host(r.field(0, 4)), o.field(oracle.FIELD_STATE, 4)),
+            "lambda(0)": rel(host(r.field(1, 0)), o.field(oracle.FIELD_ADJOINT, 0)),
+            "g": rel(host(g), g_ref)}
+    Hv = host(r.hessian_matvec(dev(vt)))
+    errs["lambda~(0)"] = rel(host(r.field(3, 0)), o.field(oracle.FIELD_INC_ADJOINT, 0))
+    errs["Hvt"] = rel(Hv, Hv_ref)
+    print("linear storage %s/%s: %s" % (st, ad, {k: "%.2e" % e for k, e in errs.items()}))
+    us, ua = UROUND[st], UROUND[ad]
+    amp = np.linalg.norm(m1) / np.linalg.norm(o.field(oracle.FIELD_ADJOINT, 4))
+    assert errs["m(1)"] < 6 * us
+    for k in ("lambda(0)", "g", "lambda~(0)", "Hvt"):
+        assert errs[k] < 6 * (ua + us * amp), k
+    r.close()
+
+
 def test_integer_shift_roll():
     n = 64
     shape = (n,) * 3
