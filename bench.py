@@ -205,6 +205,40 @@ def main():
         log("mixed-storage matvec %.3f ms (%.1f matvecs/s)" % (1e3 * tm / args.steps, args.steps / tm))
         del rm
 
+    # the same matvec with its beta A vt term on the context's side stream,
+    # beside the transport sweeps (overlap_spectral); the per-launch times
+    # are then those of kernels sharing the GPU
+    overlapped = None
+    if not args.no_mixed:
+        ro = Registration(shape, nt=4, beta_v=5e-4, gtol=1e-2, max_outer=50, max_pcg=args.max_pcg,
+                          overlap_spectral=True)
+        ro.set_images(m0, m1)
+        ro.set_velocity(dev(v_true))
+        go, _, _ = ro.gradient()
+        vto = -ro.precond(go)
+        for _ in range(args.warmup):
+            ro.hessian_matvec(vto, Hv)
+        ro.profile_enable(0xFF)
+        for _ in range(3):
+            ro.hessian_matvec(vto, Hv)
+        oclass = {}
+        for k, name in enumerate(K_NAMES):
+            ms, cnt = ro.profile_query(k)
+            if cnt:
+                oclass[name] = {"ms_per_matvec": ms / 3, "avg_launch_ms": ms / cnt}
+        ro.profile_enable(0)
+        torch.cuda.synchronize()
+        to0 = time.perf_counter()
+        for _ in range(args.steps):
+            ro.hessian_matvec(vto, Hv)
+        torch.cuda.synchronize()
+        to = time.perf_counter() - to0
+        overlapped = {"matvecs_per_s": args.steps / to, "overlap_spectral": 1,
+                      "note": "beta A vt on a side stream beside the transport sweeps; per-class times overlap",
+                      "kernels": oclass}
+        log("overlapped matvec %.3f ms (%.1f matvecs/s)" % (1e3 * to / args.steps, args.steps / to))
+        del ro
+
     # the same matvec with trilinear interpolation in every SL step
     linear = None
     if not args.no_mixed:
@@ -445,6 +479,7 @@ def main():
                      "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": avg_ms, "launches": dom_n},
         "kernels": per_class,
         "mixed_storage_matvec": mixed,
+        "overlapped_matvec": overlapped,
         "trilinear_matvec": linear,
         "near_incompressible": incompressible,
         "parameter_search": search,

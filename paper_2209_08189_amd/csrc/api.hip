@@ -35,6 +35,11 @@ struct cl_ctx {
     Grid g{};
     cl_options opt{};
     hipStream_t s = nullptr;
+    // side stream (default priority, non-blocking) for the beta A vt term of
+    // a Hessian matvec with overlap_spectral, which runs beside the transport
+    // sweeps; fork / join events order it against s
+    hipStream_t s2 = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
     int nt = 4;
     float dt = 0.25f;
     double hv = 0.0;             // h1 h2 h3
@@ -129,6 +134,7 @@ hipEvent_t prof_event(cl_ctx *ctx)
 void prof_drain(cl_ctx *ctx)
 {
     HIPCHK(hipStreamSynchronize(ctx->s));
+    if (ctx->s2) HIPCHK(hipStreamSynchronize(ctx->s2));   // a side launch may not be joined yet
     for (int k = 0; k < CL_K_COUNT; ++k) {
         for (auto &pr : ctx->prof.pending[k]) {
             float ms = 0.f;
@@ -142,23 +148,27 @@ void prof_drain(cl_ctx *ctx)
     }
 }
 
-template <typename F> void run(cl_ctx *ctx, int kclass, F &&f)
+// launches of f on stream st (ctx->s or the side stream; prof_drain
+// synchronizes both)
+template <typename F> void run_on(cl_ctx *ctx, hipStream_t st, int kclass, F &&f)
 {
     const bool on = (ctx->prof.mask >> kclass) & 1u;
     hipEvent_t a = nullptr, b = nullptr;
     if (on) {
         a = prof_event(ctx);
-        HIPCHK(hipEventRecord(a, ctx->s));
+        HIPCHK(hipEventRecord(a, st));
     }
     f();
     HIPCHK(hipGetLastError());
     if (on) {
         b = prof_event(ctx);
-        HIPCHK(hipEventRecord(b, ctx->s));
+        HIPCHK(hipEventRecord(b, st));
         ctx->prof.pending[kclass].push_back({a, b});
         if (ctx->prof.pending[kclass].size() > 4096) prof_drain(ctx);
     }
 }
+
+template <typename F> void run(cl_ctx *ctx, int kclass, F &&f) { run_on(ctx, ctx->s, kclass, std::forward<F>(f)); }
 
 // ---- helpers
 void *slot(cl_ctx *ctx, void *base, int dt, int j) { return (char *)base + (size_t)j * ctx->N * dtype_size(dt); }
@@ -363,6 +373,21 @@ void matvec(cl_ctx *ctx, const float *vt, float *Hvt, const float *Avt_known = n
     ensure_sgrad(ctx);
     const float dt = ctx->dt;
     const int nt = ctx->nt;
+    // beta A vt: on the side stream beside the sweeps (overlap_spectral; it
+    // needs only vt, and the sweeps touch neither tmp3 nor the FFT work
+    // space; s joins it before the quadrature), else after them on s
+    const float *Avt = Avt_known;
+    const bool side = !Avt && !data_only && ctx->opt.overlap_spectral;
+    if (side) {
+        HIPCHK(hipEventRecord(ctx->fork, ctx->s));
+        HIPCHK(hipStreamWaitEvent(ctx->s2, ctx->fork, 0));
+        run_on(ctx, ctx->s2, CL_K_FFT, [&] {
+            spectral_apply(ctx->fft, 0, (float)ctx->opt.beta_v, (float)ctx->opt.beta_w, 3, vt, ctx->tmp3, nullptr,
+                           ctx->s2);
+        });
+        HIPCHK(hipEventRecord(ctx->join, ctx->s2));
+        Avt = ctx->tmp3;
+    }
     // sources s^j = -vt . grad_h m^j, q^0 = dt/2 s^0: all at once from the
     // stored gradients, or one time level at a time by FD8 (lean layout)
     if (ctx->lean) {
@@ -390,8 +415,9 @@ void matvec(cl_ctx *ctx, const float *vt, float *Hvt, const float *Avt_known = n
         });
     }
     adjoint_sweep(ctx);
-    const float *Avt = Avt_known;
-    if (!Avt && !data_only) {
+    if (side) {
+        HIPCHK(hipStreamWaitEvent(ctx->s, ctx->join, 0));
+    } else if (!Avt && !data_only) {
         spectral(ctx, 0, 3, vt, ctx->tmp3, nullptr);
         Avt = ctx->tmp3;
     }
@@ -859,6 +885,7 @@ int check_options(const cl_options *o, cl_ctx *ctx)
     if (!(o->beta_w >= 0.0) || !std::isfinite(o->beta_w)) return fail(ctx, CL_ERR_ARG, "beta_w must be >= 0");
     if (o->max_outer < 0 || o->max_pcg < 1) return fail(ctx, CL_ERR_ARG, "iteration limits out of range");
     if (o->interp_order != 1 && o->interp_order != 3) return fail(ctx, CL_ERR_ARG, "interp_order must be 1 or 3");
+    if (o->overlap_spectral != 0 && o->overlap_spectral != 1) return fail(ctx, CL_ERR_ARG, "overlap_spectral must be 0 or 1");
     if (o->precond != CL_PRECOND_SPECTRAL && o->precond != CL_PRECOND_H0)
         return fail(ctx, CL_ERR_ARG, "unknown preconditioner");
     if (o->precond == CL_PRECOND_H0 && (o->precond_inner < 1 || o->precond_inner > 100))
@@ -914,6 +941,7 @@ void cl_default_options(cl_options *o)
     o->precond = CL_PRECOND_SPECTRAL;
     o->precond_inner = 5;
     o->interp_order = 3;
+    o->overlap_spectral = 0;
     o->gtol = 1e-2;
     o->max_outer = 50;
     o->max_pcg = 10;
@@ -1016,6 +1044,11 @@ int cl_create(cl_ctx **out, int n1, int n2, int n3, const cl_options *opt)
         ctx->pscal = (double *)alloc(sizeof(double) * PCG_NSCAL);
         if (hipHostMalloc((void **)&ctx->hscal, sizeof(double) * PCG_NSCAL, hipHostMallocDefault) != hipSuccess)
             throw Fail{CL_ERR_OOM};
+        if (opt->overlap_spectral) {
+            HIPCHK(hipStreamCreateWithFlags(&ctx->s2, hipStreamNonBlocking));
+            HIPCHK(hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming));
+            HIPCHK(hipEventCreateWithFlags(&ctx->join, hipEventDisableTiming));
+        }
         try {
             fft_plan_init(ctx->fft, n1, n2, n3, 3, alloc);
         } catch (hipError_t e) {
@@ -1044,6 +1077,12 @@ void cl_destroy(cl_ctx *ctx)
 {
     if (!ctx) return;
     (void)hipStreamSynchronize(ctx->s);
+    if (ctx->s2) {
+        (void)hipStreamSynchronize(ctx->s2);
+        (void)hipStreamDestroy(ctx->s2);
+    }
+    if (ctx->fork) (void)hipEventDestroy(ctx->fork);
+    if (ctx->join) (void)hipEventDestroy(ctx->join);
     for (void *p : ctx->allocs) (void)hipFree(p);
     if (ctx->hscal) (void)hipHostFree(ctx->hscal);
     for (int k = 0; k < CL_K_COUNT; ++k)

@@ -205,6 +205,44 @@ def test_hessian_matvec(n):
     assert rel(Hv, Hv_ref) < TOL_OP
 
 
+def test_overlapped_matvec_is_bitwise_serial():
+    """overlap_spectral = 1: the beta A vt term of the Hessian matvec runs on
+    the context's side stream beside the transport sweeps.  Three matvecs in
+    a row with different vt, with kernel-class profiling on for the last,
+    each bitwise equal to the serial context's result and within the matvec
+    tolerance of the oracle."""
+    from paper_2209_08189_amd.claire import K_NAMES
+    n = 64
+    shape, m0, m1, vs = _cfg1(n)
+    v = f32(0.5 * vs)
+    ctxs = []
+    for ov in (False, True):
+        r = reg(shape, overlap_spectral=ov)
+        r.set_images(dev(m0), dev(m1))
+        r.set_velocity(dev(v))
+        r.gradient(want_g=False)
+        ctxs.append(r)
+    o = oracle.Oracle(shape, nt=4, beta=5e-4)
+    o.set_images(m0, m1)
+    o.set_velocity(v)
+    o.gradient()
+    for k in range(3):
+        vt = f32(synth.trig_velocity(shape, 0.3)[[2, 0, 1]] + 0.1 * synth.random_field((3,) + shape, 30 + k))
+        if k == 2:
+            ctxs[1].profile_enable(0xFF)
+        a = host(ctxs[0].hessian_matvec(dev(vt)))
+        b = host(ctxs[1].hessian_matvec(dev(vt)))
+        e = rel(b, o.matvec(vt))
+        print("overlapped matvec %d: max |diff| to serial %.3e, rel to oracle %.2e" % (k, np.abs(a - b).max(), e))
+        assert np.array_equal(a, b)
+        assert e < TOL_OP
+    ms, cnt = ctxs[1].profile_query(K_NAMES.index("fft"))
+    assert cnt == 1 and ms > 0.0
+    ctxs[1].profile_enable(0)
+    for r in ctxs:
+        r.close()
+
+
 def test_objective_and_precond():
     shape, o, r, v = _setup_pair(32)
     J, mis, regv = o.objective()
