@@ -77,6 +77,9 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the 16-bit storage matvec measurement")
     ap.add_argument("--cpu-matvecs", type=int, default=3, help="oracle matvecs timed for the CPU baseline")
     ap.add_argument("--no-search", action="store_true", help="skip the parameter search leg")
+    ap.add_argument("--no-overlap", action="store_true",
+                    help="skip the overlap_spectral matvec leg (its transport launches share the GPU with an FFT, "
+                         "so a kernel trace that includes them no longer times the kernels alone)")
     ap.add_argument("--h0-inner", type=int, default=12,
                     help="inner CG steps of the zero-velocity preconditioner leg (0 disables the leg)")
     ap.add_argument("--beta-w", type=float, default=1e-5,
@@ -209,7 +212,7 @@ def main():
     # beside the transport sweeps (overlap_spectral); the per-launch times
     # are then those of kernels sharing the GPU
     overlapped = None
-    if not args.no_mixed:
+    if not args.no_mixed and not args.no_overlap:
         ro = Registration(shape, nt=4, beta_v=5e-4, gtol=1e-2, max_outer=50, max_pcg=args.max_pcg,
                           overlap_spectral=True)
         ro.set_images(m0, m1)

@@ -17,19 +17,23 @@ namespace {
 
 constexpr int TPB = 256;
 
-// Cubic Lagrange weights of the nodes base-1..base+2 at fraction f in [0,1),
-// with the shared factors a = f(f-1) and b = (f+1)(f-2) = a - 2 (10 VALU
-// operations); exactly (0, 1, 0, 0) at f = 0.  Every tricubic path (per
-// node, tiled, global-memory fallback) takes these weights and the same
-// contraction order, so the three agree bitwise.
+// Twice the cubic Lagrange weights of the nodes base-1..base+2 at fraction
+// f in [0,1), with the shared factors a = f(f-1), a/3 and b = (f+1)(f-2) =
+// a - 2 (8 VALU operations); exactly (0, 2, 0, 0) at f = 0.  A tricubic
+// value is the contraction with these weights times CUBIC_SCALE = 1/8 (a
+// power of two: no rounding).  Every tricubic path (per node, tiled,
+// global-memory fallback) takes these weights and the same contraction
+// order, so the three agree bitwise.
+constexpr float CUBIC_SCALE = 0.125f;
 __device__ __forceinline__ void lagrange4_fast(float f, float w[4])
 {
     const float a = fmaf(f, f, -f);
     const float b = a - 2.0f;
-    w[0] = a * fmaf(f, -1.0f / 6.0f, 1.0f / 3.0f);   // -f(f-1)(f-2)/6
-    w[1] = b * fmaf(f, 0.5f, -0.5f);                 //  (f+1)(f-1)(f-2)/2
-    w[2] = b * (-0.5f * f);                          // -(f+1)f(f-2)/2
-    w[3] = a * fmaf(f, 1.0f / 6.0f, 1.0f / 6.0f);    //  (f+1)f(f-1)/6
+    const float a3 = a * (1.0f / 3.0f);
+    w[0] = a3 * (2.0f - f);          // -f(f-1)(f-2)/3
+    w[1] = fmaf(b, f, -b);           //  (f+1)(f-1)(f-2)
+    w[2] = -b * f;                   // -(f+1)f(f-2)
+    w[3] = fmaf(a3, f, a3);          //  (f+1)f(f-1)/3
 }
 
 // Stencil of one foot: row offsets of the 4 x1 planes, 4 x2 rows, 4 x3
@@ -80,7 +84,7 @@ __device__ __forceinline__ float gather(const T *__restrict__ u, const Foot &F)
         }
         s = fmaf(F.w1[a], sa, s);
     }
-    return s;
+    return s * CUBIC_SCALE;
 }
 
 // ------------------------------------------------------------- kernels
@@ -559,7 +563,7 @@ __device__ __forceinline__ void compute_tile(const Grid &g, const Tu *__restrict
                 s = fmaf(w1[a], sa, s);
                 __builtin_amdgcn_sched_barrier(0);
             }
-            res[q] = epilogue<MODE>(prm, e[q], s);
+            res[q] = epilogue<MODE>(prm, e[q], s * CUBIC_SCALE);
             __builtin_amdgcn_sched_barrier(0);
         }
     } else {
@@ -595,7 +599,7 @@ __device__ __forceinline__ void compute_tile(const Grid &g, const Tu *__restrict
                 s = fmaf(w1[a], sa, s);
                 __builtin_amdgcn_sched_barrier(0);
             }
-            res[q] = epilogue<MODE>(prm, e[q], s);
+            res[q] = epilogue<MODE>(prm, e[q], s * CUBIC_SCALE);
             __builtin_amdgcn_sched_barrier(0);
         }
     }
