@@ -349,6 +349,23 @@ def main():
             ri.hessian_matvec(vti, Hv)
         torch.cuda.synchronize()
         ti = time.perf_counter() - ti0
+        # the same matvec with beta_v A vt beside the sweeps (overlap_spectral)
+        ti_ov = None
+        if not args.no_overlap:
+            rio = Registration(shape, nt=4, beta_v=5e-4, beta_w=args.beta_w, gtol=1e-2, max_outer=50,
+                               max_pcg=args.max_pcg, overlap_spectral=True)
+            rio.set_images(m0, m1)
+            rio.set_velocity(dev(v_true))
+            rio.gradient(want_g=False)
+            for _ in range(args.warmup):
+                rio.hessian_matvec(vti, Hv)
+            torch.cuda.synchronize()
+            tio0 = time.perf_counter()
+            for _ in range(args.steps):
+                rio.hessian_matvec(vti, Hv)
+            torch.cuda.synchronize()
+            ti_ov = time.perf_counter() - tio0
+            del rio
         ri.set_velocity(torch.zeros((3,) + shape, device="cuda"))
         torch.cuda.synchronize()
         ts = time.perf_counter()
@@ -357,6 +374,7 @@ def main():
         te = time.perf_counter()
         vsol = ri.velocity()
         incompressible = {"beta_w": args.beta_w, "matvecs_per_s": args.steps / ti,
+                          "matvecs_per_s_overlap_spectral": args.steps / ti_ov if ti_ov else None,
                           "matvec": "reduced form beta_v A vt + K b~ (two extra FFT pairs over the PCG's internal "
                                     "matvec)", "kernels": iclass,
                           "solve": {"status": rep["status_name"], "time_to_tol_s": te - ts,

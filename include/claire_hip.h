@@ -87,11 +87,11 @@ typedef struct {
     int precond_inner;        /* inner CG iterations of CL_PRECOND_H0, 1..100 (default 5) */
     int interp_order;         /* interpolation of every SL step: 3 tricubic Lagrange (default),
                                  1 trilinear (the paper's choice above 256^3, Section 2.3) */
-    int overlap_spectral;     /* 1: cl_hessian_matvec (beta_w = 0) computes its beta_v A vt term on a
-                                 side stream that the context owns (default priority), beside the
-                                 transport sweeps, and joins it to `stream` before the term is used,
-                                 so the call keeps the semantics of one stream; results are bitwise
-                                 those of 0.  0: one stream (default) */
+    int overlap_spectral;     /* 1: cl_hessian_matvec computes its beta_v A vt term on a side stream
+                                 that the context owns (default priority), beside the transport
+                                 sweeps, and joins it to `stream` before the term is used, so the
+                                 call keeps the semantics of one stream; results are bitwise those
+                                 of 0.  0: one stream (default) */
 } cl_options;
 
 /* Preconditioners of the GN system (Section 2.2).

@@ -1171,6 +1171,23 @@ int cl_hessian_matvec(cl_ctx *ctx, const float *vt, float *Hvt)
     API_BEGIN
     if (ctx->opt.beta_w == 0.0) {
         matvec(ctx, vt, Hvt);
+    } else if (ctx->opt.overlap_spectral) {
+        // reduced form H vt = beta_v A vt + K b~; beta_v A vt on the side
+        // stream beside the data term's sweeps (after the feet, whose
+        // computation precedes the fork), joined before K b~ takes the FFT
+        // work space
+        ensure_feet(ctx, true);
+        ensure_sgrad(ctx);
+        HIPCHK(hipEventRecord(ctx->fork, ctx->s));
+        HIPCHK(hipStreamWaitEvent(ctx->s2, ctx->fork, 0));
+        run_on(ctx, ctx->s2, CL_K_FFT, [&] {
+            spectral_apply(ctx->fft, 0, (float)ctx->opt.beta_v, 0.f, 3, vt, ctx->tmp3, nullptr, ctx->s2);
+        });
+        HIPCHK(hipEventRecord(ctx->join, ctx->s2));
+        matvec(ctx, vt, Hvt, nullptr, nullptr, true);
+        HIPCHK(hipStreamWaitEvent(ctx->s, ctx->join, 0));
+        spectral(ctx, 3, 3, Hvt, Hvt, nullptr);
+        run(ctx, CL_K_VEC, [&] { launch_axpy(Hvt, Hvt, ctx->tmp3, 1.0f, 3 * ctx->N, ctx->s); });
     } else {
         // reduced form H vt = beta_v A vt + K b~, each term formed directly
         matvec(ctx, vt, Hvt, nullptr, nullptr, true);

@@ -205,24 +205,26 @@ def test_hessian_matvec(n):
     assert rel(Hv, Hv_ref) < TOL_OP
 
 
-def test_overlapped_matvec_is_bitwise_serial():
-    """overlap_spectral = 1: the beta A vt term of the Hessian matvec runs on
-    the context's side stream beside the transport sweeps.  Three matvecs in
-    a row with different vt, with kernel-class profiling on for the last,
-    each bitwise equal to the serial context's result and within the matvec
-    tolerance of the oracle."""
+@pytest.mark.parametrize("bw", [0.0, 1e-3])
+def test_overlapped_matvec_is_bitwise_serial(bw):
+    """overlap_spectral = 1: the beta_v A vt term of the Hessian matvec runs
+    on the context's side stream beside the transport sweeps (beta_w > 0:
+    the reduced form, joined before K b~).  Three matvecs in a row with
+    different vt, with kernel-class profiling on for the last, each bitwise
+    equal to the serial context's result and within the matvec tolerance of
+    the oracle."""
     from paper_2209_08189_amd.claire import K_NAMES
     n = 64
     shape, m0, m1, vs = _cfg1(n)
     v = f32(0.5 * vs)
     ctxs = []
     for ov in (False, True):
-        r = reg(shape, overlap_spectral=ov)
+        r = reg(shape, beta_w=bw, overlap_spectral=ov)
         r.set_images(dev(m0), dev(m1))
         r.set_velocity(dev(v))
         r.gradient(want_g=False)
         ctxs.append(r)
-    o = oracle.Oracle(shape, nt=4, beta=5e-4)
+    o = oracle.Oracle(shape, nt=4, beta=5e-4, beta_w=bw)
     o.set_images(m0, m1)
     o.set_velocity(v)
     o.gradient()
@@ -237,7 +239,7 @@ def test_overlapped_matvec_is_bitwise_serial():
         assert np.array_equal(a, b)
         assert e < TOL_OP
     ms, cnt = ctxs[1].profile_query(K_NAMES.index("fft"))
-    assert cnt == 1 and ms > 0.0
+    assert cnt == (1 if bw == 0.0 else 2) and ms > 0.0
     ctxs[1].profile_enable(0)
     for r in ctxs:
         r.close()
