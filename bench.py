@@ -65,6 +65,79 @@ ALG_F = {
 }
 
 
+def _median_time(fn, reps):
+    ts = []
+    for _ in range(reps):
+        t = time.perf_counter()
+        fn()
+        ts.append(time.perf_counter() - t)
+    return float(np.median(ts))
+
+
+def cpu_baseline(args, shape, img, v_true, n0, n1):
+    """The FP64 oracle timed on the host cores beside the GPU.  Headline: a
+    few Hessian matvecs on the benchmark workload itself (same phantom pair,
+    v = v_true, vt = -P^-1 g) on all host threads.  Beside it, on the
+    closed-form 64^3 problem, one SL step, one gradient and one matvec
+    (median of 3) on 1 thread and on all threads, and the 64^3 solve of 5 GN
+    steps x <= 10 PCG on all threads."""
+    import oracle
+    from paper_2209_08189_amd import synth
+    nthreads = oracle.num_threads()
+    o = oracle.Oracle(shape, nt=4, beta=5e-4)
+    o.set_images(img, img)
+    o.set_velocity(v_true)
+    o.state()
+    cm1 = o.field(oracle.FIELD_STATE, 4) + n1
+    o.set_images(img + n0, cm1)
+    o.set_velocity(v_true)
+    cg, _ = o.gradient()
+    cvt = -o.precond(cg)
+    tc = time.perf_counter()
+    for _ in range(args.cpu_matvecs):
+        o.matvec(cvt)
+    tc = time.perf_counter() - tc
+    del o
+    legs = []
+    s64 = (64, 64, 64)
+    m0 = synth.trig_template(s64)
+    vstar = synth.trig_velocity(s64, 0.5)
+    o = oracle.Oracle(s64, nt=4, beta=5e-4)
+    o.set_images(m0, m0)
+    o.set_velocity(vstar)
+    o.state()
+    m1 = o.field(oracle.FIELD_STATE, 4)
+    o.set_images(m0, m1)
+    o.set_velocity(0.5 * vstar)
+    feet = oracle.feet(0.5 * vstar, 4)[0]
+    g64, _ = o.gradient()
+    vt64 = -o.precond(g64)
+    for nth in (1, nthreads):
+        oracle.set_num_threads(nth)
+        legs.append({"grid": 64, "threads": nth,
+                     "sl_step_s": _median_time(lambda: oracle.interp(m0, feet), 3),
+                     "gradient_s": _median_time(lambda: o.gradient(), 3),
+                     "matvec_s": _median_time(lambda: o.matvec(vt64), 3)})
+    oracle.set_num_threads(nthreads)
+    o.set_velocity(np.zeros_like(vstar))
+    ts = time.perf_counter()
+    o.solve(max_outer=5, max_pcg=10, gtol=0.0)
+    legs.append({"grid": 64, "threads": nthreads, "solve_5gn_x_10pcg_s": time.perf_counter() - ts})
+    del o
+    cpu_model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu_model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": args.cpu_matvecs / tc, "unit": "matvecs/s", "cores": nthreads, "kind": "oracle",
+            "sample": "%d FP64 oracle Hessian matvecs on the same %d^3 workload (%.1f s)"
+                      % (args.cpu_matvecs, shape[0], tc),
+            "cpu_model": cpu_model, "legs": legs}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -95,6 +168,12 @@ def main():
     if args.gpus != 1:
         print("bench.py measures one GPU only; this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
+
+    if not args.no_cpu_baseline:
+        # load the compiled oracle now, before this process touches the GPU
+        # (its loader never compiles; a missing or stale library is an error)
+        import oracle
+        oracle.lib()
 
     host = None
     if args.learned_train > 0 and not args.no_solve:
@@ -457,27 +536,8 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        # the FP64 oracle on the same workload (same phantom pair, v = v_true,
-        # vt = -P^-1 g), timed over a few matvecs on the host cores
-        import oracle
-        o = oracle.Oracle(shape, nt=4, beta=5e-4)
-        o.set_images(img, img)
-        o.set_velocity(v_true)
-        o.state()
-        cm1 = o.field(oracle.FIELD_STATE, 4) + n1
-        o.set_images(img + n0, cm1)
-        o.set_velocity(v_true)
-        cg, _ = o.gradient()
-        cvt = -o.precond(cg)
-        tc = time.perf_counter()
-        for _ in range(args.cpu_matvecs):
-            o.matvec(cvt)
-        tc = time.perf_counter() - tc
-        cpu = {"value": args.cpu_matvecs / tc, "unit": "matvecs/s", "cores": oracle.num_threads(), "kind": "oracle",
-               "sample": "%d FP64 oracle Hessian matvecs on the same %d^3 workload (%.1f s)"
-                         % (args.cpu_matvecs, n, tc)}
+        cpu = cpu_baseline(args, shape, img, v_true, n0, n1)
         log("cpu oracle: %s" % json.dumps(cpu))
-        del o
 
     out = {
         "metric": "Hessian matvecs/s at 256^3; time-to-tol learned+mixed vs plain (same GPU)",

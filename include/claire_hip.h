@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define CL_OPTIONS_VERSION 4
+#define CL_OPTIONS_VERSION 5
 
 typedef struct cl_ctx cl_ctx;
 
@@ -86,12 +86,16 @@ typedef struct {
     int precond;              /* CL_PRECOND_SPECTRAL (default) or CL_PRECOND_H0 */
     int precond_inner;        /* inner CG iterations of CL_PRECOND_H0, 1..100 (default 5) */
     int interp_order;         /* interpolation of every SL step: 3 tricubic Lagrange (default),
-                                 1 trilinear (the paper's choice above 256^3, Section 2.3) */
+                                 1 trilinear (the paper's choice above 256^3, Section 3.3) */
     int overlap_spectral;     /* 1: cl_hessian_matvec computes its beta_v A vt term on a side stream
                                  that the context owns (default priority), beside the transport
                                  sweeps, and joins it to `stream` before the term is used, so the
                                  call keeps the semantics of one stream; results are bitwise those
                                  of 0.  0: one stream (default) */
+    int fault_flip_direction; /* failure injection for tests of the line-search failure path: 1 makes
+                                 cl_solve step along -vt (an ascent direction), so every Armijo trial
+                                 fails and the solve returns CL_STATUS_LINESEARCH_FAIL with the last
+                                 accepted v kept.  0: off (default) */
 } cl_options;
 
 /* Preconditioners of the GN system (Section 2.2).
@@ -208,10 +212,10 @@ enum {
 int cl_get_field(cl_ctx *ctx, int which, int j, float *out);
 
 /* ---------------------------------------------------------------------
- * Parameter identification (Section 2.3).
+ * Parameter identification (Section 3.4).
  *
  * J = det grad y, y the map with m(1) = m0 o y, bounded by [J_min, 1/J_min]
- * (Section 2.3).  The paper does not say how J is computed; here grad y is
+ * (Section 3.4).  The paper does not say how J is computed; here grad y is
  * transported by v: d_t J + v.grad J = -(div v) J, J(0) = 1, with the
  * state's semi-Lagrangian step and Heun's rule for the source along the
  * characteristic, J^{j+1}(x) = J^j(X_f) (1 - dt/2 (d_f + d - dt d_f d)),
@@ -248,7 +252,7 @@ typedef struct {
 
 void cl_default_search_options(cl_search_options *so);
 
-/* Parameter search from the current v (Section 2.3, two stages):
+/* Parameter search from the current v (Section 3.4, two stages):
  *  (i)  beta_w = beta_w_max; beta_v = beta_v_max, then down by decades
  *       (not below beta_v_min) while J stays within bounds; at the first
  *       breach a bisection between the last valid and the breaching value,
@@ -262,7 +266,7 @@ void cl_default_search_options(cl_search_options *so);
  * (then beta_v* = beta_v_max).  Each trial is logged (cl_get_search_log). */
 int cl_param_search(cl_ctx *ctx, const cl_search_options *so, cl_search_report *rep);
 
-/* Parameter continuation toward known weights (Section 2.3): solves at
+/* Parameter continuation toward known weights (Section 3.4): solves at
  * beta_w = beta_w_max for beta_v = beta_v_max, beta_v_max / 10, ... down to
  * 10^ceil(log10 beta_v*), then beta_v*; then at beta_v* for beta_w from
  * beta_w_max down by decades to beta_w* (beta_w_target <= beta_w_max).

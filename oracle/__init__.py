@@ -28,9 +28,17 @@ _dp = ctypes.POINTER(ctypes.c_double)
 _ip = ctypes.POINTER(ctypes.c_int)
 
 
+def stale():
+    """True if the compiled oracle is missing or older than its sources."""
+    return not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(f) for f in _SRCS)
+
+
 def build(force=True):
-    """Compile the oracle with gcc -O2 -fopenmp (no fast-math)."""
-    if not force and os.path.exists(_LIB):
+    """Compile the oracle with gcc -O2 -fopenmp (no fast-math).  With
+    force=False only when the library is missing or stale.  Called by the
+    package build and at the start of a test session, never from a process
+    that has already initialised the GPU."""
+    if not force and not stale():
         return _LIB
     tmp = _LIB + ".tmp"
     cmd = ["gcc", "-O2", "-fopenmp", "-std=c11", "-fPIC", "-shared", "-Wall",
@@ -43,8 +51,9 @@ def build(force=True):
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(f) for f in _SRCS):
-            build()
+        if stale():
+            raise RuntimeError("the oracle library %s is missing or older than its sources; "
+                               "build it first with oracle.build() (or __graft_entry__.build())" % _LIB)
         L = ctypes.CDLL(_LIB)
         i, d = ctypes.c_int, ctypes.c_double
         vp = ctypes.c_void_p
@@ -87,6 +96,8 @@ def lib():
             "orc_pcg": (i, [vp, _dp, _dp, i, d, i, _ip]),
             "orc_solve": (i, [vp, i, i, d, _ip, _dp, _dp, _ip, _dp]),
             "orc_num_threads": (i, []),
+            "orc_set_num_threads": (None, [i]),
+            "orc_set_matvec_perturbation": (None, [vp, d, ctypes.c_ulonglong]),
             "cnv_conv3": (None, [i, i, i, i, i, _dp, _dp, _dp, _dp]),
             "cnv_conv3_t": (None, [i, i, i, i, i, _dp, _dp, _dp]),
             "cnv_conv3_dw": (None, [i, i, i, i, i, _dp, _dp, _dp, _dp]),
@@ -113,6 +124,11 @@ def _f64(a):
 
 def num_threads():
     return lib().orc_num_threads()
+
+
+def set_num_threads(n):
+    """OpenMP threads of the following oracle calls (timing legs)."""
+    lib().orc_set_num_threads(int(n))
 
 
 # ------------------------------------------------------------- primitives
@@ -355,6 +371,12 @@ class Oracle:
         its = ctypes.c_int()
         neg = lib().orc_pcg(self._h, _p(rhs), _p(x), int(max_pcg), float(eta), int(forced_iters), ctypes.byref(its))
         return x, its.value, bool(neg)
+
+    def set_matvec_perturbation(self, eps, seed=0):
+        """Sensitivity probe (tests only): every PCG matvec output is
+        multiplied elementwise by 1 + eps xi, xi uniform in [-1, 1) from a
+        counter-based hash of (seed, call, index); eps = 0 switches it off."""
+        lib().orc_set_matvec_perturbation(self._h, float(eps), int(seed))
 
     def solve(self, max_outer=5, max_pcg=10, gtol=1e-2, forced_pcg=None, forced_alpha=None):
         """Gauss-Newton-Krylov from the current velocity.  Returns

@@ -73,7 +73,7 @@ static double interp_node(int n1, int n2, int n3, const double *u,
     return s;
 }
 
-/* Trilinear value (the paper's linear interpolation option, Section 2.3
+/* Trilinear value (the paper's linear interpolation option, Section 3.3
  * and Section 3): nodes base and base + 1 per axis with weights 1 - f and
  * f, base = node + floor(d), f = d - floor(d).                            */
 static double interp_node_lin(int n1, int n2, int n3, const double *u,
@@ -518,6 +518,10 @@ typedef struct orc_ctx {
     int precond;            /* 0: spectral L^-1; 1: zero-velocity Hessian H0 */
     int precond_inner;      /* inner CG iterations of the H0 preconditioner */
     int have_feet, have_state;
+    /* sensitivity probe (tests only): relative perturbation of every PCG
+     * matvec output, see orc_set_matvec_perturbation */
+    double pert_eps;
+    unsigned long long pert_seed, pert_calls;
 } orc_ctx;
 
 orc_ctx *orc_create(int n1, int n2, int n3, int nt, double beta)
@@ -866,7 +870,7 @@ void orc_precond(orc_ctx *o, const double *r, double *z)
 }
 
 /* Jacobian determinant J = det grad y of the map y with m(x, 1) =
- * m0(y(x)) (Section 2.3, the bounds [J_min, 1/J_min] of the parameter
+ * m0(y(x)) (Section 3.4, the bounds [J_min, 1/J_min] of the parameter
  * search).  Reading (the paper does not say how J is computed): grad y
  * transported by v gives d_t J + v.grad J = -(div v) J, J(x, 0) = 1,
  * solved with the state's semi-Lagrangian step and Heun's rule for the
@@ -934,6 +938,36 @@ void orc_get_field(orc_ctx *o, int which, int j, double *out)
  * PCG iteration counts and step lengths instead of testing them.
  * log is [max_outer + 1][8]: k, J, mismatch, reg, ||g||, pcg iterations,
  * alpha, line-search trials (the last row is the final iterate).         */
+/* Sensitivity probe for the tests (not part of the method): with eps > 0,
+ * every matvec inside PCG is multiplied elementwise by (1 + eps xi), xi
+ * uniform in [-1, 1) from the splitmix64 hash (Steele, Lea and Flood 2014)
+ * of (seed, call number, index).  eps ~ 1e-6 mimics the relative rounding
+ * error of a single-precision matvec; eps = 0 switches it off.           */
+static unsigned long long splitmix64(unsigned long long x)
+{
+    x += 0x9E3779B97F4A7C15ULL;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBULL;
+    return x ^ (x >> 31);
+}
+
+void orc_set_matvec_perturbation(orc_ctx *o, double eps, unsigned long long seed)
+{
+    o->pert_eps = eps;
+    o->pert_seed = seed;
+    o->pert_calls = 0;
+}
+
+static void perturb(orc_ctx *o, double *y, long n)
+{
+    if (o->pert_eps == 0.0) return;
+    unsigned long long key = splitmix64(o->pert_seed ^ splitmix64(o->pert_calls++));
+    for (long q = 0; q < n; ++q) {
+        double xi = (double)(splitmix64(key + (unsigned long long)q) >> 11) * 0x1.0p-53 * 2.0 - 1.0;
+        y[q] *= 1.0 + o->pert_eps * xi;
+    }
+}
+
 int orc_pcg(orc_ctx *o, const double *rhs, double *x, int max_pcg, double eta, int forced_iters, int *iters_out)
 {
     long n = 3 * o->N;
@@ -950,6 +984,7 @@ int orc_pcg(orc_ctx *o, const double *rhs, double *x, int max_pcg, double eta, i
     int it = 0, negcurv = 0;
     while (it < limit) {
         orc_matvec_sym(o, p, Hp);
+        perturb(o, Hp, n);
         double pHp = dot(p, Hp, n, w);
         if (pHp <= 0.0) {
             negcurv = 1;
@@ -1054,7 +1089,7 @@ int orc_solve(orc_ctx *o, int max_outer, int max_pcg, double gtol,
 }
 
 /* ------------------------------------------ parameter identification
- * Section 2.3.  A trial sets (beta_v, beta_w), runs the GN solve from the
+ * Section 3.4.  A trial sets (beta_v, beta_w), runs the GN solve from the
  * current velocity (the previous trial's result) and tests the bounds
  * J_min <= det grad y <= 1/J_min.  Each trial appends a log row: beta_v,
  * beta_w, min J, max J, valid, GN iterations, PCG iterations, status,
@@ -1201,5 +1236,14 @@ int orc_num_threads(void)
     return omp_get_max_threads();
 #else
     return 1;
+#endif
+}
+
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
 #endif
 }

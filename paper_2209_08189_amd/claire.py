@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(HERE, "libclairehip.so")
 
 CL_F32, CL_BF16, CL_F16 = 0, 1, 2
 DTYPES = {"f32": CL_F32, "bf16": CL_BF16, "f16": CL_F16}
-CL_OPTIONS_VERSION = 4
+CL_OPTIONS_VERSION = 5
 PRECOND = {"spectral": 0, "h0": 1}
 
 FIELD_STATE, FIELD_ADJOINT, FIELD_INC_STATE, FIELD_INC_ADJOINT = 0, 1, 2, 3
@@ -44,6 +44,7 @@ class cl_options(ctypes.Structure):
         ("precond_inner", ctypes.c_int),
         ("interp_order", ctypes.c_int),
         ("overlap_spectral", ctypes.c_int),
+        ("fault_flip_direction", ctypes.c_int),
     ]
 
 
@@ -232,7 +233,7 @@ class Registration:
     def __init__(self, shape, nt=4, beta_v=5e-4, gtol=1e-2, max_outer=50, max_pcg=10,
                  forcing=1, eta_fixed=0.1, storage_state="f32", storage_adjoint="f32",
                  workspace_cap=0, stream=None, beta_w=0.0, precond="spectral", precond_inner=5,
-                 interp="cubic", overlap_spectral=False):
+                 interp="cubic", overlap_spectral=False, fault_flip_direction=False):
         import torch
         self.torch = torch
         self.shape = tuple(int(s) for s in shape)
@@ -245,6 +246,7 @@ class Registration:
         o.precond_inner = int(precond_inner)
         o.interp_order = {"cubic": 3, "linear": 1}[interp]
         o.overlap_spectral = 1 if overlap_spectral else 0
+        o.fault_flip_direction = 1 if fault_flip_direction else 0
         o.gtol = float(gtol)
         o.max_outer = int(max_outer)
         o.max_pcg = int(max_pcg)

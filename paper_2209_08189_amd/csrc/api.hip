@@ -609,6 +609,8 @@ int solve(cl_ctx *ctx, const int *forced_pcg, const double *forced_alpha, int fo
         int its = 0;
         pcg(ctx, ctx->opt.max_pcg, eta, forced ? forced_pcg[k] : -1, &its);
         R.pcg_iters_total += its;
+        if (ctx->opt.fault_flip_direction)   // failure injection: an ascent direction
+            run(ctx, CL_K_VEC, [&] { launch_scale(ctx->px, ctx->px, -1.0f, n, ctx->s); });
         const double gvt = dotw(ctx, ctx->grad, ctx->px, n);
         double alpha = 1.0;
         int trials = 0;
@@ -704,7 +706,7 @@ void set_regularization(cl_ctx *ctx, double beta_v, double beta_w)
     ctx->gref_valid = false;
 }
 
-// Parameter search (Section 2.3, parameter identification).  Every trial
+// Parameter search (Section 3.4, parameter identification).  Every trial
 // is a GN solve warm-started from the previous trial's velocity, followed
 // by the bounds test J_min <= det grad y <= 1/J_min.
 //  (i)  beta_w = beta_w_max; beta_v from beta_v_max down by decades while
@@ -818,7 +820,7 @@ int param_search(cl_ctx *ctx, const cl_search_options &so, cl_search_report *rep
     return status;
 }
 
-// Parameter continuation (Section 2.3): the search's solve sequence toward
+// Parameter continuation (Section 3.4): the search's solve sequence toward
 // known targets without bounds tests or bisection.  (i) beta_w = beta_w_max,
 // beta_v = beta_v_max, beta_v_max / 10, ... down to 10^k, k = ceil(log10
 // beta_v*), then beta_v*; (ii) beta_v = beta_v*, beta_w from beta_w_max down
@@ -886,6 +888,8 @@ int check_options(const cl_options *o, cl_ctx *ctx)
     if (o->max_outer < 0 || o->max_pcg < 1) return fail(ctx, CL_ERR_ARG, "iteration limits out of range");
     if (o->interp_order != 1 && o->interp_order != 3) return fail(ctx, CL_ERR_ARG, "interp_order must be 1 or 3");
     if (o->overlap_spectral != 0 && o->overlap_spectral != 1) return fail(ctx, CL_ERR_ARG, "overlap_spectral must be 0 or 1");
+    if (o->fault_flip_direction != 0 && o->fault_flip_direction != 1)
+        return fail(ctx, CL_ERR_ARG, "fault_flip_direction must be 0 or 1");
     if (o->precond != CL_PRECOND_SPECTRAL && o->precond != CL_PRECOND_H0)
         return fail(ctx, CL_ERR_ARG, "unknown preconditioner");
     if (o->precond == CL_PRECOND_H0 && (o->precond_inner < 1 || o->precond_inner > 100))
@@ -942,6 +946,7 @@ void cl_default_options(cl_options *o)
     o->precond_inner = 5;
     o->interp_order = 3;
     o->overlap_spectral = 0;
+    o->fault_flip_direction = 0;
     o->gtol = 1e-2;
     o->max_outer = 50;
     o->max_pcg = 10;

@@ -549,7 +549,17 @@ int cl_warm_start(cl_ctx *ctx, cl_net *net, int *used, double *J_pred, double *J
     } catch (const NFail &f) {
         return f.code;
     }
-    if ((st = cl_set_velocity(ctx, net->full_buf))) return st;
+    st = cl_set_velocity(ctx, net->full_buf);
+    if (st == CL_ERR_NONFINITE) {
+        // a diverged network (NaN or Inf in its prediction) is judged like
+        // any other prediction and discarded: the context keeps v = 0, whose
+        // state is the one just evaluated
+        if (used) *used = 0;
+        if (J_pred) *J_pred = HUGE_VAL;
+        if (J_zero) *J_zero = J0;
+        return CL_OK;
+    }
+    if (st) return st;
     if ((st = cl_objective(ctx, &Jp, nullptr, nullptr))) return st;
     const bool keep = Jp < J0;
     if (!keep) {

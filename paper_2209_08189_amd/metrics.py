@@ -1,4 +1,4 @@
-"""Registration quality measures of the paper's evaluation (Section 4,
+"""Registration quality measures of the paper's evaluation (Section 5.1,
 measures of performance): Dice coefficients of label maps and the relative
 mismatch.  Reporting helpers around the library; not part of the solver.
 

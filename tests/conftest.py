@@ -11,6 +11,10 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: CPU test taking more than a few seconds")
+    # (re)build the C oracle here, at session start, before any test touches
+    # the GPU: the oracle's loader itself never compiles
+    import oracle
+    oracle.build(force=False)
 
 
 @pytest.fixture(scope="session")

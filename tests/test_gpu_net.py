@@ -47,7 +47,11 @@ def host(t):
 
 
 CASES = [((4, 6, 32), 16, 16), ((4, 4, 16), 16, 32), ((3, 4, 20), 48, 16), ((4, 4, 8), 192, 64),
-         ((2, 2, 16), 64, 128), ((5, 3, 4), 96, 32)]
+         ((2, 2, 16), 64, 128), ((5, 3, 4), 96, 32),
+         # more than one 256-row chunk of the weight gradient (rows = D H ceil(W / 16)), with a ragged
+         # last chunk: 432 rows (256 + 176) and 640 rows (256 + 256 + 128), so the per-chunk partial sums
+         # and their fixed-order reduction are held to the layer tolerance too
+         ((12, 12, 40), 16, 32), ((20, 16, 20), 32, 16)]
 
 
 @pytest.mark.parametrize("shape,ci,co", CASES)
@@ -150,6 +154,27 @@ def test_warm_start_falls_back_when_no_gain():
     used, Jp, J0 = warm_start(reg, net)
     assert not used and Jp == J0
     assert float(torch.abs(reg.velocity()).max()) == 0.0
+
+
+def test_warm_start_discards_nonfinite_prediction():
+    """A diverged network (NaN parameters, so a NaN prediction) is judged and
+    discarded like any other prediction: the call succeeds, the prediction
+    is not used, J_pred is +inf, and the context keeps v = 0 with the
+    objective J(0) it reported."""
+    from paper_2209_08189_amd.claire import Net, Registration, warm_start
+    from paper_2209_08189_amd import synth
+    shape = (64, 64, 64)
+    m0 = synth.trig_template(shape).astype(np.float32)
+    m1 = np.roll(m0, 2, axis=0)
+    reg = Registration(shape)
+    reg.set_images(f32_dev(m0), f32_dev(m1))
+    net = Net(in_n=32, seed=1)
+    net.set_params(torch.full_like(net.params(), float("nan")))
+    used, Jp, J0 = warm_start(reg, net)
+    assert not used and np.isposinf(Jp) and np.isfinite(J0)
+    assert float(torch.abs(reg.velocity()).max()) == 0.0
+    J, _, _ = reg.objective()
+    assert J == J0
 
 
 def test_trained_network_gains_over_zero_start():

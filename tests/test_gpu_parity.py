@@ -409,11 +409,17 @@ def test_solve_cfg1_replay_5x10():
     decisions (PCG iteration counts, step lengths) replayed on the GPU.
     Every logged quantity agrees to 1e-5 up to and including the first GN
     step whose PCG stopped at the iteration limit without converging.
-    After such a step the 5-step iterate is transient (relative gradient
-    ~4e-4) and any 1e-7-relative perturbation of the operator -- measured on
-    the FP64 oracle itself -- moves it by ~1.6e-3 in v; the last iterate is
-    therefore held to 5e-3 here and the 1e-3 bar is applied to the converged
-    solve in the next test."""
+    After that step the iterate is unstable at the 1e-3 level for any
+    arithmetic: the FP64 oracle's own replay, with its matvec perturbed by
+    1e-6 to 1e-8 relative, moves by up to the envelope stored in
+    tests/golden/cfg1_replay_spread.json (v 1.7e-3, mismatch 1.3e-2; written
+    by an oracle-only script and reproduced by test_oracle_sensitivity).
+    The GPU's final iterate is held to 1.5 times that envelope; the 1e-3 bar
+    is applied to the converged solve in test_solve_cfg1_converged."""
+    import json
+    import os
+    env = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                      "cfg1_replay_spread.json")))["envelope_eps_1e-6_to_1e-8"]
     shape, m0, m1, vs = _cfg1(64)
     o = oracle.Oracle(shape, nt=4, beta=5e-4)
     o.set_images(m0, m1)
@@ -433,8 +439,9 @@ def test_solve_cfg1_replay_5x10():
             assert abs(glog[k, c] - log[k, c]) <= 1e-5 * abs(log[k, c]), (k, c)
     ev = rel(host(r.velocity()), v_ref)
     em = abs(glog[-1, 2] - log[-1, 2]) / log[-1, 2]
-    print("5-step replay: rel mismatch %.3e  rel velocity %.3e" % (em, ev))
-    assert ev < 5e-3 and em < 2e-2
+    print("5-step replay: rel mismatch %.3e  rel velocity %.3e (oracle envelope v %.3e, mismatch %.3e)"
+          % (em, ev, env["rel_v"], env["rel_mismatch"]))
+    assert ev <= 1.5 * env["rel_v"] and em <= 1.5 * env["rel_mismatch"]
 
 
 @pytest.mark.parametrize("bw", [0.0, 1e-5])
@@ -510,3 +517,54 @@ def test_error_codes():
     with pytest.raises(ClaireError) as e:
         r.hessian_matvec(x, out=x)
     assert e.value.code == -9
+
+
+def test_forced_linesearch_failure_keeps_last_v():
+    """Failure path forced from the host: with fault_flip_direction the GN
+    step is taken along -vt, an ascent direction, so all 10 Armijo trials
+    fail; the solve returns CL_STATUS_LINESEARCH_FAIL with the last accepted
+    velocity (here the start) kept bit for bit and its objective reported.
+    The same problem without the hook descends, and max_outer = 1 without
+    convergence returns CL_STATUS_MAXIT."""
+    shape, m0, m1, vs = _cfg1(32)
+    v0 = dev(0.25 * vs)
+    r = reg(shape, gtol=1e-6, max_outer=3, max_pcg=10, fault_flip_direction=True)
+    r.set_images(dev(m0), dev(m1))
+    r.set_velocity(v0)
+    J0, _, _ = r.objective()
+    rep = r.solve()
+    log = np.array(r.solve_log())
+    assert rep["status"] == 2 and rep["status_name"] == "linesearch_fail"
+    assert rep["outer_iters"] == 1 and log[0, 6] == 0.0 and log[0, 7] == 10
+    assert torch.equal(r.velocity(), v0)
+    assert rep["J"] == J0
+    ok = reg(shape, gtol=1e-6, max_outer=1, max_pcg=10)
+    ok.set_images(dev(m0), dev(m1))
+    ok.set_velocity(v0)
+    rep1 = ok.solve()
+    assert rep1["status_name"] == "maxit" and rep1["J"] < J0
+
+
+def test_run_twice_bitwise():
+    """Determinism: every reduction is a fixed-order two-stage FP64 sum and no
+    kernel uses floating-point atomics, so two fresh contexts given the same
+    inputs produce bitwise identical gradients, Hessian matvecs, solve logs
+    and final velocities."""
+    shape, m0, m1, vs = _cfg1(32)
+    vt = dev(synth.trig_velocity(shape, 0.3)[[1, 2, 0]])
+    outs = []
+    for _ in range(2):
+        r = reg(shape, gtol=1e-3, max_outer=6, max_pcg=10)
+        r.set_images(dev(m0), dev(m1))
+        r.set_velocity(dev(0.5 * vs))
+        g, gn, J = r.gradient()
+        Hv = r.hessian_matvec(vt)
+        r.set_velocity(torch.zeros((3,) + shape, device="cuda"))
+        rep = r.solve()
+        torch.cuda.synchronize()
+        outs.append((g.clone(), gn, J, Hv.clone(), np.array(r.solve_log()), r.velocity().clone(), rep["J"]))
+        del r
+    a, b = outs
+    assert torch.equal(a[0], b[0]) and a[1] == b[1] and a[2] == b[2]
+    assert torch.equal(a[3], b[3])
+    assert np.array_equal(a[4], b[4]) and torch.equal(a[5], b[5]) and a[6] == b[6]

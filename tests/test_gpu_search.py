@@ -1,6 +1,6 @@
 """Parameter identification on the GPU against the FP64 oracle: the Jacobian
 determinant det grad y, the two-stage parameter search under the J bounds
-and the parameter continuation (Section 2.3).
+and the parameter continuation (Section 3.4).
 
 J is a chain of n_t SL steps with a per-node factor: 1e-5 relative L2 like
 the other transports (its deviation J - 1 to 1e-4).  The search is compared

@@ -1,4 +1,4 @@
-"""Dice statistics of the paper's evaluation (Section 4, eqs. of D, D_a,
+"""Dice statistics of the paper's evaluation (Section 5.1, eqs. of D, D_a,
 D_vw, D_ivw), pinned by hand-counted label maps."""
 import numpy as np
 import pytest

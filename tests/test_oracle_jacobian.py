@@ -1,5 +1,5 @@
 """Pins of the oracle's Jacobian determinant J = det grad y (the map with
-m(1) = m0 o y; Section 2.3 bounds it by [J_min, 1/J_min]) against closed
+m(1) = m0 o y; Section 3.4 bounds it by [J_min, 1/J_min]) against closed
 forms.  CPU only.
 
 The compressible 1D flow v = (a sin x1, 0, 0) integrates exactly:

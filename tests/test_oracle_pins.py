@@ -427,6 +427,94 @@ def test_adjoint_identity_refines(orc):
     assert rhos[1] < 1e-3, rhos
 
 
+def _c4(u, ax, h):
+    """4th-order central first derivative (the average of the cubic Lagrange
+    interpolant's one-sided node derivatives)."""
+    return (np.roll(u, 2, ax) - 8 * np.roll(u, 1, ax) + 8 * np.roll(u, -1, ax) - np.roll(u, -2, ax)) / (12 * h)
+
+
+def test_linearisation_at_zero(orc):
+    """T16 at v = 0: the incremental state is the trapezoid integral of a
+    constant source, so mt(1) = -vt . grad_8 m0 to round-off; the central
+    difference of m(1) along vt instead tends to -vt . grad_c4 m0 (the
+    interpolant's one-sided node derivatives averaged), with an O(eps)
+    remainder since m(1) is kinked at v = 0.  A dropped source term, a wrong
+    trapezoid weight or a sign error in the source breaks the first part;
+    a wrong foot direction breaks the second."""
+    import oracle
+    n, nt = 16, 4
+    shape = (n,) * 3
+    h = TWO_PI / n
+    m0 = synth.smooth_random_field(shape, 30)
+    vt = np.stack([synth.smooth_random_field(shape, 31 + a) for a in range(3)])
+    o = _problem(n, nt)
+    o.set_images(m0, m0)
+    o.set_velocity(np.zeros((3,) + shape))
+    o.matvec(vt)
+    mt = o.field(oracle.FIELD_INC_STATE, nt)
+    g8 = oracle.grad(m0)
+    assert rel(mt, -np.sum(vt * g8, axis=0)) < 1e-12
+    pred = -sum(vt[a] * _c4(m0, a, h) for a in range(3))
+    res = []
+    for eps in (1e-5, 5e-6):
+        o.set_velocity(eps * vt); o.state(); mp = o.field(oracle.FIELD_STATE, nt)
+        o.set_velocity(-eps * vt); o.state(); mm = o.field(oracle.FIELD_STATE, nt)
+        res.append(rel((mp - mm) / (2 * eps), pred))
+    assert res[1] < 1e-4
+    assert 1.6 < res[0] / res[1] < 2.4, res
+
+
+def _general_v_problem(n, nt):
+    """cfg1's images (m1 = m0 transported by v*) at v = v*/2, direction
+    vt = v* + 0.3 w with a smooth trigonometric w: the same continuous
+    functions sampled at every resolution."""
+    import oracle
+    shape = (n,) * 3
+    m0 = synth.trig_template(shape)
+    vs = synth.trig_velocity(shape, 0.5)
+    o = _problem(n, nt)
+    o.set_images(m0, m0)
+    o.set_velocity(vs)
+    o.state()
+    o.set_images(m0, o.field(oracle.FIELD_STATE, nt))
+    x1, x2, x3 = synth.grid(shape)
+    w = np.stack([np.broadcast_to(f, shape) for f in (np.sin(x2) * np.cos(x3), np.cos(x3 + x1),
+                                                      0.5 * np.sin(x1 - x2))])
+    return o, 0.5 * vs, vs + 0.3 * w
+
+
+@pytest.mark.slow
+def test_linearisation_and_gradient_check_refine(orc):
+    """T16 and the second half of T12 at general v (consistency only: the
+    optimize-then-discretize scheme's incremental state and gradient are not
+    the exact derivatives of its discrete forward map).  Under joint
+    refinement (N, nt) = (16, 2) -> (32, 4) -> (64, 8):
+      * the central difference of m(1) along vt approaches mt(1)[vt];
+      * the central difference of J along vt approaches <g, vt>;
+    each error falling by at least 4x per level (observed ~7x and ~6-8x,
+    i.e. order ~3 in h), and the finest values are frozen as regression
+    bounds.  eps = 1e-5 leaves a difference error far below these (the
+    same errors at eps = 1e-4 to 3 digits at (32, 4))."""
+    import oracle
+    e16, e12 = [], []
+    for n, nt in ((16, 2), (32, 4), (64, 8)):
+        o, v, vt = _general_v_problem(n, nt)
+        o.set_velocity(v)
+        g, _ = o.gradient()
+        o.matvec(vt)
+        mt = o.field(oracle.FIELD_INC_STATE, nt)
+        gv = hv((n,) * 3) * np.sum(g * vt)
+        eps = 1e-5
+        o.set_velocity(v + eps * vt); o.state(); mp = o.field(oracle.FIELD_STATE, nt); Jp = o.objective()[0]
+        o.set_velocity(v - eps * vt); o.state(); mm = o.field(oracle.FIELD_STATE, nt); Jm = o.objective()[0]
+        e16.append(rel((mp - mm) / (2 * eps), mt))
+        e12.append(abs((Jp - Jm) / (2 * eps) - gv) / abs(gv))
+    print("T16 errors", e16, "FD gradient check errors", e12)
+    for e in (e16, e12):
+        assert e[0] > 4 * e[1] and e[1] > 4 * e[2], e
+    assert e16[2] < 7e-4 and e12[2] < 1.2e-4
+
+
 @pytest.mark.slow
 def test_pcg_matches_dense_solve(orc):
     """T13: brute force at 8^3, nt = 2: assemble H column by column at an

@@ -1,4 +1,4 @@
-"""The oracle's parameter search and continuation (Section 2.3) checked
+"""The oracle's parameter search and continuation (Section 3.4) checked
 against the rules the paper states, on a 32^3 closed-form pair.  CPU only.
 
 The rules: (i) beta_w = beta_w_max; beta_v starts at beta_v_max and drops
