@@ -1059,6 +1059,7 @@ int orc_solve(orc_ctx *o, int max_outer, int max_pcg, double gtol,
                 alpha *= 0.5;
             }
         }
+        if (!forced_alpha && !ok) trials = 10;   /* every one of the 10 trials failed */
         if (row) { row[5] = its; row[6] = ok ? alpha : 0.0; row[7] = trials; }
         if (!ok) {
             orc_set_velocity(o, v);

@@ -635,6 +635,7 @@ int solve(cl_ctx *ctx, const int *forced_pcg, const double *forced_alpha, int fo
                 alpha *= 0.5;
             }
         }
+        if (!forced && !ok) trials = 10;   // every one of the 10 trials failed
         ctx->log.back()[5] = its;
         ctx->log.back()[6] = ok ? alpha : 0.0;
         ctx->log.back()[7] = trials;
