@@ -294,6 +294,23 @@ int cl_fd_grad(cl_ctx *ctx, const float *u, float *g);
 int cl_fd_div(cl_ctx *ctx, const float *v, float *out);
 int cl_spectral(cl_ctx *ctx, int kind, int ncomp, const float *in, float *out);
 
+/* cl_interp without a context, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): out(x) = I[u](x + d(x)) on an n1 x n2 x n3 grid
+ * (powers of two in [16, 1024]) with tricubic Lagrange (interp_order = 3)
+ * or trilinear (1) interpolation; u, out: n1 n2 n3 FP32 values, d: three
+ * such fields of index-unit displacements, all device pointers owned by
+ * the caller, C order, x3 fastest.  Enqueued on `stream` (hipStream_t,
+ * NULL = default), no synchronisation.  The per-tile stencil boxes live in
+ * a library-held device array of CL_NOALLOC_BOX_INTS ints per GPU (4 MiB;
+ * grids of more than 2^28 voxels return CL_ERR_OOM); calls that overlap on
+ * one GPU share it and race.  No device or host memory is allocated.
+ * Errors: CL_ERR_ARG (NULL pointer, bad order), CL_ERR_SHAPE, CL_ERR_ALIAS
+ * (out overlaps u or d), CL_ERR_OOM, CL_ERR_HIP. */
+#define CL_NOALLOC_BOX_INTS (1 << 20)
+int cl_interp_noalloc(int n1, int n2, int n3, int interp_order, const float *u, const float *d, float *out,
+                      void *stream);
+
 /* FP64 inner product h1h2h3 sum a.b of two FP32 device vectors of n values;
  * synchronises. */
 int cl_dot(cl_ctx *ctx, const float *a, const float *b, size_t n, double *out);

@@ -149,6 +149,7 @@ SIGNATURES = {
     "cl_get_search_log": (_i, [_vp, _dp, _i, ctypes.POINTER(_i)]),
     "cl_get_field": (_i, [_vp, _i, _i, _vp]),
     "cl_interp": (_i, [_vp, _vp, _vp, _vp]),
+    "cl_interp_noalloc": (_i, [_i, _i, _i, _i, _vp, _vp, _vp, _vp]),
     "cl_fd_grad": (_i, [_vp, _vp, _vp]),
     "cl_fd_div": (_i, [_vp, _vp, _vp]),
     "cl_spectral": (_i, [_vp, _i, _i, _vp, _vp]),
@@ -224,6 +225,26 @@ def query_workspace(shape, nt=4, storage_state="f32", storage_adjoint="f32", wor
     if st != 0:
         raise ClaireError(st, "cl_query_workspace")
     return int(nb.value)
+
+
+def interp_noalloc(u, d, out, interp_order=3, stream=None):
+    """out = I[u](x + d) without a context (cl_interp_noalloc): u and out are
+    FP32 device tensors of shape (n1, n2, n3), d is (3, n1, n2, n3) in index
+    units; enqueued on `stream` (default: torch's current stream).  Nothing
+    is allocated; concurrent calls on one GPU share the library's scratch."""
+    import torch
+    shape = tuple(int(x) for x in u.shape)
+    if len(shape) != 3 or tuple(out.shape) != shape or tuple(d.shape) != (3,) + shape:
+        raise ValueError("shapes: u and out (n1, n2, n3), d (3, n1, n2, n3)")
+    for t in (u, d, out):
+        if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+            raise ValueError("u, d, out must be contiguous FP32 device tensors")
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    st = lib().cl_interp_noalloc(*shape, int(interp_order), _ptr(u), _ptr(d), _ptr(out), ctypes.c_void_p(stream))
+    if st != 0:
+        raise ClaireError(st, "cl_interp_noalloc")
+    return out
 
 
 class Registration:

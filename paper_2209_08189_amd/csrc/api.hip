@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -110,6 +111,18 @@ int ilog2i(int n)
     int l = 0;
     while ((1 << l) < n) ++l;
     return l;
+}
+
+Grid make_grid(int n1, int n2, int n3, int interp)
+{
+    Grid g{};
+    g.n1 = n1; g.n2 = n2; g.n3 = n3;
+    g.l1 = ilog2i(n1); g.l2 = ilog2i(n2); g.l3 = ilog2i(n3);
+    g.N = n1 * n2 * n3;
+    g.ih1 = (float)(n1 / TWO_PI); g.ih2 = (float)(n2 / TWO_PI); g.ih3 = (float)(n3 / TWO_PI);
+    g.h1 = (float)(TWO_PI / n1); g.h2 = (float)(TWO_PI / n2); g.h3 = (float)(TWO_PI / n3);
+    g.interp = interp;
+    return g;
 }
 
 bool overlap(const void *a, size_t na, const void *b, size_t nb)
@@ -999,13 +1012,8 @@ int cl_create(cl_ctx **out, int n1, int n2, int n3, const cl_options *opt)
     ctx->dt = (float)(1.0 / opt->nt);
     ctx->dts = opt->storage_state;
     ctx->dta = opt->storage_adjoint;
-    Grid &g = ctx->g;
-    g.n1 = n1; g.n2 = n2; g.n3 = n3;
-    g.l1 = ilog2i(n1); g.l2 = ilog2i(n2); g.l3 = ilog2i(n3);
-    g.N = n1 * n2 * n3;
-    g.ih1 = (float)(n1 / TWO_PI); g.ih2 = (float)(n2 / TWO_PI); g.ih3 = (float)(n3 / TWO_PI);
-    g.h1 = (float)(TWO_PI / n1); g.h2 = (float)(TWO_PI / n2); g.h3 = (float)(TWO_PI / n3);
-    g.interp = opt->interp_order;
+    ctx->g = make_grid(n1, n2, n3, opt->interp_order);
+    const Grid &g = ctx->g;
     ctx->N = (size_t)g.N;
     ctx->hv = (TWO_PI / n1) * (TWO_PI / n2) * (TWO_PI / n3);
     const size_t N = ctx->N;
@@ -1380,6 +1388,56 @@ int cl_interp(cl_ctx *ctx, const float *u, const float *d, float *out)
     run(ctx, CL_K_SL_STATE, [&] { launch_interp_f32(ctx->g, u, d, ctx->box_t, out, ctx->s); });
     return CL_OK;
     API_END
+}
+
+} // extern "C"
+
+// Scratch of cl_interp_noalloc: the per-tile stencil boxes (8 ints per tile
+// of the tiled gather).  Each device holds its own copy until the process
+// ends; host code reaches it only through the address that
+// hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) int scratch[CL_NOALLOC_BOX_INTS];
+
+namespace {
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex scratch_mu;
+int *scratch_dev[NOALLOC_MAX_DEVICES] = {};
+
+// device address of the current device's scratch (looked up once per device)
+int scratch_address(int **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= NOALLOC_MAX_DEVICES) return CL_ERR_HIP;
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if (!scratch_dev[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return CL_ERR_HIP;
+        scratch_dev[dev] = (int *)p;
+    }
+    *out = scratch_dev[dev];
+    return CL_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+int cl_interp_noalloc(int n1, int n2, int n3, int interp_order, const float *u, const float *d, float *out,
+                      void *stream)
+{
+    if (!u || !d || !out) return CL_ERR_ARG;
+    if (interp_order != 1 && interp_order != 3) return CL_ERR_ARG;
+    if (!pow2_ok(n1) || !pow2_ok(n2) || !pow2_ok(n3)) return CL_ERR_SHAPE;
+    const Grid g = make_grid(n1, n2, n3, interp_order);
+    if (tile_box_ints(g) > (size_t)CL_NOALLOC_BOX_INTS) return CL_ERR_OOM;
+    const size_t b = (size_t)g.N * sizeof(float);
+    if (overlap(u, b, out, b) || overlap(d, 3 * b, out, b)) return CL_ERR_ALIAS;
+    int *boxes = nullptr;
+    const int st = scratch_address(&boxes);
+    if (st != CL_OK) return st;
+    launch_interp_f32(g, u, d, boxes, out, (hipStream_t)stream);
+    return hipGetLastError() == hipSuccess ? CL_OK : CL_ERR_HIP;
 }
 
 int cl_fd_grad(cl_ctx *ctx, const float *u, float *gout)
