@@ -322,7 +322,9 @@ class Oracle:
 
     def set_precond(self, kind, inner=5):
         """kind 0: spectral L^-1; 1: zero-velocity Hessian H0 by `inner` CG
-        steps (the outer PCG is then flexible)."""
+        steps; 2: its two-level variant (H0 by `inner` CG steps on the
+        half-resolution grid for the band it represents, L^-1 above); the
+        outer PCG is flexible for kinds 1 and 2."""
         lib().orc_set_precond(self._h, int(kind), int(inner))
 
     def set_beta(self, beta_v, beta_w=0.0):

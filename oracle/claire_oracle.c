@@ -515,7 +515,7 @@ typedef struct orc_ctx {
     double *work3a, *work3b;
     double beta_w;          /* divergence regularisation (0: K = I) */
     int interp;             /* interpolation order: 3 tricubic (default), 1 trilinear */
-    int precond;            /* 0: spectral L^-1; 1: zero-velocity Hessian H0 */
+    int precond;            /* 0: spectral L^-1; 1: zero-velocity Hessian H0; 2: its two-level variant */
     int precond_inner;      /* inner CG iterations of the H0 preconditioner */
     int have_feet, have_state;
     /* sensitivity probe (tests only): relative perturbation of every PCG
@@ -854,6 +854,42 @@ static void precond_h0(orc_ctx *o, const double *r, double *z)
     free(gm);
 }
 
+/* Two-level coarse-grid variant (Section 2.2 names it as the default and
+ * defers its construction to a cited paper).  Reading: the Fourier modes
+ * that a half-resolution grid represents (|k_d| < n_d/4 on every axis, the
+ * band kept by spectral restriction) get the zero-velocity Hessian inverted
+ * on that grid, the modes above the band get the spectral L^-1:
+ *   r_c = R r,  z_c = iters CG steps on (L_0 + g_c g_c^T) z_c = r_c,
+ *   z   = P z_c + L^-1 (r - P R r),
+ * with R / P spectral restriction / prolongation (orc_spectral_resample),
+ * g_c = grad_h of the restricted template R m0 on the coarse grid (FD8 with
+ * the coarse spacing) and L^-1 the spectral preconditioner (k = 0 mode by
+ * 1/beta_v; r - P R r has no k = 0 mode).                                 */
+static void resample3(int a1, int a2, int a3, const double *in, int b1, int b2, int b3, double *out)
+{
+    long Na = (long)a1 * a2 * a3, Nb = (long)b1 * b2 * b3;
+    for (int c = 0; c < 3; ++c) orc_spectral_resample(a1, a2, a3, in + c * Na, b1, b2, b3, out + c * Nb);
+}
+
+static void precond_h0_2level(orc_ctx *o, const double *r, double *z)
+{
+    int n1 = o->n1, n2 = o->n2, n3 = o->n3, c1 = n1 / 2, c2 = n2 / 2, c3 = n3 / 2;
+    long N = o->N, Nc = (long)c1 * c2 * c3;
+    double *m0c = malloc(sizeof(double) * Nc), *gc = malloc(sizeof(double) * 3 * Nc);
+    double *rc = malloc(sizeof(double) * 3 * Nc), *zc = malloc(sizeof(double) * 3 * Nc);
+    double *lowr = malloc(sizeof(double) * 3 * N), *zl = malloc(sizeof(double) * 3 * N);
+    orc_spectral_resample(n1, n2, n3, o->m0, c1, c2, c3, m0c);
+    orc_grad(c1, c2, c3, m0c, gc);
+    resample3(n1, n2, n3, r, c1, c2, c3, rc);                 /* R r */
+    h0_cg(c1, c2, c3, o->beta, o->beta_w, o->precond_inner, gc, rc, zc);
+    resample3(c1, c2, c3, rc, n1, n2, n3, lowr);             /* P R r */
+    for (long q = 0; q < 3 * N; ++q) lowr[q] = r[q] - lowr[q];   /* r - P R r */
+    grid_precond(n1, n2, n3, o->beta, o->beta_w, lowr, z);   /* L^-1 of the high band */
+    resample3(c1, c2, c3, zc, n1, n2, n3, zl);               /* P z_c */
+    for (long q = 0; q < 3 * N; ++q) z[q] += zl[q];
+    free(m0c); free(gc); free(rc); free(zc); free(lowr); free(zl);
+}
+
 void orc_set_precond(orc_ctx *o, int kind, int inner)
 {
     o->precond = kind;
@@ -865,6 +901,8 @@ void orc_precond(orc_ctx *o, const double *r, double *z)
 {
     if (o->precond == 1)
         precond_h0(o, r, z);
+    else if (o->precond == 2)
+        precond_h0_2level(o, r, z);
     else
         precond_spectral(o, r, z);
 }
