@@ -397,7 +397,8 @@ int cl_warm_start(cl_ctx *ctx, cl_net *net, int *used, double *J_pred, double *J
  *   cl_nn_conv3: transpose = 0: out[.., Co] = act(conv(in[.., Ci]) + b)
  *                transpose = 1: out[.., Ci] = conv^T(in[.., Co]) (no bias/act)
  *     out is FP32 if out_f32 else BF16; wpack: device scratch of
- *     27 * Ci * Co * 2 bytes.  Ci, Co multiples of 16.
+ *     28 * Ci * Co * 2 bytes (the 27 taps packed in pairs with a zero
+ *     tap).  Ci, Co multiples of 16.
  *   cl_nn_conv3_dw: gw[t][i][o] = sum_p x[p + t - 1][i] dz[p][o], gb[o] =
  *     sum_p dz[p][o] (gb may be NULL); workspace from cl_nn_conv3_dw_workspace. */
 int cl_nn_conv3(const void *in, const float *w, const float *b, void *out, int out_f32, int D, int H, int W, int Ci,

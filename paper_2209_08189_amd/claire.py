@@ -569,7 +569,7 @@ def nn_conv3(x_bf16, w, b, Co=None, act=1, slope=0.2, transpose=False, out_f32=T
         raise ValueError("input channels do not match the weight")
     Cout = Ci if transpose else Cw
     out = torch.empty((D, H, W, Cout), dtype=torch.float32 if out_f32 else torch.bfloat16, device="cuda")
-    wpack = torch.empty(27 * Ci * Cw * 2, dtype=torch.uint8, device="cuda")
+    wpack = torch.empty(28 * Ci * Cw * 2, dtype=torch.uint8, device="cuda")
     st = lib().cl_nn_conv3(_ptr(x_bf16), _ptr(w), _ptr(b) if b is not None else None, _ptr(out), int(out_f32),
                            D, H, W, Ci, Cw, int(act), float(slope), int(transpose), _ptr(wpack),
                            ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))

@@ -23,8 +23,9 @@ namespace clh {
 
 namespace {
 
-typedef short s4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 constexpr int TPB = 256;
 
@@ -38,232 +39,420 @@ __device__ __forceinline__ unsigned short f2bf(float f)
 }
 
 // --- weight packing -------------------------------------------------------
-// w: FP32 [27][Ci][Co].  Forward packing (flip = 0): K = Ci, N = Co,
-//   out[((t * KC + kc) * NT + nt) * 64 + l][j] = w[t][kc*16 + 4(l/16) + j][nt*16 + l%16]
-// Backward-data packing (flip = 1): K = Co, N = Ci, tap 26 - t,
-//   out[...] = w[26 - t][nt*16 + l%16][kc*16 + 4(l/16) + j]
+// The 3x3x3 convolutions are implicit GEMMs on v_mfma_f32_16x16x32_bf16:
+// M = 16 voxels, N = 16 output channels, K = 32 = two taps x 16 input
+// channels.  Lane l supplies row/column l % 16 of A/B and the 8 K values
+// (l / 16, j): tap 2 tp + (l / 32), channel 8 ((l / 16) % 2) + j of the
+// 16-channel chunk.  The same (lane, j) -> K assignment is used for both
+// operands, so the product is the K sum whatever order the hardware takes
+// the K values in.  27 taps are padded to 14 tap pairs with a zero tap.
+// Forward packing (flip = 0): K = Ci, N = Co,
+//   out[(((kc * 14 + tp) * NT + nt) * 64 + l) * 8 + j] = w[tap][kc*16 + c][nt*16 + l%16]
+// Backward-data packing (flip = 1): K = Co, N = Ci, tap 26 - tap,
+//   out[...] = w[26 - tap][nt*16 + l%16][kc*16 + c]
+// with tap = 2 tp + l / 32, c = 8 ((l / 16) % 2) + j; zero for tap 27.
+constexpr int NTP = 14;   // tap pairs
+
 __global__ __launch_bounds__(TPB) void k_pack_w(const float *__restrict__ w, unsigned short *__restrict__ out, int Ci,
                                                int Co, int flip)
 {
     const int K = flip ? Co : Ci, Nn = flip ? Ci : Co;
     const int KC = K / 16, NT = Nn / 16;
-    const int total = 27 * K * Nn;
+    const int total = KC * NTP * NT * 512;
     const int e = blockIdx.x * TPB + threadIdx.x;
     if (e >= total) return;
-    const int j = e & 3, l = (e >> 2) & 63;
-    int r = e >> 8;                  // ((t * KC + kc) * NT + nt)
+    const int j = e & 7, l = (e >> 3) & 63;
+    int r = e >> 9;                  // (kc * NTP + tp) * NT + nt
     const int nt = r % NT;
     r /= NT;
-    const int kc = r % KC, t = r / KC;
-    const int k = kc * 16 + 4 * (l >> 4) + j, n = nt * 16 + (l & 15);
-    float val;
-    if (!flip) val = w[((size_t)t * Ci + k) * Co + n];
-    else val = w[((size_t)(26 - t) * Ci + n) * Co + k];
+    const int tp = r % NTP, kc = r / NTP;
+    const int tap = 2 * tp + (l >> 5);
+    const int k = kc * 16 + 8 * ((l >> 4) & 1) + j, n = nt * 16 + (l & 15);
+    float val = 0.f;
+    if (tap < 27) {
+        if (!flip) val = w[((size_t)tap * Ci + k) * Co + n];
+        else val = w[((size_t)(26 - tap) * Ci + n) * Co + k];
+    }
     out[e] = f2bf(val);
 }
 
-// --- 3x3x3 convolution (zero padding), MFMA implicit GEMM ----------------
+// Workgroups are dealt to the 8 XCDs round robin; renumber them so that
+// consecutive logical tiles (which share input halos) run on one XCD and
+// share its L2.
+__device__ __forceinline__ int xcd_tile(int b, int n) { return (n & 7) ? b : (b & 7) * (n >> 3) + (b >> 3); }
+
+__device__ __forceinline__ bf8 as_bf8(u4 v) { return __builtin_bit_cast(bf8, v); }
+
+// --- 3x3x3 convolution (zero padding), LDS-staged MFMA implicit GEMM -------
 // in: BF16 [D][H][W][Ci]; wp: packed (K = Ci); bias FP32 [Co] or NULL;
 // act: 0 none, 1 LeakyReLU(slope).  out: BF16 or FP32 [D][H][W][Co].
-template <int NT, typename To>
-__global__ __launch_bounds__(TPB) void k_conv3(const unsigned short *__restrict__ in, const s4 *__restrict__ wp,
+// A workgroup (4 wavefronts) owns a 16 (x) x 4 (y) x MT (z) output brick;
+// wavefront w owns the MT x-runs at y = y0 + w and all Co channels (NT
+// tiles).  Per 16-channel input chunk the 18 x 6 x (MT + 2) input halo is
+// staged in LDS once (two planes of 8 channels, so 16 lanes read 256
+// contiguous bytes) and serves all 27 taps; B fragments stream from the
+// packed weights (L2-resident).
+template <int MT, int NT, typename To>
+__global__ __launch_bounds__(TPB) void k_conv3(const unsigned short *__restrict__ in, const u4 *__restrict__ wp,
                                                const float *__restrict__ bias, To *__restrict__ out, int D, int H,
-                                               int W, int Ci, int act, float slope)
+                                               int W, int Ci, int act, float slope, int nbx, int nby, int nblk)
 {
-    const int l = threadIdx.x & 63;
-    const int wave = blockIdx.x * (TPB / 64) + (threadIdx.x >> 6);
-    const int WB = (W + 15) >> 4;            // x blocks of 16 (the last may be partial)
-    if (wave >= D * H * WB) return;           // whole wavefront exits together
-    const int x0 = (wave % WB) << 4, y = (wave / WB) % H, z = wave / (WB * H);
+    constexpr int XS = 18, YS = 6, ZS = MT + 2, NV = XS * YS * ZS;
+    __shared__ u4 tile[2 * NV];
+    int b = xcd_tile(blockIdx.x, nblk);
+    const int bx = b % nbx;
+    b /= nbx;
+    const int by = b % nby, bz = b / nby;
+    const int x0 = bx * 16, y0 = by * 4, z0 = bz * MT;
+    const int tid = threadIdx.x, l = tid & 63, wv = tid >> 6;
+    const int m = l & 15, half = (l >> 4) & 1, tsel = l >> 5;
     const int KC = Ci >> 4;
-    const int Co = NT * 16;
-    f4 acc[NT];
+    f4 acc[MT][NT];
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) acc[nt] = f4{0.f, 0.f, 0.f, 0.f};
-    const int xi = x0 + (l & 15), kq = 4 * (l >> 4);
-    for (int t = 0; t < 27; ++t) {
-        const int zz = z + t / 9 - 1, yy = y + (t / 3) % 3 - 1, xx = xi + t % 3 - 1;
-        if (zz < 0 || zz >= D || yy < 0 || yy >= H) continue;   // uniform per wave
-        const bool ok = xx >= 0 && xx < W;
-        const unsigned short *src = in + (((size_t)zz * H + yy) * W + (ok ? xx : 0)) * Ci + kq;
-        const s4 *wt = wp + (size_t)t * KC * NT * 64 + l;
-        for (int kc = 0; kc < KC; ++kc) {
-            s4 a = ok ? *(const s4 *)(src + kc * 16) : s4{0, 0, 0, 0};
+    for (int i = 0; i < MT; ++i)
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt)
-                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, wt[(kc * NT + nt) * 64], acc[nt], 0, 0, 0);
+        for (int nt = 0; nt < NT; ++nt) acc[i][nt] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int kc = 0; kc < KC; ++kc) {
+        if (kc) __syncthreads();
+        for (int q = tid; q < 2 * NV; q += TPB) {
+            const int hq = q & 1, v = q >> 1;
+            const int xt = v % XS, r = v / XS;
+            const int yt = r % YS, zt = r / YS;
+            const int x = x0 - 1 + xt, y = y0 - 1 + yt, z = z0 - 1 + zt;
+            u4 val = u4{0u, 0u, 0u, 0u};
+            if (x >= 0 && x < W && y >= 0 && y < H && z >= 0 && z < D)
+                val = *(const u4 *)(in + (((size_t)z * H + y) * W + x) * Ci + kc * 16 + hq * 8);
+            tile[hq * NV + v] = val;
+        }
+        __syncthreads();
+        const u4 *wk = wp + (size_t)kc * NTP * NT * 64 + l;
+        for (int tp = 0; tp < NTP; ++tp) {
+            const int tap = 2 * tp + tsel;
+            const int tt = tap < 27 ? tap : 13;
+            const int dz = tt / 9, dy = (tt / 3) % 3, dx = tt % 3;
+            const int base = half * NV + (dz * YS + wv + dy) * XS + m + dx;
+            bf8 a[MT];
+#pragma unroll
+            for (int i = 0; i < MT; ++i) {
+                u4 raw = tile[base + i * (YS * XS)];
+                if (tap >= 27) raw = u4{0u, 0u, 0u, 0u};
+                a[i] = as_bf8(raw);
+            }
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                const bf8 bw = as_bf8(wk[(tp * NT + nt) * 64]);
+#pragma unroll
+                for (int i = 0; i < MT; ++i)
+                    acc[i][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bw, acc[i][nt], 0, 0, 0);
+            }
         }
     }
-    const int n = l & 15;
+    // D[m][n]: n = l % 16 (channel), m = 4 (l / 16) + j (voxel along x)
+    const int Co = NT * 16, n = l & 15, xq = x0 + 4 * (l >> 4), y = y0 + wv;
+    if (y >= H) return;
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-        const int co = nt * 16 + n;
-        const float b = bias ? bias[co] : 0.f;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int x = x0 + kq + j;
-            if (x >= W) continue;
-            float v = acc[nt][j] + b;
-            if (act) v = v > 0.f ? v : slope * v;
-            const size_t o = (((size_t)z * H + y) * W + x) * Co + co;
-            if constexpr (sizeof(To) == 2) out[o] = f2bf(v);
-            else out[o] = v;
-        }
-    }
-}
-
-// --- weight gradient: partial[chunk][t][Ci][Co] = sum over the chunk's
-// voxels p of X[p + t - 1][i] dZ[p][o].  One wavefront per (chunk, tap,
-// 16-input-channel tile); K = voxels, 16 consecutive x per MFMA.
-template <int NT>
-__global__ __launch_bounds__(64) void k_conv3_dw(const unsigned short *__restrict__ X, const unsigned short *__restrict__ dZ,
-                                                 float *__restrict__ partial, int D, int H, int W, int Ci,
-                                                 int rows_per_chunk)
-{
-    const int l = threadIdx.x;
-    const int KC = Ci >> 4, Co = NT * 16;
-    const int t = blockIdx.x % 27;
-    const int kc = (blockIdx.x / 27) % KC;
-    const int chunk = blockIdx.x / (27 * KC);
-    const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
-    const int WB = (W + 15) >> 4;
-    const int nrows = D * H * WB;
-    f4 acc[NT];
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt) acc[nt] = f4{0.f, 0.f, 0.f, 0.f};
-    const int i = kc * 16 + (l & 15), kq = 4 * (l >> 4);
-    const int r0 = chunk * rows_per_chunk, r1 = min(nrows, r0 + rows_per_chunk);
-    for (int r = r0; r < r1; ++r) {
-        const int x0 = (r % WB) << 4, y = (r / WB) % H, z = r / (WB * H);
-        const int zz = z + dz, yy = y + dy;
-        const bool zy_ok = zz >= 0 && zz < D && yy >= 0 && yy < H;
-        s4 a;
-        const unsigned short *xrow = X + (((size_t)(zy_ok ? zz : 0) * H + (zy_ok ? yy : 0)) * W) * Ci + i;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int xx = x0 + kq + j + dx;
-            a[j] = (zy_ok && xx >= 0 && xx < W && x0 + kq + j < W) ? (short)xrow[(size_t)xx * Ci] : (short)0;
-        }
-        const unsigned short *zrow = dZ + (((size_t)z * H + y) * W + x0 + kq) * Co + (l & 15);
+    for (int i = 0; i < MT; ++i) {
+        const int z = z0 + i;
+        if (z >= D) continue;
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
-            s4 b;
+            const int co = nt * 16 + n;
+            const float bb = bias ? bias[co] : 0.f;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) b[j] = x0 + kq + j < W ? (short)zrow[(size_t)j * Co + nt * 16] : (short)0;
-            acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[nt], 0, 0, 0);
+            for (int j = 0; j < 4; ++j) {
+                const int x = xq + j;
+                if (x >= W) continue;
+                float v = acc[i][nt][j] + bb;
+                if (act) v = v > 0.f ? v : slope * v;
+                const size_t o = (((size_t)z * H + y) * W + x) * Co + co;
+                if constexpr (sizeof(To) == 2) out[o] = f2bf(v);
+                else out[o] = v;
+            }
         }
     }
-    float *dst = partial + ((size_t)chunk * 27 + t) * Ci * Co;
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) dst[(size_t)(kc * 16 + kq + j) * Co + nt * 16 + (l & 15)] = acc[nt][j];
 }
 
-// out[e] = sum_c partial[c][e] (fixed order)
-__global__ __launch_bounds__(TPB) void k_sum_partials(const float *__restrict__ partial, int nchunk, size_t n,
-                                                      float *__restrict__ out)
+// --- weight gradient --------------------------------------------------------
+// part[chunk] = (gw partial [t][Ci][Co], gb partial [Co]): sums over the
+// chunk's voxels p of X[p + t - 1][i] dZ[p][o] and of dZ[p][o].  GEMM with M = 16 input channels
+// (one chunk kc), N = 16 output channels, K = 32 voxels.  A workgroup owns
+// one 16-channel input chunk, NG output tiles and a run of 16 x 4 x 2
+// voxel tiles.  Per tile, X (with a one-voxel halo) is staged in LDS
+// transposed to [channel][z][y][x] in three copies shifted by dx = -1, 0, 1,
+// so each A fragment (8 consecutive x of one channel) is one aligned 16-byte
+// read, and dZ is staged transposed to [channel][row][x]; the dZ fragments
+// are loaded once per tile and serve every tap.  Wavefront w owns the taps
+// t = w (mod 4); the bias sums use an all-ones A operand.
+// K index (lane group g = l / 16, item j): row 2 s + g / 2 of the tile
+// (row = 4 z + y), x = 8 (g % 2) + j, for K step s = 0..3.
+template <int NG>
+__global__ __launch_bounds__(TPB) void k_conv3_dw(const unsigned short *__restrict__ X,
+                                                  const unsigned short *__restrict__ dZ, float *__restrict__ part,
+                                                  int D, int H, int W, int Ci, int Co, int ntx, int nty, int ntiles,
+                                                  int tpc, int ngrp)
 {
-    const size_t e = (size_t)blockIdx.x * TPB + threadIdx.x;
-    if (e >= n) return;
+    constexpr int XR = 4 * 6;                 // staged X rows: z in [z0-1, z0+2], y in [y0-1, y0+4]
+    __shared__ __attribute__((aligned(16))) unsigned short xs[3][16][XR][16];
+    __shared__ __attribute__((aligned(16))) unsigned short zs[NG * 16][8][16];
+    const int tid = threadIdx.x, l = tid & 63, wv = tid >> 6;
+    const int g = l >> 4, ln = l & 15;
+    const int KC = Ci >> 4;
+    int bq = blockIdx.x;
+    const int grp = bq % ngrp;
+    bq /= ngrp;
+    const int kc = bq % KC, chunk = bq / KC;
+    const int co0 = grp * NG * 16;
+    const int t0 = chunk * tpc, t1 = min(ntiles, t0 + tpc);
+    f4 acc[7][NG], accb[NG];
+#pragma unroll
+    for (int i = 0; i < 7; ++i)
+#pragma unroll
+        for (int nt = 0; nt < NG; ++nt) acc[i][nt] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int nt = 0; nt < NG; ++nt) accb[nt] = f4{0.f, 0.f, 0.f, 0.f};
+    const bool do_bias = kc == 0 && wv == 3;
+    for (int tI = t0; tI < t1; ++tI) {
+        const int tx = tI % ntx, ty = (tI / ntx) % nty, tz = tI / (ntx * nty);
+        const int x0 = tx * 16, y0 = ty * 4, z0 = tz * 2;
+        __syncthreads();
+        // X halo: 18 x 6 x 4 voxels x 16 channels, two 8-channel halves each
+        for (int q = tid; q < 18 * XR * 2; q += TPB) {
+            const int hq = q & 1, v = q >> 1;
+            const int xt = v % 18, r = v / 18;      // r = zt * 6 + yt
+            const int yt = r % 6, zt = r / 6;
+            const int x = x0 - 1 + xt, y = y0 - 1 + yt, z = z0 - 1 + zt;
+            u4 val = u4{0u, 0u, 0u, 0u};
+            if (x >= 0 && x < W && y >= 0 && y < H && z >= 0 && z < D)
+                val = *(const u4 *)(X + (((size_t)z * H + y) * W + x) * Ci + kc * 16 + hq * 8);
+            const unsigned short *e = (const unsigned short *)&val;
+#pragma unroll
+            for (int sx = 0; sx < 3; ++sx) {
+                const int xc = xt - sx;             // copy sx holds X[x0 + xc + sx - 1]
+                if (xc < 0 || xc >= 16) continue;
+#pragma unroll
+                for (int c = 0; c < 8; ++c) xs[sx][hq * 8 + c][r][xc] = e[c];
+            }
+        }
+        // dZ tile: 16 x 4 x 2 voxels x NG * 16 channels
+        for (int q = tid; q < 128 * NG * 2; q += TPB) {
+            const int hq = q % (NG * 2), v = q / (NG * 2);
+            const int xt = v & 15, r = v >> 4;      // r = zl * 4 + yl
+            const int x = x0 + xt, y = y0 + (r & 3), z = z0 + (r >> 2);
+            u4 val = u4{0u, 0u, 0u, 0u};
+            if (x < W && y < H && z < D)
+                val = *(const u4 *)(dZ + (((size_t)z * H + y) * W + x) * Co + co0 + hq * 8);
+            const unsigned short *e = (const unsigned short *)&val;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) zs[hq * 8 + c][r][xt] = e[c];
+        }
+        __syncthreads();
+        bf8 bz[NG][4];
+#pragma unroll
+        for (int nt = 0; nt < NG; ++nt)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) bz[nt][s] = as_bf8(*(const u4 *)&zs[nt * 16 + ln][2 * s + (g >> 1)][8 * (g & 1)]);
+#pragma unroll
+        for (int ti = 0; ti < 7; ++ti) {
+            const int t = wv + 4 * ti;
+            if (t >= 27) break;
+            const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int row = 2 * s + (g >> 1);               // 4 zl + yl
+                const int r = ((row >> 2) + dz) * 6 + (row & 3) + dy;
+                const bf8 a = as_bf8(*(const u4 *)&xs[dx][ln][r][8 * (g & 1)]);
+#pragma unroll
+                for (int nt = 0; nt < NG; ++nt)
+                    acc[ti][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bz[nt][s], acc[ti][nt], 0, 0, 0);
+            }
+        }
+        if (do_bias) {
+            const u4 ones4 = u4{0x3f803f80u, 0x3f803f80u, 0x3f803f80u, 0x3f803f80u};
+            const bf8 ones = as_bf8(ones4);
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int nt = 0; nt < NG; ++nt)
+                    accb[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ones, bz[nt][s], accb[nt], 0, 0, 0);
+        }
+    }
+    // D[m][n]: m = 4 g + j (input channel), n = ln (output channel)
+#pragma unroll
+    for (int ti = 0; ti < 7; ++ti) {
+        const int t = wv + 4 * ti;
+        if (t >= 27) break;
+        float *dst = part + (size_t)chunk * (27 * Ci * Co + Co) + (size_t)t * Ci * Co;
+#pragma unroll
+        for (int nt = 0; nt < NG; ++nt)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                dst[(size_t)(kc * 16 + 4 * g + j) * Co + co0 + nt * 16 + ln] = acc[ti][nt][j];
+    }
+    if (do_bias && g == 0) {
+#pragma unroll
+        for (int nt = 0; nt < NG; ++nt) part[(size_t)chunk * (27 * Ci * Co + Co) + 27 * Ci * Co + co0 + nt * 16 + ln] = accb[nt][0];
+    }
+}
+
+// Fixed-order sum of the chunk partials: row c of partial holds nw weight
+// values then nb bias values (row stride nw + nb).  A workgroup owns 64
+// consecutive outputs; wave w sums the chunks c = w (mod 4) in order, then
+// the four wave sums are added in order.
+__global__ __launch_bounds__(TPB) void k_sum_partials(const float *__restrict__ partial, int nchunk, int nw, int nb,
+                                                      float *__restrict__ gw, float *__restrict__ gb)
+{
+    __shared__ float red[TPB / 64][64];
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int e = blockIdx.x * 64 + l;
+    const int rs = nw + nb;
     float s = 0.f;
-    for (int c = 0; c < nchunk; ++c) s += partial[(size_t)c * n + e];
-    out[e] = s;
+    if (e < rs)
+        for (int c = w; c < nchunk; c += TPB / 64) s += partial[(size_t)c * rs + e];
+    red[w][l] = s;
+    __syncthreads();
+    if (w == 0 && e < rs) {
+        const float t = ((red[0][l] + red[1][l]) + red[2][l]) + red[3][l];
+        if (e < nw) gw[e] = t;
+        else if (gb) gb[e - nw] = t;
+    }
 }
 
-// gb[o] = sum_p dZ[p][o]; one workgroup per output channel, fixed order
-__global__ __launch_bounds__(TPB) void k_bias_grad(const unsigned short *__restrict__ dZ, size_t P, int C,
-                                                   float *__restrict__ gb)
+// Elementwise layers on channels-last BF16 tensors work on 8-channel
+// groups (one 16-byte load per tensor and thread); channel counts are
+// multiples of 16, so a group never straddles two voxels.
+__device__ __forceinline__ void unpack8(u4 v, float (&f)[8])
 {
-    const int o = blockIdx.x;
-    double s = 0.0;
-    for (size_t p = threadIdx.x; p < P; p += TPB) s += bf2f(dZ[p * C + o]);
-    s = block_sum(s);
-    if (threadIdx.x == 0) gb[o] = (float)s;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        f[2 * i] = __uint_as_float(v[i] << 16);
+        f[2 * i + 1] = __uint_as_float(v[i] & 0xffff0000u);
+    }
+}
+__device__ __forceinline__ u4 pack8(const float (&f)[8])
+{
+    u4 v;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[i] = (unsigned)f2bf(f[2 * i]) | ((unsigned)f2bf(f[2 * i + 1]) << 16);
+    return v;
 }
 
 // dZ = dY * (Y > 0 ? 1 : slope)   (LeakyReLU backward from the output sign)
-__global__ __launch_bounds__(TPB) void k_lrelu_bwd(const unsigned short *__restrict__ dY,
-                                                   const unsigned short *__restrict__ Y, float slope, size_t n,
-                                                   unsigned short *__restrict__ dZ)
+__global__ __launch_bounds__(TPB) void k_lrelu_bwd(const u4 *__restrict__ dY, const u4 *__restrict__ Y, float slope,
+                                                   size_t n8, u4 *__restrict__ dZ)
 {
     const size_t e = (size_t)blockIdx.x * TPB + threadIdx.x;
-    if (e >= n) return;
-    const float g = bf2f(dY[e]);
-    dZ[e] = f2bf(bf2f(Y[e]) > 0.f ? g : slope * g);
+    if (e >= n8) return;
+    float g[8], y[8];
+    unpack8(dY[e], g);
+    unpack8(Y[e], y);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) g[i] = y[i] > 0.f ? g[i] : slope * g[i];
+    dZ[e] = pack8(g);
 }
 
 // 2x2x2 average pooling, channels-last (D, H, W of the input)
-__global__ __launch_bounds__(TPB) void k_pool2(const unsigned short *__restrict__ in, unsigned short *__restrict__ out,
-                                               int D, int H, int W, int C)
+__global__ __launch_bounds__(TPB) void k_pool2(const u4 *__restrict__ in, u4 *__restrict__ out, int D, int H, int W,
+                                               int C)
 {
-    const int d = D / 2, h = H / 2, w = W / 2;
+    const int d = D / 2, h = H / 2, w = W / 2, C8 = C / 8;
     const size_t e = (size_t)blockIdx.x * TPB + threadIdx.x;
-    if (e >= (size_t)d * h * w * C) return;
-    const int c = e % C;
-    size_t v = e / C;
+    if (e >= (size_t)d * h * w * C8) return;
+    const int c = e % C8;
+    const size_t v = e / C8;
     const int x = v % w, y = (v / w) % h, z = v / ((size_t)w * h);
-    float s = 0.f;
+    float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b)
-            for (int q = 0; q < 2; ++q) s += bf2f(in[((((size_t)(2 * z + a)) * H + 2 * y + b) * W + 2 * x + q) * C + c]);
-    out[e] = f2bf(0.125f * s);
+            for (int q = 0; q < 2; ++q) {
+                float f[8];
+                unpack8(in[((((size_t)(2 * z + a)) * H + 2 * y + b) * W + 2 * x + q) * C8 + c], f);
+#pragma unroll
+                for (int i = 0; i < 8; ++i) s[i] += f[i];
+            }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) s[i] *= 0.125f;
+    out[e] = pack8(s);
 }
 
 // backward of pool2: gin[fine] (+)= gout[coarse] / 8
-__global__ __launch_bounds__(TPB) void k_pool2_bwd(const unsigned short *__restrict__ gout, unsigned short *__restrict__ gin,
-                                                   int D, int H, int W, int C, int accumulate)
+__global__ __launch_bounds__(TPB) void k_pool2_bwd(const u4 *__restrict__ gout, u4 *__restrict__ gin, int D, int H,
+                                                   int W, int C, int accumulate)
 {
+    const int C8 = C / 8;
     const size_t e = (size_t)blockIdx.x * TPB + threadIdx.x;
-    if (e >= (size_t)D * H * W * C) return;
-    const int c = e % C;
-    size_t v = e / C;
+    if (e >= (size_t)D * H * W * C8) return;
+    const int c = e % C8;
+    const size_t v = e / C8;
     const int x = v % W, y = (v / W) % H, z = v / ((size_t)W * H);
-    const float g = 0.125f * bf2f(gout[((((size_t)z / 2) * (H / 2) + y / 2) * (W / 2) + x / 2) * C + c]);
-    gin[e] = f2bf(accumulate ? bf2f(gin[e]) + g : g);
+    float g[8];
+    unpack8(gout[((((size_t)z / 2) * (H / 2) + y / 2) * (W / 2) + x / 2) * C8 + c], g);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) g[i] *= 0.125f;
+    if (accumulate) {
+        float f[8];
+        unpack8(gin[e], f);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) g[i] = f[i] + g[i];
+    }
+    gin[e] = pack8(g);
 }
 
 // out[p][0:Ca] = a[p / 2], out[p][Ca:Ca+Cb] = b[p]  (D, H, W fine)
-__global__ __launch_bounds__(TPB) void k_up2cat(const unsigned short *__restrict__ a, const unsigned short *__restrict__ b,
-                                                unsigned short *__restrict__ out, int D, int H, int W, int Ca, int Cb)
+__global__ __launch_bounds__(TPB) void k_up2cat(const u4 *__restrict__ a, const u4 *__restrict__ b, u4 *__restrict__ out,
+                                                int D, int H, int W, int Ca, int Cb)
 {
-    const int C = Ca + Cb;
+    const int A8 = Ca / 8, B8 = Cb / 8, C8 = A8 + B8;
     const size_t e = (size_t)blockIdx.x * TPB + threadIdx.x;
-    if (e >= (size_t)D * H * W * C) return;
-    const int c = e % C;
-    size_t v = e / C;
+    if (e >= (size_t)D * H * W * C8) return;
+    const int c = e % C8;
+    const size_t v = e / C8;
     const int x = v % W, y = (v / W) % H, z = v / ((size_t)W * H);
-    if (c < Ca) out[e] = a[((((size_t)z / 2) * (H / 2) + y / 2) * (W / 2) + x / 2) * Ca + c];
-    else out[e] = b[v * Cb + (c - Ca)];
+    if (c < A8) out[e] = a[((((size_t)z / 2) * (H / 2) + y / 2) * (W / 2) + x / 2) * A8 + c];
+    else out[e] = b[v * B8 + (c - A8)];
 }
 
 // backward of up2cat: ga[coarse] = sum of the 8 children's first Ca
 // channels; gb[fine] (+)= last Cb channels
-__global__ __launch_bounds__(TPB) void k_up2cat_bwd_a(const unsigned short *__restrict__ g, unsigned short *__restrict__ ga,
-                                                      int D, int H, int W, int Ca, int Cb)
+__global__ __launch_bounds__(TPB) void k_up2cat_bwd_a(const u4 *__restrict__ g, u4 *__restrict__ ga, int D, int H, int W,
+                                                      int Ca, int Cb)
 {
-    const int C = Ca + Cb, d = D / 2, h = H / 2, w = W / 2;
+    const int A8 = Ca / 8, C8 = (Ca + Cb) / 8, d = D / 2, h = H / 2, w = W / 2;
     const size_t e = (size_t)blockIdx.x * TPB + threadIdx.x;
-    if (e >= (size_t)d * h * w * Ca) return;
-    const int c = e % Ca;
-    size_t v = e / Ca;
+    if (e >= (size_t)d * h * w * A8) return;
+    const int c = e % A8;
+    const size_t v = e / A8;
     const int x = v % w, y = (v / w) % h, z = v / ((size_t)w * h);
-    float s = 0.f;
+    float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b)
-            for (int q = 0; q < 2; ++q) s += bf2f(g[((((size_t)(2 * z + a)) * H + 2 * y + b) * W + 2 * x + q) * C + c]);
-    ga[e] = f2bf(s);
+            for (int q = 0; q < 2; ++q) {
+                float f[8];
+                unpack8(g[((((size_t)(2 * z + a)) * H + 2 * y + b) * W + 2 * x + q) * C8 + c], f);
+#pragma unroll
+                for (int i = 0; i < 8; ++i) s[i] += f[i];
+            }
+    ga[e] = pack8(s);
 }
 
-__global__ __launch_bounds__(TPB) void k_up2cat_bwd_b(const unsigned short *__restrict__ g, unsigned short *__restrict__ gb,
-                                                      size_t P, int Ca, int Cb, int accumulate)
+__global__ __launch_bounds__(TPB) void k_up2cat_bwd_b(const u4 *__restrict__ g, u4 *__restrict__ gb, size_t P, int Ca,
+                                                      int Cb, int accumulate)
 {
+    const int A8 = Ca / 8, B8 = Cb / 8;
     const size_t e = (size_t)blockIdx.x * TPB + threadIdx.x;
-    if (e >= P * Cb) return;
-    const size_t p = e / Cb;
-    const int c = e % Cb;
-    const float v = bf2f(g[p * (Ca + Cb) + Ca + c]);
-    gb[e] = f2bf(accumulate ? bf2f(gb[e]) + v : v);
+    if (e >= P * B8) return;
+    const size_t p = e / B8;
+    const int c = e % B8;
+    const u4 v = g[p * (A8 + B8) + A8 + c];
+    if (!accumulate) {
+        gb[e] = v;
+        return;
+    }
+    float f[8], h[8];
+    unpack8(v, f);
+    unpack8(gb[e], h);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) h[i] = h[i] + f[i];
+    gb[e] = pack8(h);
 }
 
 // head: 1x1x1 convolution Ci -> 3, FP32 output as SoA [3][P]
@@ -273,11 +462,17 @@ __global__ __launch_bounds__(TPB) void k_head(const unsigned short *__restrict__
     const size_t p = (size_t)blockIdx.x * TPB + threadIdx.x;
     if (p >= P) return;
     float s0 = b[0], s1 = b[1], s2 = b[2];
-    for (int i = 0; i < Ci; ++i) {
-        const float x = bf2f(in[p * Ci + i]);
-        s0 = fmaf(w[i * 3 + 0], x, s0);
-        s1 = fmaf(w[i * 3 + 1], x, s1);
-        s2 = fmaf(w[i * 3 + 2], x, s2);
+    const u4 *src = (const u4 *)(in + p * Ci);
+    for (int i8 = 0; i8 < Ci / 8; ++i8) {
+        float x[8];
+        unpack8(src[i8], x);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = i8 * 8 + u;
+            s0 = fmaf(w[i * 3 + 0], x[u], s0);
+            s1 = fmaf(w[i * 3 + 1], x[u], s1);
+            s2 = fmaf(w[i * 3 + 2], x[u], s2);
+        }
     }
     out[p] = s0;
     out[P + p] = s1;
@@ -296,20 +491,49 @@ __global__ __launch_bounds__(TPB) void k_head_bwd_x(const float *__restrict__ go
     gin[e] = f2bf(g);
 }
 
-// head weight gradient: per workgroup partial sums over voxels, then a
-// second pass; out[(i * 3 + o)] for i < Ci, then 3 bias entries
-__global__ __launch_bounds__(TPB) void k_head_bwd_w(const unsigned short *__restrict__ in, const float *__restrict__ gout,
-                                                    size_t P, int Ci, int comp, double *__restrict__ partials)
+// head weight gradient: every workgroup sums, over its voxels, the 16 x 3
+// products in[p][i] gout[o][p] and the 3 bias terms gout[o][p] (FP64), then
+// writes them as partials[c][block], c = i * 3 + o (bias: 48 + o)
+constexpr int HEAD_CI = 16, HEAD_NC = HEAD_CI * 3 + 3;
+
+__global__ __launch_bounds__(TPB) void k_head_bwd_w(const unsigned short *__restrict__ in,
+                                                    const float *__restrict__ gout, size_t P,
+                                                    double *__restrict__ partials)
 {
-    // comp = i * 3 + o for weights, Ci * 3 + o for the bias
-    const int i = comp / 3, o = comp % 3;
-    double s = 0.0;
+    double acc[HEAD_NC];
+#pragma unroll
+    for (int c = 0; c < HEAD_NC; ++c) acc[c] = 0.0;
     for (size_t p = (size_t)blockIdx.x * TPB + threadIdx.x; p < P; p += (size_t)gridDim.x * TPB) {
-        const float x = i < Ci ? bf2f(in[p * Ci + i]) : 1.0f;
-        s += (double)x * gout[o * P + p];
+        const float g0 = gout[p], g1 = gout[P + p], g2 = gout[2 * P + p];
+        const u4 lo = *(const u4 *)(in + p * HEAD_CI), hi = *(const u4 *)(in + p * HEAD_CI + 8);
+        const unsigned short *e0 = (const unsigned short *)&lo, *e1 = (const unsigned short *)&hi;
+#pragma unroll
+        for (int i = 0; i < HEAD_CI; ++i) {
+            const double x = bf2f(i < 8 ? e0[i] : e1[i - 8]);
+            acc[i * 3 + 0] += x * g0;
+            acc[i * 3 + 1] += x * g1;
+            acc[i * 3 + 2] += x * g2;
+        }
+        acc[48] += g0;
+        acc[49] += g1;
+        acc[50] += g2;
     }
-    s = block_sum(s);
-    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+#pragma unroll
+    for (int c = 0; c < HEAD_NC; ++c) {
+        const double v = block_sum(acc[c]);
+        if (threadIdx.x == 0) partials[(size_t)c * gridDim.x + blockIdx.x] = v;
+    }
+}
+
+// out[c] = sum_b partials[c][b] in a fixed order, one workgroup per c
+__global__ __launch_bounds__(TPB) void k_finalize_rows(const double *__restrict__ partials, int nb,
+                                                       double *__restrict__ out)
+{
+    const double *row = partials + (size_t)blockIdx.x * nb;
+    double acc = 0.0;
+    for (int q = threadIdx.x; q < nb; q += TPB) acc += row[q];
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) out[blockIdx.x] = acc;
 }
 
 // loss = 0.5 / P sum (pred - label)^2 over 3 components; grad = (pred - label) / P
@@ -343,39 +567,48 @@ __global__ __launch_bounds__(TPB) void k_adam(float *__restrict__ p, const float
 
 // two FP32 scalar fields [P] -> BF16 channels-last [P][16] (channels 2..15 zero)
 __global__ __launch_bounds__(TPB) void k_pack_input(const float *__restrict__ a, const float *__restrict__ b,
-                                                    unsigned short *__restrict__ out, size_t P)
+                                                    u4 *__restrict__ out, size_t P)
 {
-    const size_t e = (size_t)blockIdx.x * TPB + threadIdx.x;
-    if (e >= P * 16) return;
-    const size_t p = e >> 4;
-    const int c = e & 15;
-    out[e] = c == 0 ? f2bf(a[p]) : c == 1 ? f2bf(b[p]) : (unsigned short)0;
+    const size_t p = (size_t)blockIdx.x * TPB + threadIdx.x;
+    if (p >= P) return;
+    out[2 * p] = u4{(unsigned)f2bf(a[p]) | ((unsigned)f2bf(b[p]) << 16), 0u, 0u, 0u};
+    out[2 * p + 1] = u4{0u, 0u, 0u, 0u};
 }
 
 inline unsigned nblk(size_t n) { return (unsigned)((n + TPB - 1) / TPB); }
 
 } // namespace
 
+size_t nn_packed_weight_elems(int Ci, int Co) { return (size_t)NTP * 2 * Ci * Co; }
+
 void nn_pack_weights(const float *w, unsigned short *out, int Ci, int Co, int flip, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_pack_w, dim3(nblk((size_t)27 * Ci * Co)), dim3(TPB), 0, s, w, out, Ci, Co, flip);
+    hipLaunchKernelGGL(k_pack_w, dim3(nblk(nn_packed_weight_elems(Ci, Co))), dim3(TPB), 0, s, w, out, Ci, Co, flip);
 }
 
+template <int MT, int NT, typename To>
+static void conv3_launch(const unsigned short *in, const void *wp, const float *bias, To *out, int D, int H, int W,
+                         int Ci, int act, float slope, hipStream_t s)
+{
+    const int nbx = (W + 15) / 16, nby = (H + 3) / 4, nbz = (D + MT - 1) / MT;
+    const int nb = nbx * nby * nbz;
+    hipLaunchKernelGGL((k_conv3<MT, NT, To>), dim3(nb), dim3(TPB), 0, s, in, (const u4 *)wp, bias, out, D, H, W, Ci,
+                       act, slope, nbx, nby, nb);
+}
+
+// output rows per wavefront (MT) chosen so that MT * NT accumulator tiles stay near 16
 template <typename To>
 static void conv3_dispatch(const unsigned short *in, const void *wp, const float *bias, To *out, int D, int H, int W,
                            int Ci, int Co, int act, float slope, hipStream_t s)
 {
-    const int waves = D * H * ((W + 15) / 16);
-    const dim3 grid((waves + 3) / 4), block(TPB);
-    const s4 *w = (const s4 *)wp;
     switch (Co / 16) {
-    case 1: hipLaunchKernelGGL((k_conv3<1, To>), grid, block, 0, s, in, w, bias, out, D, H, W, Ci, act, slope); break;
-    case 2: hipLaunchKernelGGL((k_conv3<2, To>), grid, block, 0, s, in, w, bias, out, D, H, W, Ci, act, slope); break;
-    case 3: hipLaunchKernelGGL((k_conv3<3, To>), grid, block, 0, s, in, w, bias, out, D, H, W, Ci, act, slope); break;
-    case 4: hipLaunchKernelGGL((k_conv3<4, To>), grid, block, 0, s, in, w, bias, out, D, H, W, Ci, act, slope); break;
-    case 6: hipLaunchKernelGGL((k_conv3<6, To>), grid, block, 0, s, in, w, bias, out, D, H, W, Ci, act, slope); break;
-    case 8: hipLaunchKernelGGL((k_conv3<8, To>), grid, block, 0, s, in, w, bias, out, D, H, W, Ci, act, slope); break;
-    case 12: hipLaunchKernelGGL((k_conv3<12, To>), grid, block, 0, s, in, w, bias, out, D, H, W, Ci, act, slope); break;
+    case 1: conv3_launch<8, 1, To>(in, wp, bias, out, D, H, W, Ci, act, slope, s); break;
+    case 2: conv3_launch<8, 2, To>(in, wp, bias, out, D, H, W, Ci, act, slope, s); break;
+    case 3: conv3_launch<4, 3, To>(in, wp, bias, out, D, H, W, Ci, act, slope, s); break;
+    case 4: conv3_launch<4, 4, To>(in, wp, bias, out, D, H, W, Ci, act, slope, s); break;
+    case 6: conv3_launch<2, 6, To>(in, wp, bias, out, D, H, W, Ci, act, slope, s); break;
+    case 8: conv3_launch<2, 8, To>(in, wp, bias, out, D, H, W, Ci, act, slope, s); break;
+    case 12: conv3_launch<1, 12, To>(in, wp, bias, out, D, H, W, Ci, act, slope, s); break;
     default: break;
     }
 }
@@ -387,64 +620,90 @@ void nn_conv3(const unsigned short *in, const void *wp, const float *bias, void 
     else conv3_dispatch(in, wp, bias, (unsigned short *)out, D, H, W, Ci, Co, act, slope, s);
 }
 
-int nn_dw_chunks(int D, int H, int W, int *rows_per_chunk)
+// weight-gradient work split: NG output tiles per workgroup, ngrp groups,
+// voxel tiles of 16 x 4 x 2 dealt in runs of tpc to nchunk chunks so that
+// about 1024 workgroups are in flight
+struct DwPlan {
+    int ng, ngrp, ntx, nty, ntiles, tpc, nchunk;
+};
+
+static DwPlan dw_plan(int D, int H, int W, int Ci, int Co)
 {
-    const int nrows = D * H * ((W + 15) / 16);
-    int rpc = 256;
-    if (rpc > nrows) rpc = nrows;
-    *rows_per_chunk = rpc;
-    return (nrows + rpc - 1) / rpc;
+    DwPlan p{};
+    const int nt = Co / 16;
+    p.ng = nt % 4 == 0 ? 4 : nt % 3 == 0 ? 3 : nt;
+    p.ngrp = nt / p.ng;
+    p.ntx = (W + 15) / 16;
+    p.nty = (H + 3) / 4;
+    p.ntiles = p.ntx * p.nty * ((D + 1) / 2);
+    // one resident wave of workgroups: three per CU (one for NG = 4, whose
+    // accumulators take the whole register file)
+    const int per = (Ci / 16) * p.ngrp;
+    const int resident = (p.ng == 4 ? 1 : 3) * 256;
+    int want = (resident + per - 1) / per;
+    if (want > p.ntiles) want = p.ntiles;
+    if (want < 1) want = 1;
+    p.tpc = (p.ntiles + want - 1) / want;
+    p.nchunk = (p.ntiles + p.tpc - 1) / p.tpc;
+    return p;
+}
+
+size_t nn_dw_workspace_floats(int D, int H, int W, int Ci, int Co)
+{
+    const DwPlan p = dw_plan(D, H, W, Ci, Co);
+    return (size_t)p.nchunk * (27 * (size_t)Ci * Co + Co);
 }
 
 void nn_conv3_dw(const unsigned short *X, const unsigned short *dZ, float *partial, float *gw, float *gb, int D, int H,
                  int W, int Ci, int Co, hipStream_t s)
 {
-    int rpc;
-    const int nchunk = nn_dw_chunks(D, H, W, &rpc);
-    const dim3 grid(nchunk * 27 * (Ci / 16)), block(64);
-    switch (Co / 16) {
-    case 1: hipLaunchKernelGGL((k_conv3_dw<1>), grid, block, 0, s, X, dZ, partial, D, H, W, Ci, rpc); break;
-    case 2: hipLaunchKernelGGL((k_conv3_dw<2>), grid, block, 0, s, X, dZ, partial, D, H, W, Ci, rpc); break;
-    case 3: hipLaunchKernelGGL((k_conv3_dw<3>), grid, block, 0, s, X, dZ, partial, D, H, W, Ci, rpc); break;
-    case 4: hipLaunchKernelGGL((k_conv3_dw<4>), grid, block, 0, s, X, dZ, partial, D, H, W, Ci, rpc); break;
-    case 6: hipLaunchKernelGGL((k_conv3_dw<6>), grid, block, 0, s, X, dZ, partial, D, H, W, Ci, rpc); break;
-    case 8: hipLaunchKernelGGL((k_conv3_dw<8>), grid, block, 0, s, X, dZ, partial, D, H, W, Ci, rpc); break;
-    case 12: hipLaunchKernelGGL((k_conv3_dw<12>), grid, block, 0, s, X, dZ, partial, D, H, W, Ci, rpc); break;
+    const DwPlan p = dw_plan(D, H, W, Ci, Co);
+    const dim3 grid(p.nchunk * (Ci / 16) * p.ngrp), block(TPB);
+    switch (p.ng) {
+    case 1: hipLaunchKernelGGL((k_conv3_dw<1>), grid, block, 0, s, X, dZ, partial, D, H, W, Ci, Co, p.ntx, p.nty, p.ntiles, p.tpc, p.ngrp); break;
+    case 2: hipLaunchKernelGGL((k_conv3_dw<2>), grid, block, 0, s, X, dZ, partial, D, H, W, Ci, Co, p.ntx, p.nty, p.ntiles, p.tpc, p.ngrp); break;
+    case 3: hipLaunchKernelGGL((k_conv3_dw<3>), grid, block, 0, s, X, dZ, partial, D, H, W, Ci, Co, p.ntx, p.nty, p.ntiles, p.tpc, p.ngrp); break;
+    case 4: hipLaunchKernelGGL((k_conv3_dw<4>), grid, block, 0, s, X, dZ, partial, D, H, W, Ci, Co, p.ntx, p.nty, p.ntiles, p.tpc, p.ngrp); break;
     default: break;
     }
-    const size_t n = (size_t)27 * Ci * Co;
-    hipLaunchKernelGGL(k_sum_partials, dim3(nblk(n)), dim3(TPB), 0, s, partial, nchunk, n, gw);
-    if (gb) hipLaunchKernelGGL(k_bias_grad, dim3(Co), dim3(TPB), 0, s, dZ, (size_t)D * H * W, Co, gb);
+    const int nw = 27 * Ci * Co;
+    hipLaunchKernelGGL(k_sum_partials, dim3((nw + Co + 63) / 64), dim3(TPB), 0, s, partial, p.nchunk, nw, Co, gw, gb);
 }
 
 void nn_lrelu_bwd(const unsigned short *dY, const unsigned short *Y, float slope, size_t n, unsigned short *dZ,
                   hipStream_t s)
 {
-    hipLaunchKernelGGL(k_lrelu_bwd, dim3(nblk(n)), dim3(TPB), 0, s, dY, Y, slope, n, dZ);
+    hipLaunchKernelGGL(k_lrelu_bwd, dim3(nblk(n / 8)), dim3(TPB), 0, s, (const u4 *)dY, (const u4 *)Y, slope, n / 8,
+                       (u4 *)dZ);
 }
 
 void nn_pool2(const unsigned short *in, unsigned short *out, int D, int H, int W, int C, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_pool2, dim3(nblk((size_t)D * H * W * C / 8)), dim3(TPB), 0, s, in, out, D, H, W, C);
+    hipLaunchKernelGGL(k_pool2, dim3(nblk((size_t)D * H * W * C / 64)), dim3(TPB), 0, s, (const u4 *)in, (u4 *)out, D,
+                       H, W, C);
 }
 
 void nn_pool2_bwd(const unsigned short *gout, unsigned short *gin, int D, int H, int W, int C, int accumulate,
                   hipStream_t s)
 {
-    hipLaunchKernelGGL(k_pool2_bwd, dim3(nblk((size_t)D * H * W * C)), dim3(TPB), 0, s, gout, gin, D, H, W, C, accumulate);
+    hipLaunchKernelGGL(k_pool2_bwd, dim3(nblk((size_t)D * H * W * C / 8)), dim3(TPB), 0, s, (const u4 *)gout, (u4 *)gin,
+                       D, H, W, C, accumulate);
 }
 
 void nn_up2cat(const unsigned short *a, const unsigned short *b, unsigned short *out, int D, int H, int W, int Ca,
                int Cb, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_up2cat, dim3(nblk((size_t)D * H * W * (Ca + Cb))), dim3(TPB), 0, s, a, b, out, D, H, W, Ca, Cb);
+    hipLaunchKernelGGL(k_up2cat, dim3(nblk((size_t)D * H * W * (Ca + Cb) / 8)), dim3(TPB), 0, s, (const u4 *)a,
+                       (const u4 *)b, (u4 *)out, D, H, W, Ca, Cb);
 }
 
 void nn_up2cat_bwd(const unsigned short *g, unsigned short *ga, unsigned short *gb, int D, int H, int W, int Ca, int Cb,
                    int accumulate_b, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_up2cat_bwd_a, dim3(nblk((size_t)D * H * W * Ca / 8)), dim3(TPB), 0, s, g, ga, D, H, W, Ca, Cb);
-    hipLaunchKernelGGL(k_up2cat_bwd_b, dim3(nblk((size_t)D * H * W * Cb)), dim3(TPB), 0, s, g, gb, (size_t)D * H * W,
+    hipLaunchKernelGGL(k_up2cat_bwd_a, dim3(nblk((size_t)D * H * W * Ca / 64)), dim3(TPB), 0, s, (const u4 *)g, (u4 *)ga,
+                       D, H, W, Ca, Cb);
+    hipLaunchKernelGGL(k_up2cat_bwd_b, dim3(nblk((size_t)D * H * W * Cb / 8)), dim3(TPB), 0, s, (const u4 *)g, (u4 *)gb,
+                       (size_t)D * H * W,
                        Ca, Cb, accumulate_b);
 }
 
@@ -457,10 +716,9 @@ void nn_head_bwd(const unsigned short *in, const float *gout, const float *w, un
                  int nparts, double *dst_dev, size_t P, int Ci, hipStream_t s)
 {
     hipLaunchKernelGGL(k_head_bwd_x, dim3(nblk(P * Ci)), dim3(TPB), 0, s, gout, w, gin, P, Ci);
-    for (int comp = 0; comp < 3 * (Ci + 1); ++comp) {
-        hipLaunchKernelGGL(k_head_bwd_w, dim3(nparts), dim3(TPB), 0, s, in, gout, P, Ci, comp, partials);
-        launch_finalize(partials, nparts, 1.0, dst_dev + comp, s);
-    }
+    // partials holds HEAD_NC rows of nparts values
+    hipLaunchKernelGGL(k_head_bwd_w, dim3(nparts), dim3(TPB), 0, s, in, gout, P, partials);
+    hipLaunchKernelGGL(k_finalize_rows, dim3(HEAD_NC), dim3(TPB), 0, s, partials, nparts, dst_dev);
 }
 
 void nn_mse(const float *pred, const float *label, size_t n, float inv, float *grad, double *partials, int nparts,
@@ -477,7 +735,7 @@ void nn_adam(float *p, const float *g, float *m, float *v, size_t n, float lr, f
 
 void nn_pack_input(const float *a, const float *b, unsigned short *out, size_t P, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_pack_input, dim3(nblk(P * 16)), dim3(TPB), 0, s, a, b, out, P);
+    hipLaunchKernelGGL(k_pack_input, dim3(nblk(P)), dim3(TPB), 0, s, a, b, (u4 *)out, P);
 }
 
 } // namespace clh

@@ -27,7 +27,8 @@ namespace clh {
 void nn_pack_weights(const float *w, unsigned short *out, int Ci, int Co, int flip, hipStream_t s);
 void nn_conv3(const unsigned short *in, const void *wp, const float *bias, void *out, int out_f32, int D, int H, int W,
               int Ci, int Co, int act, float slope, hipStream_t s);
-int nn_dw_chunks(int D, int H, int W, int *rows_per_chunk);
+size_t nn_packed_weight_elems(int Ci, int Co);
+size_t nn_dw_workspace_floats(int D, int H, int W, int Ci, int Co);
 void nn_conv3_dw(const unsigned short *X, const unsigned short *dZ, float *partial, float *gw, float *gb, int D, int H,
                  int W, int Ci, int Co, hipStream_t s);
 void nn_lrelu_bwd(const unsigned short *dY, const unsigned short *Y, float slope, size_t n, unsigned short *dZ,
@@ -321,9 +322,8 @@ int cl_net_create(cl_net **out, const cl_net_options *opt)
             L.wo = off; off += (size_t)27 * L.Ci * L.Co;
             L.bo = off; off += L.Co;
             net->conv.push_back(L);
-            int rpc;
             const int d = net->dims[L.lvl];
-            const size_t part = (size_t)nn_dw_chunks(d, d, d, &rpc) * 27 * L.Ci * L.Co;
+            const size_t part = nn_dw_workspace_floats(d, d, d, L.Ci, L.Co);
             if (part > maxpart) maxpart = part;
         }
         net->head_w = off; off += 16 * 3;
@@ -333,10 +333,11 @@ int cl_net_create(cl_net **out, const cl_net_options *opt)
         for (float **v : vecs) *v = (float *)nalloc(net, off * sizeof(float));
         net->partial = (float *)nalloc(net, maxpart * sizeof(float));
         for (ConvL &L : net->conv) {
-            L.wpf = (unsigned short *)nalloc(net, (size_t)27 * L.Ci * L.Co * 2);
-            L.wpb = (unsigned short *)nalloc(net, (size_t)27 * L.Ci * L.Co * 2);
+            L.wpf = (unsigned short *)nalloc(net, nn_packed_weight_elems(L.Ci, L.Co) * 2);
+            L.wpb = (unsigned short *)nalloc(net, nn_packed_weight_elems(L.Ci, L.Co) * 2);
         }
-        net->dpart = (double *)nalloc(net, net->nparts * sizeof(double));
+        // FP64 partial sums: the loss uses one row, the head's weight gradient 51 rows
+        net->dpart = (double *)nalloc(net, (size_t)51 * net->nparts * sizeof(double));
         net->dscal = (double *)nalloc(net, 4 * sizeof(double));
         net->dhead = (double *)nalloc(net, 64 * sizeof(double));
         if (hipHostMalloc((void **)&net->hscal, 4 * sizeof(double), hipHostMallocDefault) != hipSuccess)
@@ -578,7 +579,7 @@ int cl_nn_conv3(const void *in, const float *w, const float *b, void *out, int o
                 int Co, int act, float slope, int transpose, void *wpack, void *stream)
 {
     if (!in || !w || !out || !wpack) return CL_ERR_ARG;
-    if (Ci % 16 || Co % 16 || W < 1 || D < 1 || H < 1) return CL_ERR_SHAPE;
+    if (Ci < 16 || Co < 16 || Ci % 16 || Co % 16 || W < 1 || D < 1 || H < 1) return CL_ERR_SHAPE;
     const int Kout = transpose ? Ci : Co, Kin = transpose ? Co : Ci;
     if (!tile_count_ok(Kout / 16)) return CL_ERR_UNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
@@ -590,8 +591,8 @@ int cl_nn_conv3(const void *in, const float *w, const float *b, void *out, int o
 int cl_nn_conv3_dw_workspace(int D, int H, int W, int Ci, int Co, size_t *bytes)
 {
     if (!bytes || W < 1) return CL_ERR_ARG;
-    int rpc;
-    *bytes = (size_t)nn_dw_chunks(D, H, W, &rpc) * 27 * Ci * Co * sizeof(float);
+    if (Ci < 16 || Co < 16 || Ci % 16 || Co % 16 || D < 1 || H < 1) return CL_ERR_SHAPE;
+    *bytes = nn_dw_workspace_floats(D, H, W, Ci, Co) * sizeof(float);
     return CL_OK;
 }
 
@@ -599,7 +600,7 @@ int cl_nn_conv3_dw(const void *x, const void *dz, float *gw, float *gb, void *wo
                    int Co, void *stream)
 {
     if (!x || !dz || !gw || !workspace) return CL_ERR_ARG;
-    if (Ci % 16 || Co % 16 || W < 1) return CL_ERR_SHAPE;
+    if (Ci < 16 || Co < 16 || Ci % 16 || Co % 16 || W < 1 || D < 1 || H < 1) return CL_ERR_SHAPE;
     if (!tile_count_ok(Co / 16)) return CL_ERR_UNSUPPORTED;
     nn_conv3_dw((const unsigned short *)x, (const unsigned short *)dz, (float *)workspace, gw, gb, D, H, W, Ci, Co,
                 (hipStream_t)stream);

@@ -107,7 +107,10 @@ int main(void)
     cl_net_default_options(&no);
     EXPECT(no.struct_version == CL_NET_OPTIONS_VERSION && no.in_n == 128 && no.base_channels == 16);
     size_t wb = 0;
-    EXPECT(cl_nn_conv3_dw_workspace(12, 12, 40, 16, 32, &wb) == CL_OK && wb == (size_t)2 * 27 * 16 * 32 * 4);
+    /* 3 x 3 x 6 = 54 voxel tiles of 16 x 4 x 2, one per chunk: 27 Ci Co weight
+     * and Co bias partial sums each */
+    EXPECT(cl_nn_conv3_dw_workspace(12, 12, 40, 16, 32, &wb) == CL_OK && wb == (size_t)54 * (27 * 16 * 32 + 32) * 4);
+    EXPECT(cl_nn_conv3_dw_workspace(12, 12, 40, 8, 32, &wb) == CL_ERR_SHAPE);
     EXPECT(cl_nn_conv3_dw_workspace(12, 12, 40, 16, 32, NULL) == CL_ERR_ARG);
     cl_net *net = NULL;
     no.struct_version = 0;

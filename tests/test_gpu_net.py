@@ -121,12 +121,13 @@ def test_training_reduces_loss():
     net = Net(in_n=n, seed=2, lr=1e-3)
     m0, m1, lab = _sample(n, 9)
     a, b, c = f32_dev(m0), f32_dev(m1), f32_dev(lab)
-    losses = [net.train_step(a, b, c) for _ in range(30)]
+    losses = [net.train_step(a, b, c) for _ in range(60)]
     print("loss trace", " ".join("%.3e" % l for l in losses))
     # the head starts at zero (prediction v = 0) and Adam moves each weight by
-    # about lr per step: 30 steps give a modest decrease (about 20% observed),
-    # not a monotone one
-    assert losses[-1] < 0.9 * losses[0]
+    # about lr per step, so the loss falls slowly and not monotonically: one
+    # step's loss moves by up to 30% with the FP32 summation order of the
+    # weight gradient, so the test compares the mean of the last 10 steps
+    assert np.mean(losses[-10:]) < 0.9 * losses[0]
 
 
 @pytest.mark.parametrize("a,b", [((32, 32, 32), (16, 16, 16)), ((16, 16, 16), (32, 32, 32)),
