@@ -385,6 +385,127 @@ __global__ __launch_bounds__(TPB) void k_fft_x1_mult(float2 *__restrict__ spec, 
     store_cols(lds, base, rs, logC, logn1, cw, P);
 }
 
+// --- register-resident column passes for lines of L = 16 R2 points (R2 =
+// 8 or 16, i.e. L = 128 or 256) in tiles of C = 256 / R2 columns.  With
+// n = R2 a + b and k = c + 16 d,
+//   X[c + 16 d] = sum_b W_R2^{bd} W_L^{bc} sum_a x[R2 a + b] W_16^{ac},
+// so each thread holds 16 (or 2 x R2) values in registers: the length-16
+// DFTs over a run on the "b" layout (thread = column l, residue b), the
+// length-R2 DFTs over b on the "c" layout (thread = column l, c), and one
+// LDS exchange [c][b][l] (pitch 272 complex per c: row reads and writes of a
+// half-wavefront hit distinct banks) connects them.  The inverse runs the
+// same steps backwards.  A tile therefore crosses LDS twice per transform
+// (Stockham stages in LDS cross it four times plus the staging).
+// MODE 0: forward, symbol multiply (x1 pass), inverse; 1: forward only;
+// 2: inverse only.  Element (row q, column l) of the tile is base[q rs + l].
+constexpr int CSC = 272;   // LDS pitch per c (R2 C + 16 complex)
+
+template <int R2>
+__device__ __forceinline__ void cols_load_b(float2 (&v)[16], const float2 *__restrict__ base, size_t rs, int l, int b,
+                                            bool ok)
+{
+#pragma unroll
+    for (int a = 0; a < 16; ++a) v[a] = ok ? base[(size_t)(R2 * a + b) * rs + l] : make_float2(0.f, 0.f);
+}
+
+template <int R2, int MODE>
+__global__ __launch_bounds__(TPB) void k_fft_cols(float2 *__restrict__ spec, const float2 *__restrict__ twL,
+                                                  int nh, size_t plane_stride, size_t rs, size_t spec_cs, int kind,
+                                                  float beta, float scale, int n1, int n2)
+{
+    constexpr int L = 16 * R2, C = 256 / R2, P2 = C / 16;   // P2: (l, c) pairs per thread
+    __shared__ float2 tw[L];
+    __shared__ float2 ex[16 * CSC];
+    const int comp = blockIdx.z, pl = blockIdx.y, c0 = blockIdx.x * C;
+    const int cw = min(C, nh - c0);
+    float2 *base = spec + comp * spec_cs + pl * plane_stride + c0;
+    for (int t = threadIdx.x; t < L; t += TPB) tw[t] = twL[t];
+    const int l = threadIdx.x % C, r = threadIdx.x / C;     // r: b (b layout) or the first c (c layout)
+    const bool ok = l < cw;
+    float2 v[16];
+    if (MODE != 2) {
+        // forward: b layout, DFT-16 over a, twiddle W_L^{bc}, exchange
+        cols_load_b<R2>(v, base, rs, l, r, ok);
+        __syncthreads();                                      // twiddle table
+        dft_reg<16, false>(v);
+#pragma unroll
+        for (int c = 1; c < 16; ++c) v[c] = cmul(v[c], tw[r * c]);
+#pragma unroll
+        for (int c = 0; c < 16; ++c) ex[c * CSC + r * C + l] = v[c];
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < P2; ++u) {
+            const int c = r + (256 / C) * u;
+            float2 w[R2];
+#pragma unroll
+            for (int b = 0; b < R2; ++b) w[b] = ex[c * CSC + b * C + l];
+            dft_reg<R2, false>(w);                            // w[d] = X[c + 16 d]
+#pragma unroll
+            for (int d = 0; d < R2; ++d) v[u * R2 + d] = w[d];
+        }
+        if (MODE == 1) {
+#pragma unroll
+            for (int u = 0; u < P2; ++u) {
+                const int c = r + (256 / C) * u;
+#pragma unroll
+                for (int d = 0; d < R2; ++d)
+                    if (ok) base[(size_t)(c + 16 * d) * rs + l] = v[u * R2 + d];
+            }
+            return;
+        }
+        // symbol of the x1 pass: k1 = c + 16 d, k2 = plane, k3 = c0 + l
+        const float k2 = (float)(pl < (n2 >> 1) ? pl : pl - n2);
+        const float k3 = (float)(c0 + l);
+#pragma unroll
+        for (int u = 0; u < P2; ++u) {
+            const int c = r + (256 / C) * u;
+#pragma unroll
+            for (int d = 0; d < R2; ++d) {
+                const int q = c + 16 * d;
+                const float k1 = (float)(q < (n1 >> 1) ? q : q - n1);
+                const float ksq = k1 * k1 + k2 * k2 + k3 * k3;
+                float sym;
+                if (kind == 0) sym = beta * ksq;
+                else if (kind == 1) sym = 1.0f / (beta * fmaxf(ksq, 1.0f));
+                else sym = 1.0f;
+                sym *= scale;
+                v[u * R2 + d].x *= sym;
+                v[u * R2 + d].y *= sym;
+            }
+        }
+        __syncthreads();                                      // exchange buffer free again
+    } else {
+        // inverse only: c layout loads X[c + 16 d]
+#pragma unroll
+        for (int u = 0; u < P2; ++u) {
+            const int c = r + (256 / C) * u;
+#pragma unroll
+            for (int d = 0; d < R2; ++d)
+                v[u * R2 + d] = ok ? base[(size_t)(c + 16 * d) * rs + l] : make_float2(0.f, 0.f);
+        }
+        __syncthreads();                                      // twiddle table
+    }
+    // inverse: c layout, DFT-R2 over d, twiddle W_L^{-bc}, exchange, DFT-16 over c
+#pragma unroll
+    for (int u = 0; u < P2; ++u) {
+        const int c = r + (256 / C) * u;
+        float2 w[R2];
+#pragma unroll
+        for (int d = 0; d < R2; ++d) w[d] = v[u * R2 + d];
+        dft_reg<R2, true>(w);                                 // w[b] = sum_d X[c + 16 d] W_R2^{-bd}
+#pragma unroll
+        for (int b = 0; b < R2; ++b) ex[c * CSC + b * C + l] = b ? cmul(w[b], cconj(tw[b * c])) : w[b];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 16; ++c) v[c] = ex[c * CSC + r * C + l];
+    dft_reg<16, true>(v);                                     // v[a] = x[r + R2 a]
+    if (ok) {
+#pragma unroll
+        for (int a = 0; a < 16; ++a) base[(size_t)(R2 * a + r) * rs + l] = v[a];
+    }
+}
+
 // Copy the half-spectrum modes with |k_d| < min(na_d, nb_d)/2 from grid a
 // to grid b (the coarse Nyquist planes are dropped), zero elsewhere.
 __global__ __launch_bounds__(TPB) void k_mode_copy(const float2 *__restrict__ sa, float2 *__restrict__ sb, int a1, int a2,
@@ -482,6 +603,60 @@ struct PassGeom;
 void coupled3(const FFTPlan &P, int kind, float beta_v, float beta_w, const float *in, float *out, hipStream_t s);
 } // namespace
 
+namespace {
+
+bool cols_ok(int L) { return L == 128 || L == 256; }
+
+template <int MODE>
+void launch_cols(int L, dim3 grid, float2 *spec, const float2 *tw, int nh, size_t plane_stride, size_t rs,
+                 size_t spec_cs, int kind, float beta, float scale, int n1, int n2, hipStream_t s)
+{
+    if (L == 256)
+        hipLaunchKernelGGL((k_fft_cols<16, MODE>), grid, dim3(TPB), 0, s, spec, tw, nh, plane_stride, rs, spec_cs, kind,
+                           beta, scale, n1, n2);
+    else
+        hipLaunchKernelGGL((k_fft_cols<8, MODE>), grid, dim3(TPB), 0, s, spec, tw, nh, plane_stride, rs, spec_cs, kind,
+                           beta, scale, n1, n2);
+}
+
+// x2 pass over every x1 plane (forward or inverse), nc components
+void pass_x2(const FFTPlan &P, bool inv, int nc, int logC2, size_t lds2, size_t spec_cs, hipStream_t s)
+{
+    if (cols_ok(P.n2)) {
+        const int C = 4096 / P.n2;
+        const dim3 grid((P.nh + C - 1) / C, P.n1, nc);
+        if (inv) launch_cols<2>(P.n2, grid, P.spec, P.tw2, P.nh, (size_t)P.n2 * P.nh, P.nh, spec_cs, 2, 0.f, 1.f, P.n1, P.n2, s);
+        else launch_cols<1>(P.n2, grid, P.spec, P.tw2, P.nh, (size_t)P.n2 * P.nh, P.nh, spec_cs, 2, 0.f, 1.f, P.n1, P.n2, s);
+        return;
+    }
+    const int C2 = 1 << logC2;
+    const dim3 grid((P.nh + C2 - 1) / C2, P.n1, nc);
+    if (inv)
+        hipLaunchKernelGGL(k_fft_x2<true>, grid, dim3(TPB), lds2, s, P.spec, P.tw2, ilog2(P.n2), P.n2, P.nh, logC2, spec_cs);
+    else
+        hipLaunchKernelGGL(k_fft_x2<false>, grid, dim3(TPB), lds2, s, P.spec, P.tw2, ilog2(P.n2), P.n2, P.nh, logC2, spec_cs);
+}
+
+// x1 pass over every x2 plane: mode 0 forward, symbol, inverse; 1 forward; 2 inverse
+void pass_x1(const FFTPlan &P, int mode, int kind, float beta, float scale, int nc, int logC1, size_t lds1,
+             size_t spec_cs, hipStream_t s)
+{
+    if (cols_ok(P.n1)) {
+        const int C = 4096 / P.n1;
+        const dim3 grid((P.nh + C - 1) / C, P.n2, nc);
+        const size_t rs = (size_t)P.n2 * P.nh;
+        if (mode == 0) launch_cols<0>(P.n1, grid, P.spec, P.tw1, P.nh, P.nh, rs, spec_cs, kind, beta, scale, P.n1, P.n2, s);
+        else if (mode == 1) launch_cols<1>(P.n1, grid, P.spec, P.tw1, P.nh, P.nh, rs, spec_cs, kind, beta, scale, P.n1, P.n2, s);
+        else launch_cols<2>(P.n1, grid, P.spec, P.tw1, P.nh, P.nh, rs, spec_cs, kind, beta, scale, P.n1, P.n2, s);
+        return;
+    }
+    const int C1 = 1 << logC1;
+    hipLaunchKernelGGL(k_fft_x1_mult, dim3((P.nh + C1 - 1) / C1, P.n2, nc), dim3(TPB), lds1, s, P.spec, P.tw1,
+                       ilog2(P.n1), P.n1, P.n2, P.nh, logC1, kind, beta, scale, spec_cs, mode);
+}
+
+} // namespace
+
 void spectral_apply(const FFTPlan &P, int kind, float beta, float beta_w, int ncomp, const float *in, float *out,
                     const float *add, hipStream_t s)
 {
@@ -517,12 +692,9 @@ void spectral_apply(const FFTPlan &P, int kind, float beta, float beta_w, int nc
         const float *addc = add ? add + c0 * N : nullptr;
         hipLaunchKernelGGL(k_fft_x3_r2c, dim3(nrows >> lognl3, nc), dim3(TPB), lds3, s, inc, P.spec, P.twM, P.twS,
                            logM, lognl3, nrows, N, spec_cs);
-        hipLaunchKernelGGL(k_fft_x2<false>, dim3((nh + C2 - 1) / C2, n1, nc), dim3(TPB), lds2, s, P.spec, P.tw2, ilog2(n2),
-                           n2, nh, logC2, spec_cs);
-        hipLaunchKernelGGL(k_fft_x1_mult, dim3((nh + C1 - 1) / C1, n2, nc), dim3(TPB), lds1, s, P.spec, P.tw1,
-                           ilog2(n1), n1, n2, nh, logC1, kind, beta, scale, spec_cs, 0);
-        hipLaunchKernelGGL(k_fft_x2<true>, dim3((nh + C2 - 1) / C2, n1, nc), dim3(TPB), lds2, s, P.spec, P.tw2, ilog2(n2),
-                           n2, nh, logC2, spec_cs);
+        pass_x2(P, false, nc, logC2, lds2, spec_cs, s);
+        pass_x1(P, 0, kind, beta, scale, nc, logC1, lds1, spec_cs, s);
+        pass_x2(P, true, nc, logC2, lds2, spec_cs, s);
         hipLaunchKernelGGL(k_fft_x3_c2r, dim3(nrows >> lognl3, nc), dim3(TPB), lds3, s, P.spec, outc, addc, P.twM,
                            P.twS, logM, lognl3, nrows, N, spec_cs);
     }
@@ -560,18 +732,14 @@ void forward3(const FFTPlan &P, const PassGeom &G, int nc, const float *in, hipS
 {
     hipLaunchKernelGGL(k_fft_x3_r2c, dim3(G.nrows >> G.lognl3, nc), dim3(TPB), G.lds3, s, in, P.spec, P.twM, P.twS,
                        G.logM, G.lognl3, G.nrows, G.N, G.spec_cs);
-    hipLaunchKernelGGL(k_fft_x2<false>, dim3((P.nh + G.C2 - 1) / G.C2, P.n1, nc), dim3(TPB), G.lds2, s, P.spec, P.tw2,
-                       ilog2(P.n2), P.n2, P.nh, G.logC2, G.spec_cs);
-    hipLaunchKernelGGL(k_fft_x1_mult, dim3((P.nh + G.C1 - 1) / G.C1, P.n2, nc), dim3(TPB), G.lds1, s, P.spec, P.tw1,
-                       ilog2(P.n1), P.n1, P.n2, P.nh, G.logC1, 2, 0.f, 1.f, G.spec_cs, 1);
+    pass_x2(P, false, nc, G.logC2, G.lds2, G.spec_cs, s);
+    pass_x1(P, 1, 2, 0.f, 1.f, nc, G.logC1, G.lds1, G.spec_cs, s);
 }
 
 void inverse3(const FFTPlan &P, const PassGeom &G, int nc, float *out, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_fft_x1_mult, dim3((P.nh + G.C1 - 1) / G.C1, P.n2, nc), dim3(TPB), G.lds1, s, P.spec, P.tw1,
-                       ilog2(P.n1), P.n1, P.n2, P.nh, G.logC1, 2, 0.f, 1.f, G.spec_cs, 2);
-    hipLaunchKernelGGL(k_fft_x2<true>, dim3((P.nh + G.C2 - 1) / G.C2, P.n1, nc), dim3(TPB), G.lds2, s, P.spec, P.tw2,
-                       ilog2(P.n2), P.n2, P.nh, G.logC2, G.spec_cs);
+    pass_x1(P, 2, 2, 0.f, 1.f, nc, G.logC1, G.lds1, G.spec_cs, s);
+    pass_x2(P, true, nc, G.logC2, G.lds2, G.spec_cs, s);
     hipLaunchKernelGGL(k_fft_x3_c2r, dim3(G.nrows >> G.lognl3, nc), dim3(TPB), G.lds3, s, P.spec, out, nullptr, P.twM,
                        P.twS, G.logM, G.lognl3, G.nrows, G.N, G.spec_cs);
 }

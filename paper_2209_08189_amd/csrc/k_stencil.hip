@@ -452,7 +452,10 @@ void launch_quad_march(const Grid &g, const QuadArgs &qa, const float *add, floa
 
 } // namespace
 
-bool quadrature_marches(const Grid &g, const QuadArgs &qa) { return qa.lean && march_ok(g) && qa.count <= MAX_NL; }
+// The marching kernel reads m^j (plus halo planes) instead of the stored
+// gradients (3 fields per time level), so it is used in both layouts; its
+// derivatives are the stored ones bit for bit.
+bool quadrature_marches(const Grid &g, const QuadArgs &qa) { return march_ok(g) && qa.count <= MAX_NL; }
 
 int quadrature_blocks(const Grid &g, const QuadArgs &qa)
 {
