@@ -1,0 +1,183 @@
+"""Learned warm start at its full scale: 2000 training pairs of the 256^3
+brain-like phantom (seeds 1000-2999), each labelled with the converged
+velocity of the plain Gauss-Newton solve (relative gradient 1e-2, images
+and label restricted spectrally to the network's 128^3 grid), and 100
+held-out pairs (seeds 10000-10099) on which the solve is timed from v = 0
+and from the network's prediction.
+
+Two steps, each one process:
+
+  python -m paper_2209_08189_amd.learned256 train --out DIR
+      labels + Adam training; writes DIR/net_params.npy and DIR/train.json
+  python -m paper_2209_08189_amd.learned256 eval --params DIR/net_params.npy --out FILE.json
+      per held-out seed: plain FP32 and learned + mixed-precision solves, with
+      the spectral preconditioner and with the zero-velocity preconditioner
+
+Progress goes to stderr, one line per step.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+
+def log(msg):
+    print("[learned256] " + msg, file=sys.stderr, flush=True)
+
+
+def seed_range(s):
+    a, b = s.split(":")
+    return list(range(int(a), int(b)))
+
+
+def cmd_train(args):
+    from . import warmstart
+    host = warmstart.HostPairs()          # before the GPU is touched
+    import torch
+    from .claire import Net
+    torch.cuda.set_device(0)
+    seeds = seed_range(args.train_seeds)
+    t0 = time.perf_counter()
+    data = warmstart.generate(seeds, n=args.n, n_net=args.n // 2, log=log, host=host, max_pcg=args.max_pcg,
+                              precond=args.label_precond, log_every=args.log_every)
+    t_label = time.perf_counter() - t0
+    host.close()
+    log("labels: %d pairs in %.1f s" % (len(data), t_label))
+    net = Net(in_n=args.n // 2, seed=1, lr=args.lr)
+    t1 = time.perf_counter()
+    hist = warmstart.train(net, data, args.epochs, batch=args.batch, log=log, seed=0)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    # prediction error on the training labels (first 20 pairs)
+    errs = []
+    for m0, m1, lab in data[:20]:
+        pred = net.forward(m0, m1)
+        errs.append(float((pred - lab).norm() / lab.norm()))
+    os.makedirs(args.out, exist_ok=True)
+    np.save(os.path.join(args.out, "net_params.npy"), net.params().cpu().numpy())
+    rec = {"train_seeds": args.train_seeds, "pairs": len(data), "grid": args.n, "net_grid": args.n // 2,
+           "label_precond": args.label_precond, "max_pcg": args.max_pcg, "epochs": args.epochs,
+           "batch": args.batch, "lr": args.lr, "label_s": t_label, "train_s": t_train,
+           "train_sample_steps": args.epochs * len(data), "loss_per_epoch": hist,
+           "train_pred_rel_err_first20": errs}
+    json.dump(rec, open(os.path.join(args.out, "train.json"), "w"), indent=1)
+    log("training: %d epochs in %.1f s, final loss %.4e, train prediction error %.3f"
+        % (args.epochs, t_train, hist[-1], float(np.mean(errs))))
+
+
+def cmd_eval(args):
+    from . import warmstart
+    host = warmstart.HostPairs()
+    import torch
+    from .claire import Net
+    from .metrics import dice, warp_labels
+    torch.cuda.set_device(0)
+    n = args.n
+    net = Net(in_n=n // 2, seed=1)
+    net.set_params(torch.from_numpy(np.load(args.params)).cuda())
+    seeds = seed_range(args.eval_seeds)
+    storage = ("f16", "f16")
+    rows = []
+    t0 = time.perf_counter()
+    for i, (s, hp) in enumerate(zip(seeds, host.pairs(n, seeds))):
+        m0, m1, lab0, v_true = warmstart.device_pair(hp, with_velocity=True)
+        del hp
+        lab1 = warp_labels(lab0, v_true)
+        mis0 = 0.5 * float(((m0 - m1).double() ** 2).sum()) * (2.0 * np.pi / n) ** 3
+        row = {"seed": s, "mismatch_v0": mis0}
+        legs = {
+            "plain": dict(),
+            "learned_mixed": dict(storage=storage, net=net),
+            "plain_h0": dict(precond="h0"),
+            "learned_mixed_h0": dict(storage=storage, net=net, precond="h0"),
+        }
+        vel = {}
+        for name, kw in legs.items():
+            rep, v, dt = warmstart.solve(m0, m1, max_pcg=args.max_pcg, **kw)
+            row[name] = {"s": dt, "gn": rep["outer_iters"], "pcg": rep["pcg_iters_total"],
+                         "mismatch": rep["mismatch"], "r": rep["mismatch"] / mis0, "rel_grad": rep["gnorm"] / rep["gref"],
+                         "status": rep["status_name"], "used_prediction": bool(rep["warm_start_used"])}
+            vel[name] = v
+        pred = warmstart.predict(net, m0, m1)
+        row["pred_rel_err"] = float((pred - vel["plain"]).norm() / vel["plain"].norm())
+        row["dice_vw_pre"] = dice(lab0, lab1)["D_vw"]
+        row["dice_vw_plain"] = dice(warp_labels(lab0, vel["plain"]), lab1)["D_vw"]
+        row["dice_vw_learned_mixed"] = dice(warp_labels(lab0, vel["learned_mixed"]), lab1)["D_vw"]
+        for a, b in (("learned_mixed", "plain"), ("learned_mixed_h0", "plain_h0")):
+            row["%s_vs_%s" % (a, b)] = {
+                "time_ratio": row[a]["s"] / row[b]["s"],
+                "abs_diff_r": abs(row[a]["r"] - row[b]["r"]),
+                "rel_mismatch_diff": abs(row[a]["mismatch"] - row[b]["mismatch"]) / row[b]["mismatch"]}
+        rows.append(row)
+        log("eval %d/%d seed %d: plain %.2f s (%d GN), learned+mixed %.2f s (%d GN, used %s), plain H0 %.2f s, "
+            "learned+mixed H0 %.2f s; prediction error %.3f; |dr| %.1e (%.0f s elapsed)"
+            % (i + 1, len(seeds), s, row["plain"]["s"], row["plain"]["gn"], row["learned_mixed"]["s"],
+               row["learned_mixed"]["gn"], row["learned_mixed"]["used_prediction"], row["plain_h0"]["s"],
+               row["learned_mixed_h0"]["s"], row["pred_rel_err"], row["learned_mixed_vs_plain"]["abs_diff_r"],
+               time.perf_counter() - t0))
+    host.close()
+
+    def mean(f):
+        return float(np.mean([f(r) for r in rows]))
+
+    summary = {}
+    for name in ("plain", "learned_mixed", "plain_h0", "learned_mixed_h0"):
+        summary[name] = {"time_to_tol_s": mean(lambda r: r[name]["s"]), "gn": mean(lambda r: r[name]["gn"]),
+                         "pcg": mean(lambda r: r[name]["pcg"]), "r": mean(lambda r: r[name]["r"]),
+                         "not_converged": int(sum(r[name]["status"] != "ok" for r in rows))}
+    for a, b in (("learned_mixed", "plain"), ("learned_mixed_h0", "plain_h0")):
+        k = "%s_vs_%s" % (a, b)
+        summary[k] = {
+            "mean_time_ratio": mean(lambda r: r[k]["time_ratio"]),
+            "ratio_of_mean_times": summary[a]["time_to_tol_s"] / summary[b]["time_to_tol_s"],
+            "max_abs_diff_r": float(max(r[k]["abs_diff_r"] for r in rows)),
+            "mean_abs_diff_r": mean(lambda r: r[k]["abs_diff_r"]),
+            "max_rel_mismatch_diff": float(max(r[k]["rel_mismatch_diff"] for r in rows)),
+            "mean_rel_mismatch_diff": mean(lambda r: r[k]["rel_mismatch_diff"]),
+            "seeds_within_1e-3_rel_mismatch": int(sum(r[k]["rel_mismatch_diff"] <= 1e-3 for r in rows)),
+            "seeds_within_1e-3_abs_r": int(sum(r[k]["abs_diff_r"] <= 1e-3 for r in rows))}
+    summary["fallback_rate"] = mean(lambda r: 0.0 if r["learned_mixed"]["used_prediction"] else 1.0)
+    summary["pred_rel_err"] = mean(lambda r: r["pred_rel_err"])
+    summary["dice_vw"] = {"pre": mean(lambda r: r["dice_vw_pre"]), "plain": mean(lambda r: r["dice_vw_plain"]),
+                          "learned_mixed": mean(lambda r: r["dice_vw_learned_mixed"])}
+    rec = {"eval_seeds": args.eval_seeds, "grid": n, "net_grid": n // 2, "storage_mixed": list(storage),
+           "max_pcg": args.max_pcg, "gtol": 1e-2, "params": os.path.basename(args.params),
+           "summary": summary, "rows": rows}
+    if args.train_record and os.path.exists(args.train_record):
+        rec["training"] = json.load(open(args.train_record))
+    json.dump(rec, open(args.out, "w"), indent=1)
+    log("summary: %s" % json.dumps(summary))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("train")
+    t.add_argument("--out", required=True)
+    t.add_argument("--n", type=int, default=256)
+    t.add_argument("--train-seeds", default="1000:3000")
+    t.add_argument("--label-precond", default="h0", choices=["spectral", "h0"])
+    t.add_argument("--max-pcg", type=int, default=40)
+    t.add_argument("--epochs", type=int, default=10)
+    t.add_argument("--batch", type=int, default=2)
+    t.add_argument("--lr", type=float, default=1e-4)
+    t.add_argument("--log-every", type=int, default=25)
+    e = sub.add_parser("eval")
+    e.add_argument("--params", required=True)
+    e.add_argument("--out", required=True)
+    e.add_argument("--train-record", default=None)
+    e.add_argument("--n", type=int, default=256)
+    e.add_argument("--eval-seeds", default="10000:10100")
+    e.add_argument("--max-pcg", type=int, default=40)
+    args = ap.parse_args()
+    if args.cmd == "train":
+        cmd_train(args)
+    else:
+        cmd_eval(args)
+
+
+if __name__ == "__main__":
+    main()

@@ -95,13 +95,15 @@ def make_pair(n, seed, max_disp=6.0):
     return device_pair(host_pair(n, seed, max_disp))
 
 
-def solve(m0, m1, storage=("f32", "f32"), gtol=1e-2, net=None, max_outer=50, max_pcg=40):
+def solve(m0, m1, storage=("f32", "f32"), gtol=1e-2, net=None, max_outer=50, max_pcg=40, precond="spectral",
+          precond_inner=12):
     """Gauss-Newton solve from v = 0 (or from the network's warm start).
     Returns (report dict, final velocity tensor, seconds)."""
     import torch
     shape = tuple(m0.shape)
     reg = Registration(shape, gtol=gtol, max_outer=max_outer, max_pcg=max_pcg,
-                       storage_state=storage[0], storage_adjoint=storage[1])
+                       storage_state=storage[0], storage_adjoint=storage[1], precond=precond,
+                       precond_inner=precond_inner)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     reg.set_images(m0, m1)
@@ -117,19 +119,23 @@ def solve(m0, m1, storage=("f32", "f32"), gtol=1e-2, net=None, max_outer=50, max
     return rep, v, dt
 
 
-def generate(seeds, n=256, n_net=128, log=None, host=None, max_pcg=40):
+def generate(seeds, n=256, n_net=128, log=None, host=None, max_pcg=40, precond="spectral", log_every=1):
     """Training data on the network grid: list of (m0, m1, v_label) device
-    tensors restricted from n^3 solves.  host: a HostPairs pool (optional)."""
+    tensors restricted from n^3 solves.  host: a HostPairs pool (optional);
+    precond: preconditioner of the labelling solves."""
     down = Resampler((n,) * 3, (n_net,) * 3)
     data = []
     src = host.pairs(n, seeds) if host else (host_pair(n, s) for s in seeds)
-    for s, hp in zip(seeds, src):
+    t0 = time.perf_counter()
+    for i, (s, hp) in enumerate(zip(seeds, src)):
         m0, m1, _ = device_pair(hp)
         del hp
-        rep, v, dt = solve(m0, m1, max_pcg=max_pcg)
+        rep, v, dt = solve(m0, m1, max_pcg=max_pcg, precond=precond)
         data.append((down(m0), down(m1), down(v)))
-        if log:
-            log("label seed %d: %d GN, %d PCG, %.2f s" % (s, rep["outer_iters"], rep["pcg_iters_total"], dt))
+        if log and (i % log_every == 0 or i == len(seeds) - 1):
+            log("label %d/%d seed %d: %d GN, %d PCG, %.2f s, %s (%.0f s elapsed)"
+                % (i + 1, len(seeds), s, rep["outer_iters"], rep["pcg_iters_total"], dt, rep["status_name"],
+                   time.perf_counter() - t0))
     return data
 
 
