@@ -83,8 +83,8 @@ typedef struct {
                                                 exceeds it (0: exceeds 15/16 of the free device memory), the
                                                 lean layout is used (see cl_layout); cl_create fails with
                                                 CL_ERR_OOM when a nonzero cap is below even that */
-    int precond;              /* CL_PRECOND_SPECTRAL (default) or CL_PRECOND_H0 */
-    int precond_inner;        /* inner CG iterations of CL_PRECOND_H0, 1..100 (default 5) */
+    int precond;              /* CL_PRECOND_SPECTRAL (default), CL_PRECOND_H0 or CL_PRECOND_H0_2LEVEL */
+    int precond_inner;        /* inner CG iterations of the H0 preconditioners, 1..100 (default 5) */
     int interp_order;         /* interpolation of every SL step: 3 tricubic Lagrange (default),
                                  1 trilinear (the paper's choice above 256^3, Section 3.3) */
     int overlap_spectral;     /* 1: cl_hessian_matvec computes its beta_v A vt term on a side stream
@@ -110,8 +110,16 @@ typedef struct {
  *     definite where the data term vanishes.  The outer PCG is then flexible
  *     (beta = <r_new, z_new - z_old> / <r, z>).  Needs the full memory
  *     layout (stored grad_h m^j) and six more vector fields of workspace;
- *     cl_create returns CL_ERR_UNSUPPORTED in the lean layout. */
-enum { CL_PRECOND_SPECTRAL = 0, CL_PRECOND_H0 = 1 };
+ *     cl_create returns CL_ERR_UNSUPPORTED in the lean layout.
+ *   CL_PRECOND_H0_2LEVEL: the two-level coarse-grid variant that Section
+ *     2.2 names as the default.  The Fourier band a half-resolution grid
+ *     represents (|k_d| < n_d / 4) gets H0 inverted on that grid by
+ *     precond_inner CG steps (H0 of the spectrally restricted template,
+ *     FD8 with the coarse spacing), the modes above it get L^-1:
+ *     z = P z_c + L^-1 (r - P R r), z_c ~ H0_c^-1 R r, with R / P spectral
+ *     restriction / prolongation.  Flexible outer PCG as for CL_PRECOND_H0.
+ *     Needs n_d >= 32 (CL_ERR_SHAPE) and the full layout. */
+enum { CL_PRECOND_SPECTRAL = 0, CL_PRECOND_H0 = 1, CL_PRECOND_H0_2LEVEL = 2 };
 
 typedef struct {
     int status;               /* CL_OK (converged), CL_STATUS_MAXIT or CL_STATUS_LINESEARCH_FAIL */

@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libclairehip.so")
 CL_F32, CL_BF16, CL_F16 = 0, 1, 2
 DTYPES = {"f32": CL_F32, "bf16": CL_BF16, "f16": CL_F16}
 CL_OPTIONS_VERSION = 5
-PRECOND = {"spectral": 0, "h0": 1}
+PRECOND = {"spectral": 0, "h0": 1, "h0_2level": 2}
 
 FIELD_STATE, FIELD_ADJOINT, FIELD_INC_STATE, FIELD_INC_ADJOINT = 0, 1, 2, 3
 FIELD_FEET_F, FIELD_FEET_B, FIELD_ADJ_FACTOR = 4, 5, 6

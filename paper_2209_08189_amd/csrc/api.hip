@@ -70,6 +70,18 @@ struct cl_ctx {
     // previous outer z (flexible PCG); 3N each, allocated with that option
     float *ir = nullptr, *izi = nullptr, *ip = nullptr, *iLp = nullptr, *ih = nullptr, *ilz = nullptr,
           *zold = nullptr;
+    // two-level variant: the half-resolution grid, its FFT plan, the
+    // restricted template's FD8 gradient, the restricted residual and its
+    // inner solution, and the inner CG vectors on that grid
+    struct Coarse {
+        Grid g{};
+        FFTPlan fft{};
+        size_t N = 0;
+        double hv = 0.0;
+        float *m0 = nullptr, *G0 = nullptr, *r = nullptr, *z = nullptr;
+        float *ir = nullptr, *izi = nullptr, *ip = nullptr, *iLp = nullptr, *ih = nullptr;
+        bool valid = false;                 // G0 matches the current images
+    } cz;
     int nparts = 1;
     FFTPlan fft{};
 
@@ -408,6 +420,11 @@ void matvec(cl_ctx *ctx, const float *vt, float *Hvt, const float *Avt_known = n
             launch_inc_source_fd(ctx->g, ctx->dts, slot(ctx, ctx->m, ctx->dts, 0), vt, 0.5f * dt, ctx->dta,
                                  ctx->q[0], ctx->s);
         });
+    } else if (sources_march(ctx->g, nt)) {
+        const QuadArgs qa = quad_args(ctx);
+        run(ctx, CL_K_VEC, [&] {
+            launch_inc_sources_march(ctx->g, ctx->dts, qa, vt, nt, 0.5f * dt, ctx->dta, ctx->q[0], ctx->S, ctx->s);
+        });
     } else {
         run(ctx, CL_K_VEC, [&] {
             launch_inc_sources(ctx->g, ctx->G, vt, nt, 0.5f * dt, ctx->dta, ctx->q[0], ctx->S, ctx->s);
@@ -445,51 +462,108 @@ void matvec(cl_ctx *ctx, const float *vt, float *Hvt, const float *Avt_known = n
     }
 }
 
-// z ~ H0^-1 r (zero-velocity Hessian) by opt.precond_inner CG steps from
-// z = 0 with the spectral preconditioner; ctx->ilz receives L z.  The inner
-// operator is L_0 + G G^T with L_0 = L except that the k = 0 mode is mapped
-// by beta_v (the preconditioner's convention, definite where the data term
-// vanishes); L_0 p of the inner directions is carried by the recurrence
-// L_0 p = r + beta L_0 p (L_0 P_s = I), so the only FFT pair per step is the
-// spectral preconditioner.  Each step after the first updates the direction
-// and applies the operator in one pass.  L z for the outer recurrence is
-// one spectral operation at the end.  grad_h m0 is the stored G^0.
-void precond_h0(cl_ctx *ctx, const float *r, float *z)
+// One grid of the zero-velocity inner solve: its geometry, FFT plan,
+// grad_h m0 on that grid and the inner CG vectors.
+struct H0Level {
+    const Grid *g;
+    const FFTPlan *fft;
+    size_t N;
+    double hv;
+    const float *G0;
+    float *ir, *izi, *ip, *iLp, *ih;
+};
+
+void level_spectral(cl_ctx *ctx, const H0Level &L, int kind, const float *in, float *out)
 {
-    ensure_sgrad(ctx);
-    const size_t N = ctx->N, n = 3 * N;
+    run(ctx, CL_K_FFT, [&] {
+        spectral_apply(*L.fft, kind, (float)ctx->opt.beta_v, (float)ctx->opt.beta_w, 3, in, out, nullptr, ctx->s);
+    });
+}
+
+// z ~ H0^-1 r (zero-velocity Hessian) on grid L by opt.precond_inner CG
+// steps from z = 0 with the spectral preconditioner.  The inner operator
+// is L_0 + G G^T with L_0 = L except that the k = 0 mode is mapped by
+// beta_v (the preconditioner's convention, definite where the data term
+// vanishes); L_0 p of the inner directions is carried by the recurrence
+// L_0 p = r + beta L_0 p (L_0 P_s = I), so the only FFT pair per step is
+// the spectral preconditioner.  Each step after the first updates the
+// direction and applies the operator in one pass.
+void h0_inner(cl_ctx *ctx, const H0Level &L, const float *r, float *z)
+{
+    const size_t N = L.N, n = 3 * N;
     double *sc = ctx->pscal + PCG_INNER;
-    const float *G0 = ctx->G;
-    HIPCHK(hipMemcpyAsync(ctx->ir, r, n * sizeof(float), hipMemcpyDeviceToDevice, ctx->s));
+    const int nb = std::min(ctx->nparts, reduce_blocks(n));
+    HIPCHK(hipMemcpyAsync(L.ir, r, n * sizeof(float), hipMemcpyDeviceToDevice, ctx->s));
     run(ctx, CL_K_VEC, [&] { launch_fill_f32(z, 0.0f, n, ctx->s); });
-    spectral(ctx, 1, 3, ctx->ir, ctx->izi, nullptr);
-    HIPCHK(hipMemcpyAsync(ctx->ip, ctx->izi, n * sizeof(float), hipMemcpyDeviceToDevice, ctx->s));
-    HIPCHK(hipMemcpyAsync(ctx->iLp, ctx->ir, n * sizeof(float), hipMemcpyDeviceToDevice, ctx->s));
+    level_spectral(ctx, L, 1, L.ir, L.izi);
+    HIPCHK(hipMemcpyAsync(L.ip, L.izi, n * sizeof(float), hipMemcpyDeviceToDevice, ctx->s));
+    HIPCHK(hipMemcpyAsync(L.iLp, L.ir, n * sizeof(float), hipMemcpyDeviceToDevice, ctx->s));
     run(ctx, CL_K_VEC, [&] {
-        launch_dot(ctx->ir, ctx->izi, n, ctx->partials, ctx->nparts, ctx->s);
-        launch_finalize(ctx->partials, ctx->nparts, ctx->hv, sc + PCG_RZ, ctx->s);
+        launch_dot(L.ir, L.izi, n, ctx->partials, nb, ctx->s);
+        launch_finalize(ctx->partials, nb, L.hv, sc + PCG_RZ, ctx->s);
     });
     const int inner = ctx->opt.precond_inner;
     for (int it = 0; it < inner; ++it) {
         run(ctx, CL_K_VEC, [&] {
             if (it == 0)
-                launch_h0_apply(ctx->ip, ctx->iLp, G0, ctx->ih, N, ctx->partials, ctx->nparts, ctx->s);
+                launch_h0_apply(L.ip, L.iLp, L.G0, L.ih, N, ctx->partials, nb, ctx->s);
             else
-                launch_h0_direction_apply(ctx->ip, ctx->iLp, ctx->izi, ctx->ir, G0, ctx->ih, sc, N, ctx->partials,
-                                          ctx->nparts, ctx->s);
-            launch_finalize(ctx->partials, ctx->nparts, ctx->hv, sc + PCG_PHP, ctx->s);
+                launch_h0_direction_apply(L.ip, L.iLp, L.izi, L.ir, L.G0, L.ih, sc, N, ctx->partials, nb, ctx->s);
+            launch_finalize(ctx->partials, nb, L.hv, sc + PCG_PHP, ctx->s);
             launch_pcg_alpha(sc, ctx->s);
-            launch_h0_update(z, ctx->ir, ctx->ip, ctx->ih, sc, N, ctx->s);
+            launch_h0_update(z, L.ir, L.ip, L.ih, sc, N, ctx->s);
         });
         if (it == inner - 1) break;
-        spectral(ctx, 1, 3, ctx->ir, ctx->izi, nullptr);
+        level_spectral(ctx, L, 1, L.ir, L.izi);
         run(ctx, CL_K_VEC, [&] {
-            launch_dot(ctx->ir, ctx->izi, n, ctx->partials, ctx->nparts, ctx->s);
-            launch_finalize(ctx->partials, ctx->nparts, ctx->hv, sc + PCG_RZNEW, ctx->s);
+            launch_dot(L.ir, L.izi, n, ctx->partials, nb, ctx->s);
+            launch_finalize(ctx->partials, nb, L.hv, sc + PCG_RZNEW, ctx->s);
             launch_pcg_beta(sc, ctx->s);
         });
     }
-    // L z for the outer recurrence
+}
+
+// Full resolution: grad_h m0 is the stored G^0; ctx->ilz receives L z (one
+// spectral operation) for the outer recurrence.
+void precond_h0(cl_ctx *ctx, const float *r, float *z)
+{
+    ensure_sgrad(ctx);
+    const H0Level L{&ctx->g, &ctx->fft, ctx->N, ctx->hv, ctx->G, ctx->ir, ctx->izi, ctx->ip, ctx->iLp, ctx->ih};
+    h0_inner(ctx, L, r, z);
+    spectral(ctx, 0, 3, z, ctx->ilz, nullptr);
+}
+
+// Two-level variant (Section 2.2 names the two-level coarse-grid
+// approximation as the default; reading): the Fourier band a half-resolution
+// grid represents (|k_d| < n_d / 4) gets H0 inverted on that grid, the modes
+// above it get the spectral L^-1:
+//   z = P z_c + L^-1 (r - P R r),  z_c ~ H0_c^-1 R r,
+// R / P spectral restriction / prolongation, H0_c = L_0 + g_c g_c^T with g_c
+// = grad_h (R m0) on the coarse grid.  ctx->ilz receives L z.
+void ensure_coarse(cl_ctx *ctx)
+{
+    auto &c = ctx->cz;
+    if (c.valid) return;
+    // R m0 (FP32 copy of the stored template into the fine work vector first)
+    run(ctx, CL_K_VEC, [&] { launch_to_f32(ctx->dts, ctx->m0, ctx->ir, ctx->N, ctx->s); });
+    run(ctx, CL_K_FFT, [&] { spectral_resample(ctx->fft, c.fft, 1, ctx->ir, c.m0, ctx->s); });
+    run(ctx, CL_K_FD, [&] { launch_fd_grad(c.g, c.m0, c.G0, ctx->s); });
+    c.valid = true;
+}
+
+void precond_h0_2level(cl_ctx *ctx, const float *r, float *z)
+{
+    ensure_coarse(ctx);
+    auto &c = ctx->cz;
+    const size_t n = 3 * ctx->N;
+    run(ctx, CL_K_FFT, [&] { spectral_resample(ctx->fft, c.fft, 3, r, c.r, ctx->s); });        // R r
+    run(ctx, CL_K_FFT, [&] { spectral_resample(c.fft, ctx->fft, 3, c.r, ctx->ir, ctx->s); });  // P R r
+    run(ctx, CL_K_VEC, [&] { launch_axpy(ctx->ir, r, ctx->ir, -1.0f, n, ctx->s); });           // r - P R r
+    spectral(ctx, 1, 3, ctx->ir, z, nullptr);                                                  // L^-1 (r - P R r)
+    const H0Level L{&c.g, &c.fft, c.N, c.hv, c.G0, c.ir, c.izi, c.ip, c.iLp, c.ih};
+    h0_inner(ctx, L, c.r, c.z);
+    run(ctx, CL_K_FFT, [&] { spectral_resample(c.fft, ctx->fft, 3, c.z, ctx->ir, ctx->s); });  // P z_c
+    run(ctx, CL_K_VEC, [&] { launch_axpy(z, z, ctx->ir, 1.0f, n, ctx->s); });
     spectral(ctx, 0, 3, z, ctx->ilz, nullptr);
 }
 
@@ -497,6 +571,8 @@ void precond(cl_ctx *ctx, const float *r, float *z)
 {
     if (ctx->opt.precond == CL_PRECOND_H0)
         precond_h0(ctx, r, z);
+    else if (ctx->opt.precond == CL_PRECOND_H0_2LEVEL)
+        precond_h0_2level(ctx, r, z);
     else
         spectral(ctx, 1, 3, r, z, nullptr);
 }
@@ -529,7 +605,7 @@ int pcg(cl_ctx *ctx, int max_pcg, double eta, int forced, int *iters)
     // no k = 0 mode, the preconditioner maps it by 1/beta), so the matvecs
     // inside PCG need no FFT pair of their own.  With the zero-velocity
     // preconditioner L z comes from its inner solve.
-    const bool h0 = ctx->opt.precond == CL_PRECOND_H0;
+    const bool h0 = ctx->opt.precond == CL_PRECOND_H0 || ctx->opt.precond == CL_PRECOND_H0_2LEVEL;
     float *pAp = ctx->tmp3;
     if (h0) {
         HIPCHK(hipMemcpyAsync(pAp, ctx->ilz, n * sizeof(float), hipMemcpyDeviceToDevice, ctx->s));
@@ -688,6 +764,12 @@ size_t workspace_bytes(int n1, int n2, int n3, const cl_options &o, bool lean)
     b += 2 * N * sizeof(float);              // c, div v
     b += 12 * 3 * N * sizeof(float);         // v, vtrial, df, db, g, Av, tmp3, PCG x r z p Hp
     if (o.precond == CL_PRECOND_H0) b += 7 * 3 * N * sizeof(float);   // inner CG, L z, previous z
+    if (o.precond == CL_PRECOND_H0_2LEVEL) {
+        const size_t Nc = N / 8;
+        b += 3 * 3 * N * sizeof(float);                                   // fine work vector, L z, previous z
+        b += (1 + 3 + 2 * 3 + 5 * 3) * Nc * sizeof(float);                // R m0, g_c, r_c, z_c, inner CG
+        b += fft_spec_bytes(n1 / 2, n2 / 2, n3 / 2, 3) + 4 * 513 * sizeof(float2);
+    }
     b += fft_spec_bytes(n1, n2, n3, 3);
     b += 4 * 1025 * sizeof(float2) + 4096 * sizeof(double) + 256;   // FFT tables, reduction partials, scalars
     b += (std::max<size_t>((N / 4 + 255) / 256, 6 * (size_t)reduce_blocks(N)) + PCG_NSCAL) * sizeof(double);
@@ -904,9 +986,9 @@ int check_options(const cl_options *o, cl_ctx *ctx)
     if (o->overlap_spectral != 0 && o->overlap_spectral != 1) return fail(ctx, CL_ERR_ARG, "overlap_spectral must be 0 or 1");
     if (o->fault_flip_direction != 0 && o->fault_flip_direction != 1)
         return fail(ctx, CL_ERR_ARG, "fault_flip_direction must be 0 or 1");
-    if (o->precond != CL_PRECOND_SPECTRAL && o->precond != CL_PRECOND_H0)
+    if (o->precond != CL_PRECOND_SPECTRAL && o->precond != CL_PRECOND_H0 && o->precond != CL_PRECOND_H0_2LEVEL)
         return fail(ctx, CL_ERR_ARG, "unknown preconditioner");
-    if (o->precond == CL_PRECOND_H0 && (o->precond_inner < 1 || o->precond_inner > 100))
+    if (o->precond != CL_PRECOND_SPECTRAL && (o->precond_inner < 1 || o->precond_inner > 100))
         return fail(ctx, CL_ERR_ARG, "precond_inner out of range [1, 100]");
     if (!(o->gtol >= 0.0)) return fail(ctx, CL_ERR_ARG, "gtol must be >= 0");
     for (int dt : {o->storage_state, o->storage_adjoint})
@@ -1000,7 +1082,8 @@ int cl_create(cl_ctx **out, int n1, int n2, int n3, const cl_options *opt)
         if (hipMemGetInfo(&fr, &tot) == hipSuccess) limit = fr - fr / 16;
     }
     const bool lean = limit && full > limit;
-    if (lean && opt->precond == CL_PRECOND_H0) return CL_ERR_UNSUPPORTED;
+    if (lean && opt->precond != CL_PRECOND_SPECTRAL) return CL_ERR_UNSUPPORTED;
+    if (opt->precond == CL_PRECOND_H0_2LEVEL && (n1 < 32 || n2 < 32 || n3 < 32)) return CL_ERR_SHAPE;
     if (lean && opt->workspace_cap_bytes && workspace_bytes(n1, n2, n3, *opt, true) > opt->workspace_cap_bytes)
         return CL_ERR_OOM;
     cl_ctx *ctx = new (std::nothrow) cl_ctx();
@@ -1045,6 +1128,23 @@ int cl_create(cl_ctx **out, int n1, int n2, int n3, const cl_options *opt)
         if (opt->precond == CL_PRECOND_H0) {
             float **hv[] = {&ctx->ir, &ctx->izi, &ctx->ip, &ctx->iLp, &ctx->ih, &ctx->ilz, &ctx->zold};
             for (float **pv : hv) *pv = (float *)alloc(3 * N * sizeof(float));
+        }
+        if (opt->precond == CL_PRECOND_H0_2LEVEL) {
+            float **hv[] = {&ctx->ir, &ctx->ilz, &ctx->zold};
+            for (float **pv : hv) *pv = (float *)alloc(3 * N * sizeof(float));
+            auto &c = ctx->cz;
+            c.g = make_grid(n1 / 2, n2 / 2, n3 / 2, opt->interp_order);
+            c.N = N / 8;
+            c.hv = ctx->hv * 8.0;
+            c.m0 = (float *)alloc(c.N * sizeof(float));
+            float **cv[] = {&c.G0, &c.r, &c.z, &c.ir, &c.izi, &c.ip, &c.iLp, &c.ih};
+            for (float **pv : cv) *pv = (float *)alloc(3 * c.N * sizeof(float));
+            try {
+                fft_plan_init(c.fft, n1 / 2, n2 / 2, n3 / 2, 3, alloc);
+            } catch (hipError_t e) {
+                ctx->err = std::string("FFT tables: ") + hipGetErrorString(e);
+                throw Fail{CL_ERR_HIP};
+            }
         }
         // the feet are computed outside PCG, where z is free
         ctx->fscr = ctx->pz;
@@ -1124,6 +1224,7 @@ int cl_set_images(cl_ctx *ctx, const void *m0, const void *m1, int dt)
     ctx->images = true;
     ctx->state = false;
     ctx->gref_valid = false;
+    ctx->cz.valid = false;
     return CL_OK;
     API_END
 }
@@ -1219,7 +1320,7 @@ int cl_precond_apply(cl_ctx *ctx, const float *r, float *z)
     if (!r || !z) return fail(ctx, CL_ERR_ARG, "NULL vector pointer");
     const size_t b = 3 * ctx->N * sizeof(float);
     if (overlap(r, b, z, b)) return fail(ctx, CL_ERR_ALIAS, "r and z overlap");
-    if (ctx->opt.precond == CL_PRECOND_H0 && !ctx->images)
+    if (ctx->opt.precond != CL_PRECOND_SPECTRAL && !ctx->images)
         return fail(ctx, CL_ERR_STATE, "the zero-velocity preconditioner needs the images");
     API_BEGIN
     precond(ctx, r, z);
