@@ -151,6 +151,10 @@ struct QuadArgs {
     int lean;                 // 1: use m[] (storage dtype dt_m), 0: use G[]
     int dt_m;
 };
+// all-level sources by the marching FD8 kernel when sources_march(g, nt)
+bool sources_march(const Grid &g, int nt);
+void launch_inc_sources_march(const Grid &g, int dt_m, const QuadArgs &qa, const float *vt, int nt, float scale,
+                              int dt_q, void *q0, float *S, hipStream_t s);
 // out3 = addend3 (may be NULL) + sum_j w_j lam^j G^j
 void launch_quadrature(const Grid &g, int dt_lam, const QuadArgs &qa, const float *addend3, float *out3, hipStream_t s);
 // same, and per-block FP64 partial sums of dp . out3 in partials[0 .. quadrature_blocks(g, qa))

@@ -242,6 +242,8 @@ __device__ __forceinline__ float fd8_lds(const float *c, int st, float ih)   // 
 // MODE 0: out3 = add + sum_t w_t lam^t grad_h m^t (NL = qa.count levels),
 //         optional FP64 partials of dp . out3 per block.
 // MODE 1: out1 = scale * (-vt . grad_h m^0) (NL = 1).
+// MODE 2: the incremental sources of every level at once, s^t = -vt .
+//         grad_h m^t: out1 = scale * s^0, out3[(t - 1) N ..] = s^t, t >= 1.
 template <typename Tm, typename Tl, typename To, int NL, int MODE>
 __global__ __launch_bounds__(TPB_M) void k_fd_march(Grid g, MarchGeom mg, QuadArgs qa, const float *__restrict__ add,
                                                     float *__restrict__ out3, const float *__restrict__ dp,
@@ -330,13 +332,18 @@ __global__ __launch_bounds__(TPB_M) void k_fd_march(Grid g, MarchGeom mg, QuadAr
                 b0 = fmaf(lw[t], d0, b0);
                 b1 = fmaf(lw[t], d1, b1);
                 b2 = fmaf(lw[t], d2, b2);
+            } else if (MODE == 2) {
+                const float sv = -(e0 * d0 + e1 * d1 + e2 * d2);
+                if (t == 0) stf(out1 + p, scale * sv);
+                else out3[(size_t)(t - 1) * N + p] = sv;
             } else {
                 b0 = d0;
                 b1 = d1;
                 b2 = d2;
             }
         }
-        if (MODE == 0) {
+        if (MODE == 2) {
+        } else if (MODE == 0) {
             if (add) {
                 b0 += e0;
                 b1 += e1;
@@ -394,6 +401,11 @@ void launch_state_grad(const Grid &g, int dt_m, const StateGradArgs &a, int coun
         hipLaunchKernelGGL((k_state_grad<Tm>), dim3((g.N + TPB - 1) / TPB, count), dim3(TPB), 0, s, g, a);
     });
 }
+
+bool sources_march(const Grid &g, int nt) { return g.n3 >= 64 && g.n2 >= 8 && nt + 1 <= 5; }
+
+void launch_inc_sources_march(const Grid &g, int dt_m, const QuadArgs &qa, const float *vt, int nt, float scale,
+                              int dt_q, void *q0, float *S, hipStream_t s);
 
 void launch_inc_sources(const Grid &g, const float *G, const float *vt, int nt, float scale, int dt_q, void *q0,
                         float *S, hipStream_t s)
@@ -487,6 +499,30 @@ void launch_quadrature_dot(const Grid &g, int dt_lam, const QuadArgs &qa, const 
             hipLaunchKernelGGL((k_quadrature<Tl>), dim3(quadrature_blocks(g, qa)), dim3(TPB), 0, s, g, qa, addend3,
                                out3, dp, partials);
         }
+    });
+}
+
+// sources of every level from m^0 .. m^nt by the marching kernel (the
+// same FD8 and products as from stored gradients, bit for bit)
+void launch_inc_sources_march(const Grid &g, int dt_m, const QuadArgs &qa, const float *vt, int nt, float scale,
+                              int dt_q, void *q0, float *S, hipStream_t s)
+{
+    with_dtype(dt_m, [&](auto tm) {
+        using Tm = decltype(tm);
+        with_dtype(dt_q, [&](auto tq) {
+            using Tq = decltype(tq);
+            const dim3 grid(march_blocks(g));
+            switch (nt + 1) {
+#define CLH_SM(NL)                                                                                                   \
+    case NL:                                                                                                         \
+        hipLaunchKernelGGL((k_fd_march<Tm, float, Tq, NL, 2>), grid, dim3(TPB_M), 0, s, g, march_geom(g), qa,        \
+                           (const float *)nullptr, S, (const float *)nullptr, (double *)nullptr, vt, scale, (Tq *)q0); \
+        break;
+                CLH_SM(2) CLH_SM(3) CLH_SM(4) CLH_SM(5)
+#undef CLH_SM
+            default: break;
+            }
+        });
     });
 }
 
