@@ -506,6 +506,149 @@ __global__ __launch_bounds__(TPB) void k_fft_cols(float2 *__restrict__ spec, con
     }
 }
 
+// --- register-resident x3 passes for rows of M = 16 R2 complex values (M =
+// 128 or 64, i.e. n3 = 256 or 128), NR = 256 / R2 rows per tile.  With input
+// index n = c + 16 d and output index k = b + R2 a (M = 16 R2),
+//   X[b + R2 a] = sum_c W_16^{ac} W_M^{bc} sum_d x[c + 16 d] W_R2^{bd}
+// (conjugate twiddles for the inverse): the length-R2 DFTs over d run on the
+// "c" layout (thread = row, c; 16 / R2 pairs per thread), the length-16 DFTs
+// over c on the "b" layout (thread = row, b), joined by one LDS exchange
+// [row][c][b] (row pitch 17 R2 + 16 complex).  Loads on the c layout read
+// 16 consecutive complex values per row per instruction.
+template <int R2> constexpr int rows_pitch() { return 17 * R2 + 16; }
+
+template <int R2, bool INV>
+__device__ __forceinline__ void rows_cb(float2 (&v)[16], float2 *ex, const float2 *tw)
+{
+    constexpr int PP = 16 / R2, RS = rows_pitch<R2>();
+    const int c = threadIdx.x & 15, r0 = threadIdx.x >> 4;
+#pragma unroll
+    for (int u = 0; u < PP; ++u) {
+        const int row = r0 + 16 * u;
+        float2 w[R2];
+#pragma unroll
+        for (int d = 0; d < R2; ++d) w[d] = v[u * R2 + d];
+        dft_reg<R2, INV>(w);
+#pragma unroll
+        for (int b = 0; b < R2; ++b) {
+            float2 t = w[b];
+            if (b) t = cmul(t, INV ? cconj(tw[b * c]) : tw[b * c]);
+            ex[row * RS + c * (R2 + 1) + b] = t;
+        }
+    }
+    __syncthreads();
+    const int b = threadIdx.x % R2, row = threadIdx.x / R2;
+#pragma unroll
+    for (int cc = 0; cc < 16; ++cc) v[cc] = ex[row * RS + cc * (R2 + 1) + b];
+    dft_reg<16, INV>(v);                                      // v[a] = X[b + R2 a]
+}
+
+// x3 forward: real rows -> half spectrum
+template <int R2>
+__global__ __launch_bounds__(TPB) void k_fft_rows_r2c(const float *__restrict__ in, float2 *__restrict__ spec,
+                                                      const float2 *__restrict__ twM, const float2 *__restrict__ tw3,
+                                                      size_t in_cs, size_t spec_cs)
+{
+    constexpr int M = 16 * R2, NR = 256 / R2, PP = 16 / R2, nh = M + 1;
+    __shared__ float2 twm[M], tws[M + 1];
+    __shared__ float2 ex[NR * rows_pitch<R2>()];
+    const int comp = blockIdx.y;
+    const size_t row0 = (size_t)blockIdx.x * NR;
+    const float2 *src = (const float2 *)(in + comp * in_cs) + row0 * M;
+    float2 *dst = spec + comp * spec_cs + row0 * nh;
+    for (int t = threadIdx.x; t < M; t += TPB) twm[t] = twM[t];
+    for (int t = threadIdx.x; t <= M; t += TPB) tws[t] = tw3[t];
+    const int c = threadIdx.x & 15, r0 = threadIdx.x >> 4;
+    float2 v[16];
+#pragma unroll
+    for (int u = 0; u < PP; ++u)
+#pragma unroll
+        for (int d = 0; d < R2; ++d) v[u * R2 + d] = src[(size_t)(r0 + 16 * u) * M + c + 16 * d];
+    __syncthreads();                                          // twiddle tables
+    rows_cb<R2, false>(v, ex, twm);
+    // X[k] = E + W_n3^k O with E = (Z[k] + conj Z[M-k]) / 2, O = -i (Z[k] -
+    // conj Z[M-k]) / 2; Z[M-k] of k = b + R2 a is v[15 - a] of the lane with
+    // b' = R2 - b (b > 0) or this lane's v[(16 - a) mod 16] (b = 0)
+    const int b = threadIdx.x % R2, row = threadIdx.x / R2;
+    const int lane = threadIdx.x & 63, partner = lane - b + ((R2 - b) & (R2 - 1));
+    float2 *drow = dst + (size_t)row * nh;
+#pragma unroll
+    for (int a = 0; a < 16; ++a) {
+        float2 zc;
+        zc.x = __shfl(v[15 - a].x, partner, 64);
+        zc.y = __shfl(v[15 - a].y, partner, 64);
+        if (b == 0) zc = v[(16 - a) & 15];
+        zc = cconj(zc);
+        const float2 zk = v[a];
+        const int k = b + R2 * a;
+        const float2 E = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y + zc.y));
+        const float2 O = make_float2(0.5f * (zk.y - zc.y), -0.5f * (zk.x - zc.x));
+        drow[k] = cadd(E, cmul(tws[k], O));
+    }
+    if (b == 0) {
+        // k = M: Z[M mod M] = Z[0]
+        const float2 zk = v[0], zc = cconj(v[0]);
+        const float2 E = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y + zc.y));
+        const float2 O = make_float2(0.5f * (zk.y - zc.y), -0.5f * (zk.x - zc.x));
+        drow[M] = cadd(E, cmul(tws[M], O));
+    }
+}
+
+// x3 inverse: half spectrum -> real rows (unnormalised), optional add
+template <int R2>
+__global__ __launch_bounds__(TPB) void k_fft_rows_c2r(const float2 *__restrict__ spec, float *__restrict__ out,
+                                                      const float *__restrict__ add, const float2 *__restrict__ twM,
+                                                      const float2 *__restrict__ tw3, size_t out_cs, size_t spec_cs)
+{
+    constexpr int M = 16 * R2, NR = 256 / R2, PP = 16 / R2, nh = M + 1;
+    __shared__ float2 twm[M], tws[M + 1];
+    __shared__ float2 ex[NR * rows_pitch<R2>()];
+    const int comp = blockIdx.y;
+    const size_t row0 = (size_t)blockIdx.x * NR;
+    const float2 *src = spec + comp * spec_cs + row0 * nh;
+    float2 *dst = (float2 *)(out + comp * out_cs) + row0 * M;
+    const float2 *ad = add ? (const float2 *)(add + comp * out_cs) + row0 * M : nullptr;
+    for (int t = threadIdx.x; t < M; t += TPB) twm[t] = twM[t];
+    for (int t = threadIdx.x; t <= M; t += TPB) tws[t] = tw3[t];
+    const int c = threadIdx.x & 15, r0 = threadIdx.x >> 4;
+    float2 xa[16], xb[16];
+#pragma unroll
+    for (int u = 0; u < PP; ++u)
+#pragma unroll
+        for (int d = 0; d < R2; ++d) {
+            const float2 *srow = src + (size_t)(r0 + 16 * u) * nh;
+            const int k = c + 16 * d;
+            xa[u * R2 + d] = srow[k];
+            xb[u * R2 + d] = srow[M - k];
+        }
+    __syncthreads();                                          // twiddle tables
+    // Z[k] = (X[k] + conj X[M-k]) + i e^{+2 pi i k / n3} (X[k] - conj X[M-k])
+    float2 v[16];
+#pragma unroll
+    for (int u = 0; u < PP; ++u)
+#pragma unroll
+        for (int d = 0; d < R2; ++d) {
+            const int k = c + 16 * d;
+            const float2 a = xa[u * R2 + d], bb = cconj(xb[u * R2 + d]);
+            const float2 sum = cadd(a, bb), dif = csub(a, bb);
+            const float2 wd = cmul(cconj(tws[k]), dif);
+            v[u * R2 + d] = make_float2(sum.x - wd.y, sum.y + wd.x);
+        }
+    rows_cb<R2, true>(v, ex, twm);
+    const int b = threadIdx.x % R2, row = threadIdx.x / R2;
+#pragma unroll
+    for (int a = 0; a < 16; ++a) {
+        const size_t o = (size_t)row * M + b + R2 * a;
+        float2 val = v[a];
+        if (ad) {
+            const float2 t = ad[o];
+            val.x += t.x;
+            val.y += t.y;
+        }
+        dst[o] = val;
+    }
+}
+
 // Copy the half-spectrum modes with |k_d| < min(na_d, nb_d)/2 from grid a
 // to grid b (the coarse Nyquist planes are dropped), zero elsewhere.
 __global__ __launch_bounds__(TPB) void k_mode_copy(const float2 *__restrict__ sa, float2 *__restrict__ sb, int a1, int a2,
@@ -619,6 +762,46 @@ void launch_cols(int L, dim3 grid, float2 *spec, const float2 *tw, int nh, size_
                            beta, scale, n1, n2);
 }
 
+bool rows_ok(int n3) { return n3 == 256 || n3 == 128; }
+
+// x3 forward pass (real rows -> half spectrum), nc components
+void pass_r2c(const FFTPlan &P, const float *in, int nc, int logM, int lognl3, size_t lds3, size_t spec_cs,
+              hipStream_t s)
+{
+    const size_t N = (size_t)P.n1 * P.n2 * P.n3;
+    const int nrows = P.n1 * P.n2;
+    if (rows_ok(P.n3) && nrows % (256 / (P.n3 / 32)) == 0) {
+        if (P.n3 == 256)
+            hipLaunchKernelGGL((k_fft_rows_r2c<8>), dim3(nrows / 32, nc), dim3(TPB), 0, s, in, P.spec, P.twM, P.twS,
+                               N, spec_cs);
+        else
+            hipLaunchKernelGGL((k_fft_rows_r2c<4>), dim3(nrows / 64, nc), dim3(TPB), 0, s, in, P.spec, P.twM, P.twS,
+                               N, spec_cs);
+        return;
+    }
+    hipLaunchKernelGGL(k_fft_x3_r2c, dim3(nrows >> lognl3, nc), dim3(TPB), lds3, s, in, P.spec, P.twM, P.twS, logM,
+                       lognl3, nrows, N, spec_cs);
+}
+
+// x3 inverse pass (half spectrum -> real rows, optional add), nc components
+void pass_c2r(const FFTPlan &P, float *out, const float *add, int nc, int logM, int lognl3, size_t lds3,
+              size_t spec_cs, hipStream_t s)
+{
+    const size_t N = (size_t)P.n1 * P.n2 * P.n3;
+    const int nrows = P.n1 * P.n2;
+    if (rows_ok(P.n3) && nrows % (256 / (P.n3 / 32)) == 0) {
+        if (P.n3 == 256)
+            hipLaunchKernelGGL((k_fft_rows_c2r<8>), dim3(nrows / 32, nc), dim3(TPB), 0, s, P.spec, out, add, P.twM,
+                               P.twS, N, spec_cs);
+        else
+            hipLaunchKernelGGL((k_fft_rows_c2r<4>), dim3(nrows / 64, nc), dim3(TPB), 0, s, P.spec, out, add, P.twM,
+                               P.twS, N, spec_cs);
+        return;
+    }
+    hipLaunchKernelGGL(k_fft_x3_c2r, dim3(nrows >> lognl3, nc), dim3(TPB), lds3, s, P.spec, out, add, P.twM, P.twS,
+                       logM, lognl3, nrows, N, spec_cs);
+}
+
 // x2 pass over every x1 plane (forward or inverse), nc components
 void pass_x2(const FFTPlan &P, bool inv, int nc, int logC2, size_t lds2, size_t spec_cs, hipStream_t s)
 {
@@ -690,13 +873,11 @@ void spectral_apply(const FFTPlan &P, int kind, float beta, float beta_w, int nc
         const float *inc = in + c0 * N;
         float *outc = out + c0 * N;
         const float *addc = add ? add + c0 * N : nullptr;
-        hipLaunchKernelGGL(k_fft_x3_r2c, dim3(nrows >> lognl3, nc), dim3(TPB), lds3, s, inc, P.spec, P.twM, P.twS,
-                           logM, lognl3, nrows, N, spec_cs);
+        pass_r2c(P, inc, nc, logM, lognl3, lds3, spec_cs, s);
         pass_x2(P, false, nc, logC2, lds2, spec_cs, s);
         pass_x1(P, 0, kind, beta, scale, nc, logC1, lds1, spec_cs, s);
         pass_x2(P, true, nc, logC2, lds2, spec_cs, s);
-        hipLaunchKernelGGL(k_fft_x3_c2r, dim3(nrows >> lognl3, nc), dim3(TPB), lds3, s, P.spec, outc, addc, P.twM,
-                           P.twS, logM, lognl3, nrows, N, spec_cs);
+        pass_c2r(P, outc, addc, nc, logM, lognl3, lds3, spec_cs, s);
     }
 }
 
@@ -730,8 +911,7 @@ PassGeom geom(const FFTPlan &P)
 
 void forward3(const FFTPlan &P, const PassGeom &G, int nc, const float *in, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_fft_x3_r2c, dim3(G.nrows >> G.lognl3, nc), dim3(TPB), G.lds3, s, in, P.spec, P.twM, P.twS,
-                       G.logM, G.lognl3, G.nrows, G.N, G.spec_cs);
+    pass_r2c(P, in, nc, G.logM, G.lognl3, G.lds3, G.spec_cs, s);
     pass_x2(P, false, nc, G.logC2, G.lds2, G.spec_cs, s);
     pass_x1(P, 1, 2, 0.f, 1.f, nc, G.logC1, G.lds1, G.spec_cs, s);
 }
@@ -740,8 +920,7 @@ void inverse3(const FFTPlan &P, const PassGeom &G, int nc, float *out, hipStream
 {
     pass_x1(P, 2, 2, 0.f, 1.f, nc, G.logC1, G.lds1, G.spec_cs, s);
     pass_x2(P, true, nc, G.logC2, G.lds2, G.spec_cs, s);
-    hipLaunchKernelGGL(k_fft_x3_c2r, dim3(G.nrows >> G.lognl3, nc), dim3(TPB), G.lds3, s, P.spec, out, nullptr, P.twM,
-                       P.twS, G.logM, G.lognl3, G.nrows, G.N, G.spec_cs);
+    pass_c2r(P, out, nullptr, nc, G.logM, G.lognl3, G.lds3, G.spec_cs, s);
 }
 
 void coupled3(const FFTPlan &P, int kind, float beta_v, float beta_w, const float *in, float *out, hipStream_t s)

@@ -466,8 +466,10 @@ void launch_quad_march(const Grid &g, const QuadArgs &qa, const float *add, floa
 
 // The marching kernel reads m^j (plus halo planes) instead of the stored
 // gradients (3 fields per time level), so it is used in both layouts; its
-// derivatives are the stored ones bit for bit.
-bool quadrature_marches(const Grid &g, const QuadArgs &qa) { return march_ok(g) && qa.count <= MAX_NL; }
+// derivatives are the stored ones bit for bit.  More than MAX_NL time
+// levels are summed in groups of MAX_NL, each launch adding its group to
+// the previous partial sum (the first adds the addend).
+bool quadrature_marches(const Grid &g, const QuadArgs &qa) { (void)qa; return march_ok(g); }
 
 int quadrature_blocks(const Grid &g, const QuadArgs &qa)
 {
@@ -487,7 +489,19 @@ void launch_quadrature_dot(const Grid &g, int dt_lam, const QuadArgs &qa, const 
         if (quadrature_marches(g, qa)) {
             with_dtype(qa.dt_m, [&](auto tm) {
                 using Tm = decltype(tm);
-                launch_quad_march<Tm, Tl>(g, qa, addend3, out3, dp, partials, s);
+                for (int t0 = 0; t0 < qa.count; t0 += MAX_NL) {
+                    QuadArgs sub = qa;
+                    sub.count = std::min(MAX_NL, qa.count - t0);
+                    for (int t = 0; t < sub.count; ++t) {
+                        sub.lam[t] = qa.lam[t0 + t];
+                        sub.m[t] = qa.m[t0 + t];
+                        sub.G[t] = qa.G[t0 + t];
+                        sub.w[t] = qa.w[t0 + t];
+                    }
+                    const bool last = t0 + MAX_NL >= qa.count;
+                    launch_quad_march<Tm, Tl>(g, sub, t0 == 0 ? addend3 : out3, out3, last ? dp : nullptr,
+                                              last ? partials : nullptr, s);
+                }
             });
         } else if (qa.lean) {
             with_dtype(qa.dt_m, [&](auto tm) {
