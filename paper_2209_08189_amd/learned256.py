@@ -7,8 +7,12 @@ and from the network's prediction.
 
 Two steps, each one process:
 
-  python -m paper_2209_08189_amd.learned256 train --out DIR
-      labels + Adam training; writes DIR/net_params.npy and DIR/train.json
+  python -m paper_2209_08189_amd.learned256 train --out DIR [--init-params P]
+      labels + Adam training; writes DIR/net_params.npy and DIR/train.json.
+      The 2000 labelling solves take longer than one GPU session allows and
+      labels do not outlive a session, so the training set is labelled and
+      trained in shards (seeds 1000-1999, then 2000-2999 starting from the
+      first shard's parameters)
   python -m paper_2209_08189_amd.learned256 eval --params DIR/net_params.npy --out FILE.json
       per held-out seed: plain FP32 and learned + mixed-precision solves, with
       the spectral preconditioner and with the zero-velocity preconditioner
@@ -33,6 +37,49 @@ def seed_range(s):
     return list(range(int(a), int(b)))
 
 
+def label_pairs(seeds, n, host, precond, max_pcg, log_every):
+    """Training pairs restricted to the network grid: (m0, m1, v) with v the
+    converged velocity of the Gauss-Newton solve from v = 0 (relative
+    gradient 1e-2).  One context transports the phantom to make m1, one
+    solves; both are reused from pair to pair (set_images / set_velocity
+    reset every derived quantity).  Returns the pairs and per-pair solve
+    records."""
+    import torch
+    from .claire import Registration, Resampler
+    from .warmstart import _dev
+    shape = (n,) * 3
+    fwd = Registration(shape)
+    sol = Registration(shape, gtol=1e-2, max_outer=50, max_pcg=max_pcg, precond=precond, precond_inner=12)
+    down = Resampler(shape, (n // 2,) * 3)
+    zero = torch.zeros((3,) + shape, dtype=torch.float32, device="cuda")
+    data, recs = [], []
+    t0 = time.perf_counter()
+    for i, (s, hp) in enumerate(zip(seeds, host.pairs(n, seeds))):
+        img, _, v_true, n0, n1 = hp
+        ph = _dev(img)
+        fwd.set_images(ph, ph)
+        fwd.set_velocity(_dev(v_true))
+        m1 = fwd.deformed_template() + _dev(n1)
+        m0 = ph + _dev(n0)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        sol.set_images(m0, m1)
+        sol.set_velocity(zero)
+        rep = sol.solve()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - ts
+        data.append((down(m0), down(m1), down(sol.velocity())))
+        recs.append({"seed": s, "s": dt, "gn": rep["outer_iters"], "pcg": rep["pcg_iters_total"],
+                     "status": rep["status_name"], "rel_grad": rep["gnorm"] / rep["gref"]})
+        if i % log_every == 0 or i == len(seeds) - 1:
+            log("label %d/%d seed %d: %d GN, %d PCG, %.2f s, %s (%.0f s elapsed)"
+                % (i + 1, len(seeds), s, rep["outer_iters"], rep["pcg_iters_total"], dt, rep["status_name"],
+                   time.perf_counter() - t0))
+    fwd.close()
+    sol.close()
+    return data, recs
+
+
 def cmd_train(args):
     from . import warmstart
     host = warmstart.HostPairs()          # before the GPU is touched
@@ -41,12 +88,15 @@ def cmd_train(args):
     torch.cuda.set_device(0)
     seeds = seed_range(args.train_seeds)
     t0 = time.perf_counter()
-    data = warmstart.generate(seeds, n=args.n, n_net=args.n // 2, log=log, host=host, max_pcg=args.max_pcg,
-                              precond=args.label_precond, log_every=args.log_every)
+    data, recs = label_pairs(seeds, args.n, host, args.label_precond, args.max_pcg, args.log_every)
     t_label = time.perf_counter() - t0
     host.close()
     log("labels: %d pairs in %.1f s" % (len(data), t_label))
     net = Net(in_n=args.n // 2, seed=1, lr=args.lr)
+    if args.init_params:
+        # continue from the parameters of an earlier shard (fresh Adam moments)
+        net.set_params(torch.from_numpy(np.load(args.init_params)).cuda())
+        log("initial parameters from %s" % args.init_params)
     t1 = time.perf_counter()
     hist = warmstart.train(net, data, args.epochs, batch=args.batch, log=log, seed=0)
     torch.cuda.synchronize()
@@ -58,7 +108,8 @@ def cmd_train(args):
         errs.append(float((pred - lab).norm() / lab.norm()))
     os.makedirs(args.out, exist_ok=True)
     np.save(os.path.join(args.out, "net_params.npy"), net.params().cpu().numpy())
-    rec = {"train_seeds": args.train_seeds, "pairs": len(data), "grid": args.n, "net_grid": args.n // 2,
+    rec = {"train_seeds": args.train_seeds, "init_params": os.path.basename(args.init_params or ""),
+           "label_solves": recs, "pairs": len(data), "grid": args.n, "net_grid": args.n // 2,
            "label_precond": args.label_precond, "max_pcg": args.max_pcg, "epochs": args.epochs,
            "batch": args.batch, "lr": args.lr, "label_s": t_label, "train_s": t_train,
            "train_sample_steps": args.epochs * len(data), "loss_per_epoch": hist,
@@ -66,6 +117,19 @@ def cmd_train(args):
     json.dump(rec, open(os.path.join(args.out, "train.json"), "w"), indent=1)
     log("training: %d epochs in %.1f s, final loss %.4e, train prediction error %.3f"
         % (args.epochs, t_train, hist[-1], float(np.mean(errs))))
+
+
+def summarise_training(tr):
+    """A shard's training record with its per-pair labelling solves reduced
+    to their statistics."""
+    ls = tr.pop("label_solves", [])
+    if ls:
+        t = np.array([r["s"] for r in ls])
+        tr["label_solve_s"] = {"mean": float(t.mean()), "max": float(t.max()), "total": float(t.sum())}
+        tr["label_gn_mean"] = float(np.mean([r["gn"] for r in ls]))
+        tr["label_pcg_mean"] = float(np.mean([r["pcg"] for r in ls]))
+        tr["label_status"] = {k: int(sum(r["status"] == k for r in ls)) for k in sorted({r["status"] for r in ls})}
+    return tr
 
 
 def cmd_eval(args):
@@ -146,8 +210,7 @@ def cmd_eval(args):
     rec = {"eval_seeds": args.eval_seeds, "grid": n, "net_grid": n // 2, "storage_mixed": list(storage),
            "max_pcg": args.max_pcg, "gtol": 1e-2, "params": os.path.basename(args.params),
            "summary": summary, "rows": rows}
-    if args.train_record and os.path.exists(args.train_record):
-        rec["training"] = json.load(open(args.train_record))
+    rec["training"] = [summarise_training(json.load(open(p))) for p in (args.train_record or []) if os.path.exists(p)]
     json.dump(rec, open(args.out, "w"), indent=1)
     log("summary: %s" % json.dumps(summary))
 
@@ -165,10 +228,11 @@ def main():
     t.add_argument("--batch", type=int, default=2)
     t.add_argument("--lr", type=float, default=1e-4)
     t.add_argument("--log-every", type=int, default=25)
+    t.add_argument("--init-params", default=None, help="start from these parameters (an earlier shard's)")
     e = sub.add_parser("eval")
     e.add_argument("--params", required=True)
     e.add_argument("--out", required=True)
-    e.add_argument("--train-record", default=None)
+    e.add_argument("--train-record", action="append", help="train.json of each shard (repeatable)")
     e.add_argument("--n", type=int, default=256)
     e.add_argument("--eval-seeds", default="10000:10100")
     e.add_argument("--max-pcg", type=int, default=40)

@@ -14,8 +14,11 @@ solid is carried far outside itself (Dice 0 before and after registration):
 --rscale and --vscale scale the radius and the velocity, and the record
 states both.  n_t of the registrations grows
 with the resolution (4 at 256^3) for trilinear interpolation, as the paper
-does to keep the CFL number fixed, and is 4 for tricubic; --nt-max caps it
-(a 1024^3 context with n_t = 16 does not fit one GPU's memory).
+does to keep the CFL number fixed, and is 4 for tricubic; --nt-max caps it.
+A 1024^3 context with n_t = 16 takes 244 GiB with 16-bit field storage (the
+lean layout), so at that size the images and velocities stay in host memory
+and enter the device only while a context copies them, and the base level
+is scored with its own solving context.
 
 At large base grids: --gen-nt / --gen-storage set the generator's steps and
 field storage, --storage the registration contexts' field storage, and
@@ -54,6 +57,8 @@ def main():
                     help="field storage of the registration and evaluation contexts")
     ap.add_argument("--top-from-coarse", action="store_true")
     ap.add_argument("--top-chunk", type=int, default=2)
+    ap.add_argument("--gtol", type=float, default=1e-2,
+                    help="relative gradient tolerance of every solve (the paper's SYN runs use 5e-2)")
     a = ap.parse_args()
     log = lambda m: print("[syn] " + m, file=sys.stderr, flush=True)
     import torch
@@ -96,6 +101,32 @@ def main():
            "top_from_coarse": a.top_from_coarse, "label_voxels": np.bincount(labels0.ravel(), minlength=11)[1:].tolist(),
            "scored_labels": list(lab_ids), "dice_pre": pre, "levels": []}
     mis0 = 0.5 * float(((m0 - m1).double() ** 2).sum()) * (2 * np.pi / n) ** 3
+    # host copies of the images: at 1024^3 with n_t = 16 a context takes most
+    # of the device, so the images (and velocities) are moved in only while a
+    # context copies them
+    m0_h, m1_h = m0.cpu(), m1.cpu()
+    labels0_u8 = labels0.astype(np.uint8)
+    big = n >= 1024
+
+    def images_into(reg):
+        a0, a1 = m0_h.cuda(), m1_h.cuda()
+        reg.set_images(a0, a1)
+        del a0, a1
+        torch.cuda.empty_cache()
+
+    def velocity_into(reg, v_h):
+        vd = v_h.cuda()
+        reg.set_velocity(vd)
+        del vd
+        torch.cuda.empty_cache()
+
+    def free_mib():
+        f, t = torch.cuda.mem_get_info()
+        return "%.1f of %.1f GiB free" % (f / 2 ** 30, t / 2 ** 30)
+
+    if big:
+        del m0, m1
+        torch.cuda.empty_cache()
     levels = [int(x) for x in a.levels.split(",")]
     if a.top_from_coarse:
         levels = sorted(levels)
@@ -106,12 +137,16 @@ def main():
         if L == n and a.top_from_coarse and prev is not None:
             # one solve at the coarser level's weights from its velocity
             bv, bw, vp = prev
-            reg = Registration(shape, nt=nt, interp=a.interp, beta_v=bv, beta_w=bw, max_outer=a.top_chunk,
-                               max_pcg=a.max_pcg, **st)
-            reg.set_images(m0, m1)
-            reg.set_velocity(vp)
+            vp_h = vp.cpu()
             del vp
             prev = None
+            torch.cuda.empty_cache()
+            reg = Registration(shape, nt=nt, interp=a.interp, beta_v=bv, beta_w=bw, max_outer=a.top_chunk,
+                               max_pcg=a.max_pcg, gtol=a.gtol, **st)
+            log("level %d: context n_t %d (layout %d), %s" % (L, nt, reg.layout(), free_mib()))
+            images_into(reg)
+            velocity_into(reg, vp_h)
+            del vp_h
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             gn = pcg = 0
@@ -129,9 +164,10 @@ def main():
             srep = {"beta_v": bv, "beta_w": bw, "solves": 1, "gn_total": gn, "pcg_total": pcg, "jmin": jl,
                     "jmax": jh, "status_name": rep["status_name"]}
         else:
-            m0c = m0[::s, ::s, ::s].contiguous()
-            m1c = m1[::s, ::s, ::s].contiguous()
-            reg = Registration((L,) * 3, nt=nt, interp=a.interp, max_outer=a.max_outer, max_pcg=a.max_pcg, **st)
+            m0c = m0_h[::s, ::s, ::s].contiguous().cuda()
+            m1c = m1_h[::s, ::s, ::s].contiguous().cuda()
+            reg = Registration((L,) * 3, nt=nt, interp=a.interp, max_outer=a.max_outer, max_pcg=a.max_pcg,
+                               gtol=a.gtol, **st)
             reg.set_images(m0c, m1c)
             del m0c, m1c
             torch.cuda.synchronize()
@@ -140,20 +176,43 @@ def main():
             torch.cuda.synchronize()
             ts = time.perf_counter() - t0
         vc = reg.velocity()
-        reg.close()
-        del reg
-        v = vc if L == n else Resampler((L,) * 3, shape)(vc)
+        if L == n:
+            # the base grid itself: score with the solving context
+            v = vc
+            base = reg
+        else:
+            reg.close()
+            del reg
+            v = Resampler((L,) * 3, shape)(vc)
+            base = None
         del vc
+        torch.cuda.empty_cache()
         # the prolonged velocity on the base grid: labels, relative mismatch
         # and J bounds there
-        base = Registration(shape, nt=nt_for(n), interp=a.interp, **st)
-        base.set_images(m0, m1)
-        base.set_velocity(v)
+        if base is None:
+            v_h = v.cpu() if big else None
+            if big:
+                del v
+                torch.cuda.empty_cache()
+            base = Registration(shape, nt=nt_for(n), interp=a.interp, **st)
+            images_into(base)
+            if big:
+                velocity_into(base, v_h)
+                v = v_h
+            else:
+                base.set_velocity(v)
+        elif big:
+            v = v.cpu()
+            torch.cuda.empty_cache()
+            images_into(base)
         J, mis, _ = base.objective()
         _, jlo, jhi = base.jacobian_det()
-        lw = warp_labels(labels0, None, nlabels=11, reg=base)
+        if big:
+            log("level %d scoring: %s" % (L, free_mib()))
+        lw = warp_labels(labels0_u8, None, nlabels=11, reg=base)
         base.close()
         del base
+        torch.cuda.empty_cache()
         d = dice(lw, labels1, labels=lab_ids)
         del lw
         row = {"level": L, "nt": nt, "beta_v": srep["beta_v"], "beta_w": srep["beta_w"], "search_s": ts,

@@ -64,8 +64,21 @@ class HostPairs:
                 else:
                     os.environ[k] = v
 
-    def pairs(self, n, seeds):
-        return self.pool.imap(_host_pair_job, [(n, s) for s in seeds])
+    def pairs(self, n, seeds, ahead=32):
+        """Pairs in seed order, at most `ahead` generated ahead of the
+        consumer (each pair holds about 0.5 GB of host memory at 256^3)."""
+        from collections import deque
+        seeds = list(seeds)
+        q, k = deque(), 0
+        while k < len(seeds) and len(q) < ahead:
+            q.append(self.pool.apply_async(_host_pair_job, ((n, seeds[k]),)))
+            k += 1
+        while q:
+            r = q.popleft().get()
+            if k < len(seeds):
+                q.append(self.pool.apply_async(_host_pair_job, ((n, seeds[k]),)))
+                k += 1
+            yield r
 
     def close(self):
         self.pool.close()
