@@ -138,6 +138,21 @@ def cpu_baseline(args, shape, img, v_true, n0, n1):
             "cpu_model": cpu_model, "legs": legs}
 
 
+def full_scale_learned_record():
+    """Summary of the committed full-scale learned warm-start record (2000
+    training pairs, 100 held-out pairs; python -m paper_2209_08189_amd.learned256),
+    quoted from the file, not measured by this run."""
+    path = os.path.join(ROOT, "profiles", "learned_256.json")
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    return {"record": "profiles/learned_256.json", "measured_in_this_run": False,
+            "eval_seeds": rec.get("eval_seeds"), "summary": rec.get("summary"),
+            "training": [{k: t.get(k) for k in ("train_seeds", "pairs", "epochs", "lr", "label_precond")}
+                         for t in rec.get("training", [])]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -567,6 +582,7 @@ def main():
         "solve_fp32_h0_precond": h0,
         "solve_fp32": solve,
         "learned_warm_start": learned,
+        "learned_warm_start_full_scale": full_scale_learned_record(),
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

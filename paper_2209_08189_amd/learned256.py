@@ -17,6 +17,10 @@ Two steps, each one process:
       per held-out seed: plain FP32 and learned + mixed-precision solves, with
       the spectral preconditioner and with the zero-velocity preconditioner
 
+  python -m paper_2209_08189_amd.learned256 step [--n 128] [--steps 3]
+      times training steps and forward passes on random inputs (the
+      convolution kernels' workload, for profiling)
+
 Progress goes to stderr, one line per step.
 """
 import argparse
@@ -132,6 +136,46 @@ def summarise_training(tr):
     return tr
 
 
+def summarise(rows):
+    """Means over the held-out seeds, the learned runs against the plain ones,
+    and the spread between the two plain runs (spectral and zero-velocity
+    preconditioner, both from v = 0 to the same tolerance): the latter is
+    how far two correct stopping points of the same solve lie apart."""
+    def mean(f):
+        return float(np.mean([f(r) for r in rows]))
+
+    summary = {}
+    for name in ("plain", "learned_mixed", "plain_h0", "learned_mixed_h0"):
+        summary[name] = {"time_to_tol_s": mean(lambda r: r[name]["s"]), "gn": mean(lambda r: r[name]["gn"]),
+                         "pcg": mean(lambda r: r[name]["pcg"]), "r": mean(lambda r: r[name]["r"]),
+                         "not_converged": int(sum(r[name]["status"] != "ok" for r in rows))}
+    for a, b in (("learned_mixed", "plain"), ("learned_mixed_h0", "plain_h0"), ("plain_h0", "plain")):
+        k = "%s_vs_%s" % (a, b)
+        d_r = [abs(r[a]["r"] - r[b]["r"]) for r in rows]
+        d_rel = [abs(r[a]["mismatch"] - r[b]["mismatch"]) / r[b]["mismatch"] for r in rows]
+        ratio = [r[a]["s"] / r[b]["s"] for r in rows]
+        summary[k] = {
+            "mean_time_ratio": float(np.mean(ratio)),
+            "ratio_of_mean_times": summary[a]["time_to_tol_s"] / summary[b]["time_to_tol_s"],
+            "max_abs_diff_r": float(max(d_r)), "mean_abs_diff_r": float(np.mean(d_r)),
+            "max_rel_mismatch_diff": float(max(d_rel)), "mean_rel_mismatch_diff": float(np.mean(d_rel)),
+            "seeds_within_1e-3_rel_mismatch": int(sum(x <= 1e-3 for x in d_rel)),
+            "seeds_within_1e-3_abs_r": int(sum(x <= 1e-3 for x in d_r))}
+    summary["fallback_rate"] = mean(lambda r: 0.0 if r["learned_mixed"]["used_prediction"] else 1.0)
+    summary["pred_rel_err"] = mean(lambda r: r["pred_rel_err"])
+    summary["dice_vw"] = {"pre": mean(lambda r: r["dice_vw_pre"]), "plain": mean(lambda r: r["dice_vw_plain"]),
+                          "learned_mixed": mean(lambda r: r["dice_vw_learned_mixed"])}
+    return summary
+
+
+def cmd_summarise(args):
+    """Recompute the summary of an evaluation record from its rows."""
+    rec = json.load(open(args.record))
+    rec["summary"] = summarise(rec["rows"])
+    json.dump(rec, open(args.out or args.record, "w"), indent=1)
+    log("summary: %s" % json.dumps(rec["summary"]))
+
+
 def cmd_eval(args):
     from . import warmstart
     host = warmstart.HostPairs()
@@ -184,29 +228,7 @@ def cmd_eval(args):
                time.perf_counter() - t0))
     host.close()
 
-    def mean(f):
-        return float(np.mean([f(r) for r in rows]))
-
-    summary = {}
-    for name in ("plain", "learned_mixed", "plain_h0", "learned_mixed_h0"):
-        summary[name] = {"time_to_tol_s": mean(lambda r: r[name]["s"]), "gn": mean(lambda r: r[name]["gn"]),
-                         "pcg": mean(lambda r: r[name]["pcg"]), "r": mean(lambda r: r[name]["r"]),
-                         "not_converged": int(sum(r[name]["status"] != "ok" for r in rows))}
-    for a, b in (("learned_mixed", "plain"), ("learned_mixed_h0", "plain_h0")):
-        k = "%s_vs_%s" % (a, b)
-        summary[k] = {
-            "mean_time_ratio": mean(lambda r: r[k]["time_ratio"]),
-            "ratio_of_mean_times": summary[a]["time_to_tol_s"] / summary[b]["time_to_tol_s"],
-            "max_abs_diff_r": float(max(r[k]["abs_diff_r"] for r in rows)),
-            "mean_abs_diff_r": mean(lambda r: r[k]["abs_diff_r"]),
-            "max_rel_mismatch_diff": float(max(r[k]["rel_mismatch_diff"] for r in rows)),
-            "mean_rel_mismatch_diff": mean(lambda r: r[k]["rel_mismatch_diff"]),
-            "seeds_within_1e-3_rel_mismatch": int(sum(r[k]["rel_mismatch_diff"] <= 1e-3 for r in rows)),
-            "seeds_within_1e-3_abs_r": int(sum(r[k]["abs_diff_r"] <= 1e-3 for r in rows))}
-    summary["fallback_rate"] = mean(lambda r: 0.0 if r["learned_mixed"]["used_prediction"] else 1.0)
-    summary["pred_rel_err"] = mean(lambda r: r["pred_rel_err"])
-    summary["dice_vw"] = {"pre": mean(lambda r: r["dice_vw_pre"]), "plain": mean(lambda r: r["dice_vw_plain"]),
-                          "learned_mixed": mean(lambda r: r["dice_vw_learned_mixed"])}
+    summary = summarise(rows)
     rec = {"eval_seeds": args.eval_seeds, "grid": n, "net_grid": n // 2, "storage_mixed": list(storage),
            "max_pcg": args.max_pcg, "gtol": 1e-2, "params": os.path.basename(args.params),
            "summary": summary, "rows": rows}
@@ -215,9 +237,43 @@ def cmd_eval(args):
     log("summary: %s" % json.dumps(summary))
 
 
+def cmd_step(args):
+    """Time training steps (batch 2) and forward passes of the network on
+    random inputs: the convolution kernels' workload, for profiling."""
+    import torch
+    from .claire import Net
+    torch.cuda.set_device(0)
+    n = args.n
+    g = torch.Generator(device="cuda").manual_seed(0)
+    m0 = torch.rand((2, n, n, n), device="cuda", generator=g)
+    m1 = torch.rand((2, n, n, n), device="cuda", generator=g)
+    lab = 0.01 * torch.randn((2, 3, n, n, n), device="cuda", generator=g)
+    net = Net(in_n=n)
+    net.train_step(m0, m1, lab, batch=2)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        loss = net.train_step(m0, m1, lab, batch=2)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / args.steps
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        net.forward(m0[0], m1[0])
+    torch.cuda.synchronize()
+    df = (time.perf_counter() - t) / args.steps
+    print(json.dumps({"grid": n, "train_step_batch2_ms": dt * 1e3, "per_sample_ms": dt * 5e2,
+                      "forward_ms": df * 1e3, "loss": loss}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
+    sm = sub.add_parser("summarise")
+    sm.add_argument("--record", required=True)
+    sm.add_argument("--out", default=None)
+    st = sub.add_parser("step")
+    st.add_argument("--n", type=int, default=128)
+    st.add_argument("--steps", type=int, default=3)
     t = sub.add_parser("train")
     t.add_argument("--out", required=True)
     t.add_argument("--n", type=int, default=256)
@@ -239,6 +295,10 @@ def main():
     args = ap.parse_args()
     if args.cmd == "train":
         cmd_train(args)
+    elif args.cmd == "step":
+        cmd_step(args)
+    elif args.cmd == "summarise":
+        cmd_summarise(args)
     else:
         cmd_eval(args)
 

@@ -2,6 +2,8 @@
 
   python -m paper_2209_08189_amd.prof stats <kernel_stats.csv> <title> <command>
       -> markdown table of per-kernel calls / total / average time
+  python -m paper_2209_08189_amd.prof counters <out.md> <title> <command> <dir> [<dir> ...]
+      -> markdown table of per-kernel counter means from --pmc runs
   python -m paper_2209_08189_amd.prof traffic <fetch_dir> <write_dir> <copy_MiB> <out.json> <command>
       -> HBM bytes per launch of the SL kernels from FETCH_SIZE / WRITE_SIZE
          runs, scaled by what the same counters read for the library's plain
@@ -70,9 +72,57 @@ def traffic(fetch_dir, write_dir, copy_mib, command):
     return rec
 
 
+def counters_md(dirs, title, command, copy_mib=256, min_us=20.0):
+    """Per-kernel means over dispatches of every counter in the passes' CSVs
+    (one rocprofv3 --pmc run per directory).  FETCH_SIZE / WRITE_SIZE are
+    reported in bytes per launch, scaled by what the same counter reads for
+    the library's copy kernel k_copy4 over copy_mib MiB."""
+    vals = defaultdict(lambda: defaultdict(list))
+    dur = defaultdict(list)
+    for d in dirs:
+        path = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)[0]
+        for r in csv.DictReader(open(path)):
+            k = short(r["Kernel_Name"])
+            vals[k][r["Counter_Name"]].append(float(r["Counter_Value"]))
+            if r.get("Start_Timestamp") and r.get("End_Timestamp"):
+                dur[k].append((float(r["End_Timestamp"]) - float(r["Start_Timestamp"])) / 1e3)
+    names = sorted({c for k in vals for c in vals[k]})
+    mean = {k: {c: sum(v) / len(v) for c, v in cs.items()} for k, cs in vals.items()}
+    scale = {}
+    nbytes = copy_mib * (1 << 20)
+    if "k_copy4" in mean:
+        for c in ("FETCH_SIZE", "WRITE_SIZE"):
+            if c in mean["k_copy4"] and mean["k_copy4"][c] > 0:
+                scale[c] = nbytes / (mean["k_copy4"][c] * 1024.0)
+    out = ["# %s" % title, "", "Command (one run per counter set):", "", "```", command, "```", ""]
+    if scale:
+        out += ["FETCH_SIZE / WRITE_SIZE: bytes per launch, each scaled by the factor that makes the counter "
+                "read %d MiB for the plain copy kernel k_copy4 (%s)." % (copy_mib, ", ".join(
+                    "%s x%.3f" % (c, f) for c, f in scale.items())), ""]
+    out += ["| kernel | " + " | ".join(names) + " |", "|---|" + "---:|" * len(names)]
+    order = sorted(mean, key=lambda k: -max(dur.get(k, [0.0]) or [0.0]))
+    for k in order:
+        if dur.get(k) and max(dur[k]) < min_us and k != "k_copy4":
+            continue
+        cells = []
+        for c in names:
+            v = mean[k].get(c)
+            if v is None:
+                cells.append("")
+            elif c in scale:
+                cells.append("%.1f MB" % (v * 1024.0 * scale[c] / 1e6))
+            else:
+                cells.append("%.4g" % v)
+        out.append("| %s | %s |" % (k, " | ".join(cells)))
+    return "\n".join(out) + "\n"
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
         sys.stdout.write(stats_md(sys.argv[2], sys.argv[3], sys.argv[4]))
+    elif sys.argv[1] == "counters":
+        # counters <out.md> <title> <command> <dir> [<dir> ...]
+        open(sys.argv[2], "w").write(counters_md(sys.argv[5:], sys.argv[3], sys.argv[4]))
     elif sys.argv[1] == "traffic":
         rec = traffic(sys.argv[2], sys.argv[3], int(sys.argv[4]), sys.argv[6])
         json.dump(rec, open(sys.argv[5], "w"), indent=1)
