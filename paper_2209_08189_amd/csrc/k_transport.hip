@@ -36,6 +36,21 @@ __device__ __forceinline__ void lagrange4_fast(float f, float w[4])
     w[3] = fmaf(a3, f, a3);          //  (f+1)f(f-1)/3
 }
 
+// Fraction d - floor(d) of a displacement (v_fract_f32: one instruction,
+// exact wherever the difference is representable, and below 1 where it
+// would round up to 1).  Every SL path takes its fractions from here, so
+// the paths agree bitwise.
+__device__ __forceinline__ float frac_of(float d) { return __builtin_amdgcn_fractf(d); }
+
+// floor(d) as an integer in one instruction, for displacements known to be
+// small (the feet of a tile whose box fits, whose floors lie within the box).
+__device__ __forceinline__ int floor_small(float d)
+{
+    int r;
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(d));
+    return r;
+}
+
 // Stencil of one foot: row offsets of the 4 x1 planes, 4 x2 rows, 4 x3
 // columns (periodic wrap by masking) and the separable weights.  The
 // integer part of the foot is node + floor(d), the fraction d - floor(d),
@@ -49,9 +64,9 @@ struct Foot {
 __device__ __forceinline__ void make_foot(const Grid &g, int i, int j, int k, float d1, float d2, float d3, Foot &F)
 {
     const float f1 = floorf(d1), f2 = floorf(d2), f3 = floorf(d3);
-    lagrange4_fast(d1 - f1, F.w1);
-    lagrange4_fast(d2 - f2, F.w2);
-    lagrange4_fast(d3 - f3, F.w3);
+    lagrange4_fast(frac_of(d1), F.w1);
+    lagrange4_fast(frac_of(d2), F.w2);
+    lagrange4_fast(frac_of(d3), F.w3);
     // integer parts clamped to +-2^24 so the conversion is defined for any
     // finite input; indices are wrapped by masking below
     const float c1 = fminf(fmaxf(f1, -16777216.0f), 16777216.0f);
@@ -191,7 +206,7 @@ __device__ __forceinline__ float lin_node(const Grid &g, const Tu *__restrict__ 
                                           float d2, float d3)
 {
     const float f1 = floorf(d1), f2 = floorf(d2), f3 = floorf(d3);
-    const float a1 = d1 - f1, a2 = d2 - f2, a3 = d3 - f3;
+    const float a1 = frac_of(d1), a2 = frac_of(d2), a3 = frac_of(d3);
     const int b1 = i + (int)fminf(fmaxf(f1, -16777216.0f), 16777216.0f);
     const int b2 = j + (int)fminf(fmaxf(f2, -16777216.0f), 16777216.0f);
     const int b3 = k + (int)fminf(fmaxf(f3, -16777216.0f), 16777216.0f);
@@ -242,7 +257,9 @@ __global__ __launch_bounds__(TPB) void k_sl_lin(Grid g, const Tu *__restrict__ u
 // requested before the first wait; several workgroups per CU overlap one
 // another's memory waits with their gathers.
 constexpr int TX = 32, TY = 8, TZ = 8;
-constexpr int PY = 12, PZ = 12;               // box pitches: tile + 3 + slack of 1
+// box pitches: tile + 3 + slack (x1: 2, x2: 1); 13 x 12 x 64 words = 39.9 KB,
+// so four workgroups share a CU's 160 KB of LDS
+constexpr int PY = 12, PZ = 13;
 // x3 pitch in elements: 64 words for FP32; 16-bit boxes load element pairs
 // from an even start (one-element shift) and use 64 elements (32 words).
 template <typename T> constexpr int box_px() { return sizeof(T) == 4 ? 64 : 64; }
@@ -278,10 +295,12 @@ struct TileIdx {
 template <int SPLIT>
 __device__ __forceinline__ TileIdx tile_idx(const Grid &g, int tile, int ntx, int nty)
 {
+    // tile counts are powers of two (as are the grid sizes)
+    const int lx = __builtin_ctz(ntx), ly = __builtin_ctz(nty);
     TileIdx t;
-    t.tx = tile % ntx;
-    t.ty = (tile / ntx) % nty;
-    t.tz = tile / (ntx * nty);
+    t.tx = tile & (ntx - 1);
+    t.ty = (tile >> lx) & (nty - 1);
+    t.tz = tile >> (lx + ly);
     t.lane = threadIdx.x & (TX - 1);
     t.row = (threadIdx.x & 255) / TX;
     t.i0 = t.tz * TZ;
@@ -367,16 +386,22 @@ __device__ __forceinline__ void load_feet(const Grid &g, const float *__restrict
                                           const TileIdx &t, float (&d1)[QT], float (&d2)[QT], float (&d3)[QT],
                                           float (&e)[QT])
 {
+    // each field from its own wave-uniform base with a 32-bit byte offset
+    // (a field has at most 2^30 nodes)
     const size_t N = g.N;
+    const char *b1 = reinterpret_cast<const char *>(d), *b2 = reinterpret_cast<const char *>(d + N),
+               *b3 = reinterpret_cast<const char *>(d + 2 * N), *be = reinterpret_cast<const char *>(prm.e);
+    const unsigned o0 = (unsigned)t.p0 * 4u, dq = (unsigned)t.plane * 4u;
 #pragma unroll
     for (int q = 0; q < QT; ++q) {
-        const int p = t.p0 + q * t.plane;
-        d1[q] = d[p];
-        d2[q] = d[N + p];
-        d3[q] = d[2 * N + p];
+        const unsigned o = o0 + q * dq;
+        d1[q] = *reinterpret_cast<const float *>(b1 + o);
+        d2[q] = *reinterpret_cast<const float *>(b2 + o);
+        d3[q] = *reinterpret_cast<const float *>(b3 + o);
     }
 #pragma unroll
-    for (int q = 0; q < QT; ++q) e[q] = MODE == SL_STATE ? 0.0f : prm.e[t.p0 + q * t.plane];
+    for (int q = 0; q < QT; ++q)
+        e[q] = MODE == SL_STATE ? 0.0f : *reinterpret_cast<const float *>(be + (o0 + q * dq));
 }
 
 // Direct-to-LDS staging of a box: wave wv loads box rows (a, bb) with
@@ -394,18 +419,25 @@ __device__ __forceinline__ void stage_box(const Grid &g, const Tu *__restrict__ 
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int l64 = threadIdx.x & 63;
     const int gi0 = t.i0 + B.r1, gj0 = t.ty * TY + B.r2;
+    // byte offset of this lane's element(s) within a field row (periodic)
+    unsigned cb[NCH];
+    bool on[NCH];
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) {
+        const int c = 64 * EPL * ch + EPL * l64;            // box column of this lane's first element
+        on[ch] = c < B.E3 + B.sh;
+        cb[ch] = (unsigned)((B.c0 - B.sh + c) & (g.n3 - 1)) * (unsigned)sizeof(Tu);
+    }
     for (int a = 0; a < B.E1; ++a) {
         const int ga = ((gi0 + a) & (g.n1 - 1)) << (g.l2 + g.l3);
         for (int bb = wv; bb < B.E2; bb += NW) {
-            const int rowoff = ga + (((gj0 + bb) & (g.n2 - 1)) << g.l3);
+            const char *row = reinterpret_cast<const char *>(u + (ga + (((gj0 + bb) & (g.n2 - 1)) << g.l3)));
 #pragma unroll
-            for (int ch = 0; ch < NCH; ++ch) {
-                const int c = 64 * EPL * ch + EPL * l64;    // box column of this lane's first element
-                if (c < B.E3 + B.sh)
-                    __builtin_amdgcn_global_load_lds((const void *)(u + rowoff + ((B.c0 - B.sh + c) & (g.n3 - 1))),
+            for (int ch = 0; ch < NCH; ++ch)
+                if (on[ch])
+                    __builtin_amdgcn_global_load_lds((const void *)(row + cb[ch]),
                                                      (lds_void *)(box + (a * PY + bb) * PX + 64 * EPL * ch), 4, 0,
                                                      0);
-            }
         }
     }
 }
@@ -473,6 +505,42 @@ template <> __device__ __forceinline__ void row2<__hip_bfloat16>(unsigned a, flo
     x1 = __uint_as_float(w & 0xffff0000u);
 }
 
+// LDS addressing of the stencils of a thread's nodes in a staged box: the
+// stencil of node q starts at box element (q0 + q + i1 + lo, row + i2 + lo,
+// lane + i3 + lo) - (r1, r2, r3) (plus the 16-bit shift), i = floor(d) and
+// lo = -1 (cubic) or 0 (linear).  The part that does not depend on the
+// floors is formed once per thread; each node adds its floors by 24-bit
+// multiply-adds (the floors of a fitting tile are small).
+struct BoxAddr {
+    int row0;   // byte offset of element (q0 + lo - r1, row + lo - r2, 0) from the box start
+    int c3;     // x3 index (in elements) of the stencil start for a zero floor
+};
+template <typename Tu>
+__device__ __forceinline__ BoxAddr box_addr(const Tu *box, const TileIdx &t, const TileBox &B, int lo)
+{
+    constexpr int PX = box_px<Tu>();
+    BoxAddr A;
+    A.row0 = (int)lds_addr(box) + ((t.q0 + lo - B.r1) * PY + (t.row + lo - B.r2)) * PX * (int)sizeof(Tu);
+    A.c3 = t.lane + lo - B.r3 + B.sh;
+    return A;
+}
+// Byte address of the stencil start of node q (FP32 boxes: any column;
+// 16-bit boxes: the even column at or below it, in the copy in which the
+// stencil's rows are whole words).
+template <typename Tu>
+__device__ __forceinline__ unsigned stencil_addr(const BoxAddr &A, int q, float d1, float d2, float d3)
+{
+    constexpr int PX = box_px<Tu>();
+    constexpr int ES = sizeof(Tu);
+    const int rowb = A.row0 + q * (PY * PX * ES) + __mul24(floor_small(d1), PY * PX * ES) +
+                     __mul24(floor_small(d2), PX * ES);
+    const int s3 = A.c3 + floor_small(d3);
+    if constexpr (ES == 2)
+        return (unsigned)(rowb + (s3 & ~1) * 2 + ((s3 & 1) ? PZ * PY * PX * 2 : 0));
+    else
+        return (unsigned)(rowb + s3 * ES);
+}
+
 // Trilinear gather of the QT nodes of this thread from a staged box (box
 // origin at the lowest floor of the tile's feet), with the operations of
 // lin_node.
@@ -483,18 +551,11 @@ __device__ __forceinline__ void compute_tile_lin(const Tu *box, const TileIdx &t
 {
     constexpr int PX = box_px<Tu>();
     constexpr unsigned ES = sizeof(Tu);
+    const BoxAddr A = box_addr(box, t, B, 0);
 #pragma unroll
     for (int q = 0; q < QT; ++q) {
-        const float f1 = floorf(d1[q]), f2 = floorf(d2[q]), f3 = floorf(d3[q]);
-        const float a1 = d1[q] - f1, a2 = d2[q] - f2, a3 = d3[q] - f3;
-        const int s1 = t.q0 + q + ifloor(d1[q]) - B.r1;
-        const int s2 = t.row + ifloor(d2[q]) - B.r2;
-        const int s3 = t.lane + ifloor(d3[q]) - B.r3 + B.sh;
-        unsigned bp;
-        if constexpr (ES == 2)   // 16-bit: the copy in which the row pair is one aligned word
-            bp = lds_addr(box) + ((s3 & 1) ? (unsigned)(PZ * PY * PX * 2) : 0u) + ((s1 * PY + s2) * PX + (s3 & ~1)) * 2u;
-        else
-            bp = lds_addr(box) + ((s1 * PY + s2) * PX + s3) * ES;
+        const float a1 = frac_of(d1[q]), a2 = frac_of(d2[q]), a3 = frac_of(d3[q]);
+        const unsigned bp = stencil_addr<Tu>(A, q, d1[q], d2[q], d3[q]);
         float x000, x001, x010, x011, x100, x101, x110, x111;
         row2<Tu>(bp, x000, x001);
         row2<Tu>(bp + PX * ES, x010, x011);
@@ -511,44 +572,27 @@ __device__ __forceinline__ void compute_tile_lin(const Tu *box, const TileIdx &t
     }
 }
 
-// Gather of the QT nodes of this thread from a staged box (or from global
-// memory when the box did not fit) and the epilogue, into res.  ORDER 1:
-// trilinear, 3: tricubic.
+// Gather of the QT nodes of this thread from a staged box and the epilogue,
+// into res.  ORDER 1: trilinear, 3: tricubic.
 template <typename Tu, int MODE, int ORDER>
-__device__ __forceinline__ void compute_tile(const Grid &g, const Tu *__restrict__ u, const Tu *box, const TileIdx &t,
-                                             const TileBox &B, const float (&d1)[QT], const float (&d2)[QT],
+__device__ __forceinline__ void compute_tile(const Tu *box, const TileIdx &t, const TileBox &B, const float (&d1)[QT], const float (&d2)[QT],
                                              const float (&d3)[QT], const float (&e)[QT], const SLParams &prm,
                                              float (&res)[QT])
 {
     constexpr int PX = box_px<Tu>();
-    if (!B.fits) {
-#pragma unroll
-        for (int q = 0; q < QT; ++q) {
-            if constexpr (ORDER == 1) {
-                res[q] = epilogue<MODE>(prm, e[q], lin_node(g, u, t.i0 + t.q0 + q, t.j, t.k, d1[q], d2[q], d3[q]));
-            } else {
-                Foot F;
-                make_foot(g, t.i0 + t.q0 + q, t.j, t.k, d1[q], d2[q], d3[q], F);
-                res[q] = epilogue<MODE>(prm, e[q], gather(u, F));
-            }
-        }
-    } else if constexpr (ORDER == 1) {
+    if constexpr (ORDER == 1) {
         compute_tile_lin<Tu, MODE>(box, t, B, d1, d2, d3, e, prm, res);
     } else if constexpr (sizeof(Tu) == 2) {
         // 16-bit box: copy A as loaded, copy B shifted by one element, so the
         // 4 values of any stencil row are two aligned words of one copy
+        const BoxAddr A = box_addr(box, t, B, -1);
 #pragma unroll
         for (int q = 0; q < QT; ++q) {
-            const float f1 = floorf(d1[q]), f2 = floorf(d2[q]), f3 = floorf(d3[q]);
             float w1[4], w2[4], w3[4];
-            lagrange4_fast(d1[q] - f1, w1);
-            lagrange4_fast(d2[q] - f2, w2);
-            lagrange4_fast(d3[q] - f3, w3);
-            const int s1 = t.q0 + q + ifloor(d1[q]) - 1 - B.r1;
-            const int s2 = t.row + ifloor(d2[q]) - 1 - B.r2;
-            const int s3 = t.lane + ifloor(d3[q]) - 1 - B.r3 + B.sh;
-            const unsigned bp = lds_addr(box) + ((s3 & 1) ? (unsigned)(PZ * PY * PX * 2) : 0u) +
-                                ((s1 * PY + s2) * PX + (s3 & ~1)) * 2u;
+            lagrange4_fast(frac_of(d1[q]), w1);
+            lagrange4_fast(frac_of(d2[q]), w2);
+            lagrange4_fast(frac_of(d3[q]), w3);
+            const unsigned bp = stencil_addr<Tu>(A, q, d1[q], d2[q], d3[q]);
             float s = 0.0f;
 #pragma unroll
             for (int a = 0; a < 4; ++a) {
@@ -567,18 +611,14 @@ __device__ __forceinline__ void compute_tile(const Grid &g, const Tu *__restrict
             __builtin_amdgcn_sched_barrier(0);
         }
     } else {
+        const BoxAddr A = box_addr(box, t, B, -1);
 #pragma unroll
         for (int q = 0; q < QT; ++q) {
-            const float f1 = floorf(d1[q]), f2 = floorf(d2[q]), f3 = floorf(d3[q]);
             float w1[4], w2[4], w3[4];
-            lagrange4_fast(d1[q] - f1, w1);
-            lagrange4_fast(d2[q] - f2, w2);
-            lagrange4_fast(d3[q] - f3, w3);
-            // same clamped integer parts as the tile box
-            const int s1 = t.q0 + q + ifloor(d1[q]) - 1 - B.r1;
-            const int s2 = t.row + ifloor(d2[q]) - 1 - B.r2;
-            const int s3 = t.lane + ifloor(d3[q]) - 1 - B.r3 + B.sh;
-            const unsigned bp = lds_addr(box) + ((s1 * PY + s2) * PX + s3) * (unsigned)sizeof(Tu);
+            lagrange4_fast(frac_of(d1[q]), w1);
+            lagrange4_fast(frac_of(d2[q]), w2);
+            lagrange4_fast(frac_of(d3[q]), w3);
+            const unsigned bp = stencil_addr<Tu>(A, q, d1[q], d2[q], d3[q]);
             float s = 0.0f;
 #pragma unroll
             for (int a = 0; a < 4; ++a) {
@@ -608,8 +648,10 @@ __device__ __forceinline__ void compute_tile(const Grid &g, const Tu *__restrict
 template <typename To>
 __device__ __forceinline__ void store_tile(To *__restrict__ out, const TileIdx &t, const float (&res)[QT])
 {
+    char *b = reinterpret_cast<char *>(out);
+    const unsigned o0 = (unsigned)t.p0 * (unsigned)sizeof(To), dq = (unsigned)t.plane * (unsigned)sizeof(To);
 #pragma unroll
-    for (int q = 0; q < QT; ++q) stf(out + t.p0 + q * t.plane, res[q]);
+    for (int q = 0; q < QT; ++q) stf(reinterpret_cast<To *>(b + (o0 + q * dq)), res[q]);
 }
 
 // 16-bit boxes: copy B (words after copy A) holds the elements shifted by
@@ -632,12 +674,38 @@ __device__ __forceinline__ void shift_copy(const Tu *box, const TileBox &B)
     }
 }
 
-// One tile per workgroup: the feet, epilogue operands and box of the tile
-// are requested together, then one wait, then the gather.  At most 80 VGPRs
-// (6 waves per SIMD) so that three 512-thread workgroups share a CU; their
-// phases (waiting for memory, gathering) overlap.
+// A tile whose box exceeds the pitches: each node gathers straight from
+// global memory, with the weights and contraction order of the tiled path
+// (same results), one node at a time so that the path needs few registers.
 template <typename Tu, typename To, int MODE, int ORDER>
-__global__ __launch_bounds__(TPB_SL, 6) void k_sl_tile(Grid g, const Tu *__restrict__ u, const float *__restrict__ d,
+__device__ __forceinline__ void tile_fallback(const Grid &g, const Tu *__restrict__ u, const float *__restrict__ d,
+                                              const SLParams &prm, To *__restrict__ out, const TileIdx &t)
+{
+    const size_t N = g.N;
+#pragma unroll 1
+    for (int q = 0; q < QT; ++q) {
+        const int p = t.p0 + q * t.plane;
+        const float a1 = d[p], a2 = d[N + p], a3 = d[2 * N + p];
+        const float ev = MODE == SL_STATE ? 0.0f : prm.e[p];
+        float v;
+        if constexpr (ORDER == 1) {
+            v = lin_node(g, u, t.i0 + t.q0 + q, t.j, t.k, a1, a2, a3);
+        } else {
+            Foot F;
+            make_foot(g, t.i0 + t.q0 + q, t.j, t.k, a1, a2, a3, F);
+            v = gather(u, F);
+        }
+        stf(out + p, epilogue<MODE>(prm, ev, v));
+    }
+}
+
+// One tile per workgroup: the feet, epilogue operands and box of the tile
+// are requested together, then one wait, then the gather.  The fitting path
+// needs about 50 VGPRs (the global-memory fallback runs one node at a time
+// and adds none), so the 39.9 KB box sets the occupancy: four 512-thread
+// workgroups per CU, whose phases (waiting for memory, gathering) overlap.
+template <typename Tu, typename To, int MODE, int ORDER>
+__global__ __launch_bounds__(TPB_SL, 8) void k_sl_tile(Grid g, const Tu *__restrict__ u, const float *__restrict__ d,
                                                   SLParams prm, To *__restrict__ out, const int *__restrict__ boxes,
                                                   int ntx, int nty, int nblk)
 {
@@ -650,17 +718,21 @@ __global__ __launch_bounds__(TPB_SL, 6) void k_sl_tile(Grid g, const Tu *__restr
     const int tile = (nblk & 7) ? b : (b & 7) * (nblk >> 3) + (b >> 3);
     const TileIdx t = tile_idx<SPLIT>(g, tile, ntx, nty);
     const TileBox B = tile_box<Tu>(boxes, tile, t);
+    if (!B.fits) {                 // the whole workgroup takes this branch
+        tile_fallback<Tu, To, MODE, ORDER>(g, u, d, prm, out, t);
+        return;
+    }
     float d1[QT], d2[QT], d3[QT], e[QT], r[QT];
     load_feet<MODE>(g, d, prm, t, d1, d2, d3, e);
     __builtin_amdgcn_sched_barrier(0);
-    if (B.fits) stage_box(g, u, box, t, B);
+    stage_box(g, u, box, t, B);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if (sizeof(Tu) == 2 && B.fits) {
+    if (sizeof(Tu) == 2) {
         shift_copy(box, B);
         __syncthreads();
     }
-    compute_tile<Tu, MODE, ORDER>(g, u, box, t, B, d1, d2, d3, e, prm, r);
+    compute_tile<Tu, MODE, ORDER>(box, t, B, d1, d2, d3, e, prm, r);
     store_tile(out, t, r);
 }
 
