@@ -228,12 +228,17 @@ void launch_copy_f32(const float *src, float *dst, size_t n, hipStream_t s);
 void launch_fill_f32(float *dst, float v, size_t n, hipStream_t s);
 
 // FFT (k_fft.hip)
+// Row pitch of a half spectrum in complex values: nh = n3 / 2 + 1 rounded up
+// to a multiple of 16, so that every row starts on a 128-byte boundary (the
+// column passes read 16-column tiles of 128-byte row pieces).
+__host__ __device__ inline int fft_row_pitch(int n3) { return (n3 / 2 + 1 + 15) & ~15; }
 struct FFTPlan {
     int n1, n2, n3, nh;          // nh = n3 / 2 + 1 complex values per x3 row
+    int np;                      // row pitch of the half spectrum, fft_row_pitch(n3)
     float2 *tw1, *tw2;           // exp(-2 pi i t / n_d), t < n_d
     float2 *twM;                 // exp(-2 pi i t / M), t < M = n3 / 2
     float2 *twS;                 // exp(-2 pi i k / n3), k <= M (real-FFT split)
-    float2 *spec;                // complex work, ncomp_max * n1 * n2 * nh
+    float2 *spec;                // complex work, ncomp_max * n1 * n2 * np
     int ncomp_max;
 };
 size_t fft_spec_bytes(int n1, int n2, int n3, int ncomp);
@@ -259,7 +264,7 @@ bool ctx_has_images(const cl_ctx *ctx);
 // FFT plan owning its twiddle tables and spectrum (allocated with alloc)
 template <typename Alloc> inline void fft_plan_init(FFTPlan &P, int n1, int n2, int n3, int ncomp, Alloc &&alloc)
 {
-    P.n1 = n1; P.n2 = n2; P.n3 = n3; P.nh = n3 / 2 + 1; P.ncomp_max = ncomp;
+    P.n1 = n1; P.n2 = n2; P.n3 = n3; P.nh = n3 / 2 + 1; P.np = fft_row_pitch(n3); P.ncomp_max = ncomp;
     P.spec = (float2 *)alloc(fft_spec_bytes(n1, n2, n3, ncomp));
     float2 **tabs[4] = {&P.tw1, &P.tw2, &P.twM, &P.twS};
     const int tn[4] = {n1, n2, n3 / 2, n3};

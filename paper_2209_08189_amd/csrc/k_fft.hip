@@ -2,7 +2,8 @@
 // spectral operator costs two FFTs and one Hadamard product; Section 3 uses
 // a vendor 3D FFT on one GPU, here it is written from scratch).
 //
-// Layout: real fields [n1][n2][n3]; half spectrum [n1][n2][nh], nh = n3/2+1.
+// Layout: real fields [n1][n2][n3]; half spectrum [n1][n2][np]: nh = n3/2+1
+// values per row at a row pitch np of nh rounded up to 16 (128-byte rows).
 // One spectral apply is five passes, each a single read and a single write
 // of the field:
 //   x3 R2C    rows of n3 reals packed as M = n3/2 complex, complex FFT of
@@ -166,7 +167,8 @@ __device__ __forceinline__ void load_table(float2 *dst, const float2 *__restrict
 // --- x3 forward: real rows -> half spectrum.  nl = 2^lognl rows per tile.
 __global__ __launch_bounds__(TPB) void k_fft_x3_r2c(const float *__restrict__ in, float2 *__restrict__ spec,
                                                     const float2 *__restrict__ twM, const float2 *__restrict__ tw3,
-                                                    int logM, int lognl, int nrows, size_t in_cs, size_t spec_cs)
+                                                    int logM, int lognl, int nrows, size_t in_cs, size_t spec_cs,
+                                                    int np)
 {
     extern __shared__ float2 sm[];
     const int M = 1 << logM, nl = 1 << lognl, P = nl + 1, nh = M + 1;
@@ -201,7 +203,7 @@ __global__ __launch_bounds__(TPB) void k_fft_x3_r2c(const float *__restrict__ in
         const float2 zc = cconj(lds[((M - k) & (M - 1)) * P + r]);
         const float2 E = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y + zc.y));
         const float2 O = make_float2(0.5f * (zk.y - zc.y), -0.5f * (zk.x - zc.x));
-        dst[(size_t)row0 * nh + e] = cadd(E, cmul(tws[k], O));
+        dst[(size_t)(row0 + r) * np + k] = cadd(E, cmul(tws[k], O));
     }
 }
 
@@ -209,7 +211,7 @@ __global__ __launch_bounds__(TPB) void k_fft_x3_r2c(const float *__restrict__ in
 __global__ __launch_bounds__(TPB) void k_fft_x3_c2r(const float2 *__restrict__ spec, float *__restrict__ out,
                                                     const float *__restrict__ add, const float2 *__restrict__ twM,
                                                     const float2 *__restrict__ tw3, int logM, int lognl, int nrows,
-                                                    size_t out_cs, size_t spec_cs)
+                                                    size_t out_cs, size_t spec_cs, int np)
 {
     extern __shared__ float2 sm[];
     const int M = 1 << logM, nl = 1 << lognl, P = nl + 1, nh = M + 1;
@@ -234,7 +236,10 @@ __global__ __launch_bounds__(TPB) void k_fft_x3_c2r(const float2 *__restrict__ s
 #pragma unroll
         for (int it = 0; it < NB; ++it) {
             const int e = it * TPB + threadIdx.x;
-            if (e < totk) buf[it] = src[(size_t)row0 * nh + e];
+            if (e < totk) {
+                const int r = e / nh, k = e - r * nh;
+                buf[it] = src[(size_t)(row0 + r) * np + k];
+            }
         }
 #pragma unroll
         for (int it = 0; it < NB; ++it) {
@@ -322,7 +327,7 @@ __device__ __forceinline__ void store_cols(const float2 *lds, float2 *__restrict
 // [c0, c0 + C) of the nh per row.
 template <bool INV>
 __global__ __launch_bounds__(TPB) void k_fft_x2(float2 *__restrict__ spec, const float2 *__restrict__ tw2, int logn2,
-                                                int n2, int nh, int logC, size_t spec_cs)
+                                                int n2, int nh, int np, int logC, size_t spec_cs)
 {
     extern __shared__ float2 sm[];
     const int C = 1 << logC, P = C + 1;
@@ -330,19 +335,19 @@ __global__ __launch_bounds__(TPB) void k_fft_x2(float2 *__restrict__ spec, const
     float2 *lds = sm + n2;
     const int comp = blockIdx.z, i1 = blockIdx.y, c0 = blockIdx.x * C;
     const int cw = min(C, nh - c0);
-    float2 *base = spec + comp * spec_cs + (size_t)i1 * n2 * nh + c0;
+    float2 *base = spec + comp * spec_cs + (size_t)i1 * n2 * np + c0;
     load_table(tw, tw2, n2);
-    load_cols(lds, base, nh, logC, logn2, cw, P);
+    load_cols(lds, base, np, logC, logn2, cw, P);
     fft_lines<INV>(lds, P, logC, logn2, tw);
-    store_cols(lds, base, nh, logC, logn2, cw, P);
+    store_cols(lds, base, np, logC, logn2, cw, P);
 }
 
 // --- x1 fused: forward FFT along x1, symbol multiply, inverse FFT.
 // plane i2 = blockIdx.y, columns [c0, c0 + C).
 // mode 0: forward, multiply, inverse; 1: forward only; 2: inverse only
 __global__ __launch_bounds__(TPB) void k_fft_x1_mult(float2 *__restrict__ spec, const float2 *__restrict__ tw1,
-                                                     int logn1, int n1, int n2, int nh, int logC, int kind, float beta,
-                                                     float scale, size_t spec_cs, int mode)
+                                                     int logn1, int n1, int n2, int nh, int np, int logC, int kind,
+                                                     float beta, float scale, size_t spec_cs, int mode)
 {
     extern __shared__ float2 sm[];
     const int C = 1 << logC, P = C + 1;
@@ -350,8 +355,8 @@ __global__ __launch_bounds__(TPB) void k_fft_x1_mult(float2 *__restrict__ spec, 
     float2 *lds = sm + n1;
     const int comp = blockIdx.z, i2 = blockIdx.y, c0 = blockIdx.x * C;
     const int cw = min(C, nh - c0);
-    float2 *base = spec + comp * spec_cs + (size_t)i2 * nh + c0;
-    const size_t rs = (size_t)n2 * nh;
+    float2 *base = spec + comp * spec_cs + (size_t)i2 * np + c0;
+    const size_t rs = (size_t)n2 * np;
     load_table(tw, tw1, n1);
     load_cols(lds, base, rs, logC, logn1, cw, P);
     if (mode == 2) {
@@ -549,13 +554,13 @@ __global__ __launch_bounds__(TPB) void k_fft_rows_r2c(const float *__restrict__ 
                                                       const float2 *__restrict__ twM, const float2 *__restrict__ tw3,
                                                       size_t in_cs, size_t spec_cs)
 {
-    constexpr int M = 16 * R2, NR = 256 / R2, PP = 16 / R2, nh = M + 1;
+    constexpr int M = 16 * R2, NR = 256 / R2, PP = 16 / R2, NP = M + 16;   // NP: spectrum row pitch
     __shared__ float2 twm[M], tws[M + 1];
     __shared__ float2 ex[NR * rows_pitch<R2>()];
     const int comp = blockIdx.y;
     const size_t row0 = (size_t)blockIdx.x * NR;
     const float2 *src = (const float2 *)(in + comp * in_cs) + row0 * M;
-    float2 *dst = spec + comp * spec_cs + row0 * nh;
+    float2 *dst = spec + comp * spec_cs + row0 * NP;
     for (int t = threadIdx.x; t < M; t += TPB) twm[t] = twM[t];
     for (int t = threadIdx.x; t <= M; t += TPB) tws[t] = tw3[t];
     const int c = threadIdx.x & 15, r0 = threadIdx.x >> 4;
@@ -571,7 +576,7 @@ __global__ __launch_bounds__(TPB) void k_fft_rows_r2c(const float *__restrict__ 
     // b' = R2 - b (b > 0) or this lane's v[(16 - a) mod 16] (b = 0)
     const int b = threadIdx.x % R2, row = threadIdx.x / R2;
     const int lane = threadIdx.x & 63, partner = lane - b + ((R2 - b) & (R2 - 1));
-    float2 *drow = dst + (size_t)row * nh;
+    float2 *drow = dst + (size_t)row * NP;
 #pragma unroll
     for (int a = 0; a < 16; ++a) {
         float2 zc;
@@ -600,12 +605,12 @@ __global__ __launch_bounds__(TPB) void k_fft_rows_c2r(const float2 *__restrict__
                                                       const float *__restrict__ add, const float2 *__restrict__ twM,
                                                       const float2 *__restrict__ tw3, size_t out_cs, size_t spec_cs)
 {
-    constexpr int M = 16 * R2, NR = 256 / R2, PP = 16 / R2, nh = M + 1;
+    constexpr int M = 16 * R2, NR = 256 / R2, PP = 16 / R2, NP = M + 16;   // NP: spectrum row pitch
     __shared__ float2 twm[M], tws[M + 1];
     __shared__ float2 ex[NR * rows_pitch<R2>()];
     const int comp = blockIdx.y;
     const size_t row0 = (size_t)blockIdx.x * NR;
-    const float2 *src = spec + comp * spec_cs + row0 * nh;
+    const float2 *src = spec + comp * spec_cs + row0 * NP;
     float2 *dst = (float2 *)(out + comp * out_cs) + row0 * M;
     const float2 *ad = add ? (const float2 *)(add + comp * out_cs) + row0 * M : nullptr;
     for (int t = threadIdx.x; t < M; t += TPB) twm[t] = twM[t];
@@ -616,7 +621,7 @@ __global__ __launch_bounds__(TPB) void k_fft_rows_c2r(const float2 *__restrict__
     for (int u = 0; u < PP; ++u)
 #pragma unroll
         for (int d = 0; d < R2; ++d) {
-            const float2 *srow = src + (size_t)(r0 + 16 * u) * nh;
+            const float2 *srow = src + (size_t)(r0 + 16 * u) * NP;
             const int k = c + 16 * d;
             xa[u * R2 + d] = srow[k];
             xb[u * R2 + d] = srow[M - k];
@@ -654,7 +659,7 @@ __global__ __launch_bounds__(TPB) void k_fft_rows_c2r(const float2 *__restrict__
 __global__ __launch_bounds__(TPB) void k_mode_copy(const float2 *__restrict__ sa, float2 *__restrict__ sb, int a1, int a2,
                                                    int a3, int b1, int b2, int b3, int ncomp)
 {
-    const int bh = b3 / 2 + 1, ah = a3 / 2 + 1;
+    const int bh = b3 / 2 + 1, ap = fft_row_pitch(a3), bp = fft_row_pitch(b3);
     const size_t nb = (size_t)b1 * b2 * bh;
     const size_t e = (size_t)blockIdx.x * TPB + threadIdx.x;
     if (e >= nb * ncomp) return;
@@ -666,9 +671,9 @@ __global__ __launch_bounds__(TPB) void k_mode_copy(const float2 *__restrict__ sa
     float2 v = make_float2(0.f, 0.f);
     if (2 * abs(k1) < c1 && 2 * abs(k2) < c2 && 2 * k3 < c3) {
         const int p1 = k1 < 0 ? k1 + a1 : k1, p2 = k2 < 0 ? k2 + a2 : k2;
-        v = sa[(size_t)comp * a1 * a2 * ah + ((size_t)p1 * a2 + p2) * ah + k3];
+        v = sa[(size_t)comp * a1 * a2 * ap + ((size_t)p1 * a2 + p2) * ap + k3];
     }
-    sb[e] = v;
+    sb[(size_t)comp * b1 * b2 * bp + ((size_t)q1 * b2 + q2) * bp + q3] = v;
 }
 
 // Per-mode 3x3 operators of the near-incompressible regularisation on the
@@ -679,14 +684,15 @@ __global__ __launch_bounds__(TPB) void k_mode_copy(const float2 *__restrict__ sa
 //   kind 1: L^-1 = (I - c/(a + c |kappa|^2) kappa kappa^T) / a, 1/beta_v at k = 0
 //   kind 3: K = beta_v A L^-1 = I - c/(a + c |kappa|^2) kappa kappa^T, I at k = 0
 // (Sherman-Morrison on the rank-one term).
-__global__ __launch_bounds__(TPB) void k_spec_mult3(float2 *__restrict__ spec, int n1, int n2, int nh, int kind,
-                                                    float beta_v, float beta_w, float scale, size_t spec_cs)
+__global__ __launch_bounds__(TPB) void k_spec_mult3(float2 *__restrict__ spec, int n1, int n2, int nh, int np,
+                                                    int kind, float beta_v, float beta_w, float scale, size_t spec_cs)
 {
-    const size_t e = (size_t)blockIdx.x * TPB + threadIdx.x;
-    if (e >= spec_cs) return;
-    const int q3 = (int)(e % nh);
-    const int q2 = (int)((e / nh) % n2);
-    const int q1 = (int)(e / ((size_t)nh * n2));
+    const size_t m = (size_t)blockIdx.x * TPB + threadIdx.x;   // mode index over the n1 n2 nh modes
+    if (m >= (size_t)n1 * n2 * nh) return;
+    const int q3 = (int)(m % nh);
+    const int q2 = (int)((m / nh) % n2);
+    const int q1 = (int)(m / ((size_t)nh * n2));
+    const size_t e = ((size_t)q1 * n2 + q2) * np + q3;
     const float k1 = (float)(q1 < (n1 >> 1) ? q1 : q1 - n1);
     const float k2 = (float)(q2 < (n2 >> 1) ? q2 : q2 - n2);
     const float k3 = (float)q3;
@@ -729,7 +735,7 @@ int ilog2(int n)
 
 size_t fft_spec_bytes(int n1, int n2, int n3, int ncomp)
 {
-    return (size_t)ncomp * n1 * n2 * (n3 / 2 + 1) * sizeof(float2);
+    return (size_t)ncomp * n1 * n2 * fft_row_pitch(n3) * sizeof(float2);
 }
 
 void fft_make_twiddles(float2 *host, int n, int count)
@@ -780,7 +786,7 @@ void pass_r2c(const FFTPlan &P, const float *in, int nc, int logM, int lognl3, s
         return;
     }
     hipLaunchKernelGGL(k_fft_x3_r2c, dim3(nrows >> lognl3, nc), dim3(TPB), lds3, s, in, P.spec, P.twM, P.twS, logM,
-                       lognl3, nrows, N, spec_cs);
+                       lognl3, nrows, N, spec_cs, P.np);
 }
 
 // x3 inverse pass (half spectrum -> real rows, optional add), nc components
@@ -799,7 +805,7 @@ void pass_c2r(const FFTPlan &P, float *out, const float *add, int nc, int logM, 
         return;
     }
     hipLaunchKernelGGL(k_fft_x3_c2r, dim3(nrows >> lognl3, nc), dim3(TPB), lds3, s, P.spec, out, add, P.twM, P.twS,
-                       logM, lognl3, nrows, N, spec_cs);
+                       logM, lognl3, nrows, N, spec_cs, P.np);
 }
 
 // x2 pass over every x1 plane (forward or inverse), nc components
@@ -808,16 +814,18 @@ void pass_x2(const FFTPlan &P, bool inv, int nc, int logC2, size_t lds2, size_t 
     if (cols_ok(P.n2)) {
         const int C = 4096 / P.n2;
         const dim3 grid((P.nh + C - 1) / C, P.n1, nc);
-        if (inv) launch_cols<2>(P.n2, grid, P.spec, P.tw2, P.nh, (size_t)P.n2 * P.nh, P.nh, spec_cs, 2, 0.f, 1.f, P.n1, P.n2, s);
-        else launch_cols<1>(P.n2, grid, P.spec, P.tw2, P.nh, (size_t)P.n2 * P.nh, P.nh, spec_cs, 2, 0.f, 1.f, P.n1, P.n2, s);
+        if (inv) launch_cols<2>(P.n2, grid, P.spec, P.tw2, P.nh, (size_t)P.n2 * P.np, P.np, spec_cs, 2, 0.f, 1.f, P.n1, P.n2, s);
+        else launch_cols<1>(P.n2, grid, P.spec, P.tw2, P.nh, (size_t)P.n2 * P.np, P.np, spec_cs, 2, 0.f, 1.f, P.n1, P.n2, s);
         return;
     }
     const int C2 = 1 << logC2;
     const dim3 grid((P.nh + C2 - 1) / C2, P.n1, nc);
     if (inv)
-        hipLaunchKernelGGL(k_fft_x2<true>, grid, dim3(TPB), lds2, s, P.spec, P.tw2, ilog2(P.n2), P.n2, P.nh, logC2, spec_cs);
+        hipLaunchKernelGGL(k_fft_x2<true>, grid, dim3(TPB), lds2, s, P.spec, P.tw2, ilog2(P.n2), P.n2, P.nh, P.np, logC2,
+                           spec_cs);
     else
-        hipLaunchKernelGGL(k_fft_x2<false>, grid, dim3(TPB), lds2, s, P.spec, P.tw2, ilog2(P.n2), P.n2, P.nh, logC2, spec_cs);
+        hipLaunchKernelGGL(k_fft_x2<false>, grid, dim3(TPB), lds2, s, P.spec, P.tw2, ilog2(P.n2), P.n2, P.nh, P.np, logC2,
+                           spec_cs);
 }
 
 // x1 pass over every x2 plane: mode 0 forward, symbol, inverse; 1 forward; 2 inverse
@@ -827,15 +835,15 @@ void pass_x1(const FFTPlan &P, int mode, int kind, float beta, float scale, int 
     if (cols_ok(P.n1)) {
         const int C = 4096 / P.n1;
         const dim3 grid((P.nh + C - 1) / C, P.n2, nc);
-        const size_t rs = (size_t)P.n2 * P.nh;
-        if (mode == 0) launch_cols<0>(P.n1, grid, P.spec, P.tw1, P.nh, P.nh, rs, spec_cs, kind, beta, scale, P.n1, P.n2, s);
-        else if (mode == 1) launch_cols<1>(P.n1, grid, P.spec, P.tw1, P.nh, P.nh, rs, spec_cs, kind, beta, scale, P.n1, P.n2, s);
-        else launch_cols<2>(P.n1, grid, P.spec, P.tw1, P.nh, P.nh, rs, spec_cs, kind, beta, scale, P.n1, P.n2, s);
+        const size_t rs = (size_t)P.n2 * P.np;
+        if (mode == 0) launch_cols<0>(P.n1, grid, P.spec, P.tw1, P.nh, P.np, rs, spec_cs, kind, beta, scale, P.n1, P.n2, s);
+        else if (mode == 1) launch_cols<1>(P.n1, grid, P.spec, P.tw1, P.nh, P.np, rs, spec_cs, kind, beta, scale, P.n1, P.n2, s);
+        else launch_cols<2>(P.n1, grid, P.spec, P.tw1, P.nh, P.np, rs, spec_cs, kind, beta, scale, P.n1, P.n2, s);
         return;
     }
     const int C1 = 1 << logC1;
     hipLaunchKernelGGL(k_fft_x1_mult, dim3((P.nh + C1 - 1) / C1, P.n2, nc), dim3(TPB), lds1, s, P.spec, P.tw1,
-                       ilog2(P.n1), P.n1, P.n2, P.nh, logC1, kind, beta, scale, spec_cs, mode);
+                       ilog2(P.n1), P.n1, P.n2, P.nh, P.np, logC1, kind, beta, scale, spec_cs, mode);
 }
 
 } // namespace
@@ -851,10 +859,10 @@ void spectral_apply(const FFTPlan &P, int kind, float beta, float beta_w, int nc
         return;
     }
     if (kind == 3) kind = 2;   // K = I without the divergence term
-    const int n1 = P.n1, n2 = P.n2, n3 = P.n3, nh = P.nh;
+    const int n1 = P.n1, n2 = P.n2, n3 = P.n3;
     const int M = n3 / 2, logM = ilog2(M);
     const size_t N = (size_t)n1 * n2 * n3;
-    const size_t spec_cs = (size_t)n1 * n2 * nh;
+    const size_t spec_cs = (size_t)n1 * n2 * P.np;
     const float scale = (float)(1.0 / (double)N);
     const int nrows = n1 * n2;
     const int logT = ilog2(TILE);
@@ -905,7 +913,7 @@ PassGeom geom(const FFTPlan &P)
     G.lds2 = (size_t)(P.n2 + (size_t)P.n2 * (G.C2 + 1)) * sizeof(float2);
     G.lds1 = (size_t)(P.n1 + (size_t)P.n1 * (G.C1 + 1)) * sizeof(float2);
     G.N = (size_t)P.n1 * P.n2 * P.n3;
-    G.spec_cs = (size_t)P.n1 * P.n2 * P.nh;
+    G.spec_cs = (size_t)P.n1 * P.n2 * P.np;
     return G;
 }
 
@@ -928,8 +936,9 @@ void coupled3(const FFTPlan &P, int kind, float beta_v, float beta_w, const floa
     // every plan of the library holds three components of spectrum
     const PassGeom G = geom(P);
     forward3(P, G, 3, in, s);
-    hipLaunchKernelGGL(k_spec_mult3, dim3((unsigned)((G.spec_cs + TPB - 1) / TPB)), dim3(TPB), 0, s, P.spec, P.n1,
-                       P.n2, P.nh, kind, beta_v, beta_w, (float)(1.0 / (double)G.N), G.spec_cs);
+    const size_t modes = (size_t)P.n1 * P.n2 * P.nh;
+    hipLaunchKernelGGL(k_spec_mult3, dim3((unsigned)((modes + TPB - 1) / TPB)), dim3(TPB), 0, s, P.spec, P.n1, P.n2,
+                       P.nh, P.np, kind, beta_v, beta_w, (float)(1.0 / (double)G.N), G.spec_cs);
     inverse3(P, G, 3, out, s);
 }
 
