@@ -4,6 +4,9 @@
       -> markdown table of per-kernel calls / total / average time
   python -m paper_2209_08189_amd.prof counters <out.md> <title> <command> <dir> [<dir> ...]
       -> markdown table of per-kernel counter means from --pmc runs
+  python -m paper_2209_08189_amd.prof mfma <trace_dir> <pmc_dir> <title> <trace command> <pmc command>
+      -> markdown table of per-kernel time and BF16 MFMA rate (the
+         SQ_INSTS_VALU_MFMA_MOPS_BF16 counter counts units of 512 FLOPs)
   python -m paper_2209_08189_amd.prof traffic <fetch_dir> <write_dir> <copy_MiB> <out.json> <command>
       -> HBM bytes per launch of the SL kernels from FETCH_SIZE / WRITE_SIZE
          runs, scaled by what the same counters read for the library's plain
@@ -23,8 +26,17 @@ TRANSPORT_SRC = os.path.join(HERE, "csrc", "k_transport.hip")
 
 
 def short(name):
+    """Kernel name without namespace, return type and parameter list."""
     n = name.replace("clh::(anonymous namespace)::", "").replace("void ", "")
-    return n.split("(")[0]
+    depth = 0
+    for i, ch in enumerate(n):
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            return n[:i]
+    return n
 
 
 def stats_md(path, title, command):
@@ -117,12 +129,56 @@ def counters_md(dirs, title, command, copy_mib=256, min_us=20.0):
     return "\n".join(out) + "\n"
 
 
+def mfma_md(trace_dir, pmc_dir, title, trace_cmd, pmc_cmd, peak_tflops=2500.0):
+    """Per-kernel duration (kernel trace run) and BF16 MFMA FLOPs per
+    dispatch (counter run: SQ_INSTS_VALU_MFMA_MOPS_BF16 x 512) -> TFLOP/s
+    against the dense BF16 peak."""
+    dur, calls = defaultdict(float), defaultdict(int)
+    path = glob.glob(os.path.join(trace_dir, "**", "*kernel_trace.csv"), recursive=True)[0]
+    for r in csv.DictReader(open(path)):
+        k = short(r["Kernel_Name"])
+        dur[k] += (float(r["End_Timestamp"]) - float(r["Start_Timestamp"])) / 1e3
+        calls[k] += 1
+    mops, n = defaultdict(float), defaultdict(int)
+    path = glob.glob(os.path.join(pmc_dir, "**", "*counter_collection.csv"), recursive=True)[0]
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] == "SQ_INSTS_VALU_MFMA_MOPS_BF16":
+            k = short(r["Kernel_Name"])
+            mops[k] += float(r["Counter_Value"])
+            n[k] += 1
+    total = sum(dur.values())
+    out = ["# %s" % title, "", "Kernel trace:", "", "```", trace_cmd, "```", "", "MFMA counters (separate run):", "",
+           "```", pmc_cmd, "```", "",
+           "| kernel | calls | avg us | %% of kernel time | MFMA GFLOP / dispatch | TFLOP/s | %% of %.0f TFLOP/s |" % peak_tflops,
+           "|---|---:|---:|---:|---:|---:|---:|"]
+    fl_all = t_all = 0.0
+    for k in sorted(dur, key=lambda k: -dur[k]):
+        if dur[k] < 0.005 * total:
+            continue
+        avg = dur[k] / calls[k]
+        if n.get(k) and mops[k] > 0:
+            fl = mops[k] / n[k] * 512.0
+            tf = fl / (avg * 1e-6) / 1e12
+            fl_all += fl * calls[k]
+            t_all += dur[k]
+            out.append("| %s | %d | %.1f | %.1f | %.2f | %.1f | %.1f |" % (k, calls[k], avg, 100 * dur[k] / total,
+                                                                         fl / 1e9, tf, 100 * tf / peak_tflops))
+        else:
+            out.append("| %s | %d | %.1f | %.1f | | | |" % (k, calls[k], avg, 100 * dur[k] / total))
+    if t_all:
+        out += ["", "MFMA kernels together: %.1f TFLOP/s over %.1f ms (%.1f %% of all kernel time)." % (
+            fl_all / (t_all * 1e-6) / 1e12, t_all / 1e3, 100 * t_all / total)]
+    return "\n".join(out) + "\n"
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
         sys.stdout.write(stats_md(sys.argv[2], sys.argv[3], sys.argv[4]))
     elif sys.argv[1] == "counters":
         # counters <out.md> <title> <command> <dir> [<dir> ...]
         open(sys.argv[2], "w").write(counters_md(sys.argv[5:], sys.argv[3], sys.argv[4]))
+    elif sys.argv[1] == "mfma":
+        sys.stdout.write(mfma_md(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], sys.argv[6]))
     elif sys.argv[1] == "traffic":
         rec = traffic(sys.argv[2], sys.argv[3], int(sys.argv[4]), sys.argv[6])
         json.dump(rec, open(sys.argv[5], "w"), indent=1)
