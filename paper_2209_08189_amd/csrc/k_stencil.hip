@@ -218,7 +218,7 @@ constexpr int MAX_NL = 5;                              // time levels kept in re
 
 struct MarchGeom {
     int ntx, nty;   // tiles along x3 and x2
-    int ch;         // planes per chunk along x1
+    int nch;        // chunks per tile column: chunk c covers planes [c n1 / nch, (c + 1) n1 / nch)
 };
 
 __device__ __forceinline__ float fd8_ring(const float *u, float ih)   // u[4] is the centre
@@ -261,7 +261,9 @@ __global__ __launch_bounds__(TPB_M) void k_fd_march(Grid g, MarchGeom mg, QuadAr
     const int tx = b % mg.ntx;
     b /= mg.ntx;
     const int ty = b % mg.nty;
-    const int i0 = (b / mg.nty) * mg.ch;
+    const int c = b / mg.nty;
+    const int i0 = (int)(((long)c * g.n1) / mg.nch);
+    const int len = (int)(((long)(c + 1) * g.n1) / mg.nch) - i0;
     const int l23 = g.l2 + g.l3, m1 = g.n1 - 1;
     const int k = tx * MX + lane, j = ty * MY + w;
     const int col = (j << g.l3) + k;                                     // offset inside a plane
@@ -284,8 +286,25 @@ __global__ __launch_bounds__(TPB_M) void k_fd_march(Grid g, MarchGeom mg, QuadAr
         xv[t] = xh ? ldf(mp[t] + base + xcol) : 0.f;
         nxt[t] = ldf(mp[t] + ((((i0 + MH) & m1) << l23) + col));
     }
+    // operands of a plane's epilogue (lam^t weighted and the addend, or vt),
+    // requested one plane ahead like the stencil values
+    float nlw[NL], ne0, ne1, ne2;
+    auto epilogue_operands = [&](int pp) {
+        if (MODE == 0) {
+#pragma unroll
+            for (int t = 0; t < NL; ++t) nlw[t] = qa.w[t] * ldf((const Tl *)qa.lam[t] + pp);
+            ne0 = add ? add[pp] : 0.f;
+            ne1 = add ? add[N + pp] : 0.f;
+            ne2 = add ? add[2 * N + pp] : 0.f;
+        } else {
+            ne0 = vt[pp];
+            ne1 = vt[N + pp];
+            ne2 = vt[2 * N + pp];
+        }
+    };
+    epilogue_operands(((i0 & m1) << l23) + col);
     double acc = 0.0;
-    for (int step = 0; step < mg.ch; ++step) {
+    for (int step = 0; step < len; ++step) {
         const int i = i0 + step;
         const int buf = step & 1;
         const int p = ((i & m1) << l23) + col;
@@ -296,22 +315,14 @@ __global__ __launch_bounds__(TPB_M) void k_fd_march(Grid g, MarchGeom mg, QuadAr
             pl[buf][t][hr + MH][lane + MH] = hv[t];
             if (xh) pl[buf][t][w + MH][xc + MH] = xv[t];
         }
-        // operands of this plane's epilogue
-        float lw[NL], e0, e1, e2;
-        if (MODE == 0) {
+        float lw[NL];
 #pragma unroll
-            for (int t = 0; t < NL; ++t) lw[t] = qa.w[t] * ldf((const Tl *)qa.lam[t] + p);
-            e0 = add ? add[p] : 0.f;
-            e1 = add ? add[N + p] : 0.f;
-            e2 = add ? add[2 * N + p] : 0.f;
-        } else {
-            e0 = vt[p];
-            e1 = vt[N + p];
-            e2 = vt[2 * N + p];
-        }
+        for (int t = 0; t < NL; ++t) lw[t] = nlw[t];
+        const float e0 = ne0, e1 = ne1, e2 = ne2;
         __syncthreads();
-        // prefetch the next plane's halo and the plane i + 5 of the ring
-        if (step + 1 < mg.ch) {
+        // prefetch the next plane's halo, the plane i + 5 of the ring and the
+        // next plane's epilogue operands
+        if (step + 1 < len) {
             const int nbase = ((i + 1) & m1) << l23;
             const int rbase = ((i + 1 + MH) & m1) << l23;
 #pragma unroll
@@ -320,6 +331,7 @@ __global__ __launch_bounds__(TPB_M) void k_fd_march(Grid g, MarchGeom mg, QuadAr
                 if (xh) xv[t] = ldf(mp[t] + nbase + xcol);
                 nxt[t] = ldf(mp[t] + rbase + col);
             }
+            epilogue_operands(nbase + col);
         }
         float b0 = 0.f, b1 = 0.f, b2 = 0.f;
 #pragma unroll
@@ -424,25 +436,49 @@ void launch_quadrature(const Grid &g, int dt_lam, const QuadArgs &qa, const floa
 
 namespace {
 
-// The marching kernels need whole 64 x 8 tiles in (x3, x2).  Chunk length
-// along x1: 64 planes (8 halo planes per chunk, 12.5 % extra reads of m),
-// halved down to 16 until the launch has at least 2048 blocks.
+// The marching kernels need whole 64 x 8 tiles in (x3, x2).  Each tile
+// column along x1 is cut into nch chunks, and a chunk reads 8 halo planes of
+// m beside its own.  nch minimises (rounds of resident blocks) x (longest
+// chunk + halo), with two resident 512-thread blocks per CU (the register
+// use of five time levels): at 256^3 four chunks of 64 planes, 512 blocks
+// that all run at once (12.5 % halo reads), where 16-plane chunks took 2048
+// blocks in four rounds (50 % halo reads).
 bool march_ok(const Grid &g) { return g.n3 >= MX && g.n2 >= MY; }
+
+int device_cus()
+{
+    static const int n = [] {
+        int d = 0, v = 0;
+        if (hipGetDevice(&d) != hipSuccess || hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, d) !=
+                                                   hipSuccess)
+            v = 0;
+        return v > 0 ? v : 256;
+    }();
+    return n;
+}
 
 MarchGeom march_geom(const Grid &g)
 {
     MarchGeom mg;
     mg.ntx = g.n3 / MX;
     mg.nty = g.n2 / MY;
-    mg.ch = std::min(g.n1, 64);
-    while (mg.ch > 16 && (long)mg.ntx * mg.nty * (g.n1 / mg.ch) < 2048) mg.ch /= 2;
+    const long tiles = (long)mg.ntx * mg.nty, resident = 2L * device_cus();
+    double best = 1e300;
+    mg.nch = 1;
+    for (int n = 1; n <= std::max(1, g.n1 / 8); ++n) {
+        const double cost = (double)((tiles * n + resident - 1) / resident) * ((g.n1 + n - 1) / n + 2 * MH);
+        if (cost < best) {
+            best = cost;
+            mg.nch = n;
+        }
+    }
     return mg;
 }
 
 int march_blocks(const Grid &g)
 {
     const MarchGeom mg = march_geom(g);
-    return mg.ntx * mg.nty * (g.n1 / mg.ch);
+    return mg.ntx * mg.nty * mg.nch;
 }
 
 template <typename Tm, typename Tl>
