@@ -28,6 +28,12 @@ template <> __device__ __forceinline__ float ldf<float>(const float *p) { return
 template <> __device__ __forceinline__ float ldf<__half>(const __half *p) { return __half2float(*p); }
 template <> __device__ __forceinline__ float ldf<__hip_bfloat16>(const __hip_bfloat16 *p) { return __bfloat162float(*p); }
 
+// value at storage precision -> FP32 (so that a load can be issued early and
+// its conversion placed where the value is used)
+__device__ __forceinline__ float tof(float v) { return v; }
+__device__ __forceinline__ float tof(__half v) { return __half2float(v); }
+__device__ __forceinline__ float tof(__hip_bfloat16 v) { return __bfloat162float(v); }
+
 template <typename T> __device__ __forceinline__ void stf(T *p, float v);
 template <> __device__ __forceinline__ void stf<float>(float *p, float v) { *p = v; }
 template <> __device__ __forceinline__ void stf<__half>(__half *p, float v) { *p = __float2half(v); }

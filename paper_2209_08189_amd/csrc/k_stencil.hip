@@ -6,6 +6,8 @@
 // x1/x2 are re-read from L2 by neighbouring workgroups.
 #include "internal.h"
 
+#include <type_traits>
+
 #include <algorithm>
 
 namespace clh {
@@ -276,23 +278,35 @@ __global__ __launch_bounds__(TPB_M) void k_fd_march(Grid g, MarchGeom mg, QuadAr
 #pragma unroll
     for (int t = 0; t < NL; ++t) mp[t] = (const Tm *)qa.m[t];
 
-    float ring[NL][9], nxt[NL], hv[NL], xv[NL];
+    // prefetched values stay at storage precision until they are used, so a
+    // 16-bit load does not have to complete before the next one is issued
+    float ring[NL][9];
+    Tm nxt[NL], hv[NL], xv[NL];
 #pragma unroll
     for (int t = 0; t < NL; ++t) {
 #pragma unroll
         for (int s = 0; s < 8; ++s) ring[t][s] = ldf(mp[t] + ((((i0 - MH + s) & m1) << l23) + col));
         const int base = (i0 & m1) << l23;
-        hv[t] = ldf(mp[t] + base + hcol);
-        xv[t] = xh ? ldf(mp[t] + base + xcol) : 0.f;
-        nxt[t] = ldf(mp[t] + ((((i0 + MH) & m1) << l23) + col));
+        hv[t] = mp[t][base + hcol];
+        if (xh) xv[t] = mp[t][base + xcol];                         // used by the x3-halo lanes only
+        nxt[t] = mp[t][(((i0 + MH) & m1) << l23) + col];
     }
     // operands of a plane's epilogue (lam^t weighted and the addend, or vt),
     // requested one plane ahead like the stencil values
-    float nlw[NL], ne0, ne1, ne2;
+    // lam^t: FP32 values are weighted when they arrive; 16-bit values are kept
+    // raw until the plane that uses them
+    typedef typename std::conditional<sizeof(Tl) == 4, float, Tl>::type LamT;
+    LamT nlam[NL];
+    float ne0, ne1, ne2;
     auto epilogue_operands = [&](int pp) {
         if (MODE == 0) {
 #pragma unroll
-            for (int t = 0; t < NL; ++t) nlw[t] = qa.w[t] * ldf((const Tl *)qa.lam[t] + pp);
+            for (int t = 0; t < NL; ++t) {
+                if constexpr (sizeof(Tl) == 4)
+                    nlam[t] = qa.w[t] * ldf((const Tl *)qa.lam[t] + pp);
+                else
+                    nlam[t] = ((const Tl *)qa.lam[t])[pp];
+            }
             ne0 = add ? add[pp] : 0.f;
             ne1 = add ? add[N + pp] : 0.f;
             ne2 = add ? add[2 * N + pp] : 0.f;
@@ -310,14 +324,19 @@ __global__ __launch_bounds__(TPB_M) void k_fd_march(Grid g, MarchGeom mg, QuadAr
         const int p = ((i & m1) << l23) + col;
 #pragma unroll
         for (int t = 0; t < NL; ++t) {
-            ring[t][8] = nxt[t];
+            ring[t][8] = tof(nxt[t]);
             pl[buf][t][w + MH][lane + MH] = ring[t][4];
-            pl[buf][t][hr + MH][lane + MH] = hv[t];
-            if (xh) pl[buf][t][w + MH][xc + MH] = xv[t];
+            pl[buf][t][hr + MH][lane + MH] = tof(hv[t]);
+            if (xh) pl[buf][t][w + MH][xc + MH] = tof(xv[t]);
         }
         float lw[NL];
 #pragma unroll
-        for (int t = 0; t < NL; ++t) lw[t] = nlw[t];
+        for (int t = 0; t < NL; ++t) {
+            if constexpr (sizeof(Tl) == 4)
+                lw[t] = MODE == 0 ? nlam[t] : 0.f;
+            else
+                lw[t] = MODE == 0 ? qa.w[t] * tof(nlam[t]) : 0.f;
+        }
         const float e0 = ne0, e1 = ne1, e2 = ne2;
         __syncthreads();
         // prefetch the next plane's halo, the plane i + 5 of the ring and the
@@ -327,9 +346,9 @@ __global__ __launch_bounds__(TPB_M) void k_fd_march(Grid g, MarchGeom mg, QuadAr
             const int rbase = ((i + 1 + MH) & m1) << l23;
 #pragma unroll
             for (int t = 0; t < NL; ++t) {
-                hv[t] = ldf(mp[t] + nbase + hcol);
-                if (xh) xv[t] = ldf(mp[t] + nbase + xcol);
-                nxt[t] = ldf(mp[t] + rbase + col);
+                hv[t] = mp[t][nbase + hcol];
+                if (xh) xv[t] = mp[t][nbase + xcol];
+                nxt[t] = mp[t][rbase + col];
             }
             epilogue_operands(nbase + col);
         }
