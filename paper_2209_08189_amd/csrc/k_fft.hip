@@ -522,6 +522,14 @@ __global__ __launch_bounds__(TPB) void k_fft_cols(float2 *__restrict__ spec, con
 // 16 consecutive complex values per row per instruction.
 template <int R2> constexpr int rows_pitch() { return 17 * R2 + 16; }
 
+// Lane i of each 16-lane row receives x of lane 16 - i of the same row
+// (DPP row mirror, i -> 15 - i, then a shift by one lane); lane 0 receives 0.
+__device__ __forceinline__ float row_reflect16(float x)
+{
+    const int m = __builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x140, 0xf, 0xf, false);   // row_mirror
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, m, 0x111, 0xf, 0xf, false));         // row_shr:1
+}
+
 template <int R2, bool INV>
 __device__ __forceinline__ void rows_cb(float2 (&v)[16], float2 *ex, const float2 *tw)
 {
@@ -616,15 +624,24 @@ __global__ __launch_bounds__(TPB) void k_fft_rows_c2r(const float2 *__restrict__
     for (int t = threadIdx.x; t < M; t += TPB) twm[t] = twM[t];
     for (int t = threadIdx.x; t <= M; t += TPB) tws[t] = tw3[t];
     const int c = threadIdx.x & 15, r0 = threadIdx.x >> 4;
-    float2 xa[16], xb[16];
+    float2 xa[16], xb[16], nyq[PP];
+#pragma unroll
+    for (int u = 0; u < PP; ++u) {
+        const float2 *srow = src + (size_t)(r0 + 16 * u) * NP;
+#pragma unroll
+        for (int d = 0; d < R2; ++d) xa[u * R2 + d] = srow[c + 16 * d];
+        nyq[u] = c == 0 ? srow[M] : make_float2(0.f, 0.f);
+    }
+    // X[M - k] for k = c + 16 d: for c > 0 it is X[(16 - c) + 16 (R2 - 1 - d)],
+    // held by lane 16 - c of the same 16-lane row (a row reflection by DPP);
+    // for c = 0 it is this lane's X[16 (R2 - d)], or the Nyquist value at d = 0
 #pragma unroll
     for (int u = 0; u < PP; ++u)
 #pragma unroll
         for (int d = 0; d < R2; ++d) {
-            const float2 *srow = src + (size_t)(r0 + 16 * u) * NP;
-            const int k = c + 16 * d;
-            xa[u * R2 + d] = srow[k];
-            xb[u * R2 + d] = srow[M - k];
+            const float2 o = xa[u * R2 + R2 - 1 - d];
+            const float2 m = make_float2(row_reflect16(o.x), row_reflect16(o.y));
+            xb[u * R2 + d] = c ? m : (d ? xa[u * R2 + R2 - d] : nyq[u]);
         }
     __syncthreads();                                          // twiddle tables
     // Z[k] = (X[k] + conj X[M-k]) + i e^{+2 pi i k / n3} (X[k] - conj X[M-k])
