@@ -34,6 +34,18 @@ __device__ __forceinline__ float tof(float v) { return v; }
 __device__ __forceinline__ float tof(__half v) { return __half2float(v); }
 __device__ __forceinline__ float tof(__hip_bfloat16 v) { return __bfloat162float(v); }
 
+// element idx of a field at a wave-uniform base, addressed by a 32-bit byte
+// offset (a field has at most 2^30 nodes, so idx * sizeof(T) < 2^32): the
+// access then takes the scalar-base form with no 64-bit address arithmetic
+template <typename T> __device__ __forceinline__ const T &at(const T *base, unsigned idx)
+{
+    return *(const T *)((const char *)base + idx * (unsigned)sizeof(T));
+}
+template <typename T> __device__ __forceinline__ T &at(T *base, unsigned idx)
+{
+    return *(T *)((char *)base + idx * (unsigned)sizeof(T));
+}
+
 template <typename T> __device__ __forceinline__ void stf(T *p, float v);
 template <> __device__ __forceinline__ void stf<float>(float *p, float v) { *p = v; }
 template <> __device__ __forceinline__ void stf<__half>(__half *p, float v) { *p = __float2half(v); }

@@ -15,10 +15,11 @@
 //   x3 C2R    Hermitian merge, inverse FFT of length M, unpack to reals,
 //             optional fused add.
 // Inside a pass a workgroup owns a tile of nl lines x L points (nl L = 4096
-// complex, 32 KB): coalesced batched loads into LDS, then Stockham stages of
-// radix 16 (and one of radix 2/4/8 for the remainder) with every group's R
-// values in registers, twiddles from FP64-computed tables staged in LDS, and
-// a coalesced store.  The LDS tile is stored as [q][l] with pitch nl + 1 so
+// complex, 32 KB; in the column passes 16 columns of 512 or 1024 points,
+// held by 512 or 1024 threads): coalesced batched loads into LDS, then
+// Stockham stages of radix 16 (and one of radix 2/4/8 for the remainder)
+// with every group's R values in registers, twiddles from FP64-computed
+// tables staged in LDS, and a coalesced store.  The LDS tile is stored as [q][l] with pitch nl + 1 so
 // that both row-wise and column-wise accesses are conflict-free.
 #include "internal.h"
 
@@ -102,18 +103,18 @@ template <int R, bool INV> __device__ __forceinline__ void dft_reg(float2 *v)
 // the product of the radices of the earlier stages.  tw[t] = e^{-2 pi i t / L}
 // (t < L).  Every thread reads all its groups, the workgroup synchronises,
 // then the results are written back, so the stage is safe in place.
-template <int R, bool INV>
+template <int R, bool INV, int NT>
 __device__ __forceinline__ void stage(float2 *lds, int P, int lognl, int logL, int logNs, const float2 *tw)
 {
     constexpr int LOGR = R == 2 ? 1 : R == 4 ? 2 : R == 8 ? 3 : 4;
-    constexpr int G = EPT / R;          // groups per thread (tile holds 4096 values)
+    constexpr int G = EPT / R;          // groups per thread (the tile holds EPT values per thread)
     const int nl = 1 << lognl, L = 1 << logL, Ns = 1 << logNs;
     const int ngroups = nl << (logL - LOGR);
     const int LR = L >> LOGR;
     float2 v[G][R];
 #pragma unroll
     for (int gq = 0; gq < G; ++gq) {
-        const int gi = gq * TPB + threadIdx.x;
+        const int gi = gq * NT + threadIdx.x;
         if (gi < ngroups) {
             const int l = gi & (nl - 1), j = gi >> lognl;
 #pragma unroll
@@ -123,7 +124,7 @@ __device__ __forceinline__ void stage(float2 *lds, int P, int lognl, int logL, i
     __syncthreads();
 #pragma unroll
     for (int gq = 0; gq < G; ++gq) {
-        const int gi = gq * TPB + threadIdx.x;
+        const int gi = gq * NT + threadIdx.x;
         if (gi < ngroups) {
             const int l = gi & (nl - 1), j = gi >> lognl;
             const int jm = j & (Ns - 1);
@@ -146,22 +147,23 @@ __device__ __forceinline__ void stage(float2 *lds, int P, int lognl, int logL, i
 }
 
 // Full FFT of the tile's lines: radix-16 stages, then one radix-2/4/8 stage.
-template <bool INV> __device__ void fft_lines(float2 *lds, int P, int lognl, int logL, const float2 *tw)
+// NT threads per workgroup, EPT values per thread.
+template <bool INV, int NT = TPB> __device__ void fft_lines(float2 *lds, int P, int lognl, int logL, const float2 *tw)
 {
     int logNs = 0;
     while (logL - logNs >= 4) {
-        stage<16, INV>(lds, P, lognl, logL, logNs, tw);
+        stage<16, INV, NT>(lds, P, lognl, logL, logNs, tw);
         logNs += 4;
     }
     const int rem = logL - logNs;
-    if (rem == 3) stage<8, INV>(lds, P, lognl, logL, logNs, tw);
-    else if (rem == 2) stage<4, INV>(lds, P, lognl, logL, logNs, tw);
-    else if (rem == 1) stage<2, INV>(lds, P, lognl, logL, logNs, tw);
+    if (rem == 3) stage<8, INV, NT>(lds, P, lognl, logL, logNs, tw);
+    else if (rem == 2) stage<4, INV, NT>(lds, P, lognl, logL, logNs, tw);
+    else if (rem == 1) stage<2, INV, NT>(lds, P, lognl, logL, logNs, tw);
 }
 
-__device__ __forceinline__ void load_table(float2 *dst, const float2 *__restrict__ src, int n)
+template <int NT = TPB> __device__ __forceinline__ void load_table(float2 *dst, const float2 *__restrict__ src, int n)
 {
-    for (int t = threadIdx.x; t < n; t += TPB) dst[t] = src[t];
+    for (int t = threadIdx.x; t < n; t += NT) dst[t] = src[t];
 }
 
 // --- x3 forward: real rows -> half spectrum.  nl = 2^lognl rows per tile.
@@ -291,42 +293,48 @@ __global__ __launch_bounds__(TPB) void k_fft_x3_c2r(const float2 *__restrict__ s
 }
 
 // --- column tile load/store for the x2 and x1 passes: element (l, q) of
-// the tile is base[q * rs + l], l < cw valid columns.
+// the tile is base[q * rs + l], l < cw valid columns; NT threads.  A thread
+// keeps its column l and steps through the rows q0, q0 + NT / C, ...: the
+// row part of an address is wave-uniform (a scalar base), the thread's part a
+// 32-bit byte offset (below 1/16 of one component's half spectrum).
+template <int NT>
 __device__ __forceinline__ void load_cols(float2 *lds, const float2 *__restrict__ base, size_t rs, int logC, int logL,
                                           int cw, int P)
 {
-    const int C = 1 << logC, tot = C << logL;
+    const int C = 1 << logC, L = 1 << logL;
+    const int l = threadIdx.x & (C - 1), q0 = threadIdx.x >> logC, QS = NT >> logC;
+    const unsigned off = (unsigned)(((size_t)q0 * rs + l) * sizeof(float2));
     float2 buf[EPT];
 #pragma unroll
     for (int it = 0; it < EPT; ++it) {
-        const int e = it * TPB + threadIdx.x;
-        const int l = e & (C - 1), q = e >> logC;
-        if (e < tot) buf[it] = l < cw ? base[q * rs + l] : make_float2(0.f, 0.f);
+        const char *row = (const char *)(base + (size_t)it * QS * rs);
+        if (q0 + it * QS < L) buf[it] = l < cw ? *(const float2 *)(row + off) : make_float2(0.f, 0.f);
     }
 #pragma unroll
-    for (int it = 0; it < EPT; ++it) {
-        const int e = it * TPB + threadIdx.x;
-        if (e < tot) lds[(e >> logC) * P + (e & (C - 1))] = buf[it];
-    }
+    for (int it = 0; it < EPT; ++it)
+        if (q0 + it * QS < L) lds[(q0 + it * QS) * P + l] = buf[it];
     __syncthreads();
 }
 
+template <int NT>
 __device__ __forceinline__ void store_cols(const float2 *lds, float2 *__restrict__ base, size_t rs, int logC, int logL,
                                            int cw, int P)
 {
-    const int C = 1 << logC, tot = C << logL;
+    const int C = 1 << logC, L = 1 << logL;
+    const int l = threadIdx.x & (C - 1), q0 = threadIdx.x >> logC, QS = NT >> logC;
+    const unsigned off = (unsigned)(((size_t)q0 * rs + l) * sizeof(float2));
 #pragma unroll
     for (int it = 0; it < EPT; ++it) {
-        const int e = it * TPB + threadIdx.x;
-        const int l = e & (C - 1), q = e >> logC;
-        if (e < tot && l < cw) base[q * rs + l] = lds[q * P + l];
+        char *row = (char *)(base + (size_t)it * QS * rs);
+        if (q0 + it * QS < L && l < cw) *(float2 *)(row + off) = lds[(q0 + it * QS) * P + l];
     }
 }
 
 // --- x2 C2C in place on the half spectrum: plane i1 = blockIdx.y, columns
-// [c0, c0 + C) of the nh per row.
-template <bool INV>
-__global__ __launch_bounds__(TPB) void k_fft_x2(float2 *__restrict__ spec, const float2 *__restrict__ tw2, int logn2,
+// [c0, c0 + C) of the nh per row; NT threads hold the tile of NT EPT values.
+// (512-thread tiles take at most 128 VGPRs, so that two fit a CU)
+template <bool INV, int NT>
+__global__ __launch_bounds__(NT, NT == 512 ? 4 : 1) void k_fft_x2(float2 *__restrict__ spec, const float2 *__restrict__ tw2, int logn2,
                                                 int n2, int nh, int np, int logC, size_t spec_cs)
 {
     extern __shared__ float2 sm[];
@@ -336,16 +344,17 @@ __global__ __launch_bounds__(TPB) void k_fft_x2(float2 *__restrict__ spec, const
     const int comp = blockIdx.z, i1 = blockIdx.y, c0 = blockIdx.x * C;
     const int cw = min(C, nh - c0);
     float2 *base = spec + comp * spec_cs + (size_t)i1 * n2 * np + c0;
-    load_table(tw, tw2, n2);
-    load_cols(lds, base, np, logC, logn2, cw, P);
-    fft_lines<INV>(lds, P, logC, logn2, tw);
-    store_cols(lds, base, np, logC, logn2, cw, P);
+    load_table<NT>(tw, tw2, n2);
+    load_cols<NT>(lds, base, np, logC, logn2, cw, P);
+    fft_lines<INV, NT>(lds, P, logC, logn2, tw);
+    store_cols<NT>(lds, base, np, logC, logn2, cw, P);
 }
 
 // --- x1 fused: forward FFT along x1, symbol multiply, inverse FFT.
 // plane i2 = blockIdx.y, columns [c0, c0 + C).
 // mode 0: forward, multiply, inverse; 1: forward only; 2: inverse only
-__global__ __launch_bounds__(TPB) void k_fft_x1_mult(float2 *__restrict__ spec, const float2 *__restrict__ tw1,
+template <int NT>
+__global__ __launch_bounds__(NT, NT == 512 ? 4 : 1) void k_fft_x1_mult(float2 *__restrict__ spec, const float2 *__restrict__ tw1,
                                                      int logn1, int n1, int n2, int nh, int np, int logC, int kind,
                                                      float beta, float scale, size_t spec_cs, int mode)
 {
@@ -357,21 +366,21 @@ __global__ __launch_bounds__(TPB) void k_fft_x1_mult(float2 *__restrict__ spec, 
     const int cw = min(C, nh - c0);
     float2 *base = spec + comp * spec_cs + (size_t)i2 * np + c0;
     const size_t rs = (size_t)n2 * np;
-    load_table(tw, tw1, n1);
-    load_cols(lds, base, rs, logC, logn1, cw, P);
+    load_table<NT>(tw, tw1, n1);
+    load_cols<NT>(lds, base, rs, logC, logn1, cw, P);
     if (mode == 2) {
-        fft_lines<true>(lds, P, logC, logn1, tw);
-        store_cols(lds, base, rs, logC, logn1, cw, P);
+        fft_lines<true, NT>(lds, P, logC, logn1, tw);
+        store_cols<NT>(lds, base, rs, logC, logn1, cw, P);
         return;
     }
-    fft_lines<false>(lds, P, logC, logn1, tw);
+    fft_lines<false, NT>(lds, P, logC, logn1, tw);
     if (mode == 1) {
-        store_cols(lds, base, rs, logC, logn1, cw, P);
+        store_cols<NT>(lds, base, rs, logC, logn1, cw, P);
         return;
     }
     const float k2 = (float)(i2 < (n2 >> 1) ? i2 : i2 - n2);
     const int tot = C << logn1;
-    for (int e = threadIdx.x; e < tot; e += TPB) {
+    for (int e = threadIdx.x; e < tot; e += NT) {
         const int l = e & (C - 1), q = e >> logC;
         const float k1 = (float)(q < (n1 >> 1) ? q : q - n1);
         const float k3 = (float)(c0 + l);
@@ -386,8 +395,8 @@ __global__ __launch_bounds__(TPB) void k_fft_x1_mult(float2 *__restrict__ spec, 
         x.y *= sym;
     }
     __syncthreads();
-    fft_lines<true>(lds, P, logC, logn1, tw);
-    store_cols(lds, base, rs, logC, logn1, cw, P);
+    fft_lines<true, NT>(lds, P, logC, logn1, tw);
+    store_cols<NT>(lds, base, rs, logC, logn1, cw, P);
 }
 
 // --- register-resident column passes for lines of L = 16 R2 points (R2 =
@@ -825,8 +834,58 @@ void pass_c2r(const FFTPlan &P, float *out, const float *add, int nc, int logM, 
                        logM, lognl3, nrows, N, spec_cs, P.np);
 }
 
+// Stockham column passes (line lengths other than 128 and 256): NT threads
+// per workgroup hold a tile of NT EPT values, C = NT EPT / L columns (at most
+// 32).  Lines of 512 points and more take 512 or 1024 threads, so that a tile
+// keeps 16 columns (128-byte row pieces) up to L = 1024.
+struct ColGeom {
+    int nt, logC;
+    size_t lds;   // twiddle table + tile at pitch C + 1
+};
+
+ColGeom col_geom(int L)
+{
+    ColGeom c;
+    c.nt = L >= 1024 ? 1024 : L >= 512 ? 512 : TPB;
+    const int logT = ilog2(c.nt * EPT);
+    c.logC = logT - ilog2(L) > 5 ? 5 : logT - ilog2(L);
+    c.lds = (size_t)(L + (size_t)L * ((1 << c.logC) + 1)) * sizeof(float2);
+    return c;
+}
+
+// dynamic LDS above 64 KB (up to the 160 KB of a gfx950 CU) is granted per kernel
+template <typename K> void allow_lds(K kernel, size_t bytes)
+{
+    if (bytes > 65536)
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)bytes);
+}
+
+template <int NT>
+void launch_x2(const FFTPlan &P, bool inv, dim3 grid, int logC, size_t lds, size_t spec_cs, hipStream_t s)
+{
+    if (inv) {
+        allow_lds(k_fft_x2<true, NT>, lds);
+        hipLaunchKernelGGL((k_fft_x2<true, NT>), grid, dim3(NT), lds, s, P.spec, P.tw2, ilog2(P.n2), P.n2, P.nh, P.np,
+                           logC, spec_cs);
+    } else {
+        allow_lds(k_fft_x2<false, NT>, lds);
+        hipLaunchKernelGGL((k_fft_x2<false, NT>), grid, dim3(NT), lds, s, P.spec, P.tw2, ilog2(P.n2), P.n2, P.nh, P.np,
+                           logC, spec_cs);
+    }
+}
+
+template <int NT>
+void launch_x1(const FFTPlan &P, int mode, int kind, float beta, float scale, dim3 grid, int logC, size_t lds,
+               size_t spec_cs, hipStream_t s)
+{
+    allow_lds(k_fft_x1_mult<NT>, lds);
+    hipLaunchKernelGGL((k_fft_x1_mult<NT>), grid, dim3(NT), lds, s, P.spec, P.tw1, ilog2(P.n1), P.n1, P.n2, P.nh, P.np,
+                       logC, kind, beta, scale, spec_cs, mode);
+}
+
 // x2 pass over every x1 plane (forward or inverse), nc components
-void pass_x2(const FFTPlan &P, bool inv, int nc, int logC2, size_t lds2, size_t spec_cs, hipStream_t s)
+void pass_x2(const FFTPlan &P, bool inv, int nc, size_t spec_cs, hipStream_t s)
 {
     if (cols_ok(P.n2)) {
         const int C = 4096 / P.n2;
@@ -835,19 +894,16 @@ void pass_x2(const FFTPlan &P, bool inv, int nc, int logC2, size_t lds2, size_t 
         else launch_cols<1>(P.n2, grid, P.spec, P.tw2, P.nh, (size_t)P.n2 * P.np, P.np, spec_cs, 2, 0.f, 1.f, P.n1, P.n2, s);
         return;
     }
-    const int C2 = 1 << logC2;
+    const ColGeom cg = col_geom(P.n2);
+    const int C2 = 1 << cg.logC;
     const dim3 grid((P.nh + C2 - 1) / C2, P.n1, nc);
-    if (inv)
-        hipLaunchKernelGGL(k_fft_x2<true>, grid, dim3(TPB), lds2, s, P.spec, P.tw2, ilog2(P.n2), P.n2, P.nh, P.np, logC2,
-                           spec_cs);
-    else
-        hipLaunchKernelGGL(k_fft_x2<false>, grid, dim3(TPB), lds2, s, P.spec, P.tw2, ilog2(P.n2), P.n2, P.nh, P.np, logC2,
-                           spec_cs);
+    if (cg.nt == 1024) launch_x2<1024>(P, inv, grid, cg.logC, cg.lds, spec_cs, s);
+    else if (cg.nt == 512) launch_x2<512>(P, inv, grid, cg.logC, cg.lds, spec_cs, s);
+    else launch_x2<TPB>(P, inv, grid, cg.logC, cg.lds, spec_cs, s);
 }
 
 // x1 pass over every x2 plane: mode 0 forward, symbol, inverse; 1 forward; 2 inverse
-void pass_x1(const FFTPlan &P, int mode, int kind, float beta, float scale, int nc, int logC1, size_t lds1,
-             size_t spec_cs, hipStream_t s)
+void pass_x1(const FFTPlan &P, int mode, int kind, float beta, float scale, int nc, size_t spec_cs, hipStream_t s)
 {
     if (cols_ok(P.n1)) {
         const int C = 4096 / P.n1;
@@ -858,9 +914,12 @@ void pass_x1(const FFTPlan &P, int mode, int kind, float beta, float scale, int 
         else launch_cols<2>(P.n1, grid, P.spec, P.tw1, P.nh, P.np, rs, spec_cs, kind, beta, scale, P.n1, P.n2, s);
         return;
     }
-    const int C1 = 1 << logC1;
-    hipLaunchKernelGGL(k_fft_x1_mult, dim3((P.nh + C1 - 1) / C1, P.n2, nc), dim3(TPB), lds1, s, P.spec, P.tw1,
-                       ilog2(P.n1), P.n1, P.n2, P.nh, P.np, logC1, kind, beta, scale, spec_cs, mode);
+    const ColGeom cg = col_geom(P.n1);
+    const int C1 = 1 << cg.logC;
+    const dim3 grid((P.nh + C1 - 1) / C1, P.n2, nc);
+    if (cg.nt == 1024) launch_x1<1024>(P, mode, kind, beta, scale, grid, cg.logC, cg.lds, spec_cs, s);
+    else if (cg.nt == 512) launch_x1<512>(P, mode, kind, beta, scale, grid, cg.logC, cg.lds, spec_cs, s);
+    else launch_x1<TPB>(P, mode, kind, beta, scale, grid, cg.logC, cg.lds, spec_cs, s);
 }
 
 } // namespace
@@ -887,21 +946,15 @@ void spectral_apply(const FFTPlan &P, int kind, float beta, float beta_w, int nc
     int lognl3 = logT - logM;            // M >= 8, so nl <= TILE / 8
     if ((1 << lognl3) > nrows) lognl3 = ilog2(nrows);
     const size_t lds3 = (size_t)(M + M + 1 + ((size_t)M + 1) * ((1 << lognl3) + 1)) * sizeof(float2);
-    // x2 / x1: C columns of n2 / n1 per tile
-    const int logC2 = logT - ilog2(n2) > 5 ? 5 : logT - ilog2(n2);
-    const int logC1 = logT - ilog2(n1) > 5 ? 5 : logT - ilog2(n1);
-    const int C2 = 1 << logC2, C1 = 1 << logC1;
-    const size_t lds2 = (size_t)(n2 + (size_t)n2 * (C2 + 1)) * sizeof(float2);
-    const size_t lds1 = (size_t)(n1 + (size_t)n1 * (C1 + 1)) * sizeof(float2);
     for (int c0 = 0; c0 < ncomp; c0 += P.ncomp_max) {
         const int nc = ncomp - c0 < P.ncomp_max ? ncomp - c0 : P.ncomp_max;
         const float *inc = in + c0 * N;
         float *outc = out + c0 * N;
         const float *addc = add ? add + c0 * N : nullptr;
         pass_r2c(P, inc, nc, logM, lognl3, lds3, spec_cs, s);
-        pass_x2(P, false, nc, logC2, lds2, spec_cs, s);
-        pass_x1(P, 0, kind, beta, scale, nc, logC1, lds1, spec_cs, s);
-        pass_x2(P, true, nc, logC2, lds2, spec_cs, s);
+        pass_x2(P, false, nc, spec_cs, s);
+        pass_x1(P, 0, kind, beta, scale, nc, spec_cs, s);
+        pass_x2(P, true, nc, spec_cs, s);
         pass_c2r(P, outc, addc, nc, logM, lognl3, lds3, spec_cs, s);
     }
 }
@@ -909,8 +962,8 @@ void spectral_apply(const FFTPlan &P, int kind, float beta, float beta_w, int nc
 namespace {
 
 struct PassGeom {
-    int logM, lognl3, logC1, logC2, C1, C2, nrows;
-    size_t lds1, lds2, lds3, N, spec_cs;
+    int logM, lognl3, nrows;
+    size_t lds3, N, spec_cs;
 };
 
 PassGeom geom(const FFTPlan &P)
@@ -923,12 +976,6 @@ PassGeom geom(const FFTPlan &P)
     if ((1 << G.lognl3) > G.nrows) G.lognl3 = ilog2(G.nrows);
     const int M = P.n3 / 2;
     G.lds3 = (size_t)(M + M + 1 + ((size_t)M + 1) * ((1 << G.lognl3) + 1)) * sizeof(float2);
-    G.logC2 = logT - ilog2(P.n2) > 5 ? 5 : logT - ilog2(P.n2);
-    G.logC1 = logT - ilog2(P.n1) > 5 ? 5 : logT - ilog2(P.n1);
-    G.C1 = 1 << G.logC1;
-    G.C2 = 1 << G.logC2;
-    G.lds2 = (size_t)(P.n2 + (size_t)P.n2 * (G.C2 + 1)) * sizeof(float2);
-    G.lds1 = (size_t)(P.n1 + (size_t)P.n1 * (G.C1 + 1)) * sizeof(float2);
     G.N = (size_t)P.n1 * P.n2 * P.n3;
     G.spec_cs = (size_t)P.n1 * P.n2 * P.np;
     return G;
@@ -937,14 +984,14 @@ PassGeom geom(const FFTPlan &P)
 void forward3(const FFTPlan &P, const PassGeom &G, int nc, const float *in, hipStream_t s)
 {
     pass_r2c(P, in, nc, G.logM, G.lognl3, G.lds3, G.spec_cs, s);
-    pass_x2(P, false, nc, G.logC2, G.lds2, G.spec_cs, s);
-    pass_x1(P, 1, 2, 0.f, 1.f, nc, G.logC1, G.lds1, G.spec_cs, s);
+    pass_x2(P, false, nc, G.spec_cs, s);
+    pass_x1(P, 1, 2, 0.f, 1.f, nc, G.spec_cs, s);
 }
 
 void inverse3(const FFTPlan &P, const PassGeom &G, int nc, float *out, hipStream_t s)
 {
-    pass_x1(P, 2, 2, 0.f, 1.f, nc, G.logC1, G.lds1, G.spec_cs, s);
-    pass_x2(P, true, nc, G.logC2, G.lds2, G.spec_cs, s);
+    pass_x1(P, 2, 2, 0.f, 1.f, nc, G.spec_cs, s);
+    pass_x2(P, true, nc, G.spec_cs, s);
     pass_c2r(P, out, nullptr, nc, G.logM, G.lognl3, G.lds3, G.spec_cs, s);
 }
 

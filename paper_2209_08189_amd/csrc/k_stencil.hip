@@ -253,7 +253,7 @@ __global__ __launch_bounds__(TPB_M) void k_fd_march(Grid g, MarchGeom mg, QuadAr
                                                     float scale, To *__restrict__ out1)
 {
     __shared__ float pl[2][NL][MPY][MPX];
-    const size_t N = g.N;
+    const unsigned N = (unsigned)g.N;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     // XCD-aware order: each XCD takes a contiguous range of tiles, so the
     // x2 neighbours of a tile run on the same L2
@@ -268,15 +268,20 @@ __global__ __launch_bounds__(TPB_M) void k_fd_march(Grid g, MarchGeom mg, QuadAr
     const int len = (int)(((long)(c + 1) * g.n1) / mg.nch) - i0;
     const int l23 = g.l2 + g.l3, m1 = g.n1 - 1;
     const int k = tx * MX + lane, j = ty * MY + w;
-    const int col = (j << g.l3) + k;                                     // offset inside a plane
+    // element offsets inside a plane (unsigned: every access below is a
+    // wave-uniform field base plus a 32-bit offset)
+    const unsigned col = ((unsigned)j << g.l3) + k;
     const int hr = w < MH ? w - MH : w + MH;                             // x2 halo row of this thread
-    const int hcol = (((ty * MY + hr) & (g.n2 - 1)) << g.l3) + k;
+    const unsigned hcol = ((unsigned)((ty * MY + hr) & (g.n2 - 1)) << g.l3) + k;
     const bool xh = lane < 2 * MH;                                       // lanes that load the x3 halo
     const int xc = lane < MH ? lane - MH : MX + lane - MH;
-    const int xcol = (j << g.l3) + ((tx * MX + xc) & (g.n3 - 1));
+    const unsigned xcol = ((unsigned)j << g.l3) + ((tx * MX + xc) & (g.n3 - 1));
+    auto plane = [&](int i) { return (unsigned)(i & m1) << l23; };
     const Tm *mp[NL];
 #pragma unroll
     for (int t = 0; t < NL; ++t) mp[t] = (const Tm *)qa.m[t];
+    const float *add1 = add ? add + N : nullptr, *add2 = add ? add + 2 * (size_t)N : nullptr;
+    const float *vt1 = vt ? vt + N : nullptr, *vt2 = vt ? vt + 2 * (size_t)N : nullptr;
 
     // prefetched values stay at storage precision until they are used, so a
     // 16-bit load does not have to complete before the next one is issued
@@ -285,11 +290,11 @@ __global__ __launch_bounds__(TPB_M) void k_fd_march(Grid g, MarchGeom mg, QuadAr
 #pragma unroll
     for (int t = 0; t < NL; ++t) {
 #pragma unroll
-        for (int s = 0; s < 8; ++s) ring[t][s] = ldf(mp[t] + ((((i0 - MH + s) & m1) << l23) + col));
-        const int base = (i0 & m1) << l23;
-        hv[t] = mp[t][base + hcol];
-        if (xh) xv[t] = mp[t][base + xcol];                         // used by the x3-halo lanes only
-        nxt[t] = mp[t][(((i0 + MH) & m1) << l23) + col];
+        for (int s = 0; s < 8; ++s) ring[t][s] = tof(at(mp[t], plane(i0 - MH + s) + col));
+        const unsigned base = plane(i0);
+        hv[t] = at(mp[t], base + hcol);
+        if (xh) xv[t] = at(mp[t], base + xcol);                     // used by the x3-halo lanes only
+        nxt[t] = at(mp[t], plane(i0 + MH) + col);
     }
     // operands of a plane's epilogue (lam^t weighted and the addend, or vt),
     // requested one plane ahead like the stencil values
@@ -298,30 +303,30 @@ __global__ __launch_bounds__(TPB_M) void k_fd_march(Grid g, MarchGeom mg, QuadAr
     typedef typename std::conditional<sizeof(Tl) == 4, float, Tl>::type LamT;
     LamT nlam[NL];
     float ne0, ne1, ne2;
-    auto epilogue_operands = [&](int pp) {
+    auto epilogue_operands = [&](unsigned pp) {
         if (MODE == 0) {
 #pragma unroll
             for (int t = 0; t < NL; ++t) {
                 if constexpr (sizeof(Tl) == 4)
-                    nlam[t] = qa.w[t] * ldf((const Tl *)qa.lam[t] + pp);
+                    nlam[t] = qa.w[t] * tof(at((const Tl *)qa.lam[t], pp));
                 else
-                    nlam[t] = ((const Tl *)qa.lam[t])[pp];
+                    nlam[t] = at((const Tl *)qa.lam[t], pp);
             }
-            ne0 = add ? add[pp] : 0.f;
-            ne1 = add ? add[N + pp] : 0.f;
-            ne2 = add ? add[2 * N + pp] : 0.f;
+            ne0 = add ? at(add, pp) : 0.f;
+            ne1 = add ? at(add1, pp) : 0.f;
+            ne2 = add ? at(add2, pp) : 0.f;
         } else {
-            ne0 = vt[pp];
-            ne1 = vt[N + pp];
-            ne2 = vt[2 * N + pp];
+            ne0 = at(vt, pp);
+            ne1 = at(vt1, pp);
+            ne2 = at(vt2, pp);
         }
     };
-    epilogue_operands(((i0 & m1) << l23) + col);
+    epilogue_operands(plane(i0) + col);
     double acc = 0.0;
     for (int step = 0; step < len; ++step) {
         const int i = i0 + step;
         const int buf = step & 1;
-        const int p = ((i & m1) << l23) + col;
+        const unsigned p = plane(i) + col;
 #pragma unroll
         for (int t = 0; t < NL; ++t) {
             ring[t][8] = tof(nxt[t]);
@@ -342,13 +347,13 @@ __global__ __launch_bounds__(TPB_M) void k_fd_march(Grid g, MarchGeom mg, QuadAr
         // prefetch the next plane's halo, the plane i + 5 of the ring and the
         // next plane's epilogue operands
         if (step + 1 < len) {
-            const int nbase = ((i + 1) & m1) << l23;
-            const int rbase = ((i + 1 + MH) & m1) << l23;
+            const unsigned nbase = plane(i + 1);
+            const unsigned rbase = plane(i + 1 + MH);
 #pragma unroll
             for (int t = 0; t < NL; ++t) {
-                hv[t] = mp[t][nbase + hcol];
-                if (xh) xv[t] = mp[t][nbase + xcol];
-                nxt[t] = mp[t][rbase + col];
+                hv[t] = at(mp[t], nbase + hcol);
+                if (xh) xv[t] = at(mp[t], nbase + xcol);
+                nxt[t] = at(mp[t], rbase + col);
             }
             epilogue_operands(nbase + col);
         }
@@ -365,8 +370,8 @@ __global__ __launch_bounds__(TPB_M) void k_fd_march(Grid g, MarchGeom mg, QuadAr
                 b2 = fmaf(lw[t], d2, b2);
             } else if (MODE == 2) {
                 const float sv = -(e0 * d0 + e1 * d1 + e2 * d2);
-                if (t == 0) stf(out1 + p, scale * sv);
-                else out3[(size_t)(t - 1) * N + p] = sv;
+                if (t == 0) stf(&at(out1, p), scale * sv);
+                else at(out3 + (size_t)(t - 1) * N, p) = sv;
             } else {
                 b0 = d0;
                 b1 = d1;
@@ -380,12 +385,13 @@ __global__ __launch_bounds__(TPB_M) void k_fd_march(Grid g, MarchGeom mg, QuadAr
                 b1 += e1;
                 b2 += e2;
             }
-            out3[p] = b0;
-            out3[N + p] = b1;
-            out3[2 * N + p] = b2;
-            if (dp) acc += (double)dp[p] * b0 + (double)dp[N + p] * b1 + (double)dp[2 * N + p] * b2;
+            at(out3, p) = b0;
+            at(out3 + N, p) = b1;
+            at(out3 + 2 * (size_t)N, p) = b2;
+            if (dp)
+                acc += (double)at(dp, p) * b0 + (double)at(dp + N, p) * b1 + (double)at(dp + 2 * (size_t)N, p) * b2;
         } else {
-            stf(out1 + p, scale * -(e0 * b0 + e1 * b1 + e2 * b2));
+            stf(&at(out1, p), scale * -(e0 * b0 + e1 * b1 + e2 * b2));
         }
 #pragma unroll
         for (int t = 0; t < NL; ++t)
