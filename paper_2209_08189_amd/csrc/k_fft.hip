@@ -520,6 +520,133 @@ __global__ __launch_bounds__(TPB) void k_fft_cols(float2 *__restrict__ spec, con
     }
 }
 
+// --- register-resident column passes for lines of L = 256 E points (E = 2
+// or 4: 512 or 1024 points) in tiles of C = 32 / E columns, 512 threads.
+// The split n = R2 a + b, k = c + 16 d (R2 = 16 E) of k_fft_cols leaves a
+// length-R2 DFT over b for every (column, c); it is split again as
+// b = E beta + eps, d = d' + 16 m:
+//   X[c + 16 d' + 256 m] = sum_eps W_E^{eps m} W_R2^{eps d'} Z_eps[d'],
+//   Z_eps[d'] = sum_beta y_c[E beta + eps] W_16^{beta d'},
+// so a thread holds 16 values in both layouts: the E lanes eps of a
+// (column, c) pair are neighbours, each runs one length-16 DFT, and the
+// length-E DFT over eps runs across them (radix-2 lane exchanges; with E = 4
+// lane eps ends with m = the bit reverse of eps).  The inverse applies the
+// same steps backwards with conjugate twiddles.  Tiles of 16 (512 points) or
+// 8 columns (1024 points) keep row pieces of 128 or 64 bytes and 66 KB of
+// exchange buffer, so that two workgroups fit a CU.
+constexpr int NTX = 512;
+
+// length-E DFT over the lanes eps S, in place on 16 values (eps = (lane / S)
+// mod E: the partners of a lane are lane ^ S and lane ^ 2S)
+template <int E, bool INV, int S = 1> __device__ __forceinline__ void cross_dft(float2 (&v)[16], int eps)
+{
+    auto bfly = [&](int bit) {        // lane bit 0: own + partner; bit 1: partner - own
+        const bool hi = (eps & bit) != 0;
+        const int mask = bit * S;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const float px = __shfl_xor(v[i].x, mask), py = __shfl_xor(v[i].y, mask);
+            v[i] = hi ? make_float2(px - v[i].x, py - v[i].y) : make_float2(v[i].x + px, v[i].y + py);
+        }
+    };
+    if (E == 2) {
+        bfly(1);
+        return;
+    }
+    bfly(INV ? 1 : 2);
+    if (eps == 3) {                   // W_4^{+-1}
+#pragma unroll
+        for (int i = 0; i < 16; ++i) v[i] = INV ? make_float2(-v[i].y, v[i].x) : make_float2(v[i].y, -v[i].x);
+    }
+    bfly(INV ? 2 : 1);
+}
+
+template <int E, int MODE>
+__global__ __launch_bounds__(NTX, 4) void k_fft_colsx(float2 *__restrict__ spec, const float2 *__restrict__ twL,
+                                                      int nh, size_t plane_stride, size_t rs, size_t spec_cs, int kind,
+                                                      float beta, float scale, int n1, int n2)
+{
+    constexpr int R2 = 16 * E, L = 16 * R2, C = NTX / R2, LOGC = C == 16 ? 4 : 3, LOGE = E == 2 ? 1 : 2;
+    constexpr int CS = R2 * C + 16;   // exchange pitch per c
+    __shared__ float2 tw[L];
+    __shared__ float2 ex[16 * CS];
+    const int comp = blockIdx.z, pl = blockIdx.y, c0 = blockIdx.x * C;
+    const int cw = min(C, nh - c0);
+    float2 *base = spec + comp * spec_cs + pl * plane_stride + c0;
+    for (int t = threadIdx.x; t < L; t += NTX) tw[t] = twL[t];
+    // b layout: thread (column lb, b); c layout: thread (eps, column lc, c), eps fastest
+    const int lb = threadIdx.x & (C - 1), b = threadIdx.x >> LOGC;
+    const int eps = threadIdx.x & (E - 1), lc = (threadIdx.x >> LOGE) & (C - 1), c = threadIdx.x >> (LOGE + LOGC);
+    const int m = E == 4 ? ((eps & 1) << 1 | eps >> 1) : eps;
+    const bool okb = lb < cw, okc = lc < cw;
+    float2 v[16];
+    if (MODE != 2) {
+        cols_load_b<R2>(v, base, rs, lb, b, okb);            // v[a] = x[R2 a + b]
+        __syncthreads();                                      // twiddle table
+        dft_reg<16, false>(v);
+#pragma unroll
+        for (int k = 1; k < 16; ++k) v[k] = cmul(v[k], tw[b * k]);
+#pragma unroll
+        for (int k = 0; k < 16; ++k) ex[k * CS + b * C + lb] = v[k];
+        __syncthreads();
+#pragma unroll
+        for (int bt = 0; bt < 16; ++bt) v[bt] = ex[c * CS + (E * bt + eps) * C + lc];
+        dft_reg<16, false>(v);                                // Z_eps[d']
+#pragma unroll
+        for (int k = 1; k < 16; ++k)
+            if (eps) v[k] = cmul(v[k], tw[16 * eps * k]);
+        cross_dft<E, false>(v, eps);                          // v[d'] = X[c + 16 d' + 256 m]
+        if (MODE == 1) {
+            if (okc) {
+#pragma unroll
+                for (int k = 0; k < 16; ++k) base[(size_t)(c + 16 * k + 256 * m) * rs + lc] = v[k];
+            }
+            return;
+        }
+        // symbol of the x1 pass: k1 = c + 16 d' + 256 m, k2 = plane, k3 = c0 + lc
+        const float k2 = (float)(pl < (n2 >> 1) ? pl : pl - n2);
+        const float k3 = (float)(c0 + lc);
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int q = c + 16 * k + 256 * m;
+            const float k1 = (float)(q < (n1 >> 1) ? q : q - n1);
+            const float ksq = k1 * k1 + k2 * k2 + k3 * k3;
+            float sym;
+            if (kind == 0) sym = beta * ksq;
+            else if (kind == 1) sym = 1.0f / (beta * fmaxf(ksq, 1.0f));
+            else sym = 1.0f;
+            sym *= scale;
+            v[k].x *= sym;
+            v[k].y *= sym;
+        }
+        __syncthreads();                                      // exchange buffer free again
+    } else {
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+            v[k] = okc ? base[(size_t)(c + 16 * k + 256 * m) * rs + lc] : make_float2(0.f, 0.f);
+        __syncthreads();                                      // twiddle table
+    }
+    // inverse: lanes, twiddle W_R2^{-eps d'}, DFT-16 over d', exchange,
+    // twiddle W_L^{-b c}, DFT-16 over c
+    cross_dft<E, true>(v, eps);
+#pragma unroll
+    for (int k = 1; k < 16; ++k)
+        if (eps) v[k] = cmul(v[k], cconj(tw[16 * eps * k]));
+    dft_reg<16, true>(v);                                     // v[beta] = y_c[E beta + eps]
+#pragma unroll
+    for (int bt = 0; bt < 16; ++bt) ex[c * CS + (E * bt + eps) * C + lc] = v[bt];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; ++k) v[k] = ex[k * CS + b * C + lb];
+#pragma unroll
+    for (int k = 1; k < 16; ++k) v[k] = cmul(v[k], cconj(tw[b * k]));
+    dft_reg<16, true>(v);                                     // v[a] = x[R2 a + b]
+    if (okb) {
+#pragma unroll
+        for (int a = 0; a < 16; ++a) base[(size_t)(R2 * a + b) * rs + lb] = v[a];
+    }
+}
+
 // --- register-resident x3 passes for rows of M = 16 R2 complex values (M =
 // 128 or 64, i.e. n3 = 256 or 128), NR = 256 / R2 rows per tile.  With input
 // index n = c + 16 d and output index k = b + R2 a (M = 16 R2),
@@ -529,6 +656,12 @@ __global__ __launch_bounds__(TPB) void k_fft_cols(float2 *__restrict__ spec, con
 // over c on the "b" layout (thread = row, b), joined by one LDS exchange
 // [row][c][b] (row pitch 17 R2 + 16 complex).  Loads on the c layout read
 // 16 consecutive complex values per row per instruction.
+// Rows of M = 512 complex values (n3 = 1024, R2 = 32, NR = 8 rows per tile)
+// split the length-32 DFTs over d once more, d = 2 delta + eps, b = b' + 16 m:
+//   Y_c[b' + 16 m] = sum_eps (-1)^{eps m} W_32^{eps b'} sum_delta x[c + 16 (2 delta + eps)] W_16^{delta b'},
+// so the c layout holds (row, c, eps) with eps = bit 4 of the lane, every
+// thread runs one length-16 DFT, and the length-2 DFT over eps is a lane
+// exchange (lane ^ 16).
 template <int R2> constexpr int rows_pitch() { return 17 * R2 + 16; }
 
 // Lane i of each 16-lane row receives x of lane 16 - i of the same row
@@ -565,6 +698,33 @@ __device__ __forceinline__ void rows_cb(float2 (&v)[16], float2 *ex, const float
     dft_reg<16, INV>(v);                                      // v[a] = X[b + R2 a]
 }
 
+// rows_cb for R2 = 32: v[delta] = x[c + 16 (2 delta + eps)] on the c layout
+// (c = lane bits 0-3, eps = bit 4, row = thread / 32) in, v[a] = X[b + 32 a]
+// on the b layout out
+template <bool INV> __device__ __forceinline__ void rows_cbx(float2 (&v)[16], float2 *ex, const float2 *tw)
+{
+    constexpr int R2 = 32, RS = rows_pitch<32>();
+    const int c = threadIdx.x & 15, eps = (threadIdx.x >> 4) & 1, row = threadIdx.x >> 5;
+    dft_reg<16, INV>(v);                                      // v[b'] = sum_delta ... W_16^{delta b'}
+    if (eps) {
+#pragma unroll
+        for (int k = 1; k < 16; ++k) v[k] = cmul(v[k], INV ? cconj(tw[16 * k]) : tw[16 * k]);   // W_32^{b'}
+    }
+    cross_dft<2, INV, 16>(v, eps);                            // v[b'] = Y_c[b' + 16 eps]
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int b = k + 16 * eps;
+        float2 t = v[k];
+        if (b * c) t = cmul(t, INV ? cconj(tw[b * c]) : tw[b * c]);
+        ex[row * RS + c * (R2 + 1) + b] = t;
+    }
+    __syncthreads();
+    const int bb = threadIdx.x % R2, rb = threadIdx.x / R2;
+#pragma unroll
+    for (int cc = 0; cc < 16; ++cc) v[cc] = ex[rb * RS + cc * (R2 + 1) + bb];
+    dft_reg<16, INV>(v);                                      // v[a] = X[b + R2 a]
+}
+
 // x3 forward: real rows -> half spectrum
 template <int R2>
 __global__ __launch_bounds__(TPB) void k_fft_rows_r2c(const float *__restrict__ in, float2 *__restrict__ spec,
@@ -582,12 +742,20 @@ __global__ __launch_bounds__(TPB) void k_fft_rows_r2c(const float *__restrict__ 
     for (int t = threadIdx.x; t <= M; t += TPB) tws[t] = tw3[t];
     const int c = threadIdx.x & 15, r0 = threadIdx.x >> 4;
     float2 v[16];
+    if constexpr (R2 == 32) {
+        const int eps = r0 & 1, rw = r0 >> 1;
 #pragma unroll
-    for (int u = 0; u < PP; ++u)
+        for (int dl = 0; dl < 16; ++dl) v[dl] = src[(size_t)rw * M + c + 16 * eps + 32 * dl];
+        __syncthreads();                                      // twiddle tables
+        rows_cbx<false>(v, ex, twm);
+    } else {
 #pragma unroll
-        for (int d = 0; d < R2; ++d) v[u * R2 + d] = src[(size_t)(r0 + 16 * u) * M + c + 16 * d];
-    __syncthreads();                                          // twiddle tables
-    rows_cb<R2, false>(v, ex, twm);
+        for (int u = 0; u < PP; ++u)
+#pragma unroll
+            for (int d = 0; d < R2; ++d) v[u * R2 + d] = src[(size_t)(r0 + 16 * u) * M + c + 16 * d];
+        __syncthreads();                                      // twiddle tables
+        rows_cb<R2, false>(v, ex, twm);
+    }
     // X[k] = E + W_n3^k O with E = (Z[k] + conj Z[M-k]) / 2, O = -i (Z[k] -
     // conj Z[M-k]) / 2; Z[M-k] of k = b + R2 a is v[15 - a] of the lane with
     // b' = R2 - b (b > 0) or this lane's v[(16 - a) mod 16] (b = 0)
@@ -633,39 +801,63 @@ __global__ __launch_bounds__(TPB) void k_fft_rows_c2r(const float2 *__restrict__
     for (int t = threadIdx.x; t < M; t += TPB) twm[t] = twM[t];
     for (int t = threadIdx.x; t <= M; t += TPB) tws[t] = tw3[t];
     const int c = threadIdx.x & 15, r0 = threadIdx.x >> 4;
-    float2 xa[16], xb[16], nyq[PP];
-#pragma unroll
-    for (int u = 0; u < PP; ++u) {
-        const float2 *srow = src + (size_t)(r0 + 16 * u) * NP;
-#pragma unroll
-        for (int d = 0; d < R2; ++d) xa[u * R2 + d] = srow[c + 16 * d];
-        nyq[u] = c == 0 ? srow[M] : make_float2(0.f, 0.f);
-    }
-    // X[M - k] for k = c + 16 d: for c > 0 it is X[(16 - c) + 16 (R2 - 1 - d)],
-    // held by lane 16 - c of the same 16-lane row (a row reflection by DPP);
-    // for c = 0 it is this lane's X[16 (R2 - d)], or the Nyquist value at d = 0
-#pragma unroll
-    for (int u = 0; u < PP; ++u)
-#pragma unroll
-        for (int d = 0; d < R2; ++d) {
-            const float2 o = xa[u * R2 + R2 - 1 - d];
-            const float2 m = make_float2(row_reflect16(o.x), row_reflect16(o.y));
-            xb[u * R2 + d] = c ? m : (d ? xa[u * R2 + R2 - d] : nyq[u]);
-        }
-    __syncthreads();                                          // twiddle tables
-    // Z[k] = (X[k] + conj X[M-k]) + i e^{+2 pi i k / n3} (X[k] - conj X[M-k])
     float2 v[16];
+    if constexpr (R2 == 32) {
+        // X[k] and X[M - k] for k = c + 16 (2 delta + eps), both read from
+        // the row (k = 0 pairs with the Nyquist value X[M])
+        const int eps = r0 & 1, rw = r0 >> 1;
+        const float2 *srow = src + (size_t)rw * NP;
+        float2 xa[16], xb[16];
 #pragma unroll
-    for (int u = 0; u < PP; ++u)
+        for (int dl = 0; dl < 16; ++dl) {
+            const int k = c + 16 * eps + 32 * dl;
+            xa[dl] = srow[k];
+            xb[dl] = srow[M - k];
+        }
+        __syncthreads();                                      // twiddle tables
 #pragma unroll
-        for (int d = 0; d < R2; ++d) {
-            const int k = c + 16 * d;
-            const float2 a = xa[u * R2 + d], bb = cconj(xb[u * R2 + d]);
+        for (int dl = 0; dl < 16; ++dl) {
+            const int k = c + 16 * eps + 32 * dl;
+            const float2 a = xa[dl], bb = cconj(xb[dl]);
             const float2 sum = cadd(a, bb), dif = csub(a, bb);
             const float2 wd = cmul(cconj(tws[k]), dif);
-            v[u * R2 + d] = make_float2(sum.x - wd.y, sum.y + wd.x);
+            v[dl] = make_float2(sum.x - wd.y, sum.y + wd.x);
         }
-    rows_cb<R2, true>(v, ex, twm);
+        rows_cbx<true>(v, ex, twm);
+    } else {
+        float2 xa[16], xb[16], nyq[PP];
+#pragma unroll
+        for (int u = 0; u < PP; ++u) {
+            const float2 *srow = src + (size_t)(r0 + 16 * u) * NP;
+#pragma unroll
+            for (int d = 0; d < R2; ++d) xa[u * R2 + d] = srow[c + 16 * d];
+            nyq[u] = c == 0 ? srow[M] : make_float2(0.f, 0.f);
+        }
+        // X[M - k] for k = c + 16 d: for c > 0 it is X[(16 - c) + 16 (R2 - 1 - d)],
+        // held by lane 16 - c of the same 16-lane row (a row reflection by DPP);
+        // for c = 0 it is this lane's X[16 (R2 - d)], or the Nyquist value at d = 0
+#pragma unroll
+        for (int u = 0; u < PP; ++u)
+#pragma unroll
+            for (int d = 0; d < R2; ++d) {
+                const float2 o = xa[u * R2 + R2 - 1 - d];
+                const float2 m = make_float2(row_reflect16(o.x), row_reflect16(o.y));
+                xb[u * R2 + d] = c ? m : (d ? xa[u * R2 + R2 - d] : nyq[u]);
+            }
+        __syncthreads();                                      // twiddle tables
+        // Z[k] = (X[k] + conj X[M-k]) + i e^{+2 pi i k / n3} (X[k] - conj X[M-k])
+#pragma unroll
+        for (int u = 0; u < PP; ++u)
+#pragma unroll
+            for (int d = 0; d < R2; ++d) {
+                const int k = c + 16 * d;
+                const float2 a = xa[u * R2 + d], bb = cconj(xb[u * R2 + d]);
+                const float2 sum = cadd(a, bb), dif = csub(a, bb);
+                const float2 wd = cmul(cconj(tws[k]), dif);
+                v[u * R2 + d] = make_float2(sum.x - wd.y, sum.y + wd.x);
+            }
+        rows_cb<R2, true>(v, ex, twm);
+    }
     const int b = threadIdx.x % R2, row = threadIdx.x / R2;
 #pragma unroll
     for (int a = 0; a < 16; ++a) {
@@ -780,13 +972,22 @@ void coupled3(const FFTPlan &P, int kind, float beta_v, float beta_w, const floa
 
 namespace {
 
-bool cols_ok(int L) { return L == 128 || L == 256; }
+bool cols_ok(int L) { return L == 128 || L == 256 || L == 512 || L == 1024; }
+
+// columns per tile of the register-resident column passes
+int cols_width(int L) { return L <= 256 ? 4096 / L : 8192 / L; }
 
 template <int MODE>
 void launch_cols(int L, dim3 grid, float2 *spec, const float2 *tw, int nh, size_t plane_stride, size_t rs,
                  size_t spec_cs, int kind, float beta, float scale, int n1, int n2, hipStream_t s)
 {
-    if (L == 256)
+    if (L == 1024)
+        hipLaunchKernelGGL((k_fft_colsx<4, MODE>), grid, dim3(NTX), 0, s, spec, tw, nh, plane_stride, rs, spec_cs, kind,
+                           beta, scale, n1, n2);
+    else if (L == 512)
+        hipLaunchKernelGGL((k_fft_colsx<2, MODE>), grid, dim3(NTX), 0, s, spec, tw, nh, plane_stride, rs, spec_cs, kind,
+                           beta, scale, n1, n2);
+    else if (L == 256)
         hipLaunchKernelGGL((k_fft_cols<16, MODE>), grid, dim3(TPB), 0, s, spec, tw, nh, plane_stride, rs, spec_cs, kind,
                            beta, scale, n1, n2);
     else
@@ -794,7 +995,22 @@ void launch_cols(int L, dim3 grid, float2 *spec, const float2 *tw, int nh, size_
                            beta, scale, n1, n2);
 }
 
-bool rows_ok(int n3) { return n3 == 256 || n3 == 128; }
+bool rows_ok(int n3) { return n3 == 128 || n3 == 256 || n3 == 512 || n3 == 1024; }
+
+// register-resident row kernel for rows of n3 reals (R2 = n3 / 32, NR = 256 / R2 rows per tile)
+template <int R2>
+void launch_rows_r2c(const FFTPlan &P, const float *in, int nc, size_t N, size_t spec_cs, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_fft_rows_r2c<R2>), dim3(P.n1 * P.n2 / (256 / R2), nc), dim3(TPB), 0, s, in, P.spec, P.twM,
+                       P.twS, N, spec_cs);
+}
+
+template <int R2>
+void launch_rows_c2r(const FFTPlan &P, float *out, const float *add, int nc, size_t N, size_t spec_cs, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_fft_rows_c2r<R2>), dim3(P.n1 * P.n2 / (256 / R2), nc), dim3(TPB), 0, s, P.spec, out, add,
+                       P.twM, P.twS, N, spec_cs);
+}
 
 // x3 forward pass (real rows -> half spectrum), nc components
 void pass_r2c(const FFTPlan &P, const float *in, int nc, int logM, int lognl3, size_t lds3, size_t spec_cs,
@@ -803,12 +1019,10 @@ void pass_r2c(const FFTPlan &P, const float *in, int nc, int logM, int lognl3, s
     const size_t N = (size_t)P.n1 * P.n2 * P.n3;
     const int nrows = P.n1 * P.n2;
     if (rows_ok(P.n3) && nrows % (256 / (P.n3 / 32)) == 0) {
-        if (P.n3 == 256)
-            hipLaunchKernelGGL((k_fft_rows_r2c<8>), dim3(nrows / 32, nc), dim3(TPB), 0, s, in, P.spec, P.twM, P.twS,
-                               N, spec_cs);
-        else
-            hipLaunchKernelGGL((k_fft_rows_r2c<4>), dim3(nrows / 64, nc), dim3(TPB), 0, s, in, P.spec, P.twM, P.twS,
-                               N, spec_cs);
+        if (P.n3 == 1024) launch_rows_r2c<32>(P, in, nc, N, spec_cs, s);
+        else if (P.n3 == 512) launch_rows_r2c<16>(P, in, nc, N, spec_cs, s);
+        else if (P.n3 == 256) launch_rows_r2c<8>(P, in, nc, N, spec_cs, s);
+        else launch_rows_r2c<4>(P, in, nc, N, spec_cs, s);
         return;
     }
     hipLaunchKernelGGL(k_fft_x3_r2c, dim3(nrows >> lognl3, nc), dim3(TPB), lds3, s, in, P.spec, P.twM, P.twS, logM,
@@ -822,12 +1036,10 @@ void pass_c2r(const FFTPlan &P, float *out, const float *add, int nc, int logM, 
     const size_t N = (size_t)P.n1 * P.n2 * P.n3;
     const int nrows = P.n1 * P.n2;
     if (rows_ok(P.n3) && nrows % (256 / (P.n3 / 32)) == 0) {
-        if (P.n3 == 256)
-            hipLaunchKernelGGL((k_fft_rows_c2r<8>), dim3(nrows / 32, nc), dim3(TPB), 0, s, P.spec, out, add, P.twM,
-                               P.twS, N, spec_cs);
-        else
-            hipLaunchKernelGGL((k_fft_rows_c2r<4>), dim3(nrows / 64, nc), dim3(TPB), 0, s, P.spec, out, add, P.twM,
-                               P.twS, N, spec_cs);
+        if (P.n3 == 1024) launch_rows_c2r<32>(P, out, add, nc, N, spec_cs, s);
+        else if (P.n3 == 512) launch_rows_c2r<16>(P, out, add, nc, N, spec_cs, s);
+        else if (P.n3 == 256) launch_rows_c2r<8>(P, out, add, nc, N, spec_cs, s);
+        else launch_rows_c2r<4>(P, out, add, nc, N, spec_cs, s);
         return;
     }
     hipLaunchKernelGGL(k_fft_x3_c2r, dim3(nrows >> lognl3, nc), dim3(TPB), lds3, s, P.spec, out, add, P.twM, P.twS,
@@ -888,7 +1100,7 @@ void launch_x1(const FFTPlan &P, int mode, int kind, float beta, float scale, di
 void pass_x2(const FFTPlan &P, bool inv, int nc, size_t spec_cs, hipStream_t s)
 {
     if (cols_ok(P.n2)) {
-        const int C = 4096 / P.n2;
+        const int C = cols_width(P.n2);
         const dim3 grid((P.nh + C - 1) / C, P.n1, nc);
         if (inv) launch_cols<2>(P.n2, grid, P.spec, P.tw2, P.nh, (size_t)P.n2 * P.np, P.np, spec_cs, 2, 0.f, 1.f, P.n1, P.n2, s);
         else launch_cols<1>(P.n2, grid, P.spec, P.tw2, P.nh, (size_t)P.n2 * P.np, P.np, spec_cs, 2, 0.f, 1.f, P.n1, P.n2, s);
@@ -906,7 +1118,7 @@ void pass_x2(const FFTPlan &P, bool inv, int nc, size_t spec_cs, hipStream_t s)
 void pass_x1(const FFTPlan &P, int mode, int kind, float beta, float scale, int nc, size_t spec_cs, hipStream_t s)
 {
     if (cols_ok(P.n1)) {
-        const int C = 4096 / P.n1;
+        const int C = cols_width(P.n1);
         const dim3 grid((P.nh + C - 1) / C, P.n2, nc);
         const size_t rs = (size_t)P.n2 * P.np;
         if (mode == 0) launch_cols<0>(P.n1, grid, P.spec, P.tw1, P.nh, P.np, rs, spec_cs, kind, beta, scale, P.n1, P.n2, s);

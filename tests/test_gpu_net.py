@@ -131,7 +131,11 @@ def test_training_reduces_loss():
 
 
 @pytest.mark.parametrize("a,b", [((32, 32, 32), (16, 16, 16)), ((16, 16, 16), (32, 32, 32)),
-                                 ((16, 32, 64), (32, 16, 32))])
+                                 ((16, 32, 64), (32, 16, 32)),
+                                 # forward-only and inverse-only column passes on 512- and 1024-point lines
+                                 ((1024, 16, 32), (512, 16, 32)), ((16, 512, 32), (16, 1024, 32)),
+                                 # row passes of 512 and 1024 reals
+                                 ((16, 32, 1024), (16, 32, 512)), ((16, 16, 512), (16, 16, 1024))])
 def test_spectral_resample(a, b):
     from paper_2209_08189_amd.claire import Resampler
     r = np.random.default_rng(1)

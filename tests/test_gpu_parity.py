@@ -128,7 +128,8 @@ def test_fd_matches_oracle(shape):
 
 
 @pytest.mark.parametrize("shape", SHAPES + [(64, 128, 32), (16, 1024, 16), (1024, 16, 16), (16, 16, 1024),
-                                   (32, 256, 64), (512, 16, 64), (16, 512, 32), (16, 1024, 64), (1024, 16, 64)])
+                                   (32, 256, 64), (512, 16, 64), (16, 512, 32), (16, 1024, 64), (1024, 16, 64),
+                                   (16, 16, 512), (32, 16, 1024)])
 @pytest.mark.parametrize("kind", [0, 1, 2])
 def test_spectral_matches_oracle(shape, kind):
     x = f32(synth.random_field((3,) + shape, 5))
