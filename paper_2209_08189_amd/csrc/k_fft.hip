@@ -400,7 +400,8 @@ __global__ __launch_bounds__(NT, NT == 512 ? 4 : 1) void k_fft_x1_mult(float2 *_
 }
 
 // --- register-resident column passes for lines of L = 16 R2 points (R2 =
-// 8 or 16, i.e. L = 128 or 256) in tiles of C = 256 / R2 columns.  With
+// 8 or 16, i.e. L = 128 or 256; 512 and 1024 below) in tiles of C = 256 / R2
+// columns.  With
 // n = R2 a + b and k = c + 16 d,
 //   X[c + 16 d] = sum_b W_R2^{bd} W_L^{bc} sum_a x[R2 a + b] W_16^{ac},
 // so each thread holds 16 (or 2 x R2) values in registers: the length-16
@@ -648,17 +649,18 @@ __global__ __launch_bounds__(NTX, 4) void k_fft_colsx(float2 *__restrict__ spec,
 }
 
 // --- register-resident x3 passes for rows of M = 16 R2 complex values (M =
-// 128 or 64, i.e. n3 = 256 or 128), NR = 256 / R2 rows per tile.  With input
-// index n = c + 16 d and output index k = b + R2 a (M = 16 R2),
+// 64 ... 512, i.e. n3 = 128 ... 1024), NR = 256 / R2 rows per tile.  With
+// input index n = c + 16 d and output index k = b + R2 a (M = 16 R2),
 //   X[b + R2 a] = sum_c W_16^{ac} W_M^{bc} sum_d x[c + 16 d] W_R2^{bd}
 // (conjugate twiddles for the inverse): the length-R2 DFTs over d run on the
-// "c" layout (thread = row, c; 16 / R2 pairs per thread), the length-16 DFTs
-// over c on the "b" layout (thread = row, b), joined by one LDS exchange
+// "c" layout (thread = row, c; 16 / R2 pairs per thread; R2 = 32 below),
+// the length-16 DFTs over c on the "b" layout (thread = row, b), joined by one LDS exchange
 // [row][c][b] (row pitch 17 R2 + 16 complex).  Loads on the c layout read
 // 16 consecutive complex values per row per instruction.
 // Rows of M = 512 complex values (n3 = 1024, R2 = 32, NR = 8 rows per tile)
 // split the length-32 DFTs over d once more, d = 2 delta + eps, b = b' + 16 m:
-//   Y_c[b' + 16 m] = sum_eps (-1)^{eps m} W_32^{eps b'} sum_delta x[c + 16 (2 delta + eps)] W_16^{delta b'},
+//   Y_c[b' + 16 m] = sum_eps (-1)^{eps m} W_32^{eps b'}
+//                    sum_delta x[c + 16 (2 delta + eps)] W_16^{delta b'},
 // so the c layout holds (row, c, eps) with eps = bit 4 of the lane, every
 // thread runs one length-16 DFT, and the length-2 DFT over eps is a lane
 // exchange (lane ^ 16).
@@ -1046,7 +1048,7 @@ void pass_c2r(const FFTPlan &P, float *out, const float *add, int nc, int logM, 
                        logM, lognl3, nrows, N, spec_cs, P.np);
 }
 
-// Stockham column passes (line lengths other than 128 and 256): NT threads
+// Stockham column passes (line lengths other than 128 ... 1024): NT threads
 // per workgroup hold a tile of NT EPT values, C = NT EPT / L columns (at most
 // 32).  Lines of 512 points and more take 512 or 1024 threads, so that a tile
 // keeps 16 columns (128-byte row pieces) up to L = 1024.
