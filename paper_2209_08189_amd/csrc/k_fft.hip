@@ -14,12 +14,12 @@
 //   x2 C2C    inverse;
 //   x3 C2R    Hermitian merge, inverse FFT of length M, unpack to reals,
 //             optional fused add.
-// Inside a pass a workgroup owns a tile of nl lines x L points (nl L = 4096
-// complex, 32 KB; in the column passes 16 columns of 512 or 1024 points,
-// held by 512 or 1024 threads): coalesced batched loads into LDS, then
-// Stockham stages of radix 16 (and one of radix 2/4/8 for the remainder)
-// with every group's R values in registers, twiddles from FP64-computed
-// tables staged in LDS, and a coalesced store.  The LDS tile is stored as [q][l] with pitch nl + 1 so
+// Lines of 128 ... 1024 points take register-resident passes (below); the
+// generic passes for shorter lines work on LDS tiles: a workgroup owns a
+// tile of nl lines x L points (nl L = 4096 complex, 32 KB), coalesced
+// batched loads into LDS, then Stockham stages of radix 16 (and one of
+// radix 2/4/8 for the remainder) with every group's R values in registers,
+// twiddles from FP64-computed tables staged in LDS, and a coalesced store.  The LDS tile is stored as [q][l] with pitch nl + 1 so
 // that both row-wise and column-wise accesses are conflict-free.
 #include "internal.h"
 
@@ -332,9 +332,8 @@ __device__ __forceinline__ void store_cols(const float2 *lds, float2 *__restrict
 
 // --- x2 C2C in place on the half spectrum: plane i1 = blockIdx.y, columns
 // [c0, c0 + C) of the nh per row; NT threads hold the tile of NT EPT values.
-// (512-thread tiles take at most 128 VGPRs, so that two fit a CU)
 template <bool INV, int NT>
-__global__ __launch_bounds__(NT, NT == 512 ? 4 : 1) void k_fft_x2(float2 *__restrict__ spec, const float2 *__restrict__ tw2, int logn2,
+__global__ __launch_bounds__(NT) void k_fft_x2(float2 *__restrict__ spec, const float2 *__restrict__ tw2, int logn2,
                                                 int n2, int nh, int np, int logC, size_t spec_cs)
 {
     extern __shared__ float2 sm[];
@@ -354,7 +353,7 @@ __global__ __launch_bounds__(NT, NT == 512 ? 4 : 1) void k_fft_x2(float2 *__rest
 // plane i2 = blockIdx.y, columns [c0, c0 + C).
 // mode 0: forward, multiply, inverse; 1: forward only; 2: inverse only
 template <int NT>
-__global__ __launch_bounds__(NT, NT == 512 ? 4 : 1) void k_fft_x1_mult(float2 *__restrict__ spec, const float2 *__restrict__ tw1,
+__global__ __launch_bounds__(NT) void k_fft_x1_mult(float2 *__restrict__ spec, const float2 *__restrict__ tw1,
                                                      int logn1, int n1, int n2, int nh, int np, int logC, int kind,
                                                      float beta, float scale, size_t spec_cs, int mode)
 {
@@ -1048,55 +1047,23 @@ void pass_c2r(const FFTPlan &P, float *out, const float *add, int nc, int logM, 
                        logM, lognl3, nrows, N, spec_cs, P.np);
 }
 
-// Stockham column passes (line lengths other than 128 ... 1024): NT threads
-// per workgroup hold a tile of NT EPT values, C = NT EPT / L columns (at most
-// 32).  Lines of 512 points and more take 512 or 1024 threads, so that a tile
-// keeps 16 columns (128-byte row pieces) up to L = 1024.
+// Stockham column passes (lines of 16 ... 64 points; 128 ... 1024 take the
+// register-resident passes): a 256-thread tile of 4096 values holds C =
+// 4096 / L columns (at most 32).
 struct ColGeom {
-    int nt, logC;
+    int logC;
     size_t lds;   // twiddle table + tile at pitch C + 1
 };
 
 ColGeom col_geom(int L)
 {
     ColGeom c;
-    c.nt = L >= 1024 ? 1024 : L >= 512 ? 512 : TPB;
-    const int logT = ilog2(c.nt * EPT);
+    const int logT = ilog2(TPB * EPT);
     c.logC = logT - ilog2(L) > 5 ? 5 : logT - ilog2(L);
     c.lds = (size_t)(L + (size_t)L * ((1 << c.logC) + 1)) * sizeof(float2);
     return c;
 }
 
-// dynamic LDS above 64 KB (up to the 160 KB of a gfx950 CU) is granted per kernel
-template <typename K> void allow_lds(K kernel, size_t bytes)
-{
-    if (bytes > 65536)
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)bytes);
-}
-
-template <int NT>
-void launch_x2(const FFTPlan &P, bool inv, dim3 grid, int logC, size_t lds, size_t spec_cs, hipStream_t s)
-{
-    if (inv) {
-        allow_lds(k_fft_x2<true, NT>, lds);
-        hipLaunchKernelGGL((k_fft_x2<true, NT>), grid, dim3(NT), lds, s, P.spec, P.tw2, ilog2(P.n2), P.n2, P.nh, P.np,
-                           logC, spec_cs);
-    } else {
-        allow_lds(k_fft_x2<false, NT>, lds);
-        hipLaunchKernelGGL((k_fft_x2<false, NT>), grid, dim3(NT), lds, s, P.spec, P.tw2, ilog2(P.n2), P.n2, P.nh, P.np,
-                           logC, spec_cs);
-    }
-}
-
-template <int NT>
-void launch_x1(const FFTPlan &P, int mode, int kind, float beta, float scale, dim3 grid, int logC, size_t lds,
-               size_t spec_cs, hipStream_t s)
-{
-    allow_lds(k_fft_x1_mult<NT>, lds);
-    hipLaunchKernelGGL((k_fft_x1_mult<NT>), grid, dim3(NT), lds, s, P.spec, P.tw1, ilog2(P.n1), P.n1, P.n2, P.nh, P.np,
-                       logC, kind, beta, scale, spec_cs, mode);
-}
 
 // x2 pass over every x1 plane (forward or inverse), nc components
 void pass_x2(const FFTPlan &P, bool inv, int nc, size_t spec_cs, hipStream_t s)
@@ -1111,9 +1078,12 @@ void pass_x2(const FFTPlan &P, bool inv, int nc, size_t spec_cs, hipStream_t s)
     const ColGeom cg = col_geom(P.n2);
     const int C2 = 1 << cg.logC;
     const dim3 grid((P.nh + C2 - 1) / C2, P.n1, nc);
-    if (cg.nt == 1024) launch_x2<1024>(P, inv, grid, cg.logC, cg.lds, spec_cs, s);
-    else if (cg.nt == 512) launch_x2<512>(P, inv, grid, cg.logC, cg.lds, spec_cs, s);
-    else launch_x2<TPB>(P, inv, grid, cg.logC, cg.lds, spec_cs, s);
+    if (inv)
+        hipLaunchKernelGGL((k_fft_x2<true, TPB>), grid, dim3(TPB), cg.lds, s, P.spec, P.tw2, ilog2(P.n2), P.n2, P.nh,
+                           P.np, cg.logC, spec_cs);
+    else
+        hipLaunchKernelGGL((k_fft_x2<false, TPB>), grid, dim3(TPB), cg.lds, s, P.spec, P.tw2, ilog2(P.n2), P.n2, P.nh,
+                           P.np, cg.logC, spec_cs);
 }
 
 // x1 pass over every x2 plane: mode 0 forward, symbol, inverse; 1 forward; 2 inverse
@@ -1131,9 +1101,8 @@ void pass_x1(const FFTPlan &P, int mode, int kind, float beta, float scale, int 
     const ColGeom cg = col_geom(P.n1);
     const int C1 = 1 << cg.logC;
     const dim3 grid((P.nh + C1 - 1) / C1, P.n2, nc);
-    if (cg.nt == 1024) launch_x1<1024>(P, mode, kind, beta, scale, grid, cg.logC, cg.lds, spec_cs, s);
-    else if (cg.nt == 512) launch_x1<512>(P, mode, kind, beta, scale, grid, cg.logC, cg.lds, spec_cs, s);
-    else launch_x1<TPB>(P, mode, kind, beta, scale, grid, cg.logC, cg.lds, spec_cs, s);
+    hipLaunchKernelGGL((k_fft_x1_mult<TPB>), grid, dim3(TPB), cg.lds, s, P.spec, P.tw1, ilog2(P.n1), P.n1, P.n2, P.nh,
+                       P.np, cg.logC, kind, beta, scale, spec_cs, mode);
 }
 
 } // namespace
