@@ -1464,10 +1464,10 @@ int cl_get_field(cl_ctx *ctx, int which, int j, float *out)
         });
         break;
     case CL_FIELD_FEET_F:
-        HIPCHK(hipMemcpyAsync(out, ctx->df, 3 * N * sizeof(float), hipMemcpyDeviceToDevice, ctx->s));
+        run(ctx, CL_K_VEC, [&] { launch_feet_fields(ctx->g, ctx->df, out, ctx->s); });
         break;
     case CL_FIELD_FEET_B:
-        HIPCHK(hipMemcpyAsync(out, ctx->db, 3 * N * sizeof(float), hipMemcpyDeviceToDevice, ctx->s));
+        run(ctx, CL_K_VEC, [&] { launch_feet_fields(ctx->g, ctx->db, out, ctx->s); });
         break;
     case CL_FIELD_ADJ_FACTOR:
         HIPCHK(hipMemcpyAsync(out, ctx->c, N * sizeof(float), hipMemcpyDeviceToDevice, ctx->s));

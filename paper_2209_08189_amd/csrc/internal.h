@@ -119,9 +119,13 @@ struct SLParams {
 
 // transport (k_transport.hip)
 // Heun feet d_f (and d_b, c when db / c are not NULL) of velocity v, with the
-// tile boxes of each; scratch3: 3 FP32 fields of workspace
+// tile boxes of each; scratch3: 3 FP32 fields of workspace.  The feet are
+// stored interleaved (d1 d2 d3 of node p at 3p); every SL step below takes
+// them in that layout, except launch_interp_f32 (three fields).
 void launch_feet(const Grid &g, float dt, const float *v, float *df, float *db, const float *divv, float *c,
                  int *box_f, int *box_b, float *scratch3, hipStream_t s);
+// interleaved feet d -> three fields out
+void launch_feet_fields(const Grid &g, const float *d, float *out, hipStream_t s);
 // Per-tile stencil bounding boxes of the feet d (8 ints per 8x8x32 tile;
 // tile_box_ints() == 0 for grids too small for the tiled kernels).  Computed
 // once per velocity and direction and passed to every SL step with those feet.

@@ -114,28 +114,55 @@ __device__ __forceinline__ float gather(const T *__restrict__ u, const Foot &F)
 // (correctly rounded), so a velocity that is an exact multiple of h/dt gives
 // an exactly integer foot.
 
-// predictor displacement d = (a v) / h, a = -dt (X_f) or +dt (X_b)
+// The solver keeps its displacements interleaved per node (d1 d2 d3 of node
+// p at 3p), so an SL step reads the feet of a node with one 12-byte load;
+// the interpolation entry points take three separate fields from the caller.
+template <bool AOS>
+__device__ __forceinline__ void foot_of(const float *__restrict__ d, size_t N, size_t p, float &a1, float &a2,
+                                        float &a3)
+{
+    if constexpr (AOS) {
+        const float3 f = *reinterpret_cast<const float3 *>(d + 3 * p);
+        a1 = f.x;
+        a2 = f.y;
+        a3 = f.z;
+    } else {
+        a1 = d[p];
+        a2 = d[N + p];
+        a3 = d[2 * N + p];
+    }
+}
+
+// predictor displacement d = (a v) / h, a = -dt (X_f) or +dt (X_b), interleaved
 __global__ __launch_bounds__(TPB) void k_feet_pred(Grid g, float a, const float *__restrict__ v, float *__restrict__ d)
 {
     const int p = blockIdx.x * TPB + threadIdx.x;
     if (p >= g.N) return;
     const size_t N = g.N;
-    d[p] = (a * v[p]) / g.h1;
-    d[N + p] = (a * v[N + p]) / g.h2;
-    d[2 * N + p] = (a * v[2 * N + p]) / g.h3;
+    *reinterpret_cast<float3 *>(d + 3 * (size_t)p) =
+        make_float3((a * v[p]) / g.h1, (a * v[N + p]) / g.h2, (a * v[2 * N + p]) / g.h3);
 }
 
 // corrector displacement d = (b (v + vi)) / h, b = -dt/2 (X_f) or +dt/2 (X_b),
-// vi = v interpolated at the predictor feet
+// vi = v interpolated at the predictor feet (three fields); d interleaved
 __global__ __launch_bounds__(TPB) void k_feet_corr(Grid g, float b, const float *__restrict__ v,
                                                    const float *__restrict__ vi, float *__restrict__ d)
 {
     const int p = blockIdx.x * TPB + threadIdx.x;
     if (p >= g.N) return;
     const size_t N = g.N;
-    d[p] = (b * (v[p] + vi[p])) / g.h1;
-    d[N + p] = (b * (v[N + p] + vi[N + p])) / g.h2;
-    d[2 * N + p] = (b * (v[2 * N + p] + vi[2 * N + p])) / g.h3;
+    *reinterpret_cast<float3 *>(d + 3 * (size_t)p) =
+        make_float3((b * (v[p] + vi[p])) / g.h1, (b * (v[N + p] + vi[N + p])) / g.h2,
+                    (b * (v[2 * N + p] + vi[2 * N + p])) / g.h3);
+}
+
+// interleaved feet -> three fields (the feet a caller reads back)
+__global__ __launch_bounds__(TPB) void k_feet_fields(Grid g, const float *__restrict__ d, float *__restrict__ out)
+{
+    const int p = blockIdx.x * TPB + threadIdx.x;
+    if (p >= g.N) return;
+    const size_t N = g.N;
+    foot_of<true>(d, N, p, out[p], out[N + p], out[2 * N + p]);
 }
 
 __global__ __launch_bounds__(TPB) void k_adj_factor(Grid g, float dt, const float *__restrict__ divv,
@@ -183,7 +210,7 @@ __device__ __forceinline__ float epilogue(const SLParams &prm, float e, float va
 }
 
 // Per-node version (small grids, and tiles whose feet spread too far).
-template <typename Tu, typename To, int MODE>
+template <typename Tu, typename To, int MODE, bool AOS>
 __global__ __launch_bounds__(TPB) void k_sl_node(Grid g, const Tu *__restrict__ u, const float *__restrict__ d,
                                                  SLParams prm, To *__restrict__ out)
 {
@@ -192,8 +219,10 @@ __global__ __launch_bounds__(TPB) void k_sl_node(Grid g, const Tu *__restrict__ 
     int i, j, k;
     node_of(g, p, i, j, k);
     const float e = MODE == SL_STATE ? 0.0f : prm.e[p];
+    float a1, a2, a3;
+    foot_of<AOS>(d, g.N, p, a1, a2, a3);
     Foot F;
-    make_foot(g, i, j, k, d[p], d[g.N + p], d[2 * (size_t)g.N + p], F);
+    make_foot(g, i, j, k, a1, a2, a3, F);
     stf(out + p, epilogue<MODE>(prm, e, gather(u, F)));
 }
 
@@ -226,7 +255,7 @@ __device__ __forceinline__ float lin_node(const Grid &g, const Tu *__restrict__ 
 // Per-node trilinear version (grids too small for tiles): one node per
 // thread; the eight values come from L2 (the feet of neighbouring threads
 // are neighbours).
-template <typename Tu, typename To, int MODE>
+template <typename Tu, typename To, int MODE, bool AOS>
 __global__ __launch_bounds__(TPB) void k_sl_lin(Grid g, const Tu *__restrict__ u, const float *__restrict__ d,
                                                 SLParams prm, To *__restrict__ out)
 {
@@ -235,7 +264,9 @@ __global__ __launch_bounds__(TPB) void k_sl_lin(Grid g, const Tu *__restrict__ u
     int i, j, k;
     node_of(g, p, i, j, k);
     const float e = MODE == SL_STATE ? 0.0f : prm.e[p];
-    stf(out + p, epilogue<MODE>(prm, e, lin_node(g, u, i, j, k, d[p], d[g.N + p], d[2 * (size_t)g.N + p])));
+    float a1, a2, a3;
+    foot_of<AOS>(d, g.N, p, a1, a2, a3);
+    stf(out + p, epilogue<MODE>(prm, e, lin_node(g, u, i, j, k, a1, a2, a3)));
 }
 
 // Tiled version: tiles of TZ x TY x TX nodes (x1, x2, x3).  For a smooth
@@ -317,6 +348,7 @@ __device__ __forceinline__ TileIdx tile_idx(const Grid &g, int tile, int ntx, in
 // origin (x1, x2, x3), box[8 tile + 3..5] = extents.  The integer parts are
 // the same clamped floors that the SL kernels use, so every stencil lies
 // inside its box for any finite displacement.
+template <bool AOS>
 __global__ __launch_bounds__(TPB) void k_tile_boxes(Grid g, const float *__restrict__ d, int ntx, int nty,
                                                     int *__restrict__ box, int lo, int span)
 {
@@ -327,7 +359,9 @@ __global__ __launch_bounds__(TPB) void k_tile_boxes(Grid g, const float *__restr
 #pragma unroll
     for (int q = 0; q < TZ; ++q) {
         const int p = t.p0 + q * t.plane;
-        const int b1 = q + ifloor(d[p]), b2 = ifloor(d[N + p]), b3 = ifloor(d[2 * N + p]);
+        float a1, a2, a3;
+        foot_of<AOS>(d, N, p, a1, a2, a3);
+        const int b1 = q + ifloor(a1), b2 = ifloor(a2), b3 = ifloor(a3);
         mn1 = min(mn1, b1); mx1 = max(mx1, b1);
         mn2 = min(mn2, b2); mx2 = max(mx2, b2);
         mn3 = min(mn3, b3); mx3 = max(mx3, b3);
@@ -381,7 +415,7 @@ __device__ __forceinline__ TileBox tile_box(const int *__restrict__ boxes, int t
 constexpr int SPLIT = 2, QT = TZ / SPLIT, TPB_SL = 256 * SPLIT;
 
 // Feet and epilogue operand of the QT nodes of this thread.
-template <int MODE>
+template <int MODE, bool AOS>
 __device__ __forceinline__ void load_feet(const Grid &g, const float *__restrict__ d, const SLParams &prm,
                                           const TileIdx &t, float (&d1)[QT], float (&d2)[QT], float (&d3)[QT],
                                           float (&e)[QT])
@@ -389,15 +423,31 @@ __device__ __forceinline__ void load_feet(const Grid &g, const float *__restrict
     // each field from its own wave-uniform base with a 32-bit byte offset
     // (a field has at most 2^30 nodes)
     const size_t N = g.N;
-    const char *b1 = reinterpret_cast<const char *>(d), *b2 = reinterpret_cast<const char *>(d + N),
-               *b3 = reinterpret_cast<const char *>(d + 2 * N), *be = reinterpret_cast<const char *>(prm.e);
+    const char *be = reinterpret_cast<const char *>(prm.e);
     const unsigned o0 = (unsigned)t.p0 * 4u, dq = (unsigned)t.plane * 4u;
+    if constexpr (AOS) {
+        // interleaved feet: the tile's first node is the wave-uniform base,
+        // 12 bytes per node from there (under 2^32 within a tile)
+        const int pt = (((t.i0 << g.l2) + t.ty * TY) << g.l3) + t.tx * TX;
+        const char *bd = reinterpret_cast<const char *>(d + 3 * (size_t)pt);
+        const unsigned r0 = (unsigned)(t.p0 - pt) * 12u, rq = (unsigned)t.plane * 12u;
 #pragma unroll
-    for (int q = 0; q < QT; ++q) {
-        const unsigned o = o0 + q * dq;
-        d1[q] = *reinterpret_cast<const float *>(b1 + o);
-        d2[q] = *reinterpret_cast<const float *>(b2 + o);
-        d3[q] = *reinterpret_cast<const float *>(b3 + o);
+        for (int q = 0; q < QT; ++q) {
+            const float3 f = *reinterpret_cast<const float3 *>(bd + (r0 + q * rq));
+            d1[q] = f.x;
+            d2[q] = f.y;
+            d3[q] = f.z;
+        }
+    } else {
+        const char *b1 = reinterpret_cast<const char *>(d), *b2 = reinterpret_cast<const char *>(d + N),
+                   *b3 = reinterpret_cast<const char *>(d + 2 * N);
+#pragma unroll
+        for (int q = 0; q < QT; ++q) {
+            const unsigned o = o0 + q * dq;
+            d1[q] = *reinterpret_cast<const float *>(b1 + o);
+            d2[q] = *reinterpret_cast<const float *>(b2 + o);
+            d3[q] = *reinterpret_cast<const float *>(b3 + o);
+        }
     }
 #pragma unroll
     for (int q = 0; q < QT; ++q)
@@ -677,7 +727,7 @@ __device__ __forceinline__ void shift_copy(const Tu *box, const TileBox &B)
 // A tile whose box exceeds the pitches: each node gathers straight from
 // global memory, with the weights and contraction order of the tiled path
 // (same results), one node at a time so that the path needs few registers.
-template <typename Tu, typename To, int MODE, int ORDER>
+template <typename Tu, typename To, int MODE, int ORDER, bool AOS>
 __device__ __forceinline__ void tile_fallback(const Grid &g, const Tu *__restrict__ u, const float *__restrict__ d,
                                               const SLParams &prm, To *__restrict__ out, const TileIdx &t)
 {
@@ -685,7 +735,8 @@ __device__ __forceinline__ void tile_fallback(const Grid &g, const Tu *__restric
 #pragma unroll 1
     for (int q = 0; q < QT; ++q) {
         const int p = t.p0 + q * t.plane;
-        const float a1 = d[p], a2 = d[N + p], a3 = d[2 * N + p];
+        float a1, a2, a3;
+        foot_of<AOS>(d, N, p, a1, a2, a3);
         const float ev = MODE == SL_STATE ? 0.0f : prm.e[p];
         float v;
         if constexpr (ORDER == 1) {
@@ -704,7 +755,7 @@ __device__ __forceinline__ void tile_fallback(const Grid &g, const Tu *__restric
 // needs about 50 VGPRs (the global-memory fallback runs one node at a time
 // and adds none), so the 39.9 KB box sets the occupancy: four 512-thread
 // workgroups per CU, whose phases (waiting for memory, gathering) overlap.
-template <typename Tu, typename To, int MODE, int ORDER>
+template <typename Tu, typename To, int MODE, int ORDER, bool AOS>
 __global__ __launch_bounds__(TPB_SL, 8) void k_sl_tile(Grid g, const Tu *__restrict__ u, const float *__restrict__ d,
                                                   SLParams prm, To *__restrict__ out, const int *__restrict__ boxes,
                                                   int ntx, int nty, int nblk)
@@ -719,11 +770,11 @@ __global__ __launch_bounds__(TPB_SL, 8) void k_sl_tile(Grid g, const Tu *__restr
     const TileIdx t = tile_idx<SPLIT>(g, tile, ntx, nty);
     const TileBox B = tile_box<Tu>(boxes, tile, t);
     if (!B.fits) {                 // the whole workgroup takes this branch
-        tile_fallback<Tu, To, MODE, ORDER>(g, u, d, prm, out, t);
+        tile_fallback<Tu, To, MODE, ORDER, AOS>(g, u, d, prm, out, t);
         return;
     }
     float d1[QT], d2[QT], d3[QT], e[QT], r[QT];
-    load_feet<MODE>(g, d, prm, t, d1, d2, d3, e);
+    load_feet<MODE, AOS>(g, d, prm, t, d1, d2, d3, e);
     __builtin_amdgcn_sched_barrier(0);
     stage_box(g, u, box, t, B);
     __builtin_amdgcn_s_waitcnt(0);
@@ -740,7 +791,8 @@ inline bool tiled(const Grid &g) { return g.n3 >= TX && g.n2 >= TY && g.n1 >= TZ
 
 inline dim3 grid_of(const Grid &g) { return dim3((g.N + TPB - 1) / TPB); }
 
-template <typename Tu, typename To, int MODE>
+// AOS: interleaved feet (the solver's own); otherwise three fields
+template <typename Tu, typename To, int MODE, bool AOS = true>
 void launch_sl(const Grid &g, const Tu *u, const float *d, const SLParams &prm, To *out, const int *boxes,
                hipStream_t s)
 {
@@ -748,16 +800,24 @@ void launch_sl(const Grid &g, const Tu *u, const float *d, const SLParams &prm, 
         const int ntx = g.n3 / TX, nty = g.n2 / TY, ntz = g.n1 / TZ;
         const int nblk = ntx * nty * ntz;
         if (g.interp == 1)
-            hipLaunchKernelGGL((k_sl_tile<Tu, To, MODE, 1>), dim3(nblk), dim3(TPB_SL), 0, s, g, u, d, prm, out, boxes,
-                               ntx, nty, nblk);
+            hipLaunchKernelGGL((k_sl_tile<Tu, To, MODE, 1, AOS>), dim3(nblk), dim3(TPB_SL), 0, s, g, u, d, prm, out,
+                               boxes, ntx, nty, nblk);
         else
-            hipLaunchKernelGGL((k_sl_tile<Tu, To, MODE, 3>), dim3(nblk), dim3(TPB_SL), 0, s, g, u, d, prm, out, boxes,
-                               ntx, nty, nblk);
+            hipLaunchKernelGGL((k_sl_tile<Tu, To, MODE, 3, AOS>), dim3(nblk), dim3(TPB_SL), 0, s, g, u, d, prm, out,
+                               boxes, ntx, nty, nblk);
     } else if (g.interp == 1) {
-        hipLaunchKernelGGL((k_sl_lin<Tu, To, MODE>), grid_of(g), dim3(TPB), 0, s, g, u, d, prm, out);
+        hipLaunchKernelGGL((k_sl_lin<Tu, To, MODE, AOS>), grid_of(g), dim3(TPB), 0, s, g, u, d, prm, out);
     } else {
-        hipLaunchKernelGGL((k_sl_node<Tu, To, MODE>), grid_of(g), dim3(TPB), 0, s, g, u, d, prm, out);
+        hipLaunchKernelGGL((k_sl_node<Tu, To, MODE, AOS>), grid_of(g), dim3(TPB), 0, s, g, u, d, prm, out);
     }
+}
+
+template <bool AOS> void tile_boxes(const Grid &g, const float *d, int *boxes, hipStream_t s)
+{
+    if (!tiled(g)) return;
+    const int ntx = g.n3 / TX, nty = g.n2 / TY, ntz = g.n1 / TZ;
+    const int lo = g.interp == 1 ? 0 : 1, span = g.interp == 1 ? 2 : 4;
+    hipLaunchKernelGGL(k_tile_boxes<AOS>, dim3(ntx * nty * ntz), dim3(TPB), 0, s, g, d, ntx, nty, boxes, lo, span);
 }
 
 } // namespace
@@ -786,12 +846,11 @@ void launch_feet(const Grid &g, float dt, const float *v, float *df, float *db, 
 
 size_t tile_box_ints(const Grid &g) { return tiled(g) ? (size_t)8 * (g.N / (TX * TY * TZ)) : 0; }
 
-void launch_tile_boxes(const Grid &g, const float *d, int *boxes, hipStream_t s)
+void launch_tile_boxes(const Grid &g, const float *d, int *boxes, hipStream_t s) { tile_boxes<true>(g, d, boxes, s); }
+
+void launch_feet_fields(const Grid &g, const float *d, float *out, hipStream_t s)
 {
-    if (!tiled(g)) return;
-    const int ntx = g.n3 / TX, nty = g.n2 / TY, ntz = g.n1 / TZ;
-    const int lo = g.interp == 1 ? 0 : 1, span = g.interp == 1 ? 2 : 4;
-    hipLaunchKernelGGL(k_tile_boxes, dim3(ntx * nty * ntz), dim3(TPB), 0, s, g, d, ntx, nty, boxes, lo, span);
+    hipLaunchKernelGGL(k_feet_fields, grid_of(g), dim3(TPB), 0, s, g, d, out);
 }
 
 void launch_sl_state(const Grid &g, int dt_u, const void *u, const float *d, const int *boxes, int dt_out, void *out,
@@ -856,10 +915,11 @@ void launch_jacobian(const Grid &g, float dt, int nt, const float *divv, const f
     }
 }
 
+// d: three fields from the caller
 void launch_interp_f32(const Grid &g, const float *u, const float *d, int *boxes, float *out, hipStream_t s)
 {
-    launch_tile_boxes(g, d, boxes, s);
-    launch_sl<float, float, SL_STATE>(g, u, d, SLParams{}, out, boxes, s);
+    tile_boxes<false>(g, d, boxes, s);
+    launch_sl<float, float, SL_STATE, false>(g, u, d, SLParams{}, out, boxes, s);
 }
 
 } // namespace clh
