@@ -60,10 +60,12 @@ def counter_means(directory, counter):
     return {k: sum(v) / len(v) for k, v in acc.items()}
 
 
-# tiled SL kernels in FP32: k_sl_tile<field, output, mode, interpolation order>
-SL_NAMES = {"sl_state": "k_sl_tile<float, float, 0, 3>", "sl_adjoint": "k_sl_tile<float, float, 1, 3>",
-            "sl_inc": "k_sl_tile<float, float, 2, 3>", "sl_adjoint_trilinear": "k_sl_tile<float, float, 1, 1>",
-            "sl_inc_trilinear": "k_sl_tile<float, float, 2, 1>"}
+# tiled SL kernels of the solver in FP32: k_sl_tile<field, output, mode,
+# interpolation order, interleaved feet>
+SL_NAMES = {"sl_state": "k_sl_tile<float, float, 0, 3, true>", "sl_adjoint": "k_sl_tile<float, float, 1, 3, true>",
+            "sl_inc": "k_sl_tile<float, float, 2, 3, true>",
+            "sl_adjoint_trilinear": "k_sl_tile<float, float, 1, 1, true>",
+            "sl_inc_trilinear": "k_sl_tile<float, float, 2, 1, true>"}
 
 
 def traffic(fetch_dir, write_dir, copy_mib, command):
