@@ -164,6 +164,37 @@ def test_feet_and_adjoint_factor(n):
     assert rel(host(r.field(6)) - 1.0, c - 1.0) < TOL_KERNEL
 
 
+@pytest.mark.parametrize("shape", [(16, 16, 16), (32, 32, 16)])
+@pytest.mark.parametrize("interp", [3, 1])
+def test_untiled_grid_matches_oracle(shape, interp):
+    """Grids with n3 < 32 take the per-node SL kernels (no tiles).  The
+    solver's feet (stored interleaved) must reach them as they reach the
+    tiled kernel: feet, state, gradient and Hessian matvec against the
+    oracle, tricubic and trilinear."""
+    m0 = f32(synth.trig_template(shape))
+    vs = f32(synth.trig_velocity(shape, 0.5))
+    o = oracle.Oracle(shape, nt=4, beta=5e-4, interp=interp)
+    o.set_images(m0, m0)
+    o.set_velocity(vs)
+    o.state()
+    m1 = f32(o.field(oracle.FIELD_STATE, 4))
+    v = f32(0.5 * vs)
+    o.set_images(m0, m1)
+    o.set_velocity(v)
+    g_ref, _ = o.gradient()
+    r = reg(shape, interp="linear" if interp == 1 else "cubic")
+    r.set_images(dev(m0), dev(m1))
+    r.set_velocity(dev(v))
+    g, _, _ = r.gradient()
+    assert rel(host(r.field(4)), o.field(oracle.FIELD_FEET_F)) < TOL_KERNEL
+    assert rel(host(r.field(5)), o.field(oracle.FIELD_FEET_B)) < TOL_KERNEL
+    assert rel(host(r.field(0, 4)), o.field(oracle.FIELD_STATE, 4)) < TOL_KERNEL
+    assert rel(host(g), g_ref) < TOL_OP
+    vt = f32(synth.trig_velocity(shape, 0.3)[[2, 0, 1]])
+    assert rel(host(r.hessian_matvec(dev(vt))), o.matvec(vt)) < TOL_OP
+    r.close()
+
+
 # ------------------------------------------------------ transports/operators
 
 def _setup_pair(n, frac=0.5, shape=None):
