@@ -53,8 +53,9 @@ struct cl_ctx {
     void *lam = nullptr;                    // (nt+1) N, adjoint dtype
     void *q[2] = {nullptr, nullptr};        // adjoint dtype
     float *G = nullptr;                     // grad_h m^j, (nt+1) x 3N FP32
-    float *S = nullptr;                     // incremental sources s^1..s^nt, nt x N FP32 (lean: one field)
-    bool lean = false;                      // lean layout: no stored gradients, one source field
+    float *S = nullptr;                     // incremental sources s^1..s^nt, nt x N FP32 (or one field)
+    bool lean = false;                      // lean layout: no stored gradients
+    bool S_all = true;                      // S holds every level (else one field, lean layout only)
     int *box_f = nullptr, *box_b = nullptr, *box_t = nullptr;  // tile stencil boxes: X_f, X_b, scratch
     float *v = nullptr, *vtrial = nullptr;  // 3N
     float *df = nullptr, *db = nullptr;     // 3N
@@ -413,9 +414,11 @@ void matvec(cl_ctx *ctx, const float *vt, float *Hvt, const float *Avt_known = n
         HIPCHK(hipEventRecord(ctx->join, ctx->s2));
         Avt = ctx->tmp3;
     }
-    // sources s^j = -vt . grad_h m^j, q^0 = dt/2 s^0: all at once from the
-    // stored gradients, or one time level at a time by FD8 (lean layout)
-    if (ctx->lean) {
+    // sources s^j = -vt . grad_h m^j, q^0 = dt/2 s^0: all levels at once (by
+    // the marching FD8 kernel or from the stored gradients), or one time
+    // level at a time by FD8 (lean layout with one source field)
+    const bool per_level = !ctx->S_all;
+    if (per_level) {
         run(ctx, CL_K_VEC, [&] {
             launch_inc_source_fd(ctx->g, ctx->dts, slot(ctx, ctx->m, ctx->dts, 0), vt, 0.5f * dt, ctx->dta,
                                  ctx->q[0], ctx->s);
@@ -433,8 +436,8 @@ void matvec(cl_ctx *ctx, const float *vt, float *Hvt, const float *Avt_known = n
     for (int j = 0; j < nt; ++j) {
         const bool last = j == nt - 1;
         void *out = last ? slot(ctx, ctx->lam, ctx->dta, nt) : ctx->q[(j + 1) & 1];
-        const float *Sj = ctx->lean ? ctx->S : ctx->S + (size_t)j * ctx->N;
-        if (ctx->lean)
+        const float *Sj = per_level ? ctx->S : ctx->S + (size_t)j * ctx->N;
+        if (per_level)
             run(ctx, CL_K_VEC, [&] {
                 launch_inc_source_fd(ctx->g, ctx->dts, slot(ctx, ctx->m, ctx->dts, j + 1), vt, 1.0f, CL_F32,
                                      ctx->S, ctx->s);
@@ -1089,6 +1092,13 @@ int cl_create(cl_ctx **out, int n1, int n2, int n3, const cl_options *opt)
     cl_ctx *ctx = new (std::nothrow) cl_ctx();
     if (!ctx) return CL_ERR_OOM;
     ctx->lean = lean;
+    // the lean layout keeps the sources of every level too (n_t - 1 more
+    // fields, one marching pass per matvec instead of one per level) when
+    // they fit the limit and the marching kernel covers the grid
+    if (lean)
+        ctx->S_all = sources_march(make_grid(n1, n2, n3, opt->interp_order), opt->nt) &&
+                     workspace_bytes(n1, n2, n3, *opt, true) + (size_t)(opt->nt - 1) * ((size_t)n1 * n2 * n3) *
+                                                                   sizeof(float) <= limit;
     ctx->opt = *opt;
     ctx->s = (hipStream_t)opt->stream;
     ctx->nt = opt->nt;
@@ -1115,7 +1125,7 @@ int cl_create(cl_ctx **out, int n1, int n2, int n3, const cl_options *opt)
         ctx->q[0] = alloc(N * ea);
         ctx->q[1] = alloc(N * ea);
         if (!ctx->lean) ctx->G = (float *)alloc((size_t)(ctx->nt + 1) * 3 * N * sizeof(float));
-        ctx->S = (float *)alloc((size_t)(ctx->lean ? 1 : ctx->nt) * N * sizeof(float));
+        ctx->S = (float *)alloc((size_t)(ctx->S_all ? ctx->nt : 1) * N * sizeof(float));
         {
             const size_t nb = std::max<size_t>(tile_box_ints(ctx->g), 8) * sizeof(int);
             ctx->box_f = (int *)alloc(nb);
