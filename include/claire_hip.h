@@ -137,20 +137,18 @@ typedef struct {
 void cl_default_options(cl_options *opt);
 
 /* Device bytes cl_create would allocate for this grid and options (host-only query; with
- * workspace_cap_bytes = 0 it reports the full layout).  For the lean layout it reports the minimum
- * (one source field); cl_create adds nt - 1 source fields when they fit (see cl_layout). */
+ * workspace_cap_bytes = 0 it reports the full layout). */
 int cl_query_workspace(int n1, int n2, int n3, const cl_options *opt, unsigned long long *bytes);
 
 /* Create a context on the current HIP device; allocates all workspace. */
 int cl_create(cl_ctx **out, int n1, int n2, int n3, const cl_options *opt);
 
-/* Memory layout of a context: 0 = full (the state gradients grad_h m^j, (nt+1) x 3 FP32 fields, are
- * stored once per velocity and every incremental source field is kept), 1 = lean (the gradients are
- * taken by the 8th-order stencil inside the kernels that need them: 3(nt+1) fewer FP32 fields).  The
- * lean layout keeps the nt incremental source fields as well when nt - 1 more FP32 fields fit under
- * the cap (or 15/16 of the free device memory) and the grid has n3 >= 64, n2 >= 8 and nt <= 4;
- * otherwise it keeps one source field and computes it level by level (slower).  Same results up to
- * FP32 rounding order.  Negative: error code (NULL context). */
+/* Memory layout of a context: 0 = full (every incremental source field is kept; the state gradients
+ * grad_h m^j are stored once per velocity where a kernel reads them: all nt+1 levels, (nt+1) x 3 FP32
+ * fields, on grids with n3 < 64 or n2 < 8 or with nt > 4, level 0 for the zero-velocity
+ * preconditioners, none otherwise, since the marching kernels take the stencil of m^j on the fly),
+ * 1 = lean (no stored gradients and one source field, computed level by level: slower).  Same results
+ * up to FP32 rounding order.  Negative: error code (NULL context). */
 int cl_layout(const cl_ctx *ctx);
 void cl_destroy(cl_ctx *ctx);
 

@@ -54,8 +54,9 @@ struct cl_ctx {
     void *q[2] = {nullptr, nullptr};        // adjoint dtype
     float *G = nullptr;                     // grad_h m^j, (nt+1) x 3N FP32
     float *S = nullptr;                     // incremental sources s^1..s^nt, nt x N FP32 (or one field)
-    bool lean = false;                      // lean layout: no stored gradients
-    bool S_all = true;                      // S holds every level (else one field, lean layout only)
+    bool lean = false;                      // lean layout: one source field, no stored gradients
+    bool S_all = true;                      // S holds every level (the full layout)
+    int G_levels = 0;                       // levels of grad_h m^j kept in G (0, 1 or nt + 1)
     int *box_f = nullptr, *box_b = nullptr, *box_t = nullptr;  // tile stencil boxes: X_f, X_b, scratch
     float *v = nullptr, *vtrial = nullptr;  // 3N
     float *df = nullptr, *db = nullptr;     // 3N
@@ -278,13 +279,13 @@ void ensure_state(cl_ctx *ctx)
 void ensure_sgrad(cl_ctx *ctx)
 {
     ensure_state(ctx);
-    if (ctx->sgrad || ctx->lean) return;
+    if (ctx->sgrad || ctx->G_levels == 0) return;
     StateGradArgs a{};
-    for (int j = 0; j <= ctx->nt; ++j) {
+    for (int j = 0; j < ctx->G_levels; ++j) {
         a.m[j] = slot(ctx, ctx->m, ctx->dts, j);
         a.G[j] = ctx->G + (size_t)j * 3 * ctx->N;
     }
-    run(ctx, CL_K_FD, [&] { launch_state_grad(ctx->g, ctx->dts, a, ctx->nt + 1, ctx->s); });
+    run(ctx, CL_K_FD, [&] { launch_state_grad(ctx->g, ctx->dts, a, ctx->G_levels, ctx->s); });
     ctx->sgrad = true;
 }
 
@@ -321,12 +322,12 @@ QuadArgs quad_args(cl_ctx *ctx)
 {
     QuadArgs qa{};
     qa.count = ctx->nt + 1;
-    qa.lean = ctx->lean ? 1 : 0;
+    qa.lean = ctx->G_levels == ctx->nt + 1 ? 0 : 1;   // 0: the per-node kernels read G
     qa.dt_m = ctx->dts;
     for (int j = 0; j <= ctx->nt; ++j) {
         qa.lam[j] = slot(ctx, ctx->lam, ctx->dta, j);
         qa.m[j] = slot(ctx, ctx->m, ctx->dts, j);
-        qa.G[j] = ctx->lean ? nullptr : ctx->G + (size_t)j * 3 * ctx->N;
+        qa.G[j] = j < ctx->G_levels ? ctx->G + (size_t)j * 3 * ctx->N : nullptr;
         qa.w[j] = (j == 0 || j == ctx->nt) ? 0.5f * ctx->dt : ctx->dt;
     }
     return qa;
@@ -752,6 +753,20 @@ int solve(cl_ctx *ctx, const int *forced_pcg, const double *forced_alpha, int fo
     return status;
 }
 
+// Levels of grad_h m^j a context stores: every level where a kernel reads
+// them (grids the marching FD8 kernels do not cover, or more time steps than
+// the all-level source pass takes), level 0 for the zero-velocity
+// preconditioners, none otherwise (and none in the lean layout)
+int grad_levels(int n1, int n2, int n3, const cl_options &o, bool lean)
+{
+    if (lean) return 0;
+    const Grid g = make_grid(n1, n2, n3, o.interp_order);
+    QuadArgs qa{};
+    qa.count = o.nt + 1;
+    if (!quadrature_marches(g, qa) || !sources_march(g, o.nt)) return o.nt + 1;
+    return o.precond == CL_PRECOND_SPECTRAL ? 0 : 1;
+}
+
 size_t workspace_bytes(int n1, int n2, int n3, const cl_options &o, bool lean)
 {
     const size_t N = (size_t)n1 * n2 * n3;
@@ -761,7 +776,7 @@ size_t workspace_bytes(int n1, int n2, int n3, const cl_options &o, bool lean)
     b += (size_t)(o.nt + 1) * N * es;        // m^j
     b += (size_t)(o.nt + 1) * N * ea;        // lam^j / lam~^j
     b += 2 * N * ea;                         // q ping-pong
-    if (!lean) b += (size_t)(o.nt + 1) * 3 * N * sizeof(float);  // grad_h m^j
+    b += (size_t)grad_levels(n1, n2, n3, o, lean) * 3 * N * sizeof(float);   // grad_h m^j
     b += (size_t)(lean ? 1 : o.nt) * N * sizeof(float);   // incremental sources s^j
     b += 3 * (N / 2048 + 1) * 8 * sizeof(int);  // tile stencil boxes
     b += 2 * N * sizeof(float);              // c, div v
@@ -1092,13 +1107,8 @@ int cl_create(cl_ctx **out, int n1, int n2, int n3, const cl_options *opt)
     cl_ctx *ctx = new (std::nothrow) cl_ctx();
     if (!ctx) return CL_ERR_OOM;
     ctx->lean = lean;
-    // the lean layout keeps the sources of every level too (n_t - 1 more
-    // fields, one marching pass per matvec instead of one per level) when
-    // they fit the limit and the marching kernel covers the grid
-    if (lean)
-        ctx->S_all = sources_march(make_grid(n1, n2, n3, opt->interp_order), opt->nt) &&
-                     workspace_bytes(n1, n2, n3, *opt, true) + (size_t)(opt->nt - 1) * ((size_t)n1 * n2 * n3) *
-                                                                   sizeof(float) <= limit;
+    ctx->S_all = !lean;
+    ctx->G_levels = grad_levels(n1, n2, n3, *opt, lean);
     ctx->opt = *opt;
     ctx->s = (hipStream_t)opt->stream;
     ctx->nt = opt->nt;
@@ -1124,7 +1134,7 @@ int cl_create(cl_ctx **out, int n1, int n2, int n3, const cl_options *opt)
         ctx->lam = alloc((size_t)(ctx->nt + 1) * N * ea);
         ctx->q[0] = alloc(N * ea);
         ctx->q[1] = alloc(N * ea);
-        if (!ctx->lean) ctx->G = (float *)alloc((size_t)(ctx->nt + 1) * 3 * N * sizeof(float));
+        if (ctx->G_levels) ctx->G = (float *)alloc((size_t)ctx->G_levels * 3 * N * sizeof(float));
         ctx->S = (float *)alloc((size_t)(ctx->S_all ? ctx->nt : 1) * N * sizeof(float));
         {
             const size_t nb = std::max<size_t>(tile_box_ints(ctx->g), 8) * sizeof(int);
