@@ -145,8 +145,8 @@ int cl_create(cl_ctx **out, int n1, int n2, int n3, const cl_options *opt);
 
 /* Memory layout of a context: 0 = full (every incremental source field is kept; the state gradients
  * grad_h m^j are stored once per velocity where a kernel reads them: all nt+1 levels, (nt+1) x 3 FP32
- * fields, on grids with n3 < 64 or n2 < 8 or with nt > 4, level 0 for the zero-velocity
- * preconditioners, none otherwise, since the marching kernels take the stencil of m^j on the fly),
+ * fields, on grids with n3 < 64 or n2 < 8 or with nt > 4, level 0 for CL_PRECOND_H0, none
+ * otherwise, since the marching kernels take the stencil of m^j on the fly),
  * 1 = lean (no stored gradients and one source field, computed level by level: slower).  Same results
  * up to FP32 rounding order.  Negative: error code (NULL context). */
 int cl_layout(const cl_ctx *ctx);

@@ -211,7 +211,8 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def query_workspace(shape, nt=4, storage_state="f32", storage_adjoint="f32", workspace_cap=0):
+def query_workspace(shape, nt=4, storage_state="f32", storage_adjoint="f32", workspace_cap=0, precond="spectral",
+                    precond_inner=5):
     """Device bytes a registration context of this shape and storage needs
     (host-only query, cl_query_workspace; the lean layout when the full one
     exceeds a nonzero workspace_cap)."""
@@ -220,6 +221,8 @@ def query_workspace(shape, nt=4, storage_state="f32", storage_adjoint="f32", wor
     o.workspace_cap_bytes = int(workspace_cap)
     o.storage_state = DTYPES[storage_state]
     o.storage_adjoint = DTYPES[storage_adjoint]
+    o.precond = PRECOND[precond]
+    o.precond_inner = int(precond_inner)
     nb = ctypes.c_ulonglong()
     st = lib().cl_query_workspace(*[int(x) for x in shape], ctypes.byref(o), ctypes.byref(nb))
     if st != 0:

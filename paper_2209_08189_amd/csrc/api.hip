@@ -755,8 +755,9 @@ int solve(cl_ctx *ctx, const int *forced_pcg, const double *forced_alpha, int fo
 
 // Levels of grad_h m^j a context stores: every level where a kernel reads
 // them (grids the marching FD8 kernels do not cover, or more time steps than
-// the all-level source pass takes), level 0 for the zero-velocity
-// preconditioners, none otherwise (and none in the lean layout)
+// the all-level source pass takes), level 0 for the full-resolution
+// zero-velocity preconditioner (the two-level one takes the gradient of its
+// coarse template), none otherwise (and none in the lean layout)
 int grad_levels(int n1, int n2, int n3, const cl_options &o, bool lean)
 {
     if (lean) return 0;
@@ -764,7 +765,7 @@ int grad_levels(int n1, int n2, int n3, const cl_options &o, bool lean)
     QuadArgs qa{};
     qa.count = o.nt + 1;
     if (!quadrature_marches(g, qa) || !sources_march(g, o.nt)) return o.nt + 1;
-    return o.precond == CL_PRECOND_SPECTRAL ? 0 : 1;
+    return o.precond == CL_PRECOND_H0 ? 1 : 0;
 }
 
 size_t workspace_bytes(int n1, int n2, int n3, const cl_options &o, bool lean)

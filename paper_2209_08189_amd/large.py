@@ -8,6 +8,10 @@ algorithmic GB/s from a capped solve, the exact integer-shift roll at this
 size, and the solve's progress (time, GN / PCG iterations, relative mismatch
 and gradient per GN iteration, Dice of the warped labels).
 
+A storage entry with the suffix "+h2" (e.g. "f16+h2") solves with the
+two-level zero-velocity preconditioner (12 inner CG steps on the
+half-resolution grid) instead of the spectral one.
+
 A storage entry with the suffix "+ws" (e.g. "f32+ws") starts its solve from
 the multilevel learned warm start instead of v = 0: the images spectrally
 restricted to 256^3, the network's prediction there (network grid 128^3,
@@ -101,7 +105,8 @@ def main():
     ap.add_argument("--max-pcg", type=int, default=40)
     ap.add_argument("--storage", default="f32,f16",
                     help="comma-separated runs: f32, f16 or bf16 field storage; the suffix +ws starts the solve "
-                         "from the multilevel learned warm start (needs --net-params)")
+                         "from the multilevel learned warm start (needs --net-params), +h2 takes the two-level "
+                         "zero-velocity preconditioner")
     ap.add_argument("--net-params", default=None, help="parameters of the 128^3 warm-start network (.npy)")
     ap.add_argument("--search", type=float, default=0.0,
                     help="J_min of a parameter search (beta_v, beta_w) run instead of the plain solve (0: off)")
@@ -127,8 +132,9 @@ def main():
     dev = lambda x: torch.from_numpy(np.ascontiguousarray(x)).cuda()
     out = {"n": n, "seed": a.seed, "max_outer": a.max_outer, "max_pcg": a.max_pcg, "runs": {}}
     for key in a.storage.split(","):
-        st, ws = key.split("+")[0], key.endswith("+ws")
-        if st not in STORAGE_BYTES or key not in (st, st + "+ws"):
+        parts = key.split("+")
+        st, ws, h2 = parts[0], "ws" in parts[1:], "h2" in parts[1:]
+        if st not in STORAGE_BYTES or any(x not in ("ws", "h2") for x in parts[1:]):
             raise SystemExit("unknown storage entry %r" % key)
         if ws and a.net_params is None:
             raise SystemExit("%s needs --net-params" % key)
@@ -137,11 +143,13 @@ def main():
                 raise SystemExit("a run from v = 0 must come before the first +ws run (it makes m1)")
             out["v_ws"], out["warm_start"] = learned_warm_start(torch.from_numpy(img + n0), out["m1"], n,
                                                                 a.net_params, log=log)
-        reg = Registration(shape, max_outer=a.max_outer, max_pcg=a.max_pcg, storage_state=st, storage_adjoint=st)
+        pc = {"precond": "h0_2level", "precond_inner": 12} if h2 else {}
+        reg = Registration(shape, max_outer=a.max_outer, max_pcg=a.max_pcg, storage_state=st, storage_adjoint=st, **pc)
         free, total = torch.cuda.mem_get_info()
-        run = {"storage": st, "warm_start": ws, "layout": "lean" if reg.layout() else "full",
+        run = {"storage": st, "warm_start": ws, "precond": "h0_2level" if h2 else "spectral",
+               "layout": "lean" if reg.layout() else "full",
                "workspace_GB": query_workspace(shape, storage_state=st, storage_adjoint=st,
-                                               workspace_cap=free if reg.layout() else 0) / 1e9,
+                                               workspace_cap=free if reg.layout() else 0, **pc) / 1e9,
                "device_in_use_GB": (total - free) / 1e9, "device_GB": total / 1e9}
         log("%s: layout %s, %.1f of %.1f GB in use" % (key, run["layout"], run["device_in_use_GB"], run["device_GB"]))
         # m1 = phantom transported by v_true and the labels of m1, made once
