@@ -62,3 +62,20 @@ def test_option_validation_without_gpu():
     assert L.cl_query_workspace(64, 64, 64, ctypes.byref(o), ctypes.byref(nb)) == -1
     o = claire.default_options(); o.storage_state = 7
     assert L.cl_query_workspace(64, 64, 64, ctypes.byref(o), ctypes.byref(nb)) == -3
+
+
+def test_workspace_counts_gradients_only_where_read():
+    """Full minus lean workspace (host-only query): the n_t - 1 further
+    source fields, plus the state gradients where a kernel reads them: none
+    on grids the marching FD8 kernels cover (n3 >= 64, n2 >= 8, n_t <= 4)
+    with the spectral or the two-level preconditioner, level 0 (3 fields)
+    for the full-resolution zero-velocity preconditioner, all n_t + 1 levels
+    on the other grids."""
+    from paper_2209_08189_amd.claire import query_workspace as q
+    cases = [((64, 64, 64), 4, "spectral", 0), ((64, 64, 64), 4, "h0_2level", 0), ((64, 64, 64), 4, "h0", 1),
+             ((32, 64, 64), 2, "spectral", 0), ((64, 64, 32), 4, "spectral", 5), ((64, 64, 64), 6, "spectral", 7)]
+    for shape, nt, pc, levels in cases:
+        n = shape[0] * shape[1] * shape[2]
+        full = q(shape, nt=nt, precond=pc)
+        lean = q(shape, nt=nt, precond=pc, workspace_cap=1)
+        assert full - lean == ((nt - 1) + 3 * levels) * 4 * n, (shape, nt, pc)
