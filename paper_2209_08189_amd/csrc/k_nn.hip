@@ -87,15 +87,17 @@ __device__ __forceinline__ bf8 as_bf8(u4 v) { return __builtin_bit_cast(bf8, v);
 // in: BF16 [D][H][W][Ci]; wp: packed (K = Ci); bias FP32 [Co] or NULL;
 // act: 0 none, 1 LeakyReLU(slope).  out: BF16 or FP32 [D][H][W][Co].
 // A workgroup (4 wavefronts) owns a 16 (x) x 4 (y) x MT (z) output brick;
-// wavefront w owns the MT x-runs at y = y0 + w and all Co channels (NT
-// tiles).  Per 16-channel input chunk the 18 x 6 x (MT + 2) input halo is
+// wavefront w owns the MT x-runs at y = y0 + w and NTS of the NTT 16-channel
+// output tiles (group blockIdx.y: tiles NTS blockIdx.y ...; small grids split
+// the output channels over several groups to fill the CUs).  Per 16-channel input chunk the 18 x 6 x (MT + 2) input halo is
 // staged in LDS once (two planes of 8 channels, so 16 lanes read 256
 // contiguous bytes) and serves all 27 taps; B fragments stream from the
 // packed weights (L2-resident).
-template <int MT, int NT, typename To>
+template <int MT, int NTS, typename To>
 __global__ __launch_bounds__(TPB) void k_conv3(const unsigned short *__restrict__ in, const u4 *__restrict__ wp,
                                                const float *__restrict__ bias, To *__restrict__ out, int D, int H,
-                                               int W, int Ci, int act, float slope, int nbx, int nby, int nblk)
+                                               int W, int Ci, int act, float slope, int nbx, int nby, int nblk,
+                                               int NTT)
 {
     constexpr int XS = 18, YS = 6, ZS = MT + 2, NV = XS * YS * ZS;
     __shared__ u4 tile[2 * NV];
@@ -106,12 +108,12 @@ __global__ __launch_bounds__(TPB) void k_conv3(const unsigned short *__restrict_
     const int x0 = bx * 16, y0 = by * 4, z0 = bz * MT;
     const int tid = threadIdx.x, l = tid & 63, wv = tid >> 6;
     const int m = l & 15, half = (l >> 4) & 1, tsel = l >> 5;
-    const int KC = Ci >> 4;
-    f4 acc[MT][NT];
+    const int KC = Ci >> 4, nt0 = blockIdx.y * NTS;
+    f4 acc[MT][NTS];
 #pragma unroll
     for (int i = 0; i < MT; ++i)
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) acc[i][nt] = f4{0.f, 0.f, 0.f, 0.f};
+        for (int nt = 0; nt < NTS; ++nt) acc[i][nt] = f4{0.f, 0.f, 0.f, 0.f};
     for (int kc = 0; kc < KC; ++kc) {
         if (kc) __syncthreads();
         for (int q = tid; q < 2 * NV; q += TPB) {
@@ -125,7 +127,7 @@ __global__ __launch_bounds__(TPB) void k_conv3(const unsigned short *__restrict_
             tile[hq * NV + v] = val;
         }
         __syncthreads();
-        const u4 *wk = wp + (size_t)kc * NTP * NT * 64 + l;
+        const u4 *wk = wp + ((size_t)kc * NTP * NTT + nt0) * 64 + l;
         for (int tp = 0; tp < NTP; ++tp) {
             const int tap = 2 * tp + tsel;
             const int tt = tap < 27 ? tap : 13;
@@ -139,8 +141,8 @@ __global__ __launch_bounds__(TPB) void k_conv3(const unsigned short *__restrict_
                 a[i] = as_bf8(raw);
             }
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt) {
-                const bf8 bw = as_bf8(wk[(tp * NT + nt) * 64]);
+            for (int nt = 0; nt < NTS; ++nt) {
+                const bf8 bw = as_bf8(wk[(tp * NTT + nt) * 64]);
 #pragma unroll
                 for (int i = 0; i < MT; ++i)
                     acc[i][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bw, acc[i][nt], 0, 0, 0);
@@ -148,15 +150,15 @@ __global__ __launch_bounds__(TPB) void k_conv3(const unsigned short *__restrict_
         }
     }
     // D[m][n]: n = l % 16 (channel), m = 4 (l / 16) + j (voxel along x)
-    const int Co = NT * 16, n = l & 15, xq = x0 + 4 * (l >> 4), y = y0 + wv;
+    const int Co = NTT * 16, n = l & 15, xq = x0 + 4 * (l >> 4), y = y0 + wv;
     if (y >= H) return;
 #pragma unroll
     for (int i = 0; i < MT; ++i) {
         const int z = z0 + i;
         if (z >= D) continue;
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-            const int co = nt * 16 + n;
+        for (int nt = 0; nt < NTS; ++nt) {
+            const int co = (nt0 + nt) * 16 + n;
             const float bb = bias ? bias[co] : 0.f;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -586,14 +588,36 @@ void nn_pack_weights(const float *w, unsigned short *out, int Ci, int Co, int fl
     hipLaunchKernelGGL(k_pack_w, dim3(nblk(nn_packed_weight_elems(Ci, Co))), dim3(TPB), 0, s, w, out, Ci, Co, flip);
 }
 
-template <int MT, int NT, typename To>
+// NTS of the NT output tiles per workgroup, NT / NTS workgroup groups
+template <int MT, int NTS, typename To>
 static void conv3_launch(const unsigned short *in, const void *wp, const float *bias, To *out, int D, int H, int W,
-                         int Ci, int act, float slope, hipStream_t s)
+                         int Ci, int NT, int act, float slope, hipStream_t s)
 {
     const int nbx = (W + 15) / 16, nby = (H + 3) / 4, nbz = (D + MT - 1) / MT;
     const int nb = nbx * nby * nbz;
-    hipLaunchKernelGGL((k_conv3<MT, NT, To>), dim3(nb), dim3(TPB), 0, s, in, (const u4 *)wp, bias, out, D, H, W, Ci,
-                       act, slope, nbx, nby, nb);
+    hipLaunchKernelGGL((k_conv3<MT, NTS, To>), dim3(nb, NT / NTS), dim3(TPB), 0, s, in, (const u4 *)wp, bias, out, D,
+                       H, W, Ci, act, slope, nbx, nby, nb, NT);
+}
+
+// all NT tiles per workgroup when the bricks alone give 512 workgroups (two
+// per CU); otherwise the output channels are split over groups of 2 or 1
+// tiles (the input halo of a brick is then staged once per group)
+template <int MT, int NT, typename To>
+static void conv3_split(const unsigned short *in, const void *wp, const float *bias, To *out, int D, int H, int W,
+                        int Ci, int act, float slope, hipStream_t s)
+{
+    const int nb = ((W + 15) / 16) * ((H + 3) / 4) * ((D + MT - 1) / MT);
+    if (nb >= 512 || NT == 1) {
+        conv3_launch<MT, NT, To>(in, wp, bias, out, D, H, W, Ci, NT, act, slope, s);
+        return;
+    }
+    if constexpr (NT % 2 == 0) {
+        if (nb * (NT / 2) >= 512) {
+            conv3_launch<MT, 2, To>(in, wp, bias, out, D, H, W, Ci, NT, act, slope, s);
+            return;
+        }
+    }
+    conv3_launch<MT, 1, To>(in, wp, bias, out, D, H, W, Ci, NT, act, slope, s);
 }
 
 // output rows per wavefront (MT) chosen so that MT * NT accumulator tiles stay near 16
@@ -602,13 +626,13 @@ static void conv3_dispatch(const unsigned short *in, const void *wp, const float
                            int Ci, int Co, int act, float slope, hipStream_t s)
 {
     switch (Co / 16) {
-    case 1: conv3_launch<8, 1, To>(in, wp, bias, out, D, H, W, Ci, act, slope, s); break;
-    case 2: conv3_launch<8, 2, To>(in, wp, bias, out, D, H, W, Ci, act, slope, s); break;
-    case 3: conv3_launch<4, 3, To>(in, wp, bias, out, D, H, W, Ci, act, slope, s); break;
-    case 4: conv3_launch<4, 4, To>(in, wp, bias, out, D, H, W, Ci, act, slope, s); break;
-    case 6: conv3_launch<2, 6, To>(in, wp, bias, out, D, H, W, Ci, act, slope, s); break;
-    case 8: conv3_launch<2, 8, To>(in, wp, bias, out, D, H, W, Ci, act, slope, s); break;
-    case 12: conv3_launch<1, 12, To>(in, wp, bias, out, D, H, W, Ci, act, slope, s); break;
+    case 1: conv3_split<8, 1, To>(in, wp, bias, out, D, H, W, Ci, act, slope, s); break;
+    case 2: conv3_split<8, 2, To>(in, wp, bias, out, D, H, W, Ci, act, slope, s); break;
+    case 3: conv3_split<4, 3, To>(in, wp, bias, out, D, H, W, Ci, act, slope, s); break;
+    case 4: conv3_split<4, 4, To>(in, wp, bias, out, D, H, W, Ci, act, slope, s); break;
+    case 6: conv3_split<2, 6, To>(in, wp, bias, out, D, H, W, Ci, act, slope, s); break;
+    case 8: conv3_split<2, 8, To>(in, wp, bias, out, D, H, W, Ci, act, slope, s); break;
+    case 12: conv3_split<1, 12, To>(in, wp, bias, out, D, H, W, Ci, act, slope, s); break;
     default: break;
     }
 }

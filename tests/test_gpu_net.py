@@ -74,6 +74,20 @@ def test_conv3_forward_and_transpose(shape, ci, co):
     assert np.max(np.abs(o16 - bf16_round(out))) <= np.max(np.abs(out)) * 2.0 ** -7
 
 
+def test_conv3_forward_all_tiles_per_workgroup():
+    """A grid large enough (512 bricks of 16 x 4 x 8 voxels) that every
+    workgroup computes all output tiles; the small CASES split the output
+    channels over workgroup groups instead."""
+    from paper_2209_08189_amd.claire import nn_conv3
+    shape, ci, co = (32, 64, 128), 16, 32
+    r = np.random.default_rng(5)
+    x = bf16_round(r.standard_normal(shape + (ci,)))
+    w = r.standard_normal((27, ci, co)) / np.sqrt(27 * ci)
+    b = r.standard_normal(co)
+    out = host(nn_conv3(bf16_dev(x), f32_dev(w), f32_dev(b), co, act=0))
+    assert rel(out, oracle.conv3(x, bf16_round(w), b)) < 1e-5
+
+
 @pytest.mark.parametrize("shape,ci,co", CASES)
 def test_conv3_weight_gradient(shape, ci, co):
     from paper_2209_08189_amd.claire import nn_conv3_dw
