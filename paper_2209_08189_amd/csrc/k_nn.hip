@@ -194,8 +194,13 @@ __global__ __launch_bounds__(TPB) void k_conv3_dw(const unsigned short *__restri
                                                   int tpc, int ngrp)
 {
     constexpr int XR = 4 * 6;                 // staged X rows: z in [z0-1, z0+2], y in [y0-1, y0+4]
-    __shared__ __attribute__((aligned(16))) unsigned short xs[3][16][XR][16];
-    __shared__ __attribute__((aligned(16))) unsigned short zs[NG * 16][8][16];
+    // channel planes padded by 16 bytes: a plane pitch of 4 (mod 8) words puts
+    // the 16-byte A / B fragment reads of the 16 channel lanes on distinct
+    // banks (an unpadded pitch, a multiple of 64 words, sent all 16 to the
+    // same four banks)
+    constexpr int XP = XR * 16 + 8, ZP = 8 * 16 + 8;   // plane pitches in 16-bit elements
+    __shared__ __attribute__((aligned(16))) unsigned short xs[3][16][XP];
+    __shared__ __attribute__((aligned(16))) unsigned short zs[NG * 16][ZP];
     const int tid = threadIdx.x, l = tid & 63, wv = tid >> 6;
     const int g = l >> 4, ln = l & 15;
     const int KC = Ci >> 4;
@@ -232,7 +237,7 @@ __global__ __launch_bounds__(TPB) void k_conv3_dw(const unsigned short *__restri
                 const int xc = xt - sx;             // copy sx holds X[x0 + xc + sx - 1]
                 if (xc < 0 || xc >= 16) continue;
 #pragma unroll
-                for (int c = 0; c < 8; ++c) xs[sx][hq * 8 + c][r][xc] = e[c];
+                for (int c = 0; c < 8; ++c) xs[sx][hq * 8 + c][r * 16 + xc] = e[c];
             }
         }
         // dZ tile: 16 x 4 x 2 voxels x NG * 16 channels
@@ -245,14 +250,15 @@ __global__ __launch_bounds__(TPB) void k_conv3_dw(const unsigned short *__restri
                 val = *(const u4 *)(dZ + (((size_t)z * H + y) * W + x) * Co + co0 + hq * 8);
             const unsigned short *e = (const unsigned short *)&val;
 #pragma unroll
-            for (int c = 0; c < 8; ++c) zs[hq * 8 + c][r][xt] = e[c];
+            for (int c = 0; c < 8; ++c) zs[hq * 8 + c][r * 16 + xt] = e[c];
         }
         __syncthreads();
         bf8 bz[NG][4];
 #pragma unroll
         for (int nt = 0; nt < NG; ++nt)
 #pragma unroll
-            for (int s = 0; s < 4; ++s) bz[nt][s] = as_bf8(*(const u4 *)&zs[nt * 16 + ln][2 * s + (g >> 1)][8 * (g & 1)]);
+            for (int s = 0; s < 4; ++s)
+                bz[nt][s] = as_bf8(*(const u4 *)&zs[nt * 16 + ln][(2 * s + (g >> 1)) * 16 + 8 * (g & 1)]);
 #pragma unroll
         for (int ti = 0; ti < 7; ++ti) {
             const int t = wv + 4 * ti;
@@ -262,7 +268,7 @@ __global__ __launch_bounds__(TPB) void k_conv3_dw(const unsigned short *__restri
             for (int s = 0; s < 4; ++s) {
                 const int row = 2 * s + (g >> 1);               // 4 zl + yl
                 const int r = ((row >> 2) + dz) * 6 + (row & 3) + dy;
-                const bf8 a = as_bf8(*(const u4 *)&xs[dx][ln][r][8 * (g & 1)]);
+                const bf8 a = as_bf8(*(const u4 *)&xs[dx][ln][r * 16 + 8 * (g & 1)]);
 #pragma unroll
                 for (int nt = 0; nt < NG; ++nt)
                     acc[ti][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bz[nt][s], acc[ti][nt], 0, 0, 0);
