@@ -181,7 +181,7 @@ def main():
                     help="also run the library's plain copy kernel on this many MiB (memory-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only; this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
+        print("bench.py measures one GPU only; the library has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
     if not args.no_cpu_baseline:

@@ -58,7 +58,7 @@ enum {
     CL_ERR_OOM = -4,          /* device allocation failed or workspace cap exceeded */
     CL_ERR_HIP = -5,          /* a HIP runtime call failed */
     CL_ERR_NONFINITE = -6,    /* NaN or Inf found in an input */
-    CL_ERR_UNSUPPORTED = -7,  /* option outside this build */
+    CL_ERR_UNSUPPORTED = -7,  /* option combination the library does not implement */
     CL_ERR_STATE = -8,        /* call order violated (e.g. gradient before set_images) */
     CL_ERR_ALIAS = -9,        /* input and output buffers overlap */
     CL_STATUS_MAXIT = 1,      /* solve stopped at max_outer */
@@ -153,7 +153,7 @@ int cl_layout(const cl_ctx *ctx);
 void cl_destroy(cl_ctx *ctx);
 
 /* Template m0 and reference m1 (Section 2.1), each n1*n2*n3 values of type
- * dt (CL_F32 only in this build) on the device; copied and converted to the
+ * dt (CL_F32 only) on the device; copied and converted to the
  * context's storage precision.  Rejects NaN/Inf (CL_ERR_NONFINITE). */
 int cl_set_images(cl_ctx *ctx, const void *m0, const void *m1, int dt);
 
