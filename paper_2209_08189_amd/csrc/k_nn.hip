@@ -613,6 +613,15 @@ static void conv3_split(const unsigned short *in, const void *wp, const float *b
                         int Ci, int act, float slope, hipStream_t s)
 {
     const int nb = ((W + 15) / 16) * ((H + 3) / 4) * ((D + MT - 1) / MT);
+    if constexpr (MT == 1 && NT == 12) {
+        // one output row per wavefront uses each streamed B fragment once;
+        // two rows of 6 tiles in two groups use it twice for the same
+        // accumulator count
+        if (nb >= 512) {
+            conv3_launch<2, 6, To>(in, wp, bias, out, D, H, W, Ci, NT, act, slope, s);
+            return;
+        }
+    }
     if (nb >= 512 || NT == 1) {
         conv3_launch<MT, NT, To>(in, wp, bias, out, D, H, W, Ci, NT, act, slope, s);
         return;
